@@ -1,0 +1,231 @@
+/*
+ * ifgf.h - C ABI of the MI355X (gfx950) IFGF-accelerated apply of the
+ * discrete 3-D Helmholtz combined-field operator.
+ *
+ * The operation (paper Section 3, eq. (field1), with the combined-field
+ * kernel of Section 2.2, eqs. (CombinedLayer), (GreenFunction),
+ * (double_layer)):
+ *
+ *     u_i = sum_{j != i} w_j sigma_j K(x_i, x_j),
+ *     K(x, y) = dPhi(x, y)/dnu(y) - i eta Phi(x, y),
+ *     Phi(x, y) = exp(i k |x - y|) / (4 pi |x - y|),
+ *
+ * for pairwise distinct surface points x_j with normals nu(x_j) and
+ * quadrature weights w_j.  eta is the coupling parameter (called gamma in
+ * the paper).  The sum is approximated by the Interpolated Factored Green
+ * Function method (Section 3, Algorithm 1): level-D neighbour interactions
+ * are summed directly, all others are obtained from tensor Chebyshev
+ * interpolants of the factored field on cone segments of an octree.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked [device] must point to device memory of the current
+ *     HIP device; [host] pointers to host memory.  Arrays are row-major and
+ *     tightly packed.  Complex values are interleaved (re, im) pairs, i.e.
+ *     the layout of C99 complex / torch.complex64 / torch.complex128.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; entry points return once enqueued unless
+ *     stated otherwise.
+ *   - Nothing throws across this ABI.  Every fallible call returns an
+ *     ifgf_status; ifgf_last_error() returns a message for the last failure
+ *     on the calling thread.
+ *   - Point order: all per-point arrays (points, normals, weights, sigma,
+ *     u) are in the caller's order.  The library sorts internally and
+ *     scatters results back.
+ */
+#ifndef IFGF_H
+#define IFGF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ifgf_plan_s *ifgf_plan;
+
+typedef enum {
+    IFGF_OK = 0,
+    IFGF_EINVAL = 1,        /* invalid argument (null pointer, size, option) */
+    IFGF_EDUPLICATE = 2,    /* two points coincide (eq. field1 needs distinct points) */
+    IFGF_ENOMEM = 3,        /* device allocation failed */
+    IFGF_EHIP = 4,          /* a HIP runtime call failed; see ifgf_last_error() */
+    IFGF_EUNSUPPORTED = 5,  /* option combination not compiled in */
+    IFGF_EBUSY = 6,         /* another apply on the same plan is in progress */
+    IFGF_EINTERNAL = 7      /* internal consistency check failed */
+} ifgf_status;
+
+/* Arithmetic of the interpolation stages. */
+enum {
+    IFGF_PREC_FP64 = 0,         /* every stage in IEEE double                          */
+    IFGF_PREC_FP32_INTERP = 1   /* factors, interpolation, propagation and near field in
+                                   FP32 complex; target distances, k|x - y|, its
+                                   reduction modulo 2 pi and the centred factor in FP64 */
+};
+
+/* Element type of sigma / u / v arrays. */
+enum { IFGF_C64 = 0, IFGF_C128 = 1 };
+
+/* Kernel selector.  IFGF_KERNEL_CONSTANT (K = 1) is a test kernel: the
+ * interpolation is then exact and u_i = sum_{j != i} w_j sigma_j, which
+ * checks that the octree traversal counts every pair once. */
+enum { IFGF_KERNEL_COMBINED = 0, IFGF_KERNEL_CONSTANT = 1 };
+
+typedef struct {
+    int32_t p_s;            /* Chebyshev points per cone segment along s (paper P_s); default 4 */
+    int32_t p_ang;          /* ... along theta and along phi (paper P_ang); default 6      */
+    int32_t ns0;            /* radial cone intervals at the finest level (paper n_S,0); default 2  */
+    int32_t nc0;            /* polar cone intervals at the finest level (paper n_C,0); default 4;
+                               azimuthal intervals are 2 * nc0 (eq. deltas)              */
+    int32_t depth;          /* number of octree levels D, root = level 1 (Sec. 3.4); 0 = choose
+                               D so that the finest box side is closest to leaf_h_lambda
+                               wavelengths; 1 <= D <= 11                                   */
+    double leaf_h_lambda;   /* finest box side in wavelengths for depth = 0; default 0.5 */
+    int32_t precision;      /* IFGF_PREC_*; default IFGF_PREC_FP32_INTERP                  */
+    int32_t max_rhs;        /* largest nrhs accepted by the apply calls; default 1         */
+    int32_t kernel;         /* IFGF_KERNEL_*; default IFGF_KERNEL_COMBINED                  */
+} ifgf_options;
+
+/* Plan statistics (host struct). */
+#define IFGF_MAX_LEVELS 12
+typedef struct {
+    int32_t depth;                          /* D                                       */
+    int64_t n;                              /* number of points                         */
+    double root_side;                       /* side of the level-1 box                  */
+    double root_corner[3];                  /* lower corner of the level-1 box          */
+    int32_t p_s, p_ang;
+    int32_t precision;
+    int64_t boxes[IFGF_MAX_LEVELS];         /* relevant boxes per level (index = d)     */
+    int32_t ns[IFGF_MAX_LEVELS];            /* cone intervals along s per level         */
+    int32_t nc[IFGF_MAX_LEVELS];            /* cone intervals along theta per level     */
+    int64_t cones[IFGF_MAX_LEVELS];         /* relevant cone segments per level (d >= 3)*/
+    int64_t cousin_pairs[IFGF_MAX_LEVELS];  /* (target point, source box) cousin pairs  */
+    int64_t near_pairs;                     /* ordered (target, source) pairs summed
+                                               directly at level D, self included      */
+    int64_t prop_evals[IFGF_MAX_LEVELS];    /* child interpolations into level d-1 nodes,
+                                               indexed by the child level d            */
+    int64_t device_bytes;                   /* device memory held by the plan           */
+} ifgf_plan_stats;
+
+/* Fill *o with the defaults listed above.  o: [host], non-null. */
+void ifgf_options_default(ifgf_options *o);
+
+/*
+ * Build a plan: octree of D levels over the points, Morton (Z-curve) order
+ * (Sec. 3.5), neighbour and cousin lists (eq. NeighborsCousins), cone
+ * counts per level (Remark cone_seg_size) and relevant cone segments
+ * (eq. RelevantCones), all on the device.
+ *
+ *   out      [host]   receives the plan handle (NULL on failure)
+ *   n        number of points, n >= 1
+ *   points   [device] n x 3 doubles, the surface points x_j (pairwise distinct)
+ *   normals  [device] n x 3 doubles, nu(x_j) (used as given, not normalized)
+ *   weights  [device] n doubles, quadrature weights w_j
+ *   k        wavenumber, k > 0
+ *   eta      coupling parameter (any real; 0 gives the double layer alone)
+ *   opt      [host]   options, or NULL for the defaults
+ *   stream   hipStream_t on which the plan is built
+ *
+ * The plan copies what it needs; the inputs may be freed once the call has
+ * returned.  The call synchronizes `stream` to read back sizes.
+ * Errors: EINVAL (n < 1, null pointer, non-finite input, k <= 0, bad
+ * option), EDUPLICATE (two bitwise-equal points), ENOMEM, EHIP,
+ * EUNSUPPORTED (p_s / p_ang pair not compiled), EINTERNAL.
+ */
+ifgf_status ifgf_plan_create(ifgf_plan *out, int64_t n, const double *points,
+                             const double *normals, const double *weights,
+                             double k, double eta, const ifgf_options *opt,
+                             void *stream);
+
+/*
+ * Forward apply: u = A sigma with A_ij = w_j K(x_i, x_j) for i != j, A_ii = 0
+ * (eq. field1), approximated by Algorithm 1.
+ *
+ *   sigma  [device] n x nrhs complex (dtype IFGF_C64 or IFGF_C128), caller order
+ *   u      [device] n x nrhs complex of the same dtype, overwritten; must not alias sigma
+ *   nrhs   1 <= nrhs <= opt.max_rhs
+ *
+ * Errors: EINVAL, EBUSY (an apply on this plan is still being enqueued by
+ * another thread), EHIP.  Applies enqueued on different streams with the
+ * same plan share the plan's workspace and must be ordered by the caller.
+ */
+ifgf_status ifgf_apply(ifgf_plan p, const void *sigma, void *u, int32_t nrhs,
+                       int32_t dtype, void *stream);
+
+/*
+ * Transposed apply through the same tree: the exact transpose of every
+ * linear stage of ifgf_apply, in reverse order (near field transposed,
+ * cousin anterpolation, downward pass, leaf transposed, times w at the
+ * output point).  With conjugate = 0 it computes out = A~^T v; with
+ * conjugate = 1 it computes out = A~^H v = conj(A~^T conj(v)), the adjoint
+ * used for gradients of real losses.  Here A~ is the operator that
+ * ifgf_apply implements, so <A~ s, v> = <s, A~^T v> holds to rounding.
+ *
+ *   v, out  [device] n x nrhs complex of dtype `dtype`, caller order; no aliasing
+ * Errors as for ifgf_apply.
+ */
+ifgf_status ifgf_apply_adjoint(ifgf_plan p, const void *v, void *out, int32_t nrhs,
+                               int32_t dtype, int32_t conjugate, void *stream);
+
+/* Plan statistics.  st: [host]. */
+ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats *st);
+
+/*
+ * Test hooks (device pointers, sizes from ifgf_plan_get_stats; each call
+ * synchronizes the stream before returning).
+ *
+ * ifgf_plan_export_order: perm[i] = caller index of the i-th point in
+ *   Morton order; keys[i] = its finest-level Morton key (x bit b -> bit 3b,
+ *   y -> 3b+1, z -> 3b+2).  perm: n int32, keys: n uint32.
+ * ifgf_plan_export_boxes: level d boxes: start (boxes+1 int32 point ranges
+ *   in Morton order) and coords (boxes x 3 int32 integer box indices).
+ * ifgf_plan_export_lists: level d neighbour (kind 0) or cousin (kind 1)
+ *   lists as CSR: off (boxes+1 int32) and idx (off[boxes] int32).  Pass
+ *   idx = NULL to query the length through *len ([host]).
+ * ifgf_plan_export_cones: level d relevant cones: box (cones int32) and
+ *   cone id (cones int32), cone id = (i_s * n_C + i_theta) * 2 n_C + i_phi.
+ * ifgf_plan_export_field: after an apply, the level-d field of the last
+ *   call, as node values (what = 0) or Chebyshev coefficients (what = 1):
+ *   cones x P x nrhs complex of the plan precision (double or float pairs),
+ *   P = p_s * p_ang^2, node (a, b, c) at index (a * p_ang + b) * p_ang + c.
+ */
+ifgf_status ifgf_plan_export_order(ifgf_plan p, int32_t *perm, uint32_t *keys);
+ifgf_status ifgf_plan_export_boxes(ifgf_plan p, int32_t d, int32_t *start, int32_t *coords);
+ifgf_status ifgf_plan_export_lists(ifgf_plan p, int32_t d, int32_t kind, int32_t *off,
+                                   int32_t *idx, int64_t *len);
+ifgf_status ifgf_plan_export_cones(ifgf_plan p, int32_t d, int32_t *box, int32_t *cone);
+ifgf_status ifgf_plan_export_field(ifgf_plan p, int32_t d, int32_t what, void *dst);
+
+/*
+ * Apply with a stage mask, for stage-by-stage parity tests: bit 0 = near
+ * field, bit 1 = cousin-target interpolation; level_lo..level_hi restricts
+ * the cousin-target stage to those levels.  The upward pass always runs in
+ * full.  Arguments otherwise as ifgf_apply.
+ */
+ifgf_status ifgf_apply_stages(ifgf_plan p, const void *sigma, void *u, int32_t nrhs,
+                              int32_t dtype, int32_t stage_mask, int32_t level_lo,
+                              int32_t level_hi, void *stream);
+
+/*
+ * Device-side consistency flags accumulated since the plan was built:
+ * bit 1 = an upward-pass node fell outside the relevant cones of a child,
+ * bit 2 = a cousin point fell outside the relevant cones of a box.  Both
+ * mean a plan/apply mismatch and are 0 in a correct build.  flags: [host].
+ * Synchronizes the device.
+ */
+ifgf_status ifgf_plan_check(ifgf_plan p, int32_t *flags);
+
+/* Release the plan and its device memory (after its work has completed).
+ * NULL is ignored. */
+void ifgf_plan_destroy(ifgf_plan p);
+
+/* Static text for a status code. */
+const char *ifgf_status_string(ifgf_status st);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *ifgf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IFGF_H */

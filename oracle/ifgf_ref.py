@@ -191,23 +191,30 @@ def build_tree(points: np.ndarray, D: int) -> Tree:
     for d in range(2, D + 1):
         lev, up = levels[d], levels[d - 1]
         lev.parent = np.array([up.index[tuple(c)] for c in (lev.coords >> 1).tolist()], dtype=np.int64)
+    offsets = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
     for d in range(1, D + 1):
         lev = levels[d]
         nb = lev.coords.shape[0]
         lev.neighbours = []
         lev.cousins = []
+        children_of = {}
+        if d >= 2:
+            for j, c in enumerate(lev.coords.tolist()):
+                children_of.setdefault((c[0] >> 1, c[1] >> 1, c[2] >> 1), []).append(j)
         for b in range(nb):
-            kb = lev.coords[b]
-            nbr = [j for j in range(nb) if np.abs(lev.coords[j] - kb).max() <= 1]
+            kb = tuple(lev.coords[b].tolist())
+            nbr = sorted(lev.index[q] for q in
+                         ((kb[0] + o[0], kb[1] + o[1], kb[2] + o[2]) for o in offsets) if q in lev.index)
             lev.neighbours.append(np.array(nbr, dtype=np.int64))
+            cou = []
             if d >= 2:
-                pk = kb >> 1
-                cou = [j for j in range(nb)
-                       if np.abs(lev.coords[j] - kb).max() > 1
-                       and np.abs((lev.coords[j] >> 1) - pk).max() <= 1]
-            else:
-                cou = []
-            lev.cousins.append(np.array(cou, dtype=np.int64))
+                pk = (kb[0] >> 1, kb[1] >> 1, kb[2] >> 1)
+                nset = set(nbr)
+                for o in offsets:
+                    for j in children_of.get((pk[0] + o[0], pk[1] + o[1], pk[2] + o[2]), []):
+                        if j not in nset:
+                            cou.append(j)
+            lev.cousins.append(np.array(sorted(cou), dtype=np.int64))
     return Tree(D=D, L=L, corner=corner, perm=perm, keys=keys_s, points=pts_s, levels=levels)
 
 

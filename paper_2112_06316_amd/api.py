@@ -1,0 +1,203 @@
+"""Python binding: argument marshalling to the C ABI of libifgf.so.
+
+Every computation runs in the HIP library; torch provides device memory and
+the current stream only.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def load_library():
+    return L.load()
+
+
+def library_path() -> str:
+    return L.LIB_PATH
+
+
+_PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32_INTERP}
+_KERNEL = {"combined": L.KERNEL_COMBINED, "constant": L.KERNEL_CONSTANT}
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_f64(x, device, shape):
+    t = torch.as_tensor(x, dtype=torch.float64)
+    t = t.to(device).contiguous()
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+    return t
+
+
+class Plan:
+    """IFGF plan for the operator u_i = sum_{j != i} w_j sigma_j K(x_i, x_j).
+
+    points, normals: (n, 3) float64 (numpy or torch); weights: (n,) float64.
+    Options mirror ifgf_options (include/ifgf.h).
+    """
+
+    def __init__(self, points, normals, weights, k, eta, *, p_s=4, p_ang=6, ns0=2, nc0=4, depth=0,
+                 leaf_h_lambda=0.5, precision="fp32", max_rhs=1, kernel="combined", device="cuda"):
+        lib = L.load()
+        self._lib = lib
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the IFGF library runs on a ROCm device only")
+        n = int(np.shape(points)[0])
+        self.n = n
+        self.k, self.eta = float(k), float(eta)
+        self.precision = precision
+        pts = _dev_f64(points, self.device, (n, 3))
+        nrm = _dev_f64(normals, self.device, (n, 3))
+        w = _dev_f64(weights, self.device, (n,))
+        o = L.Options()
+        lib.ifgf_options_default(ctypes.byref(o))
+        o.p_s, o.p_ang, o.ns0, o.nc0, o.depth = int(p_s), int(p_ang), int(ns0), int(nc0), int(depth)
+        o.leaf_h_lambda = float(leaf_h_lambda)
+        o.precision = _PREC[precision]
+        o.max_rhs = int(max_rhs)
+        o.kernel = _KERNEL[kernel]
+        self.options = o
+        h = ctypes.c_void_p()
+        st = lib.ifgf_plan_create(ctypes.byref(h), n, pts.data_ptr(), nrm.data_ptr(), w.data_ptr(),
+                                  self.k, self.eta, ctypes.byref(o), _stream_ptr(self.device))
+        L.check(st, "ifgf_plan_create")
+        self._h = h
+        self.max_rhs = int(max_rhs)
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ifgf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- applies ---------------------------------------------------------------
+    def _prep(self, x):
+        x = torch.as_tensor(x)
+        if not torch.is_complex(x):
+            raise TypeError("complex input required")
+        squeeze = x.dim() == 1
+        if squeeze:
+            x = x[:, None]
+        if x.dim() != 2 or x.shape[0] != self.n:
+            raise ValueError(f"expected ({self.n},) or ({self.n}, nrhs)")
+        x = x.to(self.device).contiguous()
+        dtype = L.C128 if x.dtype == torch.complex128 else L.C64
+        if x.dtype not in (torch.complex64, torch.complex128):
+            raise TypeError("complex64 or complex128 required")
+        return x, squeeze, dtype
+
+    def apply(self, sigma, out=None):
+        """u = A sigma (forward IFGF apply)."""
+        s, squeeze, dtype = self._prep(sigma)
+        u = torch.empty_like(s) if out is None else out
+        st = self._lib.ifgf_apply(self._h, s.data_ptr(), u.data_ptr(), s.shape[1], dtype, _stream_ptr(self.device))
+        L.check(st, "ifgf_apply")
+        return u[:, 0] if squeeze else u
+
+    def apply_stages(self, sigma, stage_mask=3, level_lo=0, level_hi=99):
+        s, squeeze, dtype = self._prep(sigma)
+        u = torch.empty_like(s)
+        st = self._lib.ifgf_apply_stages(self._h, s.data_ptr(), u.data_ptr(), s.shape[1], dtype, int(stage_mask),
+                                         int(level_lo), int(level_hi), _stream_ptr(self.device))
+        L.check(st, "ifgf_apply_stages")
+        return u[:, 0] if squeeze else u
+
+    def apply_adjoint(self, v, conjugate=True):
+        """A~^T v (conjugate=False) or A~^H v (conjugate=True) through the same tree."""
+        x, squeeze, dtype = self._prep(v)
+        out = torch.empty_like(x)
+        st = self._lib.ifgf_apply_adjoint(self._h, x.data_ptr(), out.data_ptr(), x.shape[1], dtype,
+                                          1 if conjugate else 0, _stream_ptr(self.device))
+        L.check(st, "ifgf_apply_adjoint")
+        return out[:, 0] if squeeze else out
+
+    # -- introspection -------------------------------------------------------
+    def stats(self) -> dict:
+        s = L.Stats()
+        L.check(self._lib.ifgf_plan_get_stats(self._h, ctypes.byref(s)), "ifgf_plan_get_stats")
+        D = s.depth
+        return {
+            "depth": D, "n": s.n, "root_side": s.root_side, "root_corner": list(s.root_corner),
+            "p_s": s.p_s, "p_ang": s.p_ang, "precision": s.precision,
+            "boxes": {d: s.boxes[d] for d in range(1, D + 1)},
+            "ns": {d: s.ns[d] for d in range(1, D + 1)},
+            "nc": {d: s.nc[d] for d in range(1, D + 1)},
+            "cones": {d: s.cones[d] for d in range(3, D + 1)},
+            "cousin_pairs": {d: s.cousin_pairs[d] for d in range(3, D + 1)},
+            "prop_evals": {d: s.prop_evals[d] for d in range(4, D + 1)},
+            "near_pairs": s.near_pairs, "device_bytes": s.device_bytes,
+        }
+
+    def check(self) -> int:
+        f = ctypes.c_int32(0)
+        L.check(self._lib.ifgf_plan_check(self._h, ctypes.byref(f)), "ifgf_plan_check")
+        return int(f.value)
+
+    def export_order(self):
+        perm = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        keys = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        L.check(self._lib.ifgf_plan_export_order(self._h, perm.data_ptr(), keys.data_ptr()), "export_order")
+        return perm.cpu().numpy(), keys.cpu().numpy().view(np.uint32)
+
+    def export_boxes(self, d):
+        nb = self.stats()["boxes"][d]
+        start = torch.empty(nb + 1, dtype=torch.int32, device=self.device)
+        coords = torch.empty(max(1, 3 * nb), dtype=torch.int32, device=self.device)
+        L.check(self._lib.ifgf_plan_export_boxes(self._h, d, start.data_ptr(), coords.data_ptr()), "export_boxes")
+        return start.cpu().numpy(), coords[:3 * nb].cpu().numpy().reshape(nb, 3)
+
+    def export_lists(self, d, kind):
+        nb = self.stats()["boxes"][d]
+        ln = ctypes.c_int64(0)
+        L.check(self._lib.ifgf_plan_export_lists(self._h, d, kind, None, None, ctypes.byref(ln)), "export_lists")
+        off = torch.empty(nb + 1, dtype=torch.int32, device=self.device)
+        idx = torch.empty(max(1, ln.value), dtype=torch.int32, device=self.device)
+        L.check(self._lib.ifgf_plan_export_lists(self._h, d, kind, off.data_ptr(), idx.data_ptr(), ctypes.byref(ln)),
+                "export_lists")
+        off = off.cpu().numpy()
+        idx = idx[:ln.value].cpu().numpy()
+        return [idx[off[b]:off[b + 1]] for b in range(nb)]
+
+    def export_cones(self, d):
+        nr = self.stats()["cones"][d]
+        box = torch.empty(max(1, nr), dtype=torch.int32, device=self.device)
+        cone = torch.empty(max(1, nr), dtype=torch.int32, device=self.device)
+        L.check(self._lib.ifgf_plan_export_cones(self._h, d, box.data_ptr(), cone.data_ptr()), "export_cones")
+        return box[:nr].cpu().numpy(), cone[:nr].cpu().numpy()
+
+    def export_field(self, d, what=0, nrhs=1):
+        """Level-d field of the last apply: (cones, nrhs, P) complex, node values (0) or coefficients (1)."""
+        nr = self.stats()["cones"][d]
+        P = self.options.p_s * self.options.p_ang ** 2
+        dt = torch.complex64 if self.precision == "fp32" else torch.complex128
+        buf = torch.empty(max(1, nr * P * nrhs), dtype=dt, device=self.device)
+        L.check(self._lib.ifgf_plan_export_field(self._h, d, what, buf.data_ptr()), "export_field")
+        return buf[:nr * P * nrhs].cpu().numpy().reshape(nr, nrhs, P)
+
+
+class IFGFApply(torch.autograd.Function):
+    """u = A sigma with backward grad_sigma = A~^H grad_u (PyTorch's complex convention)."""
+
+    @staticmethod
+    def forward(ctx, sigma, plan: Plan):
+        ctx.plan = plan
+        return plan.apply(sigma.detach())
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        return ctx.plan.apply_adjoint(grad_u.contiguous(), conjugate=True), None

@@ -1,0 +1,631 @@
+// IFGF apply on the device (paper Section 3, Algorithm 1).
+//
+// Stages of one apply, in launch order:
+//   gather    a_j = w_j sigma_j into Morton order
+//   near      level-D neighbour interactions by direct summation, self
+//             excluded by index (Remark level_D_neighboring; eq. field1)
+//   leaf      F^{k,D} at the interpolation nodes of every relevant leaf cone
+//             (Algorithm 1, first loop): F = sum_{y in B} a_y W_c(x, y)
+//   coeffs    node values -> tensor Chebyshev coefficients per cone
+//   prop      for d = D..4: each node x of each relevant cone of a level-(d-1)
+//             box P gets sum over children B of I[F_B](x) K(x,y_B)/K(x,y_P)
+//             (Algorithm 1, parent-node update)
+//   targets   for d = D..3: every point x gets, for each box B of which it is
+//             a cousin point, e^{ikr}/(4 pi r) I[F_B](x) (Algorithm 1, cousin
+//             interpolation), plus its near-field sum; scattered back to the
+//             caller's order.
+//
+// The analytic factor is the combined W_c = W~2 - i k W3 - i eta W1 (eqs.
+// hgn2, W2W2, w23): one field per box, valid by the linearity of eq.
+// (exponential_sum_linearity) with q = 1 for each term.
+//
+// Interpolant evaluation: a lane that needs cone `slot` of some box reads
+// that cone's P coefficients.  Lanes of a wave that need the same cone are
+// served together: the wave repeatedly takes the slot of its first pending
+// lane, makes it wave-uniform with readfirstlane, and every lane holding that
+// slot evaluates with the uniform coefficient pointer.
+#include "internal.h"
+
+namespace ifgf {
+
+namespace {
+
+constexpr int TPB = 256;
+inline unsigned nblocks(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+
+template <typename T> struct Prec;
+template <> struct Prec<float> {
+  static constexpr bool f32 = true;
+};
+template <> struct Prec<double> {
+  static constexpr bool f32 = false;
+};
+
+template <typename T> __device__ __forceinline__ void sincos_t(T x, T* s, T* c);
+template <> __device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+template <> __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename T> __device__ __forceinline__ T sqrt_t(T x);
+template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return sqrt(x); }
+
+// ---------------------------------------------------------------------------
+// gather: a[i, r] = w_i sigma[perm_i, r]
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, int dtype, int conj_in,
+                                                const int* __restrict__ perm, const double* __restrict__ w,
+                                                int64_t n, int R, cpx<T>* __restrict__ a) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  int64_t j = perm[i];
+  double wi = w[i];
+  for (int r = 0; r < R; ++r) {
+    double re, im;
+    if (dtype == IFGF_C128) {
+      const double* s = (const double*)sigma + 2 * (j * R + r);
+      re = s[0];
+      im = s[1];
+    } else {
+      const float* s = (const float*)sigma + 2 * (j * R + r);
+      re = s[0];
+      im = s[1];
+    }
+    if (conj_in) im = -im;
+    a[i * R + r] = {(T)(wi * re), (T)(wi * im)};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// near field: one block per finest-level box B; targets = points of B,
+// sources = points of the neighbour boxes (self included, the i == j term
+// excluded).  Positions relative to B's centre in precision T.
+// ---------------------------------------------------------------------------
+constexpr int NEAR_CHUNK = 512;
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, const double* __restrict__ nrm,
+                                              const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
+                                              const int* __restrict__ nbr_off, const int* __restrict__ nbr,
+                                              const double* __restrict__ centre, double k, double eta, int kind,
+                                              cpx<T>* __restrict__ uacc) {
+  __shared__ T sx[NEAR_CHUNK][3];
+  __shared__ T sn[NEAR_CHUNK][3];
+  __shared__ cpx<T> sa[NEAR_CHUNK];
+  __shared__ int sidx[NEAR_CHUNK];
+  __shared__ int noff[28], nbox[27];
+  __shared__ cpx<T> red[TPB];
+  const int b = blockIdx.x, r = blockIdx.y;
+  const int t0 = start[b], nt = start[b + 1] - t0;
+  const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
+  const int nn = nbr_off[b + 1] - nbr_off[b];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int q = 0; q < nn; ++q) {
+      int j = nbr[nbr_off[b] + q];
+      nbox[q] = j;
+      noff[q] = acc;
+      acc += start[j + 1] - start[j];
+    }
+    noff[nn] = acc;
+  }
+  __syncthreads();
+  const int nsrc = noff[nn];
+  // lane mapping: TP targets per pass, S source slices
+  int TP = 1;
+  while (TP < nt && TP < TPB) TP <<= 1;
+  const int S = TPB / TP;
+  const int tl = threadIdx.x % TP, sl = threadIdx.x / TP;
+  const T kk = (T)k, ee = (T)eta;
+  const T inv4pi = (T)(1.0 / (4.0 * IFGF_PI));
+  for (int tb = 0; tb < nt; tb += TP) {
+    const int ti = tb + tl;
+    const bool tv = ti < nt;
+    T x0 = 0, x1 = 0, x2 = 0;
+    if (tv) {
+      x0 = (T)(pts[3 * (t0 + ti)] - c0);
+      x1 = (T)(pts[3 * (t0 + ti) + 1] - c1);
+      x2 = (T)(pts[3 * (t0 + ti) + 2] - c2);
+    }
+    cpx<T> acc = {0, 0};
+    for (int cb = 0; cb < nsrc; cb += NEAR_CHUNK) {
+      const int cn = min(NEAR_CHUNK, nsrc - cb);
+      __syncthreads();
+      for (int e = threadIdx.x; e < cn; e += TPB) {
+        int f = cb + e, q = 0;
+        while (noff[q + 1] <= f) ++q;
+        int j = start[nbox[q]] + (f - noff[q]);
+        sidx[e] = j;
+        sx[e][0] = (T)(pts[3 * j] - c0);
+        sx[e][1] = (T)(pts[3 * j + 1] - c1);
+        sx[e][2] = (T)(pts[3 * j + 2] - c2);
+        sn[e][0] = (T)nrm[3 * j];
+        sn[e][1] = (T)nrm[3 * j + 1];
+        sn[e][2] = (T)nrm[3 * j + 2];
+        sa[e] = a[(int64_t)j * R + r];
+      }
+      __syncthreads();
+      if (tv) {
+        const int self = t0 + ti;
+        for (int e = sl; e < cn; e += S) {
+          if (sidx[e] == self) continue;
+          cpx<T> kv;
+          if (kind == IFGF_KERNEL_CONSTANT) {
+            kv = {1, 0};
+          } else {
+            T d0 = x0 - sx[e][0], d1 = x1 - sx[e][1], d2 = x2 - sx[e][2];
+            T r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            T rr = sqrt_t<T>(r2);
+            T ir = (T)1 / rr;
+            T dn = (d0 * sn[e][0] + d1 * sn[e][1] + d2 * sn[e][2]) * ir * ir;
+            T sn_, cs_;
+            sincos_t<T>(kk * rr, &sn_, &cs_);
+            // G = e^{ikr}/(4 pi r);  K = G [ (1 - ikr) dn - i eta ]
+            T g = inv4pi * ir;
+            T pr = dn, pi = -(kk * rr * dn + ee);
+            kv = {g * (cs_ * pr - sn_ * pi), g * (sn_ * pr + cs_ * pi)};
+          }
+          cpx<T> av = sa[e];
+          acc.re += kv.re * av.re - kv.im * av.im;
+          acc.im += kv.re * av.im + kv.im * av.re;
+        }
+      }
+    }
+    __syncthreads();
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (sl == 0 && tv) {
+      cpx<T> s = red[threadIdx.x];
+      for (int q = 1; q < S; ++q) {
+        s.re += red[threadIdx.x + q * TP].re;
+        s.im += red[threadIdx.x + q * TP].im;
+      }
+      uacc[(int64_t)(t0 + ti) * R + r] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// leaf factors: one block per finest-level box, items (relevant cone, node).
+// W_c at node x = y0 + (h/s) e for a source y = y0 + h u:
+//   v = e - s u, |v|^2 = 1 + s (s|u|^2 - 2<e,u>),
+//   k r (|v| - 1) = k h (s|u|^2 - 2<e,u>) / (|v| + 1)   (bounded phase)
+//   W_c = E1 [ s <v,n> / (h |v|^3) - i ( k <v,n> / |v|^2 + eta / |v| ) ]
+// ---------------------------------------------------------------------------
+constexpr int LEAF_CHUNK = 256;
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, const double* __restrict__ nrm,
+                                              const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
+                                              const double* __restrict__ centre, const int* __restrict__ slot_off,
+                                              const int* __restrict__ rel_cone, LevelGeom g, ChebTab ct, double k,
+                                              double eta, int kind, cpx<T>* __restrict__ Fn) {
+  constexpr int P = PS * PA * PA;
+  __shared__ T su[LEAF_CHUNK][3];
+  __shared__ T sn[LEAF_CHUNK][3];
+  __shared__ T suu[LEAF_CHUNK], sun[LEAF_CHUNK];
+  __shared__ cpx<T> sa[LEAF_CHUNK];
+  const int b = blockIdx.x, r = blockIdx.y;
+  const int s0 = slot_off[b], ncn = slot_off[b + 1] - s0;
+  const int p0 = start[b], np = start[b + 1] - p0;
+  const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
+  const double invh = 1.0 / g.h;
+  const T kk = (T)k, ee = (T)eta, kh = (T)(k * g.h), ih = (T)invh;
+  const int nitems = ncn * P;
+  for (int ib = 0; ib < nitems; ib += TPB) {
+    const int it = ib + threadIdx.x;
+    const bool valid = it < nitems;
+    T e[3] = {0, 0, 0}, s = 0;
+    if (valid) {
+      int cs = it / P, node = it % P;
+      int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
+      int cid = rel_cone[s0 + cs];
+      if constexpr (Prec<T>::f32) node_dir32(cid, ai, bi, ci, g, ct, e, &s);
+      else node_dir64(cid, ai, bi, ci, g, ct, e, &s);
+    }
+    cpx<T> acc = {0, 0};
+    for (int cb = 0; cb < np; cb += LEAF_CHUNK) {
+      const int cn = min(LEAF_CHUNK, np - cb);
+      __syncthreads();
+      for (int q = threadIdx.x; q < cn; q += TPB) {
+        int j = p0 + cb + q;
+        T u0 = (T)((pts[3 * j] - c0) * invh), u1 = (T)((pts[3 * j + 1] - c1) * invh),
+          u2 = (T)((pts[3 * j + 2] - c2) * invh);
+        T n0 = (T)nrm[3 * j], n1 = (T)nrm[3 * j + 1], n2 = (T)nrm[3 * j + 2];
+        su[q][0] = u0;
+        su[q][1] = u1;
+        su[q][2] = u2;
+        sn[q][0] = n0;
+        sn[q][1] = n1;
+        sn[q][2] = n2;
+        suu[q] = u0 * u0 + u1 * u1 + u2 * u2;
+        sun[q] = u0 * n0 + u1 * n1 + u2 * n2;
+        sa[q] = a[(int64_t)j * R + r];
+      }
+      __syncthreads();
+      if (valid) {
+        for (int q = 0; q < cn; ++q) {
+          cpx<T> W;
+          if (kind == IFGF_KERNEL_CONSTANT) {
+            W = {1, 0};
+          } else {
+            T eu = e[0] * su[q][0] + e[1] * su[q][1] + e[2] * su[q][2];
+            T en = e[0] * sn[q][0] + e[1] * sn[q][1] + e[2] * sn[q][2];
+            T qq = s * suu[q] - (T)2 * eu;
+            T nv = sqrt_t<T>((T)1 + s * qq);
+            T inv = (T)1 / nv;
+            T ph = kh * qq / (nv + (T)1);
+            T sp, cp;
+            sincos_t<T>(ph, &sp, &cp);
+            T vn = en - s * sun[q];
+            T A = vn * s * inv * inv * inv * ih;
+            T B = kk * vn * inv * inv + ee * inv;
+            W = {cp * A + sp * B, sp * A - cp * B};
+          }
+          cpx<T> av = sa[q];
+          acc.re += W.re * av.re - W.im * av.im;
+          acc.im += W.re * av.im + W.im * av.re;
+        }
+      }
+    }
+    if (valid) Fn[((int64_t)(s0 + it / P) * R + r) * P + it % P] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// node values -> coefficients: c_ijl = sum_abc Ms[i][a] Ma[j][b] Ma[l][c] v_abc,
+// one block per cone, three separable passes through LDS.
+// ---------------------------------------------------------------------------
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, int nrel, int R,
+                                                const T* __restrict__ Ms, const T* __restrict__ Ma,
+                                                cpx<T>* __restrict__ Fc) {
+  constexpr int P = PS * PA * PA;
+  static_assert(P <= TPB, "one cone per block");
+  __shared__ cpx<T> v0[P], v1[P];
+  __shared__ T ms[PS * PS], ma[PA * PA];
+  const int sl = blockIdx.x, r = blockIdx.y, t = threadIdx.x;
+  if (t < PS * PS) ms[t] = Ms[t];
+  if (t < PA * PA) ma[t] = Ma[t];
+  if (t < P) v0[t] = Fn[((int64_t)sl * R + r) * P + t];
+  __syncthreads();
+  int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
+  if (t < P) {  // over a (s)
+    cpx<T> s = {0, 0};
+    for (int q = 0; q < PS; ++q) {
+      cpx<T> x = v0[(q * PA + j) * PA + l];
+      s.re += ms[i * PS + q] * x.re;
+      s.im += ms[i * PS + q] * x.im;
+    }
+    v1[t] = s;
+  }
+  __syncthreads();
+  if (t < P) {  // over b (theta)
+    cpx<T> s = {0, 0};
+    for (int q = 0; q < PA; ++q) {
+      cpx<T> x = v1[(i * PA + q) * PA + l];
+      s.re += ma[j * PA + q] * x.re;
+      s.im += ma[j * PA + q] * x.im;
+    }
+    v0[t] = s;
+  }
+  __syncthreads();
+  if (t < P) {  // over c (phi)
+    cpx<T> s = {0, 0};
+    for (int q = 0; q < PA; ++q) {
+      cpx<T> x = v0[(i * PA + j) * PA + q];
+      s.re += ma[l * PA + q] * x.re;
+      s.im += ma[l * PA + q] * x.im;
+    }
+    Fc[((int64_t)sl * R + r) * P + t] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Interpolant evaluation with wave-uniform coefficients.
+// ---------------------------------------------------------------------------
+// Coefficients are read through the constant address space: they are not
+// written while an apply kernel runs, and with a wave-uniform address the
+// reads become scalar loads shared by the wave.
+template <typename T> using cptr = const __attribute__((address_space(4))) cpx<T>*;
+
+template <typename T, int PS, int PA>
+__device__ __forceinline__ cpx<T> contract(cptr<T> C, const T* Ts, const T* Tt, const T* Tp) {
+  cpx<T> acc = {0, 0};
+#pragma unroll
+  for (int i = 0; i < PS; ++i) {
+    cpx<T> h = {0, 0};
+#pragma unroll
+    for (int j = 0; j < PA; ++j) {
+      cpx<T> gsum = {0, 0};
+#pragma unroll
+      for (int l = 0; l < PA; ++l) {
+        cpx<T> c = C[(i * PA + j) * PA + l];
+        gsum.re += c.re * Tp[l];
+        gsum.im += c.im * Tp[l];
+      }
+      h.re += gsum.re * Tt[j];
+      h.im += gsum.im * Tt[j];
+    }
+    acc.re += h.re * Ts[i];
+    acc.im += h.im * Ts[i];
+  }
+  return acc;
+}
+
+// For every active lane with slot >= 0, evaluates the interpolant of cone
+// `slot` of F (coefficient layout [slot][R][P], right-hand side r) at
+// (ts, tt, tp).
+template <typename T, int PS, int PA>
+__device__ __forceinline__ cpx<T> eval_uniform(const cpx<T>* __restrict__ F, int slot, int R, int r, T ts, T tt,
+                                               T tp) {
+  constexpr int P = PS * PA * PA;
+  T Ts[PS], Tt[PA], Tp[PA];
+  cheb_T<T, PS>(ts, Ts);
+  cheb_T<T, PA>(tt, Tt);
+  cheb_T<T, PA>(tp, Tp);
+  cpx<T> out = {0, 0};
+  uint64_t pending = __ballot(slot >= 0);
+  while (pending) {
+    int lead = first_lane(pending);
+    int su = __builtin_amdgcn_readfirstlane(__shfl(slot, lead, 64));
+    bool mine = slot == su;
+    pending &= ~__ballot(mine);
+    if (mine) {
+      // the offset is made wave-uniform here, inside the branch: the compiler
+      // may otherwise rewrite su as the (equal, per-lane) slot
+      uint64_t off = (uint64_t)(((int64_t)su * R + r) * P);
+      uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)off);
+      uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(off >> 32));
+      out = contract<T, PS, PA>((cptr<T>)(F + (((uint64_t)hi << 32) | lo)), Ts, Tt, Tp);
+    }
+  }
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// upward pass d -> d-1: one lane per (relevant parent cone, node).
+// ---------------------------------------------------------------------------
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_prop(int nrel_up, const int* __restrict__ rel_box_up,
+                                              const int* __restrict__ rel_cone_up, const int* __restrict__ child_lo_up,
+                                              const int* __restrict__ coords, const int* __restrict__ slot_c,
+                                              const cpx<T>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct,
+                                              double k, int kind, int R, cpx<T>* __restrict__ Fn_up,
+                                              int* __restrict__ err) {
+  constexpr int P = PS * PA * PA;
+  const int r = blockIdx.y;
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= (int64_t)nrel_up * P) return;
+  const int s = (int)(t / P), node = (int)(t % P);
+  const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
+  const int Pb = rel_box_up[s], pcid = rel_cone_up[s];
+  const int B0 = child_lo_up[Pb], B1 = child_lo_up[Pb + 1];
+  cpx<T> acc = {0, 0};
+  for (int B = B0; B < B1; ++B) {
+    const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+    T ts, tt, tp, ratio_re, ratio_im;
+    int cid;
+    if constexpr (Prec<T>::f32) {
+      PropF pr = prop_loc32(pcid, ai, bi, ci, oct, gp, gc, ct);
+      cid = pr.loc.cid;
+      ts = pr.loc.ts;
+      tt = pr.loc.tt;
+      tp = pr.loc.tp;
+      float sn_, cs_;
+      sincosf((float)k * pr.dr, &sn_, &cs_);
+      ratio_re = pr.rp_over_rc * cs_;
+      ratio_im = pr.rp_over_rc * sn_;
+    } else {
+      Prop64 pr = prop_loc64(pcid, ai, bi, ci, oct, gp, gc, ct);
+      cid = pr.loc.cid;
+      ts = pr.loc.ts;
+      tt = pr.loc.tt;
+      tp = pr.loc.tp;
+      double sn_, cs_;
+      sincos(k * pr.dr, &sn_, &cs_);
+      ratio_re = pr.rp_over_rc * cs_;
+      ratio_im = pr.rp_over_rc * sn_;
+    }
+    if (kind == IFGF_KERNEL_CONSTANT) {
+      ratio_re = 1;
+      ratio_im = 0;
+    }
+    int sl = slot_c[(int64_t)B * gc.ncone + cid];
+    if (sl < 0) atomicOr(err, 2);
+    cpx<T> v = eval_uniform<T, PS, PA>(Fc_c, sl, R, r, ts, tt, tp);
+    acc.re += ratio_re * v.re - ratio_im * v.im;
+    acc.im += ratio_re * v.im + ratio_im * v.re;
+  }
+  Fn_up[((int64_t)s * R + r) * P + node] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// cousin targets for a range of levels + near-field sum, scattered to the
+// caller's order.
+// ---------------------------------------------------------------------------
+template <typename T> struct TLevel {
+  const int* pbox;
+  const int* cou_off;
+  const int* cou;
+  const double* centre;
+  const int* slot;
+  const cpx<T>* Fc;
+  LevelGeom g;
+};
+template <typename T> struct TLevels {
+  TLevel<T> lv[IFGF_MAX_LEVELS];
+};
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts, int64_t n, const int* __restrict__ perm,
+                                                 const cpx<T>* __restrict__ uacc, int use_near, TLevels<T> L,
+                                                 int dlo, int dhi, double k, int kind, int R, int dtype, int conj_out,
+                                                 const double* __restrict__ wout, void* __restrict__ u,
+                                                 int* __restrict__ err) {
+  const int r = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  const double* x = pts + 3 * i;
+  double acc_re = 0, acc_im = 0;
+  if (use_near) {
+    cpx<T> v = uacc[i * R + r];
+    acc_re = v.re;
+    acc_im = v.im;
+  }
+  const double inv4pi = 1.0 / (4.0 * IFGF_PI);
+  for (int d = dhi; d >= dlo; --d) {
+    const TLevel<T>& lv = L.lv[d];
+    const int A = lv.pbox[i];
+    cpx<T> lacc = {0, 0};
+    for (int t = lv.cou_off[A]; t < lv.cou_off[A + 1]; ++t) {
+      const int B = lv.cou[t];
+      double rr;
+      T ts, tt, tp, e_re, e_im;
+      int cid;
+      if constexpr (Prec<T>::f32) {
+        LocF loc = target_loc32(x, lv.centre + 3 * B, lv.g, &rr);
+        cid = loc.cid;
+        ts = loc.ts;
+        tt = loc.tt;
+        tp = loc.tp;
+        float c, s;
+        expi_reduced32(k * rr, &c, &s);
+        float g = (float)inv4pi / (float)rr;
+        e_re = g * c;
+        e_im = g * s;
+      } else {
+        Loc loc = target_loc64(x, lv.centre + 3 * B, lv.g, &rr);
+        cid = loc.cid;
+        ts = loc.ts;
+        tt = loc.tt;
+        tp = loc.tp;
+        double c, s;
+        sincos(k * rr, &s, &c);
+        double g = inv4pi / rr;
+        e_re = g * c;
+        e_im = g * s;
+      }
+      if (kind == IFGF_KERNEL_CONSTANT) {
+        e_re = 1;
+        e_im = 0;
+      }
+      int sl = lv.slot[(int64_t)B * lv.g.ncone + cid];
+      if (sl < 0) atomicOr(err, 4);
+      cpx<T> v = eval_uniform<T, PS, PA>(lv.Fc, sl, R, r, ts, tt, tp);
+      lacc.re += e_re * v.re - e_im * v.im;
+      lacc.im += e_re * v.im + e_im * v.re;
+    }
+    acc_re += lacc.re;
+    acc_im += lacc.im;
+  }
+  if (wout) {
+    acc_re *= wout[i];
+    acc_im *= wout[i];
+  }
+  if (conj_out) acc_im = -acc_im;
+  const int64_t o = (int64_t)perm[i] * R + r;
+  if (dtype == IFGF_C128) {
+    ((double*)u)[2 * o] = acc_re;
+    ((double*)u)[2 * o + 1] = acc_im;
+  } else {
+    ((float*)u)[2 * o] = (float)acc_re;
+    ((float*)u)[2 * o + 1] = (float)acc_im;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <typename T, int PS, int PA>
+void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, int stage_mask, int level_lo,
+                int level_hi, hipStream_t s) {
+  constexpr int P = PS * PA * PA;
+  const int64_t n = p->n;
+  const int D = p->D;
+  cpx<T>* a = p->a.as<cpx<T>>();
+  cpx<T>* uacc = p->uacc.as<cpx<T>>();
+  dim3 gpts(nblocks(n), R);
+  k_gather<T><<<gpts, TPB, 0, s>>>(sigma, dtype, 0, p->perm.as<int>(), p->w.as<double>(), n, R, a);
+  HIPCHK(hipGetLastError());
+  const int kind = p->opt.kernel;
+  LevelPlan& lD = p->lev[D];
+  const bool near = stage_mask & 1;
+  if (near) {
+    k_near<T><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
+                                            lD.nbr_off.as<int>(), lD.nbr.as<int>(), lD.centre.as<double>(), p->k,
+                                            p->eta, kind, uacc);
+    HIPCHK(hipGetLastError());
+  }
+  if (D >= 3) {
+    const T* Ms = (const T*)(Prec<T>::f32 ? p->Msf.p : p->Ms.p);
+    const T* Ma = (const T*)(Prec<T>::f32 ? p->Maf.p : p->Ma.p);
+    k_leaf<T, PS, PA><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R,
+                                                     lD.start.as<int>(), lD.centre.as<double>(), lD.slot_off.as<int>(),
+                                                     lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta, kind,
+                                                     lD.Fn.as<cpx<T>>());
+    HIPCHK(hipGetLastError());
+    if (lD.nrel > 0) {
+      k_coeffs<T, PS, PA><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma, lD.Fc.as<cpx<T>>());
+      HIPCHK(hipGetLastError());
+    }
+    for (int d = D; d >= 4; --d) {
+      LevelPlan& lc = p->lev[d];
+      LevelPlan& lp = p->lev[d - 1];
+      if (lp.nrel == 0) continue;
+      int64_t items = (int64_t)lp.nrel * P;
+      k_prop<T, PS, PA><<<dim3(nblocks(items), R), TPB, 0, s>>>(
+          lp.nrel, lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
+          lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, p->k, kind, R, lp.Fn.as<cpx<T>>(),
+          p->err.as<int>());
+      HIPCHK(hipGetLastError());
+      k_coeffs<T, PS, PA><<<dim3(lp.nrel, R), TPB, 0, s>>>(lp.Fn.as<cpx<T>>(), lp.nrel, R, Ms, Ma, lp.Fc.as<cpx<T>>());
+      HIPCHK(hipGetLastError());
+    }
+  }
+  TLevels<T> L{};
+  for (int d = 3; d <= D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    L.lv[d] = {lv.pbox.as<int>(), lv.cou_off.as<int>(), lv.cou.as<int>(), lv.centre.as<double>(),
+               lv.slot.as<int>(), lv.Fc.as<cpx<T>>(), lv.geom};
+  }
+  int dlo = 3, dhi = D;
+  if (!(stage_mask & 2)) {
+    dlo = 1;
+    dhi = 0;
+  } else {
+    dlo = std::max(dlo, level_lo);
+    dhi = std::min(dhi, level_hi);
+  }
+  k_targets<T, PS, PA><<<gpts, TPB, 0, s>>>(p->pts.as<double>(), n, p->perm.as<int>(), uacc, near ? 1 : 0, L, dlo, dhi,
+                                            p->k, kind, R, dtype, 0, nullptr, u, p->err.as<int>());
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+void dispatch_apply(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, int stage_mask, int lo, int hi,
+                    hipStream_t s) {
+  int ps = p->opt.p_s, pa = p->opt.p_ang;
+  if (ps == 3 && pa == 5) return apply_impl<T, 3, 5>(p, sigma, u, R, dtype, stage_mask, lo, hi, s);
+  if (ps == 4 && pa == 6) return apply_impl<T, 4, 6>(p, sigma, u, R, dtype, stage_mask, lo, hi, s);
+  throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
+}
+
+}  // namespace
+
+bool supported_order(int ps, int pa) { return (ps == 3 && pa == 5) || (ps == 4 && pa == 6); }
+
+void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask, int level_lo,
+               int level_hi, hipStream_t s) {
+  if (p->opt.precision == IFGF_PREC_FP32_INTERP)
+    dispatch_apply<float>(p, sigma, u, nrhs, dtype, stage_mask, level_lo, level_hi, s);
+  else
+    dispatch_apply<double>(p, sigma, u, nrhs, dtype, stage_mask, level_lo, level_hi, s);
+  p->last_rhs = nrhs;
+}
+
+void run_adjoint(ifgf_plan_s*, const void*, void*, int, int, int, hipStream_t) {
+  throw Error{IFGF_EUNSUPPORTED, "transposed apply not built yet"};
+}
+
+}  // namespace ifgf

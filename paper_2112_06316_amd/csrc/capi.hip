@@ -1,0 +1,274 @@
+// C ABI of the IFGF library: argument checks, status codes, plan lifetime,
+// statistics and test hooks.  Nothing throws across this boundary.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+namespace ifgf {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& m) { g_last_error = m; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+      throw Error{IFGF_ENOMEM, std::string(what) + ": " + hipGetErrorString(e)};
+    throw Error{IFGF_EHIP, std::string(what) + ": " + hipGetErrorString(e)};
+  }
+}
+
+void DevBuf::alloc(size_t nbytes) {
+  release();
+  if (nbytes == 0) nbytes = 16;
+  hipError_t e = hipMalloc(&p, nbytes);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw Error{IFGF_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed"};
+  }
+  bytes = nbytes;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+DevBuf::~DevBuf() { release(); }
+
+}  // namespace ifgf
+
+using namespace ifgf;
+
+template <typename F> static ifgf_status guarded(F&& f) {
+  try {
+    f();
+    set_last_error("");
+    return IFGF_OK;
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return IFGF_ENOMEM;
+  } catch (...) {
+    set_last_error("unexpected exception");
+    return IFGF_EINTERNAL;
+  }
+}
+
+struct BusyGuard {
+  ifgf_plan_s* p;
+  bool ok;
+  explicit BusyGuard(ifgf_plan_s* pp) : p(pp) {
+    int expect = 0;
+    ok = p->busy.compare_exchange_strong(expect, 1);
+  }
+  ~BusyGuard() {
+    if (ok) p->busy.store(0);
+  }
+};
+
+extern "C" {
+
+void ifgf_options_default(ifgf_options* o) {
+  if (!o) return;
+  o->p_s = 4;
+  o->p_ang = 6;
+  o->ns0 = 2;
+  o->nc0 = 4;
+  o->depth = 0;
+  o->leaf_h_lambda = 0.5;
+  o->precision = IFGF_PREC_FP32_INTERP;
+  o->max_rhs = 1;
+  o->kernel = IFGF_KERNEL_COMBINED;
+}
+
+const char* ifgf_status_string(ifgf_status st) {
+  switch (st) {
+    case IFGF_OK: return "ok";
+    case IFGF_EINVAL: return "invalid argument";
+    case IFGF_EDUPLICATE: return "duplicate points";
+    case IFGF_ENOMEM: return "out of memory";
+    case IFGF_EHIP: return "HIP error";
+    case IFGF_EUNSUPPORTED: return "unsupported option";
+    case IFGF_EBUSY: return "plan busy";
+    case IFGF_EINTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* ifgf_last_error(void) { return g_last_error.c_str(); }
+
+ifgf_status ifgf_plan_create(ifgf_plan* out, int64_t n, const double* points, const double* normals,
+                             const double* weights, double k, double eta, const ifgf_options* opt, void* stream) {
+  if (out) *out = nullptr;
+  ifgf_plan_s* p = nullptr;
+  ifgf_status st = guarded([&] {
+    if (!out || !points || !normals || !weights) throw Error{IFGF_EINVAL, "null pointer argument"};
+    if (n < 1 || n > (int64_t)0x7fffffff) throw Error{IFGF_EINVAL, "n out of range"};
+    if (!(k > 0.0) || !std::isfinite(k) || !std::isfinite(eta)) throw Error{IFGF_EINVAL, "k must be finite and > 0"};
+    ifgf_options o;
+    ifgf_options_default(&o);
+    if (opt) o = *opt;
+    if (o.p_s < 1 || o.p_ang < 1 || o.p_s > IFGF_MAXP || o.p_ang > IFGF_MAXP) throw Error{IFGF_EINVAL, "bad p_s/p_ang"};
+    if (o.ns0 < 1 || o.nc0 < 1) throw Error{IFGF_EINVAL, "bad ns0/nc0"};
+    if (o.depth < 0 || o.depth > 11) throw Error{IFGF_EINVAL, "depth must be in 0..11"};
+    if (o.depth == 0 && !(o.leaf_h_lambda > 0.0)) throw Error{IFGF_EINVAL, "leaf_h_lambda must be > 0"};
+    if (o.precision != IFGF_PREC_FP64 && o.precision != IFGF_PREC_FP32_INTERP) throw Error{IFGF_EINVAL, "bad precision"};
+    if (o.max_rhs < 1) throw Error{IFGF_EINVAL, "max_rhs must be >= 1"};
+    if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
+    if (!supported_order(o.p_s, o.p_ang)) throw Error{IFGF_EUNSUPPORTED, "p_s/p_ang pair not compiled in"};
+    p = new ifgf_plan_s();
+    p->n = n;
+    p->k = k;
+    p->eta = eta;
+    p->opt = o;
+    p->P = o.p_s * o.p_ang * o.p_ang;
+    build_plan(p, points, normals, weights, (hipStream_t)stream);
+    *out = p;
+  });
+  if (st != IFGF_OK) {
+    delete p;
+  }
+  return st;
+}
+
+static void check_apply_args(ifgf_plan p, const void* in, void* outp, int32_t nrhs, int32_t dtype) {
+  if (!p || !in || !outp) throw Error{IFGF_EINVAL, "null pointer argument"};
+  if (in == outp) throw Error{IFGF_EINVAL, "input and output alias"};
+  if (nrhs < 1 || nrhs > p->opt.max_rhs) throw Error{IFGF_EINVAL, "nrhs out of range (1..max_rhs)"};
+  if (dtype != IFGF_C64 && dtype != IFGF_C128) throw Error{IFGF_EINVAL, "bad dtype"};
+}
+
+ifgf_status ifgf_apply(ifgf_plan p, const void* sigma, void* u, int32_t nrhs, int32_t dtype, void* stream) {
+  return ifgf_apply_stages(p, sigma, u, nrhs, dtype, 3, 0, 1 << 20, stream);
+}
+
+ifgf_status ifgf_apply_stages(ifgf_plan p, const void* sigma, void* u, int32_t nrhs, int32_t dtype, int32_t stage_mask,
+                              int32_t level_lo, int32_t level_hi, void* stream) {
+  return guarded([&] {
+    check_apply_args(p, sigma, u, nrhs, dtype);
+    BusyGuard g(p);
+    if (!g.ok) throw Error{IFGF_EBUSY, "another apply on this plan is being enqueued"};
+    run_apply(p, sigma, u, nrhs, dtype, stage_mask, level_lo, level_hi, (hipStream_t)stream);
+  });
+}
+
+ifgf_status ifgf_apply_adjoint(ifgf_plan p, const void* v, void* out, int32_t nrhs, int32_t dtype, int32_t conjugate,
+                               void* stream) {
+  return guarded([&] {
+    check_apply_args(p, v, out, nrhs, dtype);
+    BusyGuard g(p);
+    if (!g.ok) throw Error{IFGF_EBUSY, "another apply on this plan is being enqueued"};
+    run_adjoint(p, v, out, nrhs, dtype, conjugate ? 1 : 0, (hipStream_t)stream);
+  });
+}
+
+ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
+  return guarded([&] {
+    if (!p || !st) throw Error{IFGF_EINVAL, "null pointer argument"};
+    std::memset(st, 0, sizeof(*st));
+    st->depth = p->D;
+    st->n = p->n;
+    st->root_side = p->L;
+    for (int a = 0; a < 3; ++a) st->root_corner[a] = p->corner[a];
+    st->p_s = p->opt.p_s;
+    st->p_ang = p->opt.p_ang;
+    st->precision = p->opt.precision;
+    int64_t bytes = 0;
+    auto add = [&](const DevBuf& b) { bytes += (int64_t)b.bytes; };
+    add(p->perm); add(p->keys); add(p->pts); add(p->nrm); add(p->w); add(p->a); add(p->uacc); add(p->err);
+    add(p->Ms); add(p->Ma); add(p->Msf); add(p->Maf);
+    for (int d = 1; d <= p->D; ++d) {
+      const LevelPlan& l = p->lev[d];
+      st->boxes[d] = l.nb;
+      st->ns[d] = l.geom.ns;
+      st->nc[d] = l.geom.nc;
+      st->cones[d] = l.nrel;
+      st->cousin_pairs[d] = l.cousin_pairs;
+      st->prop_evals[d] = l.prop_evals;
+      add(l.start); add(l.coords); add(l.centre); add(l.parent); add(l.child_lo); add(l.nbr_off); add(l.nbr);
+      add(l.cou_off); add(l.cou); add(l.pbox); add(l.slot); add(l.slot_off); add(l.rel_box); add(l.rel_cone);
+      add(l.Fn); add(l.Fc);
+      add(p->adj_g[d]);
+    }
+    st->near_pairs = p->near_pairs;
+    st->device_bytes = bytes;
+  });
+}
+
+static void sync_copy(void* dst, const void* src, size_t bytes) {
+  HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToDevice));
+}
+
+ifgf_status ifgf_plan_export_order(ifgf_plan p, int32_t* perm, uint32_t* keys) {
+  return guarded([&] {
+    if (!p) throw Error{IFGF_EINVAL, "null plan"};
+    if (perm) sync_copy(perm, p->perm.p, sizeof(int) * p->n);
+    if (keys) sync_copy(keys, p->keys.p, sizeof(uint32_t) * p->n);
+  });
+}
+
+ifgf_status ifgf_plan_export_boxes(ifgf_plan p, int32_t d, int32_t* start, int32_t* coords) {
+  return guarded([&] {
+    if (!p || d < 1 || d > p->D) throw Error{IFGF_EINVAL, "bad plan or level"};
+    const LevelPlan& l = p->lev[d];
+    if (start) sync_copy(start, l.start.p, sizeof(int) * (l.nb + 1));
+    if (coords) sync_copy(coords, l.coords.p, sizeof(int) * 3 * l.nb);
+  });
+}
+
+ifgf_status ifgf_plan_export_lists(ifgf_plan p, int32_t d, int32_t kind, int32_t* off, int32_t* idx, int64_t* len) {
+  return guarded([&] {
+    if (!p || d < 1 || d > p->D) throw Error{IFGF_EINVAL, "bad plan or level"};
+    if (kind == 1 && d < 3) throw Error{IFGF_EINVAL, "cousin lists exist for d >= 3"};
+    const LevelPlan& l = p->lev[d];
+    const DevBuf& o = kind == 0 ? l.nbr_off : l.cou_off;
+    const DevBuf& x = kind == 0 ? l.nbr : l.cou;
+    int64_t cnt = kind == 0 ? l.nnbr : l.ncou;
+    if (len) *len = cnt;
+    if (off) sync_copy(off, o.p, sizeof(int) * (l.nb + 1));
+    if (idx && cnt > 0) sync_copy(idx, x.p, sizeof(int) * cnt);
+  });
+}
+
+ifgf_status ifgf_plan_export_cones(ifgf_plan p, int32_t d, int32_t* box, int32_t* cone) {
+  return guarded([&] {
+    if (!p || d < 3 || d > p->D) throw Error{IFGF_EINVAL, "bad plan or level"};
+    const LevelPlan& l = p->lev[d];
+    if (l.nrel == 0) return;
+    if (box) sync_copy(box, l.rel_box.p, sizeof(int) * l.nrel);
+    if (cone) sync_copy(cone, l.rel_cone.p, sizeof(int) * l.nrel);
+  });
+}
+
+ifgf_status ifgf_plan_export_field(ifgf_plan p, int32_t d, int32_t what, void* dst) {
+  return guarded([&] {
+    if (!p || !dst || d < 3 || d > p->D) throw Error{IFGF_EINVAL, "bad plan, level or pointer"};
+    const LevelPlan& l = p->lev[d];
+    size_t csz = p->opt.precision == IFGF_PREC_FP32_INTERP ? 8 : 16;
+    size_t bytes = csz * (size_t)l.nrel * p->P * std::max(1, p->last_rhs);
+    if (bytes) sync_copy(dst, (what == 0 ? l.Fn : l.Fc).p, bytes);
+  });
+}
+
+ifgf_status ifgf_plan_check(ifgf_plan p, int32_t* flags) {
+  return guarded([&] {
+    if (!p || !flags) throw Error{IFGF_EINVAL, "null pointer argument"};
+    HIPCHK(hipMemcpy(flags, p->err.p, sizeof(int), hipMemcpyDeviceToHost));
+  });
+}
+
+void ifgf_plan_destroy(ifgf_plan p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  delete p;
+}
+
+}  // extern "C"

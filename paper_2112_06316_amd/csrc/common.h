@@ -1,0 +1,288 @@
+// Internal device/host helpers of the IFGF library (gfx950).
+//
+// Geometry conventions (paper Section 3):
+//   * box B(y0, H) is half-open (eq. box); h = sqrt(3) H / 2 and s = h / r
+//     with r = |x - y0| (eq. def_eps); every interpolation point has
+//     s <= sqrt(3)/3 (eq. s_rest);
+//   * x(s, theta, phi; y0) = y0 + (h/s)(sin th cos ph, sin th sin ph, cos th)
+//     (eqs. defparametrizationins, defparametrizationr);
+//   * cone segment gamma = (i_s, i_th, i_ph) of a box with n_s x n_C x 2n_C
+//     segments, ds = sqrt(3)/3 / n_s, dth = dph = pi / n_C (eqs. deltas,
+//     ConeIntervals); its id is (i_s * n_C + i_th) * 2 n_C + i_ph, i.e. the
+//     radial index is the slowest and the azimuthal the fastest;
+//   * indices are floor(value / interval) clamped to the last interval, so
+//     the closed upper ends s = sqrt(3)/3, theta = pi, phi -> 2 pi belong to
+//     the last segment;
+//   * interpolation nodes are tensor products of first-kind Chebyshev points
+//     cos((2k+1) pi / (2n)) mapped affinely to each interval (eq.
+//     ChebyNodes); local coordinates t in [-1, 1].
+//
+// The same locate function is used when relevant cones are marked at plan
+// time and when they are looked up at apply time, with floating-point
+// contraction disabled inside it, so both compute bit-identical cone ids.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define IFGF_MAXP 16        // max points per interpolation axis
+#define IFGF_PI 3.14159265358979323846
+#define IFGF_TWO_PI 6.28318530717958647692
+
+template <typename T> struct cpx { T re, im; };
+
+template <typename T> __host__ __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// Per-level cone-segment geometry, passed to kernels by value.
+struct LevelGeom {
+  double H;          // box side
+  double h;          // sqrt(3)/2 * H
+  float hf;          // h in FP32
+  int ns, nc;        // n_s, n_C
+  int ncone;         // n_s * n_C * 2 n_C
+  double ds, da;     // sqrt(3)/3 / n_s, pi / n_C
+  double inv_ds, inv_da;
+  float dsf, daf, inv_dsf, inv_daf;
+};
+
+// Chebyshev node offsets u_k = (1 + x_k) / 2 in [0, 1] per axis, and the
+// node-value -> coefficient matrices (row i: (2 - delta_i0)/n T_i(x_k)).
+struct ChebTab {
+  int ps, pa;
+  double us[IFGF_MAXP], ua[IFGF_MAXP];
+  float usf[IFGF_MAXP], uaf[IFGF_MAXP];
+};
+
+struct Loc {
+  int cid;
+  double ts, tt, tp;   // local coordinates in [-1, 1]
+};
+struct LocF {
+  int cid;
+  float ts, tt, tp;
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// ---------------------------------------------------------------------------
+// Cone location, FP64: relative vector d = x - y0 and s = h / |d|.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Loc locate64(double dx, double dy, double dz, double s, const LevelGeom& g) {
+#pragma clang fp contract(off)
+  Loc L;
+  double rho = sqrt(dx * dx + dy * dy);
+  double th = atan2(rho, dz);
+  double ph = atan2(dy, dx);
+  if (ph < 0.0) ph += IFGF_TWO_PI;
+  double us = s / g.ds, ut = th / g.da, up = ph / g.da;   // correctly rounded quotients
+  int is = clampi((int)floor(us), 0, g.ns - 1);
+  int it = clampi((int)floor(ut), 0, g.nc - 1);
+  int ip = clampi((int)floor(up), 0, 2 * g.nc - 1);
+  L.cid = (is * g.nc + it) * (2 * g.nc) + ip;
+  L.ts = 2.0 * (us - is) - 1.0;
+  L.tt = 2.0 * (ut - it) - 1.0;
+  L.tp = 2.0 * (up - ip) - 1.0;
+  return L;
+}
+
+// Cone location, FP32 (used by the FP32-interpolation precision mode).
+__device__ __forceinline__ LocF locate32(float dx, float dy, float dz, float s, const LevelGeom& g) {
+#pragma clang fp contract(off)
+  LocF L;
+  float rho = sqrtf(dx * dx + dy * dy);
+  float th = atan2f(rho, dz);
+  float ph = atan2f(dy, dx);
+  if (ph < 0.0f) ph += (float)IFGF_TWO_PI;
+  float us = s * g.inv_dsf, ut = th * g.inv_daf, up = ph * g.inv_daf;
+  int is = clampi((int)floorf(us), 0, g.ns - 1);
+  int it = clampi((int)floorf(ut), 0, g.nc - 1);
+  int ip = clampi((int)floorf(up), 0, 2 * g.nc - 1);
+  L.cid = (is * g.nc + it) * (2 * g.nc) + ip;
+  L.ts = 2.0f * (us - (float)is) - 1.0f;
+  L.tt = 2.0f * (ut - (float)it) - 1.0f;
+  L.tp = 2.0f * (up - (float)ip) - 1.0f;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// A surface point x about a box centre c (cousin-target interpolation and
+// the marking of cousin points).  Returns the location and r = |x - c| in
+// FP64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ Loc target_loc64(const double* x, const double* c, const LevelGeom& g, double* r_out) {
+#pragma clang fp contract(off)
+  double dx = x[0] - c[0], dy = x[1] - c[1], dz = x[2] - c[2];
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  *r_out = r;
+  return locate64(dx, dy, dz, g.h / r, g);
+}
+
+__device__ __forceinline__ LocF target_loc32(const double* x, const double* c, const LevelGeom& g, double* r_out) {
+#pragma clang fp contract(off)
+  double dx = x[0] - c[0], dy = x[1] - c[1], dz = x[2] - c[2];
+  double r = sqrt(dx * dx + dy * dy + dz * dz);
+  *r_out = r;
+  float rf = (float)r;
+  return locate32((float)dx, (float)dy, (float)dz, g.hf / rf, g);
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation node of a cone: position relative to the box centre.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cone_split(int cid, int nc, int* is, int* it, int* ip) {
+  int nph = 2 * nc;
+  *ip = cid % nph;
+  int rest = cid / nph;
+  *it = rest % nc;
+  *is = rest / nc;
+}
+
+// node (a, b, c) of cone cid: unit direction e, s and r = h / s
+__device__ __forceinline__ void node_dir64(int cid, int a, int b, int c, const LevelGeom& g, const ChebTab& ct,
+                                           double* e, double* s_out) {
+#pragma clang fp contract(off)
+  int is, it, ip;
+  cone_split(cid, g.nc, &is, &it, &ip);
+  double s = ((double)is + ct.us[a]) * g.ds;
+  double th = ((double)it + ct.ua[b]) * g.da;
+  double ph = ((double)ip + ct.ua[c]) * g.da;
+  double st, ctt, sp, cp;
+  sincos(th, &st, &ctt);
+  sincos(ph, &sp, &cp);
+  e[0] = st * cp;
+  e[1] = st * sp;
+  e[2] = ctt;
+  *s_out = s;
+}
+
+__device__ __forceinline__ void node_dir32(int cid, int a, int b, int c, const LevelGeom& g, const ChebTab& ct,
+                                           float* e, float* s_out) {
+#pragma clang fp contract(off)
+  int is, it, ip;
+  cone_split(cid, g.nc, &is, &it, &ip);
+  float s = ((float)is + ct.usf[a]) * g.dsf;
+  float th = ((float)it + ct.uaf[b]) * g.daf;
+  float ph = ((float)ip + ct.uaf[c]) * g.daf;
+  float st, ctt, sp, cp;
+  sincosf(th, &st, &ctt);
+  sincosf(ph, &sp, &cp);
+  e[0] = st * cp;
+  e[1] = st * sp;
+  e[2] = ctt;
+  *s_out = s;
+}
+
+// ---------------------------------------------------------------------------
+// A parent-cone node about one of its parent's children (upward pass and
+// the marking of parent nodes).  The child centre is the parent centre
+// plus delta = (+-H_c/2, +-H_c/2, +-H_c/2) by octant bits (x: bit 0,
+// y: bit 1, z: bit 2; bit set = upper half).  Returns the child-cone
+// location, and the ratio of centred factors
+//   K(x, y_child) / K(x, y_parent) = (r_p / r_c) exp(i k (r_c - r_p)),
+// with r_c - r_p = (|delta|^2 - 2 <x - y_p, delta>) / (r_c + r_p), a form
+// free of cancellation (Algorithm 1, the parent-node update).
+// ---------------------------------------------------------------------------
+struct PropF {
+  LocF loc;
+  float rp_over_rc;
+  float dr;            // r_c - r_p
+};
+struct Prop64 {
+  Loc loc;
+  double rp_over_rc;
+  double dr;
+};
+
+__device__ __forceinline__ Prop64 prop_loc64(int pcid, int a, int b, int c, int oct, const LevelGeom& gp,
+                                             const LevelGeom& gc, const ChebTab& ct) {
+#pragma clang fp contract(off)
+  double e[3], s;
+  node_dir64(pcid, a, b, c, gp, ct, e, &s);
+  double rp = gp.h / s;
+  double hd = 0.5 * gc.H;
+  double dl[3] = {(oct & 1) ? hd : -hd, (oct & 2) ? hd : -hd, (oct & 4) ? hd : -hd};
+  double x0 = rp * e[0] - dl[0], x1 = rp * e[1] - dl[1], x2 = rp * e[2] - dl[2];
+  double rc = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
+  Prop64 P;
+  P.loc = locate64(x0, x1, x2, gc.h / rc, gc);
+  double dd = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+  double xd = rp * (e[0] * dl[0] + e[1] * dl[1] + e[2] * dl[2]);
+  P.dr = (dd - 2.0 * xd) / (rc + rp);
+  P.rp_over_rc = rp / rc;
+  return P;
+}
+
+__device__ __forceinline__ PropF prop_loc32(int pcid, int a, int b, int c, int oct, const LevelGeom& gp,
+                                            const LevelGeom& gc, const ChebTab& ct) {
+#pragma clang fp contract(off)
+  float e[3], s;
+  node_dir32(pcid, a, b, c, gp, ct, e, &s);
+  float rp = gp.hf / s;
+  float hd = (float)(0.5 * gc.H);
+  float dl[3] = {(oct & 1) ? hd : -hd, (oct & 2) ? hd : -hd, (oct & 4) ? hd : -hd};
+  float x0 = rp * e[0] - dl[0], x1 = rp * e[1] - dl[1], x2 = rp * e[2] - dl[2];
+  float rc = sqrtf(x0 * x0 + x1 * x1 + x2 * x2);
+  PropF P;
+  P.loc = locate32(x0, x1, x2, gc.hf / rc, gc);
+  float dd = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
+  float xd = rp * (e[0] * dl[0] + e[1] * dl[1] + e[2] * dl[2]);
+  P.dr = (dd - 2.0f * xd) / (rc + rp);
+  P.rp_over_rc = rp / rc;
+  return P;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev polynomials T_0..T_{n-1} at t by the three-term recurrence.
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__device__ __forceinline__ void cheb_T(T t, T* out) {
+  out[0] = (T)1;
+  if (N > 1) out[1] = t;
+#pragma unroll
+  for (int i = 2; i < N; ++i) out[i] = (T)2 * t * out[i - 1] - out[i - 2];
+}
+
+// exp(i phase) for a possibly large FP64 phase: Cody-Waite reduction modulo
+// 2 pi in FP64 with a two-term constant, then FP32 sin/cos of the remainder.
+__device__ __forceinline__ void expi_reduced32(double phase, float* c, float* s) {
+  const double inv2pi = 0.15915494309189533577;
+  const double p_hi = 6.283185307179586232;        // nearest double to 2 pi
+  const double p_lo = 2.4492935982947064e-16;      // 2 pi - p_hi
+  double nq = rint(phase * inv2pi);
+  double red = fma(-nq, p_hi, phase);
+  red = fma(-nq, p_lo, red);
+  sincosf((float)red, s, c);
+}
+
+// ---------------------------------------------------------------------------
+// Morton keys: bit b of ix -> 3b, iy -> 3b + 1, iz -> 3b + 2.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint32_t spread3(uint32_t v) {
+  v &= 0x3ffu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__host__ __device__ __forceinline__ uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x000003FFu;
+  return v;
+}
+__host__ __device__ __forceinline__ uint32_t morton_encode(uint32_t x, uint32_t y, uint32_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+__host__ __device__ __forceinline__ void morton_decode(uint32_t key, int* x, int* y, int* z) {
+  *x = (int)compact3(key);
+  *y = (int)compact3(key >> 1);
+  *z = (int)compact3(key >> 2);
+}
+
+// Wave-level helpers (wave64).
+__device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((unsigned long long)mask) - 1; }

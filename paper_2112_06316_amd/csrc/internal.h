@@ -1,0 +1,108 @@
+// Internal host-side declarations of the IFGF library.
+#pragma once
+
+#include <atomic>
+#include <string>
+#include <vector>
+
+#include "../../include/ifgf.h"
+#include "common.h"
+
+namespace ifgf {
+
+// Thrown inside the library and turned into an ifgf_status at the C ABI.
+struct Error {
+  ifgf_status st;
+  std::string msg;
+};
+
+void hip_check(hipError_t e, const char* what);
+#define HIPCHK(x) ::ifgf::hip_check((x), #x)
+
+void set_last_error(const std::string& m);
+
+// Device buffer owned by the plan.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  ~DevBuf();
+  void alloc(size_t nbytes);
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct LevelPlan {
+  int d = 0;
+  double H = 0;
+  int nb = 0;                 // relevant boxes
+  DevBuf start;               // int [nb + 1] point ranges (Morton order)
+  DevBuf coords;              // int [nb * 3]
+  DevBuf centre;              // double [nb * 3]
+  DevBuf parent;              // int [nb] box index at d - 1 (d >= 2)
+  DevBuf child_lo;            // int [nb + 1] children at d + 1 (d < D)
+  DevBuf nbr_off, nbr;        // neighbour CSR (incl. self)
+  int64_t nnbr = 0;
+  DevBuf cou_off, cou;        // cousin CSR (d >= 3)
+  int64_t ncou = 0;
+  DevBuf pbox;                // int [n] box of each (sorted) point at this level (d >= 3)
+  // cone segments (d >= 3)
+  LevelGeom geom{};
+  DevBuf slot;                // int [nb * ncone] relevant-cone slot or -1
+  DevBuf slot_off;            // int [nb + 1]
+  int nrel = 0;
+  DevBuf rel_box, rel_cone;   // int [nrel]
+  DevBuf Fn, Fc;              // node values / coefficients [nrel][P][max_rhs] complex
+  // statistics
+  int64_t cousin_pairs = 0;
+  int64_t prop_evals = 0;     // child interpolations into level d-1 nodes
+};
+
+}  // namespace ifgf
+
+struct ifgf_plan_s {
+  int64_t n = 0;
+  int D = 0;
+  double k = 0, eta = 0;
+  ifgf_options opt{};
+  int P = 0;                  // p_s * p_ang^2
+  double L = 0, corner[3] = {0, 0, 0};
+  ChebTab cheb{};
+  // Chebyshev node-value -> coefficient matrices (row-major n x n)
+  ifgf::DevBuf Ms, Ma;        // double
+  ifgf::DevBuf Msf, Maf;      // float
+  ifgf::DevBuf perm;          // int [n]: Morton position -> caller index
+  ifgf::DevBuf keys;          // uint32 [n]
+  ifgf::DevBuf pts, nrm, w;   // sorted geometry (double)
+  ifgf::LevelPlan lev[IFGF_MAX_LEVELS];
+  ifgf::DevBuf a;             // gathered coefficients w * sigma, [n][max_rhs] complex (plan precision)
+  ifgf::DevBuf uacc;          // near-field results, [n][max_rhs] complex (plan precision)
+  ifgf::DevBuf adj_g[IFGF_MAX_LEVELS];   // transposed-apply coefficient-space buffers
+  ifgf::DevBuf err;           // int [4] device error flags
+  int64_t near_pairs = 0;
+  std::atomic<int> busy{0};
+  int last_rhs = 0;
+};
+
+namespace ifgf {
+
+// primitives.hip
+void scan_exclusive_u8(const uint8_t* in, int* out, int64_t n, hipStream_t s);   // out[n] = total
+void scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t s);      // out[n] = total
+int64_t sort_padded_length(int64_t n);                                              // capacity sort_u64 needs
+void sort_u64(uint64_t* data, int64_t n, hipStream_t s);                          // ascending, in place
+
+// plan.hip
+void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const double* w, hipStream_t s);
+
+// apply.hip
+void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask,
+               int level_lo, int level_hi, hipStream_t s);
+void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
+
+bool supported_order(int ps, int pa);
+
+}  // namespace ifgf

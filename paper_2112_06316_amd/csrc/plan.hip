@@ -1,0 +1,614 @@
+// Plan construction on the device: root box, Morton keys and sort, per-level
+// box arrays, neighbour and cousin lists, and relevant cone segments.
+//
+// Paper: Section 3.4 (octree of D levels, eq. box, eq. RelevantBoxes,
+// eq. NeighborsCousins, eq. RelevantCones), Section 3.5 (Morton / Z-curve
+// order of boxes, then cones), Remark cone_seg_size (cone counts per level).
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace ifgf {
+
+namespace {
+
+constexpr int TPB = 256;
+inline unsigned nblocks(int64_t n, int tpb = TPB) { return (unsigned)((n + tpb - 1) / tpb); }
+
+// ---------------------------------------------------------------------------
+// a1: bounding box and finiteness check
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_bbox(const double* __restrict__ pts, const double* __restrict__ nrm,
+                                              const double* __restrict__ w, int64_t n,
+                                              double* __restrict__ part, int* __restrict__ bad) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  int nonfinite = 0;
+  for (int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    for (int a = 0; a < 3; ++a) {
+      double x = pts[3 * i + a];
+      lo[a] = fmin(lo[a], x);
+      hi[a] = fmax(hi[a], x);
+      nonfinite |= !isfinite(x) || !isfinite(nrm[3 * i + a]);
+    }
+    nonfinite |= !isfinite(w[i]);
+  }
+  __shared__ double sl[3][TPB], sh[3][TPB];
+  for (int a = 0; a < 3; ++a) {
+    sl[a][threadIdx.x] = lo[a];
+    sh[a][threadIdx.x] = hi[a];
+  }
+  if (nonfinite) atomicOr(bad, 1);
+  __syncthreads();
+  for (int st = TPB / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st)
+      for (int a = 0; a < 3; ++a) {
+        sl[a][threadIdx.x] = fmin(sl[a][threadIdx.x], sl[a][threadIdx.x + st]);
+        sh[a][threadIdx.x] = fmax(sh[a][threadIdx.x], sh[a][threadIdx.x + st]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 3; ++a) {
+      part[6 * blockIdx.x + a] = sl[a][0];
+      part[6 * blockIdx.x + 3 + a] = sh[a][0];
+    }
+}
+
+// a1: leaf box indices by an FP64 multiply and floor (no contraction), Morton
+// key in the high word, original index in the low word.
+__global__ __launch_bounds__(TPB) void k_keys(const double* __restrict__ pts, int64_t n, double c0, double c1,
+                                              double c2, double inv_h, int m, uint64_t* __restrict__ out) {
+#pragma clang fp contract(off)
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  double cc[3] = {c0, c1, c2};
+  uint32_t k[3];
+  for (int a = 0; a < 3; ++a) {
+    double t = floor((pts[3 * i + a] - cc[a]) * inv_h);
+    t = t < 0.0 ? 0.0 : (t > (double)(m - 1) ? (double)(m - 1) : t);
+    k[a] = (uint32_t)t;
+  }
+  uint64_t key = morton_encode(k[0], k[1], k[2]);
+  out[i] = (key << 32) | (uint64_t)i;
+}
+
+__global__ __launch_bounds__(TPB) void k_unpack(const uint64_t* __restrict__ sorted, int64_t n,
+                                                const double* __restrict__ pts, const double* __restrict__ nrm,
+                                                const double* __restrict__ w, int* __restrict__ perm,
+                                                uint32_t* __restrict__ keys, double* __restrict__ spts,
+                                                double* __restrict__ snrm, double* __restrict__ sw) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  uint64_t v = sorted[i];
+  int j = (int)(v & 0xffffffffu);
+  perm[i] = j;
+  keys[i] = (uint32_t)(v >> 32);
+  for (int a = 0; a < 3; ++a) {
+    spts[3 * i + a] = pts[3 * (int64_t)j + a];
+    snrm[3 * i + a] = nrm[3 * (int64_t)j + a];
+  }
+  sw[i] = w[j];
+}
+
+// ---------------------------------------------------------------------------
+// a2: per-level boxes
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_level_flags(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                     uint8_t* __restrict__ flags) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  flags[i] = (i == 0) || ((keys[i] >> shift) != (keys[i - 1] >> shift));
+}
+
+__global__ __launch_bounds__(TPB) void k_level_boxes(const uint32_t* __restrict__ keys, const uint8_t* __restrict__ flags,
+                                                     const int* __restrict__ bid, int64_t n, int shift, int nb,
+                                                     double c0, double c1, double c2, double H,
+                                                     int* __restrict__ start, int* __restrict__ coords,
+                                                     uint32_t* __restrict__ bkey, double* __restrict__ centre,
+                                                     int* __restrict__ pbox) {
+#pragma clang fp contract(off)
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  int b = bid[i] + flags[i] - 1;
+  pbox[i] = b;
+  if (i == 0) start[nb] = (int)n;
+  if (!flags[i]) return;
+  uint32_t k = keys[i] >> shift;
+  int x, y, z;
+  morton_decode(k, &x, &y, &z);
+  start[b] = (int)i;
+  bkey[b] = k;
+  coords[3 * b + 0] = x;
+  coords[3 * b + 1] = y;
+  coords[3 * b + 2] = z;
+  centre[3 * b + 0] = c0 + ((double)x + 0.5) * H;
+  centre[3 * b + 1] = c1 + ((double)y + 0.5) * H;
+  centre[3 * b + 2] = c2 + ((double)z + 0.5) * H;
+}
+
+__global__ __launch_bounds__(TPB) void k_parent(const int* __restrict__ start, int nb, const int* __restrict__ pbox_up,
+                                                int* __restrict__ parent) {
+  int b = blockIdx.x * TPB + threadIdx.x;
+  if (b < nb) parent[b] = pbox_up[start[b]];
+}
+
+__global__ __launch_bounds__(TPB) void k_child_lo(const int* __restrict__ start, int nb, const int* __restrict__ pbox_dn,
+                                                  int nb_dn, int* __restrict__ child_lo) {
+  int b = blockIdx.x * TPB + threadIdx.x;
+  if (b < nb) child_lo[b] = pbox_dn[start[b]];
+  if (b == 0) child_lo[nb] = nb_dn;
+}
+
+__device__ __forceinline__ int find_key(const uint32_t* __restrict__ keys, int nb, uint32_t k) {
+  int lo = 0, hi = nb - 1;
+  while (lo <= hi) {
+    int mid = (lo + hi) >> 1;
+    uint32_t v = keys[mid];
+    if (v == k) return mid;
+    if (v < k) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+// Neighbours (eq. NeighborsCousins): relevant boxes with |j - k|_inf <= 1,
+// self included, in (dz, dy, dx) offset order.  off == null: count only.
+__global__ __launch_bounds__(TPB) void k_neighbours(const int* __restrict__ coords, const uint32_t* __restrict__ bkey,
+                                                    int nb, int side, const int* __restrict__ off,
+                                                    int* __restrict__ cnt_or_idx) {
+  int b = blockIdx.x * TPB + threadIdx.x;
+  if (b >= nb) return;
+  int x = coords[3 * b], y = coords[3 * b + 1], z = coords[3 * b + 2];
+  int c = 0;
+  int base = off ? off[b] : 0;
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int X = x + dx, Y = y + dy, Z = z + dz;
+        if (X < 0 || Y < 0 || Z < 0 || X >= side || Y >= side || Z >= side) continue;
+        int j = find_key(bkey, nb, morton_encode(X, Y, Z));
+        if (j < 0) continue;
+        if (off) cnt_or_idx[base + c] = j;
+        ++c;
+      }
+  if (!off) cnt_or_idx[b] = c;
+}
+
+// Cousins: children of the parent's neighbours that are not neighbours.
+__global__ __launch_bounds__(TPB) void k_cousins(const int* __restrict__ coords, const int* __restrict__ parent, int nb,
+                                                 const int* __restrict__ pnbr_off, const int* __restrict__ pnbr,
+                                                 const int* __restrict__ pchild_lo, const int* __restrict__ off,
+                                                 int* __restrict__ cnt_or_idx) {
+  int b = blockIdx.x * TPB + threadIdx.x;
+  if (b >= nb) return;
+  int x = coords[3 * b], y = coords[3 * b + 1], z = coords[3 * b + 2];
+  int p = parent[b];
+  int c = 0;
+  int base = off ? off[b] : 0;
+  for (int t = pnbr_off[p]; t < pnbr_off[p + 1]; ++t) {
+    int q = pnbr[t];
+    for (int j = pchild_lo[q]; j < pchild_lo[q + 1]; ++j) {
+      int ddx = abs(coords[3 * j] - x), ddy = abs(coords[3 * j + 1] - y), ddz = abs(coords[3 * j + 2] - z);
+      if (max(ddx, max(ddy, ddz)) <= 1) continue;
+      if (off) cnt_or_idx[base + c] = j;
+      ++c;
+    }
+  }
+  if (!off) cnt_or_idx[b] = c;
+}
+
+// Pair counts for statistics: sum over boxes of npts(b) * sum_{j in list(b)} npts(j)
+// (targets x sources) when `per_target` = 1, or sum_b sum_{j} npts(j) otherwise.
+__global__ __launch_bounds__(TPB) void k_pair_stats(const int* __restrict__ start, int nb, const int* __restrict__ off,
+                                                    const int* __restrict__ idx, int weight_by_self,
+                                                    unsigned long long* __restrict__ acc) {
+  int b = blockIdx.x * TPB + threadIdx.x;
+  unsigned long long v = 0;
+  if (b < nb) {
+    long long s = 0;
+    for (int t = off[b]; t < off[b + 1]; ++t) s += start[idx[t] + 1] - start[idx[t]];
+    v = (unsigned long long)(weight_by_self ? s * (long long)(start[b + 1] - start[b]) : s);
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(acc, v);
+}
+
+// Bitwise-equal points inside one finest-level box (equal points share a box).
+__global__ __launch_bounds__(TPB) void k_duplicates(const double* __restrict__ pts, const int* __restrict__ start,
+                                                    int* __restrict__ flag) {
+  int b = blockIdx.x;
+  int lo = start[b], hi = start[b + 1];
+  for (int i = lo + threadIdx.x; i < hi; i += TPB) {
+    double x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+    for (int j = i + 1; j < hi; ++j)
+      if (pts[3 * j] == x && pts[3 * j + 1] == y && pts[3 * j + 2] == z) atomicOr(flag, 1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a3: relevant cones (eq. RelevantCones)
+// ---------------------------------------------------------------------------
+// Cones of box B hit by the points of its cousin boxes: by symmetry of the
+// cousin relation, every point x marks, for each cousin B of its own box, the
+// cone of B that contains x.
+template <bool F32>
+__global__ __launch_bounds__(TPB) void k_mark_targets(const double* __restrict__ pts, int64_t n,
+                                                      const int* __restrict__ pbox, const int* __restrict__ cou_off,
+                                                      const int* __restrict__ cou, const double* __restrict__ centre,
+                                                      LevelGeom g, uint8_t* __restrict__ mark) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  const double* x = pts + 3 * i;
+  int A = pbox[i];
+  for (int t = cou_off[A]; t < cou_off[A + 1]; ++t) {
+    int B = cou[t];
+    double r;
+    int cid;
+    if (F32) cid = target_loc32(x, centre + 3 * B, g, &r).cid;
+    else cid = target_loc64(x, centre + 3 * B, g, &r).cid;
+    mark[(int64_t)B * g.ncone + cid] = 1;
+  }
+}
+
+// Cones of box B hit by the interpolation nodes of its parent's relevant cones.
+template <bool F32>
+__global__ __launch_bounds__(TPB) void k_mark_parent_nodes(int nrel_up, int P, const int* __restrict__ rel_box_up,
+                                                           const int* __restrict__ rel_cone_up,
+                                                           const int* __restrict__ child_lo_up,
+                                                           const int* __restrict__ coords, LevelGeom gp, LevelGeom gc,
+                                                           ChebTab ct, uint8_t* __restrict__ mark) {
+  int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= (int64_t)nrel_up * P) return;
+  int s = (int)(t / P), node = (int)(t % P);
+  int a = node / (ct.pa * ct.pa), b = (node / ct.pa) % ct.pa, c = node % ct.pa;
+  int Pb = rel_box_up[s], pcid = rel_cone_up[s];
+  for (int B = child_lo_up[Pb]; B < child_lo_up[Pb + 1]; ++B) {
+    int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+    int cid = F32 ? prop_loc32(pcid, a, b, c, oct, gp, gc, ct).loc.cid : prop_loc64(pcid, a, b, c, oct, gp, gc, ct).loc.cid;
+    mark[(int64_t)B * gc.ncone + cid] = 1;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_slot_finalize(const uint8_t* __restrict__ mark, int64_t total, int ncone,
+                                                       int* __restrict__ slot, int* __restrict__ slot_off,
+                                                       int* __restrict__ rel_box, int* __restrict__ rel_cone) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= total) return;
+  int v = slot[i];
+  if (i % ncone == 0) slot_off[i / ncone] = v;
+  if (mark[i]) {
+    rel_box[v] = (int)(i / ncone);
+    rel_cone[v] = (int)(i % ncone);
+  } else {
+    slot[i] = -1;
+  }
+}
+
+__global__ __launch_bounds__(TPB) void k_prop_stats(int nrel_up, const int* __restrict__ rel_box_up,
+                                                    const int* __restrict__ child_lo_up, int P,
+                                                    unsigned long long* __restrict__ acc) {
+  int s = blockIdx.x * TPB + threadIdx.x;
+  unsigned long long v = 0;
+  if (s < nrel_up) {
+    int b = rel_box_up[s];
+    v = (unsigned long long)(child_lo_up[b + 1] - child_lo_up[b]) * (unsigned long long)P;
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(acc, v);
+}
+
+template <typename T> T read1(const void* dptr, hipStream_t s) {
+  T v;
+  HIPCHK(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return v;
+}
+
+LevelGeom make_geom(double H, int ns, int nc) {
+  LevelGeom g{};
+  g.H = H;
+  g.h = std::sqrt(3.0) / 2.0 * H;
+  g.hf = (float)g.h;
+  g.ns = ns;
+  g.nc = nc;
+  g.ncone = ns * nc * 2 * nc;
+  g.ds = (std::sqrt(3.0) / 3.0) / ns;
+  g.da = IFGF_PI / nc;
+  g.inv_ds = 1.0 / g.ds;
+  g.inv_da = 1.0 / g.da;
+  g.dsf = (float)g.ds;
+  g.daf = (float)g.da;
+  g.inv_dsf = (float)g.inv_ds;
+  g.inv_daf = (float)g.inv_da;
+  return g;
+}
+
+}  // namespace
+
+void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const double* w, hipStream_t s) {
+  const int64_t n = p->n;
+  const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
+
+  // ---- a1: root box -------------------------------------------------------
+  unsigned nbb = (unsigned)std::min<int64_t>(1024, (n + TPB - 1) / TPB);
+  DevBuf part, bad;
+  part.alloc(sizeof(double) * 6 * nbb);
+  bad.alloc(sizeof(int) * 4);
+  HIPCHK(hipMemsetAsync(bad.p, 0, sizeof(int) * 4, s));
+  k_bbox<<<nbb, TPB, 0, s>>>(pts, nrm, w, n, part.as<double>(), bad.as<int>());
+  HIPCHK(hipGetLastError());
+  std::vector<double> hpart(6 * nbb);
+  int hbad[4];
+  HIPCHK(hipMemcpyAsync(hpart.data(), part.p, sizeof(double) * 6 * nbb, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hbad, bad.p, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  part.release();
+  if (hbad[0]) throw Error{IFGF_EINVAL, "non-finite point, normal or weight"};
+  double lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = hpart[a];
+    hi[a] = hpart[3 + a];
+    for (unsigned b = 1; b < nbb; ++b) {
+      lo[a] = std::fmin(lo[a], hpart[6 * b + a]);
+      hi[a] = std::fmax(hi[a], hpart[6 * b + 3 + a]);
+    }
+  }
+  // Root cube (a reading of "B^1 contains all points"): bounding-box midpoint,
+  // side = largest extent * (1 + 2^-20).
+  double ext = 0;
+  double c[3];
+  for (int a = 0; a < 3; ++a) {
+    c[a] = (lo[a] + hi[a]) / 2.0;
+    ext = std::fmax(ext, hi[a] - lo[a]);
+  }
+  double L = ext * (1.0 + std::ldexp(1.0, -20));
+  if (L == 0.0) L = 1.0;
+  for (int a = 0; a < 3; ++a) p->corner[a] = c[a] - L / 2.0;
+  p->L = L;
+  if (p->opt.depth <= 0) {
+    double lam = 2.0 * IFGF_PI / p->k;
+    int D = 1 + (int)std::lround(std::log2(L / (p->opt.leaf_h_lambda * lam)));
+    p->D = std::max(1, std::min(11, D));
+  } else {
+    p->D = p->opt.depth;
+  }
+  const int D = p->D;
+  const int m = 1 << (D - 1);
+
+  // ---- a1: Morton keys and sort --------------------------------------------
+  {
+    DevBuf kbuf;
+    int64_t cap = sort_padded_length(n);
+    kbuf.alloc(sizeof(uint64_t) * cap);
+    k_keys<<<nblocks(n), TPB, 0, s>>>(pts, n, p->corner[0], p->corner[1], p->corner[2], (double)m / L, m,
+                                     kbuf.as<uint64_t>());
+    HIPCHK(hipGetLastError());
+    sort_u64(kbuf.as<uint64_t>(), n, s);
+    p->perm.alloc(sizeof(int) * n);
+    p->keys.alloc(sizeof(uint32_t) * n);
+    p->pts.alloc(sizeof(double) * 3 * n);
+    p->nrm.alloc(sizeof(double) * 3 * n);
+    p->w.alloc(sizeof(double) * n);
+    k_unpack<<<nblocks(n), TPB, 0, s>>>(kbuf.as<uint64_t>(), n, pts, nrm, w, p->perm.as<int>(), p->keys.as<uint32_t>(),
+                                       p->pts.as<double>(), p->nrm.as<double>(), p->w.as<double>());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  }
+
+  // ---- a2: levels -----------------------------------------------------------
+  DevBuf flags, bid;
+  flags.alloc(n);
+  bid.alloc(sizeof(int) * (n + 1));
+  std::vector<DevBuf> bkey(D + 1);
+  for (int d = 1; d <= D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    lv.d = d;
+    lv.H = L / (double)(1 << (d - 1));
+    int shift = 3 * (D - d);
+    k_level_flags<<<nblocks(n), TPB, 0, s>>>(p->keys.as<uint32_t>(), n, shift, flags.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    scan_exclusive_u8(flags.as<uint8_t>(), bid.as<int>(), n, s);
+    int nb = read1<int>(bid.as<int>() + n, s);
+    lv.nb = nb;
+    lv.start.alloc(sizeof(int) * (nb + 1));
+    lv.coords.alloc(sizeof(int) * 3 * nb);
+    lv.centre.alloc(sizeof(double) * 3 * nb);
+    bkey[d].alloc(sizeof(uint32_t) * nb);
+    lv.pbox.alloc(sizeof(int) * n);
+    k_level_boxes<<<nblocks(n), TPB, 0, s>>>(p->keys.as<uint32_t>(), flags.as<uint8_t>(), bid.as<int>(), n, shift, nb,
+                                            p->corner[0], p->corner[1], p->corner[2], lv.H, lv.start.as<int>(),
+                                            lv.coords.as<int>(), bkey[d].as<uint32_t>(), lv.centre.as<double>(),
+                                            lv.pbox.as<int>());
+    HIPCHK(hipGetLastError());
+  }
+  flags.release();
+  bid.release();
+  for (int d = 2; d <= D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    lv.parent.alloc(sizeof(int) * lv.nb);
+    k_parent<<<nblocks(lv.nb), TPB, 0, s>>>(lv.start.as<int>(), lv.nb, p->lev[d - 1].pbox.as<int>(), lv.parent.as<int>());
+    HIPCHK(hipGetLastError());
+  }
+  for (int d = 1; d < D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    lv.child_lo.alloc(sizeof(int) * (lv.nb + 1));
+    k_child_lo<<<nblocks(lv.nb), TPB, 0, s>>>(lv.start.as<int>(), lv.nb, p->lev[d + 1].pbox.as<int>(), p->lev[d + 1].nb,
+                                             lv.child_lo.as<int>());
+    HIPCHK(hipGetLastError());
+  }
+  // neighbour lists, all levels
+  for (int d = 1; d <= D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    DevBuf cnt;
+    cnt.alloc(sizeof(int) * (lv.nb + 1));
+    k_neighbours<<<nblocks(lv.nb), TPB, 0, s>>>(lv.coords.as<int>(), bkey[d].as<uint32_t>(), lv.nb, 1 << (d - 1), nullptr,
+                                               cnt.as<int>());
+    HIPCHK(hipGetLastError());
+    lv.nbr_off.alloc(sizeof(int) * (lv.nb + 1));
+    scan_exclusive_i32(cnt.as<int>(), lv.nbr_off.as<int>(), lv.nb, s);
+    lv.nnbr = read1<int>(lv.nbr_off.as<int>() + lv.nb, s);
+    lv.nbr.alloc(sizeof(int) * std::max<int64_t>(1, lv.nnbr));
+    k_neighbours<<<nblocks(lv.nb), TPB, 0, s>>>(lv.coords.as<int>(), bkey[d].as<uint32_t>(), lv.nb, 1 << (d - 1),
+                                               lv.nbr_off.as<int>(), lv.nbr.as<int>());
+    HIPCHK(hipGetLastError());
+  }
+  // cousin lists, d >= 3
+  for (int d = 3; d <= D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    LevelPlan& up = p->lev[d - 1];
+    DevBuf cnt;
+    cnt.alloc(sizeof(int) * (lv.nb + 1));
+    k_cousins<<<nblocks(lv.nb), TPB, 0, s>>>(lv.coords.as<int>(), lv.parent.as<int>(), lv.nb, up.nbr_off.as<int>(),
+                                            up.nbr.as<int>(), up.child_lo.as<int>(), nullptr, cnt.as<int>());
+    HIPCHK(hipGetLastError());
+    lv.cou_off.alloc(sizeof(int) * (lv.nb + 1));
+    scan_exclusive_i32(cnt.as<int>(), lv.cou_off.as<int>(), lv.nb, s);
+    lv.ncou = read1<int>(lv.cou_off.as<int>() + lv.nb, s);
+    lv.cou.alloc(sizeof(int) * std::max<int64_t>(1, lv.ncou));
+    k_cousins<<<nblocks(lv.nb), TPB, 0, s>>>(lv.coords.as<int>(), lv.parent.as<int>(), lv.nb, up.nbr_off.as<int>(),
+                                            up.nbr.as<int>(), up.child_lo.as<int>(), lv.cou_off.as<int>(), lv.cou.as<int>());
+    HIPCHK(hipGetLastError());
+  }
+  // statistics and duplicate check
+  {
+    DevBuf acc;
+    acc.alloc(sizeof(unsigned long long) * IFGF_MAX_LEVELS);
+    HIPCHK(hipMemsetAsync(acc.p, 0, acc.bytes, s));
+    LevelPlan& lD = p->lev[D];
+    k_pair_stats<<<nblocks(lD.nb), TPB, 0, s>>>(lD.start.as<int>(), lD.nb, lD.nbr_off.as<int>(), lD.nbr.as<int>(), 1,
+                                               acc.as<unsigned long long>());
+    for (int d = 3; d <= D; ++d) {
+      LevelPlan& lv = p->lev[d];
+      k_pair_stats<<<nblocks(lv.nb), TPB, 0, s>>>(lv.start.as<int>(), lv.nb, lv.cou_off.as<int>(), lv.cou.as<int>(), 1,
+                                                 acc.as<unsigned long long>() + d);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+    k_duplicates<<<lD.nb, TPB, 0, s>>>(p->pts.as<double>(), lD.start.as<int>(), bad.as<int>());
+    HIPCHK(hipGetLastError());
+    unsigned long long h[IFGF_MAX_LEVELS];
+    HIPCHK(hipMemcpyAsync(h, acc.p, acc.bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(hbad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    p->near_pairs = (int64_t)h[0];
+    for (int d = 3; d <= D; ++d) p->lev[d].cousin_pairs = (int64_t)h[d];
+    if (hbad[0]) throw Error{IFGF_EDUPLICATE, "two points coincide"};
+  }
+
+  // ---- cone counts per level (Remark cone_seg_size) ---------------------------
+  {
+    int ns = p->opt.ns0, nc = p->opt.nc0;
+    p->lev[D].geom = make_geom(p->lev[D].H, ns, nc);
+    for (int d = D; d >= 2; --d) {
+      if (p->k * p->lev[d].H > 0.5) {
+        ns *= 2;
+        nc *= 2;
+      }
+      p->lev[d - 1].geom = make_geom(p->lev[d - 1].H, ns, nc);
+    }
+  }
+  // Chebyshev tables
+  {
+    ChebTab& ct = p->cheb;
+    ct.ps = p->opt.p_s;
+    ct.pa = p->opt.p_ang;
+    for (int i = 0; i < ct.ps; ++i) {
+      ct.us[i] = 0.5 * (1.0 + std::cos((2.0 * i + 1.0) * IFGF_PI / (2.0 * ct.ps)));
+      ct.usf[i] = (float)ct.us[i];
+    }
+    for (int i = 0; i < ct.pa; ++i) {
+      ct.ua[i] = 0.5 * (1.0 + std::cos((2.0 * i + 1.0) * IFGF_PI / (2.0 * ct.pa)));
+      ct.uaf[i] = (float)ct.ua[i];
+    }
+    auto mat = [](int nn, DevBuf& md, DevBuf& mf, hipStream_t st) {
+      std::vector<double> M(nn * nn);
+      std::vector<float> Mf(nn * nn);
+      for (int i = 0; i < nn; ++i)
+        for (int k = 0; k < nn; ++k) {
+          double xk = std::cos((2.0 * k + 1.0) * IFGF_PI / (2.0 * nn));
+          double Ti = std::cos(i * std::acos(xk));
+          double v = (i == 0 ? 1.0 : 2.0) / nn * Ti;
+          M[i * nn + k] = v;
+          Mf[i * nn + k] = (float)v;
+        }
+      md.alloc(sizeof(double) * nn * nn);
+      mf.alloc(sizeof(float) * nn * nn);
+      HIPCHK(hipMemcpyAsync(md.p, M.data(), md.bytes, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(mf.p, Mf.data(), mf.bytes, hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+    };
+    mat(ct.ps, p->Ms, p->Msf, s);
+    mat(ct.pa, p->Ma, p->Maf, s);
+  }
+  const int P = p->P;
+
+  // ---- a3: relevant cones, top-down from d = 3 ----------------------------------
+  for (int d = 3; d <= D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    const LevelGeom& g = lv.geom;
+    int64_t total = (int64_t)lv.nb * g.ncone;
+    DevBuf mark;
+    mark.alloc(total);
+    HIPCHK(hipMemsetAsync(mark.p, 0, total, s));
+    if (f32)
+      k_mark_targets<true><<<nblocks(n), TPB, 0, s>>>(p->pts.as<double>(), n, lv.pbox.as<int>(), lv.cou_off.as<int>(),
+                                                     lv.cou.as<int>(), lv.centre.as<double>(), g, mark.as<uint8_t>());
+    else
+      k_mark_targets<false><<<nblocks(n), TPB, 0, s>>>(p->pts.as<double>(), n, lv.pbox.as<int>(), lv.cou_off.as<int>(),
+                                                      lv.cou.as<int>(), lv.centre.as<double>(), g, mark.as<uint8_t>());
+    HIPCHK(hipGetLastError());
+    if (d > 3) {
+      LevelPlan& up = p->lev[d - 1];
+      int64_t nt = (int64_t)up.nrel * P;
+      if (nt > 0) {
+        if (f32)
+          k_mark_parent_nodes<true><<<nblocks(nt), TPB, 0, s>>>(up.nrel, P, up.rel_box.as<int>(), up.rel_cone.as<int>(),
+                                                               up.child_lo.as<int>(), lv.coords.as<int>(), up.geom, g,
+                                                               p->cheb, mark.as<uint8_t>());
+        else
+          k_mark_parent_nodes<false><<<nblocks(nt), TPB, 0, s>>>(up.nrel, P, up.rel_box.as<int>(), up.rel_cone.as<int>(),
+                                                                up.child_lo.as<int>(), lv.coords.as<int>(), up.geom, g,
+                                                                p->cheb, mark.as<uint8_t>());
+        HIPCHK(hipGetLastError());
+      }
+      DevBuf acc;
+      acc.alloc(sizeof(unsigned long long));
+      HIPCHK(hipMemsetAsync(acc.p, 0, acc.bytes, s));
+      if (up.nrel > 0) {
+        k_prop_stats<<<nblocks(up.nrel), TPB, 0, s>>>(up.nrel, up.rel_box.as<int>(), up.child_lo.as<int>(), P,
+                                                     acc.as<unsigned long long>());
+        HIPCHK(hipGetLastError());
+      }
+      lv.prop_evals = (int64_t)read1<unsigned long long>(acc.p, s);
+    }
+    if (total > (int64_t)0x7fffffff) throw Error{IFGF_EUNSUPPORTED, "cone map too large for this level"};
+    lv.slot.alloc(sizeof(int) * (total + 1));
+    scan_exclusive_u8(mark.as<uint8_t>(), lv.slot.as<int>(), total, s);
+    lv.nrel = read1<int>(lv.slot.as<int>() + total, s);
+    lv.slot_off.alloc(sizeof(int) * (lv.nb + 1));
+    lv.rel_box.alloc(sizeof(int) * std::max(1, lv.nrel));
+    lv.rel_cone.alloc(sizeof(int) * std::max(1, lv.nrel));
+    k_slot_finalize<<<nblocks(total), TPB, 0, s>>>(mark.as<uint8_t>(), total, g.ncone, lv.slot.as<int>(),
+                                                  lv.slot_off.as<int>(), lv.rel_box.as<int>(), lv.rel_cone.as<int>());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(lv.slot_off.as<int>() + lv.nb, &lv.nrel, sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+
+  // ---- workspaces -------------------------------------------------------------
+  size_t csz = f32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
+  int R = p->opt.max_rhs;
+  for (int d = 3; d <= D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    lv.Fn.alloc(csz * (size_t)std::max(1, lv.nrel) * P * R);
+    lv.Fc.alloc(csz * (size_t)std::max(1, lv.nrel) * P * R);
+  }
+  p->a.alloc(csz * (size_t)n * R);
+  p->uacc.alloc(csz * (size_t)n * R);
+  p->err.alloc(sizeof(int) * 4);
+  HIPCHK(hipMemsetAsync(p->err.p, 0, sizeof(int) * 4, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+}  // namespace ifgf

@@ -1,0 +1,247 @@
+"""GPU parity of the HIP IFGF path against the oracle.
+
+Structure (octree, Morton order, lists, relevant cones) is compared exactly
+with the reference IFGF; each stage of the FP64 path element by element with
+the reference IFGF (which is pinned by its own tests); the result against the
+FP64 direct sum at the accuracy target; exact special cases (constant
+kernel, depth <= 2) at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct
+from oracle import ifgf_ref as R
+from paper_2112_06316_amd import Plan, inputs
+from paper_2112_06316_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rel_inf(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+SURF = {
+    "sphere8": lambda: inputs.cubed_sphere(8),                          # N = 384
+    "sphere32": lambda: inputs.cubed_sphere(32),                        # N = 6,144 (4 wavelengths)
+    "ellip20": lambda: inputs.ellipsoid(20, (0.5, 0.375, 0.25)),        # N = 2,400
+}
+
+
+@pytest.mark.parametrize("name,D", [("sphere32", 4), ("ellip20", 5), ("sphere8", 3)])
+def test_morton_order_bit_exact(name, D):
+    log(f"case order {name} D={D}")
+    p, nr, w = SURF[name]()
+    plan = Plan(p, nr, w, 8 * np.pi, 8 * np.pi, depth=D)
+    perm, keys = plan.export_order()
+    t = R.build_tree(p, D)
+    assert np.array_equal(perm, t.perm)
+    assert np.array_equal(keys.astype(np.uint64), t.keys)
+    st = plan.stats()
+    assert st["depth"] == D and st["root_side"] == t.L
+    assert np.array_equal(np.array(st["root_corner"]), t.corner)
+
+
+@pytest.mark.parametrize("name,D", [("sphere32", 4), ("ellip20", 5)])
+def test_boxes_neighbours_cousins(name, D):
+    log(f"case lists {name} D={D}")
+    p, nr, w = SURF[name]()
+    plan = Plan(p, nr, w, 8 * np.pi, 8 * np.pi, depth=D)
+    t = R.build_tree(p, D)
+    for d in range(1, D + 1):
+        start, coords = plan.export_boxes(d)
+        lev = t.levels[d]
+        assert np.array_equal(start, lev.start)
+        assert np.array_equal(coords, lev.coords)
+        nbr = plan.export_lists(d, 0)
+        for b in range(len(lev.coords)):
+            assert sorted(nbr[b].tolist()) == lev.neighbours[b].tolist()
+        if d >= 3:
+            cou = plan.export_lists(d, 1)
+            for b in range(len(lev.coords)):
+                assert sorted(cou[b].tolist()) == lev.cousins[b].tolist()
+
+
+@pytest.mark.parametrize("ps,pa,ns0,nc0", [(3, 5, 1, 2), (4, 6, 2, 4)])
+def test_relevant_cones_fp64(ps, pa, ns0, nc0):
+    log(f"case cones {ps},{pa},{ns0},{nc0}")
+    p, nr, w = SURF["sphere32"]()
+    k = 8 * np.pi
+    plan = Plan(p, nr, w, k, k, depth=4, p_s=ps, p_ang=pa, ns0=ns0, nc0=nc0, precision="fp64")
+    ref = R.make_plan(p, nr, w, k, k, 4, ps=ps, pa=pa, ns0=ns0, nc0=nc0)
+    st = plan.stats()
+    for d in (3, 4):
+        assert (st["ns"][d], st["nc"][d]) == ref.counts[d]
+        box, cone = plan.export_cones(d)
+        want_box = np.concatenate([np.full(c.size, b) for b, c in enumerate(ref.cones[d])])
+        want_cone = np.concatenate(ref.cones[d])
+        assert np.array_equal(box, want_box) and np.array_equal(cone, want_cone)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_stage_parity_with_reference(precision):
+    log(f"case stages {precision}")
+    p, nr, w = SURF["sphere32"]()
+    k = 8 * np.pi
+    sigma = inputs.random_density(len(p), seed=inputs.config_seed(1))
+    ref = R.make_plan(p, nr, w, k, k, 4, ps=3, pa=5, ns0=1, nc0=2)
+    u_ref, info = R.apply(ref, sigma, stages=True)
+    plan = Plan(p, nr, w, k, k, depth=4, p_s=3, p_ang=5, ns0=1, nc0=2, precision=precision)
+    s = torch.from_numpy(sigma).to(DEV)
+    tol = 1e-10 if precision == "fp64" else 2e-5
+    perm = ref.tree.perm
+    # near field alone
+    near = plan.apply_stages(s, 1).cpu().numpy()
+    assert rel_inf(near[perm], info["near"]) < tol
+    # each level's cousin interpolation alone
+    for d in (3, 4):
+        ud = plan.apply_stages(s, 2, d, d).cpu().numpy()
+        assert rel_inf(ud[perm], info["level_u"][d]) < tol * 10, d
+    # fields at the nodes, per level
+    u = plan.apply(s).cpu().numpy()
+    for d in (3, 4):
+        F = plan.export_field(d, 0)[:, 0, :]
+        Fr = np.concatenate([v.reshape(v.shape[0], -1) for v in info["F_nodes"][d]])
+        assert rel_inf(F, Fr) < tol * 10, d
+    assert rel_inf(u, u_ref) < tol * 10
+    assert plan.check() == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nface,D", [(32, 4), (64, 5), (128, 6)])
+def test_constant_kernel_exact(precision, nface, D):
+    # K = 1: every interpolation is exact, so u_i = sum_{j != i} a_j if and only
+    # if every pair is counted exactly once by the traversal.
+    log(f"case constant {precision} n={nface} D={D}")
+    p, nr, w = inputs.cubed_sphere(nface)
+    sigma = inputs.random_density(len(p), seed=7)
+    plan = Plan(p, nr, w, 16 * np.pi, 16 * np.pi, depth=D, kernel="constant", precision=precision)
+    u = plan.apply(torch.from_numpy(sigma).to(DEV)).cpu().numpy()
+    a = w * sigma
+    ref = a.sum() - a
+    tol = 1e-11 if precision == "fp64" else 2e-5
+    assert np.abs(u - ref).max() <= tol * np.abs(a).sum()
+    assert plan.check() == 0
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 3e-6)])
+@pytest.mark.parametrize("D", [1, 2])
+def test_shallow_tree_equals_direct_sum(precision, tol, D):
+    log(f"case shallow {precision} D={D}")
+    p, nr, w = inputs.cubed_sphere(12)
+    k = 8 * np.pi
+    sigma = inputs.random_density(len(p), seed=8)
+    plan = Plan(p, nr, w, k, k, depth=D, precision=precision)
+    u = plan.apply(torch.from_numpy(sigma).to(DEV)).cpu().numpy()
+    ref = direct.apply_c(p, nr, w, k, k, sigma)
+    assert rel_inf(u, ref) < tol
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_accuracy_sphere_4_wavelengths(precision):
+    log(f"case accuracy4 {precision}")
+    p, nr, w = SURF["sphere32"]()
+    k = 8 * np.pi
+    sigma = inputs.random_density(len(p), seed=inputs.config_seed(1))
+    ref = direct.apply_c(p, nr, w, k, k, sigma)
+    plan = Plan(p, nr, w, k, k, depth=4, precision=precision)
+    u = plan.apply(torch.from_numpy(sigma).to(DEV)).cpu().numpy()
+    err = rel_l2(u, ref)
+    log(f"  rel l2 err = {err:.3e}")
+    assert err < 1e-4
+    assert plan.check() == 0
+
+
+def test_multiple_rhs_equal_single_applies():
+    log("case multi-rhs")
+    p, nr, w = SURF["ellip20"]()
+    k = 8 * np.pi
+    S = inputs.random_density(len(p), nrhs=3, seed=9)
+    for precision, tol in (("fp64", 1e-13), ("fp32", 1e-6)):
+        plan = Plan(p, nr, w, k, k, depth=4, precision=precision, max_rhs=3)
+        U = plan.apply(torch.from_numpy(S).to(DEV)).cpu().numpy()
+        for r in range(3):
+            ur = plan.apply(torch.from_numpy(np.ascontiguousarray(S[:, r])).to(DEV)).cpu().numpy()
+            assert rel_inf(U[:, r], ur) < tol
+
+
+def test_complex64_io():
+    p, nr, w = SURF["sphere8"]()
+    k = 8 * np.pi
+    sigma = inputs.random_density(len(p), seed=10)
+    plan = Plan(p, nr, w, k, k, depth=3)
+    u128 = plan.apply(torch.from_numpy(sigma).to(DEV)).cpu().numpy()
+    u64 = plan.apply(torch.from_numpy(sigma.astype(np.complex64)).to(DEV)).cpu().numpy()
+    assert rel_inf(u64, u128) < 1e-5
+
+
+def test_tiny_inputs():
+    log("case tiny")
+    p = np.array([[0.0, 0.0, 0.0]])
+    plan = Plan(p, np.array([[0.0, 0.0, 1.0]]), np.array([1.0]), 3.0, 3.0, depth=1)
+    u = plan.apply(torch.ones(1, dtype=torch.complex128, device=DEV)).cpu().numpy()
+    assert u[0] == 0
+    p2, n2, w2 = inputs.cubed_sphere(1)     # 6 points
+    sig = inputs.random_density(6, seed=11)
+    for D in (1, 3, 5):
+        plan = Plan(p2, n2, w2, 3.0, 1.0, depth=D, precision="fp64")
+        u = plan.apply(torch.from_numpy(sig).to(DEV)).cpu().numpy()
+        ref = direct.apply_c(p2, n2, w2, 3.0, 1.0, sig)
+        assert rel_l2(u, ref) < 1e-3
+
+
+def test_error_paths():
+    p, nr, w = SURF["sphere8"]()
+    bad = p.copy()
+    bad[5] = bad[17]
+    with pytest.raises(L.IFGFError) as e:
+        Plan(bad, nr, w, 8.0, 8.0, depth=3)
+    assert e.value.status == L.EDUPLICATE
+    bad = p.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(L.IFGFError) as e:
+        Plan(bad, nr, w, 8.0, 8.0, depth=3)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.IFGFError) as e:
+        Plan(p, nr, w, -1.0, 8.0)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.IFGFError) as e:
+        Plan(p, nr, w, 8.0, 8.0, depth=12)
+    assert e.value.status == L.EINVAL
+    with pytest.raises(L.IFGFError) as e:
+        Plan(p, nr, w, 8.0, 8.0, p_s=9, p_ang=9)
+    assert e.value.status == L.EUNSUPPORTED
+    plan = Plan(p, nr, w, 8.0, 8.0, depth=3)
+    with pytest.raises(L.IFGFError) as e:
+        plan.apply(torch.ones(len(p), 2, dtype=torch.complex128, device=DEV))
+    assert e.value.status == L.EINVAL
+
+
+def test_sphere_32_wavelengths_sampled():
+    # the benchmark workload: N = 393,216, k = 64 pi, D = 7; error against the
+    # FP64 direct sum at 4,096 seeded targets
+    log("case sphere32 sampled")
+    wl = inputs.workload("sphere32")
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    sigma = inputs.random_density(len(p), seed=inputs.config_seed(2))
+    tg = inputs.sample_targets(len(p), 4096, seed=inputs.config_seed(2) + 100)
+    plan = Plan(p, nr, w, k, k, depth=7, precision="fp32")
+    log(f"  plan stats {plan.stats()['cones']}")
+    u = plan.apply(torch.from_numpy(sigma).to(DEV)).cpu().numpy()
+    assert plan.check() == 0
+    log("  oracle on sampled targets")
+    ref = direct.apply_c(p, nr, w, k, k, sigma, targets=tg)
+    err = rel_l2(u[tg], ref)
+    log(f"  rel l2 err = {err:.3e}")
+    assert err < 1e-4
