@@ -327,7 +327,7 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
 // Coefficients are read through the constant address space: they are not
 // written while an apply kernel runs, and with a wave-uniform address the
 // reads become scalar loads shared by the wave.
-template <typename T> using cptr = const __attribute__((address_space(4))) cpx<T>*;
+template <typename T> using cptr = const __attribute__((address_space(4))) T*;   // interleaved re, im
 
 template <typename T, int PS, int PA>
 __device__ __forceinline__ cpx<T> contract(cptr<T> C, const T* Ts, const T* Tt, const T* Tp) {
@@ -340,9 +340,9 @@ __device__ __forceinline__ cpx<T> contract(cptr<T> C, const T* Ts, const T* Tt, 
       cpx<T> gsum = {0, 0};
 #pragma unroll
       for (int l = 0; l < PA; ++l) {
-        cpx<T> c = C[(i * PA + j) * PA + l];
-        gsum.re += c.re * Tp[l];
-        gsum.im += c.im * Tp[l];
+        const int q = (i * PA + j) * PA + l;
+        gsum.re += C[2 * q] * Tp[l];
+        gsum.im += C[2 * q + 1] * Tp[l];
       }
       h.re += gsum.re * Tt[j];
       h.im += gsum.im * Tt[j];
@@ -377,7 +377,7 @@ __device__ __forceinline__ cpx<T> eval_uniform(const cpx<T>* __restrict__ F, int
       uint64_t off = (uint64_t)(((int64_t)su * R + r) * P);
       uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)off);
       uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(off >> 32));
-      out = contract<T, PS, PA>((cptr<T>)(F + (((uint64_t)hi << 32) | lo)), Ts, Tt, Tp);
+      out = contract<T, PS, PA>((cptr<T>)(const T*)(F + (((uint64_t)hi << 32) | lo)), Ts, Tt, Tp);
     }
   }
   return out;
