@@ -214,6 +214,29 @@ ifgf_status ifgf_apply_stages(ifgf_plan p, const void *sigma, void *u, int32_t n
  */
 ifgf_status ifgf_plan_check(ifgf_plan p, int32_t *flags);
 
+/*
+ * Per-kernel timing with HIP events recorded on the apply's stream.
+ * Stages: IFGF_STAGE_GATHER (a = w sigma), NEAR (near field), LEAF (leaf
+ * factors), COEFFS (node values -> coefficients), PROP (upward pass),
+ * TARGETS (cousin interpolation + scatter), plus the transposed stages of
+ * ifgf_apply_adjoint (ADJ_*).
+ *
+ * ifgf_plan_set_profiling: max_launches > 0 enables timing of up to that
+ *   many kernel launches (events are created here, on the host), 0 disables.
+ * ifgf_plan_read_profile: synchronizes the recorded events, writes the
+ *   summed milliseconds and the launch count per stage into ms[] and
+ *   launches[] (IFGF_NSTAGES entries each, [host]) and resets the record.
+ *   Launches beyond max_launches are not timed and not counted.
+ */
+enum {
+    IFGF_STAGE_GATHER = 0, IFGF_STAGE_NEAR = 1, IFGF_STAGE_LEAF = 2, IFGF_STAGE_COEFFS = 3,
+    IFGF_STAGE_PROP = 4, IFGF_STAGE_TARGETS = 5, IFGF_STAGE_ADJ_TARGETS = 6, IFGF_STAGE_ADJ_PROP = 7,
+    IFGF_STAGE_ADJ_COEFFS = 8, IFGF_STAGE_ADJ_LEAF = 9, IFGF_STAGE_ADJ_NEAR = 10, IFGF_STAGE_ADJ_OUT = 11,
+    IFGF_NSTAGES = 12
+};
+ifgf_status ifgf_plan_set_profiling(ifgf_plan p, int32_t max_launches);
+ifgf_status ifgf_plan_read_profile(ifgf_plan p, double *ms, int64_t *launches);
+
 /* Release the plan and its device memory (after its work has completed).
  * NULL is ignored. */
 void ifgf_plan_destroy(ifgf_plan p);

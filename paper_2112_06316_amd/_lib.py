@@ -12,6 +12,8 @@ OK, EINVAL, EDUPLICATE, ENOMEM, EHIP, EUNSUPPORTED, EBUSY, EINTERNAL = range(8)
 PREC_FP64, PREC_FP32_INTERP = 0, 1
 C64, C128 = 0, 1
 KERNEL_COMBINED, KERNEL_CONSTANT = 0, 1
+STAGES = ["gather", "near", "leaf", "coeffs", "prop", "targets", "adj_targets", "adj_prop", "adj_coeffs",
+          "adj_leaf", "adj_near", "adj_out"]
 
 
 class Options(ctypes.Structure):
@@ -65,6 +67,8 @@ SIGNATURES = {
     "ifgf_plan_export_cones": (I32, [VP, I32, VP, VP]),
     "ifgf_plan_export_field": (I32, [VP, I32, I32, VP]),
     "ifgf_plan_check": (I32, [VP, ctypes.POINTER(I32)]),
+    "ifgf_plan_set_profiling": (I32, [VP, I32]),
+    "ifgf_plan_read_profile": (I32, [VP, VP, VP]),
     "ifgf_plan_destroy": (None, [VP]),
     "ifgf_status_string": (ctypes.c_char_p, [I32]),
     "ifgf_last_error": (ctypes.c_char_p, []),

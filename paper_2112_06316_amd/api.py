@@ -143,6 +143,17 @@ class Plan:
             "near_pairs": s.near_pairs, "device_bytes": s.device_bytes,
         }
 
+    def set_profiling(self, max_launches: int):
+        """Time up to max_launches kernel launches with HIP events (0 = off)."""
+        L.check(self._lib.ifgf_plan_set_profiling(self._h, int(max_launches)), "ifgf_plan_set_profiling")
+
+    def read_profile(self) -> dict:
+        """{stage: (total ms, launches)} of the launches timed since the last read."""
+        ms = (ctypes.c_double * len(L.STAGES))()
+        cnt = (ctypes.c_int64 * len(L.STAGES))()
+        L.check(self._lib.ifgf_plan_read_profile(self._h, ms, cnt), "ifgf_plan_read_profile")
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(L.STAGES) if cnt[i]}
+
     def check(self) -> int:
         f = ctypes.c_int32(0)
         L.check(self._lib.ifgf_plan_check(self._h, ctypes.byref(f)), "ifgf_plan_check")

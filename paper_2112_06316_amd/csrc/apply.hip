@@ -546,12 +546,16 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   cpx<T>* a = p->a.as<cpx<T>>();
   cpx<T>* uacc = p->uacc.as<cpx<T>>();
   dim3 gpts(nblocks(n), R);
-  k_gather<T><<<gpts, TPB, 0, s>>>(sigma, dtype, 0, p->perm.as<int>(), p->w.as<double>(), n, R, a);
+  {
+    StageTimer tm(p, s, IFGF_STAGE_GATHER);
+    k_gather<T><<<gpts, TPB, 0, s>>>(sigma, dtype, 0, p->perm.as<int>(), p->w.as<double>(), n, R, a);
+  }
   HIPCHK(hipGetLastError());
   const int kind = p->opt.kernel;
   LevelPlan& lD = p->lev[D];
   const bool near = stage_mask & 1;
   if (near) {
+    StageTimer tm(p, s, IFGF_STAGE_NEAR);
     k_near<T><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
                                             lD.nbr_off.as<int>(), lD.nbr.as<int>(), lD.centre.as<double>(), p->k,
                                             p->eta, kind, uacc);
@@ -560,12 +564,16 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   if (D >= 3) {
     const T* Ms = (const T*)(Prec<T>::f32 ? p->Msf.p : p->Ms.p);
     const T* Ma = (const T*)(Prec<T>::f32 ? p->Maf.p : p->Ma.p);
-    k_leaf<T, PS, PA><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R,
-                                                     lD.start.as<int>(), lD.centre.as<double>(), lD.slot_off.as<int>(),
-                                                     lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta, kind,
-                                                     lD.Fn.as<cpx<T>>());
+    {
+      StageTimer tm(p, s, IFGF_STAGE_LEAF);
+      k_leaf<T, PS, PA><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R,
+                                                       lD.start.as<int>(), lD.centre.as<double>(), lD.slot_off.as<int>(),
+                                                       lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta, kind,
+                                                       lD.Fn.as<cpx<T>>());
+    }
     HIPCHK(hipGetLastError());
     if (lD.nrel > 0) {
+      StageTimer tm(p, s, IFGF_STAGE_COEFFS);
       k_coeffs<T, PS, PA><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma, lD.Fc.as<cpx<T>>());
       HIPCHK(hipGetLastError());
     }
@@ -574,12 +582,18 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
       LevelPlan& lp = p->lev[d - 1];
       if (lp.nrel == 0) continue;
       int64_t items = (int64_t)lp.nrel * P;
+      {
+      StageTimer tm(p, s, IFGF_STAGE_PROP);
       k_prop<T, PS, PA><<<dim3(nblocks(items), R), TPB, 0, s>>>(
           lp.nrel, lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
           lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, p->k, kind, R, lp.Fn.as<cpx<T>>(),
           p->err.as<int>());
+      }
       HIPCHK(hipGetLastError());
-      k_coeffs<T, PS, PA><<<dim3(lp.nrel, R), TPB, 0, s>>>(lp.Fn.as<cpx<T>>(), lp.nrel, R, Ms, Ma, lp.Fc.as<cpx<T>>());
+      {
+        StageTimer tm(p, s, IFGF_STAGE_COEFFS);
+        k_coeffs<T, PS, PA><<<dim3(lp.nrel, R), TPB, 0, s>>>(lp.Fn.as<cpx<T>>(), lp.nrel, R, Ms, Ma, lp.Fc.as<cpx<T>>());
+      }
       HIPCHK(hipGetLastError());
     }
   }
@@ -597,8 +611,11 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     dlo = std::max(dlo, level_lo);
     dhi = std::min(dhi, level_hi);
   }
-  k_targets<T, PS, PA><<<gpts, TPB, 0, s>>>(p->pts.as<double>(), n, p->perm.as<int>(), uacc, near ? 1 : 0, L, dlo, dhi,
-                                            p->k, kind, R, dtype, 0, nullptr, u, p->err.as<int>());
+  {
+    StageTimer tm(p, s, IFGF_STAGE_TARGETS);
+    k_targets<T, PS, PA><<<gpts, TPB, 0, s>>>(p->pts.as<double>(), n, p->perm.as<int>(), uacc, near ? 1 : 0, L, dlo,
+                                              dhi, p->k, kind, R, dtype, 0, nullptr, u, p->err.as<int>());
+  }
   HIPCHK(hipGetLastError());
 }
 

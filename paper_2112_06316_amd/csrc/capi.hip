@@ -41,6 +41,24 @@ void DevBuf::release() {
 
 DevBuf::~DevBuf() { release(); }
 
+StageTimer::StageTimer(ifgf_plan_s* pp, hipStream_t ss, int stage) : p(pp), s(ss) {
+  if (p->ev.empty() || 2 * (p->ev_used + 1) > (int)p->ev.size()) return;
+  slot = p->ev_used++;
+  p->ev_stage[slot] = stage;
+  (void)hipEventRecord(p->ev[2 * slot], s);
+}
+
+StageTimer::~StageTimer() {
+  if (slot >= 0) (void)hipEventRecord(p->ev[2 * slot + 1], s);
+}
+
+static void free_events(ifgf_plan_s* p) {
+  for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+  p->ev.clear();
+  p->ev_stage.clear();
+  p->ev_used = 0;
+}
+
 }  // namespace ifgf
 
 using namespace ifgf;
@@ -265,9 +283,40 @@ ifgf_status ifgf_plan_check(ifgf_plan p, int32_t* flags) {
   });
 }
 
+ifgf_status ifgf_plan_set_profiling(ifgf_plan p, int32_t max_launches) {
+  return guarded([&] {
+    if (!p || max_launches < 0) throw Error{IFGF_EINVAL, "bad plan or count"};
+    HIPCHK(hipDeviceSynchronize());
+    free_events(p);
+    if (max_launches == 0) return;
+    p->ev.resize(2 * (size_t)max_launches, nullptr);
+    p->ev_stage.assign(max_launches, 0);
+    for (auto& e : p->ev) HIPCHK(hipEventCreate(&e));
+  });
+}
+
+ifgf_status ifgf_plan_read_profile(ifgf_plan p, double* ms, int64_t* launches) {
+  return guarded([&] {
+    if (!p || !ms || !launches) throw Error{IFGF_EINVAL, "null pointer argument"};
+    for (int i = 0; i < IFGF_NSTAGES; ++i) {
+      ms[i] = 0;
+      launches[i] = 0;
+    }
+    for (int i = 0; i < p->ev_used; ++i) {
+      HIPCHK(hipEventSynchronize(p->ev[2 * i + 1]));
+      float t = 0;
+      HIPCHK(hipEventElapsedTime(&t, p->ev[2 * i], p->ev[2 * i + 1]));
+      ms[p->ev_stage[i]] += t;
+      launches[p->ev_stage[i]] += 1;
+    }
+    p->ev_used = 0;
+  });
+}
+
 void ifgf_plan_destroy(ifgf_plan p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
+  free_events(p);
   delete p;
 }
 

@@ -83,6 +83,10 @@ struct ifgf_plan_s {
   ifgf::DevBuf adj_g[IFGF_MAX_LEVELS];   // transposed-apply coefficient-space buffers
   ifgf::DevBuf err;           // int [4] device error flags
   int64_t near_pairs = 0;
+  // kernel timing (ifgf_plan_set_profiling)
+  std::vector<hipEvent_t> ev;        // 2 per timed launch
+  std::vector<int> ev_stage;
+  int ev_used = 0;
   std::atomic<int> busy{0};
   int last_rhs = 0;
 };
@@ -104,5 +108,14 @@ void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, 
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
 
 bool supported_order(int ps, int pa);
+
+// Brackets one kernel launch with events when profiling is enabled.
+struct StageTimer {
+  ifgf_plan_s* p;
+  hipStream_t s;
+  int slot = -1;
+  StageTimer(ifgf_plan_s* pp, hipStream_t ss, int stage);
+  ~StageTimer();
+};
 
 }  // namespace ifgf

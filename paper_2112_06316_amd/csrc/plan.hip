@@ -480,7 +480,7 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
                                                acc.as<unsigned long long>());
     for (int d = 3; d <= D; ++d) {
       LevelPlan& lv = p->lev[d];
-      k_pair_stats<<<nblocks(lv.nb), TPB, 0, s>>>(lv.start.as<int>(), lv.nb, lv.cou_off.as<int>(), lv.cou.as<int>(), 1,
+      k_pair_stats<<<nblocks(lv.nb), TPB, 0, s>>>(lv.start.as<int>(), lv.nb, lv.cou_off.as<int>(), lv.cou.as<int>(), 0,
                                                  acc.as<unsigned long long>() + d);
     }
     HIPCHK(hipGetLastError());
