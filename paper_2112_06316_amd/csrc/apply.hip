@@ -42,7 +42,7 @@ template <> struct Prec<double> {
 };
 
 template <typename T> __device__ __forceinline__ void sincos_t(T x, T* s, T* c);
-template <> __device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) { sincosf(x, s, c); }
+template <> __device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) { sincos_f(x, s, c); }
 template <> __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) { sincos(x, s, c); }
 
 template <typename T> __device__ __forceinline__ T sqrt_t(T x);
@@ -324,13 +324,8 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
 // ---------------------------------------------------------------------------
 // Interpolant evaluation with wave-uniform coefficients.
 // ---------------------------------------------------------------------------
-// Coefficients are read through the constant address space: they are not
-// written while an apply kernel runs, and with a wave-uniform address the
-// reads become scalar loads shared by the wave.
-template <typename T> using cptr = const __attribute__((address_space(4))) T*;   // interleaved re, im
-
 template <typename T, int PS, int PA>
-__device__ __forceinline__ cpx<T> contract(cptr<T> C, const T* Ts, const T* Tt, const T* Tp) {
+__device__ __forceinline__ cpx<T> contract_lds(const T* C, const T* Ts, const T* Tt, const T* Tp) {
   cpx<T> acc = {0, 0};
 #pragma unroll
   for (int i = 0; i < PS; ++i) {
@@ -355,89 +350,251 @@ __device__ __forceinline__ cpx<T> contract(cptr<T> C, const T* Ts, const T* Tt, 
 
 // For every active lane with slot >= 0, evaluates the interpolant of cone
 // `slot` of F (coefficient layout [slot][R][P], right-hand side r) at
-// (ts, tt, tp).
+// (ts, tt, tp).  The wave serves one slot at a time: the active lanes copy
+// that cone's P coefficients into the wave's LDS buffer `wbuf` (2P values,
+// one coalesced read) and the lanes holding the slot contract against it
+// with wave-uniform LDS reads.  LDS operations of a wave complete in order,
+// so the copy is visible to the reads that follow it.
 template <typename T, int PS, int PA>
 __device__ __forceinline__ cpx<T> eval_uniform(const cpx<T>* __restrict__ F, int slot, int R, int r, T ts, T tt,
-                                               T tp) {
+                                               T tp, T* wbuf) {
   constexpr int P = PS * PA * PA;
   T Ts[PS], Tt[PA], Tp[PA];
   cheb_T<T, PS>(ts, Ts);
   cheb_T<T, PA>(tt, Tt);
   cheb_T<T, PA>(tp, Tp);
   cpx<T> out = {0, 0};
+  const uint64_t act = __ballot(1);
+  const int nact = __popcll(act);
+  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0));
+  cpx<T>* wb = reinterpret_cast<cpx<T>*>(wbuf);
   uint64_t pending = __ballot(slot >= 0);
   while (pending) {
-    int lead = first_lane(pending);
-    int su = __builtin_amdgcn_readfirstlane(__shfl(slot, lead, 64));
-    bool mine = slot == su;
+    const int lead = first_lane(pending);
+    const int su = __builtin_amdgcn_readfirstlane(__shfl(slot, lead, 64));
+    const bool mine = slot == su;
     pending &= ~__ballot(mine);
-    if (mine) {
-      // the offset is made wave-uniform here, inside the branch: the compiler
-      // may otherwise rewrite su as the (equal, per-lane) slot
-      uint64_t off = (uint64_t)(((int64_t)su * R + r) * P);
-      uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)off);
-      uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(off >> 32));
-      out = contract<T, PS, PA>((cptr<T>)(const T*)(F + (((uint64_t)hi << 32) | lo)), Ts, Tt, Tp);
-    }
+    const cpx<T>* src = F + ((int64_t)su * R + r) * P;
+    for (int c = rank; c < P; c += nact) wb[c] = src[c];
+    __builtin_amdgcn_wave_barrier();
+    if (mine) out = contract_lds<T, PS, PA>(wbuf, Ts, Tt, Tp);
+    __builtin_amdgcn_wave_barrier();
   }
   return out;
 }
 
 // ---------------------------------------------------------------------------
-// upward pass d -> d-1: one lane per (relevant parent cone, node).
+// upward pass d -> d-1 (Algorithm 1, parent-node update), fused with the
+// node-value -> coefficient transform of level d-1.
+//
+// One block per work item = (parent box P, up to PropShape::CH consecutive
+// relevant cones of P).  For each child B of P the block
+//   A. locates every node of its cones in B's cone segments (slot, local
+//      coordinates, ratio K(x,y_B)/K(x,y_P)),
+//   B. buckets the nodes by child slot in LDS (hash table + counting sort),
+//   C. evaluates the child interpolants in bucket order, so that the lanes of
+//      a wave mostly share one slot and read its coefficients once, and
+//      accumulates ratio * value into the node's LDS accumulator.
+// Finally the node values of the chunk are turned into Chebyshev
+// coefficients in LDS and written to level d-1.
 // ---------------------------------------------------------------------------
-template <typename T, int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_prop(int nrel_up, const int* __restrict__ rel_box_up,
-                                              const int* __restrict__ rel_cone_up, const int* __restrict__ child_lo_up,
-                                              const int* __restrict__ coords, const int* __restrict__ slot_c,
-                                              const cpx<T>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct,
-                                              double k, int kind, int R, cpx<T>* __restrict__ Fn_up,
-                                              int* __restrict__ err) {
+// Chunking of the upward pass: CH cones of P = P_s P_ang^2 nodes per block
+// of BS threads, chosen so that CH * P (nearly) fills whole passes.
+template <int P> struct PropShape;
+template <> struct PropShape<75> { static constexpr int CH = 10, BS = 256; };    // 750 nodes, 3 x 256
+template <> struct PropShape<144> { static constexpr int CH = 4, BS = 192; };    // 576 nodes, 3 x 192
+
+template <typename T> struct PropGeomT;
+template <> struct PropGeomT<float> { using P = PropF; };
+template <> struct PropGeomT<double> { using P = Prop64; };
+
+__device__ __forceinline__ uint32_t hash_slot(int slot, int bits) {
+  return ((uint32_t)slot * 2654435761u) >> (32 - bits);
+}
+
+// In-LDS exclusive scan of n counts, in place.
+template <int BS>
+__device__ __forceinline__ void block_scan_inplace(int* a, int n, int* wsum) {
+  const int per = (n + BS - 1) / BS;
+  const int base = threadIdx.x * per;
+  const int cnt = max(0, min(per, n - base));
+  int tot = 0;
+  for (int i = 0; i < cnt; ++i) tot += a[base + i];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = tot;
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[wid] = x;
+  __syncthreads();
+  int run = x - tot;
+  for (int w = 0; w < wid; ++w) run += wsum[w];
+  for (int i = 0; i < cnt; ++i) {
+    int v = a[base + i];
+    a[base + i] = run;
+    run += v;
+  }
+  __syncthreads();
+}
+
+// Chebyshev transform of nc cones of node values in LDS (in: v, scratch: t),
+// written to global coefficients out[((cone) * R + r) * P + j].
+template <typename T, int PS, int PA, int BS>
+__device__ __forceinline__ void lds_coeffs_store(cpx<T>* v, cpx<T>* t, int nc, const T* ms, const T* ma,
+                                                 cpx<T>* __restrict__ out, int R, int r) {
   constexpr int P = PS * PA * PA;
+  const int tot = nc * P;
+  for (int q = threadIdx.x; q < tot; q += BS) {
+    const int c = q / P, j = q % P, i = j / (PA * PA), jj = (j / PA) % PA, l = j % PA;
+    cpx<T> acc = {0, 0};
+    for (int k = 0; k < PS; ++k) {
+      cpx<T> x = v[c * P + (k * PA + jj) * PA + l];
+      acc.re += ms[i * PS + k] * x.re;
+      acc.im += ms[i * PS + k] * x.im;
+    }
+    t[q] = acc;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < tot; q += BS) {
+    const int c = q / P, j = q % P, i = j / (PA * PA), jj = (j / PA) % PA, l = j % PA;
+    cpx<T> acc = {0, 0};
+    for (int k = 0; k < PA; ++k) {
+      cpx<T> x = t[c * P + (i * PA + k) * PA + l];
+      acc.re += ma[jj * PA + k] * x.re;
+      acc.im += ma[jj * PA + k] * x.im;
+    }
+    v[q] = acc;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < tot; q += BS) {
+    const int c = q / P, j = q % P, i = j / (PA * PA), jj = (j / PA) % PA, l = j % PA;
+    cpx<T> acc = {0, 0};
+    for (int k = 0; k < PA; ++k) {
+      cpx<T> x = v[c * P + (i * PA + jj) * PA + k];
+      acc.re += ma[l * PA + k] * x.re;
+      acc.im += ma[l * PA + k] * x.im;
+    }
+    out[((int64_t)c * R + r) * P + j] = acc;
+  }
+}
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
+    const int4* __restrict__ work, const int* __restrict__ rel_cone_up, const int* __restrict__ child_lo_up,
+    const int* __restrict__ coords, const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c, LevelGeom gp,
+    LevelGeom gc, ChebTab ct, const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind, int R,
+    cpx<T>* __restrict__ Fc_up, int* __restrict__ err) {
+  constexpr int P = PS * PA * PA;
+  constexpr int BS = PropShape<P>::BS;
+  constexpr int NN = PropShape<P>::CH * P;
+  constexpr int HB = NN <= 256 ? 8 : (NN <= 512 ? 9 : (NN <= 1024 ? 10 : 11));   // 2^HB >= NN
+  constexpr int HT = 1 << HB;
+  static_assert(HT >= NN, "the hash table must be able to hold every node");
+  __shared__ cpx<T> acc[NN], tmp[NN];
+  __shared__ T st[NN][3];            // local coordinates in the child cone
+  __shared__ int skey[NN];
+  __shared__ short sord[NN];
+  __shared__ int hkey[HT], hoff[HT];
+  __shared__ int wsum[BS / 64];
+  __shared__ T ms[PS * PS], ma[PA * PA];
+  __shared__ __align__(16) T cbuf[BS / 64][2 * P];
+
+  const int4 wk = work[blockIdx.x];
+  const int Pb = wk.x, s0 = wk.y, ncn = wk.z - wk.y;
+  const int nn = ncn * P;
   const int r = blockIdx.y;
-  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (t >= (int64_t)nrel_up * P) return;
-  const int s = (int)(t / P), node = (int)(t % P);
-  const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
-  const int Pb = rel_box_up[s], pcid = rel_cone_up[s];
+  if (threadIdx.x < PS * PS) ms[threadIdx.x] = Ms[threadIdx.x];
+  if (threadIdx.x < PA * PA) ma[threadIdx.x] = Ma[threadIdx.x];
+  for (int q = threadIdx.x; q < nn; q += BS) acc[q] = {0, 0};
+  for (int h = threadIdx.x; h < HT; h += BS) {
+    hkey[h] = -1;
+    hoff[h] = 0;
+  }
+  __syncthreads();
+
   const int B0 = child_lo_up[Pb], B1 = child_lo_up[Pb + 1];
-  cpx<T> acc = {0, 0};
   for (int B = B0; B < B1; ++B) {
     const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
-    T ts, tt, tp, ratio_re, ratio_im;
-    int cid;
-    if constexpr (Prec<T>::f32) {
-      PropF pr = prop_loc32(pcid, ai, bi, ci, oct, gp, gc, ct);
-      cid = pr.loc.cid;
-      ts = pr.loc.ts;
-      tt = pr.loc.tt;
-      tp = pr.loc.tp;
-      float sn_, cs_;
-      sincosf((float)k * pr.dr, &sn_, &cs_);
-      ratio_re = pr.rp_over_rc * cs_;
-      ratio_im = pr.rp_over_rc * sn_;
-    } else {
-      Prop64 pr = prop_loc64(pcid, ai, bi, ci, oct, gp, gc, ct);
-      cid = pr.loc.cid;
-      ts = pr.loc.ts;
-      tt = pr.loc.tt;
-      tp = pr.loc.tp;
-      double sn_, cs_;
-      sincos(k * pr.dr, &sn_, &cs_);
-      ratio_re = pr.rp_over_rc * cs_;
-      ratio_im = pr.rp_over_rc * sn_;
+    // A: locate each node in B's cones; count bucket sizes
+    for (int q = threadIdx.x; q < nn; q += BS) {
+      const int c = q / P, node = q % P;
+      const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
+      const int pcid = rel_cone_up[s0 + c];
+      T x[3], rp;
+      typename PropGeomT<T>::P pr;
+      if constexpr (Prec<T>::f32) {
+        node_rel32(pcid, ai, bi, ci, gp, ct, x, &rp);
+        pr = child_loc32(x, rp, oct, gc);
+      } else {
+        node_rel64(pcid, ai, bi, ci, gp, ct, x, &rp);
+        pr = child_loc64(x, rp, oct, gc);
+      }
+      const int sl = slot_c[(int64_t)B * gc.ncone + pr.loc.cid];
+      if (sl < 0) atomicOr(err, 2);
+      st[q][0] = pr.loc.ts;
+      st[q][1] = pr.loc.tt;
+      st[q][2] = pr.loc.tp;
+      tmp[q] = {pr.rp_over_rc, pr.dr};
+      skey[q] = sl;
+      const int hk = sl >= 0 ? sl : 0x7ffffffe;   // never the empty marker -1
+      uint32_t h = hash_slot(hk, HB);
+      while (true) {
+        int prev = atomicCAS(&hkey[h], -1, hk);
+        if (prev == -1 || prev == hk) break;
+        h = (h + 1) & (HT - 1);
+      }
+      atomicAdd(&hoff[h], 1);
     }
-    if (kind == IFGF_KERNEL_CONSTANT) {
-      ratio_re = 1;
-      ratio_im = 0;
+    __syncthreads();
+    block_scan_inplace<BS>(hoff, HT, wsum);
+    // B: counting sort of the nodes by slot
+    for (int q = threadIdx.x; q < nn; q += BS) {
+      const int sl = skey[q];
+      const int hk = sl >= 0 ? sl : 0x7ffffffe;
+      uint32_t h = hash_slot(hk, HB);
+      while (hkey[h] != hk) h = (h + 1) & (HT - 1);
+      const int pos = atomicAdd(&hoff[h], 1);
+      sord[pos] = (short)q;
     }
-    int sl = slot_c[(int64_t)B * gc.ncone + cid];
-    if (sl < 0) atomicOr(err, 2);
-    cpx<T> v = eval_uniform<T, PS, PA>(Fc_c, sl, R, r, ts, tt, tp);
-    acc.re += ratio_re * v.re - ratio_im * v.im;
-    acc.im += ratio_re * v.im + ratio_im * v.re;
+    __syncthreads();
+    for (int h = threadIdx.x; h < HT; h += BS) {   // the table is free again; cleared for the next child
+      hkey[h] = -1;
+      hoff[h] = 0;
+    }
+    // C: evaluate in bucket order
+    for (int qb = 0; qb < nn; qb += BS) {
+      const int qq = qb + threadIdx.x;
+      int n = -1, sl = -1;
+      if (qq < nn) {
+        n = sord[qq];
+        sl = skey[n];
+      }
+      T ts = 0, tt = 0, tp = 0;
+      if (n >= 0) {
+        ts = st[n][0];
+        tt = st[n][1];
+        tp = st[n][2];
+      }
+      cpx<T> v = eval_uniform<T, PS, PA>(Fc_c, sl, R, r, ts, tt, tp, cbuf[threadIdx.x >> 6]);
+      if (n >= 0 && sl >= 0) {
+        T rr = tmp[n].re, dr = tmp[n].im;
+        T c_, s_;
+        if (kind == IFGF_KERNEL_CONSTANT) {
+          c_ = 1;
+          s_ = 0;
+          rr = 1;
+        } else {
+          sincos_t<T>((T)k * dr, &s_, &c_);
+        }
+        const T rre = rr * c_, rim = rr * s_;
+        acc[n].re += rre * v.re - rim * v.im;
+        acc[n].im += rre * v.im + rim * v.re;
+      }
+    }
+    __syncthreads();
   }
-  Fn_up[((int64_t)s * R + r) * P + node] = acc;
+  lds_coeffs_store<T, PS, PA, BS>(acc, tmp, ncn, ms, ma, Fc_up + (int64_t)s0 * R * P, R, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -463,6 +620,8 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
                                                  int dlo, int dhi, double k, int kind, int R, int dtype, int conj_out,
                                                  const double* __restrict__ wout, void* __restrict__ u,
                                                  int* __restrict__ err) {
+  constexpr int P = PS * PA * PA;
+  __shared__ __align__(16) T cbuf[TPB / 64][2 * P];
   const int r = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (i >= n) return;
@@ -512,7 +671,7 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
       }
       int sl = lv.slot[(int64_t)B * lv.g.ncone + cid];
       if (sl < 0) atomicOr(err, 4);
-      cpx<T> v = eval_uniform<T, PS, PA>(lv.Fc, sl, R, r, ts, tt, tp);
+      cpx<T> v = eval_uniform<T, PS, PA>(lv.Fc, sl, R, r, ts, tt, tp, cbuf[threadIdx.x >> 6]);
       lacc.re += e_re * v.re - e_im * v.im;
       lacc.im += e_re * v.im + e_im * v.re;
     }
@@ -580,20 +739,11 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     for (int d = D; d >= 4; --d) {
       LevelPlan& lc = p->lev[d];
       LevelPlan& lp = p->lev[d - 1];
-      if (lp.nrel == 0) continue;
-      int64_t items = (int64_t)lp.nrel * P;
-      {
+      if (lp.nrel == 0 || lp.nwork == 0) continue;
       StageTimer tm(p, s, IFGF_STAGE_PROP);
-      k_prop<T, PS, PA><<<dim3(nblocks(items), R), TPB, 0, s>>>(
-          lp.nrel, lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
-          lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, p->k, kind, R, lp.Fn.as<cpx<T>>(),
-          p->err.as<int>());
-      }
-      HIPCHK(hipGetLastError());
-      {
-        StageTimer tm(p, s, IFGF_STAGE_COEFFS);
-        k_coeffs<T, PS, PA><<<dim3(lp.nrel, R), TPB, 0, s>>>(lp.Fn.as<cpx<T>>(), lp.nrel, R, Ms, Ma, lp.Fc.as<cpx<T>>());
-      }
+      k_prop<T, PS, PA><<<dim3((unsigned)lp.nwork, R), PropShape<P>::BS, 0, s>>>(
+          lp.work.as<int4>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(), lc.slot.as<int>(),
+          lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, Ms, Ma, p->k, kind, R, lp.Fc.as<cpx<T>>(), p->err.as<int>());
       HIPCHK(hipGetLastError());
     }
   }
@@ -629,6 +779,12 @@ void dispatch_apply(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype
 }
 
 }  // namespace
+
+int prop_chunk(int P) {
+  if (P == 75) return PropShape<75>::CH;
+  if (P == 144) return PropShape<144>::CH;
+  return 1;
+}
 
 bool supported_order(int ps, int pa) { return (ps == 3 && pa == 5) || (ps == 4 && pa == 6); }
 

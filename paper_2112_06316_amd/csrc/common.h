@@ -87,13 +87,66 @@ __device__ __forceinline__ Loc locate64(double dx, double dy, double dz, double 
   return L;
 }
 
+// FP32 helpers of the FP32-interpolation mode: hardware reciprocal and
+// square root (about 1 ulp) and a polynomial atan2.  The atan kernel is an
+// odd polynomial fitted by least squares on |t| <= tan(pi/8) (max error
+// 4.4e-8 rad); larger ratios are folded with atan(t) = pi/4 + atan((t-1)/(t+1))
+// and the octant symmetries.  Used identically at plan and apply time.
+__device__ __forceinline__ float rcp_f(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float sqrt_f(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+__device__ __forceinline__ float atan2_f(float y, float x) {
+#pragma clang fp contract(off)
+  const float ax = fabsf(x), ay = fabsf(y);
+  const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+  if (mx == 0.0f) return 0.0f;
+  const float t = mn * rcp_f(mx);
+  const bool big = t > 0.41421356f;
+  const float u = big ? (t - 1.0f) * rcp_f(t + 1.0f) : t;
+  const float u2 = u * u;
+  float q = fmaf(u2, 0.0772617757f, -0.1375157684f);
+  q = fmaf(u2, q, 0.1996154934f);
+  q = fmaf(u2, q, -0.3333218396f);
+  q = fmaf(u2, q, 0.9999998808f);
+  float r = u * q;
+  if (big) r += 0.785398163f;
+  if (ay > ax) r = 1.570796327f - r;
+  if (x < 0.0f) r = 3.141592654f - r;
+  return y < 0.0f ? -r : r;
+}
+
+// sin and cos in FP32: quadrant k = rint(2x/pi), remainder x - k pi/2 by a
+// three-term Cody-Waite reduction with FMAs (pi/2 split into FP32 parts),
+// then polynomials on |r| <= pi/4 whose coefficients are a least-squares fit
+// (max error 6e-8 for sin, 8e-8 for cos).  Meant for |x| up to ~1e5.
+__device__ __forceinline__ void sincos_f(float x, float* sn, float* cs) {
+#pragma clang fp contract(off)
+  const float kq = rintf(x * 0.636619772f);
+  float r = fmaf(-kq, 1.57079637f, x);
+  r = fmaf(-kq, -4.37113883e-08f, r);
+  r = fmaf(-kq, -1.77635684e-15f, r);
+  const float r2 = r * r;
+  float ps = fmaf(r2, -0.000194934968f, 0.00833195820f);
+  ps = fmaf(r2, ps, -0.166666508f);
+  const float sr = fmaf(r * r2, ps, r);
+  float pc = fmaf(r2, 2.43892027e-05f, -0.00138867483f);
+  pc = fmaf(r2, pc, 0.0416666232f);
+  pc = fmaf(r2, pc, -0.5f);
+  const float cr = fmaf(r2, pc, 1.0f);
+  const int q = ((int)kq) & 3;
+  const float s0 = (q & 1) ? cr : sr;
+  const float c0 = (q & 1) ? sr : cr;
+  *sn = (q & 2) ? -s0 : s0;
+  *cs = ((q + 1) & 2) ? -c0 : c0;
+}
+
 // Cone location, FP32 (used by the FP32-interpolation precision mode).
 __device__ __forceinline__ LocF locate32(float dx, float dy, float dz, float s, const LevelGeom& g) {
 #pragma clang fp contract(off)
   LocF L;
-  float rho = sqrtf(dx * dx + dy * dy);
-  float th = atan2f(rho, dz);
-  float ph = atan2f(dy, dx);
+  float rho = sqrt_f(dx * dx + dy * dy);
+  float th = atan2_f(rho, dz);
+  float ph = atan2_f(dy, dx);
   if (ph < 0.0f) ph += (float)IFGF_TWO_PI;
   float us = s * g.inv_dsf, ut = th * g.inv_daf, up = ph * g.inv_daf;
   int is = clampi((int)floorf(us), 0, g.ns - 1);
@@ -125,7 +178,7 @@ __device__ __forceinline__ LocF target_loc32(const double* x, const double* c, c
   double r = sqrt(dx * dx + dy * dy + dz * dz);
   *r_out = r;
   float rf = (float)r;
-  return locate32((float)dx, (float)dy, (float)dz, g.hf / rf, g);
+  return locate32((float)dx, (float)dy, (float)dz, g.hf * rcp_f(rf), g);
 }
 
 // ---------------------------------------------------------------------------
@@ -166,8 +219,8 @@ __device__ __forceinline__ void node_dir32(int cid, int a, int b, int c, const L
   float th = ((float)it + ct.uaf[b]) * g.daf;
   float ph = ((float)ip + ct.uaf[c]) * g.daf;
   float st, ctt, sp, cp;
-  sincosf(th, &st, &ctt);
-  sincosf(ph, &sp, &cp);
+  sincos_f(th, &st, &ctt);
+  sincos_f(ph, &sp, &cp);
   e[0] = st * cp;
   e[1] = st * sp;
   e[2] = ctt;
@@ -195,41 +248,62 @@ struct Prop64 {
   double dr;
 };
 
-__device__ __forceinline__ Prop64 prop_loc64(int pcid, int a, int b, int c, int oct, const LevelGeom& gp,
-                                             const LevelGeom& gc, const ChebTab& ct) {
+// Position of node (a, b, c) of parent cone pcid relative to the parent
+// centre, and its distance r_p = h_p / s.
+__device__ __forceinline__ void node_rel64(int pcid, int a, int b, int c, const LevelGeom& gp, const ChebTab& ct,
+                                           double* x, double* rp) {
 #pragma clang fp contract(off)
   double e[3], s;
   node_dir64(pcid, a, b, c, gp, ct, e, &s);
-  double rp = gp.h / s;
+  double r = gp.h / s;
+  x[0] = r * e[0];
+  x[1] = r * e[1];
+  x[2] = r * e[2];
+  *rp = r;
+}
+
+__device__ __forceinline__ void node_rel32(int pcid, int a, int b, int c, const LevelGeom& gp, const ChebTab& ct,
+                                           float* x, float* rp) {
+#pragma clang fp contract(off)
+  float e[3], s;
+  node_dir32(pcid, a, b, c, gp, ct, e, &s);
+  float r = gp.hf * rcp_f(s);
+  x[0] = r * e[0];
+  x[1] = r * e[1];
+  x[2] = r * e[2];
+  *rp = r;
+}
+
+// The node x (relative to the parent centre, |x| = rp) about the child of
+// octant `oct`.
+__device__ __forceinline__ Prop64 child_loc64(const double* x, double rp, int oct, const LevelGeom& gc) {
+#pragma clang fp contract(off)
   double hd = 0.5 * gc.H;
   double dl[3] = {(oct & 1) ? hd : -hd, (oct & 2) ? hd : -hd, (oct & 4) ? hd : -hd};
-  double x0 = rp * e[0] - dl[0], x1 = rp * e[1] - dl[1], x2 = rp * e[2] - dl[2];
+  double x0 = x[0] - dl[0], x1 = x[1] - dl[1], x2 = x[2] - dl[2];
   double rc = sqrt(x0 * x0 + x1 * x1 + x2 * x2);
   Prop64 P;
   P.loc = locate64(x0, x1, x2, gc.h / rc, gc);
   double dd = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
-  double xd = rp * (e[0] * dl[0] + e[1] * dl[1] + e[2] * dl[2]);
+  double xd = x[0] * dl[0] + x[1] * dl[1] + x[2] * dl[2];
   P.dr = (dd - 2.0 * xd) / (rc + rp);
   P.rp_over_rc = rp / rc;
   return P;
 }
 
-__device__ __forceinline__ PropF prop_loc32(int pcid, int a, int b, int c, int oct, const LevelGeom& gp,
-                                            const LevelGeom& gc, const ChebTab& ct) {
+__device__ __forceinline__ PropF child_loc32(const float* x, float rp, int oct, const LevelGeom& gc) {
 #pragma clang fp contract(off)
-  float e[3], s;
-  node_dir32(pcid, a, b, c, gp, ct, e, &s);
-  float rp = gp.hf / s;
   float hd = (float)(0.5 * gc.H);
   float dl[3] = {(oct & 1) ? hd : -hd, (oct & 2) ? hd : -hd, (oct & 4) ? hd : -hd};
-  float x0 = rp * e[0] - dl[0], x1 = rp * e[1] - dl[1], x2 = rp * e[2] - dl[2];
-  float rc = sqrtf(x0 * x0 + x1 * x1 + x2 * x2);
+  float x0 = x[0] - dl[0], x1 = x[1] - dl[1], x2 = x[2] - dl[2];
+  float rc = sqrt_f(x0 * x0 + x1 * x1 + x2 * x2);
+  float irc = rcp_f(rc);
   PropF P;
-  P.loc = locate32(x0, x1, x2, gc.hf / rc, gc);
+  P.loc = locate32(x0, x1, x2, gc.hf * irc, gc);
   float dd = dl[0] * dl[0] + dl[1] * dl[1] + dl[2] * dl[2];
-  float xd = rp * (e[0] * dl[0] + e[1] * dl[1] + e[2] * dl[2]);
-  P.dr = (dd - 2.0f * xd) / (rc + rp);
-  P.rp_over_rc = rp / rc;
+  float xd = x[0] * dl[0] + x[1] * dl[1] + x[2] * dl[2];
+  P.dr = (dd - 2.0f * xd) * rcp_f(rc + rp);
+  P.rp_over_rc = rp * irc;
   return P;
 }
 
@@ -253,7 +327,7 @@ __device__ __forceinline__ void expi_reduced32(double phase, float* c, float* s)
   double nq = rint(phase * inv2pi);
   double red = fma(-nq, p_hi, phase);
   red = fma(-nq, p_lo, red);
-  sincosf((float)red, s, c);
+  sincos_f((float)red, s, c);
 }
 
 // ---------------------------------------------------------------------------

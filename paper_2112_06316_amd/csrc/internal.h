@@ -55,7 +55,9 @@ struct LevelPlan {
   DevBuf slot_off;            // int [nb + 1]
   int nrel = 0;
   DevBuf rel_box, rel_cone;   // int [nrel]
-  DevBuf Fn, Fc;              // node values / coefficients [nrel][P][max_rhs] complex
+  DevBuf Fn, Fc;              // node values (finest level only) / coefficients [nrel][max_rhs][P] complex
+  DevBuf work;                // int4 [nwork]: (box, first slot, end slot, 0) chunks of this level's
+  int64_t nwork = 0;          //   relevant cones, the work items of the upward pass into this level
   // statistics
   int64_t cousin_pairs = 0;
   int64_t prop_evals = 0;     // child interpolations into level d-1 nodes
@@ -108,6 +110,7 @@ void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, 
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
 
 bool supported_order(int ps, int pa);
+int prop_chunk(int P);
 
 // Brackets one kernel launch with events when profiling is enabled.
 struct StageTimer {

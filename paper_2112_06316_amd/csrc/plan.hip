@@ -263,9 +263,13 @@ __global__ __launch_bounds__(TPB) void k_mark_parent_nodes(int nrel_up, int P, c
   int s = (int)(t / P), node = (int)(t % P);
   int a = node / (ct.pa * ct.pa), b = (node / ct.pa) % ct.pa, c = node % ct.pa;
   int Pb = rel_box_up[s], pcid = rel_cone_up[s];
+  float xf[3], rpf;
+  double xd[3], rpd;
+  if (F32) node_rel32(pcid, a, b, c, gp, ct, xf, &rpf);
+  else node_rel64(pcid, a, b, c, gp, ct, xd, &rpd);
   for (int B = child_lo_up[Pb]; B < child_lo_up[Pb + 1]; ++B) {
     int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
-    int cid = F32 ? prop_loc32(pcid, a, b, c, oct, gp, gc, ct).loc.cid : prop_loc64(pcid, a, b, c, oct, gp, gc, ct).loc.cid;
+    int cid = F32 ? child_loc32(xf, rpf, oct, gc).loc.cid : child_loc64(xd, rpd, oct, gc).loc.cid;
     mark[(int64_t)B * gc.ncone + cid] = 1;
   }
 }
@@ -596,12 +600,31 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
     HIPCHK(hipStreamSynchronize(s));
   }
 
+  // ---- work items of the upward pass: chunks of each box's relevant cones --------
+  const int CH = prop_chunk(P);
+  for (int d = 3; d < D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    std::vector<int> so(lv.nb + 1);
+    HIPCHK(hipMemcpy(so.data(), lv.slot_off.p, sizeof(int) * (lv.nb + 1), hipMemcpyDeviceToHost));
+    std::vector<int> wk;
+    for (int b = 0; b < lv.nb; ++b)
+      for (int s0 = so[b]; s0 < so[b + 1]; s0 += CH) {
+        wk.push_back(b);
+        wk.push_back(s0);
+        wk.push_back(std::min(s0 + CH, so[b + 1]));
+        wk.push_back(0);
+      }
+    lv.nwork = (int64_t)wk.size() / 4;
+    lv.work.alloc(sizeof(int) * std::max<size_t>(4, wk.size()));
+    if (!wk.empty()) HIPCHK(hipMemcpy(lv.work.p, wk.data(), sizeof(int) * wk.size(), hipMemcpyHostToDevice));
+  }
+
   // ---- workspaces -------------------------------------------------------------
   size_t csz = f32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
   int R = p->opt.max_rhs;
   for (int d = 3; d <= D; ++d) {
     LevelPlan& lv = p->lev[d];
-    lv.Fn.alloc(csz * (size_t)std::max(1, lv.nrel) * P * R);
+    if (d == D) lv.Fn.alloc(csz * (size_t)std::max(1, lv.nrel) * P * R);
     lv.Fc.alloc(csz * (size_t)std::max(1, lv.nrel) * P * R);
   }
   p->a.alloc(csz * (size_t)n * R);

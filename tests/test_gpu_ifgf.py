@@ -107,12 +107,15 @@ def test_stage_parity_with_reference(precision):
     for d in (3, 4):
         ud = plan.apply_stages(s, 2, d, d).cpu().numpy()
         assert rel_inf(ud[perm], info["level_u"][d]) < tol * 10, d
-    # fields at the nodes, per level
+    # fields per level: node values at the finest level, coefficients at all
     u = plan.apply(s).cpu().numpy()
+    F = plan.export_field(4, 0)[:, 0, :]
+    Fr = np.concatenate([v.reshape(v.shape[0], -1) for v in info["F_nodes"][4]])
+    assert rel_inf(F, Fr) < tol * 10
     for d in (3, 4):
-        F = plan.export_field(d, 0)[:, 0, :]
-        Fr = np.concatenate([v.reshape(v.shape[0], -1) for v in info["F_nodes"][d]])
-        assert rel_inf(F, Fr) < tol * 10, d
+        C = plan.export_field(d, 1)[:, 0, :]
+        Cr = np.concatenate([R.cheb_coeffs_3d(v).reshape(v.shape[0], -1) for v in info["F_nodes"][d]])
+        assert rel_inf(C, Cr) < tol * 10, d
     assert rel_inf(u, u_ref) < tol * 10
     assert plan.check() == 0
 
