@@ -324,49 +324,59 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
 // ---------------------------------------------------------------------------
 // Interpolant evaluation with wave-uniform coefficients.
 // ---------------------------------------------------------------------------
+// sum_ijl C_ijl T_i(ts) T_j(tt) T_l(tp) with C in LDS (interleaved re, im).
+// T_0 = 1, so every partial sum starts from its T_0 term.
 template <typename T, int PS, int PA>
 __device__ __forceinline__ cpx<T> contract_lds(const T* C, const T* Ts, const T* Tt, const T* Tp) {
-  cpx<T> acc = {0, 0};
+  cpx<T> acc;
 #pragma unroll
   for (int i = 0; i < PS; ++i) {
-    cpx<T> h = {0, 0};
+    cpx<T> h;
 #pragma unroll
     for (int j = 0; j < PA; ++j) {
-      cpx<T> gsum = {0, 0};
+      const int q0 = (i * PA + j) * PA;
+      cpx<T> g = {C[2 * q0], C[2 * q0 + 1]};
 #pragma unroll
-      for (int l = 0; l < PA; ++l) {
-        const int q = (i * PA + j) * PA + l;
-        gsum.re += C[2 * q] * Tp[l];
-        gsum.im += C[2 * q + 1] * Tp[l];
+      for (int l = 1; l < PA; ++l) {
+        g.re += C[2 * (q0 + l)] * Tp[l];
+        g.im += C[2 * (q0 + l) + 1] * Tp[l];
       }
-      h.re += gsum.re * Tt[j];
-      h.im += gsum.im * Tt[j];
+      if (j == 0) {
+        h = g;
+      } else {
+        h.re += g.re * Tt[j];
+        h.im += g.im * Tt[j];
+      }
     }
-    acc.re += h.re * Ts[i];
-    acc.im += h.im * Ts[i];
+    if (i == 0) {
+      acc = h;
+    } else {
+      acc.re += h.re * Ts[i];
+      acc.im += h.im * Ts[i];
+    }
   }
   return acc;
 }
 
-// For every active lane with slot >= 0, evaluates the interpolant of cone
-// `slot` of F (coefficient layout [slot][R][P], right-hand side r) at
-// (ts, tt, tp).  The wave serves one slot at a time: the active lanes copy
-// that cone's P coefficients into the wave's LDS buffer `wbuf` (2P values,
-// one coalesced read) and the lanes holding the slot contract against it
-// with wave-uniform LDS reads.  LDS operations of a wave complete in order,
-// so the copy is visible to the reads that follow it.
+// For every lane with slot >= 0, evaluates the interpolant of cone `slot` of
+// F (coefficient layout [slot][R][P], right-hand side r) at (ts, tt, tp).
+// All 64 lanes of the wave must call it together (lanes without work pass
+// slot = -1).  The wave serves one slot at a time: its lanes copy that cone's
+// P coefficients into the wave's LDS buffer `wbuf` (2P values, coalesced
+// reads issued together) and the lanes holding the slot contract against
+// it with wave-uniform LDS reads.  LDS operations of a wave complete in
+// order, so the copy is visible to the reads that follow it.
 template <typename T, int PS, int PA>
 __device__ __forceinline__ cpx<T> eval_uniform(const cpx<T>* __restrict__ F, int slot, int R, int r, T ts, T tt,
                                                T tp, T* wbuf) {
   constexpr int P = PS * PA * PA;
+  constexpr int NCP = (P + 63) / 64;
   T Ts[PS], Tt[PA], Tp[PA];
   cheb_T<T, PS>(ts, Ts);
   cheb_T<T, PA>(tt, Tt);
   cheb_T<T, PA>(tp, Tp);
   cpx<T> out = {0, 0};
-  const uint64_t act = __ballot(1);
-  const int nact = __popcll(act);
-  const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0));
+  const int lane = threadIdx.x & 63;
   cpx<T>* wb = reinterpret_cast<cpx<T>*>(wbuf);
   uint64_t pending = __ballot(slot >= 0);
   while (pending) {
@@ -375,7 +385,13 @@ __device__ __forceinline__ cpx<T> eval_uniform(const cpx<T>* __restrict__ F, int
     const bool mine = slot == su;
     pending &= ~__ballot(mine);
     const cpx<T>* src = F + ((int64_t)su * R + r) * P;
-    for (int c = rank; c < P; c += nact) wb[c] = src[c];
+    cpx<T> v[NCP];
+#pragma unroll
+    for (int j = 0; j < NCP; ++j)
+      if (lane + 64 * j < P) v[j] = src[lane + 64 * j];
+#pragma unroll
+    for (int j = 0; j < NCP; ++j)
+      if (lane + 64 * j < P) wb[lane + 64 * j] = v[j];
     __builtin_amdgcn_wave_barrier();
     if (mine) out = contract_lds<T, PS, PA>(wbuf, Ts, Tt, Tp);
     __builtin_amdgcn_wave_barrier();
@@ -623,8 +639,9 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
   constexpr int P = PS * PA * PA;
   __shared__ __align__(16) T cbuf[TPB / 64][2 * P];
   const int r = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const bool valid = i0 < n;
+  const int64_t i = valid ? i0 : n - 1;      // lanes past the end follow the last point and store nothing
   const double* x = pts + 3 * i;
   double acc_re = 0, acc_im = 0;
   if (use_near) {
@@ -637,43 +654,56 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
     const TLevel<T>& lv = L.lv[d];
     const int A = lv.pbox[i];
     cpx<T> lacc = {0, 0};
-    for (int t = lv.cou_off[A]; t < lv.cou_off[A + 1]; ++t) {
-      const int B = lv.cou[t];
+    // The lanes of a wave may belong to different boxes with different
+    // cousin counts; the loop runs to the wave's largest count so that every
+    // lane takes part in each coefficient staging of eval_uniform.
+    const int c0 = lv.cou_off[A], cnt = lv.cou_off[A + 1] - c0;
+    int cmax = cnt;
+    for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, 64));
+    for (int t = 0; t < cmax; ++t) {
+      const bool has = valid && t < cnt;
+      const int B = lv.cou[c0 + min(t, max(cnt - 1, 0))];
       double rr;
-      T ts, tt, tp, e_re, e_im;
-      int cid;
-      if constexpr (Prec<T>::f32) {
-        LocF loc = target_loc32(x, lv.centre + 3 * B, lv.g, &rr);
-        cid = loc.cid;
-        ts = loc.ts;
-        tt = loc.tt;
-        tp = loc.tp;
-        float c, s;
-        expi_reduced32(k * rr, &c, &s);
-        float g = (float)inv4pi / (float)rr;
-        e_re = g * c;
-        e_im = g * s;
-      } else {
-        Loc loc = target_loc64(x, lv.centre + 3 * B, lv.g, &rr);
-        cid = loc.cid;
-        ts = loc.ts;
-        tt = loc.tt;
-        tp = loc.tp;
-        double c, s;
-        sincos(k * rr, &s, &c);
-        double g = inv4pi / rr;
-        e_re = g * c;
-        e_im = g * s;
+      T ts = 0, tt = 0, tp = 0, e_re = 0, e_im = 0;
+      int sl = -1;
+      if (cnt > 0) {
+        int cid;
+        if constexpr (Prec<T>::f32) {
+          LocF loc = target_loc32(x, lv.centre + 3 * B, lv.g, &rr);
+          cid = loc.cid;
+          ts = loc.ts;
+          tt = loc.tt;
+          tp = loc.tp;
+          float c, s;
+          expi_reduced32(k * rr, &c, &s);
+          float g = (float)inv4pi / (float)rr;
+          e_re = g * c;
+          e_im = g * s;
+        } else {
+          Loc loc = target_loc64(x, lv.centre + 3 * B, lv.g, &rr);
+          cid = loc.cid;
+          ts = loc.ts;
+          tt = loc.tt;
+          tp = loc.tp;
+          double c, s;
+          sincos(k * rr, &s, &c);
+          double g = inv4pi / rr;
+          e_re = g * c;
+          e_im = g * s;
+        }
+        if (kind == IFGF_KERNEL_CONSTANT) {
+          e_re = 1;
+          e_im = 0;
+        }
+        sl = lv.slot[(int64_t)B * lv.g.ncone + cid];
+        if (sl < 0 && has) atomicOr(err, 4);
       }
-      if (kind == IFGF_KERNEL_CONSTANT) {
-        e_re = 1;
-        e_im = 0;
-      }
-      int sl = lv.slot[(int64_t)B * lv.g.ncone + cid];
-      if (sl < 0) atomicOr(err, 4);
+      if (!has) sl = -1;
       cpx<T> v = eval_uniform<T, PS, PA>(lv.Fc, sl, R, r, ts, tt, tp, cbuf[threadIdx.x >> 6]);
-      lacc.re += e_re * v.re - e_im * v.im;
-      lacc.im += e_re * v.im + e_im * v.re;
+      if (has) {
+        lacc.re += e_re * v.re - e_im * v.im;
+        lacc.im += e_re * v.im + e_im * v.re;
+      }
     }
     acc_re += lacc.re;
     acc_im += lacc.im;
@@ -683,6 +713,7 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
     acc_im *= wout[i];
   }
   if (conj_out) acc_im = -acc_im;
+  if (!valid) return;
   const int64_t o = (int64_t)perm[i] * R + r;
   if (dtype == IFGF_C128) {
     ((double*)u)[2 * o] = acc_re;
