@@ -59,7 +59,7 @@ __global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, 
   int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (i >= n) return;
   int64_t j = perm[i];
-  double wi = w[i];
+  double wi = w ? w[i] : 1.0;
   for (int r = 0; r < R; ++r) {
     double re, im;
     if (dtype == IFGF_C128) {
@@ -79,11 +79,13 @@ __global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, 
 // ---------------------------------------------------------------------------
 // near field: one block per finest-level box B; targets = points of B,
 // sources = points of the neighbour boxes (self included, the i == j term
-// excluded).  Positions relative to B's centre in precision T.
+// excluded).  Positions relative to B's centre in precision T.  With TR the
+// transposed sum is formed: output j collects v_i K(x_i, x_j), whose normal
+// is the one at the output point x_j.
 // ---------------------------------------------------------------------------
 constexpr int NEAR_CHUNK = 512;
 
-template <typename T>
+template <typename T, bool TR>
 __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, const double* __restrict__ nrm,
                                               const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
                                               const int* __restrict__ nbr_off, const int* __restrict__ nbr,
@@ -121,11 +123,16 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
   for (int tb = 0; tb < nt; tb += TP) {
     const int ti = tb + tl;
     const bool tv = ti < nt;
-    T x0 = 0, x1 = 0, x2 = 0;
+    T x0 = 0, x1 = 0, x2 = 0, m0 = 0, m1 = 0, m2 = 0;
     if (tv) {
       x0 = (T)(pts[3 * (t0 + ti)] - c0);
       x1 = (T)(pts[3 * (t0 + ti) + 1] - c1);
       x2 = (T)(pts[3 * (t0 + ti) + 2] - c2);
+      if (TR) {
+        m0 = (T)nrm[3 * (t0 + ti)];
+        m1 = (T)nrm[3 * (t0 + ti) + 1];
+        m2 = (T)nrm[3 * (t0 + ti) + 2];
+      }
     }
     cpx<T> acc = {0, 0};
     for (int cb = 0; cb < nsrc; cb += NEAR_CHUNK) {
@@ -157,7 +164,9 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
             T r2 = d0 * d0 + d1 * d1 + d2 * d2;
             T rr = sqrt_t<T>(r2);
             T ir = (T)1 / rr;
-            T dn = (d0 * sn[e][0] + d1 * sn[e][1] + d2 * sn[e][2]) * ir * ir;
+            // forward: <x_t - x_s, n_s>; transposed: <x_s - x_t, n_t>
+            T dn = TR ? -(d0 * m0 + d1 * m1 + d2 * m2) * ir * ir
+                      : (d0 * sn[e][0] + d1 * sn[e][1] + d2 * sn[e][2]) * ir * ir;
             T sn_, cs_;
             sincos_t<T>(kk * rr, &sn_, &cs_);
             // G = e^{ikr}/(4 pi r);  K = G [ (1 - ikr) dn - i eta ]
@@ -274,9 +283,10 @@ __global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, co
 
 // ---------------------------------------------------------------------------
 // node values -> coefficients: c_ijl = sum_abc Ms[i][a] Ma[j][b] Ma[l][c] v_abc,
-// one block per cone, three separable passes through LDS.
+// one block per cone, three separable passes through LDS.  With TR the
+// transposed map (Ms^T, Ma^T) is applied.  Fn may equal Fc (in place).
 // ---------------------------------------------------------------------------
-template <typename T, int PS, int PA>
+template <typename T, int PS, int PA, bool TR>
 __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, int nrel, int R,
                                                 const T* __restrict__ Ms, const T* __restrict__ Ma,
                                                 cpx<T>* __restrict__ Fc) {
@@ -285,8 +295,8 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
   __shared__ cpx<T> v0[P], v1[P];
   __shared__ T ms[PS * PS], ma[PA * PA];
   const int sl = blockIdx.x, r = blockIdx.y, t = threadIdx.x;
-  if (t < PS * PS) ms[t] = Ms[t];
-  if (t < PA * PA) ma[t] = Ma[t];
+  if (t < PS * PS) ms[t] = TR ? Ms[(t % PS) * PS + t / PS] : Ms[t];
+  if (t < PA * PA) ma[t] = TR ? Ma[(t % PA) * PA + t / PA] : Ma[t];
   if (t < P) v0[t] = Fn[((int64_t)sl * R + r) * P + t];
   __syncthreads();
   int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
@@ -725,6 +735,345 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
 }
 
 // ---------------------------------------------------------------------------
+// Transposed apply.  The forward operator is
+//   u = N a + sum_d T_d c_d,  c_D = X L a,  c_{d-1} = X P_d c_d,
+// (N near field, L leaf factors, X node values -> coefficients, P_d upward
+// pass, T_d cousin-target interpolation, a = w sigma).  Its exact transpose
+//   g = N^T v + L^T X^T chat_D,  chat_3 = T_3^T v,
+//   chat_d = T_d^T v + P_d^T X^T chat_{d-1}   (d = 4..D),  out = w g,
+// is formed stage by stage.  T^T and P^T scatter into coefficient space: the
+// lanes of a wave that hit the same cone sum their contributions in LDS and
+// add them with one coalesced atomic add per coefficient.
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ void atomic_add_t(T* p, T v);
+template <> __device__ __forceinline__ void atomic_add_t<float>(float* p, float v) { unsafeAtomicAdd(p, v); }
+template <> __device__ __forceinline__ void atomic_add_t<double>(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+template <typename T, int PS, int PA> struct AntShape {
+  static constexpr int P = PS * PA * PA;
+  static constexpr int NF = 2 + PS + 2 * PA;   // weight (re, im) and the three Chebyshev vectors
+  static constexpr int NCP = (P + 63) / 64;
+};
+
+// For every lane with slot >= 0: G[slot] += wt * (T_a(ts) T_b(tt) T_c(tp))_abc
+// (layout [slot][R][P], right-hand side r).  All 64 lanes of the wave call it
+// together; fbuf is the wave's LDS buffer of 64 * NF values.
+template <typename T, int PS, int PA>
+__device__ __forceinline__ void anterp_uniform(cpx<T>* __restrict__ G, int slot, int R, int r, T ts, T tt, T tp,
+                                               cpx<T> wt, T* fbuf) {
+  using S = AntShape<T, PS, PA>;
+  constexpr int P = S::P, NF = S::NF, NCP = S::NCP;
+  const int lane = threadIdx.x & 63;
+  T* f = fbuf + lane * NF;
+  f[0] = wt.re;
+  f[1] = wt.im;
+  cheb_T<T, PS>(ts, f + 2);
+  cheb_T<T, PA>(tt, f + 2 + PS);
+  cheb_T<T, PA>(tp, f + 2 + PS + PA);
+  int ia[NCP], ib[NCP], ic[NCP];
+#pragma unroll
+  for (int m = 0; m < NCP; ++m) {
+    const int j = min(lane + 64 * m, P - 1);
+    ia[m] = 2 + j / (PA * PA);
+    ib[m] = 2 + PS + (j / PA) % PA;
+    ic[m] = 2 + PS + PA + j % PA;
+  }
+  __builtin_amdgcn_wave_barrier();
+  uint64_t pending = __ballot(slot >= 0);
+  while (pending) {
+    const int lead = first_lane(pending);
+    const int su = __builtin_amdgcn_readfirstlane(__shfl(slot, lead, 64));
+    uint64_t grp = __ballot(slot == su);
+    pending &= ~grp;
+    cpx<T> acc[NCP];
+#pragma unroll
+    for (int m = 0; m < NCP; ++m) acc[m] = {0, 0};
+    while (grp) {
+      const int q = first_lane(grp);
+      grp &= grp - 1;
+      const T* fq = fbuf + q * NF;
+      const T wre = fq[0], wim = fq[1];
+#pragma unroll
+      for (int m = 0; m < NCP; ++m) {
+        const T b = fq[ia[m]] * fq[ib[m]] * fq[ic[m]];
+        acc[m].re += wre * b;
+        acc[m].im += wim * b;
+      }
+    }
+    cpx<T>* dst = G + ((int64_t)su * R + r) * P;
+#pragma unroll
+    for (int m = 0; m < NCP; ++m) {
+      const int j = lane + 64 * m;
+      if (j < P) {
+        atomic_add_t<T>(&dst[j].re, acc[m].re);
+        atomic_add_t<T>(&dst[j].im, acc[m].im);
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_fill_zero(cpx<T>* __restrict__ x, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) x[i] = {0, 0};
+}
+
+// T_d^T for the levels dlo..dhi: every target x with value v (gathered,
+// T precision) scatters v e^{ikr}/(4 pi r) basis(x) into the coefficient
+// adjoint of the cone of each box of which it is a cousin point.
+template <typename T> struct ALevel {
+  const int* pbox;
+  const int* cou_off;
+  const int* cou;
+  const double* centre;
+  const int* slot;
+  cpx<T>* G;
+  LevelGeom g;
+};
+template <typename T> struct ALevels {
+  ALevel<T> lv[IFGF_MAX_LEVELS];
+};
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_adj_targets(const double* __restrict__ pts, int64_t n,
+                                                     const cpx<T>* __restrict__ vs, ALevels<T> L, int dlo, int dhi,
+                                                     double k, int kind, int R, int* __restrict__ err) {
+  using S = AntShape<T, PS, PA>;
+  __shared__ T fbuf[TPB / 64][64 * S::NF];
+  const int r = blockIdx.y;
+  const int64_t i0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const bool valid = i0 < n;
+  const int64_t i = valid ? i0 : n - 1;
+  const double* x = pts + 3 * i;
+  const cpx<T> vi = vs[i * R + r];
+  const double inv4pi = 1.0 / (4.0 * IFGF_PI);
+  for (int d = dhi; d >= dlo; --d) {
+    const ALevel<T>& lv = L.lv[d];
+    const int A = lv.pbox[i];
+    const int c0 = lv.cou_off[A], cnt = lv.cou_off[A + 1] - c0;
+    int cmax = cnt;
+    for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, 64));
+    for (int t = 0; t < cmax; ++t) {
+      const bool has = valid && t < cnt;
+      const int B = lv.cou[c0 + min(t, max(cnt - 1, 0))];
+      T ts = 0, tt = 0, tp = 0, e_re = 0, e_im = 0;
+      int sl = -1;
+      if (cnt > 0) {
+        double rr;
+        int cid;
+        if constexpr (Prec<T>::f32) {
+          LocF loc = target_loc32(x, lv.centre + 3 * B, lv.g, &rr);
+          cid = loc.cid;
+          ts = loc.ts;
+          tt = loc.tt;
+          tp = loc.tp;
+          float c, s;
+          expi_reduced32(k * rr, &c, &s);
+          float g = (float)inv4pi / (float)rr;
+          e_re = g * c;
+          e_im = g * s;
+        } else {
+          Loc loc = target_loc64(x, lv.centre + 3 * B, lv.g, &rr);
+          cid = loc.cid;
+          ts = loc.ts;
+          tt = loc.tt;
+          tp = loc.tp;
+          double c, s;
+          sincos(k * rr, &s, &c);
+          double g = inv4pi / rr;
+          e_re = g * c;
+          e_im = g * s;
+        }
+        if (kind == IFGF_KERNEL_CONSTANT) {
+          e_re = 1;
+          e_im = 0;
+        }
+        sl = lv.slot[(int64_t)B * lv.g.ncone + cid];
+        if (sl < 0 && has) atomicOr(err, 4);
+      }
+      if (!has) sl = -1;
+      const cpx<T> wt = {e_re * vi.re - e_im * vi.im, e_re * vi.im + e_im * vi.re};
+      anterp_uniform<T, PS, PA>(lv.G, sl, R, r, ts, tt, tp, wt, fbuf[threadIdx.x >> 6]);
+    }
+  }
+}
+
+// P_{d+1}^T: every node of every relevant cone of a level-d box P, holding
+// the node-space adjoint Fhat, scatters ratio * Fhat * basis into the
+// coefficient adjoint of the child cone that contains it, for each child.
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_adj_prop(int nrel_up, const int* __restrict__ rel_box_up,
+                                                  const int* __restrict__ rel_cone_up,
+                                                  const int* __restrict__ child_lo_up, const int* __restrict__ coords,
+                                                  const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fhat_up,
+                                                  cpx<T>* __restrict__ G_c, LevelGeom gp, LevelGeom gc, ChebTab ct,
+                                                  double k, int kind, int R, int* __restrict__ err) {
+  using S = AntShape<T, PS, PA>;
+  constexpr int P = S::P;
+  __shared__ T fbuf[TPB / 64][64 * S::NF];
+  const int r = blockIdx.y;
+  const int64_t t0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const bool valid = t0 < (int64_t)nrel_up * P;
+  const int64_t t = valid ? t0 : (int64_t)nrel_up * P - 1;
+  const int sp = (int)(t / P), node = (int)(t % P);
+  const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
+  const int Pb = rel_box_up[sp], pcid = rel_cone_up[sp];
+  const cpx<T> fh = Fhat_up[((int64_t)sp * R + r) * P + node];
+  T x[3], rp;
+  if constexpr (Prec<T>::f32) node_rel32(pcid, ai, bi, ci, gp, ct, x, &rp);
+  else node_rel64(pcid, ai, bi, ci, gp, ct, x, &rp);
+  const int B0 = child_lo_up[Pb], nch = child_lo_up[Pb + 1] - B0;
+  int cmax = nch;
+  for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, 64));
+  for (int c = 0; c < cmax; ++c) {
+    const bool has = valid && c < nch;
+    const int B = B0 + min(c, nch - 1);
+    const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+    typename PropGeomT<T>::P pr;
+    if constexpr (Prec<T>::f32) pr = child_loc32(x, rp, oct, gc);
+    else pr = child_loc64(x, rp, oct, gc);
+    int sl = slot_c[(int64_t)B * gc.ncone + pr.loc.cid];
+    if (sl < 0 && has) atomicOr(err, 2);
+    if (!has) sl = -1;
+    T rr = pr.rp_over_rc, c_, s_;
+    if (kind == IFGF_KERNEL_CONSTANT) {
+      c_ = 1;
+      s_ = 0;
+      rr = 1;
+    } else {
+      sincos_t<T>((T)k * pr.dr, &s_, &c_);
+    }
+    const T rre = rr * c_, rim = rr * s_;
+    const cpx<T> wt = {rre * fh.re - rim * fh.im, rre * fh.im + rim * fh.re};
+    anterp_uniform<T, PS, PA>(G_c, sl, R, r, pr.loc.ts, pr.loc.tt, pr.loc.tp, wt, fbuf[threadIdx.x >> 6]);
+  }
+}
+
+// L^T: each source y of a finest-level box gets sum over the box's relevant
+// cones and their nodes of W_c(node, y) Fhat(node), added to acc.  The
+// sources are taken SC at a time; each thread sums its share of the nodes in
+// registers, then the block reduces per source.
+constexpr int ADJ_LEAF_SC = 8;
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_adj_leaf(const double* __restrict__ pts, const double* __restrict__ nrm,
+                                                  const int* __restrict__ start, const double* __restrict__ centre,
+                                                  const int* __restrict__ slot_off, const int* __restrict__ rel_cone,
+                                                  const cpx<T>* __restrict__ Fhat, LevelGeom g, ChebTab ct, double k,
+                                                  double eta, int kind, int R, cpx<T>* __restrict__ acc_out) {
+  constexpr int P = PS * PA * PA;
+  constexpr int SC = ADJ_LEAF_SC;
+  __shared__ T su[SC][3], sn[SC][3], suu[SC], sun[SC];
+  __shared__ cpx<T> red[TPB / 64][SC];
+  const int b = blockIdx.x, r = blockIdx.y;
+  const int s0 = slot_off[b], ncn = slot_off[b + 1] - s0;
+  const int p0 = start[b], np = start[b + 1] - p0;
+  const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
+  const double invh = 1.0 / g.h;
+  const T kk = (T)k, ee = (T)eta, kh = (T)(k * g.h), ih = (T)invh;
+  const int nitems = ncn * P;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int sb = 0; sb < np; sb += SC) {
+    const int sc = min(SC, np - sb);
+    __syncthreads();
+    if (threadIdx.x < sc) {
+      const int j = p0 + sb + threadIdx.x;
+      T u0 = (T)((pts[3 * j] - c0) * invh), u1 = (T)((pts[3 * j + 1] - c1) * invh),
+        u2 = (T)((pts[3 * j + 2] - c2) * invh);
+      T n0 = (T)nrm[3 * j], n1 = (T)nrm[3 * j + 1], n2 = (T)nrm[3 * j + 2];
+      su[threadIdx.x][0] = u0;
+      su[threadIdx.x][1] = u1;
+      su[threadIdx.x][2] = u2;
+      sn[threadIdx.x][0] = n0;
+      sn[threadIdx.x][1] = n1;
+      sn[threadIdx.x][2] = n2;
+      suu[threadIdx.x] = u0 * u0 + u1 * u1 + u2 * u2;
+      sun[threadIdx.x] = u0 * n0 + u1 * n1 + u2 * n2;
+    }
+    __syncthreads();
+    cpx<T> acc[SC];
+#pragma unroll
+    for (int q = 0; q < SC; ++q) acc[q] = {0, 0};
+    for (int it = threadIdx.x; it < nitems; it += TPB) {
+      const int cs = it / P, node = it % P;
+      const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
+      const int cid = rel_cone[s0 + cs];
+      T e[3], s;
+      if constexpr (Prec<T>::f32) node_dir32(cid, ai, bi, ci, g, ct, e, &s);
+      else node_dir64(cid, ai, bi, ci, g, ct, e, &s);
+      const cpx<T> fh = Fhat[((int64_t)(s0 + cs) * R + r) * P + node];
+#pragma unroll
+      for (int q = 0; q < SC; ++q) {
+        if (q >= sc) break;
+        cpx<T> W;
+        if (kind == IFGF_KERNEL_CONSTANT) {
+          W = {1, 0};
+        } else {
+          T eu = e[0] * su[q][0] + e[1] * su[q][1] + e[2] * su[q][2];
+          T en = e[0] * sn[q][0] + e[1] * sn[q][1] + e[2] * sn[q][2];
+          T qq = s * suu[q] - (T)2 * eu;
+          T nv = sqrt_t<T>((T)1 + s * qq);
+          T inv = (T)1 / nv;
+          T ph = kh * qq / (nv + (T)1);
+          T sp, cp;
+          sincos_t<T>(ph, &sp, &cp);
+          T vn = en - s * sun[q];
+          T A = vn * s * inv * inv * inv * ih;
+          T Bv = kk * vn * inv * inv + ee * inv;
+          W = {cp * A + sp * Bv, sp * A - cp * Bv};
+        }
+        acc[q].re += W.re * fh.re - W.im * fh.im;
+        acc[q].im += W.re * fh.im + W.im * fh.re;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SC; ++q) {
+      T re = acc[q].re, im = acc[q].im;
+      for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_xor(re, off, 64);
+        im += __shfl_xor(im, off, 64);
+      }
+      if (lane == 0) red[wid][q] = {re, im};
+    }
+    __syncthreads();
+    if (threadIdx.x < sc) {
+      cpx<T> t = {0, 0};
+      for (int w = 0; w < TPB / 64; ++w) {
+        t.re += red[w][threadIdx.x].re;
+        t.im += red[w][threadIdx.x].im;
+      }
+      const int64_t o = (int64_t)(p0 + sb + threadIdx.x) * R + r;
+      acc_out[o].re += t.re;
+      acc_out[o].im += t.im;
+    }
+  }
+}
+
+// out[perm_j] = conj?(w_j g_j) in the caller's dtype.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_adj_out(const cpx<T>* __restrict__ g, const int* __restrict__ perm,
+                                                 const double* __restrict__ w, int64_t n, int R, int dtype, int conj_out,
+                                                 void* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  const double wi = w[i];
+  for (int r = 0; r < R; ++r) {
+    const cpx<T> v = g[i * R + r];
+    double re = wi * (double)v.re, im = wi * (double)v.im;
+    if (conj_out) im = -im;
+    const int64_t o = (int64_t)perm[i] * R + r;
+    if (dtype == IFGF_C128) {
+      ((double*)out)[2 * o] = re;
+      ((double*)out)[2 * o + 1] = im;
+    } else {
+      ((float*)out)[2 * o] = (float)re;
+      ((float*)out)[2 * o + 1] = (float)im;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 template <typename T, int PS, int PA>
@@ -746,7 +1095,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   const bool near = stage_mask & 1;
   if (near) {
     StageTimer tm(p, s, IFGF_STAGE_NEAR);
-    k_near<T><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
+    k_near<T, false><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
                                             lD.nbr_off.as<int>(), lD.nbr.as<int>(), lD.centre.as<double>(), p->k,
                                             p->eta, kind, uacc);
     HIPCHK(hipGetLastError());
@@ -764,7 +1113,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     HIPCHK(hipGetLastError());
     if (lD.nrel > 0) {
       StageTimer tm(p, s, IFGF_STAGE_COEFFS);
-      k_coeffs<T, PS, PA><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma, lD.Fc.as<cpx<T>>());
+      k_coeffs<T, PS, PA, false><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma, lD.Fc.as<cpx<T>>());
       HIPCHK(hipGetLastError());
     }
     for (int d = D; d >= 4; --d) {
@@ -800,6 +1149,96 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   HIPCHK(hipGetLastError());
 }
 
+template <typename T, int PS, int PA>
+void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, int conj, hipStream_t s) {
+  constexpr int P = PS * PA * PA;
+  const int64_t n = p->n;
+  const int D = p->D;
+  const int kind = p->opt.kernel;
+  cpx<T>* vs = p->a.as<cpx<T>>();
+  cpx<T>* g = p->uacc.as<cpx<T>>();
+  dim3 gpts(nblocks(n), R);
+  {
+    StageTimer tm(p, s, IFGF_STAGE_GATHER);
+    k_gather<T><<<gpts, TPB, 0, s>>>(v, dtype, conj, p->perm.as<int>(), nullptr, n, R, vs);
+  }
+  HIPCHK(hipGetLastError());
+  LevelPlan& lD = p->lev[D];
+  {
+    StageTimer tm(p, s, IFGF_STAGE_ADJ_NEAR);
+    k_near<T, true><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), vs, R,
+                                                   lD.start.as<int>(), lD.nbr_off.as<int>(), lD.nbr.as<int>(),
+                                                   lD.centre.as<double>(), p->k, p->eta, kind, g);
+  }
+  HIPCHK(hipGetLastError());
+  if (D >= 3) {
+    const size_t csz = sizeof(cpx<T>);
+    ALevels<T> L{};
+    for (int d = 3; d <= D; ++d) {
+      LevelPlan& lv = p->lev[d];
+      size_t need = csz * (size_t)std::max(1, lv.nrel) * P * p->opt.max_rhs;
+      if (p->adj_g[d].bytes < need) p->adj_g[d].alloc(need);
+      const int64_t cnt = (int64_t)lv.nrel * R * P;
+      if (cnt > 0) {
+        k_fill_zero<T><<<nblocks(cnt), TPB, 0, s>>>(p->adj_g[d].as<cpx<T>>(), cnt);
+        HIPCHK(hipGetLastError());
+      }
+      L.lv[d] = {lv.pbox.as<int>(), lv.cou_off.as<int>(), lv.cou.as<int>(), lv.centre.as<double>(),
+                 lv.slot.as<int>(), p->adj_g[d].as<cpx<T>>(), lv.geom};
+    }
+    {
+      StageTimer tm(p, s, IFGF_STAGE_ADJ_TARGETS);
+      k_adj_targets<T, PS, PA><<<gpts, TPB, 0, s>>>(p->pts.as<double>(), n, vs, L, 3, D, p->k, kind, R,
+                                                    p->err.as<int>());
+    }
+    HIPCHK(hipGetLastError());
+    const T* Ms = (const T*)(Prec<T>::f32 ? p->Msf.p : p->Ms.p);
+    const T* Ma = (const T*)(Prec<T>::f32 ? p->Maf.p : p->Ma.p);
+    for (int d = 3; d <= D; ++d) {
+      LevelPlan& lv = p->lev[d];
+      if (lv.nrel > 0) {
+        StageTimer tm(p, s, IFGF_STAGE_ADJ_COEFFS);
+        k_coeffs<T, PS, PA, true><<<dim3(lv.nrel, R), TPB, 0, s>>>(p->adj_g[d].as<cpx<T>>(), lv.nrel, R, Ms, Ma,
+                                                                  p->adj_g[d].as<cpx<T>>());
+      }
+      HIPCHK(hipGetLastError());
+      if (d == D || lv.nrel == 0) continue;
+      LevelPlan& lc = p->lev[d + 1];
+      int64_t items = (int64_t)lv.nrel * P;
+      {
+        StageTimer tm(p, s, IFGF_STAGE_ADJ_PROP);
+        k_adj_prop<T, PS, PA><<<dim3(nblocks(items), R), TPB, 0, s>>>(
+            lv.nrel, lv.rel_box.as<int>(), lv.rel_cone.as<int>(), lv.child_lo.as<int>(), lc.coords.as<int>(),
+            lc.slot.as<int>(), p->adj_g[d].as<cpx<T>>(), p->adj_g[d + 1].as<cpx<T>>(), lv.geom, lc.geom, p->cheb,
+            p->k, kind, R, p->err.as<int>());
+      }
+      HIPCHK(hipGetLastError());
+    }
+    {
+      StageTimer tm(p, s, IFGF_STAGE_ADJ_LEAF);
+      k_adj_leaf<T, PS, PA><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(),
+                                                           lD.start.as<int>(), lD.centre.as<double>(),
+                                                           lD.slot_off.as<int>(), lD.rel_cone.as<int>(),
+                                                           p->adj_g[D].as<cpx<T>>(), lD.geom, p->cheb, p->k, p->eta,
+                                                           kind, R, g);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  {
+    StageTimer tm(p, s, IFGF_STAGE_ADJ_OUT);
+    k_adj_out<T><<<nblocks(n), TPB, 0, s>>>(g, p->perm.as<int>(), p->w.as<double>(), n, R, dtype, conj, out);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+void dispatch_adjoint(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, int conj, hipStream_t s) {
+  int ps = p->opt.p_s, pa = p->opt.p_ang;
+  if (ps == 3 && pa == 5) return adjoint_impl<T, 3, 5>(p, v, out, R, dtype, conj, s);
+  if (ps == 4 && pa == 6) return adjoint_impl<T, 4, 6>(p, v, out, R, dtype, conj, s);
+  throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
+}
+
 template <typename T>
 void dispatch_apply(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, int stage_mask, int lo, int hi,
                     hipStream_t s) {
@@ -828,8 +1267,11 @@ void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, 
   p->last_rhs = nrhs;
 }
 
-void run_adjoint(ifgf_plan_s*, const void*, void*, int, int, int, hipStream_t) {
-  throw Error{IFGF_EUNSUPPORTED, "transposed apply not built yet"};
+void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s) {
+  if (p->opt.precision == IFGF_PREC_FP32_INTERP)
+    dispatch_adjoint<float>(p, v, out, nrhs, dtype, conj, s);
+  else
+    dispatch_adjoint<double>(p, v, out, nrhs, dtype, conj, s);
 }
 
 }  // namespace ifgf
