@@ -192,13 +192,15 @@ class Plan:
         return box[:nr].cpu().numpy(), cone[:nr].cpu().numpy()
 
     def export_field(self, d, what=0, nrhs=1):
-        """Level-d field of the last apply: (cones, nrhs, P) complex, node values (0) or coefficients (1)."""
+        """Level-d field of the last apply: (cones, nrhs, P) complex, node values (0) or coefficients (1).
+
+        The library stores (cones, P, nrhs); the result is transposed to (cones, nrhs, P)."""
         nr = self.stats()["cones"][d]
         P = self.options.p_s * self.options.p_ang ** 2
         dt = torch.complex64 if self.precision == "fp32" else torch.complex128
         buf = torch.empty(max(1, nr * P * nrhs), dtype=dt, device=self.device)
         L.check(self._lib.ifgf_plan_export_field(self._h, d, what, buf.data_ptr()), "export_field")
-        return buf[:nr * P * nrhs].cpu().numpy().reshape(nr, nrhs, P)
+        return buf[:nr * P * nrhs].cpu().numpy().reshape(nr, P, nrhs).transpose(0, 2, 1)
 
 
 class IFGFApply(torch.autograd.Function):

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, co
         }
       }
     }
-    if (valid) Fn[((int64_t)(s0 + it / P) * R + r) * P + it % P] = acc;
+    if (valid) Fn[((int64_t)s0 * P + it) * R + r] = acc;
   }
 }
 
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
   const int sl = blockIdx.x, r = blockIdx.y, t = threadIdx.x;
   if (t < PS * PS) ms[t] = TR ? Ms[(t % PS) * PS + t / PS] : Ms[t];
   if (t < PA * PA) ma[t] = TR ? Ma[(t % PA) * PA + t / PA] : Ma[t];
-  if (t < P) v0[t] = Fn[((int64_t)sl * R + r) * P + t];
+  if (t < P) v0[t] = Fn[((int64_t)sl * P + t) * R + r];
   __syncthreads();
   int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
   if (t < P) {  // over a (s)
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
       s.re += ma[l * PA + q] * x.re;
       s.im += ma[l * PA + q] * x.im;
     }
-    Fc[((int64_t)sl * R + r) * P + t] = s;
+    Fc[((int64_t)sl * P + t) * R + r] = s;
   }
 }
 
@@ -369,7 +369,7 @@ __device__ __forceinline__ cpx<T> contract_lds(const T* C, const T* Ts, const T*
 }
 
 // For every lane with slot >= 0, evaluates the interpolant of cone `slot` of
-// F (coefficient layout [slot][R][P], right-hand side r) at (ts, tt, tp).
+// F (coefficient layout [slot][P][R], right-hand side r) at (ts, tt, tp).
 // All 64 lanes of the wave must call it together (lanes without work pass
 // slot = -1).  The wave serves one slot at a time: its lanes copy that cone's
 // P coefficients into the wave's LDS buffer `wbuf` (2P values, coalesced
@@ -394,11 +394,11 @@ __device__ __forceinline__ cpx<T> eval_uniform(const cpx<T>* __restrict__ F, int
     const int su = __builtin_amdgcn_readfirstlane(__shfl(slot, lead, 64));
     const bool mine = slot == su;
     pending &= ~__ballot(mine);
-    const cpx<T>* src = F + ((int64_t)su * R + r) * P;
+    const cpx<T>* src = F + (int64_t)su * P * R + r;
     cpx<T> v[NCP];
 #pragma unroll
     for (int j = 0; j < NCP; ++j)
-      if (lane + 64 * j < P) v[j] = src[lane + 64 * j];
+      if (lane + 64 * j < P) v[j] = src[(int64_t)(lane + 64 * j) * R];
 #pragma unroll
     for (int j = 0; j < NCP; ++j)
       if (lane + 64 * j < P) wb[lane + 64 * j] = v[j];
@@ -465,7 +465,7 @@ __device__ __forceinline__ void block_scan_inplace(int* a, int n, int* wsum) {
 }
 
 // Chebyshev transform of nc cones of node values in LDS (in: v, scratch: t),
-// written to global coefficients out[((cone) * R + r) * P + j].
+// written to global coefficients out[((cone) * P + j) * R + r].
 template <typename T, int PS, int PA, int BS>
 __device__ __forceinline__ void lds_coeffs_store(cpx<T>* v, cpx<T>* t, int nc, const T* ms, const T* ma,
                                                  cpx<T>* __restrict__ out, int R, int r) {
@@ -501,7 +501,7 @@ __device__ __forceinline__ void lds_coeffs_store(cpx<T>* v, cpx<T>* t, int nc, c
       acc.re += ma[l * PA + k] * x.re;
       acc.im += ma[l * PA + k] * x.im;
     }
-    out[((int64_t)c * R + r) * P + j] = acc;
+    out[((int64_t)c * P + j) * R + r] = acc;
   }
 }
 
@@ -620,7 +620,7 @@ __global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
     }
     __syncthreads();
   }
-  lds_coeffs_store<T, PS, PA, BS>(acc, tmp, ncn, ms, ma, Fc_up + (int64_t)s0 * R * P, R, r);
+  lds_coeffs_store<T, PS, PA, BS>(acc, tmp, ncn, ms, ma, Fc_up + (int64_t)s0 * P * R, R, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -735,6 +735,267 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
 }
 
 // ---------------------------------------------------------------------------
+// Batched right-hand sides on MFMA (FP32 mode, nrhs a multiple of 16).
+//
+// For the 64 evaluations held by a wave (one per lane: a target and a cousin
+// box, or a parent node and a child), the interpolants of one cone for 16
+// right-hand sides form the product
+//     OUT[row][e] = sum_k C[k][row] B[k][e],
+// rows = 16 RHS x (re, im) in two 16-row tiles, k = basis index, and
+// B[k][e] = T_a(ts_e) T_b(tt_e) T_c(tp_e) for evaluations whose cone is the
+// current one (0 otherwise).  It runs on v_mfma_f32_16x16x4_f32 with the
+// evaluations as four 16-column blocks and the basis index ordered (b, c, a)
+// so that the radial index a fills the instruction's 4-wide K step: each
+// lane's B operand is then T_a(ts) T_b(tt) T_c(tp) with its own a and
+// compile-time b, c.  Lane layouts: A[i][k] from lane 16k + i, B[k][j] from
+// lane 16k + j, D[4q + v][j] in lane 16q + j, element v.
+// ---------------------------------------------------------------------------
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int MF_RG = 16;   // right-hand sides per pass
+
+template <int PS, int PA> struct MfRec {
+  static constexpr int NR = PS + 2 * PA + 3;   // Ts, Tt, Tp, slot (as int), factor (re, im)
+};
+
+template <int PS, int PA>
+__device__ __forceinline__ void mfma_cone(const float* __restrict__ Cb, int R, int g, const float (&wq)[4][PA],
+                                          const float (&tq)[4][PA], floatx4 (&acc)[2][4]) {
+  const int l = threadIdx.x & 63;
+  const int h = min(l >> 4, PS - 1);
+  const int i = l & 15;
+#pragma unroll
+  for (int bb = 0; bb < PA; ++bb) {
+#pragma unroll
+    for (int c = 0; c < PA; ++c) {
+      const int64_t j = (h * PA + bb) * PA + c;
+      const float a0 = Cb[(j * R + g * MF_RG) * 2 + i];
+      const float a1 = Cb[(j * R + g * MF_RG) * 2 + 16 + i];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const float bv = wq[b][bb] * tq[b][c];
+        acc[0][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv, acc[0][b], 0, 0, 0);
+        acc[1][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv, acc[1][b], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// One evaluation per lane (all 64 lanes call; slot < 0 = none): adds
+// f_e * I_e[rhs] into tot for the evaluations and RHS this lane holds:
+// tot[b][2 rt + p] is RHS 8 rt + 2 (lane >> 4) + p of evaluation 16 b + (lane & 15).
+template <int PS, int PA>
+__device__ __forceinline__ void wave_eval_mfma(const cpx<float>* __restrict__ F, int R, int g, int slot, float ts,
+                                               float tt, float tp, float fre, float fim, float* rec,
+                                               cpx<float> (&tot)[4][4]) {
+  constexpr int P = PS * PA * PA;
+  constexpr int NR = MfRec<PS, PA>::NR;
+  const int l = threadIdx.x & 63;
+  float* my = rec + l * NR;
+  cheb_T<float, PS>(ts, my);
+  cheb_T<float, PA>(tt, my + PS);
+  cheb_T<float, PA>(tp, my + PS + PA);
+  my[PS + 2 * PA] = __int_as_float(slot);
+  my[PS + 2 * PA + 1] = fre;
+  my[PS + 2 * PA + 2] = fim;
+  __builtin_amdgcn_wave_barrier();
+  const int h = l >> 4;
+  floatx4 acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[rt][b] = (floatx4){0.f, 0.f, 0.f, 0.f};
+  uint64_t pending = __ballot(slot >= 0);
+  while (pending) {
+    const int lead = first_lane(pending);
+    const int su = __builtin_amdgcn_readfirstlane(__shfl(slot, lead, 64));
+    pending &= ~__ballot(slot == su);
+    float wq[4][PA], tq[4][PA];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float* re = rec + (16 * b + (l & 15)) * NR;
+      const bool m = __float_as_int(re[PS + 2 * PA]) == su && h < PS;
+      const float ta = m ? re[min(h, PS - 1)] : 0.f;
+#pragma unroll
+      for (int bb = 0; bb < PA; ++bb) wq[b][bb] = ta * re[PS + bb];
+#pragma unroll
+      for (int c = 0; c < PA; ++c) tq[b][c] = re[PS + PA + c];
+    }
+    mfma_cone<PS, PA>(reinterpret_cast<const float*>(F + (int64_t)su * P * R), R, g, wq, tq, acc);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const float* re = rec + (16 * b + (l & 15)) * NR;
+    const float er = re[PS + 2 * PA + 1], ei = re[PS + 2 * PA + 2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int p2 = 0; p2 < 2; ++p2) {
+        const float vr = acc[rt][b][2 * p2], vi = acc[rt][b][2 * p2 + 1];
+        tot[b][2 * rt + p2].re += er * vr - ei * vi;
+        tot[b][2 * rt + p2].im += er * vi + ei * vr;
+      }
+  }
+  (void)h;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Cousin targets (levels dlo..dhi) for RHS group blockIdx.y, plus the near
+// field, scattered to the caller's order.  Same traversal as k_targets.
+template <int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets_mfma(const double* __restrict__ pts, int64_t n,
+                                                      const int* __restrict__ perm, const cpx<float>* __restrict__ uacc,
+                                                      int use_near, TLevels<float> L, int dlo, int dhi, double k,
+                                                      int kind, int R, int dtype, void* __restrict__ u,
+                                                      int* __restrict__ err) {
+  constexpr int NR = MfRec<PS, PA>::NR;
+  __shared__ float rec[TPB / 64][64 * NR];
+  const int g = blockIdx.y;
+  const int l = threadIdx.x & 63;
+  const int64_t i0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const bool valid = i0 < n;
+  const int64_t i = valid ? i0 : n - 1;
+  const double* x = pts + 3 * i;
+  cpx<float> tot[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tot[b][q] = {0.f, 0.f};
+  const double inv4pi = 1.0 / (4.0 * IFGF_PI);
+  for (int d = dhi; d >= dlo; --d) {
+    const TLevel<float>& lv = L.lv[d];
+    const int A = lv.pbox[i];
+    const int c0 = lv.cou_off[A], cnt = lv.cou_off[A + 1] - c0;
+    int cmax = cnt;
+    for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, 64));
+    for (int t = 0; t < cmax; ++t) {
+      const bool has = valid && t < cnt;
+      const int B = lv.cou[c0 + min(t, max(cnt - 1, 0))];
+      float ts = 0, tt = 0, tp = 0, e_re = 0, e_im = 0;
+      int sl = -1;
+      if (cnt > 0) {
+        double rr;
+        LocF loc = target_loc32(x, lv.centre + 3 * B, lv.g, &rr);
+        ts = loc.ts;
+        tt = loc.tt;
+        tp = loc.tp;
+        float c, s;
+        expi_reduced32(k * rr, &c, &s);
+        float gf = (float)inv4pi / (float)rr;
+        e_re = gf * c;
+        e_im = gf * s;
+        if (kind == IFGF_KERNEL_CONSTANT) {
+          e_re = 1;
+          e_im = 0;
+        }
+        sl = lv.slot[(int64_t)B * lv.g.ncone + loc.cid];
+        if (sl < 0 && has) atomicOr(err, 4);
+      }
+      if (!has) {
+        sl = -1;
+        e_re = e_im = 0;
+      }
+      wave_eval_mfma<PS, PA>(lv.Fc, R, g, sl, ts, tt, tp, e_re, e_im, rec[threadIdx.x >> 6], tot);
+    }
+  }
+  // lane l holds RHS 8 rt + 2 (l >> 4) + p of target 16 b + (l & 15) of its wave
+  const int64_t wbase = i0 - l;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t ti = wbase + 16 * b + (l & 15);
+    if (ti >= n) continue;
+    const int64_t po = perm[ti];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int p2 = 0; p2 < 2; ++p2) {
+        const int rr = g * MF_RG + 8 * rt + 2 * (l >> 4) + p2;
+        double re = tot[b][2 * rt + p2].re, im = tot[b][2 * rt + p2].im;
+        if (use_near) {
+          const cpx<float> v = uacc[ti * R + rr];
+          re += v.re;
+          im += v.im;
+        }
+        const int64_t o = po * R + rr;
+        if (dtype == IFGF_C128) {
+          ((double*)u)[2 * o] = re;
+          ((double*)u)[2 * o + 1] = im;
+        } else {
+          ((float*)u)[2 * o] = (float)re;
+          ((float*)u)[2 * o + 1] = (float)im;
+        }
+      }
+  }
+}
+
+// Upward pass for RHS group blockIdx.y: one lane per (parent slot, node),
+// the children of its parent in turn; writes node values of level d-1.
+template <int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_prop_mfma(int nrel_up, const int* __restrict__ rel_box_up,
+                                                   const int* __restrict__ rel_cone_up,
+                                                   const int* __restrict__ child_lo_up, const int* __restrict__ coords,
+                                                   const int* __restrict__ slot_c, const cpx<float>* __restrict__ Fc_c,
+                                                   LevelGeom gp, LevelGeom gc, ChebTab ct, double k, int kind, int R,
+                                                   cpx<float>* __restrict__ Fn_up, int* __restrict__ err) {
+  constexpr int P = PS * PA * PA;
+  constexpr int NR = MfRec<PS, PA>::NR;
+  __shared__ float rec[TPB / 64][64 * NR];
+  const int g = blockIdx.y;
+  const int l = threadIdx.x & 63;
+  const int64_t nitem = (int64_t)nrel_up * P;
+  const int64_t t0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const bool valid = t0 < nitem;
+  const int64_t t = valid ? t0 : nitem - 1;
+  const int sp = (int)(t / P), node = (int)(t % P);
+  const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
+  const int Pb = rel_box_up[sp], pcid = rel_cone_up[sp];
+  float x[3], rp;
+  node_rel32(pcid, ai, bi, ci, gp, ct, x, &rp);
+  cpx<float> tot[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tot[b][q] = {0.f, 0.f};
+  const int B0 = child_lo_up[Pb], nch = child_lo_up[Pb + 1] - B0;
+  int cmax = nch;
+  for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, 64));
+  for (int c = 0; c < cmax; ++c) {
+    const bool has = valid && c < nch;
+    const int B = B0 + min(c, nch - 1);
+    const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+    PropF pr = child_loc32(x, rp, oct, gc);
+    int sl = slot_c[(int64_t)B * gc.ncone + pr.loc.cid];
+    if (sl < 0 && has) atomicOr(err, 2);
+    float rr = pr.rp_over_rc, c_, s_;
+    if (kind == IFGF_KERNEL_CONSTANT) {
+      c_ = 1;
+      s_ = 0;
+      rr = 1;
+    } else {
+      sincos_f((float)k * pr.dr, &s_, &c_);
+    }
+    float fre = rr * c_, fim = rr * s_;
+    if (!has) {
+      sl = -1;
+      fre = fim = 0;
+    }
+    wave_eval_mfma<PS, PA>(Fc_c, R, g, sl, pr.loc.ts, pr.loc.tt, pr.loc.tp, fre, fim, rec[threadIdx.x >> 6], tot);
+  }
+  const int64_t wbase = t0 - l;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t ti = wbase + 16 * b + (l & 15);
+    if (ti >= nitem) continue;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int p2 = 0; p2 < 2; ++p2) {
+        const int rr = g * MF_RG + 8 * rt + 2 * (l >> 4) + p2;
+        Fn_up[ti * R + rr] = tot[b][2 * rt + p2];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Transposed apply.  The forward operator is
 //   u = N a + sum_d T_d c_d,  c_D = X L a,  c_{d-1} = X P_d c_d,
 // (N near field, L leaf factors, X node values -> coefficients, P_d upward
@@ -756,7 +1017,7 @@ template <typename T, int PS, int PA> struct AntShape {
 };
 
 // For every lane with slot >= 0: G[slot] += wt * (T_a(ts) T_b(tt) T_c(tp))_abc
-// (layout [slot][R][P], right-hand side r).  All 64 lanes of the wave call it
+// (layout [slot][P][R], right-hand side r).  All 64 lanes of the wave call it
 // together; fbuf is the wave's LDS buffer of 64 * NF values.
 template <typename T, int PS, int PA>
 __device__ __forceinline__ void anterp_uniform(cpx<T>* __restrict__ G, int slot, int R, int r, T ts, T tt, T tp,
@@ -800,13 +1061,13 @@ __device__ __forceinline__ void anterp_uniform(cpx<T>* __restrict__ G, int slot,
         acc[m].im += wim * b;
       }
     }
-    cpx<T>* dst = G + ((int64_t)su * R + r) * P;
+    cpx<T>* dst = G + (int64_t)su * P * R + r;
 #pragma unroll
     for (int m = 0; m < NCP; ++m) {
       const int j = lane + 64 * m;
       if (j < P) {
-        atomic_add_t<T>(&dst[j].re, acc[m].re);
-        atomic_add_t<T>(&dst[j].im, acc[m].im);
+        atomic_add_t<T>(&dst[(int64_t)j * R].re, acc[m].re);
+        atomic_add_t<T>(&dst[(int64_t)j * R].im, acc[m].im);
       }
     }
   }
@@ -919,7 +1180,7 @@ __global__ __launch_bounds__(TPB) void k_adj_prop(int nrel_up, const int* __rest
   const int sp = (int)(t / P), node = (int)(t % P);
   const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
   const int Pb = rel_box_up[sp], pcid = rel_cone_up[sp];
-  const cpx<T> fh = Fhat_up[((int64_t)sp * R + r) * P + node];
+  const cpx<T> fh = Fhat_up[((int64_t)sp * P + node) * R + r];
   T x[3], rp;
   if constexpr (Prec<T>::f32) node_rel32(pcid, ai, bi, ci, gp, ct, x, &rp);
   else node_rel64(pcid, ai, bi, ci, gp, ct, x, &rp);
@@ -1002,7 +1263,7 @@ __global__ __launch_bounds__(TPB) void k_adj_leaf(const double* __restrict__ pts
       T e[3], s;
       if constexpr (Prec<T>::f32) node_dir32(cid, ai, bi, ci, g, ct, e, &s);
       else node_dir64(cid, ai, bi, ci, g, ct, e, &s);
-      const cpx<T> fh = Fhat[((int64_t)(s0 + cs) * R + r) * P + node];
+      const cpx<T> fh = Fhat[((int64_t)(s0 + cs) * P + node) * R + r];
 #pragma unroll
       for (int q = 0; q < SC; ++q) {
         if (q >= sc) break;
@@ -1116,10 +1377,37 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
       k_coeffs<T, PS, PA, false><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma, lD.Fc.as<cpx<T>>());
       HIPCHK(hipGetLastError());
     }
+    const bool mfma = Prec<T>::f32 && R % MF_RG == 0 && PS <= 4;
+    if (mfma) {
+      // RHS groups of 16 on MFMA: node values into a scratch level, then coefficients
+      size_t need = 0;
+      for (int d = 3; d < D; ++d) need = std::max(need, sizeof(cpx<T>) * (size_t)p->lev[d].nrel * P * R);
+      if (p->scratch_fn.bytes < need) p->scratch_fn.alloc(need);
+    }
     for (int d = D; d >= 4; --d) {
       LevelPlan& lc = p->lev[d];
       LevelPlan& lp = p->lev[d - 1];
       if (lp.nrel == 0 || lp.nwork == 0) continue;
+      if constexpr (Prec<T>::f32 && PS <= 4) {
+        if (mfma) {
+          const int64_t items = (int64_t)lp.nrel * P;
+          {
+            StageTimer tm(p, s, IFGF_STAGE_PROP);
+            k_prop_mfma<PS, PA><<<dim3(nblocks(items), R / MF_RG), TPB, 0, s>>>(
+                lp.nrel, lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
+                lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, p->k, kind, R,
+                p->scratch_fn.as<cpx<T>>(), p->err.as<int>());
+          }
+          HIPCHK(hipGetLastError());
+          {
+            StageTimer tm(p, s, IFGF_STAGE_COEFFS);
+            k_coeffs<T, PS, PA, false><<<dim3(lp.nrel, R), TPB, 0, s>>>(p->scratch_fn.as<cpx<T>>(), lp.nrel, R, Ms,
+                                                                       Ma, lp.Fc.as<cpx<T>>());
+          }
+          HIPCHK(hipGetLastError());
+          continue;
+        }
+      }
       StageTimer tm(p, s, IFGF_STAGE_PROP);
       k_prop<T, PS, PA><<<dim3((unsigned)lp.nwork, R), PropShape<P>::BS, 0, s>>>(
           lp.work.as<int4>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(), lc.slot.as<int>(),
@@ -1140,6 +1428,16 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   } else {
     dlo = std::max(dlo, level_lo);
     dhi = std::min(dhi, level_hi);
+  }
+  if constexpr (Prec<T>::f32 && PS <= 4) {
+    if (R % MF_RG == 0) {
+      StageTimer tm(p, s, IFGF_STAGE_TARGETS);
+      k_targets_mfma<PS, PA><<<dim3(nblocks(n), R / MF_RG), TPB, 0, s>>>(p->pts.as<double>(), n, p->perm.as<int>(),
+                                                                        uacc, near ? 1 : 0, L, dlo, dhi, p->k, kind, R,
+                                                                        dtype, u, p->err.as<int>());
+      HIPCHK(hipGetLastError());
+      return;
+    }
   }
   {
     StageTimer tm(p, s, IFGF_STAGE_TARGETS);

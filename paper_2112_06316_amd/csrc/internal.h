@@ -55,7 +55,7 @@ struct LevelPlan {
   DevBuf slot_off;            // int [nb + 1]
   int nrel = 0;
   DevBuf rel_box, rel_cone;   // int [nrel]
-  DevBuf Fn, Fc;              // node values (finest level only) / coefficients [nrel][max_rhs][P] complex
+  DevBuf Fn, Fc;              // node values (finest level only) / coefficients [nrel][P][max_rhs] complex
   DevBuf work;                // int4 [nwork]: (box, first slot, end slot, 0) chunks of this level's
   int64_t nwork = 0;          //   relevant cones, the work items of the upward pass into this level
   // statistics
@@ -83,6 +83,7 @@ struct ifgf_plan_s {
   ifgf::DevBuf a;             // gathered coefficients w * sigma, [n][max_rhs] complex (plan precision)
   ifgf::DevBuf uacc;          // near-field results, [n][max_rhs] complex (plan precision)
   ifgf::DevBuf adj_g[IFGF_MAX_LEVELS];   // transposed-apply coefficient-space buffers
+  ifgf::DevBuf scratch_fn;    // node values of one level for the batched (MFMA) upward pass
   ifgf::DevBuf err;           // int [4] device error flags
   int64_t near_pairs = 0;
   // kernel timing (ifgf_plan_set_profiling)
