@@ -60,6 +60,9 @@ def main():
     ap.add_argument("--p-ang", type=int, default=6)
     ap.add_argument("--ns0", type=int, default=2)
     ap.add_argument("--nc0", type=int, default=4)
+    ap.add_argument("--batched-rhs", type=int, default=64, help="RHS of the batched leg (0 = skip)")
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--adjoint-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: only --gpus 1 is supported: this build runs on one GPU "
@@ -118,6 +121,22 @@ def main():
 
     r32 = run("fp32", args.steps, args.warmup, True)
     st = r32["stats"]
+
+    # ---- transposed apply (autograd backward) at the same workload --------------
+    adj = None
+    if args.adjoint_steps > 0:
+        plan = r32["plan"]
+        v = torch.empty_like(sig_d)
+        plan.apply_adjoint(sig_d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.adjoint_steps):
+            plan.apply_adjoint(sig_d)
+        torch.cuda.synchronize()
+        adj = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.adjoint_steps, "conjugate": True}
+        log(f"adjoint: {adj['ms_per_step']:.3f} ms/apply")
+        del v, plan
+    r32.pop("plan")
     r64 = run("fp64", args.fp64_steps, 2, False) if args.fp64_steps > 0 else None
 
     # ---- oracle: error and CPU baseline on the sampled targets ----------------
@@ -185,6 +204,57 @@ def main():
         "algorithmic_bytes_per_launch": traffic[dom] / (cnt_dom / args.steps),
     }
 
+    # ---- batched right-hand sides (MFMA) -----------------------------------------
+    batched = None
+    if args.batched_rhs > 0:
+        wb = inputs.workload("sphere16")
+        pb, nb_, wb_ = inputs.build_surface(wb)
+        Rb = args.batched_rhs
+        Sb = inputs.plane_wave_densities(pb, wb["k"], Rb, seed=inputs.config_seed(wb["config"]))
+        Sb_d = torch.from_numpy(Sb.astype(np.complex64)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        planb = Plan(pb, nb_, wb_, wb["k"], wb["eta"], precision="fp32", max_rhs=Rb,
+                     **dict(opts, depth=wb["depth"]))
+        torch.cuda.synchronize()
+        t_planb = time.perf_counter() - t0
+        Ub = planb.apply(Sb_d)
+        torch.cuda.synchronize()
+        planb.set_profiling(64 * args.batched_steps)
+        t0 = time.perf_counter()
+        for _ in range(args.batched_steps):
+            planb.apply(Sb_d, out=Ub)
+        torch.cuda.synchronize()
+        wall_b = time.perf_counter() - t0
+        profb = planb.read_profile()
+        planb.set_profiling(0)
+        stb = planb.stats()
+        Ubh = Ub.cpu().numpy()
+        log(f"batched: {Rb} RHS, {wall_b * 1e3 / args.batched_steps:.2f} ms/apply")
+        errb = None
+        if not args.no_cpu_baseline:
+            from oracle import direct
+            tgb = inputs.sample_targets(len(pb), 512, seed=inputs.config_seed(wb["config"]) + 100)
+            cols = [0, Rb // 2, Rb - 1]
+            refb = direct.apply_c(pb, nb_, wb_, wb["k"], wb["eta"], Sb[:, cols], targets=tgb)
+            errb = float(np.linalg.norm(Ubh[tgb][:, cols] - refb) / np.linalg.norm(refb))
+        pe = sum(stb["prop_evals"].values())
+        flops_prop = pe * Rb * 4 * P          # complex coefficients x real basis, per RHS
+        ms_p, cnt_p = profb.get("prop", (0.0, 0))
+        ach = flops_prop / (ms_p / args.batched_steps * 1e-3) / 1e12 if ms_p else None
+        batched = {
+            "workload": (f"sphere16: cubed sphere 6x{wb['n']}^2, N={len(pb)}, k=32pi, eta=k, D={wb['depth']}, "
+                         f"{Rb} plane-wave RHS, FP32, MFMA contraction over RHS groups of 16"),
+            "ms_per_step": wall_b * 1e3 / args.batched_steps, "ms_per_rhs": wall_b * 1e3 / args.batched_steps / Rb,
+            "rel_err": errb, "plan_create_s": t_planb,
+            "stages": {k2: {"ms_per_apply": v2[0] / args.batched_steps, "launches_per_apply": v2[1] / args.batched_steps}
+                       for k2, v2 in profb.items()},
+            "roofline_prop": {"bound": "mfma", "achieved": ach, "peak": 157.3, "unit": "TFLOP/s",
+                              "frac": (ach / 157.3) if ach else None, "kernel": "k_prop_mfma",
+                              "algorithmic_flops_per_apply": flops_prop},
+        }
+        del planb, Ub, Sb_d
+
     ms_per_step = r32["wall"] * 1e3 / args.steps
     out = {
         "metric": METRIC,
@@ -217,6 +287,8 @@ def main():
                  "cousin_pairs": cousin, "prop_evals": prop_evals, "device_bytes": st["device_bytes"]},
         "consistency_flags": r32["flags"],
     }
+    out["adjoint"] = adj
+    out["batched"] = batched
     if r64 is not None:
         out["fp64"] = {"ms_per_step": r64["wall"] * 1e3 / args.fp64_steps, "rel_err": err64,
                        "plan_create_s": r64["t_plan"], "consistency_flags": r64["flags"]}

@@ -56,11 +56,14 @@ template <typename T>
 __global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, int dtype, int conj_in,
                                                 const int* __restrict__ perm, const double* __restrict__ w,
                                                 int64_t n, int R, cpx<T>* __restrict__ a) {
-  int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i >= n) return;
-  int64_t j = perm[i];
-  double wi = w ? w[i] : 1.0;
-  for (int r = 0; r < R; ++r) {
+  // one thread per (point, right-hand side), right-hand sides fastest
+  const int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q >= n * R) return;
+  const int64_t i = q / R;
+  const int r = (int)(q % R);
+  const int64_t j = perm[i];
+  const double wi = w ? w[i] : 1.0;
+  {
     double re, im;
     if (dtype == IFGF_C128) {
       const double* s = (const double*)sigma + 2 * (j * R + r);
@@ -83,21 +86,22 @@ __global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, 
 // transposed sum is formed: output j collects v_i K(x_i, x_j), whose normal
 // is the one at the output point x_j.
 // ---------------------------------------------------------------------------
-constexpr int NEAR_CHUNK = 512;
+template <int RG> struct NearChunk { static constexpr int N = RG == 1 ? 512 : 128; };
 
-template <typename T, bool TR>
+template <typename T, bool TR, int RG>
 __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, const double* __restrict__ nrm,
                                               const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
                                               const int* __restrict__ nbr_off, const int* __restrict__ nbr,
                                               const double* __restrict__ centre, double k, double eta, int kind,
                                               cpx<T>* __restrict__ uacc) {
-  __shared__ T sx[NEAR_CHUNK][3];
-  __shared__ T sn[NEAR_CHUNK][3];
-  __shared__ cpx<T> sa[NEAR_CHUNK];
-  __shared__ int sidx[NEAR_CHUNK];
+  constexpr int NC = NearChunk<RG>::N;
+  __shared__ T sx[NC][3];
+  __shared__ T sn[NC][3];
+  __shared__ cpx<T> sa[NC][RG];
+  __shared__ int sidx[NC];
   __shared__ int noff[28], nbox[27];
-  __shared__ cpx<T> red[TPB];
-  const int b = blockIdx.x, r = blockIdx.y;
+  __shared__ cpx<T> red[TPB][RG];
+  const int b = blockIdx.x, r0 = blockIdx.y * RG;
   const int t0 = start[b], nt = start[b + 1] - t0;
   const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
   const int nn = nbr_off[b + 1] - nbr_off[b];
@@ -134,9 +138,11 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
         m2 = (T)nrm[3 * (t0 + ti) + 2];
       }
     }
-    cpx<T> acc = {0, 0};
-    for (int cb = 0; cb < nsrc; cb += NEAR_CHUNK) {
-      const int cn = min(NEAR_CHUNK, nsrc - cb);
+    cpx<T> acc[RG];
+#pragma unroll
+    for (int q = 0; q < RG; ++q) acc[q] = {0, 0};
+    for (int cb = 0; cb < nsrc; cb += NC) {
+      const int cn = min(NC, nsrc - cb);
       __syncthreads();
       for (int e = threadIdx.x; e < cn; e += TPB) {
         int f = cb + e, q = 0;
@@ -149,7 +155,8 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
         sn[e][0] = (T)nrm[3 * j];
         sn[e][1] = (T)nrm[3 * j + 1];
         sn[e][2] = (T)nrm[3 * j + 2];
-        sa[e] = a[(int64_t)j * R + r];
+#pragma unroll
+        for (int q2 = 0; q2 < RG; ++q2) sa[e][q2] = a[(int64_t)j * R + r0 + q2];
       }
       __syncthreads();
       if (tv) {
@@ -174,22 +181,29 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
             T pr = dn, pi = -(kk * rr * dn + ee);
             kv = {g * (cs_ * pr - sn_ * pi), g * (sn_ * pr + cs_ * pi)};
           }
-          cpx<T> av = sa[e];
-          acc.re += kv.re * av.re - kv.im * av.im;
-          acc.im += kv.re * av.im + kv.im * av.re;
+#pragma unroll
+          for (int q2 = 0; q2 < RG; ++q2) {
+            const cpx<T> av = sa[e][q2];
+            acc[q2].re += kv.re * av.re - kv.im * av.im;
+            acc[q2].im += kv.re * av.im + kv.im * av.re;
+          }
         }
       }
     }
     __syncthreads();
-    red[threadIdx.x] = acc;
+#pragma unroll
+    for (int q2 = 0; q2 < RG; ++q2) red[threadIdx.x][q2] = acc[q2];
     __syncthreads();
     if (sl == 0 && tv) {
-      cpx<T> s = red[threadIdx.x];
-      for (int q = 1; q < S; ++q) {
-        s.re += red[threadIdx.x + q * TP].re;
-        s.im += red[threadIdx.x + q * TP].im;
+#pragma unroll
+      for (int q2 = 0; q2 < RG; ++q2) {
+        cpx<T> s2 = red[threadIdx.x][q2];
+        for (int q = 1; q < S; ++q) {
+          s2.re += red[threadIdx.x + q * TP][q2].re;
+          s2.im += red[threadIdx.x + q * TP][q2].im;
+        }
+        uacc[(int64_t)(t0 + ti) * R + r0 + q2] = s2;
       }
-      uacc[(int64_t)(t0 + ti) * R + r] = s;
     }
   }
 }
@@ -201,20 +215,21 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
 //   k r (|v| - 1) = k h (s|u|^2 - 2<e,u>) / (|v| + 1)   (bounded phase)
 //   W_c = E1 [ s <v,n> / (h |v|^3) - i ( k <v,n> / |v|^2 + eta / |v| ) ]
 // ---------------------------------------------------------------------------
-constexpr int LEAF_CHUNK = 256;
+template <int RG> struct LeafChunk { static constexpr int N = RG == 1 ? 256 : 64; };
 
-template <typename T, int PS, int PA>
+template <typename T, int PS, int PA, int RG>
 __global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, const double* __restrict__ nrm,
                                               const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
                                               const double* __restrict__ centre, const int* __restrict__ slot_off,
                                               const int* __restrict__ rel_cone, LevelGeom g, ChebTab ct, double k,
                                               double eta, int kind, cpx<T>* __restrict__ Fn) {
   constexpr int P = PS * PA * PA;
-  __shared__ T su[LEAF_CHUNK][3];
-  __shared__ T sn[LEAF_CHUNK][3];
-  __shared__ T suu[LEAF_CHUNK], sun[LEAF_CHUNK];
-  __shared__ cpx<T> sa[LEAF_CHUNK];
-  const int b = blockIdx.x, r = blockIdx.y;
+  constexpr int LC = LeafChunk<RG>::N;
+  __shared__ T su[LC][3];
+  __shared__ T sn[LC][3];
+  __shared__ T suu[LC], sun[LC];
+  __shared__ cpx<T> sa[LC][RG];
+  const int b = blockIdx.x, r0 = blockIdx.y * RG;
   const int s0 = slot_off[b], ncn = slot_off[b + 1] - s0;
   const int p0 = start[b], np = start[b + 1] - p0;
   const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
@@ -232,9 +247,11 @@ __global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, co
       if constexpr (Prec<T>::f32) node_dir32(cid, ai, bi, ci, g, ct, e, &s);
       else node_dir64(cid, ai, bi, ci, g, ct, e, &s);
     }
-    cpx<T> acc = {0, 0};
-    for (int cb = 0; cb < np; cb += LEAF_CHUNK) {
-      const int cn = min(LEAF_CHUNK, np - cb);
+    cpx<T> acc[RG];
+#pragma unroll
+    for (int q2 = 0; q2 < RG; ++q2) acc[q2] = {0, 0};
+    for (int cb = 0; cb < np; cb += LC) {
+      const int cn = min(LC, np - cb);
       __syncthreads();
       for (int q = threadIdx.x; q < cn; q += TPB) {
         int j = p0 + cb + q;
@@ -249,7 +266,8 @@ __global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, co
         sn[q][2] = n2;
         suu[q] = u0 * u0 + u1 * u1 + u2 * u2;
         sun[q] = u0 * n0 + u1 * n1 + u2 * n2;
-        sa[q] = a[(int64_t)j * R + r];
+#pragma unroll
+        for (int q2 = 0; q2 < RG; ++q2) sa[q][q2] = a[(int64_t)j * R + r0 + q2];
       }
       __syncthreads();
       if (valid) {
@@ -271,13 +289,19 @@ __global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, co
             T B = kk * vn * inv * inv + ee * inv;
             W = {cp * A + sp * B, sp * A - cp * B};
           }
-          cpx<T> av = sa[q];
-          acc.re += W.re * av.re - W.im * av.im;
-          acc.im += W.re * av.im + W.im * av.re;
+#pragma unroll
+          for (int q2 = 0; q2 < RG; ++q2) {
+            const cpx<T> av = sa[q][q2];
+            acc[q2].re += W.re * av.re - W.im * av.im;
+            acc[q2].im += W.re * av.im + W.im * av.re;
+          }
         }
       }
     }
-    if (valid) Fn[((int64_t)s0 * P + it) * R + r] = acc;
+    if (valid) {
+#pragma unroll
+      for (int q2 = 0; q2 < RG; ++q2) Fn[((int64_t)s0 * P + it) * R + r0 + q2] = acc[q2];
+    }
   }
 }
 
@@ -328,6 +352,58 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
       s.im += ma[l * PA + q] * x.im;
     }
     Fc[((int64_t)sl * P + t) * R + r] = s;
+  }
+}
+
+// Node values -> coefficients for RG right-hand sides at once (layout
+// [slot][P][R]): one block per (cone, RHS group); the P x RG tile is read and
+// written in rows of RG consecutive values.
+template <typename T, int PS, int PA, int RG>
+__global__ __launch_bounds__(TPB) void k_coeffs_rg(const cpx<T>* __restrict__ Fn, int R, const T* __restrict__ Ms,
+                                                   const T* __restrict__ Ma, cpx<T>* __restrict__ Fc) {
+  constexpr int P = PS * PA * PA;
+  constexpr int N = P * RG;
+  __shared__ cpx<T> v0[N], v1[N];
+  __shared__ T ms[PS * PS], ma[PA * PA];
+  const int sl = blockIdx.x, r0 = blockIdx.y * RG;
+  const int t = threadIdx.x;
+  if (t < PS * PS) ms[t] = Ms[t];
+  if (t < PA * PA) ma[t] = Ma[t];
+  const cpx<T>* src = Fn + (int64_t)sl * P * R + r0;
+  for (int q = t; q < N; q += TPB) v0[q] = src[(int64_t)(q / RG) * R + q % RG];
+  __syncthreads();
+  for (int q = t; q < N; q += TPB) {   // over a (s)
+    const int j = q / RG, rr = q % RG, i = j / (PA * PA), jj = (j / PA) % PA, l = j % PA;
+    cpx<T> acc = {0, 0};
+    for (int k = 0; k < PS; ++k) {
+      const cpx<T> x = v0[((k * PA + jj) * PA + l) * RG + rr];
+      acc.re += ms[i * PS + k] * x.re;
+      acc.im += ms[i * PS + k] * x.im;
+    }
+    v1[q] = acc;
+  }
+  __syncthreads();
+  for (int q = t; q < N; q += TPB) {   // over b (theta)
+    const int j = q / RG, rr = q % RG, i = j / (PA * PA), jj = (j / PA) % PA, l = j % PA;
+    cpx<T> acc = {0, 0};
+    for (int k = 0; k < PA; ++k) {
+      const cpx<T> x = v1[((i * PA + k) * PA + l) * RG + rr];
+      acc.re += ma[jj * PA + k] * x.re;
+      acc.im += ma[jj * PA + k] * x.im;
+    }
+    v0[q] = acc;
+  }
+  __syncthreads();
+  cpx<T>* dst = Fc + (int64_t)sl * P * R + r0;
+  for (int q = t; q < N; q += TPB) {   // over c (phi)
+    const int j = q / RG, rr = q % RG, i = j / (PA * PA), jj = (j / PA) % PA, l = j % PA;
+    cpx<T> acc = {0, 0};
+    for (int k = 0; k < PA; ++k) {
+      const cpx<T> x = v0[((i * PA + jj) * PA + k) * RG + rr];
+      acc.re += ma[l * PA + k] * x.re;
+      acc.im += ma[l * PA + k] * x.im;
+    }
+    dst[(int64_t)j * R + rr] = acc;
   }
 }
 
@@ -396,9 +472,15 @@ __device__ __forceinline__ cpx<T> eval_uniform(const cpx<T>* __restrict__ F, int
     pending &= ~__ballot(mine);
     const cpx<T>* src = F + (int64_t)su * P * R + r;
     cpx<T> v[NCP];
+    if (R == 1) {
 #pragma unroll
-    for (int j = 0; j < NCP; ++j)
-      if (lane + 64 * j < P) v[j] = src[(int64_t)(lane + 64 * j) * R];
+      for (int j = 0; j < NCP; ++j)
+        if (lane + 64 * j < P) v[j] = src[lane + 64 * j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NCP; ++j)
+        if (lane + 64 * j < P) v[j] = src[(int64_t)(lane + 64 * j) * R];
+    }
 #pragma unroll
     for (int j = 0; j < NCP; ++j)
       if (lane + 64 * j < P) wb[lane + 64 * j] = v[j];
@@ -505,14 +587,16 @@ __device__ __forceinline__ void lds_coeffs_store(cpx<T>* v, cpx<T>* t, int nc, c
   }
 }
 
-template <typename T, int PS, int PA>
+// ONE: a single right-hand side (R = 1 at compile time, contiguous cones).
+template <typename T, int PS, int PA, bool ONE>
 __global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
     const int4* __restrict__ work, const int* __restrict__ rel_cone_up, const int* __restrict__ child_lo_up,
     const int* __restrict__ coords, const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c, LevelGeom gp,
-    LevelGeom gc, ChebTab ct, const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind, int R,
+    LevelGeom gc, ChebTab ct, const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind, int R_,
     cpx<T>* __restrict__ Fc_up, int* __restrict__ err) {
   constexpr int P = PS * PA * PA;
   constexpr int BS = PropShape<P>::BS;
+  const int R = ONE ? 1 : R_;
   constexpr int NN = PropShape<P>::CH * P;
   constexpr int HB = NN <= 256 ? 8 : (NN <= 512 ? 9 : (NN <= 1024 ? 10 : 11));   // 2^HB >= NN
   constexpr int HT = 1 << HB;
@@ -529,7 +613,7 @@ __global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
   const int4 wk = work[blockIdx.x];
   const int Pb = wk.x, s0 = wk.y, ncn = wk.z - wk.y;
   const int nn = ncn * P;
-  const int r = blockIdx.y;
+  const int r = ONE ? 0 : blockIdx.y;
   if (threadIdx.x < PS * PS) ms[threadIdx.x] = Ms[threadIdx.x];
   if (threadIdx.x < PA * PA) ma[threadIdx.x] = Ma[threadIdx.x];
   for (int q = threadIdx.x; q < nn; q += BS) acc[q] = {0, 0};
@@ -1348,17 +1432,23 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   dim3 gpts(nblocks(n), R);
   {
     StageTimer tm(p, s, IFGF_STAGE_GATHER);
-    k_gather<T><<<gpts, TPB, 0, s>>>(sigma, dtype, 0, p->perm.as<int>(), p->w.as<double>(), n, R, a);
+    k_gather<T><<<nblocks(n * R), TPB, 0, s>>>(sigma, dtype, 0, p->perm.as<int>(), p->w.as<double>(), n, R, a);
   }
   HIPCHK(hipGetLastError());
   const int kind = p->opt.kernel;
   LevelPlan& lD = p->lev[D];
   const bool near = stage_mask & 1;
+  const bool grouped = R % MF_RG == 0;   // right-hand sides in groups of 16 per launch column
   if (near) {
     StageTimer tm(p, s, IFGF_STAGE_NEAR);
-    k_near<T, false><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
-                                            lD.nbr_off.as<int>(), lD.nbr.as<int>(), lD.centre.as<double>(), p->k,
-                                            p->eta, kind, uacc);
+    if (grouped)
+      k_near<T, false, MF_RG><<<dim3(lD.nb, R / MF_RG), TPB, 0, s>>>(
+          p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(), lD.nbr_off.as<int>(), lD.nbr.as<int>(),
+          lD.centre.as<double>(), p->k, p->eta, kind, uacc);
+    else
+      k_near<T, false, 1><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R,
+                                                         lD.start.as<int>(), lD.nbr_off.as<int>(), lD.nbr.as<int>(),
+                                                         lD.centre.as<double>(), p->k, p->eta, kind, uacc);
     HIPCHK(hipGetLastError());
   }
   if (D >= 3) {
@@ -1366,15 +1456,25 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     const T* Ma = (const T*)(Prec<T>::f32 ? p->Maf.p : p->Ma.p);
     {
       StageTimer tm(p, s, IFGF_STAGE_LEAF);
-      k_leaf<T, PS, PA><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R,
-                                                       lD.start.as<int>(), lD.centre.as<double>(), lD.slot_off.as<int>(),
-                                                       lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta, kind,
-                                                       lD.Fn.as<cpx<T>>());
+      if (grouped)
+        k_leaf<T, PS, PA, MF_RG><<<dim3(lD.nb, R / MF_RG), TPB, 0, s>>>(
+            p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(), lD.centre.as<double>(),
+            lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta, kind, lD.Fn.as<cpx<T>>());
+      else
+        k_leaf<T, PS, PA, 1><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R,
+                                                            lD.start.as<int>(), lD.centre.as<double>(),
+                                                            lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom,
+                                                            p->cheb, p->k, p->eta, kind, lD.Fn.as<cpx<T>>());
     }
     HIPCHK(hipGetLastError());
     if (lD.nrel > 0) {
       StageTimer tm(p, s, IFGF_STAGE_COEFFS);
-      k_coeffs<T, PS, PA, false><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma, lD.Fc.as<cpx<T>>());
+      if (grouped)
+        k_coeffs_rg<T, PS, PA, MF_RG><<<dim3(lD.nrel, R / MF_RG), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), R, Ms, Ma,
+                                                                              lD.Fc.as<cpx<T>>());
+      else
+        k_coeffs<T, PS, PA, false><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma,
+                                                                   lD.Fc.as<cpx<T>>());
       HIPCHK(hipGetLastError());
     }
     const bool mfma = Prec<T>::f32 && R % MF_RG == 0 && PS <= 4;
@@ -1401,15 +1501,16 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           HIPCHK(hipGetLastError());
           {
             StageTimer tm(p, s, IFGF_STAGE_COEFFS);
-            k_coeffs<T, PS, PA, false><<<dim3(lp.nrel, R), TPB, 0, s>>>(p->scratch_fn.as<cpx<T>>(), lp.nrel, R, Ms,
-                                                                       Ma, lp.Fc.as<cpx<T>>());
+            k_coeffs_rg<T, PS, PA, MF_RG><<<dim3(lp.nrel, R / MF_RG), TPB, 0, s>>>(p->scratch_fn.as<cpx<T>>(), R, Ms,
+                                                                                  Ma, lp.Fc.as<cpx<T>>());
           }
           HIPCHK(hipGetLastError());
           continue;
         }
       }
       StageTimer tm(p, s, IFGF_STAGE_PROP);
-      k_prop<T, PS, PA><<<dim3((unsigned)lp.nwork, R), PropShape<P>::BS, 0, s>>>(
+      auto kp = R == 1 ? k_prop<T, PS, PA, true> : k_prop<T, PS, PA, false>;
+      kp<<<dim3((unsigned)lp.nwork, R), PropShape<P>::BS, 0, s>>>(
           lp.work.as<int4>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(), lc.slot.as<int>(),
           lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, Ms, Ma, p->k, kind, R, lp.Fc.as<cpx<T>>(), p->err.as<int>());
       HIPCHK(hipGetLastError());
@@ -1458,13 +1559,13 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
   dim3 gpts(nblocks(n), R);
   {
     StageTimer tm(p, s, IFGF_STAGE_GATHER);
-    k_gather<T><<<gpts, TPB, 0, s>>>(v, dtype, conj, p->perm.as<int>(), nullptr, n, R, vs);
+    k_gather<T><<<nblocks(n * R), TPB, 0, s>>>(v, dtype, conj, p->perm.as<int>(), nullptr, n, R, vs);
   }
   HIPCHK(hipGetLastError());
   LevelPlan& lD = p->lev[D];
   {
     StageTimer tm(p, s, IFGF_STAGE_ADJ_NEAR);
-    k_near<T, true><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), vs, R,
+    k_near<T, true, 1><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), vs, R,
                                                    lD.start.as<int>(), lD.nbr_off.as<int>(), lD.nbr.as<int>(),
                                                    lD.centre.as<double>(), p->k, p->eta, kind, g);
   }
