@@ -47,6 +47,47 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+# HBM bytes per launch of the upward-pass kernel, from hardware byte counters
+# (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter reads for a
+# device copy of known size).  The summary records the SHA-256 of the kernel
+# sources it was taken with; when the sources have changed since, the figure
+# no longer describes this kernel and is not reported.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_prop_sphere32_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_06316_amd", "csrc", f) for f in ("apply.hip", "common.h")]
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def config_tag(args):
+    return f"{args.workload} p_s={args.p_s} p_ang={args.p_ang} ns0={args.ns0} nc0={args.nc0}"
+
+
+def measured_traffic(tag):
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for ln in lines:
+        if ln.startswith("- ") and ": " in ln:
+            key, val = ln[2:].split(": ", 1)
+            kv[key.strip().strip("`")] = val.strip().strip("`")
+    if kv.get("source_sha256") != kernel_source_sha() or kv.get("config") != tag:
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +104,9 @@ def main():
     ap.add_argument("--batched-rhs", type=int, default=64, help="RHS of the batched leg (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--adjoint-steps", type=int, default=5)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the FP32 leg, copy a buffer of this many MiB three times with a plain device copy "
+                         "(the reference point that scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: only --gpus 1 is supported: this build runs on one GPU "
@@ -121,6 +165,14 @@ def main():
 
     r32 = run("fp32", args.steps, args.warmup, True)
     st = r32["stats"]
+    if args.copy_probe_mib > 0:
+        src = torch.ones((args.copy_probe_mib << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: 3 x {args.copy_probe_mib} MiB device copy")
+        del src, dst
 
     # ---- transposed apply (autograd backward) at the same workload --------------
     adj = None
@@ -196,9 +248,10 @@ def main():
     avg_launch_s = ms_dom / cnt_dom * 1e-3
     per_launch_flops = work[dom] / (cnt_dom / args.steps)
     achieved = per_launch_flops / avg_launch_s / 1e12
+    measured = measured_traffic(config_tag(args)) if dom == "prop" else None
     roofline = {
         "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None, "kernel": dom,
+        "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured, "kernel": dom,
         "avg_launch_ms": avg_launch_s * 1e3, "launches_per_apply": cnt_dom / args.steps,
         "algorithmic_flops_per_launch": per_launch_flops,
         "algorithmic_bytes_per_launch": traffic[dom] / (cnt_dom / args.steps),

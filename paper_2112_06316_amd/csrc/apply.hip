@@ -101,7 +101,7 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
   __shared__ int sidx[NC];
   __shared__ int noff[28], nbox[27];
   __shared__ cpx<T> red[TPB][RG];
-  const int b = blockIdx.x, r0 = blockIdx.y * RG;
+  const int b = xcd_block(blockIdx.x, gridDim.x), r0 = blockIdx.y * RG;
   const int t0 = start[b], nt = start[b + 1] - t0;
   const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
   const int nn = nbr_off[b + 1] - nbr_off[b];
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
   __shared__ T ms[PS * PS], ma[PA * PA];
   __shared__ __align__(16) T cbuf[BS / 64][2 * P];
 
-  const int4 wk = work[blockIdx.x];
+  const int4 wk = work[xcd_block(blockIdx.x, gridDim.x)];
   const int Pb = wk.x, s0 = wk.y, ncn = wk.z - wk.y;
   const int nn = ncn * P;
   const int r = ONE ? 0 : blockIdx.y;
@@ -733,7 +733,7 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
   constexpr int P = PS * PA * PA;
   __shared__ __align__(16) T cbuf[TPB / 64][2 * P];
   const int r = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
   const bool valid = i0 < n;
   const int64_t i = valid ? i0 : n - 1;      // lanes past the end follow the last point and store nothing
   const double* x = pts + 3 * i;
@@ -935,7 +935,7 @@ __global__ __launch_bounds__(TPB) void k_targets_mfma(const double* __restrict__
   __shared__ float rec[TPB / 64][64 * NR];
   const int g = blockIdx.y;
   const int l = threadIdx.x & 63;
-  const int64_t i0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
   const bool valid = i0 < n;
   const int64_t i = valid ? i0 : n - 1;
   const double* x = pts + 3 * i;
@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma(int nrel_up, const int* __res
   const int g = blockIdx.y;
   const int l = threadIdx.x & 63;
   const int64_t nitem = (int64_t)nrel_up * P;
-  const int64_t t0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
   const bool valid = t0 < nitem;
   const int64_t t = valid ? t0 : nitem - 1;
   const int sp = (int)(t / P), node = (int)(t % P);
@@ -1187,7 +1187,7 @@ __global__ __launch_bounds__(TPB) void k_adj_targets(const double* __restrict__ 
   using S = AntShape<T, PS, PA>;
   __shared__ T fbuf[TPB / 64][64 * S::NF];
   const int r = blockIdx.y;
-  const int64_t i0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
   const bool valid = i0 < n;
   const int64_t i = valid ? i0 : n - 1;
   const double* x = pts + 3 * i;
@@ -1258,7 +1258,7 @@ __global__ __launch_bounds__(TPB) void k_adj_prop(int nrel_up, const int* __rest
   constexpr int P = S::P;
   __shared__ T fbuf[TPB / 64][64 * S::NF];
   const int r = blockIdx.y;
-  const int64_t t0 = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
   const bool valid = t0 < (int64_t)nrel_up * P;
   const int64_t t = valid ? t0 : (int64_t)nrel_up * P - 1;
   const int sp = (int)(t / P), node = (int)(t % P);

@@ -360,3 +360,14 @@ __host__ __device__ __forceinline__ void morton_decode(uint32_t key, int* x, int
 
 // Wave-level helpers (wave64).
 __device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((unsigned long long)mask) - 1; }
+
+// Workgroups of a launch are dealt to the 8 XCDs round-robin (block b to XCD
+// b mod 8), and each XCD has its own L2.  xcd_block(b, G) maps the block index
+// to a work index so that the blocks of one XCD take one contiguous range of
+// the G work items: neighbouring items (the same parent box, nearby targets in
+// Morton order) then share that XCD's L2.  A bijection of [0, G).
+__device__ __forceinline__ int xcd_block(int b, int G) {
+  constexpr int NX = 8;
+  const int x = b % NX, l = b / NX, q = G / NX, r = G % NX;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
