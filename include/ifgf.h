@@ -42,6 +42,7 @@ extern "C" {
 #endif
 
 typedef struct ifgf_plan_s *ifgf_plan;
+typedef struct ifgf_batch_s *ifgf_batch;
 
 typedef enum {
     IFGF_OK = 0,
@@ -242,6 +243,55 @@ ifgf_status ifgf_plan_read_profile(ifgf_plan p, double *ms, int64_t *launches);
 /* Release the plan and its device memory (after its work has completed).
  * NULL is ignored. */
 void ifgf_plan_destroy(ifgf_plan p);
+
+/*
+ * Ragged batch: the forward apply (as ifgf_apply, one right-hand side) of
+ * several plans - different geometries, sizes, depths and wavenumbers - in
+ * ONE persistent kernel launch.  Algorithm 1 of every geometry is cut into
+ * work items (gather chunks, near-field boxes, leaf boxes, coefficient
+ * chunks, upward-pass items of each level, target chunks) held in one
+ * queue in data-flow order; work-groups take items from the queue and wait
+ * on per-geometry completion counters before items whose inputs other
+ * work-groups produce (the leaf coefficients before the upward pass, level
+ * d before level d-1, every level and the near field before the targets).
+ * Small geometries thereby share the device with large ones instead of
+ * leaving it idle between launches.  The result of each geometry is the
+ * same as ifgf_apply on its plan with nrhs = 1.
+ *
+ * ifgf_batch_create: plans [host] array of nplans handles, 1 <= nplans <=
+ *   IFGF_BATCH_MAX, pairwise distinct, all with the same precision, p_s and
+ *   p_ang (the kernel and everything else may differ).  The batch does not
+ *   own the plans: they must outlive it.  It holds a small device queue
+ *   description.  Synchronizes the device.  Errors: EINVAL, EUNSUPPORTED,
+ *   ENOMEM, EHIP.
+ * ifgf_batch_apply: sigma, u [host] arrays of nplans [device] pointers, each
+ *   an n_g x 1 complex array of dtype `dtype` in the caller's order of plan
+ *   g; u[g] is overwritten and must not alias any sigma.  The applies use
+ *   the plans' own workspaces: no apply on any of these plans may run
+ *   concurrently (EBUSY while one is being enqueued).  Errors: EINVAL,
+ *   EBUSY, EHIP.
+ * ifgf_batch_check: [host] *flags = bit 0 set if, in some batch apply since
+ *   the batch was created, a work item's wait for its inputs exceeded the
+ *   poll limit and the item went ahead without them (results then invalid),
+ *   OR the consistency flags of the plans (ifgf_plan_check).  Synchronizes
+ *   the device.
+ * ifgf_batch_set_spin_limit: polls of a completion counter before a wait is
+ *   abandoned (default 4194304, each about 0.3 us apart; 0 = never wait).
+ *   A test hook for the bounded wait.
+ * ifgf_batch_get_info: [host] outputs, each may be NULL: queue items,
+ *   queue segments, work-groups of the persistent launch, threads per
+ *   work-group.
+ * ifgf_batch_destroy: releases the batch (not the plans).  NULL is ignored.
+ */
+#define IFGF_BATCH_MAX 64
+ifgf_status ifgf_batch_create(ifgf_batch *out, int32_t nplans, const ifgf_plan *plans);
+ifgf_status ifgf_batch_apply(ifgf_batch b, const void *const *sigma, void *const *u, int32_t dtype,
+                             void *stream);
+ifgf_status ifgf_batch_check(ifgf_batch b, int32_t *flags);
+ifgf_status ifgf_batch_set_spin_limit(ifgf_batch b, int32_t limit);
+ifgf_status ifgf_batch_get_info(ifgf_batch b, int64_t *items, int32_t *segments, int32_t *grid,
+                                int32_t *block);
+void ifgf_batch_destroy(ifgf_batch b);
 
 /* Static text for a status code. */
 const char *ifgf_status_string(ifgf_status st);

@@ -5,6 +5,6 @@ The compute path is the HIP library `libifgf.so` (C ABI in include/ifgf.h);
 this package only marshals arguments to it.  Importing the package does not
 load the library; `Plan` loads it on first use and raises if it is missing.
 """
-from .api import IFGFApply, Plan, library_path, load_library  # noqa: F401
+from .api import Batch, IFGFApply, Plan, library_path, load_library  # noqa: F401
 
-__all__ = ["Plan", "IFGFApply", "load_library", "library_path"]
+__all__ = ["Plan", "Batch", "IFGFApply", "load_library", "library_path"]

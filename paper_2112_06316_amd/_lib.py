@@ -7,6 +7,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libifgf.so")
 MAX_LEVELS = 12
+BATCH_MAX = 64
 
 OK, EINVAL, EDUPLICATE, ENOMEM, EHIP, EUNSUPPORTED, EBUSY, EINTERNAL = range(8)
 PREC_FP64, PREC_FP32_INTERP = 0, 1
@@ -70,6 +71,13 @@ SIGNATURES = {
     "ifgf_plan_set_profiling": (I32, [VP, I32]),
     "ifgf_plan_read_profile": (I32, [VP, VP, VP]),
     "ifgf_plan_destroy": (None, [VP]),
+    "ifgf_batch_create": (I32, [ctypes.POINTER(VP), I32, ctypes.POINTER(VP)]),
+    "ifgf_batch_apply": (I32, [VP, ctypes.POINTER(VP), ctypes.POINTER(VP), I32, VP]),
+    "ifgf_batch_check": (I32, [VP, ctypes.POINTER(I32)]),
+    "ifgf_batch_set_spin_limit": (I32, [VP, I32]),
+    "ifgf_batch_get_info": (I32, [VP, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                  ctypes.POINTER(I32)]),
+    "ifgf_batch_destroy": (None, [VP]),
     "ifgf_status_string": (ctypes.c_char_p, [I32]),
     "ifgf_last_error": (ctypes.c_char_p, []),
 }

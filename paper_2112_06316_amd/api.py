@@ -203,6 +203,75 @@ class Plan:
         return buf[:nr * P * nrhs].cpu().numpy().reshape(nr, P, nrhs).transpose(0, 2, 1)
 
 
+class Batch:
+    """Ragged batch of plans applied in one launch (ifgf_batch_* in include/ifgf.h).
+
+    All plans share precision, p_s and p_ang; each takes one right-hand side.
+    The batch keeps references to its plans so that they outlive it.
+    """
+
+    def __init__(self, plans):
+        plans = list(plans)
+        if not plans:
+            raise ValueError("empty batch")
+        self._lib = L.load()
+        self.plans = plans
+        self.device = plans[0].device
+        hs = (ctypes.c_void_p * len(plans))(*[p._h for p in plans])
+        h = ctypes.c_void_p()
+        L.check(self._lib.ifgf_batch_create(ctypes.byref(h), len(plans), hs), "ifgf_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ifgf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, sigmas, outs=None):
+        """[u_g = A_g sigma_g for each plan g]; sigma_g of shape (n_g,), one complex dtype for all."""
+        if len(sigmas) != len(self.plans):
+            raise ValueError("one density per plan")
+        xs, dtype = [], None
+        for p, x in zip(self.plans, sigmas):
+            x = torch.as_tensor(x)
+            if x.dim() == 2 and x.shape[1] == 1:
+                x = x[:, 0]
+            if x.dim() != 1 or x.shape[0] != p.n:
+                raise ValueError(f"expected a ({p.n},) density")
+            if x.dtype not in (torch.complex64, torch.complex128):
+                raise TypeError("complex64 or complex128 required")
+            d = L.C128 if x.dtype == torch.complex128 else L.C64
+            if dtype is not None and d != dtype:
+                raise TypeError("all densities must share one dtype")
+            dtype = d
+            xs.append(x.to(self.device).contiguous())
+        us = [torch.empty_like(x) for x in xs] if outs is None else list(outs)
+        sp = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        up = (ctypes.c_void_p * len(us))(*[u.data_ptr() for u in us])
+        L.check(self._lib.ifgf_batch_apply(self._h, sp, up, dtype, _stream_ptr(self.device)), "ifgf_batch_apply")
+        return us
+
+    def check(self) -> int:
+        f = ctypes.c_int32(0)
+        L.check(self._lib.ifgf_batch_check(self._h, ctypes.byref(f)), "ifgf_batch_check")
+        return int(f.value)
+
+    def set_spin_limit(self, limit: int):
+        L.check(self._lib.ifgf_batch_set_spin_limit(self._h, int(limit)), "ifgf_batch_set_spin_limit")
+
+    def info(self) -> dict:
+        items, segs, grid, block = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        L.check(self._lib.ifgf_batch_get_info(self._h, ctypes.byref(items), ctypes.byref(segs), ctypes.byref(grid),
+                                              ctypes.byref(block)), "ifgf_batch_get_info")
+        return {"items": items.value, "segments": segs.value, "grid": grid.value, "block": block.value}
+
+
 class IFGFApply(torch.autograd.Function):
     """u = A sigma with backward grad_sigma = A~^H grad_u (PyTorch's complex convention)."""
 

@@ -52,31 +52,35 @@ template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return 
 // ---------------------------------------------------------------------------
 // gather: a[i, r] = w_i sigma[perm_i, r]
 // ---------------------------------------------------------------------------
+// Element q = (point i, right-hand side r), right-hand sides fastest.
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, int dtype, int conj_in,
-                                                const int* __restrict__ perm, const double* __restrict__ w,
-                                                int64_t n, int R, cpx<T>* __restrict__ a) {
-  // one thread per (point, right-hand side), right-hand sides fastest
-  const int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+__device__ __forceinline__ void gather_one(int64_t q, const void* __restrict__ sigma, int dtype, int conj_in,
+                                           const int* __restrict__ perm, const double* __restrict__ w, int64_t n,
+                                           int R, cpx<T>* __restrict__ a) {
   if (q >= n * R) return;
   const int64_t i = q / R;
   const int r = (int)(q % R);
   const int64_t j = perm[i];
   const double wi = w ? w[i] : 1.0;
-  {
-    double re, im;
-    if (dtype == IFGF_C128) {
-      const double* s = (const double*)sigma + 2 * (j * R + r);
-      re = s[0];
-      im = s[1];
-    } else {
-      const float* s = (const float*)sigma + 2 * (j * R + r);
-      re = s[0];
-      im = s[1];
-    }
-    if (conj_in) im = -im;
-    a[i * R + r] = {(T)(wi * re), (T)(wi * im)};
+  double re, im;
+  if (dtype == IFGF_C128) {
+    const double* s = (const double*)sigma + 2 * (j * R + r);
+    re = s[0];
+    im = s[1];
+  } else {
+    const float* s = (const float*)sigma + 2 * (j * R + r);
+    re = s[0];
+    im = s[1];
   }
+  if (conj_in) im = -im;
+  a[i * R + r] = {(T)(wi * re), (T)(wi * im)};
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, int dtype, int conj_in,
+                                                const int* __restrict__ perm, const double* __restrict__ w,
+                                                int64_t n, int R, cpx<T>* __restrict__ a) {
+  gather_one<T>((int64_t)blockIdx.x * TPB + threadIdx.x, sigma, dtype, conj_in, perm, w, n, R, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -88,20 +92,32 @@ __global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, 
 // ---------------------------------------------------------------------------
 template <int RG> struct NearChunk { static constexpr int N = RG == 1 ? 512 : 128; };
 
-template <typename T, bool TR, int RG>
-__global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, const double* __restrict__ nrm,
-                                              const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
-                                              const int* __restrict__ nbr_off, const int* __restrict__ nbr,
-                                              const double* __restrict__ centre, double k, double eta, int kind,
-                                              cpx<T>* __restrict__ uacc) {
+template <typename T, int RG, int BS> struct NearSmem {
+  static constexpr int NC = NearChunk<RG>::N;
+  T sx[NC][3];
+  T sn[NC][3];
+  cpx<T> sa[NC][RG];
+  int sidx[NC];
+  int noff[28], nbox[27];
+  cpx<T> red[BS][RG];
+};
+
+// Near field of finest-level box b, right-hand sides r0 .. r0 + RG - 1, by a
+// block of BS threads.
+template <typename T, bool TR, int RG, int BS>
+__device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int r0, const double* __restrict__ pts,
+                                         const double* __restrict__ nrm, const cpx<T>* __restrict__ a, int R,
+                                         const int* __restrict__ start, const int* __restrict__ nbr_off,
+                                         const int* __restrict__ nbr, const double* __restrict__ centre, double k,
+                                         double eta, int kind, cpx<T>* __restrict__ uacc) {
   constexpr int NC = NearChunk<RG>::N;
-  __shared__ T sx[NC][3];
-  __shared__ T sn[NC][3];
-  __shared__ cpx<T> sa[NC][RG];
-  __shared__ int sidx[NC];
-  __shared__ int noff[28], nbox[27];
-  __shared__ cpx<T> red[TPB][RG];
-  const int b = xcd_block(blockIdx.x, gridDim.x), r0 = blockIdx.y * RG;
+  auto& sx = sm.sx;
+  auto& sn = sm.sn;
+  auto& sa = sm.sa;
+  auto& sidx = sm.sidx;
+  auto& noff = sm.noff;
+  auto& nbox = sm.nbox;
+  auto& red = sm.red;
   const int t0 = start[b], nt = start[b + 1] - t0;
   const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
   const int nn = nbr_off[b + 1] - nbr_off[b];
@@ -119,14 +135,14 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
   const int nsrc = noff[nn];
   // lane mapping: TP targets per pass, S source slices
   int TP = 1;
-  while (TP < nt && TP < TPB) TP <<= 1;
-  const int S = TPB / TP;
+  while (TP < nt && 2 * TP <= BS) TP <<= 1;
+  const int S = BS / TP;   // threads with sl >= S (BS not a power of two) stay idle
   const int tl = threadIdx.x % TP, sl = threadIdx.x / TP;
   const T kk = (T)k, ee = (T)eta;
   const T inv4pi = (T)(1.0 / (4.0 * IFGF_PI));
   for (int tb = 0; tb < nt; tb += TP) {
     const int ti = tb + tl;
-    const bool tv = ti < nt;
+    const bool tv = ti < nt && sl < S;
     T x0 = 0, x1 = 0, x2 = 0, m0 = 0, m1 = 0, m2 = 0;
     if (tv) {
       x0 = (T)(pts[3 * (t0 + ti)] - c0);
@@ -144,7 +160,7 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
     for (int cb = 0; cb < nsrc; cb += NC) {
       const int cn = min(NC, nsrc - cb);
       __syncthreads();
-      for (int e = threadIdx.x; e < cn; e += TPB) {
+      for (int e = threadIdx.x; e < cn; e += BS) {
         int f = cb + e, q = 0;
         while (noff[q + 1] <= f) ++q;
         int j = start[nbox[q]] + (f - noff[q]);
@@ -208,6 +224,17 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
   }
 }
 
+template <typename T, bool TR, int RG>
+__global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, const double* __restrict__ nrm,
+                                              const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
+                                              const int* __restrict__ nbr_off, const int* __restrict__ nbr,
+                                              const double* __restrict__ centre, double k, double eta, int kind,
+                                              cpx<T>* __restrict__ uacc) {
+  __shared__ NearSmem<T, RG, TPB> sm;
+  near_box<T, TR, RG, TPB>(sm, xcd_block(blockIdx.x, gridDim.x), blockIdx.y * RG, pts, nrm, a, R, start, nbr_off, nbr,
+                           centre, k, eta, kind, uacc);
+}
+
 // ---------------------------------------------------------------------------
 // leaf factors: one block per finest-level box, items (relevant cone, node).
 // W_c at node x = y0 + (h/s) e for a source y = y0 + h u:
@@ -217,26 +244,37 @@ __global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, co
 // ---------------------------------------------------------------------------
 template <int RG> struct LeafChunk { static constexpr int N = RG == 1 ? 256 : 64; };
 
-template <typename T, int PS, int PA, int RG>
-__global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, const double* __restrict__ nrm,
-                                              const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
-                                              const double* __restrict__ centre, const int* __restrict__ slot_off,
-                                              const int* __restrict__ rel_cone, LevelGeom g, ChebTab ct, double k,
-                                              double eta, int kind, cpx<T>* __restrict__ Fn) {
+template <typename T, int RG> struct LeafSmem {
+  static constexpr int LC = LeafChunk<RG>::N;
+  T su[LC][3];
+  T sn[LC][3];
+  T suu[LC], sun[LC];
+  cpx<T> sa[LC][RG];
+};
+
+// Leaf factors of finest-level box b, right-hand sides r0 .. r0 + RG - 1, by
+// a block of BS threads.
+template <typename T, int PS, int PA, int RG, int BS>
+__device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int r0, const double* __restrict__ pts,
+                                         const double* __restrict__ nrm, const cpx<T>* __restrict__ a, int R,
+                                         const int* __restrict__ start, const double* __restrict__ centre,
+                                         const int* __restrict__ slot_off, const int* __restrict__ rel_cone,
+                                         const LevelGeom& g, const ChebTab& ct, double k, double eta, int kind,
+                                         cpx<T>* __restrict__ Fn) {
   constexpr int P = PS * PA * PA;
   constexpr int LC = LeafChunk<RG>::N;
-  __shared__ T su[LC][3];
-  __shared__ T sn[LC][3];
-  __shared__ T suu[LC], sun[LC];
-  __shared__ cpx<T> sa[LC][RG];
-  const int b = blockIdx.x, r0 = blockIdx.y * RG;
+  auto& su = sm.su;
+  auto& sn = sm.sn;
+  auto& suu = sm.suu;
+  auto& sun = sm.sun;
+  auto& sa = sm.sa;
   const int s0 = slot_off[b], ncn = slot_off[b + 1] - s0;
   const int p0 = start[b], np = start[b + 1] - p0;
   const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
   const double invh = 1.0 / g.h;
   const T kk = (T)k, ee = (T)eta, kh = (T)(k * g.h), ih = (T)invh;
   const int nitems = ncn * P;
-  for (int ib = 0; ib < nitems; ib += TPB) {
+  for (int ib = 0; ib < nitems; ib += BS) {
     const int it = ib + threadIdx.x;
     const bool valid = it < nitems;
     T e[3] = {0, 0, 0}, s = 0;
@@ -253,7 +291,7 @@ __global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, co
     for (int cb = 0; cb < np; cb += LC) {
       const int cn = min(LC, np - cb);
       __syncthreads();
-      for (int q = threadIdx.x; q < cn; q += TPB) {
+      for (int q = threadIdx.x; q < cn; q += BS) {
         int j = p0 + cb + q;
         T u0 = (T)((pts[3 * j] - c0) * invh), u1 = (T)((pts[3 * j + 1] - c1) * invh),
           u2 = (T)((pts[3 * j + 2] - c2) * invh);
@@ -303,6 +341,17 @@ __global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, co
       for (int q2 = 0; q2 < RG; ++q2) Fn[((int64_t)s0 * P + it) * R + r0 + q2] = acc[q2];
     }
   }
+}
+
+template <typename T, int PS, int PA, int RG>
+__global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, const double* __restrict__ nrm,
+                                              const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
+                                              const double* __restrict__ centre, const int* __restrict__ slot_off,
+                                              const int* __restrict__ rel_cone, LevelGeom g, ChebTab ct, double k,
+                                              double eta, int kind, cpx<T>* __restrict__ Fn) {
+  __shared__ LeafSmem<T, RG> sm;
+  leaf_box<T, PS, PA, RG, TPB>(sm, blockIdx.x, blockIdx.y * RG, pts, nrm, a, R, start, centre, slot_off, rel_cone, g,
+                               ct, k, eta, kind, Fn);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,33 +636,53 @@ __device__ __forceinline__ void lds_coeffs_store(cpx<T>* v, cpx<T>* t, int nc, c
   }
 }
 
-// ONE: a single right-hand side (R = 1 at compile time, contiguous cones).
-template <typename T, int PS, int PA, bool ONE>
-__global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
-    const int4* __restrict__ work, const int* __restrict__ rel_cone_up, const int* __restrict__ child_lo_up,
-    const int* __restrict__ coords, const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c, LevelGeom gp,
-    LevelGeom gc, ChebTab ct, const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind, int R_,
-    cpx<T>* __restrict__ Fc_up, int* __restrict__ err) {
-  constexpr int P = PS * PA * PA;
-  constexpr int BS = PropShape<P>::BS;
-  const int R = ONE ? 1 : R_;
-  constexpr int NN = PropShape<P>::CH * P;
-  constexpr int HB = NN <= 256 ? 8 : (NN <= 512 ? 9 : (NN <= 1024 ? 10 : 11));   // 2^HB >= NN
-  constexpr int HT = 1 << HB;
+template <typename T, int PS, int PA> struct PropSmem {
+  static constexpr int P = PS * PA * PA;
+  static constexpr int BS = PropShape<P>::BS;
+  static constexpr int NN = PropShape<P>::CH * P;
+  static constexpr int HB = NN <= 256 ? 8 : (NN <= 512 ? 9 : (NN <= 1024 ? 10 : 11));   // 2^HB >= NN
+  static constexpr int HT = 1 << HB;
   static_assert(HT >= NN, "the hash table must be able to hold every node");
-  __shared__ cpx<T> acc[NN], tmp[NN];
-  __shared__ T st[NN][3];            // local coordinates in the child cone
-  __shared__ int skey[NN];
-  __shared__ short sord[NN];
-  __shared__ int hkey[HT], hoff[HT];
-  __shared__ int wsum[BS / 64];
-  __shared__ T ms[PS * PS], ma[PA * PA];
-  __shared__ __align__(16) T cbuf[BS / 64][2 * P];
+  cpx<T> acc[NN], tmp[NN];
+  T st[NN][3];            // local coordinates in the child cone
+  int skey[NN];
+  short sord[NN];
+  int hkey[HT], hoff[HT];
+  int wsum[BS / 64];
+  T ms[PS * PS], ma[PA * PA];
+  __align__(16) T cbuf[BS / 64][2 * P];
+};
 
-  const int4 wk = work[xcd_block(blockIdx.x, gridDim.x)];
+// One work item wk = (parent box, first slot, end slot) of the upward pass,
+// right-hand side r, by a block of PropShape::BS threads.  ONE: a single
+// right-hand side (R = 1 at compile time, contiguous cones).
+template <typename T, int PS, int PA, bool ONE>
+__device__ __forceinline__ void prop_item(PropSmem<T, PS, PA>& sm, int4 wk, int r, const int* __restrict__ rel_cone_up,
+                                          const int* __restrict__ child_lo_up, const int* __restrict__ coords,
+                                          const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c,
+                                          const LevelGeom& gp, const LevelGeom& gc, const ChebTab& ct,
+                                          const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind,
+                                          int R_, cpx<T>* __restrict__ Fc_up, int* __restrict__ err) {
+  using S = PropSmem<T, PS, PA>;
+  constexpr int P = S::P;
+  constexpr int BS = S::BS;
+  constexpr int NN = S::NN;
+  constexpr int HB = S::HB;
+  constexpr int HT = S::HT;
+  const int R = ONE ? 1 : R_;
+  auto& acc = sm.acc;
+  auto& tmp = sm.tmp;
+  auto& st = sm.st;
+  auto& skey = sm.skey;
+  auto& sord = sm.sord;
+  auto& hkey = sm.hkey;
+  auto& hoff = sm.hoff;
+  auto& wsum = sm.wsum;
+  auto& ms = sm.ms;
+  auto& ma = sm.ma;
+  auto& cbuf = sm.cbuf;
   const int Pb = wk.x, s0 = wk.y, ncn = wk.z - wk.y;
   const int nn = ncn * P;
-  const int r = ONE ? 0 : blockIdx.y;
   if (threadIdx.x < PS * PS) ms[threadIdx.x] = Ms[threadIdx.x];
   if (threadIdx.x < PA * PA) ma[threadIdx.x] = Ma[threadIdx.x];
   for (int q = threadIdx.x; q < nn; q += BS) acc[q] = {0, 0};
@@ -707,33 +776,44 @@ __global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
   lds_coeffs_store<T, PS, PA, BS>(acc, tmp, ncn, ms, ma, Fc_up + (int64_t)s0 * P * R, R, r);
 }
 
+template <typename T, int PS, int PA, bool ONE>
+__global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
+    const int4* __restrict__ work, const int* __restrict__ rel_cone_up, const int* __restrict__ child_lo_up,
+    const int* __restrict__ coords, const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c, LevelGeom gp,
+    LevelGeom gc, ChebTab ct, const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind, int R,
+    cpx<T>* __restrict__ Fc_up, int* __restrict__ err) {
+  __shared__ PropSmem<T, PS, PA> sm;
+  prop_item<T, PS, PA, ONE>(sm, work[xcd_block(blockIdx.x, gridDim.x)], ONE ? 0 : blockIdx.y, rel_cone_up,
+                            child_lo_up, coords, slot_c, Fc_c, gp, gc, ct, Ms, Ma, k, kind, R, Fc_up, err);
+}
+
 // ---------------------------------------------------------------------------
 // cousin targets for a range of levels + near-field sum, scattered to the
 // caller's order.
 // ---------------------------------------------------------------------------
 template <typename T> struct TLevel {
-  const int* pbox;
-  const int* cou_off;
-  const int* cou;
-  const double* centre;
-  const int* slot;
-  const cpx<T>* Fc;
+  const int IFGF_GAS* pbox;
+  const int IFGF_GAS* cou_off;
+  const int IFGF_GAS* cou;
+  const double IFGF_GAS* centre;
+  const int IFGF_GAS* slot;
+  const cpx<T> IFGF_GAS* Fc;
   LevelGeom g;
 };
 template <typename T> struct TLevels {
   TLevel<T> lv[IFGF_MAX_LEVELS];
 };
 
+// Cousin targets of point i0 (Morton order) for levels dlo..dhi, right-hand
+// side r, plus its near-field value; scattered to the caller's order.  Every
+// lane of the wave calls it (i0 >= n: no point); wbuf is the wave's staging
+// buffer of 2P values.
 template <typename T, int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts, int64_t n, const int* __restrict__ perm,
-                                                 const cpx<T>* __restrict__ uacc, int use_near, TLevels<T> L,
-                                                 int dlo, int dhi, double k, int kind, int R, int dtype, int conj_out,
-                                                 const double* __restrict__ wout, void* __restrict__ u,
-                                                 int* __restrict__ err) {
-  constexpr int P = PS * PA * PA;
-  __shared__ __align__(16) T cbuf[TPB / 64][2 * P];
-  const int r = blockIdx.y;
-  const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+__device__ __forceinline__ void target_point(T* wbuf, int64_t i0, int r, const double* __restrict__ pts, int64_t n,
+                                             const int* __restrict__ perm, const cpx<T>* __restrict__ uacc,
+                                             int use_near, const TLevels<T>& L, int dlo, int dhi, double k, int kind,
+                                             int R, int dtype, int conj_out, const double* __restrict__ wout,
+                                             void* __restrict__ u, int* __restrict__ err) {
   const bool valid = i0 < n;
   const int64_t i = valid ? i0 : n - 1;      // lanes past the end follow the last point and store nothing
   const double* x = pts + 3 * i;
@@ -763,7 +843,7 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
       if (cnt > 0) {
         int cid;
         if constexpr (Prec<T>::f32) {
-          LocF loc = target_loc32(x, lv.centre + 3 * B, lv.g, &rr);
+          LocF loc = target_loc32(x, gen(lv.centre) + 3 * B, lv.g, &rr);
           cid = loc.cid;
           ts = loc.ts;
           tt = loc.tt;
@@ -774,7 +854,7 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
           e_re = g * c;
           e_im = g * s;
         } else {
-          Loc loc = target_loc64(x, lv.centre + 3 * B, lv.g, &rr);
+          Loc loc = target_loc64(x, gen(lv.centre) + 3 * B, lv.g, &rr);
           cid = loc.cid;
           ts = loc.ts;
           tt = loc.tt;
@@ -793,7 +873,7 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
         if (sl < 0 && has) atomicOr(err, 4);
       }
       if (!has) sl = -1;
-      cpx<T> v = eval_uniform<T, PS, PA>(lv.Fc, sl, R, r, ts, tt, tp, cbuf[threadIdx.x >> 6]);
+      cpx<T> v = eval_uniform<T, PS, PA>(gen(lv.Fc), sl, R, r, ts, tt, tp, wbuf);
       if (has) {
         lacc.re += e_re * v.re - e_im * v.im;
         lacc.im += e_re * v.im + e_im * v.re;
@@ -816,6 +896,19 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
     ((float*)u)[2 * o] = (float)acc_re;
     ((float*)u)[2 * o + 1] = (float)acc_im;
   }
+}
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts, int64_t n, const int* __restrict__ perm,
+                                                 const cpx<T>* __restrict__ uacc, int use_near, TLevels<T> L,
+                                                 int dlo, int dhi, double k, int kind, int R, int dtype, int conj_out,
+                                                 const double* __restrict__ wout, void* __restrict__ u,
+                                                 int* __restrict__ err) {
+  constexpr int P = PS * PA * PA;
+  __shared__ __align__(16) T cbuf[TPB / 64][2 * P];
+  const int64_t i0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
+  target_point<T, PS, PA>(cbuf[threadIdx.x >> 6], i0, blockIdx.y, pts, n, perm, uacc, use_near, L, dlo, dhi, k, kind,
+                          R, dtype, conj_out, wout, u, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -958,7 +1051,7 @@ __global__ __launch_bounds__(TPB) void k_targets_mfma(const double* __restrict__
       int sl = -1;
       if (cnt > 0) {
         double rr;
-        LocF loc = target_loc32(x, lv.centre + 3 * B, lv.g, &rr);
+        LocF loc = target_loc32(x, gen(lv.centre) + 3 * B, lv.g, &rr);
         ts = loc.ts;
         tt = loc.tt;
         tp = loc.tp;
@@ -978,7 +1071,7 @@ __global__ __launch_bounds__(TPB) void k_targets_mfma(const double* __restrict__
         sl = -1;
         e_re = e_im = 0;
       }
-      wave_eval_mfma<PS, PA>(lv.Fc, R, g, sl, ts, tt, tp, e_re, e_im, rec[threadIdx.x >> 6], tot);
+      wave_eval_mfma<PS, PA>(gen(lv.Fc), R, g, sl, ts, tt, tp, e_re, e_im, rec[threadIdx.x >> 6], tot);
     }
   }
   // lane l holds RHS 8 rt + 2 (l >> 4) + p of target 16 b + (l & 15) of its wave
@@ -1519,8 +1612,9 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   TLevels<T> L{};
   for (int d = 3; d <= D; ++d) {
     LevelPlan& lv = p->lev[d];
-    L.lv[d] = {lv.pbox.as<int>(), lv.cou_off.as<int>(), lv.cou.as<int>(), lv.centre.as<double>(),
-               lv.slot.as<int>(), lv.Fc.as<cpx<T>>(), lv.geom};
+    L.lv[d] = {gas(lv.pbox.as<const int>()), gas(lv.cou_off.as<const int>()), gas(lv.cou.as<const int>()),
+               gas(lv.centre.as<const double>()), gas(lv.slot.as<const int>()), gas(lv.Fc.as<const cpx<T>>()),
+               lv.geom};
   }
   int dlo = 3, dhi = D;
   if (!(stage_mask & 2)) {
@@ -1630,6 +1724,358 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
   HIPCHK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Ragged batch: several plans (geometries) in one persistent launch.
+//
+// The whole apply of every geometry is cut into work items - gather chunks,
+// near-field boxes, leaf boxes, coefficient chunks of the finest level,
+// upward-pass items per level, target chunks - and laid out in one queue in
+// an order that respects the data flow (gather < leaf, near < coefficients <
+// upward pass d = D..4 < targets, per geometry; geometries interleaved within
+// each phase).  A queue segment is a run of items of one kind, geometry and
+// level; it names up to two (counter, count) pairs it needs and the counter
+// its items increment.  Work-groups take items in queue order from one
+// atomic head and wait, before an item, until its counters reach their
+// counts.  Every counter an item waits on is incremented only by items of
+// earlier segments, which running work-groups already hold, so the lowest
+// unfinished item can always proceed: no cycle is possible, whatever the
+// number of resident work-groups.  The wait is bounded (spin_limit polls);
+// past the bound the item proceeds and the batch error flag is raised.
+//
+// Memory ordering across work-groups (and XCDs, whose L2 caches are not
+// coherent with one another): after its item every wave issues an
+// agent-scope release fence (its stores written back) before the block's
+// counter increment; after a wait every wave issues an agent-scope acquire
+// fence (stale cache lines dropped) before it reads.
+// ---------------------------------------------------------------------------
+enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_COEF = 3, BT_PROP = 4, BT_TARGET = 5 };
+
+template <typename T> struct BLevel {
+  int nb, nrel;
+  const int IFGF_GAS* start;
+  const int IFGF_GAS* nbr_off;
+  const int IFGF_GAS* nbr;
+  const int IFGF_GAS* slot_off;
+  const int IFGF_GAS* rel_cone;
+  const int IFGF_GAS* child_lo;
+  const int IFGF_GAS* coords;
+  const int IFGF_GAS* slot;
+  const double IFGF_GAS* centre;
+  const int4 IFGF_GAS* work;
+  cpx<T> IFGF_GAS* Fn;
+  cpx<T> IFGF_GAS* Fc;
+  LevelGeom g;
+};
+
+template <typename T> struct BGeom {
+  int64_t n;
+  int D, kind;
+  double k, eta;
+  const double IFGF_GAS* pts;
+  const double IFGF_GAS* nrm;
+  const double IFGF_GAS* w;
+  const int IFGF_GAS* perm;
+  const T IFGF_GAS* Ms;
+  const T IFGF_GAS* Ma;
+  cpx<T> IFGF_GAS* a;
+  cpx<T> IFGF_GAS* uacc;
+  int IFGF_GAS* err;
+  ChebTab ct;
+  TLevels<T> tl;
+  BLevel<T> lv[IFGF_MAX_LEVELS];
+};
+
+// Per-apply input and output pointers, one pair per geometry.
+struct BIo {
+  const void* sigma[IFGF_BATCH_MAX];
+  void* u[IFGF_BATCH_MAX];
+};
+
+__device__ __forceinline__ void batch_wait(int* ctr, int dep, int need, int spin_limit, int* berr) {
+  if (dep < 0) return;
+  int polls = 0;
+  while (__hip_atomic_load(&ctr[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    if (polls++ >= spin_limit) {
+      atomicOr(berr, 1);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+}
+
+template <typename T, int PS, int PA> struct BatchSmem {
+  static constexpr int BS = PropShape<PS * PA * PA>::BS;
+  static constexpr size_t a = sizeof(PropSmem<T, PS, PA>), b = sizeof(NearSmem<T, 1, BS>), c = sizeof(LeafSmem<T, 1>);
+  static constexpr size_t bytes = a > b ? (a > c ? a : c) : (b > c ? b : c);
+};
+
+// One launch of `total` work-groups; each takes the next ticket of the queue
+// when it starts and processes that item.  A work-group holds its ticket only
+// while it runs, so every lower ticket belongs to a running or finished
+// work-group.  (A loop over several items per work-group would let the
+// compiler hoist every body's per-thread invariants out of the loop and keep
+// them all live at once, which costs far more registers than any one body.)
+// FP32: 3 waves per SIMD, as the standalone upward pass; FP64: 1 (its bodies need
+// more than the 256 registers a wave can address, the rest goes to AGPRs).
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(PropShape<PS * PA * PA>::BS)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const BSeg* __restrict__ segs, int nseg,
+                                                                          int total,
+                                                                          const BGeom<T>* __restrict__ geoms, BIo io,
+                                                                          int dtype, int* ctr, int spin_limit,
+                                                                          int* berr) {
+  constexpr int P = PS * PA * PA;
+  constexpr int BS = PropShape<P>::BS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item, s_seg;
+  if (threadIdx.x == 0) {
+    const int it = atomicAdd(&ctr[0], 1);
+    int sg = -1;
+    if (it < total) {
+      int lo = 0, hi = nseg - 1;   // last segment whose first item is <= it
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].first <= it) lo = mid;
+        else hi = mid - 1;
+      }
+      sg = lo;
+      batch_wait(ctr, segs[sg].dep0, segs[sg].need0, spin_limit, berr);
+      batch_wait(ctr, segs[sg].dep1, segs[sg].need1, spin_limit, berr);
+    }
+    s_item = it;
+    s_seg = sg;
+  }
+  __syncthreads();
+  // block-uniform; readfirstlane lets the compiler branch on them as such
+  const int it = __builtin_amdgcn_readfirstlane(s_item), sg = __builtin_amdgcn_readfirstlane(s_seg);
+  if (it >= total) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const BSeg S = segs[sg];
+  const BGeom<T>& G = geoms[S.geom];
+  const int local = it - S.first;
+  const int D = G.D;
+  switch (S.type) {
+    case BT_GATHER:
+      gather_one<T>((int64_t)local * BS + threadIdx.x, io.sigma[S.geom], dtype, 0, gen(G.perm), gen(G.w), G.n, 1,
+                    gen(G.a));
+      break;
+    case BT_NEAR: {
+      const BLevel<T>& L = G.lv[D];
+      near_box<T, false, 1, BS>(*reinterpret_cast<NearSmem<T, 1, BS>*>(smem), local, 0, gen(G.pts), gen(G.nrm),
+                                gen(G.a), 1, gen(L.start), gen(L.nbr_off), gen(L.nbr), gen(L.centre), G.k, G.eta,
+                                G.kind, gen(G.uacc));
+      break;
+    }
+    case BT_LEAF: {
+      const BLevel<T>& L = G.lv[D];
+      leaf_box<T, PS, PA, 1, BS>(*reinterpret_cast<LeafSmem<T, 1>*>(smem), local, 0, gen(G.pts), gen(G.nrm),
+                                 gen(G.a), 1, gen(L.start), gen(L.centre), gen(L.slot_off), gen(L.rel_cone), L.g,
+                                 G.ct, G.k, G.eta, G.kind, gen(L.Fn));
+      break;
+    }
+    case BT_COEF: {
+      // cones [c0, c0 + nc) of the finest level: node values -> coefficients
+      auto& sm = *reinterpret_cast<PropSmem<T, PS, PA>*>(smem);
+      const BLevel<T>& L = G.lv[D];
+      constexpr int CH = PropShape<P>::CH;
+      const int c0 = local * CH, nc = min(CH, L.nrel - c0);
+      if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = G.Ms[threadIdx.x];
+      if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = G.Ma[threadIdx.x];
+      for (int q = threadIdx.x; q < nc * P; q += BS) sm.acc[q] = gen(L.Fn)[(int64_t)c0 * P + q];
+      __syncthreads();
+      lds_coeffs_store<T, PS, PA, BS>(sm.acc, sm.tmp, nc, sm.ms, sm.ma, gen(L.Fc) + (int64_t)c0 * P, 1, 0);
+      break;
+    }
+    case BT_PROP: {
+      const int d = S.level;   // child level
+      const BLevel<T>& lc = G.lv[d];
+      const BLevel<T>& lp = G.lv[d - 1];
+      prop_item<T, PS, PA, true>(*reinterpret_cast<PropSmem<T, PS, PA>*>(smem), gen(lp.work)[local], 0, gen(lp.rel_cone),
+                                 gen(lp.child_lo), gen(lc.coords), gen(lc.slot), gen(lc.Fc), lp.g, lc.g, G.ct,
+                                 gen(G.Ms), gen(G.Ma), G.k, G.kind, 1, gen(lp.Fc), gen(G.err));
+      break;
+    }
+    case BT_TARGET: {
+      auto& sm = *reinterpret_cast<PropSmem<T, PS, PA>*>(smem);
+      const int dlo = D >= 3 ? 3 : 1, dhi = D >= 3 ? D : 0;
+      target_point<T, PS, PA>(sm.cbuf[threadIdx.x >> 6], (int64_t)local * BS + threadIdx.x, 0, gen(G.pts), G.n,
+                              gen(G.perm), gen(G.uacc), 1, G.tl, dlo, dhi, G.k, G.kind, 1, dtype, 0, nullptr,
+                              io.u[S.geom], gen(G.err));
+      break;
+    }
+    default:
+      break;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&ctr[S.done], 1);
+}
+
+__global__ __launch_bounds__(TPB) void k_zero_i32(int* __restrict__ x, int n) {
+  const int i = blockIdx.x * TPB + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
+template <typename T, int PS, int PA>
+void batch_prepare_impl(ifgf_batch_s* b) {
+  constexpr int P = PS * PA * PA;
+  constexpr int BS = PropShape<P>::BS;
+  constexpr int CH = PropShape<P>::CH;
+  const int ng = (int)b->plans.size();
+  std::vector<BGeom<T>> geo(ng);
+  for (int g = 0; g < ng; ++g) {
+    ifgf_plan_s* p = b->plans[g];
+    BGeom<T>& G = geo[g];
+    G = BGeom<T>{};
+    G.n = p->n;
+    G.D = p->D;
+    G.kind = p->opt.kernel;
+    G.k = p->k;
+    G.eta = p->eta;
+    G.pts = gas(p->pts.as<const double>());
+    G.nrm = gas(p->nrm.as<const double>());
+    G.w = gas(p->w.as<const double>());
+    G.perm = gas(p->perm.as<const int>());
+    G.Ms = gas((const T*)(Prec<T>::f32 ? p->Msf.p : p->Ms.p));
+    G.Ma = gas((const T*)(Prec<T>::f32 ? p->Maf.p : p->Ma.p));
+    G.a = gas(p->a.as<cpx<T>>());
+    G.uacc = gas(p->uacc.as<cpx<T>>());
+    G.err = gas(p->err.as<int>());
+    G.ct = p->cheb;
+    for (int d = 1; d <= p->D; ++d) {
+      const LevelPlan& l = p->lev[d];
+      BLevel<T>& L = G.lv[d];
+      L.nb = l.nb;
+      L.nrel = l.nrel;
+      L.start = gas(l.start.as<const int>());
+      L.nbr_off = gas(l.nbr_off.as<const int>());
+      L.nbr = gas(l.nbr.as<const int>());
+      L.slot_off = gas(l.slot_off.as<const int>());
+      L.rel_cone = gas(l.rel_cone.as<const int>());
+      L.child_lo = gas(l.child_lo.as<const int>());
+      L.coords = gas(l.coords.as<const int>());
+      L.slot = gas(l.slot.as<const int>());
+      L.centre = gas(l.centre.as<const double>());
+      L.work = gas(l.work.as<const int4>());
+      L.Fn = gas(l.Fn.as<cpx<T>>());
+      L.Fc = gas(l.Fc.as<cpx<T>>());
+      L.g = l.geom;
+      if (d >= 3)
+        G.tl.lv[d] = {gas(l.pbox.as<const int>()), gas(l.cou_off.as<const int>()), gas(l.cou.as<const int>()),
+                      gas(l.centre.as<const double>()), gas(l.slot.as<const int>()), gas(l.Fc.as<const cpx<T>>()),
+                      l.geom};
+    }
+  }
+
+  // ---- the queue ----------------------------------------------------------------
+  auto C = [](int g, int k) { return 1 + 16 * g + k; };   // counters: 0 = queue head, then 16 per geometry
+  enum { K_GATHER = 0, K_LEAF = 1, K_NEAR = 2, K_COEF = 3, K_PROP0 = 4, K_TARGET = 15 };   // K_PROP0 + d: into level d
+  std::vector<BSeg> segs;
+  int64_t first = 0;
+  auto emit = [&](int type, int g, int level, int64_t count, int dep0, int need0, int dep1, int need1, int done) {
+    if (count <= 0) return;
+    BSeg q{};
+    q.type = type;
+    q.geom = g;
+    q.level = level;
+    q.count = (int)count;
+    q.first = (int)first;
+    q.dep0 = need0 > 0 ? dep0 : -1;
+    q.need0 = need0;
+    q.dep1 = need1 > 0 ? dep1 : -1;
+    q.need1 = need1;
+    q.done = done;
+    segs.push_back(q);
+    first += count;
+    if (first > (int64_t)0x7fffffff) throw Error{IFGF_EUNSUPPORTED, "batch queue too long"};
+  };
+  std::vector<int64_t> ngat(ng), nnear(ng), nleaf(ng);
+  std::vector<std::pair<int, int>> last(ng, {-1, 0});   // producer of the newest coefficient level
+  for (int g = 0; g < ng; ++g) {
+    ngat[g] = (b->plans[g]->n + BS - 1) / BS;
+    emit(BT_GATHER, g, 0, ngat[g], -1, 0, -1, 0, C(g, K_GATHER));
+  }
+  for (int g = 0; g < ng; ++g) {
+    ifgf_plan_s* p = b->plans[g];
+    nleaf[g] = p->D >= 3 ? p->lev[p->D].nb : 0;
+    emit(BT_LEAF, g, p->D, nleaf[g], C(g, K_GATHER), (int)ngat[g], -1, 0, C(g, K_LEAF));
+  }
+  for (int g = 0; g < ng; ++g) {
+    ifgf_plan_s* p = b->plans[g];
+    nnear[g] = p->lev[p->D].nb;
+    emit(BT_NEAR, g, p->D, nnear[g], C(g, K_GATHER), (int)ngat[g], -1, 0, C(g, K_NEAR));
+  }
+  for (int g = 0; g < ng; ++g) {
+    ifgf_plan_s* p = b->plans[g];
+    if (p->D < 3) continue;
+    const int64_t cnt = (p->lev[p->D].nrel + CH - 1) / CH;
+    emit(BT_COEF, g, p->D, cnt, C(g, K_LEAF), (int)nleaf[g], -1, 0, C(g, K_COEF));
+    if (cnt > 0) last[g] = {C(g, K_COEF), (int)cnt};
+  }
+  int maxD = 0;
+  for (auto* p : b->plans) maxD = std::max(maxD, p->D);
+  for (int j = 0; j + 4 <= maxD; ++j) {
+    for (int g = 0; g < ng; ++g) {
+      ifgf_plan_s* p = b->plans[g];
+      const int d = p->D - j;   // child level
+      if (d < 4) continue;
+      const LevelPlan& lp = p->lev[d - 1];
+      if (lp.nrel == 0 || lp.nwork == 0) continue;
+      emit(BT_PROP, g, d, lp.nwork, last[g].first, last[g].second, -1, 0, C(g, K_PROP0 + d - 1));
+      last[g] = {C(g, K_PROP0 + d - 1), (int)lp.nwork};
+    }
+  }
+  for (int g = 0; g < ng; ++g)
+    emit(BT_TARGET, g, 0, ngat[g], C(g, K_NEAR), (int)nnear[g], last[g].first, last[g].second, C(g, K_TARGET));
+
+  // Every counter a segment waits on must be complete-able by earlier segments
+  // alone, with exactly the awaited number of items.
+  for (size_t i = 0; i < segs.size(); ++i) {
+    for (int w = 0; w < 2; ++w) {
+      const int dep = w ? segs[i].dep1 : segs[i].dep0, need = w ? segs[i].need1 : segs[i].need0;
+      if (dep < 0) continue;
+      int64_t before = 0, after = 0;
+      for (size_t j = 0; j < segs.size(); ++j)
+        if (segs[j].done == dep) (j < i ? before : after) += segs[j].count;
+      if (before != need || after != 0) throw Error{IFGF_EUNSUPPORTED, "internal error: batch queue order"};
+    }
+  }
+
+  b->nseg = (int)segs.size();
+  b->total = (int)first;
+  b->nctr = 1 + 16 * ng;
+  b->segs.alloc(sizeof(BSeg) * std::max<size_t>(1, segs.size()));
+  if (!segs.empty()) HIPCHK(hipMemcpy(b->segs.p, segs.data(), sizeof(BSeg) * segs.size(), hipMemcpyHostToDevice));
+  b->geoms.alloc(sizeof(BGeom<T>) * ng);
+  HIPCHK(hipMemcpy(b->geoms.p, geo.data(), sizeof(BGeom<T>) * ng, hipMemcpyHostToDevice));
+  b->ctr.alloc(sizeof(int) * b->nctr);
+  b->err.alloc(sizeof(int) * 4);
+  HIPCHK(hipMemset(b->err.p, 0, sizeof(int) * 4));
+  b->smem = BatchSmem<T, PS, PA>::bytes;
+  int per_cu = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch<T, PS, PA>, BS, b->smem));
+  if (per_cu < 1) throw Error{IFGF_EUNSUPPORTED, "batch kernel does not fit on a compute unit"};
+  b->grid = b->total;
+  b->block = BS;
+}
+
+template <typename T, int PS, int PA>
+void batch_apply_impl(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, hipStream_t s) {
+  BIo io{};
+  const int ng = (int)b->plans.size();
+  for (int g = 0; g < ng; ++g) {
+    io.sigma[g] = sigma[g];
+    io.u[g] = u[g];
+  }
+  k_zero_i32<<<nblocks(b->nctr), TPB, 0, s>>>(b->ctr.as<int>(), b->nctr);
+  HIPCHK(hipGetLastError());
+  if (b->total == 0) return;
+  k_batch<T, PS, PA><<<b->grid, b->block, b->smem, s>>>(b->segs.as<BSeg>(), b->nseg, b->total,
+                                                        b->geoms.as<BGeom<T>>(), io, dtype, b->ctr.as<int>(),
+                                                        b->spin_limit, b->err.as<int>());
+  HIPCHK(hipGetLastError());
+}
+
 template <typename T>
 void dispatch_adjoint(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, int conj, hipStream_t s) {
   int ps = p->opt.p_s, pa = p->opt.p_ang;
@@ -1671,6 +2117,26 @@ void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, 
     dispatch_adjoint<float>(p, v, out, nrhs, dtype, conj, s);
   else
     dispatch_adjoint<double>(p, v, out, nrhs, dtype, conj, s);
+}
+
+void run_batch_prepare(ifgf_batch_s* b) {
+  ifgf_plan_s* p = b->plans[0];
+  const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+  if (ps == 3 && pa == 5) return f32 ? batch_prepare_impl<float, 3, 5>(b) : batch_prepare_impl<double, 3, 5>(b);
+  if (ps == 4 && pa == 6) return f32 ? batch_prepare_impl<float, 4, 6>(b) : batch_prepare_impl<double, 4, 6>(b);
+  throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
+}
+
+void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, hipStream_t s) {
+  ifgf_plan_s* p = b->plans[0];
+  const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+  if (ps == 3 && pa == 5)
+    return f32 ? batch_apply_impl<float, 3, 5>(b, sigma, u, dtype, s) : batch_apply_impl<double, 3, 5>(b, sigma, u, dtype, s);
+  if (ps == 4 && pa == 6)
+    return f32 ? batch_apply_impl<float, 4, 6>(b, sigma, u, dtype, s) : batch_apply_impl<double, 4, 6>(b, sigma, u, dtype, s);
+  throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
 }
 
 }  // namespace ifgf

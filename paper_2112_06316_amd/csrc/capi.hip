@@ -5,6 +5,8 @@
 #include <cstring>
 #include <new>
 
+#include <memory>
+
 #include "internal.h"
 
 namespace ifgf {
@@ -81,14 +83,14 @@ template <typename F> static ifgf_status guarded(F&& f) {
 }
 
 struct BusyGuard {
-  ifgf_plan_s* p;
+  std::atomic<int>* busy;
   bool ok;
-  explicit BusyGuard(ifgf_plan_s* pp) : p(pp) {
+  template <typename H> explicit BusyGuard(H* h) : busy(&h->busy) {
     int expect = 0;
-    ok = p->busy.compare_exchange_strong(expect, 1);
+    ok = busy->compare_exchange_strong(expect, 1);
   }
   ~BusyGuard() {
-    if (ok) p->busy.store(0);
+    if (ok) busy->store(0);
   }
 };
 
@@ -319,6 +321,90 @@ void ifgf_plan_destroy(ifgf_plan p) {
   (void)hipDeviceSynchronize();
   free_events(p);
   delete p;
+}
+
+ifgf_status ifgf_batch_create(ifgf_batch* out, int32_t nplans, const ifgf_plan* plans) {
+  if (out) *out = nullptr;
+  std::unique_ptr<ifgf_batch_s> b;
+  ifgf_status st = guarded([&] {
+    if (!out || !plans) throw Error{IFGF_EINVAL, "null pointer argument"};
+    if (nplans < 1 || nplans > IFGF_BATCH_MAX) throw Error{IFGF_EINVAL, "nplans out of range (1..IFGF_BATCH_MAX)"};
+    b.reset(new ifgf_batch_s);
+    for (int g = 0; g < nplans; ++g) {
+      ifgf_plan_s* p = plans[g];
+      if (!p) throw Error{IFGF_EINVAL, "null plan in batch"};
+      for (auto* q : b->plans)
+        if (q == p) throw Error{IFGF_EINVAL, "a plan appears twice in the batch"};
+      const ifgf_plan_s* p0 = plans[0];
+      if (p->opt.precision != p0->opt.precision || p->opt.p_s != p0->opt.p_s || p->opt.p_ang != p0->opt.p_ang)
+        throw Error{IFGF_EINVAL, "batch plans must share precision, p_s and p_ang"};
+      b->plans.push_back(p);
+    }
+    HIPCHK(hipDeviceSynchronize());
+    run_batch_prepare(b.get());
+    HIPCHK(hipDeviceSynchronize());
+  });
+  if (st == IFGF_OK) *out = b.release();
+  return st;
+}
+
+ifgf_status ifgf_batch_apply(ifgf_batch b, const void* const* sigma, void* const* u, int32_t dtype, void* stream) {
+  return guarded([&] {
+    if (!b || !sigma || !u) throw Error{IFGF_EINVAL, "null pointer argument"};
+    if (dtype != IFGF_C64 && dtype != IFGF_C128) throw Error{IFGF_EINVAL, "bad dtype"};
+    const int ng = (int)b->plans.size();
+    for (int g = 0; g < ng; ++g) {
+      if (!sigma[g] || !u[g]) throw Error{IFGF_EINVAL, "null sigma or u pointer"};
+      for (int h = 0; h < ng; ++h)
+        if ((const void*)u[g] == sigma[h]) throw Error{IFGF_EINVAL, "an output aliases an input"};
+    }
+    BusyGuard gb(b);
+    if (!gb.ok) throw Error{IFGF_EBUSY, "another apply of this batch is being enqueued"};
+    std::vector<std::unique_ptr<BusyGuard>> guards;
+    for (auto* p : b->plans) {
+      guards.emplace_back(new BusyGuard(p));
+      if (!guards.back()->ok) throw Error{IFGF_EBUSY, "an apply on a plan of the batch is being enqueued"};
+    }
+    run_batch_apply(b, sigma, u, dtype, (hipStream_t)stream);
+    for (auto* p : b->plans) p->last_rhs = 1;
+  });
+}
+
+ifgf_status ifgf_batch_check(ifgf_batch b, int32_t* flags) {
+  return guarded([&] {
+    if (!b || !flags) throw Error{IFGF_EINVAL, "null pointer argument"};
+    int f = 0;
+    HIPCHK(hipMemcpy(&f, b->err.p, sizeof(int), hipMemcpyDeviceToHost));
+    for (auto* p : b->plans) {
+      int pf = 0;
+      HIPCHK(hipMemcpy(&pf, p->err.p, sizeof(int), hipMemcpyDeviceToHost));
+      f |= pf;
+    }
+    *flags = f;
+  });
+}
+
+ifgf_status ifgf_batch_set_spin_limit(ifgf_batch b, int32_t limit) {
+  return guarded([&] {
+    if (!b || limit < 0) throw Error{IFGF_EINVAL, "bad batch or limit"};
+    b->spin_limit = limit;
+  });
+}
+
+ifgf_status ifgf_batch_get_info(ifgf_batch b, int64_t* items, int32_t* segments, int32_t* grid, int32_t* block) {
+  return guarded([&] {
+    if (!b) throw Error{IFGF_EINVAL, "null batch"};
+    if (items) *items = b->total;
+    if (segments) *segments = b->nseg;
+    if (grid) *grid = b->grid;
+    if (block) *block = b->block;
+  });
+}
+
+void ifgf_batch_destroy(ifgf_batch b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  delete b;
 }
 
 }  // extern "C"

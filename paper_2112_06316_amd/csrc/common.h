@@ -358,6 +358,14 @@ __host__ __device__ __forceinline__ void morton_decode(uint32_t key, int* x, int
   *z = (int)compact3(key >> 2);
 }
 
+// Pointers to global memory held in device-side structs.  A pointer loaded
+// from memory is otherwise of unknown address space, and its accesses become
+// flat instructions (64-bit VGPR addresses, waits shared with LDS); typed
+// global pointers keep global instructions with scalar bases.
+#define IFGF_GAS __attribute__((address_space(1)))
+template <typename T> __host__ __device__ inline T IFGF_GAS* gas(T* p) { return (T IFGF_GAS*)p; }
+template <typename T> __device__ __forceinline__ T* gen(T IFGF_GAS* p) { return (T*)p; }
+
 // Wave-level helpers (wave64).
 __device__ __forceinline__ int first_lane(uint64_t mask) { return __ffsll((unsigned long long)mask) - 1; }
 

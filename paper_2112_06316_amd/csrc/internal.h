@@ -96,6 +96,33 @@ struct ifgf_plan_s {
 
 namespace ifgf {
 
+// One segment of the batch work queue: items [first, first + count) of one
+// kind, geometry and level.  Before an item, wait until ctr[dep0] >= need0 and
+// ctr[dep1] >= need1 (dep < 0: none); after it, increment ctr[done].
+struct BSeg {
+  int type, geom, level, count;
+  int first;
+  int dep0, need0, dep1, need1;
+  int done;
+};
+
+}  // namespace ifgf
+
+struct ifgf_batch_s {
+  std::vector<ifgf_plan_s*> plans;   // not owned
+  ifgf::DevBuf segs;                 // BSeg [nseg]
+  ifgf::DevBuf geoms;                // per-geometry device descriptors
+  ifgf::DevBuf ctr;                  // int [nctr]: queue head, then 16 completion counters per geometry
+  ifgf::DevBuf err;                  // int [4]: bit 0 = a dependency wait hit the poll limit
+  int nseg = 0, total = 0, nctr = 0;
+  int grid = 0, block = 0;
+  size_t smem = 0;
+  int spin_limit = 1 << 22;
+  std::atomic<int> busy{0};
+};
+
+namespace ifgf {
+
 // primitives.hip
 void scan_exclusive_u8(const uint8_t* in, int* out, int64_t n, hipStream_t s);   // out[n] = total
 void scan_exclusive_i32(const int* in, int* out, int64_t n, hipStream_t s);      // out[n] = total
@@ -109,6 +136,9 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask,
                int level_lo, int level_hi, hipStream_t s);
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
+
+void run_batch_prepare(ifgf_batch_s* b);
+void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, hipStream_t s);
 
 bool supported_order(int ps, int pa);
 int prop_chunk(int P);

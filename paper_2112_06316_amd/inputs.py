@@ -148,3 +148,24 @@ def build_surface(w: dict):
     if w["kind"] == "spheroid":
         return ellipsoid(w["n"], (1.0, 1.0, 5.0))
     raise KeyError(w["kind"])
+
+
+RAGGED_N = (32, 48, 64, 80, 96, 112, 128, 128)
+
+
+def ragged_batch(sizes=RAGGED_N):
+    """Ragged multi-geometry batch: geometry b has 6 x n_b^2 points; even b a
+    sphere of radius 0.5, odd b an ellipsoid with semi-axes (0.5, 0.375,
+    0.25).  Both have largest diameter 1, and k_b = 2 pi (n_b / 8), so the
+    diameter is n_b / 8 wavelengths (about 10 points per wavelength, as the
+    16-wavelength sphere); eta_b = k_b.  Returns a list of dicts with keys
+    points, normals, weights, k, eta, n, seed."""
+    out = []
+    for b, nb in enumerate(sizes):
+        if b % 2 == 0:
+            p, nr, w = cubed_sphere(nb, 0.5)
+        else:
+            p, nr, w = ellipsoid(nb, (0.5, 0.375, 0.25))
+        k = 2.0 * np.pi * nb / 8.0
+        out.append(dict(points=p, normals=nr, weights=w, k=k, eta=k, n=len(p), seed=config_seed(3) + 1000 + b))
+    return out
