@@ -104,6 +104,7 @@ def main():
     ap.add_argument("--batched-rhs", type=int, default=64, help="RHS of the batched leg (0 = skip)")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--adjoint-steps", type=int, default=5)
+    ap.add_argument("--ragged-steps", type=int, default=5, help="applies of the ragged 8-geometry batch (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the FP32 leg, copy a buffer of this many MiB three times with a plain device copy "
                          "(the reference point that scales HBM byte counters)")
@@ -308,6 +309,58 @@ def main():
         }
         del planb, Ub, Sb_d
 
+    # ---- ragged batch: 8 geometries in one launch vs 8 separate applies ----------
+    ragged = None
+    if args.ragged_steps > 0:
+        from paper_2112_06316_amd import Batch
+        geoms = inputs.ragged_batch()
+        plans_r = [Plan(g["points"], g["normals"], g["weights"], g["k"], g["eta"], precision="fp32",
+                        leaf_h_lambda=0.5, **dict(opts, depth=0)) for g in geoms]
+        sig_r = [torch.from_numpy(inputs.random_density(g["n"], seed=g["seed"]).astype(np.complex64)).to(dev)
+                 for g in geoms]
+        out_r = [torch.empty_like(x) for x in sig_r]
+        bat = Batch(plans_r)
+        stream = torch.cuda.current_stream(dev)
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        def separate():
+            for pl, x, o in zip(plans_r, sig_r, out_r):
+                pl.apply(x, out=o[:, None])
+
+        ms_sep = timed(separate, args.ragged_steps)
+        ms_bat = timed(lambda: bat.apply(sig_r, outs=out_r), args.ragged_steps)
+        log(f"ragged: batch {ms_bat:.3f} ms, separate {ms_sep:.3f} ms")
+        errs = None
+        if not args.no_cpu_baseline:
+            from oracle import direct
+            errs = []
+            for g, geo in enumerate(geoms):
+                tgr = inputs.sample_targets(geo["n"], 256, seed=geo["seed"] + 100)
+                sg = inputs.random_density(geo["n"], seed=geo["seed"])
+                ref = direct.apply_c(geo["points"], geo["normals"], geo["weights"], geo["k"], geo["eta"], sg,
+                                     targets=tgr)
+                errs.append(float(np.linalg.norm(out_r[g].cpu().numpy()[tgr] - ref) / np.linalg.norm(ref)))
+        ragged = {
+            "workload": ("8 geometries, 6 x n_b^2 points, n_b = 32..128 (N = 6,144..98,304, 410,112 in all); "
+                         "spheres (even b) and ellipsoids (0.5, 0.375, 0.25) (odd b); n_b/8 wavelengths across; "
+                         "FP32, one density each"),
+            "N": [g["n"] for g in geoms], "depth": [pl.stats()["depth"] for pl in plans_r],
+            "ms_batch_one_launch": ms_bat, "ms_separate_applies": ms_sep, "speedup": ms_sep / ms_bat,
+            "queue": bat.info(), "rel_err": errs, "rel_err_targets_per_geometry": 256,
+            "consistency_flags": bat.check(),
+        }
+        del bat, plans_r, sig_r, out_r
+
     ms_per_step = r32["wall"] * 1e3 / args.steps
     out = {
         "metric": METRIC,
@@ -342,6 +395,7 @@ def main():
     }
     out["adjoint"] = adj
     out["batched"] = batched
+    out["ragged"] = ragged
     if r64 is not None:
         out["fp64"] = {"ms_per_step": r64["wall"] * 1e3 / args.fp64_steps, "rel_err": err64,
                        "plan_create_s": r64["t_plan"], "consistency_flags": r64["flags"]}

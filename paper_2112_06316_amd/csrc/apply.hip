@@ -1749,9 +1749,14 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
 // fence (stale cache lines dropped) before it reads.
 // ---------------------------------------------------------------------------
 enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_COEF = 3, BT_PROP = 4, BT_TARGET = 5 };
+// Work units per queue item (fewer items, fewer counter updates and fences):
+// gather chunks of BS points, leaf and near-field boxes, upward-pass work
+// items, groups of PropShape::CH cones of the coefficient transform; target
+// items hold BS points.
+constexpr int BG_GATHER = 4, BG_BOX = 4, BG_PROP = 8, BG_COEF = 8;
 
 template <typename T> struct BLevel {
-  int nb, nrel;
+  int nb, nrel, nwork;
   const int IFGF_GAS* start;
   const int IFGF_GAS* nbr_off;
   const int IFGF_GAS* nbr;
@@ -1819,8 +1824,8 @@ template <typename T, int PS, int PA> struct BatchSmem {
 // more than the 256 registers a wave can address, the rest goes to AGPRs).
 template <typename T, int PS, int PA>
 __global__ __launch_bounds__(PropShape<PS * PA * PA>::BS)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const BSeg* __restrict__ segs, int nseg,
-                                                                          int total,
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const BSeg* __restrict__ segs,
+                                                                          const int* __restrict__ seg_of, int total,
                                                                           const BGeom<T>* __restrict__ geoms, BIo io,
                                                                           int dtype, int* ctr, int spin_limit,
                                                                           int* berr) {
@@ -1832,16 +1837,14 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
     const int it = atomicAdd(&ctr[0], 1);
     int sg = -1;
     if (it < total) {
-      int lo = 0, hi = nseg - 1;   // last segment whose first item is <= it
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (segs[mid].first <= it) lo = mid;
-        else hi = mid - 1;
-      }
-      sg = lo;
+      sg = seg_of[it];
       batch_wait(ctr, segs[sg].dep0, segs[sg].need0, spin_limit, berr);
       batch_wait(ctr, segs[sg].dep1, segs[sg].need1, spin_limit, berr);
     }
+    // one agent-scope acquire per item that consumes other work-groups'
+    // results: the L1/L2 lines it drops are dropped for every wave of the
+    // work-group
+    if (sg >= 0 && (segs[sg].dep0 >= 0 || segs[sg].dep1 >= 0)) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     s_item = it;
     s_seg = sg;
   }
@@ -1849,50 +1852,66 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
   // block-uniform; readfirstlane lets the compiler branch on them as such
   const int it = __builtin_amdgcn_readfirstlane(s_item), sg = __builtin_amdgcn_readfirstlane(s_seg);
   if (it >= total) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const BSeg S = segs[sg];
   const BGeom<T>& G = geoms[S.geom];
   const int local = it - S.first;
   const int D = G.D;
   switch (S.type) {
     case BT_GATHER:
-      gather_one<T>((int64_t)local * BS + threadIdx.x, io.sigma[S.geom], dtype, 0, gen(G.perm), gen(G.w), G.n, 1,
-                    gen(G.a));
+      for (int u = 0; u < BG_GATHER; ++u)
+        gather_one<T>(((int64_t)local * BG_GATHER + u) * BS + threadIdx.x, io.sigma[S.geom], dtype, 0, gen(G.perm),
+                      gen(G.w), G.n, 1, gen(G.a));
       break;
     case BT_NEAR: {
       const BLevel<T>& L = G.lv[D];
-      near_box<T, false, 1, BS>(*reinterpret_cast<NearSmem<T, 1, BS>*>(smem), local, 0, gen(G.pts), gen(G.nrm),
-                                gen(G.a), 1, gen(L.start), gen(L.nbr_off), gen(L.nbr), gen(L.centre), G.k, G.eta,
-                                G.kind, gen(G.uacc));
+      const int b1 = min((local + 1) * BG_BOX, L.nb);
+      for (int bx = local * BG_BOX; bx < b1; ++bx) {
+        if (bx > local * BG_BOX) __syncthreads();   // LDS reuse
+        near_box<T, false, 1, BS>(*reinterpret_cast<NearSmem<T, 1, BS>*>(smem), bx, 0, gen(G.pts), gen(G.nrm),
+                                  gen(G.a), 1, gen(L.start), gen(L.nbr_off), gen(L.nbr), gen(L.centre), G.k, G.eta,
+                                  G.kind, gen(G.uacc));
+      }
       break;
     }
     case BT_LEAF: {
       const BLevel<T>& L = G.lv[D];
-      leaf_box<T, PS, PA, 1, BS>(*reinterpret_cast<LeafSmem<T, 1>*>(smem), local, 0, gen(G.pts), gen(G.nrm),
-                                 gen(G.a), 1, gen(L.start), gen(L.centre), gen(L.slot_off), gen(L.rel_cone), L.g,
-                                 G.ct, G.k, G.eta, G.kind, gen(L.Fn));
+      const int b1 = min((local + 1) * BG_BOX, L.nb);
+      for (int bx = local * BG_BOX; bx < b1; ++bx) {
+        if (bx > local * BG_BOX) __syncthreads();   // LDS reuse
+        leaf_box<T, PS, PA, 1, BS>(*reinterpret_cast<LeafSmem<T, 1>*>(smem), bx, 0, gen(G.pts), gen(G.nrm),
+                                   gen(G.a), 1, gen(L.start), gen(L.centre), gen(L.slot_off), gen(L.rel_cone), L.g,
+                                   G.ct, G.k, G.eta, G.kind, gen(L.Fn));
+      }
       break;
     }
     case BT_COEF: {
-      // cones [c0, c0 + nc) of the finest level: node values -> coefficients
+      // groups of CH cones of the finest level: node values -> coefficients
       auto& sm = *reinterpret_cast<PropSmem<T, PS, PA>*>(smem);
       const BLevel<T>& L = G.lv[D];
       constexpr int CH = PropShape<P>::CH;
-      const int c0 = local * CH, nc = min(CH, L.nrel - c0);
       if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = G.Ms[threadIdx.x];
       if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = G.Ma[threadIdx.x];
-      for (int q = threadIdx.x; q < nc * P; q += BS) sm.acc[q] = gen(L.Fn)[(int64_t)c0 * P + q];
-      __syncthreads();
-      lds_coeffs_store<T, PS, PA, BS>(sm.acc, sm.tmp, nc, sm.ms, sm.ma, gen(L.Fc) + (int64_t)c0 * P, 1, 0);
+      const int cend = min((local + 1) * BG_COEF * CH, L.nrel);
+      for (int c0 = local * BG_COEF * CH; c0 < cend; c0 += CH) {
+        const int nc = min(CH, cend - c0);
+        __syncthreads();   // ms, ma written; LDS of the previous group free
+        for (int q = threadIdx.x; q < nc * P; q += BS) sm.acc[q] = gen(L.Fn)[(int64_t)c0 * P + q];
+        __syncthreads();
+        lds_coeffs_store<T, PS, PA, BS>(sm.acc, sm.tmp, nc, sm.ms, sm.ma, gen(L.Fc) + (int64_t)c0 * P, 1, 0);
+      }
       break;
     }
     case BT_PROP: {
       const int d = S.level;   // child level
       const BLevel<T>& lc = G.lv[d];
       const BLevel<T>& lp = G.lv[d - 1];
-      prop_item<T, PS, PA, true>(*reinterpret_cast<PropSmem<T, PS, PA>*>(smem), gen(lp.work)[local], 0, gen(lp.rel_cone),
-                                 gen(lp.child_lo), gen(lc.coords), gen(lc.slot), gen(lc.Fc), lp.g, lc.g, G.ct,
-                                 gen(G.Ms), gen(G.Ma), G.k, G.kind, 1, gen(lp.Fc), gen(G.err));
+      const int w1 = min((local + 1) * BG_PROP, lp.nwork);
+      for (int w = local * BG_PROP; w < w1; ++w) {
+        if (w > local * BG_PROP) __syncthreads();   // LDS reuse
+        prop_item<T, PS, PA, true>(*reinterpret_cast<PropSmem<T, PS, PA>*>(smem), gen(lp.work)[w], 0,
+                                   gen(lp.rel_cone), gen(lp.child_lo), gen(lc.coords), gen(lc.slot), gen(lc.Fc), lp.g,
+                                   lc.g, G.ct, gen(G.Ms), gen(G.Ma), G.k, G.kind, 1, gen(lp.Fc), gen(G.err));
+      }
       break;
     }
     case BT_TARGET: {
@@ -1906,9 +1925,15 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
     default:
       break;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  // every wave waits until its stores have reached L2; then one agent-scope
+  // release (L2 write-back) covers the stores of the whole work-group
+  if (S.type == BT_TARGET) return;   // nothing in the launch consumes the targets' output
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(&ctr[S.done], 1);
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    atomicAdd(&ctr[S.done], 1);
+  }
 }
 
 __global__ __launch_bounds__(TPB) void k_zero_i32(int* __restrict__ x, int n) {
@@ -1947,6 +1972,7 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       BLevel<T>& L = G.lv[d];
       L.nb = l.nb;
       L.nrel = l.nrel;
+      L.nwork = (int)l.nwork;
       L.start = gas(l.start.as<const int>());
       L.nbr_off = gas(l.nbr_off.as<const int>());
       L.nbr = gas(l.nbr.as<const int>());
@@ -1992,28 +2018,37 @@ void batch_prepare_impl(ifgf_batch_s* b) {
   std::vector<int64_t> ngat(ng), nnear(ng), nleaf(ng);
   std::vector<std::pair<int, int>> last(ng, {-1, 0});   // producer of the newest coefficient level
   for (int g = 0; g < ng; ++g) {
-    ngat[g] = (b->plans[g]->n + BS - 1) / BS;
+    ngat[g] = (b->plans[g]->n + (int64_t)BS * BG_GATHER - 1) / ((int64_t)BS * BG_GATHER);
     emit(BT_GATHER, g, 0, ngat[g], -1, 0, -1, 0, C(g, K_GATHER));
   }
   for (int g = 0; g < ng; ++g) {
     ifgf_plan_s* p = b->plans[g];
-    nleaf[g] = p->D >= 3 ? p->lev[p->D].nb : 0;
+    nleaf[g] = p->D >= 3 ? (p->lev[p->D].nb + BG_BOX - 1) / BG_BOX : 0;
     emit(BT_LEAF, g, p->D, nleaf[g], C(g, K_GATHER), (int)ngat[g], -1, 0, C(g, K_LEAF));
   }
   for (int g = 0; g < ng; ++g) {
     ifgf_plan_s* p = b->plans[g];
-    nnear[g] = p->lev[p->D].nb;
+    nnear[g] = (p->lev[p->D].nb + BG_BOX - 1) / BG_BOX;
     emit(BT_NEAR, g, p->D, nnear[g], C(g, K_GATHER), (int)ngat[g], -1, 0, C(g, K_NEAR));
   }
   for (int g = 0; g < ng; ++g) {
     ifgf_plan_s* p = b->plans[g];
     if (p->D < 3) continue;
-    const int64_t cnt = (p->lev[p->D].nrel + CH - 1) / CH;
+    const int64_t cnt = (p->lev[p->D].nrel + (int64_t)BG_COEF * CH - 1) / ((int64_t)BG_COEF * CH);
     emit(BT_COEF, g, p->D, cnt, C(g, K_LEAF), (int)nleaf[g], -1, 0, C(g, K_COEF));
     if (cnt > 0) last[g] = {C(g, K_COEF), (int)cnt};
   }
+  // Upward pass in steps j = 0, 1, ...: step j takes level D_g - j -> D_g - j - 1
+  // of every geometry g.  A geometry's targets follow its last step, so the
+  // targets of shallow trees overlap the upward pass of deeper ones.
   int maxD = 0;
   for (auto* p : b->plans) maxD = std::max(maxD, p->D);
+  auto emit_targets = [&](int g) {
+    emit(BT_TARGET, g, 0, (b->plans[g]->n + BS - 1) / BS, C(g, K_NEAR), (int)nnear[g], last[g].first,
+         last[g].second, C(g, K_TARGET));
+  };
+  for (int g = 0; g < ng; ++g)
+    if (b->plans[g]->D < 4) emit_targets(g);
   for (int j = 0; j + 4 <= maxD; ++j) {
     for (int g = 0; g < ng; ++g) {
       ifgf_plan_s* p = b->plans[g];
@@ -2021,12 +2056,13 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       if (d < 4) continue;
       const LevelPlan& lp = p->lev[d - 1];
       if (lp.nrel == 0 || lp.nwork == 0) continue;
-      emit(BT_PROP, g, d, lp.nwork, last[g].first, last[g].second, -1, 0, C(g, K_PROP0 + d - 1));
-      last[g] = {C(g, K_PROP0 + d - 1), (int)lp.nwork};
+      const int64_t cnt = (lp.nwork + BG_PROP - 1) / BG_PROP;
+      emit(BT_PROP, g, d, cnt, last[g].first, last[g].second, -1, 0, C(g, K_PROP0 + d - 1));
+      last[g] = {C(g, K_PROP0 + d - 1), (int)cnt};
     }
+    for (int g = 0; g < ng; ++g)
+      if (b->plans[g]->D - j == 4) emit_targets(g);   // its last step was this one
   }
-  for (int g = 0; g < ng; ++g)
-    emit(BT_TARGET, g, 0, ngat[g], C(g, K_NEAR), (int)nnear[g], last[g].first, last[g].second, C(g, K_TARGET));
 
   // Every counter a segment waits on must be complete-able by earlier segments
   // alone, with exactly the awaited number of items.
@@ -2043,6 +2079,11 @@ void batch_prepare_impl(ifgf_batch_s* b) {
 
   b->nseg = (int)segs.size();
   b->total = (int)first;
+  std::vector<int> seg_of((size_t)std::max<int64_t>(1, first));
+  for (size_t i = 0; i < segs.size(); ++i)
+    for (int q = 0; q < segs[i].count; ++q) seg_of[(size_t)segs[i].first + q] = (int)i;
+  b->seg_of.alloc(sizeof(int) * seg_of.size());
+  HIPCHK(hipMemcpy(b->seg_of.p, seg_of.data(), sizeof(int) * seg_of.size(), hipMemcpyHostToDevice));
   b->nctr = 1 + 16 * ng;
   b->segs.alloc(sizeof(BSeg) * std::max<size_t>(1, segs.size()));
   if (!segs.empty()) HIPCHK(hipMemcpy(b->segs.p, segs.data(), sizeof(BSeg) * segs.size(), hipMemcpyHostToDevice));
@@ -2070,7 +2111,7 @@ void batch_apply_impl(ifgf_batch_s* b, const void* const* sigma, void* const* u,
   k_zero_i32<<<nblocks(b->nctr), TPB, 0, s>>>(b->ctr.as<int>(), b->nctr);
   HIPCHK(hipGetLastError());
   if (b->total == 0) return;
-  k_batch<T, PS, PA><<<b->grid, b->block, b->smem, s>>>(b->segs.as<BSeg>(), b->nseg, b->total,
+  k_batch<T, PS, PA><<<b->grid, b->block, b->smem, s>>>(b->segs.as<BSeg>(), b->seg_of.as<int>(), b->total,
                                                         b->geoms.as<BGeom<T>>(), io, dtype, b->ctr.as<int>(),
                                                         b->spin_limit, b->err.as<int>());
   HIPCHK(hipGetLastError());

@@ -111,6 +111,7 @@ struct BSeg {
 struct ifgf_batch_s {
   std::vector<ifgf_plan_s*> plans;   // not owned
   ifgf::DevBuf segs;                 // BSeg [nseg]
+  ifgf::DevBuf seg_of;               // int [total]: segment of each queue item
   ifgf::DevBuf geoms;                // per-geometry device descriptors
   ifgf::DevBuf ctr;                  // int [nctr]: queue head, then 16 completion counters per geometry
   ifgf::DevBuf err;                  // int [4]: bit 0 = a dependency wait hit the poll limit
