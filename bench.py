@@ -52,7 +52,12 @@ def log(msg):
 # device copy of known size).  The summary records the SHA-256 of the kernel
 # sources it was taken with; when the sources have changed since, the figure
 # no longer describes this kernel and is not reported.
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_prop_sphere32_hbm_traffic.md")
+TRAFFIC_SUMMARY = {
+    "prop": os.path.join(ROOT, "profiles", "k_prop_sphere32_hbm_traffic.md"),
+    "prop_cone": os.path.join(ROOT, "profiles", "k_prop_ti_sphere32_hbm_traffic.md"),
+}
+KERNEL_OF_STAGE = {"prop": "k_prop (node formulation)", "prop_cone": "k_prop_ti (cone-major, MFMA)",
+                   "targets": "k_targets", "leaf": "k_leaf", "near": "k_near", "coeffs": "k_coeffs"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_06316_amd", "csrc", f) for f in ("apply.hip", "common.h")]
 
 
@@ -69,9 +74,11 @@ def config_tag(args):
     return f"{args.workload} p_s={args.p_s} p_ang={args.p_ang} ns0={args.ns0} nc0={args.nc0}"
 
 
-def measured_traffic(tag):
+def measured_traffic(tag, stage):
+    if stage not in TRAFFIC_SUMMARY:
+        return None
     try:
-        with open(TRAFFIC_SUMMARY) as fh:
+        with open(TRAFFIC_SUMMARY[stage]) as fh:
             lines = fh.read().splitlines()
     except OSError:
         return None
@@ -218,6 +225,8 @@ def main():
     fi = interp_flops(ps, pa)
     prop_evals = sum(st["prop_evals"].values())
     cousin = sum(st["cousin_pairs"].values())
+    cone_lv = [d for d, m in st["prop_kernel"].items() if m == "cone"]
+    node_lv = [d for d, m in st["prop_kernel"].items() if m == "node"]
     leaf_cones = st["cones"][D] if D >= 3 else 0
     pts_per_leaf = n / st["boxes"][D]
     # leaf factors: every relevant leaf cone node against every source of its box
@@ -226,12 +235,14 @@ def main():
         "near": st["near_pairs"] * NEAR_FLOPS,
         "leaf": leaf_cones * P * pts_per_leaf * LEAF_FLOPS,
         "coeffs": sum(st["cones"].values()) * coeff_flops(ps, pa),
-        "prop": prop_evals * fi,
+        "prop": sum(st["prop_evals"][d] for d in node_lv) * fi,
+        "prop_cone": sum(st["prop_evals"][d] for d in cone_lv) * fi,
         "targets": cousin * fi,
     }
     F_bytes = {d: st["cones"][d] * P * 8 for d in st["cones"]}
     traffic = {
-        "prop": sum(F_bytes[d] + F_bytes[d - 1] for d in range(4, D + 1)),
+        "prop": sum(F_bytes[d] + F_bytes[d - 1] for d in node_lv),
+        "prop_cone": sum(F_bytes[d] + F_bytes[d - 1] for d in cone_lv),
         "targets": sum(F_bytes.values()) + n * (24 + 8 + 4 + 16),
         "leaf": n * (24 + 24 + 8) + F_bytes.get(D, 0),
         "near": n * (24 + 24 + 8 + 8),
@@ -249,10 +260,13 @@ def main():
     avg_launch_s = ms_dom / cnt_dom * 1e-3
     per_launch_flops = work[dom] / (cnt_dom / args.steps)
     achieved = per_launch_flops / avg_launch_s / 1e12
-    measured = measured_traffic(config_tag(args)) if dom == "prop" else None
+    measured = measured_traffic(config_tag(args), dom)
+    # the cone-major upward pass runs its contraction on FP32 MFMA (dense peak
+    # 157.3 TFLOP/s); the other kernels on the FP32 vector ALUs (157.3 TFLOP/s)
     roofline = {
-        "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured, "kernel": dom,
+        "bound": "mfma" if dom == "prop_cone" else "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": measured,
+        "kernel": KERNEL_OF_STAGE.get(dom, dom), "stage": dom,
         "avg_launch_ms": avg_launch_s * 1e3, "launches_per_apply": cnt_dom / args.steps,
         "algorithmic_flops_per_launch": per_launch_flops,
         "algorithmic_bytes_per_launch": traffic[dom] / (cnt_dom / args.steps),
@@ -390,6 +404,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plan": {"cones": st["cones"], "boxes": st["boxes"], "near_pairs": st["near_pairs"],
+                 "upward_pass_formulation": st["prop_kernel"],
                  "cousin_pairs": cousin, "prop_evals": prop_evals, "device_bytes": st["device_bytes"]},
         "consistency_flags": r32["flags"],
     }

@@ -84,7 +84,21 @@ typedef struct {
     int32_t precision;      /* IFGF_PREC_*; default IFGF_PREC_FP32_INTERP                  */
     int32_t max_rhs;        /* largest nrhs accepted by the apply calls; default 1         */
     int32_t kernel;         /* IFGF_KERNEL_*; default IFGF_KERNEL_COMBINED                  */
+    int32_t prop_kernel;    /* upward pass with one right-hand side in FP32: IFGF_PROP_AUTO
+                               (default), IFGF_PROP_NODE or IFGF_PROP_CONE (below)          */
 } ifgf_options;
+
+/* Upward-pass formulation (FP32, nrhs = 1; FP64 and other nrhs always use
+ * IFGF_PROP_NODE).  NODE: every parent node of every relevant parent cone
+ * evaluates its child interpolants (work items = a parent box and a few of
+ * its cones).  CONE: all boxes of a level have the same size, so a parent
+ * node's position in a child's frame depends only on (parent cone id, child
+ * octant, node); the boxes holding the same parent cone id are taken
+ * together and the interpolation becomes a product of their child
+ * coefficients with one basis matrix, on MFMA.  AUTO picks CONE for the
+ * levels where the boxes per parent cone id fill its tiles.  Both give the
+ * same operator up to FP32 rounding. */
+enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2 };
 
 /* Plan statistics (host struct). */
 #define IFGF_MAX_LEVELS 12
@@ -105,6 +119,9 @@ typedef struct {
     int64_t prop_evals[IFGF_MAX_LEVELS];    /* child interpolations into level d-1 nodes,
                                                indexed by the child level d            */
     int64_t device_bytes;                   /* device memory held by the plan           */
+    int32_t prop_kernel[IFGF_MAX_LEVELS];   /* upward pass from child level d (index d):
+                                               IFGF_PROP_NODE or IFGF_PROP_CONE with one
+                                               FP32 right-hand side, 0 if no pass       */
 } ifgf_plan_stats;
 
 /* Fill *o with the defaults listed above.  o: [host], non-null. */
@@ -220,7 +237,8 @@ ifgf_status ifgf_plan_check(ifgf_plan p, int32_t *flags);
 /*
  * Per-kernel timing with HIP events recorded on the apply's stream.
  * Stages: IFGF_STAGE_GATHER (a = w sigma), NEAR (near field), LEAF (leaf
- * factors), COEFFS (node values -> coefficients), PROP (upward pass),
+ * factors), COEFFS (node values -> coefficients), PROP (upward pass,
+ * node formulation), PROP_CONE (upward pass, cone-major formulation),
  * TARGETS (cousin interpolation + scatter), plus the transposed stages of
  * ifgf_apply_adjoint (ADJ_*).
  *
@@ -235,7 +253,7 @@ enum {
     IFGF_STAGE_GATHER = 0, IFGF_STAGE_NEAR = 1, IFGF_STAGE_LEAF = 2, IFGF_STAGE_COEFFS = 3,
     IFGF_STAGE_PROP = 4, IFGF_STAGE_TARGETS = 5, IFGF_STAGE_ADJ_TARGETS = 6, IFGF_STAGE_ADJ_PROP = 7,
     IFGF_STAGE_ADJ_COEFFS = 8, IFGF_STAGE_ADJ_LEAF = 9, IFGF_STAGE_ADJ_NEAR = 10, IFGF_STAGE_ADJ_OUT = 11,
-    IFGF_NSTAGES = 12
+    IFGF_STAGE_PROP_CONE = 12, IFGF_NSTAGES = 13
 };
 ifgf_status ifgf_plan_set_profiling(ifgf_plan p, int32_t max_launches);
 ifgf_status ifgf_plan_read_profile(ifgf_plan p, double *ms, int64_t *launches);

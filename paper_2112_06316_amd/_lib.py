@@ -13,8 +13,9 @@ OK, EINVAL, EDUPLICATE, ENOMEM, EHIP, EUNSUPPORTED, EBUSY, EINTERNAL = range(8)
 PREC_FP64, PREC_FP32_INTERP = 0, 1
 C64, C128 = 0, 1
 KERNEL_COMBINED, KERNEL_CONSTANT = 0, 1
+PROP_AUTO, PROP_NODE, PROP_CONE = 0, 1, 2
 STAGES = ["gather", "near", "leaf", "coeffs", "prop", "targets", "adj_targets", "adj_prop", "adj_coeffs",
-          "adj_leaf", "adj_near", "adj_out"]
+          "adj_leaf", "adj_near", "adj_out", "prop_cone"]
 
 
 class Options(ctypes.Structure):
@@ -28,6 +29,7 @@ class Options(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("max_rhs", ctypes.c_int32),
         ("kernel", ctypes.c_int32),
+        ("prop_kernel", ctypes.c_int32),
     ]
 
 
@@ -48,6 +50,7 @@ class Stats(ctypes.Structure):
         ("near_pairs", ctypes.c_int64),
         ("prop_evals", ctypes.c_int64 * MAX_LEVELS),
         ("device_bytes", ctypes.c_int64),
+        ("prop_kernel", ctypes.c_int32 * MAX_LEVELS),
     ]
 
 

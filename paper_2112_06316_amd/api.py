@@ -23,6 +23,7 @@ def library_path() -> str:
 
 _PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32_INTERP}
 _KERNEL = {"combined": L.KERNEL_COMBINED, "constant": L.KERNEL_CONSTANT}
+_PROP = {"auto": L.PROP_AUTO, "node": L.PROP_NODE, "cone": L.PROP_CONE}
 
 
 def _stream_ptr(device) -> int:
@@ -45,7 +46,8 @@ class Plan:
     """
 
     def __init__(self, points, normals, weights, k, eta, *, p_s=4, p_ang=6, ns0=2, nc0=4, depth=0,
-                 leaf_h_lambda=0.5, precision="fp32", max_rhs=1, kernel="combined", device="cuda"):
+                 leaf_h_lambda=0.5, precision="fp32", max_rhs=1, kernel="combined", prop_kernel="auto",
+                 device="cuda"):
         lib = L.load()
         self._lib = lib
         self.device = torch.device(device)
@@ -65,6 +67,7 @@ class Plan:
         o.precision = _PREC[precision]
         o.max_rhs = int(max_rhs)
         o.kernel = _KERNEL[kernel]
+        o.prop_kernel = _PROP[prop_kernel]
         self.options = o
         h = ctypes.c_void_p()
         st = lib.ifgf_plan_create(ctypes.byref(h), n, pts.data_ptr(), nrm.data_ptr(), w.data_ptr(),
@@ -141,6 +144,7 @@ class Plan:
             "cousin_pairs": {d: s.cousin_pairs[d] for d in range(3, D + 1)},
             "prop_evals": {d: s.prop_evals[d] for d in range(4, D + 1)},
             "near_pairs": s.near_pairs, "device_bytes": s.device_bytes,
+            "prop_kernel": {d: {1: "node", 2: "cone"}.get(s.prop_kernel[d], "none") for d in range(4, D + 1)},
         }
 
     def set_profiling(self, max_launches: int):

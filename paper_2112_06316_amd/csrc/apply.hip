@@ -1173,6 +1173,306 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma(int nrel_up, const int* __res
 }
 
 // ---------------------------------------------------------------------------
+// Cone-major upward pass on MFMA (FP32, one right-hand side).
+//
+// Every box of a level has the same size, so the position of parent node
+// (a, b, c) of parent cone id q relative to the centre of the child in
+// octant o - hence its child cone, local coordinates and the ratio
+// K(x, y_B)/K(x, y_P) - depends on (q, o, node) only, not on the box.  A
+// work item is one cone id q and up to 8 NW parent boxes holding it.  For
+// each octant the block computes the P node geometries once and groups the
+// nodes by child cone; then each wave evaluates, for its 8 boxes, the child
+// interpolants at the nodes of a group as the product
+//     OUT[row][e] = sum_k C[row][k] B[k][e],
+// rows = 8 boxes x (re, im) of the child cone's coefficients, columns = 16
+// nodes of the group, B[k][e] = T_a(ts_e) T_b(tt_e) T_c(tp_e), on
+// v_mfma_f32_16x16x4_f32 with the basis index ordered (b, c, a) so that a
+// fills the 4-wide K step.  The wave adds ratio * OUT to its boxes' node
+// values in LDS (each (box, node) has one writer per octant, octants in
+// order: deterministic).  After the 8 octants the node values are turned
+// into coefficients in place and written to the parent level.
+// ---------------------------------------------------------------------------
+template <int PS, int PA, int NW> struct TiSmem {
+  static constexpr int P = PS * PA * PA;
+  static constexpr int NB = 8 * NW;
+  static constexpr int NBAS = PS + 2 * PA;
+  // Row strides padded so that lanes reading different nodes (bas) or
+  // different boxes (acc) fall in different LDS banks.
+  static constexpr int BAS_LD = NBAS | 1;
+  static constexpr int ACC_LD = P + 4;
+  cpx<float> acc[NB][ACC_LD];  // node values of the tile's boxes
+  float bas[P][BAS_LD];        // per node, current octant: T_a(ts), T_b(tt), T_c(tp)
+  float rat[P][2];             // ratio K(x, y_B) / K(x, y_P)
+  int cid[P];                  // child cone id
+  short order[P];              // nodes grouped by child cone
+  int gstart[P + 1], gcid[P];
+  int ngroup;
+  int child[NB][8];            // child box per (box, octant), -1 if none
+  int pslot[NB];               // parent slot of each box
+  int anychild;                // bit o: some box of the tile has a child in octant o
+  float ms[PS * PS], ma[PA * PA];
+};
+
+template <int PS, int PA, int NW>
+__global__ __launch_bounds__(64 * NW) void k_prop_ti(
+    const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ rel_box_up,
+    const int* __restrict__ child_lo_up, const int* __restrict__ coords, const int* __restrict__ slot_c,
+    const cpx<float>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct, const float* __restrict__ Ms,
+    const float* __restrict__ Ma, double k, int kind, cpx<float>* __restrict__ Fc_up, int* __restrict__ err) {
+  using S = TiSmem<PS, PA, NW>;
+  constexpr int P = S::P;
+  constexpr int NB = S::NB;
+  constexpr int BS = 64 * NW;
+  __shared__ S sm;
+  const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const int q = tl.x, nb = tl.z;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  // ---- set-up: boxes, their children by octant, node positions ----------------
+  if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = Ms[threadIdx.x];
+  if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
+  if (threadIdx.x == 0) sm.anychild = 0;
+  for (int t = threadIdx.x; t < NB * 8; t += BS) sm.child[t >> 3][t & 7] = -1;
+  for (int t = threadIdx.x; t < NB * S::ACC_LD; t += BS) sm.acc[t / S::ACC_LD][t % S::ACC_LD] = {0.f, 0.f};
+  __syncthreads();
+  if (threadIdx.x < nb) {
+    const int sl = ti_slot[tl.y + threadIdx.x];
+    const int Pb = rel_box_up[sl];
+    sm.pslot[threadIdx.x] = sl;
+    int mask = 0;
+    for (int B = child_lo_up[Pb]; B < child_lo_up[Pb + 1]; ++B) {
+      const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+      sm.child[threadIdx.x][oct] = B;
+      mask |= 1 << oct;
+    }
+    atomicOr(&sm.anychild, mask);
+  }
+  __syncthreads();
+  const int anychild = sm.anychild;
+
+  // this lane's A rows and B columns
+  const int li = lane & 15;       // A row (box, re/im) and B / OUT column
+  const int la = lane >> 4;       // index within the 4-wide K step: the radial index a
+  const int lbox = wv * 8 + (li >> 1), reim = li & 1;
+
+  for (int o = 0; o < 8; ++o) {
+    if (!((anychild >> o) & 1)) continue;   // block-uniform
+    // ---- node geometry in the child frame of octant o ------------------------
+    for (int n = threadIdx.x; n < P; n += BS) {
+      float x[3], rp;   // node relative to the parent centre (recomputed: cheaper than the LDS it would hold)
+      node_rel32(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
+      const PropF pr = child_loc32(x, rp, o, gc);
+      sm.cid[n] = pr.loc.cid;
+      cheb_T<float, PS>(pr.loc.ts, &sm.bas[n][0]);
+      cheb_T<float, PA>(pr.loc.tt, &sm.bas[n][PS]);
+      cheb_T<float, PA>(pr.loc.tp, &sm.bas[n][PS + PA]);
+      float c_ = 1.f, s_ = 0.f, rr = 1.f;
+      if (kind != IFGF_KERNEL_CONSTANT) {
+        sincos_f((float)k * pr.dr, &s_, &c_);
+        rr = pr.rp_over_rc;
+      }
+      sm.rat[n][0] = rr * c_;
+      sm.rat[n][1] = rr * s_;
+    }
+    __syncthreads();
+    // ---- group the nodes by child cone (wave 0) ----------------------------------
+    if (wv == 0) {
+      constexpr int NPL = (P + 63) / 64;   // nodes per lane
+      int cv[NPL];
+      bool pend[NPL];
+#pragma unroll
+      for (int m = 0; m < NPL; ++m) {
+        const int n = lane + 64 * m;
+        pend[m] = n < P;
+        cv[m] = pend[m] ? sm.cid[n] : 0;
+      }
+      int pos = 0, g = 0;
+      while (true) {
+        int lead = -1, su = 0;
+#pragma unroll
+        for (int m = 0; m < NPL && lead < 0; ++m) {
+          const uint64_t b = __ballot(pend[m]);
+          if (b) {
+            lead = first_lane(b);
+            su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
+          }
+        }
+        if (lead < 0) break;
+        if (lane == 0) {
+          sm.gstart[g] = pos;
+          sm.gcid[g] = su;
+        }
+#pragma unroll
+        for (int m = 0; m < NPL; ++m) {
+          const bool hit = pend[m] && cv[m] == su;
+          const uint64_t b = __ballot(hit);
+          if (hit) sm.order[pos + __popcll(b & ((1ull << lane) - 1))] = (short)(lane + 64 * m);
+          pos += __popcll(b);
+          pend[m] = pend[m] && !hit;
+        }
+        ++g;
+      }
+      if (lane == 0) {
+        sm.gstart[g] = pos;
+        sm.ngroup = g;
+      }
+    }
+    __syncthreads();
+    // ---- child interpolants on MFMA, group by group -----------------------------------
+    // The A operand (this lane's coefficient row of its box's child cone) is
+    // software-pipelined: while group g is evaluated, the coefficients of
+    // group g+1 and the slot of group g+2 are in flight.
+    const int ng = sm.ngroup;
+    const int Bc = lbox < nb ? sm.child[lbox][o] : -1;
+    const bool wave_has = __ballot(Bc >= 0) != 0;   // some box of this wave has a child in octant o
+    auto slot_of = [&](int g) -> int {
+      return (g < ng && Bc >= 0) ? slot_c[(int64_t)Bc * gc.ncone + sm.gcid[g]] : -1;
+    };
+    // Wide loads (16 B where the row is 16-byte aligned) keep the number of
+    // loads in flight - this group's and the next group's - under what the
+    // vector-memory counter can track, so the waits stay per load.
+    auto load_row = [&](int sl, float(&dst)[PA * PA]) {
+      if (sl >= 0 && la < PS) {
+        const cpx<float>* row = Fc_c + (int64_t)sl * P + la * PA * PA;
+        if constexpr (P % 2 == 0 && (PA * PA) % 2 == 0) {
+          const float4* src = reinterpret_cast<const float4*>(row);
+#pragma unroll
+          for (int u = 0; u < PA * PA / 2; ++u) {
+            const float4 v = src[u];
+            dst[2 * u] = reim ? v.y : v.x;
+            dst[2 * u + 1] = reim ? v.w : v.z;
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < PA * PA; ++t) {
+            const cpx<float> v = row[t];
+            dst[t] = reim ? v.im : v.re;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < PA * PA; ++t) dst[t] = 0.f;
+      }
+    };
+    float av[PA * PA], an[PA * PA];
+    int s_cur = -1, s_nxt = -1;
+    if (wave_has) {
+      s_cur = slot_of(0);
+      s_nxt = slot_of(1);
+      load_row(s_cur, av);
+    }
+    for (int g = 0; g < (wave_has ? ng : 0); ++g) {
+      const int n0 = sm.gstart[g], n1 = sm.gstart[g + 1];
+      const int s_nn = slot_of(g + 2);
+      load_row(s_nxt, an);
+      if (Bc >= 0 && s_cur < 0) atomicOr(err, 2);
+      for (int c0 = n0; c0 < n1; c0 += 16) {
+        const int e = c0 + li;
+        const int n = e < n1 ? sm.order[e] : -1;
+        float ta = 0.f, tt[PA], tp[PA];
+        if (n >= 0) {
+          ta = la < PS ? sm.bas[n][min(la, PS - 1)] : 0.f;
+#pragma unroll
+          for (int b = 0; b < PA; ++b) tt[b] = sm.bas[n][PS + b];
+#pragma unroll
+          for (int c = 0; c < PA; ++c) tp[c] = sm.bas[n][PS + PA + c];
+        } else {
+#pragma unroll
+          for (int b = 0; b < PA; ++b) tt[b] = tp[b] = 0.f;
+        }
+        floatx4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < PA; ++b) {
+          const float w = ta * tt[b];
+#pragma unroll
+          for (int c = 0; c < PA; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b * PA + c], w * tp[c], d, 0, 0, 0);
+        }
+        // lane 16 r + j holds rows 4r..4r+3 = boxes 2r, 2r+1 (re, im) of column j
+        const int col = c0 + li;
+        if (col < n1) {
+          const int nn = sm.order[col];
+          const float er = sm.rat[nn][0], ei = sm.rat[nn][1];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int bx = wv * 8 + 2 * la + h;
+            if (bx < nb && sm.child[bx][o] >= 0) {
+              const float vr = d[2 * h], vi = d[2 * h + 1];
+              sm.acc[bx][nn].re += er * vr - ei * vi;
+              sm.acc[bx][nn].im += er * vi + ei * vr;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < PA * PA; ++t) av[t] = an[t];
+      s_cur = s_nxt;
+      s_nxt = s_nn;
+    }
+    __syncthreads();
+  }
+
+  // ---- node values -> coefficients, in place, then to the parent level -------------
+  for (int t = threadIdx.x; t < nb * PA * PA; t += BS) {   // over a (s)
+    const int bx = t / (PA * PA), r = t % (PA * PA);
+    cpx<float> v[PS], w[PS];
+#pragma unroll
+    for (int a = 0; a < PS; ++a) v[a] = sm.acc[bx][a * PA * PA + r];
+#pragma unroll
+    for (int i = 0; i < PS; ++i) {
+      w[i] = {0.f, 0.f};
+#pragma unroll
+      for (int a = 0; a < PS; ++a) {
+        w[i].re += sm.ms[i * PS + a] * v[a].re;
+        w[i].im += sm.ms[i * PS + a] * v[a].im;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PS; ++i) sm.acc[bx][i * PA * PA + r] = w[i];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * PS * PA; t += BS) {   // over b (theta)
+    const int bx = t / (PS * PA), i = (t / PA) % PS, c = t % PA;
+    cpx<float> v[PA], w[PA];
+#pragma unroll
+    for (int b = 0; b < PA; ++b) v[b] = sm.acc[bx][(i * PA + b) * PA + c];
+#pragma unroll
+    for (int j = 0; j < PA; ++j) {
+      w[j] = {0.f, 0.f};
+#pragma unroll
+      for (int b = 0; b < PA; ++b) {
+        w[j].re += sm.ma[j * PA + b] * v[b].re;
+        w[j].im += sm.ma[j * PA + b] * v[b].im;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PA; ++j) sm.acc[bx][(i * PA + j) * PA + c] = w[j];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * PS * PA; t += BS) {   // over c (phi)
+    const int bx = t / (PS * PA), i = (t / PA) % PS, j = t % PA;
+    cpx<float> v[PA], w[PA];
+#pragma unroll
+    for (int c = 0; c < PA; ++c) v[c] = sm.acc[bx][(i * PA + j) * PA + c];
+#pragma unroll
+    for (int l = 0; l < PA; ++l) {
+      w[l] = {0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < PA; ++c) {
+        w[l].re += sm.ma[l * PA + c] * v[c].re;
+        w[l].im += sm.ma[l * PA + c] * v[c].im;
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < PA; ++l) sm.acc[bx][(i * PA + j) * PA + l] = w[l];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * P; t += BS) {
+    const int bx = t / P, jn = t % P;
+    Fc_up[(int64_t)sm.pslot[bx] * P + jn] = sm.acc[bx][jn];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Transposed apply.  The forward operator is
 //   u = N a + sum_d T_d c_d,  c_D = X L a,  c_{d-1} = X P_d c_d,
 // (N near field, L leaf factors, X node values -> coefficients, P_d upward
@@ -1597,6 +1897,22 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
             k_coeffs_rg<T, PS, PA, MF_RG><<<dim3(lp.nrel, R / MF_RG), TPB, 0, s>>>(p->scratch_fn.as<cpx<T>>(), R, Ms,
                                                                                   Ma, lp.Fc.as<cpx<T>>());
           }
+          HIPCHK(hipGetLastError());
+          continue;
+        }
+      }
+      if constexpr (Prec<T>::f32 && PS <= 4) {
+        if (R == 1 && lp.ntile > 0) {
+          StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
+          auto launch = [&](auto kern, int nw) {
+            kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
+                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.rel_box.as<int>(), lp.child_lo.as<int>(),
+                lc.coords.as<int>(), lc.slot.as<int>(), lc.Fc.as<cpx<float>>(), lp.geom, lc.geom, p->cheb,
+                (const float*)Ms, (const float*)Ma, p->k, kind, lp.Fc.as<cpx<float>>(), p->err.as<int>());
+          };
+          if (lp.ti_nw == 4) launch(k_prop_ti<PS, PA, 4>, 4);
+          else if (lp.ti_nw == 2) launch(k_prop_ti<PS, PA, 2>, 2);
+          else launch(k_prop_ti<PS, PA, 1>, 1);
           HIPCHK(hipGetLastError());
           continue;
         }
@@ -2143,6 +2459,11 @@ int prop_chunk(int P) {
 }
 
 bool supported_order(int ps, int pa) { return (ps == 3 && pa == 5) || (ps == 4 && pa == 6); }
+
+bool cone_prop_supported(const ifgf_plan_s* p) {
+  return p->opt.precision == IFGF_PREC_FP32_INTERP && p->opt.p_s <= 4 && p->opt.prop_kernel != IFGF_PROP_NODE &&
+         supported_order(p->opt.p_s, p->opt.p_ang);
+}
 
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask, int level_lo,
                int level_hi, hipStream_t s) {

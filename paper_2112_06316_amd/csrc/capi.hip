@@ -107,6 +107,7 @@ void ifgf_options_default(ifgf_options* o) {
   o->precision = IFGF_PREC_FP32_INTERP;
   o->max_rhs = 1;
   o->kernel = IFGF_KERNEL_COMBINED;
+  o->prop_kernel = IFGF_PROP_AUTO;
 }
 
 const char* ifgf_status_string(ifgf_status st) {
@@ -142,6 +143,7 @@ ifgf_status ifgf_plan_create(ifgf_plan* out, int64_t n, const double* points, co
     if (o.depth == 0 && !(o.leaf_h_lambda > 0.0)) throw Error{IFGF_EINVAL, "leaf_h_lambda must be > 0"};
     if (o.precision != IFGF_PREC_FP64 && o.precision != IFGF_PREC_FP32_INTERP) throw Error{IFGF_EINVAL, "bad precision"};
     if (o.max_rhs < 1) throw Error{IFGF_EINVAL, "max_rhs must be >= 1"};
+    if (o.prop_kernel < IFGF_PROP_AUTO || o.prop_kernel > IFGF_PROP_CONE) throw Error{IFGF_EINVAL, "bad prop_kernel"};
     if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
     if (!supported_order(o.p_s, o.p_ang)) throw Error{IFGF_EUNSUPPORTED, "p_s/p_ang pair not compiled in"};
     p = new ifgf_plan_s();
@@ -215,8 +217,10 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
       st->prop_evals[d] = l.prop_evals;
       add(l.start); add(l.coords); add(l.centre); add(l.parent); add(l.child_lo); add(l.nbr_off); add(l.nbr);
       add(l.cou_off); add(l.cou); add(l.pbox); add(l.slot); add(l.slot_off); add(l.rel_box); add(l.rel_cone);
-      add(l.Fn); add(l.Fc);
+      add(l.Fn); add(l.Fc); add(l.work); add(l.ti_slot); add(l.ti_tile);
       add(p->adj_g[d]);
+      if (d >= 4 && p->lev[d - 1].nrel > 0)
+        st->prop_kernel[d] = p->lev[d - 1].ntile > 0 ? IFGF_PROP_CONE : IFGF_PROP_NODE;
     }
     st->near_pairs = p->near_pairs;
     st->device_bytes = bytes;

@@ -58,6 +58,12 @@ struct LevelPlan {
   DevBuf Fn, Fc;              // node values (finest level only) / coefficients [nrel][P][max_rhs] complex
   DevBuf work;                // int4 [nwork]: (box, first slot, end slot, 0) chunks of this level's
   int64_t nwork = 0;          //   relevant cones, the work items of the upward pass into this level
+  // cone-major upward pass into this level (IFGF_PROP_CONE): this level's
+  // relevant cones sorted by (cone id, slot), in tiles of up to 8 * ti_nw
+  // boxes sharing one cone id: int4 (cone id, first index into ti_slot, count, 0)
+  DevBuf ti_slot, ti_tile;
+  int64_t ntile = 0;
+  int ti_nw = 0;              // 0: this level uses the node formulation
   // statistics
   int64_t cousin_pairs = 0;
   int64_t prop_evals = 0;     // child interpolations into level d-1 nodes
@@ -143,6 +149,7 @@ void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, 
 
 bool supported_order(int ps, int pa);
 int prop_chunk(int P);
+bool cone_prop_supported(const ifgf_plan_s* p);
 
 // Brackets one kernel launch with events when profiling is enabled.
 struct StageTimer {

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace ifgf {
@@ -330,6 +332,13 @@ LevelGeom make_geom(double H, int ns, int nc) {
 
 }  // namespace
 
+// Sort keys (cone id, slot) of a level's relevant cones.
+__global__ __launch_bounds__(TPB) void k_cone_keys(const int* __restrict__ rel_cone, int nrel,
+                                                   uint64_t* __restrict__ keys) {
+  const int i = blockIdx.x * TPB + threadIdx.x;
+  if (i < nrel) keys[i] = ((uint64_t)(uint32_t)rel_cone[i] << 32) | (uint32_t)i;
+}
+
 void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const double* w, hipStream_t s) {
   const int64_t n = p->n;
   const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
@@ -617,6 +626,67 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
     lv.nwork = (int64_t)wk.size() / 4;
     lv.work.alloc(sizeof(int) * std::max<size_t>(4, wk.size()));
     if (!wk.empty()) HIPCHK(hipMemcpy(lv.work.p, wk.data(), sizeof(int) * wk.size(), hipMemcpyHostToDevice));
+  }
+
+  // ---- cone-major tiles of the upward pass (FP32, one RHS) ------------------------
+  // Boxes per distinct cone id decide the tile height: 32, 16 or 8 boxes
+  // (4, 2 or 1 waves of 8 boxes); AUTO leaves levels with fewer than 6 boxes
+  // per cone id to the node formulation.
+  if (cone_prop_supported(p)) {
+    for (int d = 3; d < D; ++d) {
+      LevelPlan& lv = p->lev[d];
+      if (lv.nrel == 0) continue;
+      DevBuf kb;
+      kb.alloc(sizeof(uint64_t) * sort_padded_length(lv.nrel));
+      k_cone_keys<<<nblocks(lv.nrel), TPB, 0, s>>>(lv.rel_cone.as<int>(), lv.nrel, kb.as<uint64_t>());
+      HIPCHK(hipGetLastError());
+      sort_u64(kb.as<uint64_t>(), lv.nrel, s);
+      std::vector<uint64_t> keys(lv.nrel);
+      HIPCHK(hipMemcpyAsync(keys.data(), kb.p, sizeof(uint64_t) * lv.nrel, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      int64_t ndistinct = 0;
+      for (int64_t i = 0; i < lv.nrel; ++i)
+        if (i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32)) ++ndistinct;
+      const double per = (double)lv.nrel / (double)ndistinct;
+      int nw = per >= 24.0 ? 4 : (per >= 12.0 ? 2 : (per >= 6.0 ? 1 : 0));
+      if (p->opt.prop_kernel == IFGF_PROP_CONE && nw == 0) nw = 1;
+      if (nw == 0) continue;
+      const int cap = 8 * nw;
+      // child-octant mask of every box of this level, to order the boxes of
+      // one cone id so that the 8 boxes of a wave tend to share their octants
+      std::vector<int> clo(lv.nb + 1), ccoords(3 * (size_t)std::max(1, p->lev[d + 1].nb)), rbox(lv.nrel);
+      HIPCHK(hipMemcpy(clo.data(), lv.child_lo.p, sizeof(int) * (lv.nb + 1), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(ccoords.data(), p->lev[d + 1].coords.p, sizeof(int) * 3 * p->lev[d + 1].nb,
+                       hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(rbox.data(), lv.rel_box.p, sizeof(int) * lv.nrel, hipMemcpyDeviceToHost));
+      std::vector<uint8_t> cmask(lv.nb, 0);
+      for (int b = 0; b < lv.nb; ++b)
+        for (int c = clo[b]; c < clo[b + 1]; ++c)
+          cmask[b] |= (uint8_t)(1u << ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) |
+                                       ((ccoords[3 * c + 2] & 1) << 2)));
+      std::vector<int> slots(lv.nrel), tiles;
+      for (int64_t i = 0; i < lv.nrel; ++i) slots[i] = (int)(keys[i] & 0xffffffffu);
+      for (int64_t i = 0; i < lv.nrel;) {
+        const int cid = (int)(keys[i] >> 32);
+        int64_t j = i;
+        while (j < lv.nrel && (int)(keys[j] >> 32) == cid) ++j;
+        std::stable_sort(slots.begin() + i, slots.begin() + j,
+                         [&](int x, int y) { return cmask[rbox[x]] < cmask[rbox[y]]; });
+        for (int64_t t = i; t < j; t += cap) {
+          tiles.push_back(cid);
+          tiles.push_back((int)t);
+          tiles.push_back((int)std::min<int64_t>(cap, j - t));
+          tiles.push_back(0);
+        }
+        i = j;
+      }
+      lv.ti_nw = nw;
+      lv.ntile = (int64_t)tiles.size() / 4;
+      lv.ti_slot.alloc(sizeof(int) * lv.nrel);
+      lv.ti_tile.alloc(sizeof(int) * tiles.size());
+      HIPCHK(hipMemcpy(lv.ti_slot.p, slots.data(), sizeof(int) * lv.nrel, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(lv.ti_tile.p, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice));
+    }
   }
 
   // ---- workspaces -------------------------------------------------------------

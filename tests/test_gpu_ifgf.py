@@ -248,3 +248,38 @@ def test_sphere_32_wavelengths_sampled():
     err = rel_l2(u[tg], ref)
     log(f"  rel l2 err = {err:.3e}")
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("ps,pa,ns0,nc0,D", [(4, 6, 2, 4, 5), (3, 5, 1, 2, 5), (4, 6, 2, 4, 6)])
+def test_cone_major_upward_pass_equals_node_formulation(ps, pa, ns0, nc0, D):
+    # The cone-major (MFMA) and node formulations of the upward pass compute
+    # the same coefficients at every level, up to FP32 rounding.
+    log(f"case cone-major P=({ps},{pa}) D={D}")
+    p, nr, w = inputs.cubed_sphere(48)
+    k = 16 * np.pi
+    s = torch.from_numpy(inputs.random_density(len(p), seed=61)).to(DEV).to(torch.complex64)
+    opts = dict(depth=D, p_s=ps, p_ang=pa, ns0=ns0, nc0=nc0, precision="fp32")
+    node = Plan(p, nr, w, k, k, prop_kernel="node", **opts)
+    cone = Plan(p, nr, w, k, k, prop_kernel="cone", **opts)
+    un = node.apply(s).cpu().numpy()
+    uc = cone.apply(s).cpu().numpy()
+    for d in range(3, D):
+        Cn = node.export_field(d, 1)[:, 0, :]
+        Cc = cone.export_field(d, 1)[:, 0, :]
+        e = np.abs(Cc - Cn).max() / np.abs(Cn).max()
+        log(f"  level {d}: {Cn.shape[0]} cones, max rel diff {e:.2e}")
+        assert e < 2e-5, d
+    assert np.linalg.norm(uc - un) / np.linalg.norm(un) < 1e-5
+    assert cone.check() == 0 and node.check() == 0
+
+
+@pytest.mark.parametrize("ps,pa", [(4, 6), (3, 5)])
+def test_cone_major_constant_kernel_exact(ps, pa):
+    p, nr, w = inputs.cubed_sphere(48)
+    sigma = inputs.random_density(len(p), seed=62)
+    plan = Plan(p, nr, w, 16 * np.pi, 16 * np.pi, depth=5, p_s=ps, p_ang=pa, kernel="constant", precision="fp32",
+                prop_kernel="cone")
+    u = plan.apply(torch.from_numpy(sigma).to(DEV)).cpu().numpy()
+    a = w * sigma
+    ref = a.sum() - a
+    assert np.abs(u - ref).max() <= 2e-5 * np.abs(a).sum()
