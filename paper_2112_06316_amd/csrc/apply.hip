@@ -46,8 +46,13 @@ template <> __device__ __forceinline__ void sincos_t<float>(float x, float* s, f
 template <> __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) { sincos(x, s, c); }
 
 template <typename T> __device__ __forceinline__ T sqrt_t(T x);
-template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return sqrtf(x); }
+template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return sqrt_f(x); }   // hardware, ~1 ulp
 template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return sqrt(x); }
+// 1/x: the hardware reciprocal in FP32 (about 1 ulp, as elsewhere in the FP32
+// path), IEEE division in FP64.
+template <typename T> __device__ __forceinline__ T rcp_t(T x);
+template <> __device__ __forceinline__ float rcp_t<float>(float x) { return rcp_f(x); }
+template <> __device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
 
 // ---------------------------------------------------------------------------
 // gather: a[i, r] = w_i sigma[perm_i, r]
@@ -186,7 +191,7 @@ __device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int r0,
             T d0 = x0 - sx[e][0], d1 = x1 - sx[e][1], d2 = x2 - sx[e][2];
             T r2 = d0 * d0 + d1 * d1 + d2 * d2;
             T rr = sqrt_t<T>(r2);
-            T ir = (T)1 / rr;
+            T ir = rcp_t<T>(rr);
             // forward: <x_t - x_s, n_s>; transposed: <x_s - x_t, n_t>
             T dn = TR ? -(d0 * m0 + d1 * m1 + d2 * m2) * ir * ir
                       : (d0 * sn[e][0] + d1 * sn[e][1] + d2 * sn[e][2]) * ir * ir;
@@ -274,6 +279,33 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int r0, con
   const double invh = 1.0 / g.h;
   const T kk = (T)k, ee = (T)eta, kh = (T)(k * g.h), ih = (T)invh;
   const int nitems = ncn * P;
+  // sources of the box, relative to its centre in units of h, staged in LDS
+  auto stage = [&](int cb, int cn) {
+    for (int q = threadIdx.x; q < cn; q += BS) {
+        int j = p0 + cb + q;
+        T u0 = (T)((pts[3 * j] - c0) * invh), u1 = (T)((pts[3 * j + 1] - c1) * invh),
+          u2 = (T)((pts[3 * j + 2] - c2) * invh);
+        T n0 = (T)nrm[3 * j], n1 = (T)nrm[3 * j + 1], n2 = (T)nrm[3 * j + 2];
+        su[q][0] = u0;
+        su[q][1] = u1;
+        su[q][2] = u2;
+        sn[q][0] = n0;
+        sn[q][1] = n1;
+        sn[q][2] = n2;
+        suu[q] = u0 * u0 + u1 * u1 + u2 * u2;
+        sun[q] = u0 * n0 + u1 * n1 + u2 * n2;
+#pragma unroll
+        for (int q2 = 0; q2 < RG; ++q2) sa[q][q2] = a[(int64_t)j * R + r0 + q2];
+    }
+  };
+  // a box's sources usually fit in one chunk: then they are staged once for
+  // all passes over its (cone, node) items
+  const bool once = np <= LC;
+  if (once) {
+    __syncthreads();
+    stage(0, np);
+    __syncthreads();
+  }
   for (int ib = 0; ib < nitems; ib += BS) {
     const int it = ib + threadIdx.x;
     const bool valid = it < nitems;
@@ -290,24 +322,11 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int r0, con
     for (int q2 = 0; q2 < RG; ++q2) acc[q2] = {0, 0};
     for (int cb = 0; cb < np; cb += LC) {
       const int cn = min(LC, np - cb);
-      __syncthreads();
-      for (int q = threadIdx.x; q < cn; q += BS) {
-        int j = p0 + cb + q;
-        T u0 = (T)((pts[3 * j] - c0) * invh), u1 = (T)((pts[3 * j + 1] - c1) * invh),
-          u2 = (T)((pts[3 * j + 2] - c2) * invh);
-        T n0 = (T)nrm[3 * j], n1 = (T)nrm[3 * j + 1], n2 = (T)nrm[3 * j + 2];
-        su[q][0] = u0;
-        su[q][1] = u1;
-        su[q][2] = u2;
-        sn[q][0] = n0;
-        sn[q][1] = n1;
-        sn[q][2] = n2;
-        suu[q] = u0 * u0 + u1 * u1 + u2 * u2;
-        sun[q] = u0 * n0 + u1 * n1 + u2 * n2;
-#pragma unroll
-        for (int q2 = 0; q2 < RG; ++q2) sa[q][q2] = a[(int64_t)j * R + r0 + q2];
+      if (!once) {
+        __syncthreads();
+        stage(cb, cn);
+        __syncthreads();
       }
-      __syncthreads();
       if (valid) {
         for (int q = 0; q < cn; ++q) {
           cpx<T> W;
@@ -318,8 +337,8 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int r0, con
             T en = e[0] * sn[q][0] + e[1] * sn[q][1] + e[2] * sn[q][2];
             T qq = s * suu[q] - (T)2 * eu;
             T nv = sqrt_t<T>((T)1 + s * qq);
-            T inv = (T)1 / nv;
-            T ph = kh * qq / (nv + (T)1);
+            T inv = rcp_t<T>(nv);
+            T ph = kh * qq * rcp_t<T>(nv + (T)1);
             T sp, cp;
             sincos_t<T>(ph, &sp, &cp);
             T vn = en - s * sun[q];

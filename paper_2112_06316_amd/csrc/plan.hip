@@ -8,6 +8,7 @@
 #include <cstring>
 
 #include <algorithm>
+#include <array>
 
 #include "internal.h"
 
@@ -664,21 +665,41 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
         for (int c = clo[b]; c < clo[b + 1]; ++c)
           cmask[b] |= (uint8_t)(1u << ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) |
                                        ((ccoords[3 * c + 2] & 1) << 2)));
-      std::vector<int> slots(lv.nrel), tiles;
+      // Within a cone id the boxes come in Morton order (slot order); each run
+      // of 4 tiles is sorted by child mask, then cut into tiles.  The tiles
+      // are then ordered by their first box, so that tiles of different cone
+      // ids over the same boxes - which read the same child cones - run
+      // back to back (and, with the XCD-aware block mapping, on one XCD).
+      std::vector<int> slots(lv.nrel);
+      std::vector<std::array<int, 5>> tl;   // (first box, cid, start, count, 0)
       for (int64_t i = 0; i < lv.nrel; ++i) slots[i] = (int)(keys[i] & 0xffffffffu);
       for (int64_t i = 0; i < lv.nrel;) {
         const int cid = (int)(keys[i] >> 32);
         int64_t j = i;
         while (j < lv.nrel && (int)(keys[j] >> 32) == cid) ++j;
-        std::stable_sort(slots.begin() + i, slots.begin() + j,
-                         [&](int x, int y) { return cmask[rbox[x]] < cmask[rbox[y]]; });
-        for (int64_t t = i; t < j; t += cap) {
-          tiles.push_back(cid);
-          tiles.push_back((int)t);
-          tiles.push_back((int)std::min<int64_t>(cap, j - t));
-          tiles.push_back(0);
+        for (int64_t c0 = i; c0 < j; c0 += 4 * cap) {
+          const int64_t c1 = std::min<int64_t>(j, c0 + 4 * cap);
+          std::stable_sort(slots.begin() + c0, slots.begin() + c1,
+                           [&](int x, int y) { return cmask[rbox[x]] < cmask[rbox[y]]; });
+          for (int64_t t = c0; t < c1; t += cap) {
+            const int cnt = (int)std::min<int64_t>(cap, c1 - t);
+            int b0 = rbox[slots[t]];
+            for (int u = 1; u < cnt; ++u) b0 = std::min(b0, rbox[slots[t + u]]);
+            tl.push_back({b0, cid, (int)t, cnt, 0});
+          }
         }
         i = j;
+      }
+      std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
+        return x[0] < y[0];
+      });
+      std::vector<int> tiles;
+      tiles.reserve(tl.size() * 4);
+      for (const auto& t : tl) {
+        tiles.push_back(t[1]);
+        tiles.push_back(t[2]);
+        tiles.push_back(t[3]);
+        tiles.push_back(0);
       }
       lv.ti_nw = nw;
       lv.ntile = (int64_t)tiles.size() / 4;
