@@ -24,6 +24,8 @@
 // served together: the wave repeatedly takes the slot of its first pending
 // lane, makes it wave-uniform with readfirstlane, and every lane holding that
 // slot evaluates with the uniform coefficient pointer.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ifgf {
@@ -1347,43 +1349,66 @@ __global__ __launch_bounds__(64 * NW) void k_prop_ti(
     auto slot_of = [&](int g) -> int {
       return (g < ng && Bc >= 0) ? slot_c[(int64_t)Bc * gc.ncone + sm.gcid[g]] : -1;
     };
-    // Wide loads (16 B where the row is 16-byte aligned) keep the number of
-    // loads in flight - this group's and the next group's - under what the
-    // vector-memory counter can track, so the waits stay per load.
-    auto load_row = [&](int sl, float(&dst)[PA * PA]) {
+    // The A operand is loaded one group ahead.  Where a row is 16-byte aligned
+    // (P = 144) the two lanes of a box (re row, im row; neighbours) each load
+    // every other 16-byte chunk of the cone's slab - 2 coefficients, re and
+    // im - and swap the halves the other one needs (DPP between neighbouring
+    // lanes): 9 loads and 36 registers per row and group, so that this
+    // group's operand and the next group's loads in flight stay within what
+    // the vector-memory counter tracks and within 3 waves per SIMD.
+    constexpr bool QUAD = (PA * PA) % 4 == 0;
+    constexpr int NRAW = QUAD ? PA * PA / 4 : PA * PA;
+    using Raw = typename std::conditional<QUAD, float4, float2>::type;
+    auto load_raw = [&](int sl, Raw(&dst)[NRAW]) {
       if (sl >= 0 && la < PS) {
         const cpx<float>* row = Fc_c + (int64_t)sl * P + la * PA * PA;
-        if constexpr (P % 2 == 0 && (PA * PA) % 2 == 0) {
-          const float4* src = reinterpret_cast<const float4*>(row);
+        if constexpr (QUAD) {
+          const float4* src = reinterpret_cast<const float4*>(row) + reim;   // chunks 2u + reim
 #pragma unroll
-          for (int u = 0; u < PA * PA / 2; ++u) {
-            const float4 v = src[u];
-            dst[2 * u] = reim ? v.y : v.x;
-            dst[2 * u + 1] = reim ? v.w : v.z;
-          }
+          for (int u = 0; u < NRAW; ++u) dst[u] = src[2 * u];
         } else {
 #pragma unroll
-          for (int t = 0; t < PA * PA; ++t) {
-            const cpx<float> v = row[t];
-            dst[t] = reim ? v.im : v.re;
-          }
+          for (int u = 0; u < NRAW; ++u) dst[u] = reinterpret_cast<const float2*>(row)[u];
         }
       } else {
 #pragma unroll
-        for (int t = 0; t < PA * PA; ++t) dst[t] = 0.f;
+        for (int u = 0; u < NRAW; ++u) {
+          if constexpr (QUAD) dst[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+          else dst[u] = make_float2(0.f, 0.f);
+        }
       }
     };
-    float av[PA * PA], an[PA * PA];
+    auto unpack = [&](const Raw(&raw)[NRAW], float(&dst)[PA * PA]) {
+#pragma unroll
+      for (int u = 0; u < NRAW; ++u) {
+        if constexpr (QUAD) {
+          // lane re holds (re, im) of coefficients 4u, 4u+1; lane im those of 4u+2, 4u+3
+          const float4 v = raw[u];
+          const float s0 = reim ? v.x : v.y, s1 = reim ? v.z : v.w;
+          const float r0 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s0), 0xB1, 0xF, 0xF, false));
+          const float r1 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s1), 0xB1, 0xF, 0xF, false));
+          dst[4 * u + 0] = reim ? r0 : v.x;
+          dst[4 * u + 1] = reim ? r1 : v.z;
+          dst[4 * u + 2] = reim ? v.y : r0;
+          dst[4 * u + 3] = reim ? v.w : r1;
+        } else {
+          dst[u] = reim ? raw[u].y : raw[u].x;
+        }
+      }
+    };
+    float av[PA * PA];
+    Raw rn[NRAW];
     int s_cur = -1, s_nxt = -1;
     if (wave_has) {
       s_cur = slot_of(0);
       s_nxt = slot_of(1);
-      load_row(s_cur, av);
+      load_raw(s_cur, rn);
+      unpack(rn, av);
     }
     for (int g = 0; g < (wave_has ? ng : 0); ++g) {
       const int n0 = sm.gstart[g], n1 = sm.gstart[g + 1];
       const int s_nn = slot_of(g + 2);
-      load_row(s_nxt, an);
+      load_raw(s_nxt, rn);
       if (Bc >= 0 && s_cur < 0) atomicOr(err, 2);
       for (int c0 = n0; c0 < n1; c0 += 16) {
         const int e = c0 + li;
@@ -1422,8 +1447,7 @@ __global__ __launch_bounds__(64 * NW) void k_prop_ti(
           }
         }
       }
-#pragma unroll
-      for (int t = 0; t < PA * PA; ++t) av[t] = an[t];
+      unpack(rn, av);
       s_cur = s_nxt;
       s_nxt = s_nn;
     }
