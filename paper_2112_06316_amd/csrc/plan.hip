@@ -630,9 +630,10 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
   }
 
   // ---- cone-major tiles of the upward pass (FP32, one RHS) ------------------------
-  // Boxes per distinct cone id decide the tile height: 32, 16 or 8 boxes
-  // (4, 2 or 1 waves of 8 boxes); AUTO leaves levels with fewer than 6 boxes
-  // per cone id to the node formulation.
+  // Boxes per distinct cone id decide the tile height: 32 boxes (4 waves of
+  // 8) from 12 boxes per cone id on - partly filled 4-wave tiles beat fuller
+  // 2-wave ones, which leave the CU at 2 waves per SIMD - 16 boxes from 6;
+  // AUTO leaves sparser levels to the node formulation (forced CONE: 8).
   if (cone_prop_supported(p)) {
     for (int d = 3; d < D; ++d) {
       LevelPlan& lv = p->lev[d];
@@ -649,7 +650,7 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
       for (int64_t i = 0; i < lv.nrel; ++i)
         if (i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32)) ++ndistinct;
       const double per = (double)lv.nrel / (double)ndistinct;
-      int nw = per >= 24.0 ? 4 : (per >= 12.0 ? 2 : (per >= 6.0 ? 1 : 0));
+      int nw = per >= 12.0 ? 4 : (per >= 6.0 ? 2 : 0);
       if (p->opt.prop_kernel == IFGF_PROP_CONE && nw == 0) nw = 1;
       if (nw == 0) continue;
       const int cap = 8 * nw;
