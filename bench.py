@@ -58,7 +58,7 @@ TRAFFIC_SUMMARY = {
 }
 KERNEL_OF_STAGE = {"prop": "k_prop (node formulation)", "prop_cone": "k_prop_ti (cone-major, MFMA)",
                    "targets": "k_targets", "leaf": "k_leaf", "near": "k_near", "coeffs": "k_coeffs"}
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_06316_amd", "csrc", f) for f in ("apply.hip", "common.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_06316_amd", "csrc", f) for f in ("apply.hip", "common.h", "plan.hip")]
 
 
 def kernel_source_sha():
