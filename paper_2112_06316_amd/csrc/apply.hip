@@ -657,9 +657,9 @@ __device__ __forceinline__ void lds_coeffs_store(cpx<T>* v, cpx<T>* t, int nc, c
   }
 }
 
-template <typename T, int PS, int PA> struct PropSmem {
+template <typename T, int PS, int PA, int BS_ = PropShape<PS * PA * PA>::BS> struct PropSmem {
   static constexpr int P = PS * PA * PA;
-  static constexpr int BS = PropShape<P>::BS;
+  static constexpr int BS = BS_;
   static constexpr int NN = PropShape<P>::CH * P;
   static constexpr int HB = NN <= 256 ? 8 : (NN <= 512 ? 9 : (NN <= 1024 ? 10 : 11));   // 2^HB >= NN
   static constexpr int HT = 1 << HB;
@@ -675,16 +675,17 @@ template <typename T, int PS, int PA> struct PropSmem {
 };
 
 // One work item wk = (parent box, first slot, end slot) of the upward pass,
-// right-hand side r, by a block of PropShape::BS threads.  ONE: a single
-// right-hand side (R = 1 at compile time, contiguous cones).
-template <typename T, int PS, int PA, bool ONE>
-__device__ __forceinline__ void prop_item(PropSmem<T, PS, PA>& sm, int4 wk, int r, const int* __restrict__ rel_cone_up,
+// right-hand side r, by a block of BS threads (PropShape::BS in the
+// standalone kernel).  ONE: a single right-hand side (R = 1 at compile time,
+// contiguous cones).
+template <typename T, int PS, int PA, bool ONE, int BS_ = PropShape<PS * PA * PA>::BS>
+__device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_>& sm, int4 wk, int r, const int* __restrict__ rel_cone_up,
                                           const int* __restrict__ child_lo_up, const int* __restrict__ coords,
                                           const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c,
                                           const LevelGeom& gp, const LevelGeom& gc, const ChebTab& ct,
                                           const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind,
                                           int R_, cpx<T>* __restrict__ Fc_up, int* __restrict__ err) {
-  using S = PropSmem<T, PS, PA>;
+  using S = PropSmem<T, PS, PA, BS_>;
   constexpr int P = S::P;
   constexpr int BS = S::BS;
   constexpr int NN = S::NN;
@@ -1234,18 +1235,19 @@ template <int PS, int PA, int NW> struct TiSmem {
   float ms[PS * PS], ma[PA * PA];
 };
 
+// One tile tl = (cone id, first index into ti_slot, boxes) by a block of 64 NW threads.
 template <int PS, int PA, int NW>
-__global__ __launch_bounds__(64 * NW) void k_prop_ti(
-    const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ rel_box_up,
-    const int* __restrict__ child_lo_up, const int* __restrict__ coords, const int* __restrict__ slot_c,
-    const cpx<float>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct, const float* __restrict__ Ms,
-    const float* __restrict__ Ma, double k, int kind, cpx<float>* __restrict__ Fc_up, int* __restrict__ err) {
+__device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, const int* __restrict__ ti_slot,
+                                             const int* __restrict__ rel_box_up, const int* __restrict__ child_lo_up,
+                                             const int* __restrict__ coords, const int* __restrict__ slot_c,
+                                             const cpx<float>* __restrict__ Fc_c, const LevelGeom& gp,
+                                             const LevelGeom& gc, const ChebTab& ct, const float* __restrict__ Ms,
+                                             const float* __restrict__ Ma, double k, int kind,
+                                             cpx<float>* __restrict__ Fc_up, int* __restrict__ err) {
   using S = TiSmem<PS, PA, NW>;
   constexpr int P = S::P;
   constexpr int NB = S::NB;
   constexpr int BS = 64 * NW;
-  __shared__ S sm;
-  const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
   const int q = tl.x, nb = tl.z;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
@@ -1513,6 +1515,17 @@ __global__ __launch_bounds__(64 * NW) void k_prop_ti(
     const int bx = t / P, jn = t % P;
     Fc_up[(int64_t)sm.pslot[bx] * P + jn] = sm.acc[bx][jn];
   }
+}
+
+template <int PS, int PA, int NW>
+__global__ __launch_bounds__(64 * NW) void k_prop_ti(
+    const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ rel_box_up,
+    const int* __restrict__ child_lo_up, const int* __restrict__ coords, const int* __restrict__ slot_c,
+    const cpx<float>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct, const float* __restrict__ Ms,
+    const float* __restrict__ Ma, double k, int kind, cpx<float>* __restrict__ Fc_up, int* __restrict__ err) {
+  __shared__ TiSmem<PS, PA, NW> sm;
+  prop_ti_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, rel_box_up, child_lo_up, coords,
+                           slot_c, Fc_c, gp, gc, ct, Ms, Ma, k, kind, Fc_up, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -2107,11 +2120,14 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
 // counter increment; after a wait every wave issues an agent-scope acquire
 // fence (stale cache lines dropped) before it reads.
 // ---------------------------------------------------------------------------
-enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_COEF = 3, BT_PROP = 4, BT_TARGET = 5 };
+enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_COEF = 3, BT_PROP = 4, BT_TARGET = 5, BT_PROPTI = 6 };
+// Threads per work-group of the batch launch: every stage body runs at this
+// size (the cone-major tiles need 4 waves of 8 boxes).
+constexpr int BBS = 256;
 // Work units per queue item (fewer items, fewer counter updates and fences):
 // gather chunks of BS points, leaf and near-field boxes, upward-pass work
 // items, groups of PropShape::CH cones of the coefficient transform; target
-// items hold BS points.
+// items hold BBS points; a cone-major item is one tile.
 constexpr int BG_GATHER = 4, BG_BOX = 4, BG_PROP = 8, BG_COEF = 8;
 
 template <typename T> struct BLevel {
@@ -2121,11 +2137,14 @@ template <typename T> struct BLevel {
   const int IFGF_GAS* nbr;
   const int IFGF_GAS* slot_off;
   const int IFGF_GAS* rel_cone;
+  const int IFGF_GAS* rel_box;
   const int IFGF_GAS* child_lo;
   const int IFGF_GAS* coords;
   const int IFGF_GAS* slot;
   const double IFGF_GAS* centre;
   const int4 IFGF_GAS* work;
+  const int4 IFGF_GAS* ti_tile;   // cone-major tiles of the pass into this level (FP32)
+  const int IFGF_GAS* ti_slot;
   cpx<T> IFGF_GAS* Fn;
   cpx<T> IFGF_GAS* Fc;
   LevelGeom g;
@@ -2168,9 +2187,10 @@ __device__ __forceinline__ void batch_wait(int* ctr, int dep, int need, int spin
 }
 
 template <typename T, int PS, int PA> struct BatchSmem {
-  static constexpr int BS = PropShape<PS * PA * PA>::BS;
-  static constexpr size_t a = sizeof(PropSmem<T, PS, PA>), b = sizeof(NearSmem<T, 1, BS>), c = sizeof(LeafSmem<T, 1>);
-  static constexpr size_t bytes = a > b ? (a > c ? a : c) : (b > c ? b : c);
+  static constexpr size_t a = sizeof(PropSmem<T, PS, PA, BBS>), b = sizeof(NearSmem<T, 1, BBS>),
+                          c = sizeof(LeafSmem<T, 1>), t = Prec<T>::f32 ? sizeof(TiSmem<PS, PA, 4>) : 0;
+  static constexpr size_t ab = a > b ? a : b, ct = c > t ? c : t;
+  static constexpr size_t bytes = ab > ct ? ab : ct;
 };
 
 // One launch of `total` work-groups; each takes the next ticket of the queue
@@ -2182,14 +2202,14 @@ template <typename T, int PS, int PA> struct BatchSmem {
 // FP32: 3 waves per SIMD, as the standalone upward pass; FP64: 1 (its bodies need
 // more than the 256 registers a wave can address, the rest goes to AGPRs).
 template <typename T, int PS, int PA>
-__global__ __launch_bounds__(PropShape<PS * PA * PA>::BS)
+__global__ __launch_bounds__(BBS)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const BSeg* __restrict__ segs,
                                                                           const int* __restrict__ seg_of, int total,
                                                                           const BGeom<T>* __restrict__ geoms, BIo io,
                                                                           int dtype, int* ctr, int spin_limit,
                                                                           int* berr) {
   constexpr int P = PS * PA * PA;
-  constexpr int BS = PropShape<P>::BS;
+  constexpr int BS = BBS;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int s_item, s_seg;
   if (threadIdx.x == 0) {
@@ -2245,7 +2265,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
     }
     case BT_COEF: {
       // groups of CH cones of the finest level: node values -> coefficients
-      auto& sm = *reinterpret_cast<PropSmem<T, PS, PA>*>(smem);
+      auto& sm = *reinterpret_cast<PropSmem<T, PS, PA, BBS>*>(smem);
       const BLevel<T>& L = G.lv[D];
       constexpr int CH = PropShape<P>::CH;
       if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = G.Ms[threadIdx.x];
@@ -2267,14 +2287,26 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
       const int w1 = min((local + 1) * BG_PROP, lp.nwork);
       for (int w = local * BG_PROP; w < w1; ++w) {
         if (w > local * BG_PROP) __syncthreads();   // LDS reuse
-        prop_item<T, PS, PA, true>(*reinterpret_cast<PropSmem<T, PS, PA>*>(smem), gen(lp.work)[w], 0,
+        prop_item<T, PS, PA, true, BBS>(*reinterpret_cast<PropSmem<T, PS, PA, BBS>*>(smem), gen(lp.work)[w], 0,
                                    gen(lp.rel_cone), gen(lp.child_lo), gen(lc.coords), gen(lc.slot), gen(lc.Fc), lp.g,
                                    lc.g, G.ct, gen(G.Ms), gen(G.Ma), G.k, G.kind, 1, gen(lp.Fc), gen(G.err));
       }
       break;
     }
+    case BT_PROPTI: {
+      if constexpr (Prec<T>::f32) {
+        const int d = S.level;   // child level
+        const BLevel<T>& lc = G.lv[d];
+        const BLevel<T>& lp = G.lv[d - 1];
+        prop_ti_tile<PS, PA, 4>(*reinterpret_cast<TiSmem<PS, PA, 4>*>(smem), gen(lp.ti_tile)[local],
+                                gen(lp.ti_slot), gen(lp.rel_box), gen(lp.child_lo), gen(lc.coords), gen(lc.slot),
+                                gen(lc.Fc), lp.g, lc.g, G.ct, gen(G.Ms), gen(G.Ma), G.k, G.kind, gen(lp.Fc),
+                                gen(G.err));
+      }
+      break;
+    }
     case BT_TARGET: {
-      auto& sm = *reinterpret_cast<PropSmem<T, PS, PA>*>(smem);
+      auto& sm = *reinterpret_cast<PropSmem<T, PS, PA, BBS>*>(smem);
       const int dlo = D >= 3 ? 3 : 1, dhi = D >= 3 ? D : 0;
       target_point<T, PS, PA>(sm.cbuf[threadIdx.x >> 6], (int64_t)local * BS + threadIdx.x, 0, gen(G.pts), G.n,
                               gen(G.perm), gen(G.uacc), 1, G.tl, dlo, dhi, G.k, G.kind, 1, dtype, 0, nullptr,
@@ -2303,7 +2335,7 @@ __global__ __launch_bounds__(TPB) void k_zero_i32(int* __restrict__ x, int n) {
 template <typename T, int PS, int PA>
 void batch_prepare_impl(ifgf_batch_s* b) {
   constexpr int P = PS * PA * PA;
-  constexpr int BS = PropShape<P>::BS;
+  constexpr int BS = BBS;
   constexpr int CH = PropShape<P>::CH;
   const int ng = (int)b->plans.size();
   std::vector<BGeom<T>> geo(ng);
@@ -2337,11 +2369,14 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       L.nbr = gas(l.nbr.as<const int>());
       L.slot_off = gas(l.slot_off.as<const int>());
       L.rel_cone = gas(l.rel_cone.as<const int>());
+      L.rel_box = gas(l.rel_box.as<const int>());
       L.child_lo = gas(l.child_lo.as<const int>());
       L.coords = gas(l.coords.as<const int>());
       L.slot = gas(l.slot.as<const int>());
       L.centre = gas(l.centre.as<const double>());
       L.work = gas(l.work.as<const int4>());
+      L.ti_tile = gas(l.ti_tile.as<const int4>());
+      L.ti_slot = gas(l.ti_slot.as<const int>());
       L.Fn = gas(l.Fn.as<cpx<T>>());
       L.Fc = gas(l.Fc.as<cpx<T>>());
       L.g = l.geom;
@@ -2415,8 +2450,10 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       if (d < 4) continue;
       const LevelPlan& lp = p->lev[d - 1];
       if (lp.nrel == 0 || lp.nwork == 0) continue;
-      const int64_t cnt = (lp.nwork + BG_PROP - 1) / BG_PROP;
-      emit(BT_PROP, g, d, cnt, last[g].first, last[g].second, -1, 0, C(g, K_PROP0 + d - 1));
+      // the cone-major tiles where the plan has them (FP32), else node work items
+      const bool ti = Prec<T>::f32 && lp.ntile > 0;
+      const int64_t cnt = ti ? lp.ntile : (lp.nwork + BG_PROP - 1) / BG_PROP;
+      emit(ti ? BT_PROPTI : BT_PROP, g, d, cnt, last[g].first, last[g].second, -1, 0, C(g, K_PROP0 + d - 1));
       last[g] = {C(g, K_PROP0 + d - 1), (int)cnt};
     }
     for (int g = 0; g < ng; ++g)
