@@ -1194,6 +1194,167 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma(int nrel_up, const int* __res
   }
 }
 
+// Upward pass for RHS group blockIdx.y with the nodes grouped by child cone:
+// one work-group per parent slot.  For each child, the P node geometries are
+// computed once and grouped by child cone; the waves then evaluate, per
+// group, OUT[row][e] = sum_k C[row][k] B[k][e] with rows = 16 RHS (one tile
+// for re, one for im) of the child cone's coefficients and columns = 16
+// nodes of the group, so that no column of an MFMA tile belongs to another
+// cone.  ratio * OUT is added to the node values in LDS (one writer per
+// (node, RHS) per child: deterministic); they are written to level d-1.
+template <int PS, int PA> struct BcSmem {
+  static constexpr int P = PS * PA * PA;
+  static constexpr int NBAS = PS + 2 * PA;
+  static constexpr int BAS_LD = NBAS | 1;
+  cpx<float> acc[P][MF_RG + 1];   // node values for the 16 RHS of the group (padded row)
+  float bas[P][BAS_LD];
+  float rat[P][2];
+  int cid[P];
+  short order[P];
+  int gstart[P + 1], gcid[P];
+  int ngroup;
+};
+
+template <int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ rel_box_up,
+                                                        const int* __restrict__ rel_cone_up,
+                                                        const int* __restrict__ child_lo_up,
+                                                        const int* __restrict__ coords, const int* __restrict__ slot_c,
+                                                        const cpx<float>* __restrict__ Fc_c, LevelGeom gp,
+                                                        LevelGeom gc, ChebTab ct, double k, int kind, int R,
+                                                        cpx<float>* __restrict__ Fn_up, int* __restrict__ err) {
+  using S = BcSmem<PS, PA>;
+  constexpr int P = S::P;
+  constexpr int NWV = TPB / 64;
+  __shared__ S sm;
+  const int sp = xcd_block(blockIdx.x, gridDim.x);
+  const int g = blockIdx.y;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, la = lane >> 4;
+  const int Pb = rel_box_up[sp], q = rel_cone_up[sp];
+  for (int t = threadIdx.x; t < P * (MF_RG + 1); t += TPB) sm.acc[t / (MF_RG + 1)][t % (MF_RG + 1)] = {0.f, 0.f};
+  const int B0 = child_lo_up[Pb], B1 = child_lo_up[Pb + 1];
+  for (int B = B0; B < B1; ++B) {
+    const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+    __syncthreads();   // previous child's groups and geometry no longer read
+    for (int n = threadIdx.x; n < P; n += TPB) {
+      float x[3], rp;
+      node_rel32(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
+      const PropF pr = child_loc32(x, rp, oct, gc);
+      sm.cid[n] = pr.loc.cid;
+      cheb_T<float, PS>(pr.loc.ts, &sm.bas[n][0]);
+      cheb_T<float, PA>(pr.loc.tt, &sm.bas[n][PS]);
+      cheb_T<float, PA>(pr.loc.tp, &sm.bas[n][PS + PA]);
+      float c_ = 1.f, s_ = 0.f, rr = 1.f;
+      if (kind != IFGF_KERNEL_CONSTANT) {
+        sincos_f((float)k * pr.dr, &s_, &c_);
+        rr = pr.rp_over_rc;
+      }
+      sm.rat[n][0] = rr * c_;
+      sm.rat[n][1] = rr * s_;
+    }
+    __syncthreads();
+    if (wv == 0) {   // group the nodes by child cone
+      constexpr int NPL = (P + 63) / 64;
+      int cv[NPL];
+      bool pend[NPL];
+#pragma unroll
+      for (int m = 0; m < NPL; ++m) {
+        const int n = lane + 64 * m;
+        pend[m] = n < P;
+        cv[m] = pend[m] ? sm.cid[n] : 0;
+      }
+      int pos = 0, ng = 0;
+      while (true) {
+        int lead = -1, su = 0;
+#pragma unroll
+        for (int m = 0; m < NPL && lead < 0; ++m) {
+          const uint64_t b = __ballot(pend[m]);
+          if (b) {
+            lead = first_lane(b);
+            su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
+          }
+        }
+        if (lead < 0) break;
+        if (lane == 0) {
+          sm.gstart[ng] = pos;
+          sm.gcid[ng] = su;
+        }
+#pragma unroll
+        for (int m = 0; m < NPL; ++m) {
+          const bool hit = pend[m] && cv[m] == su;
+          const uint64_t b = __ballot(hit);
+          if (hit) sm.order[pos + __popcll(b & ((1ull << lane) - 1))] = (short)(lane + 64 * m);
+          pos += __popcll(b);
+          pend[m] = pend[m] && !hit;
+        }
+        ++ng;
+      }
+      if (lane == 0) {
+        sm.gstart[ng] = pos;
+        sm.ngroup = ng;
+      }
+    }
+    __syncthreads();
+    // column tiles of all groups, dealt to the waves in turn
+    const int ng = sm.ngroup;
+    int tile = 0;
+    for (int gi = 0; gi < ng; ++gi) {
+      const int n0 = sm.gstart[gi], n1 = sm.gstart[gi + 1];
+      for (int c0 = n0; c0 < n1; c0 += 16, ++tile) {
+        if (tile % NWV != wv) continue;
+        const int sl = slot_c[(int64_t)B * gc.ncone + sm.gcid[gi]];
+        if (sl < 0) {
+          if (lane == 0) atomicOr(err, 2);
+          continue;
+        }
+        const int e = c0 + li;
+        const int n = e < n1 ? sm.order[e] : -1;
+        float ta = 0.f, tt[PA], tp[PA];
+        if (n >= 0) {
+          ta = la < PS ? sm.bas[n][min(la, PS - 1)] : 0.f;
+#pragma unroll
+          for (int b = 0; b < PA; ++b) tt[b] = sm.bas[n][PS + b];
+#pragma unroll
+          for (int c = 0; c < PA; ++c) tp[c] = sm.bas[n][PS + PA + c];
+        } else {
+#pragma unroll
+          for (int b = 0; b < PA; ++b) tt[b] = tp[b] = 0.f;
+        }
+        // A rows: RHS g*16 + li of coefficient (la, b, c) of the child cone, re (tile 0) and im (tile 1)
+        const cpx<float>* Cs = Fc_c + ((int64_t)sl * P + (la < PS ? la : 0) * PA * PA) * R + g * MF_RG + li;
+        floatx4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < PA; ++b) {
+          const float w = ta * tt[b];
+#pragma unroll
+          for (int c = 0; c < PA; ++c) {
+            const cpx<float> av = la < PS ? Cs[(int64_t)(b * PA + c) * R] : cpx<float>{0.f, 0.f};
+            const float bv = w * tp[c];
+            d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv, d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv, d1, 0, 0, 0);
+          }
+        }
+        // lane 16 r + j: RHS 4r..4r+3 of column j
+        if (e < n1) {
+          const float er = sm.rat[n][0], ei = sm.rat[n][1];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const float vr = d0[v], vi = d1[v];
+            sm.acc[n][4 * la + v].re += er * vr - ei * vi;
+            sm.acc[n][4 * la + v].im += er * vi + ei * vr;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < P * MF_RG; t += TPB) {
+    const int n = t / MF_RG, r = t % MF_RG;
+    Fn_up[((int64_t)sp * P + n) * R + g * MF_RG + r] = sm.acc[n][r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Cone-major upward pass on MFMA (FP32, one right-hand side).
 //
@@ -1942,8 +2103,9 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           const int64_t items = (int64_t)lp.nrel * P;
           {
             StageTimer tm(p, s, IFGF_STAGE_PROP);
-            k_prop_mfma<PS, PA><<<dim3(nblocks(items), R / MF_RG), TPB, 0, s>>>(
-                lp.nrel, lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
+            (void)items;
+            k_prop_mfma_cone<PS, PA><<<dim3((unsigned)lp.nrel, R / MF_RG), TPB, 0, s>>>(
+                lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
                 lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, p->k, kind, R,
                 p->scratch_fn.as<cpx<T>>(), p->err.as<int>());
           }
