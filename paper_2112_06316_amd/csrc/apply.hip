@@ -1296,18 +1296,29 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
       }
     }
     __syncthreads();
-    // column tiles of all groups, dealt to the waves in turn
+    // whole groups dealt to the waves in turn; a wave loads the group's A
+    // operand (the child cone's coefficients for the 16 RHS, re and im) once
+    // and runs all of the group's column tiles with it
     const int ng = sm.ngroup;
-    int tile = 0;
-    for (int gi = 0; gi < ng; ++gi) {
+    for (int gi = wv; gi < ng; gi += NWV) {
       const int n0 = sm.gstart[gi], n1 = sm.gstart[gi + 1];
-      for (int c0 = n0; c0 < n1; c0 += 16, ++tile) {
-        if (tile % NWV != wv) continue;
-        const int sl = slot_c[(int64_t)B * gc.ncone + sm.gcid[gi]];
-        if (sl < 0) {
-          if (lane == 0) atomicOr(err, 2);
-          continue;
+      const int sl = slot_c[(int64_t)B * gc.ncone + sm.gcid[gi]];
+      if (sl < 0) {
+        if (lane == 0) atomicOr(err, 2);
+        continue;
+      }
+      // A rows: RHS g*16 + li of coefficient (la, b, c) of the child cone
+      float are[PA * PA], aim[PA * PA];
+      {
+        const cpx<float>* Cs = Fc_c + ((int64_t)sl * P + (la < PS ? la : 0) * PA * PA) * R + g * MF_RG + li;
+#pragma unroll
+        for (int t = 0; t < PA * PA; ++t) {
+          const cpx<float> av = la < PS ? Cs[(int64_t)t * R] : cpx<float>{0.f, 0.f};
+          are[t] = av.re;
+          aim[t] = av.im;
         }
+      }
+      for (int c0 = n0; c0 < n1; c0 += 16) {
         const int e = c0 + li;
         const int n = e < n1 ? sm.order[e] : -1;
         float ta = 0.f, tt[PA], tp[PA];
@@ -1321,18 +1332,15 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
 #pragma unroll
           for (int b = 0; b < PA; ++b) tt[b] = tp[b] = 0.f;
         }
-        // A rows: RHS g*16 + li of coefficient (la, b, c) of the child cone, re (tile 0) and im (tile 1)
-        const cpx<float>* Cs = Fc_c + ((int64_t)sl * P + (la < PS ? la : 0) * PA * PA) * R + g * MF_RG + li;
         floatx4 d0 = {0.f, 0.f, 0.f, 0.f}, d1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int b = 0; b < PA; ++b) {
           const float w = ta * tt[b];
 #pragma unroll
           for (int c = 0; c < PA; ++c) {
-            const cpx<float> av = la < PS ? Cs[(int64_t)(b * PA + c) * R] : cpx<float>{0.f, 0.f};
             const float bv = w * tp[c];
-            d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv, d0, 0, 0, 0);
-            d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv, d1, 0, 0, 0);
+            d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(are[b * PA + c], bv, d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aim[b * PA + c], bv, d1, 0, 0, 0);
           }
         }
         // lane 16 r + j: RHS 4r..4r+3 of column j
