@@ -1201,7 +1201,8 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma(int nrel_up, const int* __res
 // for re, one for im) of the child cone's coefficients and columns = 16
 // nodes of the group, so that no column of an MFMA tile belongs to another
 // cone.  ratio * OUT is added to the node values in LDS (one writer per
-// (node, RHS) per child: deterministic); they are written to level d-1.
+// (node, RHS) per child: deterministic); they are turned into coefficients
+// in place and written to level d-1.
 template <int PS, int PA> struct BcSmem {
   static constexpr int P = PS * PA * PA;
   static constexpr int NBAS = PS + 2 * PA;
@@ -1213,6 +1214,7 @@ template <int PS, int PA> struct BcSmem {
   short order[P];
   int gstart[P + 1], gcid[P];
   int ngroup;
+  float ms[PS * PS], ma[PA * PA];
 };
 
 template <int PS, int PA>
@@ -1221,8 +1223,9 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
                                                         const int* __restrict__ child_lo_up,
                                                         const int* __restrict__ coords, const int* __restrict__ slot_c,
                                                         const cpx<float>* __restrict__ Fc_c, LevelGeom gp,
-                                                        LevelGeom gc, ChebTab ct, double k, int kind, int R,
-                                                        cpx<float>* __restrict__ Fn_up, int* __restrict__ err) {
+                                                        LevelGeom gc, ChebTab ct, const float* __restrict__ Ms,
+                                                        const float* __restrict__ Ma, double k, int kind, int R,
+                                                        cpx<float>* __restrict__ Fc_up, int* __restrict__ err) {
   using S = BcSmem<PS, PA>;
   constexpr int P = S::P;
   constexpr int NWV = TPB / 64;
@@ -1233,6 +1236,8 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
   const int li = lane & 15, la = lane >> 4;
   const int Pb = rel_box_up[sp], q = rel_cone_up[sp];
   for (int t = threadIdx.x; t < P * (MF_RG + 1); t += TPB) sm.acc[t / (MF_RG + 1)][t % (MF_RG + 1)] = {0.f, 0.f};
+  if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = Ms[threadIdx.x];
+  if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
   const int B0 = child_lo_up[Pb], B1 = child_lo_up[Pb + 1];
   for (int B = B0; B < B1; ++B) {
     const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
@@ -1356,10 +1361,65 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
       }
     }
   }
+  // node values -> coefficients, in place, one line of one RHS per thread and pass
+  __syncthreads();
+  for (int t = threadIdx.x; t < PA * PA * MF_RG; t += TPB) {   // over a (s)
+    const int bc = t / MF_RG, r = t % MF_RG;
+    cpx<float> v[PS], w[PS];
+#pragma unroll
+    for (int a = 0; a < PS; ++a) v[a] = sm.acc[a * PA * PA + bc][r];
+#pragma unroll
+    for (int i = 0; i < PS; ++i) {
+      w[i] = {0.f, 0.f};
+#pragma unroll
+      for (int a = 0; a < PS; ++a) {
+        w[i].re += sm.ms[i * PS + a] * v[a].re;
+        w[i].im += sm.ms[i * PS + a] * v[a].im;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PS; ++i) sm.acc[i * PA * PA + bc][r] = w[i];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < PS * PA * MF_RG; t += TPB) {   // over b (theta)
+    const int ic = t / MF_RG, r = t % MF_RG, i = ic / PA, c = ic % PA;
+    cpx<float> v[PA], w[PA];
+#pragma unroll
+    for (int b = 0; b < PA; ++b) v[b] = sm.acc[(i * PA + b) * PA + c][r];
+#pragma unroll
+    for (int j = 0; j < PA; ++j) {
+      w[j] = {0.f, 0.f};
+#pragma unroll
+      for (int b = 0; b < PA; ++b) {
+        w[j].re += sm.ma[j * PA + b] * v[b].re;
+        w[j].im += sm.ma[j * PA + b] * v[b].im;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PA; ++j) sm.acc[(i * PA + j) * PA + c][r] = w[j];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < PS * PA * MF_RG; t += TPB) {   // over c (phi)
+    const int ij = t / MF_RG, r = t % MF_RG;
+    cpx<float> v[PA], w[PA];
+#pragma unroll
+    for (int c = 0; c < PA; ++c) v[c] = sm.acc[ij * PA + c][r];
+#pragma unroll
+    for (int l = 0; l < PA; ++l) {
+      w[l] = {0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < PA; ++c) {
+        w[l].re += sm.ma[l * PA + c] * v[c].re;
+        w[l].im += sm.ma[l * PA + c] * v[c].im;
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < PA; ++l) sm.acc[ij * PA + l][r] = w[l];
+  }
   __syncthreads();
   for (int t = threadIdx.x; t < P * MF_RG; t += TPB) {
     const int n = t / MF_RG, r = t % MF_RG;
-    Fn_up[((int64_t)sp * P + n) * R + g * MF_RG + r] = sm.acc[n][r];
+    Fc_up[((int64_t)sp * P + n) * R + g * MF_RG + r] = sm.acc[n][r];
   }
 }
 
@@ -2096,12 +2156,6 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
       HIPCHK(hipGetLastError());
     }
     const bool mfma = Prec<T>::f32 && R % MF_RG == 0 && PS <= 4;
-    if (mfma) {
-      // RHS groups of 16 on MFMA: node values into a scratch level, then coefficients
-      size_t need = 0;
-      for (int d = 3; d < D; ++d) need = std::max(need, sizeof(cpx<T>) * (size_t)p->lev[d].nrel * P * R);
-      if (p->scratch_fn.bytes < need) p->scratch_fn.alloc(need);
-    }
     for (int d = D; d >= 4; --d) {
       LevelPlan& lc = p->lev[d];
       LevelPlan& lp = p->lev[d - 1];
@@ -2114,14 +2168,8 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
             (void)items;
             k_prop_mfma_cone<PS, PA><<<dim3((unsigned)lp.nrel, R / MF_RG), TPB, 0, s>>>(
                 lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
-                lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, p->k, kind, R,
-                p->scratch_fn.as<cpx<T>>(), p->err.as<int>());
-          }
-          HIPCHK(hipGetLastError());
-          {
-            StageTimer tm(p, s, IFGF_STAGE_COEFFS);
-            k_coeffs_rg<T, PS, PA, MF_RG><<<dim3(lp.nrel, R / MF_RG), TPB, 0, s>>>(p->scratch_fn.as<cpx<T>>(), R, Ms,
-                                                                                  Ma, lp.Fc.as<cpx<T>>());
+                lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms,
+                (const float*)Ma, p->k, kind, R, lp.Fc.as<cpx<T>>(), p->err.as<int>());
           }
           HIPCHK(hipGetLastError());
           continue;

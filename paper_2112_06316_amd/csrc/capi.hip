@@ -206,7 +206,7 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
     int64_t bytes = 0;
     auto add = [&](const DevBuf& b) { bytes += (int64_t)b.bytes; };
     add(p->perm); add(p->keys); add(p->pts); add(p->nrm); add(p->w); add(p->a); add(p->uacc); add(p->err);
-    add(p->Ms); add(p->Ma); add(p->Msf); add(p->Maf); add(p->scratch_fn);
+    add(p->Ms); add(p->Ma); add(p->Msf); add(p->Maf);
     for (int d = 1; d <= p->D; ++d) {
       const LevelPlan& l = p->lev[d];
       st->boxes[d] = l.nb;

@@ -89,7 +89,6 @@ struct ifgf_plan_s {
   ifgf::DevBuf a;             // gathered coefficients w * sigma, [n][max_rhs] complex (plan precision)
   ifgf::DevBuf uacc;          // near-field results, [n][max_rhs] complex (plan precision)
   ifgf::DevBuf adj_g[IFGF_MAX_LEVELS];   // transposed-apply coefficient-space buffers
-  ifgf::DevBuf scratch_fn;    // node values of one level for the batched (MFMA) upward pass
   ifgf::DevBuf err;           // int [4] device error flags
   int64_t near_pairs = 0;
   // kernel timing (ifgf_plan_set_profiling)
