@@ -318,7 +318,7 @@ def main():
             "stages": {k2: {"ms_per_apply": v2[0] / args.batched_steps, "launches_per_apply": v2[1] / args.batched_steps}
                        for k2, v2 in profb.items()},
             "roofline_prop": {"bound": "mfma", "achieved": ach, "peak": 157.3, "unit": "TFLOP/s",
-                              "frac": (ach / 157.3) if ach else None, "kernel": "k_prop_mfma",
+                              "frac": (ach / 157.3) if ach else None, "kernel": "k_prop_mfma_cone",
                               "algorithmic_flops_per_apply": flops_prop},
         }
         del planb, Ub, Sb_d

@@ -1126,74 +1126,6 @@ __global__ __launch_bounds__(TPB) void k_targets_mfma(const double* __restrict__
   }
 }
 
-// Upward pass for RHS group blockIdx.y: one lane per (parent slot, node),
-// the children of its parent in turn; writes node values of level d-1.
-template <int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_prop_mfma(int nrel_up, const int* __restrict__ rel_box_up,
-                                                   const int* __restrict__ rel_cone_up,
-                                                   const int* __restrict__ child_lo_up, const int* __restrict__ coords,
-                                                   const int* __restrict__ slot_c, const cpx<float>* __restrict__ Fc_c,
-                                                   LevelGeom gp, LevelGeom gc, ChebTab ct, double k, int kind, int R,
-                                                   cpx<float>* __restrict__ Fn_up, int* __restrict__ err) {
-  constexpr int P = PS * PA * PA;
-  constexpr int NR = MfRec<PS, PA>::NR;
-  __shared__ float rec[TPB / 64][64 * NR];
-  const int g = blockIdx.y;
-  const int l = threadIdx.x & 63;
-  const int64_t nitem = (int64_t)nrel_up * P;
-  const int64_t t0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB + threadIdx.x;
-  const bool valid = t0 < nitem;
-  const int64_t t = valid ? t0 : nitem - 1;
-  const int sp = (int)(t / P), node = (int)(t % P);
-  const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
-  const int Pb = rel_box_up[sp], pcid = rel_cone_up[sp];
-  float x[3], rp;
-  node_rel32(pcid, ai, bi, ci, gp, ct, x, &rp);
-  cpx<float> tot[4][4];
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) tot[b][q] = {0.f, 0.f};
-  const int B0 = child_lo_up[Pb], nch = child_lo_up[Pb + 1] - B0;
-  int cmax = nch;
-  for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, 64));
-  for (int c = 0; c < cmax; ++c) {
-    const bool has = valid && c < nch;
-    const int B = B0 + min(c, nch - 1);
-    const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
-    PropF pr = child_loc32(x, rp, oct, gc);
-    int sl = slot_c[(int64_t)B * gc.ncone + pr.loc.cid];
-    if (sl < 0 && has) atomicOr(err, 2);
-    float rr = pr.rp_over_rc, c_, s_;
-    if (kind == IFGF_KERNEL_CONSTANT) {
-      c_ = 1;
-      s_ = 0;
-      rr = 1;
-    } else {
-      sincos_f((float)k * pr.dr, &s_, &c_);
-    }
-    float fre = rr * c_, fim = rr * s_;
-    if (!has) {
-      sl = -1;
-      fre = fim = 0;
-    }
-    wave_eval_mfma<PS, PA>(Fc_c, R, g, sl, pr.loc.ts, pr.loc.tt, pr.loc.tp, fre, fim, rec[threadIdx.x >> 6], tot);
-  }
-  const int64_t wbase = t0 - l;
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int64_t ti = wbase + 16 * b + (l & 15);
-    if (ti >= nitem) continue;
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-      for (int p2 = 0; p2 < 2; ++p2) {
-        const int rr = g * MF_RG + 8 * rt + 2 * (l >> 4) + p2;
-        Fn_up[ti * R + rr] = tot[b][2 * rt + p2];
-      }
-  }
-}
-
 // Upward pass for RHS group blockIdx.y with the nodes grouped by child cone:
 // one work-group per parent slot.  For each child, the P node geometries are
 // computed once and grouped by child cone; the waves then evaluate, per
