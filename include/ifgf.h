@@ -86,6 +86,9 @@ typedef struct {
     int32_t kernel;         /* IFGF_KERNEL_*; default IFGF_KERNEL_COMBINED                  */
     int32_t prop_kernel;    /* upward pass with one right-hand side in FP32: IFGF_PROP_AUTO
                                (default), IFGF_PROP_NODE or IFGF_PROP_CONE (below)          */
+    int32_t target_kernel;  /* cousin-target stage with one right-hand side in FP32:
+                               IFGF_TARGET_AUTO (default), IFGF_TARGET_WAVE or
+                               IFGF_TARGET_ROWS (below)                                    */
 } ifgf_options;
 
 /* Upward-pass formulation (FP32, nrhs = 1; FP64 and other nrhs always use
@@ -99,6 +102,18 @@ typedef struct {
  * levels where the boxes per parent cone id fill its tiles.  Both give the
  * same operator up to FP32 rounding. */
 enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2 };
+
+/* Cousin-target formulation (Algorithm 1, target evaluation; FP32 with
+ * nrhs = 1 — FP64 and other nrhs always use their own kernels).  WAVE: a
+ * lane per target walks its box's cousin list; the wave stages each distinct
+ * cone it meets in LDS and the lanes holding that cone contract against it.
+ * ROWS: the 16 lanes of a row walk the merged cousin lists of their targets
+ * together, load the row's current cone across the row and contract with the
+ * coefficients broadcast between lanes (no LDS); levels run as separate
+ * work-groups and are added afterwards, which needs n x (D - 2) FP32 complex
+ * values of plan memory.  AUTO = ROWS.  Both give the same operator up to
+ * FP32 rounding. */
+enum { IFGF_TARGET_AUTO = 0, IFGF_TARGET_WAVE = 1, IFGF_TARGET_ROWS = 2 };
 
 /* Plan statistics (host struct). */
 #define IFGF_MAX_LEVELS 12

@@ -14,6 +14,7 @@ PREC_FP64, PREC_FP32_INTERP = 0, 1
 C64, C128 = 0, 1
 KERNEL_COMBINED, KERNEL_CONSTANT = 0, 1
 PROP_AUTO, PROP_NODE, PROP_CONE = 0, 1, 2
+TARGET_AUTO, TARGET_WAVE, TARGET_ROWS = 0, 1, 2
 STAGES = ["gather", "near", "leaf", "coeffs", "prop", "targets", "adj_targets", "adj_prop", "adj_coeffs",
           "adj_leaf", "adj_near", "adj_out", "prop_cone"]
 
@@ -30,6 +31,7 @@ class Options(ctypes.Structure):
         ("max_rhs", ctypes.c_int32),
         ("kernel", ctypes.c_int32),
         ("prop_kernel", ctypes.c_int32),
+        ("target_kernel", ctypes.c_int32),
     ]
 
 

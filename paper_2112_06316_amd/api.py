@@ -24,6 +24,7 @@ def library_path() -> str:
 _PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32_INTERP}
 _KERNEL = {"combined": L.KERNEL_COMBINED, "constant": L.KERNEL_CONSTANT}
 _PROP = {"auto": L.PROP_AUTO, "node": L.PROP_NODE, "cone": L.PROP_CONE}
+_TARGET = {"auto": L.TARGET_AUTO, "wave": L.TARGET_WAVE, "rows": L.TARGET_ROWS}
 
 
 def _stream_ptr(device) -> int:
@@ -47,7 +48,7 @@ class Plan:
 
     def __init__(self, points, normals, weights, k, eta, *, p_s=4, p_ang=6, ns0=2, nc0=4, depth=0,
                  leaf_h_lambda=0.5, precision="fp32", max_rhs=1, kernel="combined", prop_kernel="auto",
-                 device="cuda"):
+                 target_kernel="auto", device="cuda"):
         lib = L.load()
         self._lib = lib
         self.device = torch.device(device)
@@ -68,6 +69,7 @@ class Plan:
         o.max_rhs = int(max_rhs)
         o.kernel = _KERNEL[kernel]
         o.prop_kernel = _PROP[prop_kernel]
+        o.target_kernel = _TARGET[target_kernel]
         self.options = o
         h = ctypes.c_void_p()
         st = lib.ifgf_plan_create(ctypes.byref(h), n, pts.data_ptr(), nrm.data_ptr(), w.data_ptr(),

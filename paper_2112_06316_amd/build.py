@@ -32,6 +32,8 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
+    # generated asm of the row-broadcast target contraction
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_row_stage1.py")], check=True)
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"

@@ -934,6 +934,183 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
 }
 
 // ---------------------------------------------------------------------------
+// Cousin targets, FP32, one right-hand side: row-broadcast formulation.
+//
+// A wave takes 64 consecutive (Morton-order) targets at one level d; a row of
+// 16 lanes holds 16 neighbouring targets.  Each row walks the merged,
+// ascending cousin lists of its lanes: at each step the row takes the
+// smallest cousin box B still pending in any of its lanes, and the lanes
+// whose list holds B evaluate B's interpolant at their target.  Such targets
+// are close together and mostly fall in one cone of B; the row loads that
+// cone's 2P coefficients across its 16 lanes (one float4 per lane per 64
+// floats) and every lane contracts against them with the coefficients
+// broadcast from their lanes by DPP (RowStage1), so four rows of a wave serve
+// four cones at once and no coefficient passes through LDS.  Lanes whose
+// cone differs from the row's current one wait for a further round.  Each
+// lane sums its cousins in ascending box order: deterministic.  The level's
+// sum goes to part[d - dlo][i]; k_targets_sum adds the levels.
+// ---------------------------------------------------------------------------
+#include "row_stage1.inc"
+
+// Minimum of v over the 16 lanes of each row.
+__device__ __forceinline__ int row_min16(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));    // quad_perm [1,0,3,2]
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));    // quad_perm [2,3,0,1]
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));   // row_half_mirror
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));   // row_mirror
+  return v;
+}
+
+// Lane nl (0..15) of a row loads its share of one cone's 2P floats: float
+// 64 m + 4 nl + e into register 4 m + e.  Registers past the cone stay 0.
+template <int P, int NREG>
+__device__ __forceinline__ void row_load_cone(const float* __restrict__ src, int nl, float (&c)[NREG]) {
+#pragma unroll
+  for (int m = 0; m < NREG / 4; ++m) {
+    const int off = 64 * m + 4 * nl;
+    if constexpr (P % 2 == 0) {   // cone base 16-byte aligned
+      float4 v = {0, 0, 0, 0};
+      if (off + 4 <= 2 * P) v = *reinterpret_cast<const float4*>(src + off);
+      c[4 * m] = v.x;
+      c[4 * m + 1] = v.y;
+      c[4 * m + 2] = v.z;
+      c[4 * m + 3] = v.w;
+    } else {                      // 8-byte aligned
+      float2 a = {0, 0}, b = {0, 0};
+      if (off + 2 <= 2 * P) a = *reinterpret_cast<const float2*>(src + off);
+      if (off + 4 <= 2 * P) b = *reinterpret_cast<const float2*>(src + off + 2);
+      c[4 * m] = a.x;
+      c[4 * m + 1] = a.y;
+      c[4 * m + 2] = b.x;
+      c[4 * m + 3] = b.y;
+    }
+  }
+}
+
+template <int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets_rows(const double* __restrict__ pts, int64_t n, TLevels<float> L,
+                                                      int dlo, double k, int kind, float2* __restrict__ part,
+                                                      int* __restrict__ err) {
+  constexpr int P = PS * PA * PA;
+  using S1 = RowStage1<PS, PA>;
+  constexpr int NREG = S1::NREG;
+  const int nchunk = (int)gridDim.x;
+  const int lin = xcd_block((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+  const int d = dlo + lin / nchunk;
+  const int64_t i0 = (int64_t)(lin % nchunk) * TPB + threadIdx.x;
+  const TLevel<float>& lv = L.lv[d];
+  const bool valid = i0 < n;
+  const int64_t i = valid ? i0 : n - 1;
+  const double x[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+  int ptr = 0, end = 0;
+  if (valid) {
+    const int A = lv.pbox[i];
+    ptr = lv.cou_off[A];
+    end = lv.cou_off[A + 1];
+  }
+  constexpr int NONE = 0x7fffffff;
+  int nxt = ptr < end ? lv.cou[ptr] : NONE;
+  const int nl = threadIdx.x & 15;
+  const float* F = reinterpret_cast<const float*>(gen(lv.Fc));
+  const float inv4pi = (float)(1.0 / (4.0 * IFGF_PI));
+  float acc_re = 0, acc_im = 0;
+  while (true) {
+    const int B = row_min16(nxt);
+    if (__ballot(B != NONE) == 0) break;
+    int sl = NONE;
+    float ts = 0, tt = 0, tp = 0, e_re = 0, e_im = 0;
+    if (nxt == B && B != NONE) {
+      double rr;
+      const LocF loc = target_loc32(x, gen(lv.centre) + 3 * B, lv.g, &rr);
+      ts = loc.ts;
+      tt = loc.tt;
+      tp = loc.tp;
+      if (kind == IFGF_KERNEL_CONSTANT) {
+        e_re = 1;
+        e_im = 0;
+      } else {
+        float c, s;
+        expi_reduced32(k * rr, &c, &s);
+        const float g = inv4pi / (float)rr;
+        e_re = g * c;
+        e_im = g * s;
+      }
+      const int s0 = lv.slot[(int64_t)B * lv.g.ncone + loc.cid];
+      if (s0 < 0)
+        atomicOr(err, 4);
+      else
+        sl = s0;
+      ++ptr;
+      nxt = ptr < end ? lv.cou[ptr] : NONE;
+    }
+    float Ts[PS], Tt[PA], Tp[PA];
+    cheb_T<float, PS>(ts, Ts);
+    cheb_T<float, PA>(tt, Tt);
+    cheb_T<float, PA>(tp, Tp);
+    bool pend = sl != NONE;
+    while (__ballot(pend)) {
+      const int su = row_min16(pend ? sl : NONE);
+      float c[NREG];
+      row_load_cone<P, NREG>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, c);
+      float D[2 * PS * PA];
+      S1::run(c, Tp, D);
+      float h_re[PS], h_im[PS];
+#pragma unroll
+      for (int a = 0; a < PS; ++a) {
+        h_re[a] = D[2 * a * PA];
+        h_im[a] = D[2 * a * PA + 1];
+#pragma unroll
+        for (int b = 1; b < PA; ++b) {
+          h_re[a] += D[2 * (a * PA + b)] * Tt[b];
+          h_im[a] += D[2 * (a * PA + b) + 1] * Tt[b];
+        }
+      }
+      float v_re = h_re[0], v_im = h_im[0];
+#pragma unroll
+      for (int a = 1; a < PS; ++a) {
+        v_re += h_re[a] * Ts[a];
+        v_im += h_im[a] * Ts[a];
+      }
+      if (pend && sl == su) {
+        acc_re += e_re * v_re - e_im * v_im;
+        acc_im += e_re * v_im + e_im * v_re;
+        pend = false;
+      }
+    }
+  }
+  if (valid) part[(int64_t)(d - dlo) * n + i] = {acc_re, acc_im};
+}
+
+// u = near field + the level sums of k_targets_rows (levels from the finest
+// down, as target_point adds them), scattered to the caller's order; one
+// right-hand side.
+__global__ __launch_bounds__(TPB) void k_targets_sum(int64_t n, const int* __restrict__ perm,
+                                                     const cpx<float>* __restrict__ uacc, int use_near,
+                                                     const float2* __restrict__ part, int nlev, int dtype,
+                                                     void* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  double re = 0, im = 0;
+  if (use_near) {
+    re = uacc[i].re;
+    im = uacc[i].im;
+  }
+  for (int l = nlev - 1; l >= 0; --l) {
+    const float2 v = part[(int64_t)l * n + i];
+    re += v.x;
+    im += v.y;
+  }
+  const int64_t o = perm[i];
+  if (dtype == IFGF_C128) {
+    ((double*)u)[2 * o] = re;
+    ((double*)u)[2 * o + 1] = im;
+  } else {
+    ((float*)u)[2 * o] = (float)re;
+    ((float*)u)[2 * o + 1] = (float)im;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Batched right-hand sides on MFMA (FP32 mode, nrhs a multiple of 16).
 //
 // For the 64 evaluations held by a wave (one per lane: a target and a cousin
@@ -2152,6 +2329,22 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
       k_targets_mfma<PS, PA><<<dim3(nblocks(n), R / MF_RG), TPB, 0, s>>>(p->pts.as<double>(), n, p->perm.as<int>(),
                                                                         uacc, near ? 1 : 0, L, dlo, dhi, p->k, kind, R,
                                                                         dtype, u, p->err.as<int>());
+      HIPCHK(hipGetLastError());
+      return;
+    }
+  }
+  if constexpr (Prec<T>::f32) {
+    if (R == 1 && p->opt.target_kernel != IFGF_TARGET_WAVE) {
+      StageTimer tm(p, s, IFGF_STAGE_TARGETS);
+      const int nlev = dlo <= dhi ? dhi - dlo + 1 : 0;
+      if ((size_t)nlev * n * sizeof(float2) > p->tpart.bytes) throw Error{IFGF_EINTERNAL, "target level buffer"};
+      float2* part = p->tpart.as<float2>();
+      if (nlev > 0) {
+        k_targets_rows<PS, PA><<<dim3(nblocks(n), nlev), TPB, 0, s>>>(p->pts.as<double>(), n, L, dlo, p->k, kind,
+                                                                      part, p->err.as<int>());
+        HIPCHK(hipGetLastError());
+      }
+      k_targets_sum<<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), uacc, near ? 1 : 0, part, nlev, dtype, u);
       HIPCHK(hipGetLastError());
       return;
     }

@@ -108,6 +108,7 @@ void ifgf_options_default(ifgf_options* o) {
   o->max_rhs = 1;
   o->kernel = IFGF_KERNEL_COMBINED;
   o->prop_kernel = IFGF_PROP_AUTO;
+  o->target_kernel = IFGF_TARGET_AUTO;
 }
 
 const char* ifgf_status_string(ifgf_status st) {
@@ -144,6 +145,8 @@ ifgf_status ifgf_plan_create(ifgf_plan* out, int64_t n, const double* points, co
     if (o.precision != IFGF_PREC_FP64 && o.precision != IFGF_PREC_FP32_INTERP) throw Error{IFGF_EINVAL, "bad precision"};
     if (o.max_rhs < 1) throw Error{IFGF_EINVAL, "max_rhs must be >= 1"};
     if (o.prop_kernel < IFGF_PROP_AUTO || o.prop_kernel > IFGF_PROP_CONE) throw Error{IFGF_EINVAL, "bad prop_kernel"};
+    if (o.target_kernel < IFGF_TARGET_AUTO || o.target_kernel > IFGF_TARGET_ROWS)
+      throw Error{IFGF_EINVAL, "bad target_kernel"};
     if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
     if (!supported_order(o.p_s, o.p_ang)) throw Error{IFGF_EUNSUPPORTED, "p_s/p_ang pair not compiled in"};
     p = new ifgf_plan_s();
@@ -206,6 +209,7 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
     int64_t bytes = 0;
     auto add = [&](const DevBuf& b) { bytes += (int64_t)b.bytes; };
     add(p->perm); add(p->keys); add(p->pts); add(p->nrm); add(p->w); add(p->a); add(p->uacc); add(p->err);
+    add(p->tpart);
     add(p->Ms); add(p->Ma); add(p->Msf); add(p->Maf);
     for (int d = 1; d <= p->D; ++d) {
       const LevelPlan& l = p->lev[d];

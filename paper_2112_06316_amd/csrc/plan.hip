@@ -201,6 +201,24 @@ __global__ __launch_bounds__(TPB) void k_cousins(const int* __restrict__ coords,
   if (!off) cnt_or_idx[b] = c;
 }
 
+// Sorts each box's list ascending (insertion sort; lists hold at most
+// 6^3 - 3^3 boxes).  The target stage merges the lists of neighbouring
+// targets, which needs a common order.
+__global__ __launch_bounds__(TPB) void k_sort_segments(const int* __restrict__ off, int* __restrict__ idx, int nb) {
+  int b = blockIdx.x * TPB + threadIdx.x;
+  if (b >= nb) return;
+  const int lo = off[b], hi = off[b + 1];
+  for (int t = lo + 1; t < hi; ++t) {
+    const int v = idx[t];
+    int u = t - 1;
+    while (u >= lo && idx[u] > v) {
+      idx[u + 1] = idx[u];
+      --u;
+    }
+    idx[u + 1] = v;
+  }
+}
+
 // Pair counts for statistics: sum over boxes of npts(b) * sum_{j in list(b)} npts(j)
 // (targets x sources) when `per_target` = 1, or sum_b sum_{j} npts(j) otherwise.
 __global__ __launch_bounds__(TPB) void k_pair_stats(const int* __restrict__ start, int nb, const int* __restrict__ off,
@@ -483,6 +501,8 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
     k_cousins<<<nblocks(lv.nb), TPB, 0, s>>>(lv.coords.as<int>(), lv.parent.as<int>(), lv.nb, up.nbr_off.as<int>(),
                                             up.nbr.as<int>(), up.child_lo.as<int>(), lv.cou_off.as<int>(), lv.cou.as<int>());
     HIPCHK(hipGetLastError());
+    k_sort_segments<<<nblocks(lv.nb), TPB, 0, s>>>(lv.cou_off.as<int>(), lv.cou.as<int>(), lv.nb);
+    HIPCHK(hipGetLastError());
   }
   // statistics and duplicate check
   {
@@ -721,6 +741,7 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
   }
   p->a.alloc(csz * (size_t)n * R);
   p->uacc.alloc(csz * (size_t)n * R);
+  if (f32 && p->opt.target_kernel != IFGF_TARGET_WAVE && D >= 3) p->tpart.alloc(sizeof(float) * 2 * (size_t)n * (D - 2));
   p->err.alloc(sizeof(int) * 4);
   HIPCHK(hipMemsetAsync(p->err.p, 0, sizeof(int) * 4, s));
   HIPCHK(hipStreamSynchronize(s));

@@ -38,10 +38,12 @@ def test_status_strings_and_defaults_without_gpu():
     lib.ifgf_options_default(ctypes.byref(o))
     assert (o.p_s, o.p_ang, o.ns0, o.nc0, o.depth, o.max_rhs) == (4, 6, 2, 4, 0, 1)
     assert o.leaf_h_lambda == 0.5
+    assert (o.prop_kernel, o.target_kernel) == (_lib.PROP_AUTO, _lib.TARGET_AUTO)
 
 
 def test_struct_layout_matches_header():
     # offsets of the C structs as laid out by a C compiler for x86-64
-    assert ctypes.sizeof(_lib.Options) == 48
+    assert ctypes.sizeof(_lib.Options) == 56
     assert _lib.Options.leaf_h_lambda.offset == 24
+    assert _lib.Options.target_kernel.offset == 48
     assert _lib.Stats.boxes.offset == 64
