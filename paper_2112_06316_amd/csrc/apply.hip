@@ -1541,8 +1541,9 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
 // K(x, y_B)/K(x, y_P) - depends on (q, o, node) only, not on the box.  A
 // work item is one cone id q and up to 8 NW parent boxes holding it.  For
 // each octant the block computes the P node geometries once and groups the
-// nodes by child cone; then each wave evaluates, for its 8 boxes, the child
-// interpolants at the nodes of a group as the product
+// nodes by child cone; then each wave evaluates, for 8 boxes that have a
+// child in octant o (the octant's boxes are packed into the waves' rows),
+// the child interpolants at the nodes of a group as the product
 //     OUT[row][e] = sum_k C[row][k] B[k][e],
 // rows = 8 boxes x (re, im) of the child cone's coefficients, columns = 16
 // nodes of the group, B[k][e] = T_a(ts_e) T_b(tt_e) T_c(tp_e), on
@@ -1568,6 +1569,8 @@ template <int PS, int PA, int NW> struct TiSmem {
   int gstart[P + 1], gcid[P];
   int ngroup;
   int child[NB][8];            // child box per (box, octant), -1 if none
+  signed char olist[8][NB];    // per octant: the tile's boxes with a child there, ascending
+  int ocnt[8];
   int pslot[NB];               // parent slot of each box
   int anychild;                // bit o: some box of the tile has a child in octant o
   float ms[PS * PS], ma[PA * PA];
@@ -1609,12 +1612,21 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
     atomicOr(&sm.anychild, mask);
   }
   __syncthreads();
+  if (threadIdx.x < 8) {   // per octant, the boxes that have a child in it (MFMA rows are packed with them)
+    const int o = threadIdx.x;
+    int c = 0;
+    for (int t = 0; t < nb; ++t)
+      if (sm.child[t][o] >= 0) sm.olist[o][c++] = (signed char)t;
+    sm.ocnt[o] = c;
+  }
+  __syncthreads();
   const int anychild = sm.anychild;
 
-  // this lane's A rows and B columns
+  // this lane's A rows and B columns; in each octant, the wave's 8 rows are
+  // entries 8 wv .. 8 wv + 7 of that octant's box list
   const int li = lane & 15;       // A row (box, re/im) and B / OUT column
   const int la = lane >> 4;       // index within the 4-wide K step: the radial index a
-  const int lbox = wv * 8 + (li >> 1), reim = li & 1;
+  const int reim = li & 1;
 
   for (int o = 0; o < 8; ++o) {
     if (!((anychild >> o) & 1)) continue;   // block-uniform
@@ -1684,8 +1696,10 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
     // software-pipelined: while group g is evaluated, the coefficients of
     // group g+1 and the slot of group g+2 are in flight.
     const int ng = sm.ngroup;
-    const int Bc = lbox < nb ? sm.child[lbox][o] : -1;
-    const bool wave_has = __ballot(Bc >= 0) != 0;   // some box of this wave has a child in octant o
+    const int no = sm.ocnt[o];
+    const int le = wv * 8 + (li >> 1);
+    const int Bc = le < no ? sm.child[sm.olist[o][le]][o] : -1;
+    const bool wave_has = 8 * wv < no;   // wave-uniform: the octant's list reaches this wave's rows
     auto slot_of = [&](int g) -> int {
       return (g < ng && Bc >= 0) ? slot_c[(int64_t)Bc * gc.ncone + sm.gcid[g]] : -1;
     };
@@ -1778,8 +1792,9 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
           const float er = sm.rat[nn][0], ei = sm.rat[nn][1];
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            const int bx = wv * 8 + 2 * la + h;
-            if (bx < nb && sm.child[bx][o] >= 0) {
+            const int e2 = wv * 8 + 2 * la + h;
+            if (e2 < no) {
+              const int bx = sm.olist[o][e2];
               const float vr = d[2 * h], vi = d[2 * h + 1];
               sm.acc[bx][nn].re += er * vr - ei * vi;
               sm.acc[bx][nn].im += er * vi + ei * vr;

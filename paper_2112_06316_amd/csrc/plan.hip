@@ -686,11 +686,15 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
         for (int c = clo[b]; c < clo[b + 1]; ++c)
           cmask[b] |= (uint8_t)(1u << ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) |
                                        ((ccoords[3 * c + 2] & 1) << 2)));
-      // Within a cone id the boxes come in Morton order (slot order); each run
-      // of 4 tiles is sorted by child mask, then cut into tiles.  The tiles
-      // are then ordered by their first box, so that tiles of different cone
-      // ids over the same boxes - which read the same child cones - run
-      // back to back (and, with the XCD-aware block mapping, on one XCD).
+      // Within a cone id the boxes come in Morton order (slot order); they are
+      // sorted by child mask (stable: Morton order within a mask), then cut
+      // into tiles, so that the boxes of a tile - and the 8 rows of a wave -
+      // mostly have children in the same octants (MFMA rows of a box without
+      // a child in the current octant are wasted, and a wave whose boxes have
+      // none waits at the octant's barriers).  The tiles are then ordered by
+      // their first box, so that tiles of different cone ids over the same
+      // boxes - which read the same child cones - run back to back (and, with
+      // the XCD-aware block mapping, on one XCD).
       std::vector<int> slots(lv.nrel);
       std::vector<std::array<int, 5>> tl;   // (first box, cid, start, count, 0)
       for (int64_t i = 0; i < lv.nrel; ++i) slots[i] = (int)(keys[i] & 0xffffffffu);
@@ -698,16 +702,13 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
         const int cid = (int)(keys[i] >> 32);
         int64_t j = i;
         while (j < lv.nrel && (int)(keys[j] >> 32) == cid) ++j;
-        for (int64_t c0 = i; c0 < j; c0 += 4 * cap) {
-          const int64_t c1 = std::min<int64_t>(j, c0 + 4 * cap);
-          std::stable_sort(slots.begin() + c0, slots.begin() + c1,
-                           [&](int x, int y) { return cmask[rbox[x]] < cmask[rbox[y]]; });
-          for (int64_t t = c0; t < c1; t += cap) {
-            const int cnt = (int)std::min<int64_t>(cap, c1 - t);
-            int b0 = rbox[slots[t]];
-            for (int u = 1; u < cnt; ++u) b0 = std::min(b0, rbox[slots[t + u]]);
-            tl.push_back({b0, cid, (int)t, cnt, 0});
-          }
+        std::stable_sort(slots.begin() + i, slots.begin() + j,
+                         [&](int x, int y) { return cmask[rbox[x]] < cmask[rbox[y]]; });
+        for (int64_t t = i; t < j; t += cap) {
+          const int cnt = (int)std::min<int64_t>(cap, j - t);
+          int b0 = rbox[slots[t]];
+          for (int u = 1; u < cnt; ++u) b0 = std::min(b0, rbox[slots[t + u]]);
+          tl.push_back({b0, cid, (int)t, cnt, 0});
         }
         i = j;
       }
