@@ -987,33 +987,29 @@ __device__ __forceinline__ void row_load_cone(const float* __restrict__ src, int
   }
 }
 
+// Sum over the cousins at level d of the lane's target x (valid: the lane
+// holds a target; i: its Morton index, any in-range index when !valid).
+// Every lane of the wave must call it together with the same level.
 template <int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_targets_rows(const double* __restrict__ pts, int64_t n, TLevels<float> L,
-                                                      int dlo, double k, int kind, float2* __restrict__ part,
-                                                      int* __restrict__ err) {
+__device__ __forceinline__ void rows_level(const TLevel<float>& lv, const double (&x)[3], bool valid, int64_t i,
+                                           double k, int kind, int* __restrict__ err, float& acc_re,
+                                           float& acc_im) {
   constexpr int P = PS * PA * PA;
   using S1 = RowStage1<PS, PA>;
   constexpr int NREG = S1::NREG;
-  const int nchunk = (int)gridDim.x;
-  const int lin = xcd_block((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
-  const int d = dlo + lin / nchunk;
-  const int64_t i0 = (int64_t)(lin % nchunk) * TPB + threadIdx.x;
-  const TLevel<float>& lv = L.lv[d];
-  const bool valid = i0 < n;
-  const int64_t i = valid ? i0 : n - 1;
-  const double x[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+  constexpr int NONE = 0x7fffffff;
   int ptr = 0, end = 0;
   if (valid) {
     const int A = lv.pbox[i];
     ptr = lv.cou_off[A];
     end = lv.cou_off[A + 1];
   }
-  constexpr int NONE = 0x7fffffff;
   int nxt = ptr < end ? lv.cou[ptr] : NONE;
   const int nl = threadIdx.x & 15;
   const float* F = reinterpret_cast<const float*>(gen(lv.Fc));
   const float inv4pi = (float)(1.0 / (4.0 * IFGF_PI));
-  float acc_re = 0, acc_im = 0;
+  acc_re = 0;
+  acc_im = 0;
   while (true) {
     const int B = row_min16(nxt);
     if (__ballot(B != NONE) == 0) break;
@@ -1078,6 +1074,21 @@ __global__ __launch_bounds__(TPB) void k_targets_rows(const double* __restrict__
       }
     }
   }
+}
+
+template <int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets_rows(const double* __restrict__ pts, int64_t n, TLevels<float> L,
+                                                      int dlo, double k, int kind, float2* __restrict__ part,
+                                                      int* __restrict__ err) {
+  const int nchunk = (int)gridDim.x;
+  const int lin = xcd_block((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
+  const int d = dlo + lin / nchunk;
+  const int64_t i0 = (int64_t)(lin % nchunk) * TPB + threadIdx.x;
+  const bool valid = i0 < n;
+  const int64_t i = valid ? i0 : n - 1;
+  const double x[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+  float acc_re, acc_im;
+  rows_level<PS, PA>(L.lv[d], x, valid, i, k, kind, err, acc_re, acc_im);
   if (valid) part[(int64_t)(d - dlo) * n + i] = {acc_re, acc_im};
 }
 
@@ -2511,6 +2522,7 @@ template <typename T> struct BLevel {
 template <typename T> struct BGeom {
   int64_t n;
   int D, kind;
+  int trows;   // FP32 cousin targets in the row-broadcast formulation
   double k, eta;
   const double IFGF_GAS* pts;
   const double IFGF_GAS* nrm;
@@ -2664,11 +2676,41 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
       break;
     }
     case BT_TARGET: {
-      auto& sm = *reinterpret_cast<PropSmem<T, PS, PA, BBS>*>(smem);
       const int dlo = D >= 3 ? 3 : 1, dhi = D >= 3 ? D : 0;
-      target_point<T, PS, PA>(sm.cbuf[threadIdx.x >> 6], (int64_t)local * BS + threadIdx.x, 0, gen(G.pts), G.n,
-                              gen(G.perm), gen(G.uacc), 1, G.tl, dlo, dhi, G.k, G.kind, 1, dtype, 0, nullptr,
-                              io.u[S.geom], gen(G.err));
+      bool rows = false;
+      if constexpr (Prec<T>::f32) rows = G.trows != 0;
+      if (rows) {
+        // the row-broadcast formulation, all levels in turn (as the separate
+        // apply adds them: near field, then the levels from the finest down)
+        const int64_t i0 = (int64_t)local * BS + threadIdx.x;
+        const bool valid = i0 < G.n;
+        const int64_t i = valid ? i0 : G.n - 1;
+        const double* P3 = gen(G.pts) + 3 * i;
+        const double x[3] = {P3[0], P3[1], P3[2]};
+        const cpx<T> un = gen(G.uacc)[i];
+        double re = un.re, im = un.im;
+        for (int d = dhi; d >= dlo; --d) {
+          float lr = 0, li = 0;
+          if constexpr (Prec<T>::f32) rows_level<PS, PA>(G.tl.lv[d], x, valid, i, G.k, G.kind, gen(G.err), lr, li);
+          re += lr;
+          im += li;
+        }
+        if (valid) {
+          const int64_t o = gen(G.perm)[i];
+          if (dtype == IFGF_C128) {
+            ((double*)io.u[S.geom])[2 * o] = re;
+            ((double*)io.u[S.geom])[2 * o + 1] = im;
+          } else {
+            ((float*)io.u[S.geom])[2 * o] = (float)re;
+            ((float*)io.u[S.geom])[2 * o + 1] = (float)im;
+          }
+        }
+      } else {
+        auto& sm = *reinterpret_cast<PropSmem<T, PS, PA, BBS>*>(smem);
+        target_point<T, PS, PA>(sm.cbuf[threadIdx.x >> 6], (int64_t)local * BS + threadIdx.x, 0, gen(G.pts), G.n,
+                                gen(G.perm), gen(G.uacc), 1, G.tl, dlo, dhi, G.k, G.kind, 1, dtype, 0, nullptr,
+                                io.u[S.geom], gen(G.err));
+      }
       break;
     }
     default:
@@ -2704,6 +2746,7 @@ void batch_prepare_impl(ifgf_batch_s* b) {
     G.n = p->n;
     G.D = p->D;
     G.kind = p->opt.kernel;
+    G.trows = Prec<T>::f32 && p->opt.target_kernel != IFGF_TARGET_WAVE;
     G.k = p->k;
     G.eta = p->eta;
     G.pts = gas(p->pts.as<const double>());
