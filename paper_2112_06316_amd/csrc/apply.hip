@@ -1572,7 +1572,7 @@ template <int PS, int PA, int NW> struct TiSmem {
   // different boxes (acc) fall in different LDS banks.
   static constexpr int BAS_LD = NBAS | 1;
   static constexpr int ACC_LD = P + 4;
-  cpx<float> acc[NB][ACC_LD];  // node values of the tile's boxes
+  cpx<float> acc[NB + 1][ACC_LD];  // node values of the tile's boxes; row NB takes unused updates
   float bas[P][BAS_LD];        // per node, current octant: T_a(ts), T_b(tt), T_c(tp)
   float rat[P][2];             // ratio K(x, y_B) / K(x, y_P)
   int cid[P];                  // child cone id
@@ -1775,20 +1775,35 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
       const int s_nn = slot_of(g + 2);
       load_raw(s_nxt, rn);
       if (Bc >= 0 && s_cur < 0) atomicOr(err, 2);
+      // The column tiles of the group.  Branch-free: a column past the group
+      // gets a zero basis, and the accumulation of a tile - deferred to the
+      // next tile's iteration so that it can run under that tile's MFMAs -
+      // sends unused (column, row) entries to the spare row NB.
+      // lane 16 r + j holds rows 4r..4r+3 = boxes 2r, 2r+1 (re, im) of column j
+      const int e2a = wv * 8 + 2 * la, e2b = e2a + 1;
+      const int bxa = e2a < no ? (int)sm.olist[o][e2a] : NB, bxb = e2b < no ? (int)sm.olist[o][e2b] : NB;
+      floatx4 dq = {0.f, 0.f, 0.f, 0.f};
+      int qn = 0, qa = NB, qb = NB;
+      auto flush = [&]() {
+        const float er = sm.rat[qn][0], ei = sm.rat[qn][1];
+        cpx<float>& ua = sm.acc[qa][qn];
+        cpx<float>& ub = sm.acc[qb][qn];
+        ua.re += er * dq[0] - ei * dq[1];
+        ua.im += er * dq[1] + ei * dq[0];
+        ub.re += er * dq[2] - ei * dq[3];
+        ub.im += er * dq[3] + ei * dq[2];
+      };
       for (int c0 = n0; c0 < n1; c0 += 16) {
         const int e = c0 + li;
-        const int n = e < n1 ? sm.order[e] : -1;
-        float ta = 0.f, tt[PA], tp[PA];
-        if (n >= 0) {
-          ta = la < PS ? sm.bas[n][min(la, PS - 1)] : 0.f;
+        const bool ok = e < n1;
+        const int n = sm.order[ok ? e : n0];
+        const float ta = (ok && la < PS) ? sm.bas[n][min(la, PS - 1)] : 0.f;
+        float tt[PA], tp[PA];
 #pragma unroll
-          for (int b = 0; b < PA; ++b) tt[b] = sm.bas[n][PS + b];
+        for (int b = 0; b < PA; ++b) tt[b] = sm.bas[n][PS + b];
 #pragma unroll
-          for (int c = 0; c < PA; ++c) tp[c] = sm.bas[n][PS + PA + c];
-        } else {
-#pragma unroll
-          for (int b = 0; b < PA; ++b) tt[b] = tp[b] = 0.f;
-        }
+        for (int c = 0; c < PA; ++c) tp[c] = sm.bas[n][PS + PA + c];
+        flush();   // the previous tile's (the first time: zeros to the spare row)
         floatx4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int b = 0; b < PA; ++b) {
@@ -1796,23 +1811,12 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
 #pragma unroll
           for (int c = 0; c < PA; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b * PA + c], w * tp[c], d, 0, 0, 0);
         }
-        // lane 16 r + j holds rows 4r..4r+3 = boxes 2r, 2r+1 (re, im) of column j
-        const int col = c0 + li;
-        if (col < n1) {
-          const int nn = sm.order[col];
-          const float er = sm.rat[nn][0], ei = sm.rat[nn][1];
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int e2 = wv * 8 + 2 * la + h;
-            if (e2 < no) {
-              const int bx = sm.olist[o][e2];
-              const float vr = d[2 * h], vi = d[2 * h + 1];
-              sm.acc[bx][nn].re += er * vr - ei * vi;
-              sm.acc[bx][nn].im += er * vi + ei * vr;
-            }
-          }
-        }
+        dq = d;
+        qn = n;
+        qa = ok ? bxa : NB;
+        qb = ok ? bxb : NB;
       }
+      if (n1 > n0) flush();
       unpack(rn, av);
       s_cur = s_nxt;
       s_nxt = s_nn;
