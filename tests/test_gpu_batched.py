@@ -64,3 +64,24 @@ def test_batched_constant_kernel_exact():
     A = w[:, None] * S
     ref = A.sum(0)[None, :] - A
     assert np.abs(U - ref).max() <= 2e-5 * np.abs(A).sum(0).max()
+
+
+def test_batched_64_plane_waves_sphere16_sampled():
+    # the batched workload at full size: N = 98,304 (16 wavelengths), D = 6,
+    # 64 plane-wave right-hand sides on MFMA; four columns against the FP64
+    # direct sum at 256 seeded targets
+    log("case batched sphere16, 64 RHS")
+    wl = inputs.workload("sphere16")
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    R = 64
+    S = inputs.plane_wave_densities(p, k, R, seed=inputs.config_seed(3))
+    plan = Plan(p, nr, w, k, k, depth=wl["depth"], precision="fp32", max_rhs=R)
+    U = plan.apply(to_dev(S.astype(np.complex64))).cpu().numpy()
+    assert plan.check() == 0
+    tg = inputs.sample_targets(len(p), 256, seed=inputs.config_seed(3) + 100)
+    cols = [0, 21, 42, 63]
+    ref = direct.apply_c(p, nr, w, k, k, S[:, cols], targets=tg)
+    err = np.linalg.norm(U[tg][:, cols] - ref) / np.linalg.norm(ref)
+    log(f"  rel l2 err {err:.3e}")
+    assert err < 1e-4

@@ -1,0 +1,98 @@
+"""GPU parity at the largest workloads, on sampled outputs.
+
+* The 1.5M-point spheroid (1, 1, 5), 40 wavelengths long: the gradient of
+  L(s) = ||A s - f||^2 through the transposed apply against a central
+  difference along a seeded direction (FP64 plan: the IFGF operator is a
+  fixed linear map, so the difference is exact up to rounding), and the
+  FP32 plan's gradient against the FP64 one.
+* The 6.29M-point sphere at 128 wavelengths (D = 9): the FP32 apply against
+  the FP64 direct sum at 2,048 seeded targets.
+
+Collected after the other GPU tests: they allocate tens of GB and run for
+tens of seconds.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import direct
+from paper_2112_06316_amd import IFGFApply, Plan, inputs
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+@pytest.mark.timeout(600)
+def test_spheroid_40_wavelengths_gradient():
+    wl = inputs.workload("spheroid40")
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    n = len(p)
+    log(f"case spheroid40 gradient: N={n} D={wl['depth']}")
+    s0 = inputs.random_density(n, seed=inputs.config_seed(4))
+    f = inputs.plane_wave_densities(p, k, 1, seed=inputs.config_seed(4) + 1)[:, 0]
+    d = inputs.random_density(n, seed=inputs.config_seed(4) + 2)
+
+    def grad_and_fd(precision):
+        plan = Plan(p, nr, w, k, k, depth=wl["depth"], precision=precision)
+        log(f"  {precision} plan: {plan.stats()['device_bytes'] / 1e9:.2f} GB")
+        cdt = torch.complex128 if precision == "fp64" else torch.complex64
+        ft = to_dev(f).to(cdt)
+
+        def loss(s):
+            u = IFGFApply.apply(s, plan)
+            return torch.sum(torch.abs(u - ft) ** 2)
+
+        s = to_dev(s0).to(cdt).requires_grad_(True)
+        L = loss(s)
+        L.backward()
+        g = s.grad.detach().to(torch.complex128).cpu().numpy()
+        fd = None
+        if precision == "fp64":
+            h = 1e-3
+            with torch.no_grad():
+                Lp = loss(to_dev(s0 + h * d)).item()
+                Lm = loss(to_dev(s0 - h * d)).item()
+            fd = (Lp - Lm) / (2 * h)
+        assert plan.check() == 0
+        plan.close()
+        return g, fd
+
+    g64, fd = grad_and_fd("fp64")
+    an = float(np.real(np.sum(np.conj(g64) * d)))
+    log(f"  directional derivative: autograd {an:.12e}, central difference {fd:.12e}")
+    assert abs(fd - an) <= 1e-5 * abs(an)
+    g32, _ = grad_and_fd("fp32")
+    e = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    log(f"  FP32 gradient vs FP64 gradient: rel l2 {e:.3e}")
+    assert e < 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_sphere_128_wavelengths_sampled():
+    wl = inputs.workload("sphere128")
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    n = len(p)
+    log(f"case sphere128: N={n} D={wl['depth']}")
+    sigma = inputs.random_density(n, seed=inputs.config_seed(5))
+    tg = inputs.sample_targets(n, 2048, seed=inputs.config_seed(5) + 100)
+    plan = Plan(p, nr, w, k, k, depth=wl["depth"], precision="fp32")
+    st = plan.stats()
+    log(f"  plan: {st['device_bytes'] / 1e9:.2f} GB, cones {st['cones']}")
+    u = plan.apply(to_dev(sigma).to(torch.complex64)).cpu().numpy()
+    assert plan.check() == 0
+    plan.close()
+    log("  oracle on sampled targets")
+    ref = direct.apply_c(p, nr, w, k, k, sigma, targets=tg)
+    err = float(np.linalg.norm(u[tg] - ref) / np.linalg.norm(ref))
+    log(f"  rel l2 err = {err:.3e}")
+    assert err < 1e-4
