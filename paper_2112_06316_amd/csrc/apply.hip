@@ -112,7 +112,8 @@ template <typename T, int RG, int BS> struct NearSmem {
 // Near field of finest-level box b, right-hand sides r0 .. r0 + RG - 1, by a
 // block of BS threads.
 template <typename T, bool TR, int RG, int BS>
-__device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int r0, const double* __restrict__ pts,
+__device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int toff, int tcnt, int r0,
+                                         const double* __restrict__ pts,
                                          const double* __restrict__ nrm, const cpx<T>* __restrict__ a, int R,
                                          const int* __restrict__ start, const int* __restrict__ nbr_off,
                                          const int* __restrict__ nbr, const double* __restrict__ centre, double k,
@@ -125,7 +126,7 @@ __device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int r0,
   auto& noff = sm.noff;
   auto& nbox = sm.nbox;
   auto& red = sm.red;
-  const int t0 = start[b], nt = start[b + 1] - t0;
+  const int t0 = start[b] + toff, nt = tcnt;
   const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
   const int nn = nbr_off[b + 1] - nbr_off[b];
   if (threadIdx.x == 0) {
@@ -140,10 +141,26 @@ __device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int r0,
   }
   __syncthreads();
   const int nsrc = noff[nn];
-  // lane mapping: TP targets per pass, S source slices
-  int TP = 1;
-  while (TP < nt && 2 * TP <= BS) TP <<= 1;
-  const int S = BS / TP;   // threads with sl >= S (BS not a power of two) stay idle
+  // lane mapping: TP targets per pass, S = BS / TP source slices (threads
+  // with sl >= S stay idle).  A pass costs about nsrc / S pair evaluations
+  // per thread plus the staging of the sources (about half a pair per
+  // source and block thread), so of the pass counts p from ceil(nt / BS) on
+  // the one with the least p (1/S + 1/(2 BS)) is taken, TP = ceil(nt / p).
+  int TP = 1, S = BS;
+  {
+    float best = 3.0e38f;
+    const int p0 = max(1, (nt + BS - 1) / BS);
+    for (int p = p0; p < p0 + 8; ++p) {
+      const int tp = max(1, (nt + p - 1) / p);
+      const int s = BS / tp;
+      const float c = (float)p * (1.0f / (float)s + 0.5f / (float)BS);
+      if (c < best) {
+        best = c;
+        TP = tp;
+        S = s;
+      }
+    }
+  }
   const int tl = threadIdx.x % TP, sl = threadIdx.x / TP;
   const T kk = (T)k, ee = (T)eta;
   const T inv4pi = (T)(1.0 / (4.0 * IFGF_PI));
@@ -231,15 +248,18 @@ __device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int r0,
   }
 }
 
+// One block per work item (box, first target, target count): boxes with
+// many points are split so that the blocks carry similar work.
 template <typename T, bool TR, int RG>
-__global__ __launch_bounds__(TPB) void k_near(const double* __restrict__ pts, const double* __restrict__ nrm,
-                                              const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
-                                              const int* __restrict__ nbr_off, const int* __restrict__ nbr,
-                                              const double* __restrict__ centre, double k, double eta, int kind,
-                                              cpx<T>* __restrict__ uacc) {
+__global__ __launch_bounds__(TPB) void k_near(const int4* __restrict__ work, const double* __restrict__ pts,
+                                              const double* __restrict__ nrm, const cpx<T>* __restrict__ a, int R,
+                                              const int* __restrict__ start, const int* __restrict__ nbr_off,
+                                              const int* __restrict__ nbr, const double* __restrict__ centre,
+                                              double k, double eta, int kind, cpx<T>* __restrict__ uacc) {
   __shared__ NearSmem<T, RG, TPB> sm;
-  near_box<T, TR, RG, TPB>(sm, xcd_block(blockIdx.x, gridDim.x), blockIdx.y * RG, pts, nrm, a, R, start, nbr_off, nbr,
-                           centre, k, eta, kind, uacc);
+  const int4 wk = work[xcd_block(blockIdx.x, gridDim.x)];
+  near_box<T, TR, RG, TPB>(sm, wk.x, wk.y, wk.z, blockIdx.y * RG, pts, nrm, a, R, start, nbr_off, nbr, centre, k,
+                           eta, kind, uacc);
 }
 
 // ---------------------------------------------------------------------------
@@ -262,7 +282,8 @@ template <typename T, int RG> struct LeafSmem {
 // Leaf factors of finest-level box b, right-hand sides r0 .. r0 + RG - 1, by
 // a block of BS threads.
 template <typename T, int PS, int PA, int RG, int BS>
-__device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int r0, const double* __restrict__ pts,
+__device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int i0, int icnt, int r0,
+                                         const double* __restrict__ pts,
                                          const double* __restrict__ nrm, const cpx<T>* __restrict__ a, int R,
                                          const int* __restrict__ start, const double* __restrict__ centre,
                                          const int* __restrict__ slot_off, const int* __restrict__ rel_cone,
@@ -280,7 +301,7 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int r0, con
   const double c0 = centre[3 * b], c1 = centre[3 * b + 1], c2 = centre[3 * b + 2];
   const double invh = 1.0 / g.h;
   const T kk = (T)k, ee = (T)eta, kh = (T)(k * g.h), ih = (T)invh;
-  const int nitems = ncn * P;
+  const int i1 = min(ncn * P, i0 + icnt);   // this block's (cone, node) items: i0 .. i1 - 1
   // sources of the box, relative to its centre in units of h, staged in LDS
   auto stage = [&](int cb, int cn) {
     for (int q = threadIdx.x; q < cn; q += BS) {
@@ -308,9 +329,9 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int r0, con
     stage(0, np);
     __syncthreads();
   }
-  for (int ib = 0; ib < nitems; ib += BS) {
+  for (int ib = i0; ib < i1; ib += BS) {
     const int it = ib + threadIdx.x;
-    const bool valid = it < nitems;
+    const bool valid = it < i1;
     T e[3] = {0, 0, 0}, s = 0;
     if (valid) {
       int cs = it / P, node = it % P;
@@ -364,15 +385,19 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int r0, con
   }
 }
 
+// One block per work item (box, first item, item count): a box's (cone,
+// node) items are split into chunks so that the blocks carry similar work.
 template <typename T, int PS, int PA, int RG>
-__global__ __launch_bounds__(TPB) void k_leaf(const double* __restrict__ pts, const double* __restrict__ nrm,
-                                              const cpx<T>* __restrict__ a, int R, const int* __restrict__ start,
-                                              const double* __restrict__ centre, const int* __restrict__ slot_off,
-                                              const int* __restrict__ rel_cone, LevelGeom g, ChebTab ct, double k,
-                                              double eta, int kind, cpx<T>* __restrict__ Fn) {
+__global__ __launch_bounds__(TPB) void k_leaf(const int4* __restrict__ work, const double* __restrict__ pts,
+                                              const double* __restrict__ nrm, const cpx<T>* __restrict__ a, int R,
+                                              const int* __restrict__ start, const double* __restrict__ centre,
+                                              const int* __restrict__ slot_off, const int* __restrict__ rel_cone,
+                                              LevelGeom g, ChebTab ct, double k, double eta, int kind,
+                                              cpx<T>* __restrict__ Fn) {
   __shared__ LeafSmem<T, RG> sm;
-  leaf_box<T, PS, PA, RG, TPB>(sm, blockIdx.x, blockIdx.y * RG, pts, nrm, a, R, start, centre, slot_off, rel_cone, g,
-                               ct, k, eta, kind, Fn);
+  const int4 wk = work[xcd_block(blockIdx.x, gridDim.x)];
+  leaf_box<T, PS, PA, RG, TPB>(sm, wk.x, wk.y, wk.z, blockIdx.y * RG, pts, nrm, a, R, start, centre, slot_off,
+                               rel_cone, g, ct, k, eta, kind, Fn);
 }
 
 // ---------------------------------------------------------------------------
@@ -2259,29 +2284,31 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   if (near) {
     StageTimer tm(p, s, IFGF_STAGE_NEAR);
     if (grouped)
-      k_near<T, false, MF_RG><<<dim3(lD.nb, R / MF_RG), TPB, 0, s>>>(
-          p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(), lD.nbr_off.as<int>(), lD.nbr.as<int>(),
-          lD.centre.as<double>(), p->k, p->eta, kind, uacc);
+      k_near<T, false, MF_RG><<<dim3(lD.n_near, R / MF_RG), TPB, 0, s>>>(
+          lD.near_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
+          lD.nbr_off.as<int>(), lD.nbr.as<int>(), lD.centre.as<double>(), p->k, p->eta, kind, uacc);
     else
-      k_near<T, false, 1><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R,
-                                                         lD.start.as<int>(), lD.nbr_off.as<int>(), lD.nbr.as<int>(),
-                                                         lD.centre.as<double>(), p->k, p->eta, kind, uacc);
+      k_near<T, false, 1><<<dim3(lD.n_near, R), TPB, 0, s>>>(lD.near_work.as<int4>(), p->pts.as<double>(),
+                                                             p->nrm.as<double>(), a, R, lD.start.as<int>(),
+                                                             lD.nbr_off.as<int>(), lD.nbr.as<int>(),
+                                                             lD.centre.as<double>(), p->k, p->eta, kind, uacc);
     HIPCHK(hipGetLastError());
   }
   if (D >= 3) {
     const T* Ms = (const T*)(Prec<T>::f32 ? p->Msf.p : p->Ms.p);
     const T* Ma = (const T*)(Prec<T>::f32 ? p->Maf.p : p->Ma.p);
-    {
+    if (lD.n_leaf > 0) {
       StageTimer tm(p, s, IFGF_STAGE_LEAF);
       if (grouped)
-        k_leaf<T, PS, PA, MF_RG><<<dim3(lD.nb, R / MF_RG), TPB, 0, s>>>(
-            p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(), lD.centre.as<double>(),
-            lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta, kind, lD.Fn.as<cpx<T>>());
+        k_leaf<T, PS, PA, MF_RG><<<dim3(lD.n_leaf, R / MF_RG), TPB, 0, s>>>(
+            lD.leaf_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
+            lD.centre.as<double>(), lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta,
+            kind, lD.Fn.as<cpx<T>>());
       else
-        k_leaf<T, PS, PA, 1><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), a, R,
-                                                            lD.start.as<int>(), lD.centre.as<double>(),
-                                                            lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom,
-                                                            p->cheb, p->k, p->eta, kind, lD.Fn.as<cpx<T>>());
+        k_leaf<T, PS, PA, 1><<<dim3(lD.n_leaf, R), TPB, 0, s>>>(
+            lD.leaf_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
+            lD.centre.as<double>(), lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta,
+            kind, lD.Fn.as<cpx<T>>());
     }
     HIPCHK(hipGetLastError());
     if (lD.nrel > 0) {
@@ -2404,9 +2431,10 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
   LevelPlan& lD = p->lev[D];
   {
     StageTimer tm(p, s, IFGF_STAGE_ADJ_NEAR);
-    k_near<T, true, 1><<<dim3(lD.nb, R), TPB, 0, s>>>(p->pts.as<double>(), p->nrm.as<double>(), vs, R,
-                                                   lD.start.as<int>(), lD.nbr_off.as<int>(), lD.nbr.as<int>(),
-                                                   lD.centre.as<double>(), p->k, p->eta, kind, g);
+    k_near<T, true, 1><<<dim3(lD.n_near, R), TPB, 0, s>>>(lD.near_work.as<int4>(), p->pts.as<double>(),
+                                                        p->nrm.as<double>(), vs, R, lD.start.as<int>(),
+                                                        lD.nbr_off.as<int>(), lD.nbr.as<int>(),
+                                                        lD.centre.as<double>(), p->k, p->eta, kind, g);
   }
   HIPCHK(hipGetLastError());
   if (D >= 3) {
@@ -2620,7 +2648,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
       const int b1 = min((local + 1) * BG_BOX, L.nb);
       for (int bx = local * BG_BOX; bx < b1; ++bx) {
         if (bx > local * BG_BOX) __syncthreads();   // LDS reuse
-        near_box<T, false, 1, BS>(*reinterpret_cast<NearSmem<T, 1, BS>*>(smem), bx, 0, gen(G.pts), gen(G.nrm),
+        const int* st = gen(L.start);
+        near_box<T, false, 1, BS>(*reinterpret_cast<NearSmem<T, 1, BS>*>(smem), bx, 0, st[bx + 1] - st[bx], 0,
+                                  gen(G.pts), gen(G.nrm),
                                   gen(G.a), 1, gen(L.start), gen(L.nbr_off), gen(L.nbr), gen(L.centre), G.k, G.eta,
                                   G.kind, gen(G.uacc));
       }
@@ -2631,7 +2661,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
       const int b1 = min((local + 1) * BG_BOX, L.nb);
       for (int bx = local * BG_BOX; bx < b1; ++bx) {
         if (bx > local * BG_BOX) __syncthreads();   // LDS reuse
-        leaf_box<T, PS, PA, 1, BS>(*reinterpret_cast<LeafSmem<T, 1>*>(smem), bx, 0, gen(G.pts), gen(G.nrm),
+        const int* so = gen(L.slot_off);
+        leaf_box<T, PS, PA, 1, BS>(*reinterpret_cast<LeafSmem<T, 1>*>(smem), bx, 0, (so[bx + 1] - so[bx]) * P, 0,
+                                   gen(G.pts), gen(G.nrm),
                                    gen(G.a), 1, gen(L.start), gen(L.centre), gen(L.slot_off), gen(L.rel_cone), L.g,
                                    G.ct, G.k, G.eta, G.kind, gen(L.Fn));
       }

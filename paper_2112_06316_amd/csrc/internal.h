@@ -35,6 +35,9 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+constexpr int kNearChunk = 128;   // targets per near-field work item
+constexpr int kLeafChunk = 1024;  // (cone, node) items per leaf-factor work item
+
 struct LevelPlan {
   int d = 0;
   double H = 0;
@@ -63,6 +66,15 @@ struct LevelPlan {
   // boxes sharing one cone id: int4 (cone id, first index into ti_slot, count, 0)
   DevBuf ti_slot, ti_tile;
   int64_t ntile = 0;
+  // near field at the finest level: int4 [n_near] (box, first target, target
+  // count, 0), boxes split into chunks of at most kNearChunk targets
+  DevBuf near_work;
+  int n_near = 0;
+  // leaf factors at the finest level: int4 [n_leaf] (box, first item, item
+  // count, 0) over the box's (relevant cone, node) items, chunks of at most
+  // kLeafChunk items
+  DevBuf leaf_work;
+  int n_leaf = 0;
   int ti_nw = 0;              // 0: this level uses the node formulation
   // statistics
   int64_t cousin_pairs = 0;

@@ -630,6 +630,39 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
     HIPCHK(hipStreamSynchronize(s));
   }
 
+  // ---- near-field work items at the finest level --------------------------------
+  {
+    LevelPlan& lD = p->lev[D];
+    std::vector<int> st(lD.nb + 1);
+    HIPCHK(hipMemcpy(st.data(), lD.start.p, sizeof(int) * (lD.nb + 1), hipMemcpyDeviceToHost));
+    std::vector<int4> wk;
+    for (int b = 0; b < lD.nb; ++b)
+      for (int t = 0; t < st[b + 1] - st[b]; t += kNearChunk)
+        wk.push_back(make_int4(b, t, std::min(kNearChunk, st[b + 1] - st[b] - t), 0));
+    lD.n_near = (int)wk.size();
+    lD.near_work.alloc(sizeof(int4) * std::max<size_t>(1, wk.size()));
+    if (!wk.empty())
+      HIPCHK(hipMemcpy(lD.near_work.p, wk.data(), sizeof(int4) * wk.size(), hipMemcpyHostToDevice));
+  }
+
+  // ---- leaf-factor work items at the finest level ------------------------------
+  {
+    LevelPlan& lD = p->lev[D];
+    std::vector<int4> wk;
+    if (D >= 3) {
+      std::vector<int> so(lD.nb + 1);
+      HIPCHK(hipMemcpy(so.data(), lD.slot_off.p, sizeof(int) * (lD.nb + 1), hipMemcpyDeviceToHost));
+      for (int b = 0; b < lD.nb; ++b) {
+        const int items = (so[b + 1] - so[b]) * P;
+        for (int t = 0; t < items; t += kLeafChunk) wk.push_back(make_int4(b, t, std::min(kLeafChunk, items - t), 0));
+      }
+    }
+    lD.n_leaf = (int)wk.size();
+    lD.leaf_work.alloc(sizeof(int4) * std::max<size_t>(1, wk.size()));
+    if (!wk.empty())
+      HIPCHK(hipMemcpy(lD.leaf_work.p, wk.data(), sizeof(int4) * wk.size(), hipMemcpyHostToDevice));
+  }
+
   // ---- work items of the upward pass: chunks of each box's relevant cones --------
   const int CH = prop_chunk(P);
   for (int d = 3; d < D; ++d) {
