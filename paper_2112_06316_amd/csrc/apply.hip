@@ -1922,6 +1922,340 @@ __global__ __launch_bounds__(64 * NW) void k_prop_ti(
 }
 
 // ---------------------------------------------------------------------------
+// Cone-major upward pass in FP64 on v_mfma_f64_16x16x4_f64 (one right-hand
+// side): the scheme of prop_ti_tile with complex double coefficients and node
+// values.  Tiles hold up to 8 NW boxes (NW <= 2).  The nodes' local
+// coordinates (ts, tt, tp) are kept in LDS and each lane forms the Chebyshev
+// basis of its column, which keeps a 2-wave block under 49 KB of LDS.  The A
+// operand: the two lanes of a box (re row, im row; neighbours) each load every
+// other complex coefficient of the cone's slab and swap the halves the other
+// one needs (64-bit DPP between neighbouring lanes).
+// ---------------------------------------------------------------------------
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <int PS, int PA, int NW> struct Ti64Smem {
+  static constexpr int P = PS * PA * PA;
+  static constexpr int NB = 8 * NW;
+  static constexpr int ACC_LD = P + 1;
+  cpx<double> acc[NB + 1][ACC_LD];  // node values of the tile's boxes; row NB takes unused updates
+  double crd[P][3];                 // per node, current octant: ts, tt, tp
+  double rat[P][2];                 // ratio K(x, y_B) / K(x, y_P)
+  int cid[P];
+  short order[P];
+  int gstart[P + 1], gcid[P];
+  int ngroup;
+  int child[NB][8];
+  signed char olist[8][NB];
+  int ocnt[8];
+  int pslot[NB];
+  int anychild;
+  double ms[PS * PS], ma[PA * PA];
+};
+
+__device__ __forceinline__ double swap_lane_pair(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
+}
+
+template <int PS, int PA, int NW>
+__device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl, const int* __restrict__ ti_slot,
+                                               const int* __restrict__ rel_box_up,
+                                               const int* __restrict__ child_lo_up, const int* __restrict__ coords,
+                                               const int* __restrict__ slot_c, const cpx<double>* __restrict__ Fc_c,
+                                               const LevelGeom& gp, const LevelGeom& gc, const ChebTab& ct,
+                                               const double* __restrict__ Ms, const double* __restrict__ Ma,
+                                               double k, int kind, cpx<double>* __restrict__ Fc_up,
+                                               int* __restrict__ err) {
+  using S = Ti64Smem<PS, PA, NW>;
+  constexpr int P = S::P;
+  constexpr int NB = S::NB;
+  constexpr int BS = 64 * NW;
+  const int q = tl.x, nb = tl.z;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  // ---- set-up: boxes, their children by octant ----------------------------------
+  if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = Ms[threadIdx.x];
+  if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
+  if (threadIdx.x == 0) sm.anychild = 0;
+  for (int t = threadIdx.x; t < NB * 8; t += BS) sm.child[t >> 3][t & 7] = -1;
+  for (int t = threadIdx.x; t < NB * S::ACC_LD; t += BS) sm.acc[t / S::ACC_LD][t % S::ACC_LD] = {0.0, 0.0};
+  __syncthreads();
+  if (threadIdx.x < nb) {
+    const int sl = ti_slot[tl.y + threadIdx.x];
+    const int Pb = rel_box_up[sl];
+    sm.pslot[threadIdx.x] = sl;
+    int mask = 0;
+    for (int B = child_lo_up[Pb]; B < child_lo_up[Pb + 1]; ++B) {
+      const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+      sm.child[threadIdx.x][oct] = B;
+      mask |= 1 << oct;
+    }
+    atomicOr(&sm.anychild, mask);
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int o = threadIdx.x;
+    int c = 0;
+    for (int t = 0; t < nb; ++t)
+      if (sm.child[t][o] >= 0) sm.olist[o][c++] = (signed char)t;
+    sm.ocnt[o] = c;
+  }
+  __syncthreads();
+  const int anychild = sm.anychild;
+  const int li = lane & 15;       // A row (box, re/im) and B / OUT column
+  const int la = lane >> 4;       // index within the 4-wide K step: the radial index a
+  const int reim = li & 1;
+
+  for (int o = 0; o < 8; ++o) {
+    if (!((anychild >> o) & 1)) continue;   // block-uniform
+    // ---- node geometry in the child frame of octant o ------------------------
+    for (int n = threadIdx.x; n < P; n += BS) {
+      double x[3], rp;
+      node_rel64(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
+      const Prop64 pr = child_loc64(x, rp, o, gc);
+      sm.cid[n] = pr.loc.cid;
+      sm.crd[n][0] = pr.loc.ts;
+      sm.crd[n][1] = pr.loc.tt;
+      sm.crd[n][2] = pr.loc.tp;
+      double c_ = 1.0, s_ = 0.0, rr = 1.0;
+      if (kind != IFGF_KERNEL_CONSTANT) {
+        sincos(k * pr.dr, &s_, &c_);
+        rr = pr.rp_over_rc;
+      }
+      sm.rat[n][0] = rr * c_;
+      sm.rat[n][1] = rr * s_;
+    }
+    __syncthreads();
+    // ---- group the nodes by child cone (wave 0) ----------------------------------
+    if (wv == 0) {
+      constexpr int NPL = (P + 63) / 64;
+      int cv[NPL];
+      bool pend[NPL];
+#pragma unroll
+      for (int m = 0; m < NPL; ++m) {
+        const int n = lane + 64 * m;
+        pend[m] = n < P;
+        cv[m] = pend[m] ? sm.cid[n] : 0;
+      }
+      int pos = 0, g = 0;
+      while (true) {
+        int lead = -1, su = 0;
+#pragma unroll
+        for (int m = 0; m < NPL && lead < 0; ++m) {
+          const uint64_t b = __ballot(pend[m]);
+          if (b) {
+            lead = first_lane(b);
+            su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
+          }
+        }
+        if (lead < 0) break;
+        if (lane == 0) {
+          sm.gstart[g] = pos;
+          sm.gcid[g] = su;
+        }
+#pragma unroll
+        for (int m = 0; m < NPL; ++m) {
+          const bool hit = pend[m] && cv[m] == su;
+          const uint64_t b = __ballot(hit);
+          if (hit) sm.order[pos + __popcll(b & ((1ull << lane) - 1))] = (short)(lane + 64 * m);
+          pos += __popcll(b);
+          pend[m] = pend[m] && !hit;
+        }
+        ++g;
+      }
+      if (lane == 0) {
+        sm.gstart[g] = pos;
+        sm.ngroup = g;
+      }
+    }
+    __syncthreads();
+    // ---- child interpolants on MFMA, group by group -----------------------------------
+    const int ng = sm.ngroup;
+    const int no = sm.ocnt[o];
+    const int le = wv * 8 + (li >> 1);
+    const int Bc = le < no ? sm.child[sm.olist[o][le]][o] : -1;
+    const bool wave_has = 8 * wv < no;
+    auto slot_of = [&](int g) -> int {
+      return (g < ng && Bc >= 0) ? slot_c[(int64_t)Bc * gc.ncone + sm.gcid[g]] : -1;
+    };
+    constexpr bool PAIR = (PA * PA) % 2 == 0;
+    constexpr int NRAW = PAIR ? PA * PA / 2 : PA * PA;
+    auto load_raw = [&](int sl, double2(&dst)[NRAW]) {
+      if (sl >= 0 && la < PS) {
+        const double2* row = reinterpret_cast<const double2*>(Fc_c + (int64_t)sl * P + la * PA * PA);
+#pragma unroll
+        for (int u = 0; u < NRAW; ++u) dst[u] = PAIR ? row[2 * u + reim] : row[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < NRAW; ++u) dst[u] = make_double2(0.0, 0.0);
+      }
+    };
+    auto unpack = [&](const double2(&raw)[NRAW], double(&dst)[PA * PA]) {
+#pragma unroll
+      for (int u = 0; u < NRAW; ++u) {
+        if constexpr (PAIR) {
+          // lane re holds coefficient 2u, lane im coefficient 2u + 1 (re, im each)
+          const double2 v = raw[u];
+          const double r = swap_lane_pair(reim ? v.x : v.y);
+          dst[2 * u] = reim ? r : v.x;
+          dst[2 * u + 1] = reim ? v.y : r;
+        } else {
+          dst[u] = reim ? raw[u].y : raw[u].x;
+        }
+      }
+    };
+    double av[PA * PA];
+    double2 rn[NRAW];
+    int s_cur = -1, s_nxt = -1;
+    if (wave_has) {
+      s_cur = slot_of(0);
+      s_nxt = slot_of(1);
+      load_raw(s_cur, rn);
+      unpack(rn, av);
+    }
+    for (int g = 0; g < (wave_has ? ng : 0); ++g) {
+      const int n0 = sm.gstart[g], n1 = sm.gstart[g + 1];
+      const int s_nn = slot_of(g + 2);
+      load_raw(s_nxt, rn);
+      if (Bc >= 0 && s_cur < 0) atomicOr(err, 2);
+      // The f64 MFMA spreads a lane's four outputs over the rows: element v of
+      // lane 16 r + j is row 4 v + r, i.e. box 2 v + (r >> 1), part r & 1, of
+      // column j.  Lanes r and r ^ 1 (16 apart) exchange their values, and
+      // each lane then adds two boxes: r even elements 0, 1 (boxes r >> 1,
+      // 2 + (r >> 1)), r odd elements 2, 3 (boxes 4 + (r >> 1), 6 + (r >> 1)).
+      // A tile's accumulation is deferred to the next tile's iteration.
+      const bool odd = la & 1;
+      const int e2a = wv * 8 + (odd ? 4 : 0) + (la >> 1), e2b = e2a + 2;
+      const int bxa = e2a < no ? (int)sm.olist[o][e2a] : NB, bxb = e2b < no ? (int)sm.olist[o][e2b] : NB;
+      doublex4 dq = {0.0, 0.0, 0.0, 0.0};
+      int qn = 0, qa = NB, qb = NB;
+      auto xchg = [](double v) {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const int lo = __shfl_xor((int)(unsigned)b, 16, 64), hi = __shfl_xor((int)(unsigned)(b >> 32), 16, 64);
+        return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
+      };
+      auto flush = [&]() {
+        const double o0 = xchg(dq[0]), o1 = xchg(dq[1]), o2 = xchg(dq[2]), o3 = xchg(dq[3]);
+        const double m0 = odd ? dq[2] : dq[0], m1 = odd ? dq[3] : dq[1];
+        const double t0 = odd ? o2 : o0, t1 = odd ? o3 : o1;
+        const double re0 = odd ? t0 : m0, im0 = odd ? m0 : t0, re1 = odd ? t1 : m1, im1 = odd ? m1 : t1;
+        const double er = sm.rat[qn][0], ei = sm.rat[qn][1];
+        cpx<double>& ua = sm.acc[qa][qn];
+        cpx<double>& ub = sm.acc[qb][qn];
+        ua.re += er * re0 - ei * im0;
+        ua.im += er * im0 + ei * re0;
+        ub.re += er * re1 - ei * im1;
+        ub.im += er * im1 + ei * re1;
+      };
+      for (int c0 = n0; c0 < n1; c0 += 16) {
+        const int e = c0 + li;
+        const bool ok = e < n1;
+        const int n = sm.order[ok ? e : n0];
+        double Ts[PS], Tt[PA], Tp[PA];
+        cheb_T<double, PS>(sm.crd[n][0], Ts);
+        cheb_T<double, PA>(sm.crd[n][1], Tt);
+        cheb_T<double, PA>(sm.crd[n][2], Tp);
+        double ta = 0.0;
+#pragma unroll
+        for (int a = 0; a < PS; ++a)
+          if (la == a) ta = Ts[a];
+        if (!ok) ta = 0.0;
+        flush();   // the previous tile's (the first time: zeros to the spare row)
+        doublex4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < PA; ++b) {
+          const double w = ta * Tt[b];
+#pragma unroll
+          for (int c = 0; c < PA; ++c) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[b * PA + c], w * Tp[c], d, 0, 0, 0);
+        }
+        dq = d;
+        qn = n;
+        qa = ok ? bxa : NB;
+        qb = ok ? bxb : NB;
+      }
+      if (n1 > n0) flush();
+      unpack(rn, av);
+      s_cur = s_nxt;
+      s_nxt = s_nn;
+    }
+    __syncthreads();
+  }
+
+  // ---- node values -> coefficients, in place, then to the parent level -------------
+  for (int t = threadIdx.x; t < nb * PA * PA; t += BS) {   // over a (s)
+    const int bx = t / (PA * PA), r = t % (PA * PA);
+    cpx<double> v[PS], w[PS];
+#pragma unroll
+    for (int a = 0; a < PS; ++a) v[a] = sm.acc[bx][a * PA * PA + r];
+#pragma unroll
+    for (int i = 0; i < PS; ++i) {
+      w[i] = {0.0, 0.0};
+#pragma unroll
+      for (int a = 0; a < PS; ++a) {
+        w[i].re += sm.ms[i * PS + a] * v[a].re;
+        w[i].im += sm.ms[i * PS + a] * v[a].im;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PS; ++i) sm.acc[bx][i * PA * PA + r] = w[i];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * PS * PA; t += BS) {   // over b (theta)
+    const int bx = t / (PS * PA), i = (t / PA) % PS, c = t % PA;
+    cpx<double> v[PA], w[PA];
+#pragma unroll
+    for (int b = 0; b < PA; ++b) v[b] = sm.acc[bx][(i * PA + b) * PA + c];
+#pragma unroll
+    for (int j = 0; j < PA; ++j) {
+      w[j] = {0.0, 0.0};
+#pragma unroll
+      for (int b = 0; b < PA; ++b) {
+        w[j].re += sm.ma[j * PA + b] * v[b].re;
+        w[j].im += sm.ma[j * PA + b] * v[b].im;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PA; ++j) sm.acc[bx][(i * PA + j) * PA + c] = w[j];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * PS * PA; t += BS) {   // over c (phi)
+    const int bx = t / (PS * PA), i = (t / PA) % PS, j = t % PA;
+    cpx<double> v[PA], w[PA];
+#pragma unroll
+    for (int c = 0; c < PA; ++c) v[c] = sm.acc[bx][(i * PA + j) * PA + c];
+#pragma unroll
+    for (int l = 0; l < PA; ++l) {
+      w[l] = {0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < PA; ++c) {
+        w[l].re += sm.ma[l * PA + c] * v[c].re;
+        w[l].im += sm.ma[l * PA + c] * v[c].im;
+      }
+    }
+#pragma unroll
+    for (int l = 0; l < PA; ++l) sm.acc[bx][(i * PA + j) * PA + l] = w[l];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nb * P; t += BS) {
+    const int bx = t / P, jn = t % P;
+    Fc_up[(int64_t)sm.pslot[bx] * P + jn] = sm.acc[bx][jn];
+  }
+}
+
+template <int PS, int PA, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_prop_ti64(
+    const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ rel_box_up,
+    const int* __restrict__ child_lo_up, const int* __restrict__ coords, const int* __restrict__ slot_c,
+    const cpx<double>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct, const double* __restrict__ Ms,
+    const double* __restrict__ Ma, double k, int kind, cpx<double>* __restrict__ Fc_up, int* __restrict__ err) {
+  __shared__ Ti64Smem<PS, PA, NW> sm;
+  prop_ti64_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, rel_box_up, child_lo_up, coords,
+                             slot_c, Fc_c, gp, gc, ct, Ms, Ma, k, kind, Fc_up, err);
+}
+
+// ---------------------------------------------------------------------------
 // Transposed apply.  The forward operator is
 //   u = N a + sum_d T_d c_d,  c_D = X L a,  c_{d-1} = X P_d c_d,
 // (N near field, L leaf factors, X node values -> coefficients, P_d upward
@@ -2353,6 +2687,21 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           if (lp.ti_nw == 4) launch(k_prop_ti<PS, PA, 4>, 4);
           else if (lp.ti_nw == 2) launch(k_prop_ti<PS, PA, 2>, 2);
           else launch(k_prop_ti<PS, PA, 1>, 1);
+          HIPCHK(hipGetLastError());
+          continue;
+        }
+      }
+      if constexpr (!Prec<T>::f32 && PS <= 4) {
+        if (R == 1 && lp.ntile > 0) {
+          StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
+          auto launch = [&](auto kern, int nw) {
+            kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
+                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.rel_box.as<int>(), lp.child_lo.as<int>(),
+                lc.coords.as<int>(), lc.slot.as<int>(), lc.Fc.as<cpx<double>>(), lp.geom, lc.geom, p->cheb,
+                (const double*)Ms, (const double*)Ma, p->k, kind, lp.Fc.as<cpx<double>>(), p->err.as<int>());
+          };
+          if (lp.ti_nw == 2) launch(k_prop_ti64<PS, PA, 2>, 2);
+          else launch(k_prop_ti64<PS, PA, 1>, 1);
           HIPCHK(hipGetLastError());
           continue;
         }
@@ -2978,8 +3327,7 @@ int prop_chunk(int P) {
 bool supported_order(int ps, int pa) { return (ps == 3 && pa == 5) || (ps == 4 && pa == 6); }
 
 bool cone_prop_supported(const ifgf_plan_s* p) {
-  return p->opt.precision == IFGF_PREC_FP32_INTERP && p->opt.p_s <= 4 && p->opt.prop_kernel != IFGF_PROP_NODE &&
-         supported_order(p->opt.p_s, p->opt.p_ang);
+  return p->opt.p_s <= 4 && p->opt.prop_kernel != IFGF_PROP_NODE && supported_order(p->opt.p_s, p->opt.p_ang);
 }
 
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask, int level_lo,

@@ -704,6 +704,7 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
         if (i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32)) ++ndistinct;
       const double per = (double)lv.nrel / (double)ndistinct;
       int nw = per >= 12.0 ? 4 : (per >= 6.0 ? 2 : 0);
+      if (!f32 && nw > 2) nw = 2;   // FP64 tiles: at most 16 boxes (LDS)
       if (p->opt.prop_kernel == IFGF_PROP_CONE && nw == 0) nw = 1;
       if (nw == 0) continue;
       const int cap = 8 * nw;

@@ -250,15 +250,18 @@ def test_sphere_32_wavelengths_sampled():
     assert err < 1e-4
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp64", 1e-11)])
 @pytest.mark.parametrize("ps,pa,ns0,nc0,D", [(4, 6, 2, 4, 5), (3, 5, 1, 2, 5), (4, 6, 2, 4, 6)])
-def test_cone_major_upward_pass_equals_node_formulation(ps, pa, ns0, nc0, D):
+def test_cone_major_upward_pass_equals_node_formulation(ps, pa, ns0, nc0, D, precision, tol):
     # The cone-major (MFMA) and node formulations of the upward pass compute
-    # the same coefficients at every level, up to FP32 rounding.
-    log(f"case cone-major P=({ps},{pa}) D={D}")
+    # the same coefficients at every level, up to rounding.
+    log(f"case cone-major {precision} P=({ps},{pa}) D={D}")
     p, nr, w = inputs.cubed_sphere(48)
     k = 16 * np.pi
-    s = torch.from_numpy(inputs.random_density(len(p), seed=61)).to(DEV).to(torch.complex64)
-    opts = dict(depth=D, p_s=ps, p_ang=pa, ns0=ns0, nc0=nc0, precision="fp32")
+    s = torch.from_numpy(inputs.random_density(len(p), seed=61)).to(DEV)
+    if precision == "fp32":
+        s = s.to(torch.complex64)
+    opts = dict(depth=D, p_s=ps, p_ang=pa, ns0=ns0, nc0=nc0, precision=precision)
     node = Plan(p, nr, w, k, k, prop_kernel="node", **opts)
     cone = Plan(p, nr, w, k, k, prop_kernel="cone", **opts)
     un = node.apply(s).cpu().numpy()
@@ -268,21 +271,23 @@ def test_cone_major_upward_pass_equals_node_formulation(ps, pa, ns0, nc0, D):
         Cc = cone.export_field(d, 1)[:, 0, :]
         e = np.abs(Cc - Cn).max() / np.abs(Cn).max()
         log(f"  level {d}: {Cn.shape[0]} cones, max rel diff {e:.2e}")
-        assert e < 2e-5, d
-    assert np.linalg.norm(uc - un) / np.linalg.norm(un) < 1e-5
+        assert e < tol, d
+    assert np.linalg.norm(uc - un) / np.linalg.norm(un) < tol / 2
     assert cone.check() == 0 and node.check() == 0
 
 
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp64", 1e-11)])
 @pytest.mark.parametrize("ps,pa", [(4, 6), (3, 5)])
-def test_cone_major_constant_kernel_exact(ps, pa):
+def test_cone_major_constant_kernel_exact(ps, pa, precision, tol):
     p, nr, w = inputs.cubed_sphere(48)
     sigma = inputs.random_density(len(p), seed=62)
-    plan = Plan(p, nr, w, 16 * np.pi, 16 * np.pi, depth=5, p_s=ps, p_ang=pa, kernel="constant", precision="fp32",
+    plan = Plan(p, nr, w, 16 * np.pi, 16 * np.pi, depth=5, p_s=ps, p_ang=pa, kernel="constant", precision=precision,
                 prop_kernel="cone")
+    assert set(plan.stats()["prop_kernel"].values()) == {"cone"}
     u = plan.apply(torch.from_numpy(sigma).to(DEV)).cpu().numpy()
     a = w * sigma
     ref = a.sum() - a
-    assert np.abs(u - ref).max() <= 2e-5 * np.abs(a).sum()
+    assert np.abs(u - ref).max() <= tol * np.abs(a).sum()
 
 
 @pytest.mark.parametrize("surf,ps,pa,ns0,nc0,D", [("sphere48", 4, 6, 2, 4, 5), ("ellip20", 3, 5, 1, 2, 4),
