@@ -986,8 +986,21 @@ __device__ __forceinline__ int row_min16(int v) {
   return v;
 }
 
-// Lane nl (0..15) of a row loads its share of one cone's 2P floats: float
-// 64 m + 4 nl + e into register 4 m + e.  Registers past the cone stay 0.
+// Lane nl (0..15) of a row loads its share of one cone's 2P values.  FP32:
+// float 64 m + 4 nl + e into register 4 m + e; FP64: double 32 m + 2 nl + e
+// into register 2 m + e.  Registers past the cone stay 0.
+template <int P, int NREG>
+__device__ __forceinline__ void row_load_cone(const double* __restrict__ src, int nl, double (&c)[NREG]) {
+#pragma unroll
+  for (int m = 0; m < NREG / 2; ++m) {
+    const int off = 32 * m + 2 * nl;
+    double2 v = make_double2(0.0, 0.0);
+    if (off + 2 <= 2 * P) v = *reinterpret_cast<const double2*>(src + off);
+    c[2 * m] = v.x;
+    c[2 * m + 1] = v.y;
+  }
+}
+
 template <int P, int NREG>
 __device__ __forceinline__ void row_load_cone(const float* __restrict__ src, int nl, float (&c)[NREG]) {
 #pragma unroll
@@ -1015,12 +1028,11 @@ __device__ __forceinline__ void row_load_cone(const float* __restrict__ src, int
 // Sum over the cousins at level d of the lane's target x (valid: the lane
 // holds a target; i: its Morton index, any in-range index when !valid).
 // Every lane of the wave must call it together with the same level.
-template <int PS, int PA>
-__device__ __forceinline__ void rows_level(const TLevel<float>& lv, const double (&x)[3], bool valid, int64_t i,
-                                           double k, int kind, int* __restrict__ err, float& acc_re,
-                                           float& acc_im) {
+template <typename T, int PS, int PA>
+__device__ __forceinline__ void rows_level(const TLevel<T>& lv, const double (&x)[3], bool valid, int64_t i,
+                                           double k, int kind, int* __restrict__ err, T& acc_re, T& acc_im) {
   constexpr int P = PS * PA * PA;
-  using S1 = RowStage1<PS, PA>;
+  using S1 = RowStage1<T, PS, PA>;
   constexpr int NREG = S1::NREG;
   constexpr int NONE = 0x7fffffff;
   int ptr = 0, end = 0;
@@ -1031,32 +1043,51 @@ __device__ __forceinline__ void rows_level(const TLevel<float>& lv, const double
   }
   int nxt = ptr < end ? lv.cou[ptr] : NONE;
   const int nl = threadIdx.x & 15;
-  const float* F = reinterpret_cast<const float*>(gen(lv.Fc));
-  const float inv4pi = (float)(1.0 / (4.0 * IFGF_PI));
+  const T* F = reinterpret_cast<const T*>(gen(lv.Fc));
   acc_re = 0;
   acc_im = 0;
   while (true) {
     const int B = row_min16(nxt);
     if (__ballot(B != NONE) == 0) break;
     int sl = NONE;
-    float ts = 0, tt = 0, tp = 0, e_re = 0, e_im = 0;
+    T ts = 0, tt = 0, tp = 0, e_re = 0, e_im = 0;
     if (nxt == B && B != NONE) {
       double rr;
-      const LocF loc = target_loc32(x, gen(lv.centre) + 3 * B, lv.g, &rr);
-      ts = loc.ts;
-      tt = loc.tt;
-      tp = loc.tp;
-      if (kind == IFGF_KERNEL_CONSTANT) {
-        e_re = 1;
-        e_im = 0;
+      int cid;
+      if constexpr (Prec<T>::f32) {
+        const LocF loc = target_loc32(x, gen(lv.centre) + 3 * B, lv.g, &rr);
+        cid = loc.cid;
+        ts = loc.ts;
+        tt = loc.tt;
+        tp = loc.tp;
+        if (kind == IFGF_KERNEL_CONSTANT) {
+          e_re = 1;
+          e_im = 0;
+        } else {
+          float c, s;
+          expi_reduced32(k * rr, &c, &s);
+          const float g = (float)(1.0 / (4.0 * IFGF_PI)) / (float)rr;
+          e_re = g * c;
+          e_im = g * s;
+        }
       } else {
-        float c, s;
-        expi_reduced32(k * rr, &c, &s);
-        const float g = inv4pi / (float)rr;
-        e_re = g * c;
-        e_im = g * s;
+        const Loc loc = target_loc64(x, gen(lv.centre) + 3 * B, lv.g, &rr);
+        cid = loc.cid;
+        ts = loc.ts;
+        tt = loc.tt;
+        tp = loc.tp;
+        if (kind == IFGF_KERNEL_CONSTANT) {
+          e_re = 1;
+          e_im = 0;
+        } else {
+          double c, s;
+          sincos(k * rr, &s, &c);
+          const double g = (1.0 / (4.0 * IFGF_PI)) / rr;
+          e_re = g * c;
+          e_im = g * s;
+        }
       }
-      const int s0 = lv.slot[(int64_t)B * lv.g.ncone + loc.cid];
+      const int s0 = lv.slot[(int64_t)B * lv.g.ncone + cid];
       if (s0 < 0)
         atomicOr(err, 4);
       else
@@ -1064,18 +1095,18 @@ __device__ __forceinline__ void rows_level(const TLevel<float>& lv, const double
       ++ptr;
       nxt = ptr < end ? lv.cou[ptr] : NONE;
     }
-    float Ts[PS], Tt[PA], Tp[PA];
-    cheb_T<float, PS>(ts, Ts);
-    cheb_T<float, PA>(tt, Tt);
-    cheb_T<float, PA>(tp, Tp);
+    T Ts[PS], Tt[PA], Tp[PA];
+    cheb_T<T, PS>(ts, Ts);
+    cheb_T<T, PA>(tt, Tt);
+    cheb_T<T, PA>(tp, Tp);
     bool pend = sl != NONE;
     while (__ballot(pend)) {
       const int su = row_min16(pend ? sl : NONE);
-      float c[NREG];
+      T c[NREG];
       row_load_cone<P, NREG>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, c);
-      float D[2 * PS * PA];
+      T D[2 * PS * PA];
       S1::run(c, Tp, D);
-      float h_re[PS], h_im[PS];
+      T h_re[PS], h_im[PS];
 #pragma unroll
       for (int a = 0; a < PS; ++a) {
         h_re[a] = D[2 * a * PA];
@@ -1086,7 +1117,7 @@ __device__ __forceinline__ void rows_level(const TLevel<float>& lv, const double
           h_im[a] += D[2 * (a * PA + b) + 1] * Tt[b];
         }
       }
-      float v_re = h_re[0], v_im = h_im[0];
+      T v_re = h_re[0], v_im = h_im[0];
 #pragma unroll
       for (int a = 1; a < PS; ++a) {
         v_re += h_re[a] * Ts[a];
@@ -1101,9 +1132,9 @@ __device__ __forceinline__ void rows_level(const TLevel<float>& lv, const double
   }
 }
 
-template <int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_targets_rows(const double* __restrict__ pts, int64_t n, TLevels<float> L,
-                                                      int dlo, double k, int kind, float2* __restrict__ part,
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets_rows(const double* __restrict__ pts, int64_t n, TLevels<T> L,
+                                                      int dlo, double k, int kind, cpx<T>* __restrict__ part,
                                                       int* __restrict__ err) {
   const int nchunk = (int)gridDim.x;
   const int lin = xcd_block((int)(blockIdx.y * gridDim.x + blockIdx.x), (int)(gridDim.x * gridDim.y));
@@ -1112,17 +1143,18 @@ __global__ __launch_bounds__(TPB) void k_targets_rows(const double* __restrict__
   const bool valid = i0 < n;
   const int64_t i = valid ? i0 : n - 1;
   const double x[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
-  float acc_re, acc_im;
-  rows_level<PS, PA>(L.lv[d], x, valid, i, k, kind, err, acc_re, acc_im);
+  T acc_re, acc_im;
+  rows_level<T, PS, PA>(L.lv[d], x, valid, i, k, kind, err, acc_re, acc_im);
   if (valid) part[(int64_t)(d - dlo) * n + i] = {acc_re, acc_im};
 }
 
 // u = near field + the level sums of k_targets_rows (levels from the finest
 // down, as target_point adds them), scattered to the caller's order; one
 // right-hand side.
+template <typename T>
 __global__ __launch_bounds__(TPB) void k_targets_sum(int64_t n, const int* __restrict__ perm,
-                                                     const cpx<float>* __restrict__ uacc, int use_near,
-                                                     const float2* __restrict__ part, int nlev, int dtype,
+                                                     const cpx<T>* __restrict__ uacc, int use_near,
+                                                     const cpx<T>* __restrict__ part, int nlev, int dtype,
                                                      void* __restrict__ u) {
   const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
   if (i >= n) return;
@@ -1132,9 +1164,9 @@ __global__ __launch_bounds__(TPB) void k_targets_sum(int64_t n, const int* __res
     im = uacc[i].im;
   }
   for (int l = nlev - 1; l >= 0; --l) {
-    const float2 v = part[(int64_t)l * n + i];
-    re += v.x;
-    im += v.y;
+    const cpx<T> v = part[(int64_t)l * n + i];
+    re += v.re;
+    im += v.im;
   }
   const int64_t o = perm[i];
   if (dtype == IFGF_C128) {
@@ -2739,21 +2771,19 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
       return;
     }
   }
-  if constexpr (Prec<T>::f32) {
-    if (R == 1 && p->opt.target_kernel != IFGF_TARGET_WAVE) {
-      StageTimer tm(p, s, IFGF_STAGE_TARGETS);
-      const int nlev = dlo <= dhi ? dhi - dlo + 1 : 0;
-      if ((size_t)nlev * n * sizeof(float2) > p->tpart.bytes) throw Error{IFGF_EINTERNAL, "target level buffer"};
-      float2* part = p->tpart.as<float2>();
-      if (nlev > 0) {
-        k_targets_rows<PS, PA><<<dim3(nblocks(n), nlev), TPB, 0, s>>>(p->pts.as<double>(), n, L, dlo, p->k, kind,
-                                                                      part, p->err.as<int>());
-        HIPCHK(hipGetLastError());
-      }
-      k_targets_sum<<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), uacc, near ? 1 : 0, part, nlev, dtype, u);
+  if (R == 1 && p->opt.target_kernel != IFGF_TARGET_WAVE) {
+    StageTimer tm(p, s, IFGF_STAGE_TARGETS);
+    const int nlev = dlo <= dhi ? dhi - dlo + 1 : 0;
+    if ((size_t)nlev * n * sizeof(cpx<T>) > p->tpart.bytes) throw Error{IFGF_EINTERNAL, "target level buffer"};
+    cpx<T>* part = p->tpart.as<cpx<T>>();
+    if (nlev > 0) {
+      k_targets_rows<T, PS, PA><<<dim3(nblocks(n), nlev), TPB, 0, s>>>(p->pts.as<double>(), n, L, dlo, p->k, kind,
+                                                                       part, p->err.as<int>());
       HIPCHK(hipGetLastError());
-      return;
     }
+    k_targets_sum<T><<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), uacc, near ? 1 : 0, part, nlev, dtype, u);
+    HIPCHK(hipGetLastError());
+    return;
   }
   {
     StageTimer tm(p, s, IFGF_STAGE_TARGETS);
@@ -2903,7 +2933,7 @@ template <typename T> struct BLevel {
 template <typename T> struct BGeom {
   int64_t n;
   int D, kind;
-  int trows;   // FP32 cousin targets in the row-broadcast formulation
+  int trows;   // cousin targets in the row-broadcast formulation
   double k, eta;
   const double IFGF_GAS* pts;
   const double IFGF_GAS* nrm;
@@ -3062,9 +3092,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
     }
     case BT_TARGET: {
       const int dlo = D >= 3 ? 3 : 1, dhi = D >= 3 ? D : 0;
-      bool rows = false;
-      if constexpr (Prec<T>::f32) rows = G.trows != 0;
-      if (rows) {
+      if (G.trows) {
         // the row-broadcast formulation, all levels in turn (as the separate
         // apply adds them: near field, then the levels from the finest down)
         const int64_t i0 = (int64_t)local * BS + threadIdx.x;
@@ -3075,8 +3103,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
         const cpx<T> un = gen(G.uacc)[i];
         double re = un.re, im = un.im;
         for (int d = dhi; d >= dlo; --d) {
-          float lr = 0, li = 0;
-          if constexpr (Prec<T>::f32) rows_level<PS, PA>(G.tl.lv[d], x, valid, i, G.k, G.kind, gen(G.err), lr, li);
+          T lr = 0, li = 0;
+          rows_level<T, PS, PA>(G.tl.lv[d], x, valid, i, G.k, G.kind, gen(G.err), lr, li);
           re += lr;
           im += li;
         }
@@ -3131,7 +3159,7 @@ void batch_prepare_impl(ifgf_batch_s* b) {
     G.n = p->n;
     G.D = p->D;
     G.kind = p->opt.kernel;
-    G.trows = Prec<T>::f32 && p->opt.target_kernel != IFGF_TARGET_WAVE;
+    G.trows = p->opt.target_kernel != IFGF_TARGET_WAVE;
     G.k = p->k;
     G.eta = p->eta;
     G.pts = gas(p->pts.as<const double>());

@@ -100,7 +100,7 @@ struct ifgf_plan_s {
   ifgf::LevelPlan lev[IFGF_MAX_LEVELS];
   ifgf::DevBuf a;             // gathered coefficients w * sigma, [n][max_rhs] complex (plan precision)
   ifgf::DevBuf uacc;          // near-field results, [n][max_rhs] complex (plan precision)
-  ifgf::DevBuf tpart;         // FP32 cousin-target level sums, [D - 2][n] complex float
+  ifgf::DevBuf tpart;         // cousin-target level sums, [D - 2][n] complex (plan precision)
   ifgf::DevBuf adj_g[IFGF_MAX_LEVELS];   // transposed-apply coefficient-space buffers
   ifgf::DevBuf err;           // int [4] device error flags
   int64_t near_pairs = 0;

@@ -776,7 +776,7 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
   }
   p->a.alloc(csz * (size_t)n * R);
   p->uacc.alloc(csz * (size_t)n * R);
-  if (f32 && p->opt.target_kernel != IFGF_TARGET_WAVE && D >= 3) p->tpart.alloc(sizeof(float) * 2 * (size_t)n * (D - 2));
+  if (p->opt.target_kernel != IFGF_TARGET_WAVE && D >= 3) p->tpart.alloc(csz * (size_t)n * (D - 2));
   p->err.alloc(sizeof(int) * 4);
   HIPCHK(hipMemsetAsync(p->err.p, 0, sizeof(int) * 4, s));
   HIPCHK(hipStreamSynchronize(s));
