@@ -84,15 +84,15 @@ typedef struct {
     int32_t precision;      /* IFGF_PREC_*; default IFGF_PREC_FP32_INTERP                  */
     int32_t max_rhs;        /* largest nrhs accepted by the apply calls; default 1         */
     int32_t kernel;         /* IFGF_KERNEL_*; default IFGF_KERNEL_COMBINED                  */
-    int32_t prop_kernel;    /* upward pass with one right-hand side in FP32: IFGF_PROP_AUTO
+    int32_t prop_kernel;    /* upward pass with one right-hand side: IFGF_PROP_AUTO
                                (default), IFGF_PROP_NODE or IFGF_PROP_CONE (below)          */
-    int32_t target_kernel;  /* cousin-target stage with one right-hand side in FP32:
+    int32_t target_kernel;  /* cousin-target stage with one right-hand side:
                                IFGF_TARGET_AUTO (default), IFGF_TARGET_WAVE or
                                IFGF_TARGET_ROWS (below)                                    */
 } ifgf_options;
 
-/* Upward-pass formulation (FP32, nrhs = 1; FP64 and other nrhs always use
- * IFGF_PROP_NODE).  NODE: every parent node of every relevant parent cone
+/* Upward-pass formulation (nrhs = 1, FP32 or FP64; other nrhs always use
+ * their own kernels).  NODE: every parent node of every relevant parent cone
  * evaluates its child interpolants (work items = a parent box and a few of
  * its cones).  CONE: all boxes of a level have the same size, so a parent
  * node's position in a child's frame depends only on (parent cone id, child
@@ -100,19 +100,19 @@ typedef struct {
  * together and the interpolation becomes a product of their child
  * coefficients with one basis matrix, on MFMA.  AUTO picks CONE for the
  * levels where the boxes per parent cone id fill its tiles.  Both give the
- * same operator up to FP32 rounding. */
+ * same operator up to rounding. */
 enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2 };
 
-/* Cousin-target formulation (Algorithm 1, target evaluation; FP32 with
- * nrhs = 1 — FP64 and other nrhs always use their own kernels).  WAVE: a
+/* Cousin-target formulation (Algorithm 1, target evaluation; nrhs = 1, FP32
+ * or FP64 — other nrhs always use their own kernels).  WAVE: a
  * lane per target walks its box's cousin list; the wave stages each distinct
  * cone it meets in LDS and the lanes holding that cone contract against it.
  * ROWS: the 16 lanes of a row walk the merged cousin lists of their targets
  * together, load the row's current cone across the row and contract with the
  * coefficients broadcast between lanes (no LDS); levels run as separate
- * work-groups and are added afterwards, which needs n x (D - 2) FP32 complex
- * values of plan memory.  AUTO = ROWS.  Both give the same operator up to
- * FP32 rounding. */
+ * work-groups and are added afterwards, which needs n x (D - 2) complex values
+ * (plan precision) of plan memory.  AUTO = ROWS.  Both give the same operator
+ * up to rounding. */
 enum { IFGF_TARGET_AUTO = 0, IFGF_TARGET_WAVE = 1, IFGF_TARGET_ROWS = 2 };
 
 /* Plan statistics (host struct). */
