@@ -95,6 +95,27 @@ def measured_traffic(tag, stage):
         return None
 
 
+def measure_peaks(log):
+    """Rates this GPU sustains for the instructions the kernels use (MFMA FP32
+    chains, FP32 and FP64 FMA chains, a 1 GiB 16-byte-vector copy), from the
+    probe library; None where it is not built."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2112_06316_amd", "libifgf_probe.so")
+    if not os.path.exists(path):
+        return None
+    lib = ctypes.CDLL(path)
+    lib.ifgf_probe_run.restype = ctypes.c_int
+    lib.ifgf_probe_run.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    names = ["mfma_f32_tflops", "valu_f32_tflops", "valu_f64_tflops", "hbm_copy_gbs"]
+    out = {}
+    for i, name in enumerate(names):
+        v = ctypes.c_double(0.0)
+        st = lib.ifgf_probe_run(i, ctypes.byref(v))
+        out[name] = v.value if st == 0 else None
+    log(f"measured peaks: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +133,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--adjoint-steps", type=int, default=5)
     ap.add_argument("--ragged-steps", type=int, default=5, help="applies of the ragged 8-geometry batch (0 = skip)")
+    ap.add_argument("--no-peak-probe", action="store_true", help="skip the measured-peak probes")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the FP32 leg, copy a buffer of this many MiB three times with a plain device copy "
                          "(the reference point that scales HBM byte counters)")
@@ -254,6 +276,8 @@ def main():
         entry = {"ms_per_apply": ms / args.steps, "launches_per_apply": cnt / args.steps}
         if name in work and ms > 0:
             entry["achieved_tflops"] = work[name] / (ms / args.steps * 1e-3) / 1e12
+        if name in traffic and ms > 0:   # algorithmic bytes: inputs read once, outputs written once
+            entry["algorithmic_gbs"] = traffic[name] / (ms / args.steps * 1e-3) / 1e9
         stages[name] = entry
     dom = max((s for s in prof if s in work), key=lambda s: prof[s][0])
     ms_dom, cnt_dom = prof[dom]
@@ -375,6 +399,13 @@ def main():
         }
         del bat, plans_r, sig_r, out_r
 
+    peaks = None if args.no_peak_probe else measure_peaks(log)
+    if peaks:
+        key = "mfma_f32_tflops" if roofline["bound"] == "mfma" else "valu_f32_tflops"
+        if peaks.get(key):
+            roofline["measured_peak"] = peaks[key]
+            roofline["frac_of_measured_peak"] = roofline["achieved"] / peaks[key]
+
     ms_per_step = r32["wall"] * 1e3 / args.steps
     out = {
         "metric": METRIC,
@@ -403,6 +434,7 @@ def main():
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "peaks_measured": peaks,
         "plan": {"cones": st["cones"], "boxes": st["boxes"], "near_pairs": st["near_pairs"],
                  "upward_pass_formulation": st["prop_kernel"],
                  "cousin_pairs": cousin, "prop_evals": prop_evals, "device_bytes": st["device_bytes"]},

@@ -30,6 +30,23 @@ def _compile(src: str) -> str:
     return obj
 
 
+PROBE_LIB = os.path.join(HERE, "libifgf_probe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The peak-probe library used by the benchmark (not part of the C ABI)."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-shared", os.path.join(CSRC, "probe.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for probe.hip:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     # generated asm of the row-broadcast target contraction
@@ -44,6 +61,7 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(LIB)
+    build_probe(verbose)
     return LIB
 
 
