@@ -586,6 +586,107 @@ __device__ __forceinline__ cpx<T> eval_uniform(const cpx<T>* __restrict__ F, int
   return out;
 }
 
+#include "row_stage1.inc"
+
+// Minimum of v over the 16 lanes of each row.
+__device__ __forceinline__ int row_min16(int v) {
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));    // quad_perm [1,0,3,2]
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));    // quad_perm [2,3,0,1]
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));   // row_half_mirror
+  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));   // row_mirror
+  return v;
+}
+
+// Lane nl (0..15) of a row loads its share of one cone's 2P values.  FP32:
+// float 64 m + 4 nl + e into register 4 m + e; FP64: double 32 m + 2 nl + e
+// into register 2 m + e.  Registers past the cone stay 0.
+template <int P, int NREG>
+__device__ __forceinline__ void row_load_cone(const double* __restrict__ src, int nl, double (&c)[NREG]) {
+#pragma unroll
+  for (int m = 0; m < NREG / 2; ++m) {
+    const int off = 32 * m + 2 * nl;
+    double2 v = make_double2(0.0, 0.0);
+    if (off + 2 <= 2 * P) v = *reinterpret_cast<const double2*>(src + off);
+    c[2 * m] = v.x;
+    c[2 * m + 1] = v.y;
+  }
+}
+
+template <int P, int NREG>
+__device__ __forceinline__ void row_load_cone(const float* __restrict__ src, int nl, float (&c)[NREG]) {
+#pragma unroll
+  for (int m = 0; m < NREG / 4; ++m) {
+    const int off = 64 * m + 4 * nl;
+    if constexpr (P % 2 == 0) {   // cone base 16-byte aligned
+      float4 v = {0, 0, 0, 0};
+      if (off + 4 <= 2 * P) v = *reinterpret_cast<const float4*>(src + off);
+      c[4 * m] = v.x;
+      c[4 * m + 1] = v.y;
+      c[4 * m + 2] = v.z;
+      c[4 * m + 3] = v.w;
+    } else {                      // 8-byte aligned
+      float2 a = {0, 0}, b = {0, 0};
+      if (off + 2 <= 2 * P) a = *reinterpret_cast<const float2*>(src + off);
+      if (off + 4 <= 2 * P) b = *reinterpret_cast<const float2*>(src + off + 2);
+      c[4 * m] = a.x;
+      c[4 * m + 1] = a.y;
+      c[4 * m + 2] = b.x;
+      c[4 * m + 3] = b.y;
+    }
+  }
+}
+
+
+// For every lane with slot >= 0, the interpolant of cone `slot` of F (one
+// right-hand side, layout [slot][P]) at (ts, tt, tp), by rows: each row of
+// 16 lanes loads one cone across its lanes and contracts with the
+// coefficients broadcast by DPP (RowStage1); lanes of the row that need
+// another cone take a further round.  All 64 lanes of the wave call it
+// together (lanes without work pass slot = -1).
+template <typename T, int PS, int PA>
+__device__ __forceinline__ cpx<T> eval_rows(const cpx<T>* __restrict__ Fc, int slot, T ts, T tt, T tp) {
+  constexpr int P = PS * PA * PA;
+  using S1 = RowStage1<T, PS, PA>;
+  constexpr int NREG = S1::NREG;
+  constexpr int NONE = 0x7fffffff;
+  const T* F = reinterpret_cast<const T*>(Fc);
+  const int nl = threadIdx.x & 15;
+  T Ts[PS], Tt[PA], Tp[PA];
+  cheb_T<T, PS>(ts, Ts);
+  cheb_T<T, PA>(tt, Tt);
+  cheb_T<T, PA>(tp, Tp);
+  cpx<T> out = {0, 0};
+  bool pend = slot >= 0;
+  while (__ballot(pend)) {
+    const int su = row_min16(pend ? slot : NONE);
+    T c[NREG];
+    row_load_cone<P, NREG>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, c);
+    T D[2 * PS * PA];
+    S1::run(c, Tp, D);
+    if (pend && slot == su) {
+      T h_re[PS], h_im[PS];
+#pragma unroll
+      for (int a = 0; a < PS; ++a) {
+        h_re[a] = D[2 * a * PA];
+        h_im[a] = D[2 * a * PA + 1];
+#pragma unroll
+        for (int b = 1; b < PA; ++b) {
+          h_re[a] += D[2 * (a * PA + b)] * Tt[b];
+          h_im[a] += D[2 * (a * PA + b) + 1] * Tt[b];
+        }
+      }
+      out = {h_re[0], h_im[0]};
+#pragma unroll
+      for (int a = 1; a < PS; ++a) {
+        out.re += h_re[a] * Ts[a];
+        out.im += h_im[a] * Ts[a];
+      }
+      pend = false;
+    }
+  }
+  return out;
+}
+
 // ---------------------------------------------------------------------------
 // upward pass d -> d-1 (Algorithm 1, parent-node update), fused with the
 // node-value -> coefficient transform of level d-1.
@@ -802,7 +903,11 @@ __device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_>& sm, int4 wk,
         tt = st[n][1];
         tp = st[n][2];
       }
-      cpx<T> v = eval_uniform<T, PS, PA>(Fc_c, sl, R, r, ts, tt, tp, cbuf[threadIdx.x >> 6]);
+      cpx<T> v;
+      if constexpr (ONE)
+        v = eval_rows<T, PS, PA>(Fc_c, sl, ts, tt, tp);
+      else
+        v = eval_uniform<T, PS, PA>(Fc_c, sl, R, r, ts, tt, tp, cbuf[threadIdx.x >> 6]);
       if (n >= 0 && sl >= 0) {
         T rr = tmp[n].re, dr = tmp[n].im;
         T c_, s_;
@@ -975,56 +1080,6 @@ __global__ __launch_bounds__(TPB) void k_targets(const double* __restrict__ pts,
 // lane sums its cousins in ascending box order: deterministic.  The level's
 // sum goes to part[d - dlo][i]; k_targets_sum adds the levels.
 // ---------------------------------------------------------------------------
-#include "row_stage1.inc"
-
-// Minimum of v over the 16 lanes of each row.
-__device__ __forceinline__ int row_min16(int v) {
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));    // quad_perm [1,0,3,2]
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));    // quad_perm [2,3,0,1]
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));   // row_half_mirror
-  v = min(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));   // row_mirror
-  return v;
-}
-
-// Lane nl (0..15) of a row loads its share of one cone's 2P values.  FP32:
-// float 64 m + 4 nl + e into register 4 m + e; FP64: double 32 m + 2 nl + e
-// into register 2 m + e.  Registers past the cone stay 0.
-template <int P, int NREG>
-__device__ __forceinline__ void row_load_cone(const double* __restrict__ src, int nl, double (&c)[NREG]) {
-#pragma unroll
-  for (int m = 0; m < NREG / 2; ++m) {
-    const int off = 32 * m + 2 * nl;
-    double2 v = make_double2(0.0, 0.0);
-    if (off + 2 <= 2 * P) v = *reinterpret_cast<const double2*>(src + off);
-    c[2 * m] = v.x;
-    c[2 * m + 1] = v.y;
-  }
-}
-
-template <int P, int NREG>
-__device__ __forceinline__ void row_load_cone(const float* __restrict__ src, int nl, float (&c)[NREG]) {
-#pragma unroll
-  for (int m = 0; m < NREG / 4; ++m) {
-    const int off = 64 * m + 4 * nl;
-    if constexpr (P % 2 == 0) {   // cone base 16-byte aligned
-      float4 v = {0, 0, 0, 0};
-      if (off + 4 <= 2 * P) v = *reinterpret_cast<const float4*>(src + off);
-      c[4 * m] = v.x;
-      c[4 * m + 1] = v.y;
-      c[4 * m + 2] = v.z;
-      c[4 * m + 3] = v.w;
-    } else {                      // 8-byte aligned
-      float2 a = {0, 0}, b = {0, 0};
-      if (off + 2 <= 2 * P) a = *reinterpret_cast<const float2*>(src + off);
-      if (off + 4 <= 2 * P) b = *reinterpret_cast<const float2*>(src + off + 2);
-      c[4 * m] = a.x;
-      c[4 * m + 1] = a.y;
-      c[4 * m + 2] = b.x;
-      c[4 * m + 3] = b.y;
-    }
-  }
-}
-
 // Sum over the cousins at level d of the lane's target x (valid: the lane
 // holds a target; i: its Morton index, any in-range index when !valid).
 // Every lane of the wave must call it together with the same level.
