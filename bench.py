@@ -256,7 +256,7 @@ def main():
     work = {
         "near": st["near_pairs"] * NEAR_FLOPS,
         "leaf": leaf_cones * P * pts_per_leaf * LEAF_FLOPS,
-        "coeffs": sum(st["cones"].values()) * coeff_flops(ps, pa),
+        "coeffs": leaf_cones * coeff_flops(ps, pa),
         "prop": sum(st["prop_evals"][d] for d in node_lv) * fi,
         "prop_cone": sum(st["prop_evals"][d] for d in cone_lv) * fi,
         "targets": cousin * fi,
@@ -268,9 +268,13 @@ def main():
         "targets": sum(F_bytes.values()) + n * (24 + 8 + 4 + 16),
         "leaf": n * (24 + 24 + 8) + F_bytes.get(D, 0),
         "near": n * (24 + 24 + 8 + 8),
-        "coeffs": 2 * sum(F_bytes.values()),
+        "coeffs": 2 * F_bytes.get(D, 0),
     }
     prof = r32["prof"]
+    if "coeffs" not in prof:   # one RHS: the finest level's transform runs inside the leaf kernel
+        work["leaf"] += work.pop("coeffs")
+        traffic["leaf"] += F_bytes.get(D, 0)
+        traffic.pop("coeffs")
     stages = {}
     for name, (ms, cnt) in prof.items():
         entry = {"ms_per_apply": ms / args.steps, "launches_per_apply": cnt / args.steps}

@@ -288,7 +288,7 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int i0, int
                                          const int* __restrict__ start, const double* __restrict__ centre,
                                          const int* __restrict__ slot_off, const int* __restrict__ rel_cone,
                                          const LevelGeom& g, const ChebTab& ct, double k, double eta, int kind,
-                                         cpx<T>* __restrict__ Fn) {
+                                         cpx<T>* __restrict__ Fn, cpx<T>* fv = nullptr) {
   constexpr int P = PS * PA * PA;
   constexpr int LC = LeafChunk<RG>::N;
   auto& su = sm.su;
@@ -381,23 +381,45 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int i0, int
     if (valid) {
 #pragma unroll
       for (int q2 = 0; q2 < RG; ++q2) Fn[((int64_t)s0 * P + it) * R + r0 + q2] = acc[q2];
+      if (fv) fv[it - i0] = acc[0];   // the node values also kept in LDS (one RHS)
     }
   }
 }
 
+template <typename T, int PS, int PA, int BS>
+__device__ __forceinline__ void lds_coeffs_store(cpx<T>* v, cpx<T>* t, int nc, const T* ms, const T* ma,
+                                                 cpx<T>* __restrict__ out, int R, int r);
+
 // One block per work item (box, first item, item count): a box's (cone,
-// node) items are split into chunks so that the blocks carry similar work.
-template <typename T, int PS, int PA, int RG>
+// node) items are split into chunks of whole cones so that the blocks carry
+// similar work.  With FUSE (one RHS) the block also turns its cones' node
+// values into Chebyshev coefficients in LDS and writes them to Fc.
+template <typename T, int PS, int PA, int RG, bool FUSE>
 __global__ __launch_bounds__(TPB) void k_leaf(const int4* __restrict__ work, const double* __restrict__ pts,
                                               const double* __restrict__ nrm, const cpx<T>* __restrict__ a, int R,
                                               const int* __restrict__ start, const double* __restrict__ centre,
                                               const int* __restrict__ slot_off, const int* __restrict__ rel_cone,
                                               LevelGeom g, ChebTab ct, double k, double eta, int kind,
-                                              cpx<T>* __restrict__ Fn) {
+                                              cpx<T>* __restrict__ Fn, const T* __restrict__ Ms,
+                                              const T* __restrict__ Ma, cpx<T>* __restrict__ Fc) {
+  constexpr int P = PS * PA * PA;
+  constexpr int NCF = FUSE ? (kLeafChunk / P > 0 ? kLeafChunk / P : 1) : 1;
   __shared__ LeafSmem<T, RG> sm;
+  __shared__ cpx<T> fv[FUSE ? NCF * P : 1], ft[FUSE ? NCF * P : 1];
+  __shared__ T fms[PS * PS], fma_[PA * PA];
   const int4 wk = work[xcd_block(blockIdx.x, gridDim.x)];
+  if (FUSE) {
+    if (threadIdx.x < PS * PS) fms[threadIdx.x] = Ms[threadIdx.x];
+    if (threadIdx.x < PA * PA) fma_[threadIdx.x] = Ma[threadIdx.x];
+  }
   leaf_box<T, PS, PA, RG, TPB>(sm, wk.x, wk.y, wk.z, blockIdx.y * RG, pts, nrm, a, R, start, centre, slot_off,
-                               rel_cone, g, ct, k, eta, kind, Fn);
+                               rel_cone, g, ct, k, eta, kind, Fn, FUSE ? fv : nullptr);
+  if constexpr (FUSE) {
+    __syncthreads();
+    const int ncn = slot_off[wk.x + 1] - slot_off[wk.x];
+    const int c0 = wk.y / P, nc = min(ncn * P, wk.y + wk.z) / P - c0;
+    lds_coeffs_store<T, PS, PA, TPB>(fv, ft, nc, fms, fma_, Fc + ((int64_t)slot_off[wk.x] + c0) * P, 1, 0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2721,18 +2743,23 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     if (lD.n_leaf > 0) {
       StageTimer tm(p, s, IFGF_STAGE_LEAF);
       if (grouped)
-        k_leaf<T, PS, PA, MF_RG><<<dim3(lD.n_leaf, R / MF_RG), TPB, 0, s>>>(
+        k_leaf<T, PS, PA, MF_RG, false><<<dim3(lD.n_leaf, R / MF_RG), TPB, 0, s>>>(
             lD.leaf_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
             lD.centre.as<double>(), lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta,
-            kind, lD.Fn.as<cpx<T>>());
+            kind, lD.Fn.as<cpx<T>>(), Ms, Ma, lD.Fc.as<cpx<T>>());
+      else if (R == 1)
+        k_leaf<T, PS, PA, 1, true><<<dim3(lD.n_leaf, 1), TPB, 0, s>>>(
+            lD.leaf_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
+            lD.centre.as<double>(), lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta,
+            kind, lD.Fn.as<cpx<T>>(), Ms, Ma, lD.Fc.as<cpx<T>>());
       else
-        k_leaf<T, PS, PA, 1><<<dim3(lD.n_leaf, R), TPB, 0, s>>>(
+        k_leaf<T, PS, PA, 1, false><<<dim3(lD.n_leaf, R), TPB, 0, s>>>(
             lD.leaf_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
             lD.centre.as<double>(), lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta,
-            kind, lD.Fn.as<cpx<T>>());
+            kind, lD.Fn.as<cpx<T>>(), Ms, Ma, lD.Fc.as<cpx<T>>());
     }
     HIPCHK(hipGetLastError());
-    if (lD.nrel > 0) {
+    if (lD.nrel > 0 && (grouped || R > 1)) {   // one RHS: done inside k_leaf
       StageTimer tm(p, s, IFGF_STAGE_COEFFS);
       if (grouped)
         k_coeffs_rg<T, PS, PA, MF_RG><<<dim3(lD.nrel, R / MF_RG), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), R, Ms, Ma,

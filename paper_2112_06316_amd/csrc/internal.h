@@ -36,7 +36,7 @@ struct DevBuf {
 };
 
 constexpr int kNearChunk = 128;   // targets per near-field work item
-constexpr int kLeafChunk = 1024;  // (cone, node) items per leaf-factor work item
+constexpr int kLeafChunk = 1024;  // (cone, node) items per leaf-factor work item, rounded down to whole cones
 
 struct LevelPlan {
   int d = 0;
@@ -71,8 +71,8 @@ struct LevelPlan {
   DevBuf near_work;
   int n_near = 0;
   // leaf factors at the finest level: int4 [n_leaf] (box, first item, item
-  // count, 0) over the box's (relevant cone, node) items, chunks of at most
-  // kLeafChunk items
+  // count, 0) over the box's (relevant cone, node) items, chunks of whole
+  // cones of at most kLeafChunk items
   DevBuf leaf_work;
   int n_leaf = 0;
   int ti_nw = 0;              // 0: this level uses the node formulation

@@ -652,9 +652,10 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
     if (D >= 3) {
       std::vector<int> so(lD.nb + 1);
       HIPCHK(hipMemcpy(so.data(), lD.slot_off.p, sizeof(int) * (lD.nb + 1), hipMemcpyDeviceToHost));
+      const int chunk = std::max(1, kLeafChunk / P) * P;   // whole cones
       for (int b = 0; b < lD.nb; ++b) {
         const int items = (so[b + 1] - so[b]) * P;
-        for (int t = 0; t < items; t += kLeafChunk) wk.push_back(make_int4(b, t, std::min(kLeafChunk, items - t), 0));
+        for (int t = 0; t < items; t += chunk) wk.push_back(make_int4(b, t, std::min(chunk, items - t), 0));
       }
     }
     lD.n_leaf = (int)wk.size();
