@@ -1697,22 +1697,31 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
 // values in LDS (each (box, node) has one writer per octant, octants in
 // order: deterministic).  After the 8 octants the node values are turned
 // into coefficients in place and written to the parent level.
+//
+// Latency hiding: the geometry of the next octant with children is computed
+// and grouped before the current octant's MFMA phase (two geometry buffers),
+// so that a wave's A-operand pipeline runs on from the last group of one
+// octant into the first group of the next; node records are stored in group
+// order, so a column tile reads its nodes with one LDS access each.
 // ---------------------------------------------------------------------------
 template <int PS, int PA, int NW> struct TiSmem {
   static constexpr int P = PS * PA * PA;
   static constexpr int NB = 8 * NW;
-  static constexpr int NBAS = PS + 2 * PA;
-  // Row strides padded so that lanes reading different nodes (bas) or
-  // different boxes (acc) fall in different LDS banks.
-  static constexpr int BAS_LD = NBAS | 1;
+  // Row stride padded so that lanes reading different boxes fall in
+  // different LDS banks; columns P and P + 1 of row NB take unused updates.
   static constexpr int ACC_LD = P + 4;
+  struct Geo {                 // one octant, nodes in group order
+    float4 loc[P];             // (ts, tt, tp, -): local coordinates in the node's child cone
+    float2 rat[P];             // ratio K(x, y_B) / K(x, y_P)
+    short node[P];             // node index
+    short gstart[P + 1];       // group g: entries gstart[g] .. gstart[g+1]-1
+    int gcid[P];               // child cone id of group g
+    int ngroup;
+  };
   cpx<float> acc[NB + 1][ACC_LD];  // node values of the tile's boxes; row NB takes unused updates
-  float bas[P][BAS_LD];        // per node, current octant: T_a(ts), T_b(tt), T_c(tp)
-  float rat[P][2];             // ratio K(x, y_B) / K(x, y_P)
-  int cid[P];                  // child cone id
-  short order[P];              // nodes grouped by child cone
-  int gstart[P + 1], gcid[P];
-  int ngroup;
+  Geo geo[2];
+  int cid[P];                  // child cone id per node (octant being grouped)
+  short rank[P];               // position of each node in group order
   int child[NB][8];            // child box per (box, octant), -1 if none
   signed char olist[8][NB];    // per octant: the tile's boxes with a child there, ascending
   int ocnt[8];
@@ -1734,10 +1743,11 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
   constexpr int P = S::P;
   constexpr int NB = S::NB;
   constexpr int BS = 64 * NW;
+  constexpr int NPT = (P + BS - 1) / BS;   // nodes per thread in the geometry pass
   const int q = tl.x, nb = tl.z;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
-  // ---- set-up: boxes, their children by octant, node positions ----------------
+  // ---- set-up: boxes, their children by octant -----------------------------------
   if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = Ms[threadIdx.x];
   if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
   if (threadIdx.x == 0) sm.anychild = 0;
@@ -1764,8 +1774,89 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
       if (sm.child[t][o] >= 0) sm.olist[o][c++] = (signed char)t;
     sm.ocnt[o] = c;
   }
-  __syncthreads();
-  const int anychild = sm.anychild;
+  const int anychild = sm.anychild;   // written before the barrier above
+  auto next_oct = [&](int o) -> int {  // next octant with children after o, -1 if none
+    const int m = o < 0 ? anychild : anychild & ~((2 << o) - 1);
+    return m ? __builtin_ctz(m) : -1;
+  };
+
+  // ---- geometry of an octant: thread t holds nodes t, t + BS, ... -------------------
+  float4 gloc[NPT];
+  float2 grat[NPT];
+  auto geometry = [&](int o) {   // each node's child cone (to LDS), local coordinates and ratio
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int n = threadIdx.x + m * BS;
+      if (n < P) {
+        float x[3], rp;   // node relative to the parent centre (recomputed: cheaper than the LDS it would hold)
+        node_rel32(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
+        const PropF pr = child_loc32(x, rp, o, gc);
+        sm.cid[n] = pr.loc.cid;
+        gloc[m] = make_float4(pr.loc.ts, pr.loc.tt, pr.loc.tp, 0.f);
+        float c_ = 1.f, s_ = 0.f, rr = 1.f;
+        if (kind != IFGF_KERNEL_CONSTANT) {
+          sincos_f((float)k * pr.dr, &s_, &c_);
+          rr = pr.rp_over_rc;
+        }
+        grat[m] = make_float2(rr * c_, rr * s_);
+      }
+    }
+  };
+  // group the nodes by child cone (wave 0): group starts, cone ids and each node's rank
+  auto group = [&](typename S::Geo& G) {
+    if (wv != 0) return;
+    constexpr int NPL = (P + 63) / 64;   // nodes per lane
+    int cv[NPL];
+    bool pend[NPL];
+#pragma unroll
+    for (int m = 0; m < NPL; ++m) {
+      const int n = lane + 64 * m;
+      pend[m] = n < P;
+      cv[m] = pend[m] ? sm.cid[n] : 0;
+    }
+    int pos = 0, g = 0;
+    while (true) {
+      int lead = -1, su = 0;
+#pragma unroll
+      for (int m = 0; m < NPL && lead < 0; ++m) {
+        const uint64_t b = __ballot(pend[m]);
+        if (b) {
+          lead = first_lane(b);
+          su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
+        }
+      }
+      if (lead < 0) break;
+      if (lane == 0) {
+        G.gstart[g] = (short)pos;
+        G.gcid[g] = su;
+      }
+#pragma unroll
+      for (int m = 0; m < NPL; ++m) {
+        const bool hit = pend[m] && cv[m] == su;
+        const uint64_t b = __ballot(hit);
+        if (hit) sm.rank[lane + 64 * m] = (short)(pos + __popcll(b & ((1ull << lane) - 1)));
+        pos += __popcll(b);
+        pend[m] = pend[m] && !hit;
+      }
+      ++g;
+    }
+    if (lane == 0) {
+      G.gstart[g] = (short)pos;
+      G.ngroup = g;
+    }
+  };
+  auto place = [&](typename S::Geo& G) {   // each node's record at its rank
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int n = threadIdx.x + m * BS;
+      if (n < P) {
+        const int r = sm.rank[n];
+        G.loc[r] = gloc[m];
+        G.rat[r] = grat[m];
+        G.node[r] = (short)n;
+      }
+    }
+  };
 
   // this lane's A rows and B columns; in each octant, the wave's 8 rows are
   // entries 8 wv .. 8 wv + 7 of that octant's box list
@@ -1773,190 +1864,189 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
   const int la = lane >> 4;       // index within the 4-wide K step: the radial index a
   const int reim = li & 1;
 
-  for (int o = 0; o < 8; ++o) {
-    if (!((anychild >> o) & 1)) continue;   // block-uniform
-    // ---- node geometry in the child frame of octant o ------------------------
-    for (int n = threadIdx.x; n < P; n += BS) {
-      float x[3], rp;   // node relative to the parent centre (recomputed: cheaper than the LDS it would hold)
-      node_rel32(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
-      const PropF pr = child_loc32(x, rp, o, gc);
-      sm.cid[n] = pr.loc.cid;
-      cheb_T<float, PS>(pr.loc.ts, &sm.bas[n][0]);
-      cheb_T<float, PA>(pr.loc.tt, &sm.bas[n][PS]);
-      cheb_T<float, PA>(pr.loc.tp, &sm.bas[n][PS + PA]);
-      float c_ = 1.f, s_ = 0.f, rr = 1.f;
-      if (kind != IFGF_KERNEL_CONSTANT) {
-        sincos_f((float)k * pr.dr, &s_, &c_);
-        rr = pr.rp_over_rc;
-      }
-      sm.rat[n][0] = rr * c_;
-      sm.rat[n][1] = rr * s_;
-    }
-    __syncthreads();
-    // ---- group the nodes by child cone (wave 0) ----------------------------------
-    if (wv == 0) {
-      constexpr int NPL = (P + 63) / 64;   // nodes per lane
-      int cv[NPL];
-      bool pend[NPL];
+  // Where a row is 16-byte aligned (P = 144) the two lanes of a box (re row,
+  // im row; neighbours) each load every other 16-byte chunk of the cone's
+  // slab - 2 coefficients, re and im - and swap the halves the other one
+  // needs (DPP between neighbouring lanes): 9 loads and 36 registers per row
+  // and group, so that this group's operand and the next group's loads in
+  // flight stay within what the vector-memory counter tracks and within 3
+  // waves per SIMD.
+  constexpr bool QUAD = (PA * PA) % 4 == 0;
+  constexpr int NRAW = QUAD ? PA * PA / 4 : PA * PA;
+  using Raw = typename std::conditional<QUAD, float4, float2>::type;
+  auto load_raw = [&](int sl, Raw(&dst)[NRAW]) {
+    if (sl >= 0 && la < PS) {
+      const cpx<float>* row = Fc_c + (int64_t)sl * P + la * PA * PA;
+      if constexpr (QUAD) {
+        const float4* src = reinterpret_cast<const float4*>(row) + reim;   // chunks 2u + reim
 #pragma unroll
-      for (int m = 0; m < NPL; ++m) {
-        const int n = lane + 64 * m;
-        pend[m] = n < P;
-        cv[m] = pend[m] ? sm.cid[n] : 0;
-      }
-      int pos = 0, g = 0;
-      while (true) {
-        int lead = -1, su = 0;
-#pragma unroll
-        for (int m = 0; m < NPL && lead < 0; ++m) {
-          const uint64_t b = __ballot(pend[m]);
-          if (b) {
-            lead = first_lane(b);
-            su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
-          }
-        }
-        if (lead < 0) break;
-        if (lane == 0) {
-          sm.gstart[g] = pos;
-          sm.gcid[g] = su;
-        }
-#pragma unroll
-        for (int m = 0; m < NPL; ++m) {
-          const bool hit = pend[m] && cv[m] == su;
-          const uint64_t b = __ballot(hit);
-          if (hit) sm.order[pos + __popcll(b & ((1ull << lane) - 1))] = (short)(lane + 64 * m);
-          pos += __popcll(b);
-          pend[m] = pend[m] && !hit;
-        }
-        ++g;
-      }
-      if (lane == 0) {
-        sm.gstart[g] = pos;
-        sm.ngroup = g;
-      }
-    }
-    __syncthreads();
-    // ---- child interpolants on MFMA, group by group -----------------------------------
-    // The A operand (this lane's coefficient row of its box's child cone) is
-    // software-pipelined: while group g is evaluated, the coefficients of
-    // group g+1 and the slot of group g+2 are in flight.
-    const int ng = sm.ngroup;
-    const int no = sm.ocnt[o];
-    const int le = wv * 8 + (li >> 1);
-    const int Bc = le < no ? sm.child[sm.olist[o][le]][o] : -1;
-    const bool wave_has = 8 * wv < no;   // wave-uniform: the octant's list reaches this wave's rows
-    auto slot_of = [&](int g) -> int {
-      return (g < ng && Bc >= 0) ? slot_c[(int64_t)Bc * gc.ncone + sm.gcid[g]] : -1;
-    };
-    // The A operand is loaded one group ahead.  Where a row is 16-byte aligned
-    // (P = 144) the two lanes of a box (re row, im row; neighbours) each load
-    // every other 16-byte chunk of the cone's slab - 2 coefficients, re and
-    // im - and swap the halves the other one needs (DPP between neighbouring
-    // lanes): 9 loads and 36 registers per row and group, so that this
-    // group's operand and the next group's loads in flight stay within what
-    // the vector-memory counter tracks and within 3 waves per SIMD.
-    constexpr bool QUAD = (PA * PA) % 4 == 0;
-    constexpr int NRAW = QUAD ? PA * PA / 4 : PA * PA;
-    using Raw = typename std::conditional<QUAD, float4, float2>::type;
-    auto load_raw = [&](int sl, Raw(&dst)[NRAW]) {
-      if (sl >= 0 && la < PS) {
-        const cpx<float>* row = Fc_c + (int64_t)sl * P + la * PA * PA;
-        if constexpr (QUAD) {
-          const float4* src = reinterpret_cast<const float4*>(row) + reim;   // chunks 2u + reim
-#pragma unroll
-          for (int u = 0; u < NRAW; ++u) dst[u] = src[2 * u];
-        } else {
-#pragma unroll
-          for (int u = 0; u < NRAW; ++u) dst[u] = reinterpret_cast<const float2*>(row)[u];
-        }
+        for (int u = 0; u < NRAW; ++u) dst[u] = src[2 * u];
       } else {
 #pragma unroll
-        for (int u = 0; u < NRAW; ++u) {
-          if constexpr (QUAD) dst[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-          else dst[u] = make_float2(0.f, 0.f);
-        }
+        for (int u = 0; u < NRAW; ++u) dst[u] = reinterpret_cast<const float2*>(row)[u];
       }
-    };
-    auto unpack = [&](const Raw(&raw)[NRAW], float(&dst)[PA * PA]) {
+    } else {
 #pragma unroll
       for (int u = 0; u < NRAW; ++u) {
-        if constexpr (QUAD) {
-          // lane re holds (re, im) of coefficients 4u, 4u+1; lane im those of 4u+2, 4u+3
-          const float4 v = raw[u];
-          const float s0 = reim ? v.x : v.y, s1 = reim ? v.z : v.w;
-          const float r0 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s0), 0xB1, 0xF, 0xF, false));
-          const float r1 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s1), 0xB1, 0xF, 0xF, false));
-          dst[4 * u + 0] = reim ? r0 : v.x;
-          dst[4 * u + 1] = reim ? r1 : v.z;
-          dst[4 * u + 2] = reim ? v.y : r0;
-          dst[4 * u + 3] = reim ? v.w : r1;
-        } else {
-          dst[u] = reim ? raw[u].y : raw[u].x;
-        }
+        if constexpr (QUAD) dst[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+        else dst[u] = make_float2(0.f, 0.f);
       }
-    };
-    float av[PA * PA];
-    Raw rn[NRAW];
-    int s_cur = -1, s_nxt = -1;
-    if (wave_has) {
-      s_cur = slot_of(0);
-      s_nxt = slot_of(1);
-      load_raw(s_cur, rn);
-      unpack(rn, av);
     }
-    for (int g = 0; g < (wave_has ? ng : 0); ++g) {
-      const int n0 = sm.gstart[g], n1 = sm.gstart[g + 1];
-      const int s_nn = slot_of(g + 2);
-      load_raw(s_nxt, rn);
-      if (Bc >= 0 && s_cur < 0) atomicOr(err, 2);
-      // The column tiles of the group.  Branch-free: a column past the group
-      // gets a zero basis, and the accumulation of a tile - deferred to the
-      // next tile's iteration so that it can run under that tile's MFMAs -
-      // sends unused (column, row) entries to the spare row NB.
+  };
+  auto unpack = [&](const Raw(&raw)[NRAW], float(&dst)[PA * PA]) {
+#pragma unroll
+    for (int u = 0; u < NRAW; ++u) {
+      if constexpr (QUAD) {
+        // lane re holds (re, im) of coefficients 4u, 4u+1; lane im those of 4u+2, 4u+3
+        const float4 v = raw[u];
+        const float s0 = reim ? v.x : v.y, s1 = reim ? v.z : v.w;
+        const float r0 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s0), 0xB1, 0xF, 0xF, false));
+        const float r1 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(s1), 0xB1, 0xF, 0xF, false));
+        dst[4 * u + 0] = reim ? r0 : v.x;
+        dst[4 * u + 1] = reim ? r1 : v.z;
+        dst[4 * u + 2] = reim ? v.y : r0;
+        dst[4 * u + 3] = reim ? v.w : r1;
+      } else {
+        dst[u] = reim ? raw[u].y : raw[u].x;
+      }
+    }
+  };
+  // the child box of this lane's A row in octant o, -1 if none
+  auto row_child = [&](int o) -> int {
+    const int le = wv * 8 + (li >> 1);
+    return (o >= 0 && le < sm.ocnt[o]) ? sm.child[sm.olist[o][le]][o] : -1;
+  };
+
+  // ---- octants ----------------------------------------------------------------------
+  int o = next_oct(-1);   // block-uniform; -1 only if no box of the tile has a child
+  int cb = 0;             // geometry buffer of octant o
+  if (o >= 0) {
+    geometry(o);
+    __syncthreads();
+    group(sm.geo[0]);
+    __syncthreads();
+    place(sm.geo[0]);
+  }
+  // A-operand pipeline state carried from one octant to the next: when
+  // primed, av holds the operand of the octant's first group and s_cur /
+  // s_nxt the slots of its groups 0 and 1.
+  bool primed = false;
+  float av[PA * PA];
+  Raw rn[NRAW];
+  int s_cur = -1, s_nxt = -1;
+  while (o >= 0) {
+    const int o1 = next_oct(o);
+    typename S::Geo& G = sm.geo[cb];
+    typename S::Geo& G1 = sm.geo[cb ^ 1];
+    if (o1 >= 0) geometry(o1);
+    __syncthreads();   // G's records placed; cid of octant o1 written; G1 no longer read
+    if (o1 >= 0) group(G1);
+    __syncthreads();   // ranks and G1's groups written
+    if (o1 >= 0) place(G1);   // read from the next octant's MFMA phase on, after the next barrier
+
+    // ---- child interpolants on MFMA, group by group ---------------------------------
+    // The A operand is software-pipelined: while group g is evaluated, the
+    // coefficients of group g+1 and the slot of group g+2 are in flight;
+    // past the last group these are the first groups of octant o1.
+    const int ng = G.ngroup, no = sm.ocnt[o];
+    const int ng1 = o1 >= 0 ? G1.ngroup : 0;
+    const bool wave_has = 8 * wv < no;   // wave-uniform: the octant's list reaches this wave's rows
+    const bool wave_has1 = o1 >= 0 && 8 * wv < sm.ocnt[o1];
+    const int Bc = row_child(o), Bc1 = row_child(o1);
+    // Slot of group g of octant o, continuing into octant o1; -1: no child
+    // cone (zero operand); -2: a group past octant o1, whose geometry is not
+    // known yet (looked up again when octant o1 starts).
+    auto slot_at = [&](int g) -> int {
+      if (g < ng) return Bc >= 0 ? slot_c[(int64_t)Bc * gc.ncone + G.gcid[g]] : -1;
+      g -= ng;
+      if (g >= ng1) return o1 >= 0 ? -2 : -1;
+      return (wave_has1 && Bc1 >= 0) ? slot_c[(int64_t)Bc1 * gc.ncone + G1.gcid[g]] : -1;
+    };
+    if (wave_has) {
+      if (!primed) {
+        s_cur = slot_at(0);
+        s_nxt = slot_at(1);
+        load_raw(s_cur, rn);
+        unpack(rn, av);
+      } else if (s_nxt == -2) {   // wave-uniform: octant o has one group, its successor was unknown
+        s_nxt = slot_at(1);
+      }
       // lane 16 r + j holds rows 4r..4r+3 = boxes 2r, 2r+1 (re, im) of column j
       const int e2a = wv * 8 + 2 * la, e2b = e2a + 1;
       const int bxa = e2a < no ? (int)sm.olist[o][e2a] : NB, bxb = e2b < no ? (int)sm.olist[o][e2b] : NB;
+      // The accumulation of a column tile is deferred to the next tile's
+      // iteration (the first time: zeros to the spare row), so that it can
+      // run under that tile's MFMAs.  A column past its group gets a zero
+      // basis; its entries, and rows past the octant's list, go to row NB,
+      // the b entry to column P + 1 there, so that the two entries of a
+      // lane never coincide and both can be read before either is written.
       floatx4 dq = {0.f, 0.f, 0.f, 0.f};
+      float2 qr = make_float2(0.f, 0.f);
       int qn = 0, qa = NB, qb = NB;
       auto flush = [&]() {
-        const float er = sm.rat[qn][0], ei = sm.rat[qn][1];
         cpx<float>& ua = sm.acc[qa][qn];
-        cpx<float>& ub = sm.acc[qb][qn];
-        ua.re += er * dq[0] - ei * dq[1];
-        ua.im += er * dq[1] + ei * dq[0];
-        ub.re += er * dq[2] - ei * dq[3];
-        ub.im += er * dq[3] + ei * dq[2];
+        cpx<float>& ub = sm.acc[qb][qb == NB ? P + 1 : qn];
+        cpx<float> va = ua, vb = ub;
+        va.re += qr.x * dq[0] - qr.y * dq[1];
+        va.im += qr.x * dq[1] + qr.y * dq[0];
+        vb.re += qr.x * dq[2] - qr.y * dq[3];
+        vb.im += qr.x * dq[3] + qr.y * dq[2];
+        ua = va;
+        ub = vb;
       };
-      for (int c0 = n0; c0 < n1; c0 += 16) {
-        const int e = c0 + li;
-        const bool ok = e < n1;
-        const int n = sm.order[ok ? e : n0];
-        const float ta = (ok && la < PS) ? sm.bas[n][min(la, PS - 1)] : 0.f;
-        float tt[PA], tp[PA];
+      for (int g = 0; g < ng; ++g) {
+        const int n0 = G.gstart[g], n1 = G.gstart[g + 1];
+        const int s_nn = slot_at(g + 2);
+        load_raw(s_nxt, rn);
+        if (Bc >= 0 && s_cur < 0) atomicOr(err, 2);
+        for (int c0 = n0; c0 < n1; c0 += 16) {
+          const int e = c0 + li;
+          const bool ok = e < n1;
+          const int ee = ok ? e : n0;
+          const float4 lc = G.loc[ee];
+          const float2 rt = G.rat[ee];
+          const int n = G.node[ee];
+          float ts[PS], tt[PA], tp[PA];
+          cheb_T<float, PS>(lc.x, ts);
+          cheb_T<float, PA>(lc.y, tt);
+          cheb_T<float, PA>(lc.z, tp);
+          float ta = ts[0];
 #pragma unroll
-        for (int b = 0; b < PA; ++b) tt[b] = sm.bas[n][PS + b];
+          for (int a = 1; a < PS; ++a) ta = la == a ? ts[a] : ta;
+          ta = (ok && la < PS) ? ta : 0.f;
+          flush();   // the previous tile's
+          floatx4 d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int c = 0; c < PA; ++c) tp[c] = sm.bas[n][PS + PA + c];
-        flush();   // the previous tile's (the first time: zeros to the spare row)
-        floatx4 d = {0.f, 0.f, 0.f, 0.f};
+          for (int b = 0; b < PA; ++b) {
+            const float w = ta * tt[b];
 #pragma unroll
-        for (int b = 0; b < PA; ++b) {
-          const float w = ta * tt[b];
-#pragma unroll
-          for (int c = 0; c < PA; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b * PA + c], w * tp[c], d, 0, 0, 0);
+            for (int c = 0; c < PA; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b * PA + c], w * tp[c], d, 0, 0, 0);
+          }
+          dq = d;
+          qr = rt;
+          qn = n;
+          qa = ok ? bxa : NB;
+          qb = ok ? bxb : NB;
         }
-        dq = d;
-        qn = n;
-        qa = ok ? bxa : NB;
-        qb = ok ? bxb : NB;
+        unpack(rn, av);
+        s_cur = s_nxt;
+        s_nxt = s_nn;
       }
-      if (n1 > n0) flush();
+      flush();
+      primed = wave_has1;
+    } else if (wave_has1) {   // idle in octant o: prime the pipeline for octant o1
+      s_cur = slot_at(ng);
+      s_nxt = slot_at(ng + 1);
+      load_raw(s_cur, rn);
       unpack(rn, av);
-      s_cur = s_nxt;
-      s_nxt = s_nn;
+      primed = true;
+    } else {
+      primed = false;
     }
-    __syncthreads();
+    o = o1;
+    cb ^= 1;
   }
+  __syncthreads();
 
   // ---- node values -> coefficients, in place, then to the parent level -------------
   for (int t = threadIdx.x; t < nb * PA * PA; t += BS) {   // over a (s)
