@@ -1704,6 +1704,14 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
 // octant into the first group of the next; node records are stored in group
 // order, so a column tile reads its nodes with one LDS access each.
 // ---------------------------------------------------------------------------
+// A run of a wave's work units with the same row block and group: octant
+// k (0: current, 1: next; SEG_NONE / SEG_UNKNOWN: none, or not known yet),
+// row block r, group g, units u .. ue-1.
+constexpr int SEG_NONE = -1, SEG_UNKNOWN = -2;
+struct Seg {
+  int k, r, g, u, ue;
+};
+
 template <int PS, int PA, int NW> struct TiSmem {
   static constexpr int P = PS * PA * PA;
   static constexpr int NB = 8 * NW;
@@ -1715,6 +1723,8 @@ template <int PS, int PA, int NW> struct TiSmem {
     float2 rat[P];             // ratio K(x, y_B) / K(x, y_P)
     short node[P];             // node index
     short gstart[P + 1];       // group g: entries gstart[g] .. gstart[g+1]-1
+    short tstart[P + 1];       // group g: column tiles tstart[g] .. tstart[g+1]-1 (16 entries each)
+    short tgrp[P + P / 16 + 1];  // group of each column tile
     int gcid[P];               // child cone id of group g
     int ngroup;
   };
@@ -1726,6 +1736,7 @@ template <int PS, int PA, int NW> struct TiSmem {
   signed char olist[8][NB];    // per octant: the tile's boxes with a child there, ascending
   int ocnt[8];
   int pslot[NB];               // parent slot of each box
+  int clo[NB], ccnt[NB];       // first child and number of children of each box
   int anychild;                // bit o: some box of the tile has a child in octant o
   float ms[PS * PS], ma[PA * PA];
 };
@@ -1754,25 +1765,34 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
   for (int t = threadIdx.x; t < NB * 8; t += BS) sm.child[t >> 3][t & 7] = -1;
   for (int t = threadIdx.x; t < NB * S::ACC_LD; t += BS) sm.acc[t / S::ACC_LD][t % S::ACC_LD] = {0.f, 0.f};
   __syncthreads();
-  if (threadIdx.x < nb) {
+  if (threadIdx.x < nb) {   // each box: its parent slot and the range of its children
     const int sl = ti_slot[tl.y + threadIdx.x];
     const int Pb = rel_box_up[sl];
+    const int lo = child_lo_up[Pb], hi = child_lo_up[Pb + 1];
     sm.pslot[threadIdx.x] = sl;
-    int mask = 0;
-    for (int B = child_lo_up[Pb]; B < child_lo_up[Pb + 1]; ++B) {
-      const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
-      sm.child[threadIdx.x][oct] = B;
-      mask |= 1 << oct;
-    }
-    atomicOr(&sm.anychild, mask);
+    sm.clo[threadIdx.x] = lo;
+    sm.ccnt[threadIdx.x] = hi - lo;
   }
   __syncthreads();
-  if (threadIdx.x < 8) {   // per octant, the boxes that have a child in it (MFMA rows are packed with them)
-    const int o = threadIdx.x;
-    int c = 0;
-    for (int t = 0; t < nb; ++t)
-      if (sm.child[t][o] >= 0) sm.olist[o][c++] = (signed char)t;
-    sm.ocnt[o] = c;
+  for (int t = threadIdx.x; t < nb * 8; t += BS) {   // (box, child): the child's octant
+    const int bx = t >> 3, c = t & 7;
+    if (c < sm.ccnt[bx]) {
+      const int B = sm.clo[bx] + c;
+      const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+      sm.child[bx][oct] = B;
+      atomicOr(&sm.anychild, 1 << oct);
+    }
+  }
+  __syncthreads();
+  if (wv == 0) {   // per octant, the boxes that have a child in it (MFMA rows are packed with them)
+    static_assert(NB <= 64, "one lane per box");
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      const bool has = lane < nb && sm.child[lane < nb ? lane : 0][o] >= 0;
+      const uint64_t b = __ballot(has);
+      if (has) sm.olist[o][__popcll(b & ((1ull << lane) - 1))] = (signed char)lane;
+      if (lane == 0) sm.ocnt[o] = __popcll(b);
+    }
   }
   const int anychild = sm.anychild;   // written before the barrier above
   auto next_oct = [&](int o) -> int {  // next octant with children after o, -1 if none
@@ -1814,7 +1834,7 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
       pend[m] = n < P;
       cv[m] = pend[m] ? sm.cid[n] : 0;
     }
-    int pos = 0, g = 0;
+    int pos = 0, g = 0, tpos = 0;
     while (true) {
       int lead = -1, su = 0;
 #pragma unroll
@@ -1828,8 +1848,10 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
       if (lead < 0) break;
       if (lane == 0) {
         G.gstart[g] = (short)pos;
+        G.tstart[g] = (short)tpos;
         G.gcid[g] = su;
       }
+      const int pos0 = pos;
 #pragma unroll
       for (int m = 0; m < NPL; ++m) {
         const bool hit = pend[m] && cv[m] == su;
@@ -1838,10 +1860,14 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
         pos += __popcll(b);
         pend[m] = pend[m] && !hit;
       }
+      const int nt = (pos - pos0 + 15) >> 4;   // at most ceil(P / 16) <= 64 column tiles
+      if (lane < nt) G.tgrp[tpos + lane] = (short)g;
+      tpos += nt;
       ++g;
     }
     if (lane == 0) {
       G.gstart[g] = (short)pos;
+      G.tstart[g] = (short)tpos;
       G.ngroup = g;
     }
   };
@@ -1928,12 +1954,14 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
     place(sm.geo[0]);
   }
   // A-operand pipeline state carried from one octant to the next: when
-  // primed, av holds the operand of the octant's first group and s_cur /
-  // s_nxt the slots of its groups 0 and 1.
+  // primed, av holds the operand of segment cur, the wave's first in the
+  // octant, and s_nxt the slot of segment nxt (SEG_UNKNOWN: in an octant
+  // whose groups were not known yet).
   bool primed = false;
   float av[PA * PA];
   Raw rn[NRAW];
-  int s_cur = -1, s_nxt = -1;
+  Seg cur{SEG_NONE, 0, 0, 0, 0}, nxt{SEG_NONE, 0, 0, 0, 0};
+  int s_cur = -1, s_nxt = -1, b_cur = -1, b_nxt = -1;
   while (o >= 0) {
     const int o1 = next_oct(o);
     typename S::Geo& G = sm.geo[cb];
@@ -1944,105 +1972,128 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
     __syncthreads();   // ranks and G1's groups written
     if (o1 >= 0) place(G1);   // read from the next octant's MFMA phase on, after the next barrier
 
-    // ---- child interpolants on MFMA, group by group ---------------------------------
-    // The A operand is software-pipelined: while group g is evaluated, the
-    // coefficients of group g+1 and the slot of group g+2 are in flight;
-    // past the last group these are the first groups of octant o1.
-    const int ng = G.ngroup, no = sm.ocnt[o];
-    const int ng1 = o1 >= 0 ? G1.ngroup : 0;
-    const bool wave_has = 8 * wv < no;   // wave-uniform: the octant's list reaches this wave's rows
-    const bool wave_has1 = o1 >= 0 && 8 * wv < sm.ocnt[o1];
-    const int Bc = row_child(o), Bc1 = row_child(o1);
-    // Slot of group g of octant o, continuing into octant o1; -1: no child
-    // cone (zero operand); -2: a group past octant o1, whose geometry is not
-    // known yet (looked up again when octant o1 starts).
-    auto slot_at = [&](int g) -> int {
-      if (g < ng) return Bc >= 0 ? slot_c[(int64_t)Bc * gc.ncone + G.gcid[g]] : -1;
-      g -= ng;
-      if (g >= ng1) return o1 >= 0 ? -2 : -1;
-      return (wave_has1 && Bc1 >= 0) ? slot_c[(int64_t)Bc1 * gc.ncone + G1.gcid[g]] : -1;
+    // ---- child interpolants on MFMA ------------------------------------------------
+    // Work units are (row block r: 8 boxes of the octant's list, column tile
+    // t of the groups), r-major; wave wv takes the units [wv U / NW,
+    // (wv + 1) U / NW), so every wave has about the same share whatever the
+    // octant's box count.  A run of units with the same (r, group) is a
+    // segment and needs one A operand (the 8 boxes' coefficients of the
+    // group's child cone).  A wave's segments continue into octant o1, whose
+    // groups are known: while a segment is evaluated, the A operand of the
+    // next one and the slot of the one after are in flight, across the
+    // octant boundary too.  Units are disjoint in (box, node), so the waves'
+    // LDS accumulations within an octant never meet.
+    const int no = sm.ocnt[o], T = G.tstart[G.ngroup];
+    const int U = ((no + 7) >> 3) * T, u0 = wv * U / NW, u1 = (wv + 1) * U / NW;
+    const int no1 = o1 >= 0 ? sm.ocnt[o1] : 0, T1 = o1 >= 0 ? G1.tstart[G1.ngroup] : 0;
+    const int U1 = ((no1 + 7) >> 3) * T1, v0 = wv * U1 / NW, v1 = (wv + 1) * U1 / NW;
+    auto decode = [&](int kk, int u) -> Seg {   // the segment of unit u of octant o (kk = 0) or o1 (kk = 1)
+      const int TT = kk ? T1 : T, ue = kk ? v1 : u1;
+      const typename S::Geo& GG = kk ? G1 : G;
+      const int r = u / TT, g = GG.tgrp[u - r * TT];
+      return Seg{kk, r, g, u, min(ue, r * TT + GG.tstart[g + 1])};
     };
-    if (wave_has) {
-      if (!primed) {
-        s_cur = slot_at(0);
-        s_nxt = slot_at(1);
-        load_raw(s_cur, rn);
-        unpack(rn, av);
-      } else if (s_nxt == -2) {   // wave-uniform: octant o has one group, its successor was unknown
-        s_nxt = slot_at(1);
+    auto after = [&](const Seg& sg) -> Seg {   // the next segment of this wave's stream
+      if (sg.k == 0) {
+        if (sg.ue < u1) return decode(0, sg.ue);
+        if (v0 < v1) return decode(1, v0);
+        return Seg{o1 >= 0 ? SEG_UNKNOWN : SEG_NONE, 0, 0, 0, 0};
       }
-      // lane 16 r + j holds rows 4r..4r+3 = boxes 2r, 2r+1 (re, im) of column j
-      const int e2a = wv * 8 + 2 * la, e2b = e2a + 1;
-      const int bxa = e2a < no ? (int)sm.olist[o][e2a] : NB, bxb = e2b < no ? (int)sm.olist[o][e2b] : NB;
-      // The accumulation of a column tile is deferred to the next tile's
-      // iteration (the first time: zeros to the spare row), so that it can
-      // run under that tile's MFMAs.  A column past its group gets a zero
-      // basis; its entries, and rows past the octant's list, go to row NB,
-      // the b entry to column P + 1 there, so that the two entries of a
-      // lane never coincide and both can be read before either is written.
-      floatx4 dq = {0.f, 0.f, 0.f, 0.f};
-      float2 qr = make_float2(0.f, 0.f);
-      int qn = 0, qa = NB, qb = NB;
-      auto flush = [&]() {
-        cpx<float>& ua = sm.acc[qa][qn];
-        cpx<float>& ub = sm.acc[qb][qb == NB ? P + 1 : qn];
-        cpx<float> va = ua, vb = ub;
-        va.re += qr.x * dq[0] - qr.y * dq[1];
-        va.im += qr.x * dq[1] + qr.y * dq[0];
-        vb.re += qr.x * dq[2] - qr.y * dq[3];
-        vb.im += qr.x * dq[3] + qr.y * dq[2];
-        ua = va;
-        ub = vb;
-      };
-      for (int g = 0; g < ng; ++g) {
-        const int n0 = G.gstart[g], n1 = G.gstart[g + 1];
-        const int s_nn = slot_at(g + 2);
-        load_raw(s_nxt, rn);
-        if (Bc >= 0 && s_cur < 0) atomicOr(err, 2);
-        for (int c0 = n0; c0 < n1; c0 += 16) {
-          const int e = c0 + li;
-          const bool ok = e < n1;
-          const int ee = ok ? e : n0;
-          const float4 lc = G.loc[ee];
-          const float2 rt = G.rat[ee];
-          const int n = G.node[ee];
-          float ts[PS], tt[PA], tp[PA];
-          cheb_T<float, PS>(lc.x, ts);
-          cheb_T<float, PA>(lc.y, tt);
-          cheb_T<float, PA>(lc.z, tp);
-          float ta = ts[0];
-#pragma unroll
-          for (int a = 1; a < PS; ++a) ta = la == a ? ts[a] : ta;
-          ta = (ok && la < PS) ? ta : 0.f;
-          flush();   // the previous tile's
-          floatx4 d = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int b = 0; b < PA; ++b) {
-            const float w = ta * tt[b];
-#pragma unroll
-            for (int c = 0; c < PA; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b * PA + c], w * tp[c], d, 0, 0, 0);
-          }
-          dq = d;
-          qr = rt;
-          qn = n;
-          qa = ok ? bxa : NB;
-          qb = ok ? bxb : NB;
-        }
-        unpack(rn, av);
-        s_cur = s_nxt;
-        s_nxt = s_nn;
-      }
-      flush();
-      primed = wave_has1;
-    } else if (wave_has1) {   // idle in octant o: prime the pipeline for octant o1
-      s_cur = slot_at(ng);
-      s_nxt = slot_at(ng + 1);
+      if (sg.k == 1 && sg.ue < v1) return decode(1, sg.ue);
+      return Seg{sg.k == SEG_NONE ? SEG_NONE : SEG_UNKNOWN, 0, 0, 0, 0};
+    };
+    // slot of a segment's cone for this lane's A row (bc: the row's child box, -1 if none)
+    auto slot_of = [&](const Seg& sg, int& bc) -> int {
+      bc = -1;
+      if (sg.k < 0) return -1;
+      const int oo = sg.k ? o1 : o;
+      const int le = sg.r * 8 + (li >> 1);
+      if (le < sm.ocnt[oo]) bc = sm.child[sm.olist[oo][le]][oo];
+      return bc >= 0 ? slot_c[(int64_t)bc * gc.ncone + (sg.k ? G1 : G).gcid[sg.g]] : -1;
+    };
+    if (!primed) {
+      cur = u0 < u1 ? decode(0, u0) : (v0 < v1 ? decode(1, v0) : Seg{o1 >= 0 ? SEG_UNKNOWN : SEG_NONE, 0, 0, 0, 0});
+      nxt = after(cur);
+      s_cur = slot_of(cur, b_cur);
+      s_nxt = slot_of(nxt, b_nxt);
       load_raw(s_cur, rn);
       unpack(rn, av);
-      primed = true;
-    } else {
-      primed = false;
+    } else if (nxt.k == SEG_UNKNOWN) {   // known now that its octant is this one or o1
+      nxt = after(cur);
+      s_nxt = slot_of(nxt, b_nxt);
     }
+    // The accumulation of a column tile is deferred to the next tile's
+    // iteration (the first time: zeros to the spare row), so that it can run
+    // under that tile's MFMAs.  A column past its group gets a zero basis;
+    // its entries, and rows past the octant's list, go to row NB, the b entry
+    // to column P + 1 there, so that the two entries of a lane never
+    // coincide and both can be read before either is written.
+    floatx4 dq = {0.f, 0.f, 0.f, 0.f};
+    float2 qr = make_float2(0.f, 0.f);
+    int qn = 0, qa = NB, qb = NB;
+    auto flush = [&]() {
+      cpx<float>& ua = sm.acc[qa][qn];
+      cpx<float>& ub = sm.acc[qb][qb == NB ? P + 1 : qn];
+      cpx<float> va = ua, vb = ub;
+      va.re += qr.x * dq[0] - qr.y * dq[1];
+      va.im += qr.x * dq[1] + qr.y * dq[0];
+      vb.re += qr.x * dq[2] - qr.y * dq[3];
+      vb.im += qr.x * dq[3] + qr.y * dq[2];
+      ua = va;
+      ub = vb;
+    };
+    while (cur.k == 0) {   // wave-uniform
+      const Seg nn = after(nxt);
+      int b_nn;
+      const int s_nn = slot_of(nn, b_nn);
+      load_raw(s_nxt, rn);
+      if (b_cur >= 0 && s_cur < 0) atomicOr(err, 2);
+      const int g = cur.g, t0 = cur.r * T + G.tstart[g];
+      const int n0 = G.gstart[g], n1 = G.gstart[g + 1];
+      // lane 16 r + j holds rows 4r..4r+3 = boxes 2r, 2r+1 (re, im) of column j
+      const int e2a = cur.r * 8 + 2 * la, e2b = e2a + 1;
+      const int bxa = e2a < no ? (int)sm.olist[o][e2a] : NB, bxb = e2b < no ? (int)sm.olist[o][e2b] : NB;
+      for (int u = cur.u; u < cur.ue; ++u) {
+        const int e = n0 + 16 * (u - t0) + li;
+        const bool ok = e < n1;
+        const int ee = ok ? e : n0;
+        const float4 lc = G.loc[ee];
+        const float2 rt = G.rat[ee];
+        const int n = G.node[ee];
+        float ts[PS], tt[PA], tp[PA];
+        cheb_T<float, PS>(lc.x, ts);
+        cheb_T<float, PA>(lc.y, tt);
+        cheb_T<float, PA>(lc.z, tp);
+        float ta = ts[0];
+#pragma unroll
+        for (int a = 1; a < PS; ++a) ta = la == a ? ts[a] : ta;
+        ta = (ok && la < PS) ? ta : 0.f;
+        flush();   // the previous tile's
+        floatx4 d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < PA; ++b) {
+          const float w = ta * tt[b];
+#pragma unroll
+          for (int c = 0; c < PA; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(av[b * PA + c], w * tp[c], d, 0, 0, 0);
+        }
+        dq = d;
+        qr = rt;
+        qn = n;
+        qa = ok ? bxa : NB;
+        qb = ok ? bxb : NB;
+      }
+      unpack(rn, av);
+      cur = nxt;
+      nxt = nn;
+      s_cur = s_nxt;
+      s_nxt = s_nn;
+      b_cur = b_nxt;
+      b_nxt = b_nn;
+    }
+    flush();
+    primed = cur.k == 1;   // av holds the operand of cur, a segment of octant o1
+    if (cur.k == 1) cur.k = 0;   // octant o1 becomes the current one
+    if (nxt.k == 1) nxt.k = 0;
     o = o1;
     cb ^= 1;
   }
@@ -2110,7 +2161,7 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
 }
 
 template <int PS, int PA, int NW>
-__global__ __launch_bounds__(64 * NW) void k_prop_ti(
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void k_prop_ti(
     const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ rel_box_up,
     const int* __restrict__ child_lo_up, const int* __restrict__ coords, const int* __restrict__ slot_c,
     const cpx<float>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct, const float* __restrict__ Ms,
