@@ -1736,16 +1736,15 @@ template <int PS, int PA, int NW> struct TiSmem {
   signed char olist[8][NB];    // per octant: the tile's boxes with a child there, ascending
   int ocnt[8];
   int pslot[NB];               // parent slot of each box
-  int clo[NB], ccnt[NB];       // first child and number of children of each box
-  int anychild;                // bit o: some box of the tile has a child in octant o
   float ms[PS * PS], ma[PA * PA];
 };
 
-// One tile tl = (cone id, first index into ti_slot, boxes) by a block of 64 NW threads.
+// One tile tl = (cone id, first index into ti_slot, boxes) by a block of 64 NW
+// threads; ti_child[8 i + o] is the child in octant o of the box of ti_slot[i]
+// (-1 if none).
 template <int PS, int PA, int NW>
 __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, const int* __restrict__ ti_slot,
-                                             const int* __restrict__ rel_box_up, const int* __restrict__ child_lo_up,
-                                             const int* __restrict__ coords, const int* __restrict__ slot_c,
+                                             const int* __restrict__ ti_child, const int* __restrict__ slot_c,
                                              const cpx<float>* __restrict__ Fc_c, const LevelGeom& gp,
                                              const LevelGeom& gc, const ChebTab& ct, const float* __restrict__ Ms,
                                              const float* __restrict__ Ma, double k, int kind,
@@ -1761,40 +1760,25 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
   // ---- set-up: boxes, their children by octant -----------------------------------
   if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = Ms[threadIdx.x];
   if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
-  if (threadIdx.x == 0) sm.anychild = 0;
-  for (int t = threadIdx.x; t < NB * 8; t += BS) sm.child[t >> 3][t & 7] = -1;
+  for (int t = threadIdx.x; t < NB * 8; t += BS)
+    sm.child[t >> 3][t & 7] = (t >> 3) < nb ? ti_child[(int64_t)(tl.y + (t >> 3)) * 8 + (t & 7)] : -1;
+  if (threadIdx.x < nb) sm.pslot[threadIdx.x] = ti_slot[tl.y + threadIdx.x];
   for (int t = threadIdx.x; t < NB * S::ACC_LD; t += BS) sm.acc[t / S::ACC_LD][t % S::ACC_LD] = {0.f, 0.f};
   __syncthreads();
-  if (threadIdx.x < nb) {   // each box: its parent slot and the range of its children
-    const int sl = ti_slot[tl.y + threadIdx.x];
-    const int Pb = rel_box_up[sl];
-    const int lo = child_lo_up[Pb], hi = child_lo_up[Pb + 1];
-    sm.pslot[threadIdx.x] = sl;
-    sm.clo[threadIdx.x] = lo;
-    sm.ccnt[threadIdx.x] = hi - lo;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < nb * 8; t += BS) {   // (box, child): the child's octant
-    const int bx = t >> 3, c = t & 7;
-    if (c < sm.ccnt[bx]) {
-      const int B = sm.clo[bx] + c;
-      const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
-      sm.child[bx][oct] = B;
-      atomicOr(&sm.anychild, 1 << oct);
-    }
-  }
-  __syncthreads();
-  if (wv == 0) {   // per octant, the boxes that have a child in it (MFMA rows are packed with them)
-    static_assert(NB <= 64, "one lane per box");
+  // per octant, the boxes that have a child in it (MFMA rows are packed with
+  // them): every wave forms the octant mask, wave 0 writes the lists
+  static_assert(NB <= 64, "one lane per box");
+  int anychild = 0;
 #pragma unroll
-    for (int o = 0; o < 8; ++o) {
-      const bool has = lane < nb && sm.child[lane < nb ? lane : 0][o] >= 0;
-      const uint64_t b = __ballot(has);
+  for (int o = 0; o < 8; ++o) {
+    const bool has = lane < nb && sm.child[lane < nb ? lane : 0][o] >= 0;
+    const uint64_t b = __ballot(has);
+    anychild |= b ? 1 << o : 0;
+    if (wv == 0) {
       if (has) sm.olist[o][__popcll(b & ((1ull << lane) - 1))] = (signed char)lane;
       if (lane == 0) sm.ocnt[o] = __popcll(b);
     }
   }
-  const int anychild = sm.anychild;   // written before the barrier above
   auto next_oct = [&](int o) -> int {  // next octant with children after o, -1 if none
     const int m = o < 0 ? anychild : anychild & ~((2 << o) - 1);
     return m ? __builtin_ctz(m) : -1;
@@ -2162,13 +2146,13 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
 
 template <int PS, int PA, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void k_prop_ti(
-    const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ rel_box_up,
-    const int* __restrict__ child_lo_up, const int* __restrict__ coords, const int* __restrict__ slot_c,
-    const cpx<float>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct, const float* __restrict__ Ms,
-    const float* __restrict__ Ma, double k, int kind, cpx<float>* __restrict__ Fc_up, int* __restrict__ err) {
+    const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ ti_child,
+    const int* __restrict__ slot_c, const cpx<float>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct,
+    const float* __restrict__ Ms, const float* __restrict__ Ma, double k, int kind, cpx<float>* __restrict__ Fc_up,
+    int* __restrict__ err) {
   __shared__ TiSmem<PS, PA, NW> sm;
-  prop_ti_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, rel_box_up, child_lo_up, coords,
-                           slot_c, Fc_c, gp, gc, ct, Ms, Ma, k, kind, Fc_up, err);
+  prop_ti_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, ti_child, slot_c, Fc_c, gp, gc, ct,
+                           Ms, Ma, k, kind, Fc_up, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -2935,9 +2919,9 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
           auto launch = [&](auto kern, int nw) {
             kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
-                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.rel_box.as<int>(), lp.child_lo.as<int>(),
-                lc.coords.as<int>(), lc.slot.as<int>(), lc.Fc.as<cpx<float>>(), lp.geom, lc.geom, p->cheb,
-                (const float*)Ms, (const float*)Ma, p->k, kind, lp.Fc.as<cpx<float>>(), p->err.as<int>());
+                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lc.slot.as<int>(),
+                lc.Fc.as<cpx<float>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms, (const float*)Ma, p->k, kind,
+                lp.Fc.as<cpx<float>>(), p->err.as<int>());
           };
           if (lp.ti_nw == 4) launch(k_prop_ti<PS, PA, 4>, 4);
           else if (lp.ti_nw == 2) launch(k_prop_ti<PS, PA, 2>, 2);
@@ -3148,6 +3132,7 @@ template <typename T> struct BLevel {
   const int4 IFGF_GAS* work;
   const int4 IFGF_GAS* ti_tile;   // cone-major tiles of the pass into this level (FP32)
   const int IFGF_GAS* ti_slot;
+  const int IFGF_GAS* ti_child;
   cpx<T> IFGF_GAS* Fn;
   cpx<T> IFGF_GAS* Fc;
   LevelGeom g;
@@ -3307,9 +3292,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
         const BLevel<T>& lc = G.lv[d];
         const BLevel<T>& lp = G.lv[d - 1];
         prop_ti_tile<PS, PA, 4>(*reinterpret_cast<TiSmem<PS, PA, 4>*>(smem), gen(lp.ti_tile)[local],
-                                gen(lp.ti_slot), gen(lp.rel_box), gen(lp.child_lo), gen(lc.coords), gen(lc.slot),
-                                gen(lc.Fc), lp.g, lc.g, G.ct, gen(G.Ms), gen(G.Ma), G.k, G.kind, gen(lp.Fc),
-                                gen(G.err));
+                                gen(lp.ti_slot), gen(lp.ti_child), gen(lc.slot), gen(lc.Fc), lp.g, lc.g, G.ct,
+                                gen(G.Ms), gen(G.Ma), G.k, G.kind, gen(lp.Fc), gen(G.err));
       }
       break;
     }
@@ -3414,6 +3398,7 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       L.work = gas(l.work.as<const int4>());
       L.ti_tile = gas(l.ti_tile.as<const int4>());
       L.ti_slot = gas(l.ti_slot.as<const int>());
+      L.ti_child = gas(l.ti_child.as<const int>());
       L.Fn = gas(l.Fn.as<cpx<T>>());
       L.Fc = gas(l.Fc.as<cpx<T>>());
       L.g = l.geom;

@@ -65,6 +65,7 @@ struct LevelPlan {
   // relevant cones sorted by (cone id, slot), in tiles of up to 8 * ti_nw
   // boxes sharing one cone id: int4 (cone id, first index into ti_slot, count, 0)
   DevBuf ti_slot, ti_tile;
+  DevBuf ti_child;            // per ti_slot entry: its box's child in each octant (8 ints, -1 if none)
   int64_t ntile = 0;
   // near field at the finest level: int4 [n_near] (box, first target, target
   // count, 0), boxes split into chunks of at most kNearChunk targets

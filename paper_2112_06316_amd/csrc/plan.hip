@@ -758,12 +758,22 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
         tiles.push_back(t[3]);
         tiles.push_back(0);
       }
+      // each tile box's child per octant, in ti_slot order, so that a tile
+      // reads its boxes' children with one coalesced load
+      std::vector<int> tchild(8 * (size_t)lv.nrel, -1);
+      for (int64_t i = 0; i < lv.nrel; ++i) {
+        const int b = rbox[slots[i]];
+        for (int c = clo[b]; c < clo[b + 1]; ++c)
+          tchild[8 * i + ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) | ((ccoords[3 * c + 2] & 1) << 2))] = c;
+      }
       lv.ti_nw = nw;
       lv.ntile = (int64_t)tiles.size() / 4;
       lv.ti_slot.alloc(sizeof(int) * lv.nrel);
       lv.ti_tile.alloc(sizeof(int) * tiles.size());
+      lv.ti_child.alloc(sizeof(int) * tchild.size());
       HIPCHK(hipMemcpy(lv.ti_slot.p, slots.data(), sizeof(int) * lv.nrel, hipMemcpyHostToDevice));
       HIPCHK(hipMemcpy(lv.ti_tile.p, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(lv.ti_child.p, tchild.data(), sizeof(int) * tchild.size(), hipMemcpyHostToDevice));
     }
   }
 
