@@ -1712,26 +1712,120 @@ struct Seg {
   int k, r, g, u, ue;
 };
 
+// The nodes of parent cone id q in the frame of the child in octant o,
+// grouped by child cone, in group order.  The same for every box of a level:
+// the plan computes one per (cone id, octant) of the cone-major tiles.
+template <int PS, int PA> struct alignas(16) TiGeo {
+  static constexpr int P = PS * PA * PA;
+  float4 loc[P];               // (ts, tt, tp, -): local coordinates in the node's child cone
+  float2 rat[P];               // ratio K(x, y_B) / K(x, y_P)
+  short node[P];               // node index
+  short gstart[P + 1];         // group g: entries gstart[g] .. gstart[g+1]-1
+  short tstart[P + 1];         // group g: column tiles tstart[g] .. tstart[g+1]-1 (16 entries each)
+  short tgrp[P + P / 16 + 1];  // group of each column tile
+  int gcid[P];                 // child cone id of group g
+  int ngroup;
+};
+
+// One TiGeo record per work-group: (cone id qlist[b / 8], octant b % 8), node
+// n on thread n; geometry, grouping by child cone (wave 0), then the records
+// in group order.
+template <int PS, int PA>
+__global__ __launch_bounds__(256) void k_ti_geo(const int* __restrict__ qlist, LevelGeom gp, LevelGeom gc,
+                                                ChebTab ct, double k, int kind, TiGeo<PS, PA>* __restrict__ out) {
+  using Geo = TiGeo<PS, PA>;
+  constexpr int P = Geo::P;
+  static_assert(P <= 256, "one node per thread");
+  __shared__ Geo G;
+  __shared__ int cid[P];
+  __shared__ short rank[P];
+  const int q = qlist[blockIdx.x >> 3], o = blockIdx.x & 7;
+  const int n = threadIdx.x, lane = n & 63, wv = n >> 6;
+  float4 loc = make_float4(0.f, 0.f, 0.f, 0.f);
+  float2 rat = make_float2(0.f, 0.f);
+  if (n < P) {
+    float x[3], rp;   // node relative to the parent centre
+    node_rel32(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
+    const PropF pr = child_loc32(x, rp, o, gc);
+    cid[n] = pr.loc.cid;
+    loc = make_float4(pr.loc.ts, pr.loc.tt, pr.loc.tp, 0.f);
+    float c_ = 1.f, s_ = 0.f, rr = 1.f;
+    if (kind != IFGF_KERNEL_CONSTANT) {
+      sincos_f((float)k * pr.dr, &s_, &c_);
+      rr = pr.rp_over_rc;
+    }
+    rat = make_float2(rr * c_, rr * s_);
+  }
+  __syncthreads();
+  if (wv == 0) {   // groups in order of first appearance; ranks within them
+    constexpr int NPL = (P + 63) / 64;   // nodes per lane
+    int cv[NPL];
+    bool pend[NPL];
+#pragma unroll
+    for (int m = 0; m < NPL; ++m) {
+      const int nn = lane + 64 * m;
+      pend[m] = nn < P;
+      cv[m] = pend[m] ? cid[nn] : 0;
+    }
+    int pos = 0, g = 0, tpos = 0;
+    while (true) {
+      int lead = -1, su = 0;
+#pragma unroll
+      for (int m = 0; m < NPL && lead < 0; ++m) {
+        const uint64_t b = __ballot(pend[m]);
+        if (b) {
+          lead = first_lane(b);
+          su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
+        }
+      }
+      if (lead < 0) break;
+      if (lane == 0) {
+        G.gstart[g] = (short)pos;
+        G.tstart[g] = (short)tpos;
+        G.gcid[g] = su;
+      }
+      const int pos0 = pos;
+#pragma unroll
+      for (int m = 0; m < NPL; ++m) {
+        const bool hit = pend[m] && cv[m] == su;
+        const uint64_t b = __ballot(hit);
+        if (hit) rank[lane + 64 * m] = (short)(pos + __popcll(b & ((1ull << lane) - 1)));
+        pos += __popcll(b);
+        pend[m] = pend[m] && !hit;
+      }
+      const int nt = (pos - pos0 + 15) >> 4;   // at most ceil(P / 16) <= 64 column tiles
+      if (lane < nt) G.tgrp[tpos + lane] = (short)g;
+      tpos += nt;
+      ++g;
+    }
+    if (lane == 0) {
+      G.gstart[g] = (short)pos;
+      G.tstart[g] = (short)tpos;
+      G.ngroup = g;
+    }
+  }
+  __syncthreads();
+  if (n < P) {
+    const int r = rank[n];
+    G.loc[r] = loc;
+    G.rat[r] = rat;
+    G.node[r] = (short)n;
+  }
+  __syncthreads();
+  const uint4* src = reinterpret_cast<const uint4*>(&G);
+  uint4* dst = reinterpret_cast<uint4*>(out + blockIdx.x);
+  for (int i = threadIdx.x; i < (int)(sizeof(Geo) / 16); i += 256) dst[i] = src[i];
+}
+
 template <int PS, int PA, int NW> struct TiSmem {
   static constexpr int P = PS * PA * PA;
   static constexpr int NB = 8 * NW;
   // Row stride padded so that lanes reading different boxes fall in
   // different LDS banks; columns P and P + 1 of row NB take unused updates.
   static constexpr int ACC_LD = P + 4;
-  struct Geo {                 // one octant, nodes in group order
-    float4 loc[P];             // (ts, tt, tp, -): local coordinates in the node's child cone
-    float2 rat[P];             // ratio K(x, y_B) / K(x, y_P)
-    short node[P];             // node index
-    short gstart[P + 1];       // group g: entries gstart[g] .. gstart[g+1]-1
-    short tstart[P + 1];       // group g: column tiles tstart[g] .. tstart[g+1]-1 (16 entries each)
-    short tgrp[P + P / 16 + 1];  // group of each column tile
-    int gcid[P];               // child cone id of group g
-    int ngroup;
-  };
+  using Geo = TiGeo<PS, PA>;
   cpx<float> acc[NB + 1][ACC_LD];  // node values of the tile's boxes; row NB takes unused updates
   Geo geo[2];
-  int cid[P];                  // child cone id per node (octant being grouped)
-  short rank[P];               // position of each node in group order
   int child[NB][8];            // child box per (box, octant), -1 if none
   signed char olist[8][NB];    // per octant: the tile's boxes with a child there, ascending
   int ocnt[8];
@@ -1739,12 +1833,14 @@ template <int PS, int PA, int NW> struct TiSmem {
   float ms[PS * PS], ma[PA * PA];
 };
 
-// One tile tl = (cone id, first index into ti_slot, boxes) by a block of 64 NW
-// threads; ti_child[8 i + o] is the child in octant o of the box of ti_slot[i]
-// (-1 if none).
+// One tile tl = (cone id, first index into ti_slot, boxes, index of the cone
+// id's records in ti_geo) by a block of 64 NW threads; ti_child[8 i + o] is
+// the child in octant o of the box of ti_slot[i] (-1 if none), ti_geo[8 j + o]
+// the node records of octant o of the tile's cone id.
 template <int PS, int PA, int NW>
 __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, const int* __restrict__ ti_slot,
-                                             const int* __restrict__ ti_child, const int* __restrict__ slot_c,
+                                             const int* __restrict__ ti_child,
+                                             const TiGeo<PS, PA>* __restrict__ ti_geo, const int* __restrict__ slot_c,
                                              const cpx<float>* __restrict__ Fc_c, const LevelGeom& gp,
                                              const LevelGeom& gc, const ChebTab& ct, const float* __restrict__ Ms,
                                              const float* __restrict__ Ma, double k, int kind,
@@ -1753,8 +1849,7 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
   constexpr int P = S::P;
   constexpr int NB = S::NB;
   constexpr int BS = 64 * NW;
-  constexpr int NPT = (P + BS - 1) / BS;   // nodes per thread in the geometry pass
-  const int q = tl.x, nb = tl.z;
+  const int nb = tl.z;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
   // ---- set-up: boxes, their children by octant -----------------------------------
@@ -1784,88 +1879,11 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
     return m ? __builtin_ctz(m) : -1;
   };
 
-  // ---- geometry of an octant: thread t holds nodes t, t + BS, ... -------------------
-  float4 gloc[NPT];
-  float2 grat[NPT];
-  auto geometry = [&](int o) {   // each node's child cone (to LDS), local coordinates and ratio
-#pragma unroll
-    for (int m = 0; m < NPT; ++m) {
-      const int n = threadIdx.x + m * BS;
-      if (n < P) {
-        float x[3], rp;   // node relative to the parent centre (recomputed: cheaper than the LDS it would hold)
-        node_rel32(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
-        const PropF pr = child_loc32(x, rp, o, gc);
-        sm.cid[n] = pr.loc.cid;
-        gloc[m] = make_float4(pr.loc.ts, pr.loc.tt, pr.loc.tp, 0.f);
-        float c_ = 1.f, s_ = 0.f, rr = 1.f;
-        if (kind != IFGF_KERNEL_CONSTANT) {
-          sincos_f((float)k * pr.dr, &s_, &c_);
-          rr = pr.rp_over_rc;
-        }
-        grat[m] = make_float2(rr * c_, rr * s_);
-      }
-    }
-  };
-  // group the nodes by child cone (wave 0): group starts, cone ids and each node's rank
-  auto group = [&](typename S::Geo& G) {
-    if (wv != 0) return;
-    constexpr int NPL = (P + 63) / 64;   // nodes per lane
-    int cv[NPL];
-    bool pend[NPL];
-#pragma unroll
-    for (int m = 0; m < NPL; ++m) {
-      const int n = lane + 64 * m;
-      pend[m] = n < P;
-      cv[m] = pend[m] ? sm.cid[n] : 0;
-    }
-    int pos = 0, g = 0, tpos = 0;
-    while (true) {
-      int lead = -1, su = 0;
-#pragma unroll
-      for (int m = 0; m < NPL && lead < 0; ++m) {
-        const uint64_t b = __ballot(pend[m]);
-        if (b) {
-          lead = first_lane(b);
-          su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
-        }
-      }
-      if (lead < 0) break;
-      if (lane == 0) {
-        G.gstart[g] = (short)pos;
-        G.tstart[g] = (short)tpos;
-        G.gcid[g] = su;
-      }
-      const int pos0 = pos;
-#pragma unroll
-      for (int m = 0; m < NPL; ++m) {
-        const bool hit = pend[m] && cv[m] == su;
-        const uint64_t b = __ballot(hit);
-        if (hit) sm.rank[lane + 64 * m] = (short)(pos + __popcll(b & ((1ull << lane) - 1)));
-        pos += __popcll(b);
-        pend[m] = pend[m] && !hit;
-      }
-      const int nt = (pos - pos0 + 15) >> 4;   // at most ceil(P / 16) <= 64 column tiles
-      if (lane < nt) G.tgrp[tpos + lane] = (short)g;
-      tpos += nt;
-      ++g;
-    }
-    if (lane == 0) {
-      G.gstart[g] = (short)pos;
-      G.tstart[g] = (short)tpos;
-      G.ngroup = g;
-    }
-  };
-  auto place = [&](typename S::Geo& G) {   // each node's record at its rank
-#pragma unroll
-    for (int m = 0; m < NPT; ++m) {
-      const int n = threadIdx.x + m * BS;
-      if (n < P) {
-        const int r = sm.rank[n];
-        G.loc[r] = gloc[m];
-        G.rat[r] = grat[m];
-        G.node[r] = (short)n;
-      }
-    }
+  // ---- an octant's node records, from the plan's table ---------------------------
+  auto fetch = [&](typename S::Geo& dst, int oo) {
+    const uint4* src = reinterpret_cast<const uint4*>(ti_geo + (int64_t)tl.w * 8 + oo);
+    uint4* d = reinterpret_cast<uint4*>(&dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(typename S::Geo) / 16); i += BS) d[i] = src[i];
   };
 
   // this lane's A rows and B columns; in each octant, the wave's 8 rows are
@@ -1929,14 +1947,8 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
 
   // ---- octants ----------------------------------------------------------------------
   int o = next_oct(-1);   // block-uniform; -1 only if no box of the tile has a child
-  int cb = 0;             // geometry buffer of octant o
-  if (o >= 0) {
-    geometry(o);
-    __syncthreads();
-    group(sm.geo[0]);
-    __syncthreads();
-    place(sm.geo[0]);
-  }
+  int cb = 0;             // record buffer of octant o
+  if (o >= 0) fetch(sm.geo[0], o);
   // A-operand pipeline state carried from one octant to the next: when
   // primed, av holds the operand of segment cur, the wave's first in the
   // octant, and s_nxt the slot of segment nxt (SEG_UNKNOWN: in an octant
@@ -1950,11 +1962,9 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
     const int o1 = next_oct(o);
     typename S::Geo& G = sm.geo[cb];
     typename S::Geo& G1 = sm.geo[cb ^ 1];
-    if (o1 >= 0) geometry(o1);
-    __syncthreads();   // G's records placed; cid of octant o1 written; G1 no longer read
-    if (o1 >= 0) group(G1);
-    __syncthreads();   // ranks and G1's groups written
-    if (o1 >= 0) place(G1);   // read from the next octant's MFMA phase on, after the next barrier
+    __syncthreads();   // G's records visible; G1 no longer read (previous octant's MFMA phase done)
+    if (o1 >= 0) fetch(G1, o1);
+    __syncthreads();   // G1's records visible
 
     // ---- child interpolants on MFMA ------------------------------------------------
     // Work units are (row block r: 8 boxes of the octant's list, column tile
@@ -2147,12 +2157,12 @@ __device__ __forceinline__ void prop_ti_tile(TiSmem<PS, PA, NW>& sm, int4 tl, co
 template <int PS, int PA, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) void k_prop_ti(
     const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ ti_child,
-    const int* __restrict__ slot_c, const cpx<float>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct,
-    const float* __restrict__ Ms, const float* __restrict__ Ma, double k, int kind, cpx<float>* __restrict__ Fc_up,
-    int* __restrict__ err) {
+    const TiGeo<PS, PA>* __restrict__ ti_geo, const int* __restrict__ slot_c, const cpx<float>* __restrict__ Fc_c,
+    LevelGeom gp, LevelGeom gc, ChebTab ct, const float* __restrict__ Ms, const float* __restrict__ Ma, double k,
+    int kind, cpx<float>* __restrict__ Fc_up, int* __restrict__ err) {
   __shared__ TiSmem<PS, PA, NW> sm;
-  prop_ti_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, ti_child, slot_c, Fc_c, gp, gc, ct,
-                           Ms, Ma, k, kind, Fc_up, err);
+  prop_ti_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, ti_child, ti_geo, slot_c, Fc_c, gp,
+                           gc, ct, Ms, Ma, k, kind, Fc_up, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -2919,9 +2929,9 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
           auto launch = [&](auto kern, int nw) {
             kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
-                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lc.slot.as<int>(),
-                lc.Fc.as<cpx<float>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms, (const float*)Ma, p->k, kind,
-                lp.Fc.as<cpx<float>>(), p->err.as<int>());
+                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lp.ti_geo.as<TiGeo<PS, PA>>(),
+                lc.slot.as<int>(), lc.Fc.as<cpx<float>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms,
+                (const float*)Ma, p->k, kind, lp.Fc.as<cpx<float>>(), p->err.as<int>());
           };
           if (lp.ti_nw == 4) launch(k_prop_ti<PS, PA, 4>, 4);
           else if (lp.ti_nw == 2) launch(k_prop_ti<PS, PA, 2>, 2);
@@ -3133,6 +3143,7 @@ template <typename T> struct BLevel {
   const int4 IFGF_GAS* ti_tile;   // cone-major tiles of the pass into this level (FP32)
   const int IFGF_GAS* ti_slot;
   const int IFGF_GAS* ti_child;
+  const uint4 IFGF_GAS* ti_geo;   // node records per (cone id, octant) of the tiles (FP32)
   cpx<T> IFGF_GAS* Fn;
   cpx<T> IFGF_GAS* Fc;
   LevelGeom g;
@@ -3292,8 +3303,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
         const BLevel<T>& lc = G.lv[d];
         const BLevel<T>& lp = G.lv[d - 1];
         prop_ti_tile<PS, PA, 4>(*reinterpret_cast<TiSmem<PS, PA, 4>*>(smem), gen(lp.ti_tile)[local],
-                                gen(lp.ti_slot), gen(lp.ti_child), gen(lc.slot), gen(lc.Fc), lp.g, lc.g, G.ct,
-                                gen(G.Ms), gen(G.Ma), G.k, G.kind, gen(lp.Fc), gen(G.err));
+                                gen(lp.ti_slot), gen(lp.ti_child),
+                                reinterpret_cast<const TiGeo<PS, PA>*>(gen(lp.ti_geo)), gen(lc.slot), gen(lc.Fc),
+                                lp.g, lc.g, G.ct, gen(G.Ms), gen(G.Ma), G.k, G.kind, gen(lp.Fc), gen(G.err));
       }
       break;
     }
@@ -3399,6 +3411,7 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       L.ti_tile = gas(l.ti_tile.as<const int4>());
       L.ti_slot = gas(l.ti_slot.as<const int>());
       L.ti_child = gas(l.ti_child.as<const int>());
+      L.ti_geo = gas(l.ti_geo.as<const uint4>());
       L.Fn = gas(l.Fn.as<cpx<T>>());
       L.Fc = gas(l.Fc.as<cpx<T>>());
       L.g = l.geom;
@@ -3552,7 +3565,29 @@ void dispatch_apply(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
 }
 
+template <int PS, int PA>
+void ti_geo_impl(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s) {
+  LevelPlan& lp = p->lev[d];
+  const LevelPlan& lc = p->lev[d + 1];
+  DevBuf qd;
+  qd.alloc(sizeof(int) * qlist.size());
+  HIPCHK(hipMemcpyAsync(qd.p, qlist.data(), sizeof(int) * qlist.size(), hipMemcpyHostToDevice, s));
+  lp.ti_geo.alloc(sizeof(TiGeo<PS, PA>) * 8 * qlist.size());
+  k_ti_geo<PS, PA><<<(unsigned)(8 * qlist.size()), 256, 0, s>>>(qd.as<int>(), lp.geom, lc.geom, p->cheb, p->k,
+                                                                 p->opt.kernel, lp.ti_geo.as<TiGeo<PS, PA>>());
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));   // qd is freed on return
+}
+
 }  // namespace
+
+void build_ti_geo(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s) {
+  if (qlist.empty()) return;
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+  if (ps == 3 && pa == 5) return ti_geo_impl<3, 5>(p, d, qlist, s);
+  if (ps == 4 && pa == 6) return ti_geo_impl<4, 6>(p, d, qlist, s);
+  throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
+}
 
 int prop_chunk(int P) {
   if (P == 75) return PropShape<75>::CH;

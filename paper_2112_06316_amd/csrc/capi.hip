@@ -221,7 +221,7 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
       st->prop_evals[d] = l.prop_evals;
       add(l.start); add(l.coords); add(l.centre); add(l.parent); add(l.child_lo); add(l.nbr_off); add(l.nbr);
       add(l.cou_off); add(l.cou); add(l.pbox); add(l.slot); add(l.slot_off); add(l.rel_box); add(l.rel_cone);
-      add(l.Fn); add(l.Fc); add(l.work); add(l.ti_slot); add(l.ti_tile); add(l.ti_child); add(l.near_work); add(l.leaf_work);
+      add(l.Fn); add(l.Fc); add(l.work); add(l.ti_slot); add(l.ti_tile); add(l.ti_child); add(l.ti_geo); add(l.near_work); add(l.leaf_work);
       add(p->adj_g[d]);
       if (d >= 4 && p->lev[d - 1].nrel > 0)
         st->prop_kernel[d] = p->lev[d - 1].ntile > 0 ? IFGF_PROP_CONE : IFGF_PROP_NODE;

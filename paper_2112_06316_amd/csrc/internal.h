@@ -66,6 +66,7 @@ struct LevelPlan {
   // boxes sharing one cone id: int4 (cone id, first index into ti_slot, count, 0)
   DevBuf ti_slot, ti_tile;
   DevBuf ti_child;            // per ti_slot entry: its box's child in each octant (8 ints, -1 if none)
+  DevBuf ti_geo;              // FP32: node records per (cone id of the tiles, octant), see build_ti_geo
   int64_t ntile = 0;
   // near field at the finest level: int4 [n_near] (box, first target, target
   // count, 0), boxes split into chunks of at most kNearChunk targets
@@ -160,6 +161,9 @@ void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, 
 void run_batch_prepare(ifgf_batch_s* b);
 void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, hipStream_t s);
 
+// The cone-major tiles' node records of level d (one per cone id in qlist and
+// octant), computed on the GPU into p->lev[d].ti_geo.
+void build_ti_geo(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s);
 bool supported_order(int ps, int pa);
 int prop_chunk(int P);
 bool cone_prop_supported(const ifgf_plan_s* p);

@@ -750,14 +750,21 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
       std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
         return x[0] < y[0];
       });
+      // FP32: the node records of each (cone id, octant) are computed once
+      // per level; a tile's fourth entry indexes its cone id's records
+      std::vector<int> qlist;
+      for (const auto& t : tl) qlist.push_back(t[1]);
+      std::sort(qlist.begin(), qlist.end());
+      qlist.erase(std::unique(qlist.begin(), qlist.end()), qlist.end());
       std::vector<int> tiles;
       tiles.reserve(tl.size() * 4);
       for (const auto& t : tl) {
         tiles.push_back(t[1]);
         tiles.push_back(t[2]);
         tiles.push_back(t[3]);
-        tiles.push_back(0);
+        tiles.push_back(f32 ? (int)(std::lower_bound(qlist.begin(), qlist.end(), t[1]) - qlist.begin()) : 0);
       }
+      if (f32) build_ti_geo(p, d, qlist, s);
       // each tile box's child per octant, in ti_slot order, so that a tile
       // reads its boxes' children with one coalesced load
       std::vector<int> tchild(8 * (size_t)lv.nrel, -1);
