@@ -3581,6 +3581,12 @@ void ti_geo_impl(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream
 
 }  // namespace
 
+size_t ti_geo_bytes(int ps, int pa) {
+  if (ps == 3 && pa == 5) return sizeof(TiGeo<3, 5>);
+  if (ps == 4 && pa == 6) return sizeof(TiGeo<4, 6>);
+  return 0;
+}
+
 void build_ti_geo(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s) {
   if (qlist.empty()) return;
   const int ps = p->opt.p_s, pa = p->opt.p_ang;

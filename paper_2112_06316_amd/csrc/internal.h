@@ -164,6 +164,7 @@ void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, 
 // The cone-major tiles' node records of level d (one per cone id in qlist and
 // octant), computed on the GPU into p->lev[d].ti_geo.
 void build_ti_geo(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s);
+size_t ti_geo_bytes(int ps, int pa);   // one (cone id, octant) record
 bool supported_order(int ps, int pa);
 int prop_chunk(int P);
 bool cone_prop_supported(const ifgf_plan_s* p);

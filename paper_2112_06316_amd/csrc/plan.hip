@@ -706,7 +706,16 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
       const double per = (double)lv.nrel / (double)ndistinct;
       int nw = per >= 12.0 ? 4 : (per >= 6.0 ? 2 : 0);
       if (!f32 && nw > 2) nw = 2;   // FP64 tiles: at most 16 boxes (LDS)
-      if (p->opt.prop_kernel == IFGF_PROP_CONE && nw == 0) nw = 1;
+      // FP32 tiles read their node records from a table of 8 records per
+      // cone id (about 42 KB at P = 144); where that would exceed 2.5 times
+      // the level's coefficients (few boxes per cone id), AUTO keeps the node
+      // formulation
+      const bool forced = p->opt.prop_kernel == IFGF_PROP_CONE;
+      if (f32 && !forced &&
+          (double)ndistinct * 8.0 * (double)ti_geo_bytes(p->opt.p_s, p->opt.p_ang) >
+              2.5 * (double)lv.nrel * P * sizeof(cpx<float>))
+        nw = 0;
+      if (forced && nw == 0) nw = 1;
       if (nw == 0) continue;
       const int cap = 8 * nw;
       // child-octant mask of every box of this level, to order the boxes of
