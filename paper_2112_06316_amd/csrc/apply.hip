@@ -3117,18 +3117,19 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
 // counter increment; after a wait every wave issues an agent-scope acquire
 // fence (stale cache lines dropped) before it reads.
 // ---------------------------------------------------------------------------
-enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_COEF = 3, BT_PROP = 4, BT_TARGET = 5, BT_PROPTI = 6 };
+enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_PROP = 4, BT_TARGET = 5, BT_PROPTI = 6 };
 // Threads per work-group of the batch launch: every stage body runs at this
 // size (the cone-major tiles need 4 waves of 8 boxes).
 constexpr int BBS = 256;
 // Work units per queue item (fewer items, fewer counter updates and fences):
-// gather chunks of BS points, leaf and near-field boxes, upward-pass work
-// items, groups of PropShape::CH cones of the coefficient transform; target
-// items hold BBS points; a cone-major item is one tile.
-constexpr int BG_GATHER = 4, BG_BOX = 4, BG_PROP = 8, BG_COEF = 8;
+// gather chunks of BS points, upward-pass work items, the plan's balanced
+// near-field and leaf work items (the leaf items also turn their whole
+// cones' node values into coefficients); target items hold BBS points; a
+// cone-major item is one tile.
+constexpr int BG_GATHER = 4, BG_PROP = 8, BG_NEAR = 16, BG_LEAF = 8;
 
 template <typename T> struct BLevel {
-  int nb, nrel, nwork;
+  int nb, nrel, nwork, n_near, n_leaf;
   const int IFGF_GAS* start;
   const int IFGF_GAS* nbr_off;
   const int IFGF_GAS* nbr;
@@ -3140,6 +3141,8 @@ template <typename T> struct BLevel {
   const int IFGF_GAS* slot;
   const double IFGF_GAS* centre;
   const int4 IFGF_GAS* work;
+  const int4 IFGF_GAS* near_work;   // finest level: near-field work items
+  const int4 IFGF_GAS* leaf_work;   // finest level: leaf work items (whole cones)
   const int4 IFGF_GAS* ti_tile;   // cone-major tiles of the pass into this level (FP32)
   const int IFGF_GAS* ti_slot;
   const int IFGF_GAS* ti_child;
@@ -3186,9 +3189,18 @@ __device__ __forceinline__ void batch_wait(int* ctr, int dep, int need, int spin
   }
 }
 
+// A leaf item with its cones' coefficient transform (one RHS).
+template <typename T, int PS, int PA> struct BLeafSmem {
+  static constexpr int P = PS * PA * PA;
+  static constexpr int NCF = kLeafChunk / P > 0 ? kLeafChunk / P : 1;
+  LeafSmem<T, 1> leaf;
+  cpx<T> fv[NCF * P], ft[NCF * P];
+  T ms[PS * PS], ma[PA * PA];
+};
+
 template <typename T, int PS, int PA> struct BatchSmem {
   static constexpr size_t a = sizeof(PropSmem<T, PS, PA, BBS>), b = sizeof(NearSmem<T, 1, BBS>),
-                          c = sizeof(LeafSmem<T, 1>), t = Prec<T>::f32 ? sizeof(TiSmem<PS, PA, 4>) : 0;
+                          c = sizeof(BLeafSmem<T, PS, PA>), t = Prec<T>::f32 ? sizeof(TiSmem<PS, PA, 4>) : 0;
   static constexpr size_t ab = a > b ? a : b, ct = c > t ? c : t;
   static constexpr size_t bytes = ab > ct ? ab : ct;
 };
@@ -3241,46 +3253,36 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
         gather_one<T>(((int64_t)local * BG_GATHER + u) * BS + threadIdx.x, io.sigma[S.geom], dtype, 0, gen(G.perm),
                       gen(G.w), G.n, 1, gen(G.a));
       break;
-    case BT_NEAR: {
+    case BT_NEAR: {   // near-field work items (box, first target, targets)
       const BLevel<T>& L = G.lv[D];
-      const int b1 = min((local + 1) * BG_BOX, L.nb);
-      for (int bx = local * BG_BOX; bx < b1; ++bx) {
-        if (bx > local * BG_BOX) __syncthreads();   // LDS reuse
-        const int* st = gen(L.start);
-        near_box<T, false, 1, BS>(*reinterpret_cast<NearSmem<T, 1, BS>*>(smem), bx, 0, st[bx + 1] - st[bx], 0,
-                                  gen(G.pts), gen(G.nrm),
-                                  gen(G.a), 1, gen(L.start), gen(L.nbr_off), gen(L.nbr), gen(L.centre), G.k, G.eta,
-                                  G.kind, gen(G.uacc));
+      const int w1 = min((local + 1) * BG_NEAR, L.n_near);
+      for (int w = local * BG_NEAR; w < w1; ++w) {
+        if (w > local * BG_NEAR) __syncthreads();   // LDS reuse
+        const int4 wk = gen(L.near_work)[w];
+        near_box<T, false, 1, BS>(*reinterpret_cast<NearSmem<T, 1, BS>*>(smem), wk.x, wk.y, wk.z, 0, gen(G.pts),
+                                  gen(G.nrm), gen(G.a), 1, gen(L.start), gen(L.nbr_off), gen(L.nbr), gen(L.centre),
+                                  G.k, G.eta, G.kind, gen(G.uacc));
       }
       break;
     }
-    case BT_LEAF: {
+    case BT_LEAF: {   // leaf work items (box, first item, items; whole cones), then their coefficients
+      auto& sm = *reinterpret_cast<BLeafSmem<T, PS, PA>*>(smem);
       const BLevel<T>& L = G.lv[D];
-      const int b1 = min((local + 1) * BG_BOX, L.nb);
-      for (int bx = local * BG_BOX; bx < b1; ++bx) {
-        if (bx > local * BG_BOX) __syncthreads();   // LDS reuse
-        const int* so = gen(L.slot_off);
-        leaf_box<T, PS, PA, 1, BS>(*reinterpret_cast<LeafSmem<T, 1>*>(smem), bx, 0, (so[bx + 1] - so[bx]) * P, 0,
-                                   gen(G.pts), gen(G.nrm),
-                                   gen(G.a), 1, gen(L.start), gen(L.centre), gen(L.slot_off), gen(L.rel_cone), L.g,
-                                   G.ct, G.k, G.eta, G.kind, gen(L.Fn));
-      }
-      break;
-    }
-    case BT_COEF: {
-      // groups of CH cones of the finest level: node values -> coefficients
-      auto& sm = *reinterpret_cast<PropSmem<T, PS, PA, BBS>*>(smem);
-      const BLevel<T>& L = G.lv[D];
-      constexpr int CH = PropShape<P>::CH;
       if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = G.Ms[threadIdx.x];
       if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = G.Ma[threadIdx.x];
-      const int cend = min((local + 1) * BG_COEF * CH, L.nrel);
-      for (int c0 = local * BG_COEF * CH; c0 < cend; c0 += CH) {
-        const int nc = min(CH, cend - c0);
-        __syncthreads();   // ms, ma written; LDS of the previous group free
-        for (int q = threadIdx.x; q < nc * P; q += BS) sm.acc[q] = gen(L.Fn)[(int64_t)c0 * P + q];
+      const int w1 = min((local + 1) * BG_LEAF, L.n_leaf);
+      for (int w = local * BG_LEAF; w < w1; ++w) {
+        if (w > local * BG_LEAF) __syncthreads();   // LDS reuse
+        const int4 wk = gen(L.leaf_work)[w];
+        leaf_box<T, PS, PA, 1, BS>(sm.leaf, wk.x, wk.y, wk.z, 0, gen(G.pts), gen(G.nrm), gen(G.a), 1, gen(L.start),
+                                   gen(L.centre), gen(L.slot_off), gen(L.rel_cone), L.g, G.ct, G.k, G.eta, G.kind,
+                                   gen(L.Fn), sm.fv);
         __syncthreads();
-        lds_coeffs_store<T, PS, PA, BS>(sm.acc, sm.tmp, nc, sm.ms, sm.ma, gen(L.Fc) + (int64_t)c0 * P, 1, 0);
+        const int* so = gen(L.slot_off);
+        const int ncn = so[wk.x + 1] - so[wk.x];
+        const int c0 = wk.y / P, nc = min(ncn * P, wk.y + wk.z) / P - c0;
+        lds_coeffs_store<T, PS, PA, BS>(sm.fv, sm.ft, nc, sm.ms, sm.ma, gen(L.Fc) + ((int64_t)so[wk.x] + c0) * P,
+                                        1, 0);
       }
       break;
     }
@@ -3368,7 +3370,6 @@ template <typename T, int PS, int PA>
 void batch_prepare_impl(ifgf_batch_s* b) {
   constexpr int P = PS * PA * PA;
   constexpr int BS = BBS;
-  constexpr int CH = PropShape<P>::CH;
   const int ng = (int)b->plans.size();
   std::vector<BGeom<T>> geo(ng);
   for (int g = 0; g < ng; ++g) {
@@ -3397,6 +3398,8 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       L.nb = l.nb;
       L.nrel = l.nrel;
       L.nwork = (int)l.nwork;
+      L.n_near = l.n_near;
+      L.n_leaf = l.n_leaf;
       L.start = gas(l.start.as<const int>());
       L.nbr_off = gas(l.nbr_off.as<const int>());
       L.nbr = gas(l.nbr.as<const int>());
@@ -3408,6 +3411,8 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       L.slot = gas(l.slot.as<const int>());
       L.centre = gas(l.centre.as<const double>());
       L.work = gas(l.work.as<const int4>());
+      L.near_work = gas(l.near_work.as<const int4>());
+      L.leaf_work = gas(l.leaf_work.as<const int4>());
       L.ti_tile = gas(l.ti_tile.as<const int4>());
       L.ti_slot = gas(l.ti_slot.as<const int>());
       L.ti_child = gas(l.ti_child.as<const int>());
@@ -3424,7 +3429,7 @@ void batch_prepare_impl(ifgf_batch_s* b) {
 
   // ---- the queue ----------------------------------------------------------------
   auto C = [](int g, int k) { return 1 + 16 * g + k; };   // counters: 0 = queue head, then 16 per geometry
-  enum { K_GATHER = 0, K_LEAF = 1, K_NEAR = 2, K_COEF = 3, K_PROP0 = 4, K_TARGET = 15 };   // K_PROP0 + d: into level d
+  enum { K_GATHER = 0, K_LEAF = 1, K_NEAR = 2, K_PROP0 = 4, K_TARGET = 15 };   // K_PROP0 + d: into level d
   std::vector<BSeg> segs;
   int64_t first = 0;
   auto emit = [&](int type, int g, int level, int64_t count, int dep0, int need0, int dep1, int need1, int done) {
@@ -3450,22 +3455,16 @@ void batch_prepare_impl(ifgf_batch_s* b) {
     ngat[g] = (b->plans[g]->n + (int64_t)BS * BG_GATHER - 1) / ((int64_t)BS * BG_GATHER);
     emit(BT_GATHER, g, 0, ngat[g], -1, 0, -1, 0, C(g, K_GATHER));
   }
-  for (int g = 0; g < ng; ++g) {
+  for (int g = 0; g < ng; ++g) {   // leaf factors with the finest level's coefficients
     ifgf_plan_s* p = b->plans[g];
-    nleaf[g] = p->D >= 3 ? (p->lev[p->D].nb + BG_BOX - 1) / BG_BOX : 0;
+    nleaf[g] = p->D >= 3 ? (p->lev[p->D].n_leaf + BG_LEAF - 1) / BG_LEAF : 0;
     emit(BT_LEAF, g, p->D, nleaf[g], C(g, K_GATHER), (int)ngat[g], -1, 0, C(g, K_LEAF));
+    if (nleaf[g] > 0) last[g] = {C(g, K_LEAF), (int)nleaf[g]};
   }
   for (int g = 0; g < ng; ++g) {
     ifgf_plan_s* p = b->plans[g];
-    nnear[g] = (p->lev[p->D].nb + BG_BOX - 1) / BG_BOX;
+    nnear[g] = (p->lev[p->D].n_near + BG_NEAR - 1) / BG_NEAR;
     emit(BT_NEAR, g, p->D, nnear[g], C(g, K_GATHER), (int)ngat[g], -1, 0, C(g, K_NEAR));
-  }
-  for (int g = 0; g < ng; ++g) {
-    ifgf_plan_s* p = b->plans[g];
-    if (p->D < 3) continue;
-    const int64_t cnt = (p->lev[p->D].nrel + (int64_t)BG_COEF * CH - 1) / ((int64_t)BG_COEF * CH);
-    emit(BT_COEF, g, p->D, cnt, C(g, K_LEAF), (int)nleaf[g], -1, 0, C(g, K_COEF));
-    if (cnt > 0) last[g] = {C(g, K_COEF), (int)cnt};
   }
   // Upward pass in steps j = 0, 1, ...: step j takes level D_g - j -> D_g - j - 1
   // of every geometry g.  A geometry's targets follow its last step, so the
