@@ -1683,26 +1683,27 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
 // Every box of a level has the same size, so the position of parent node
 // (a, b, c) of parent cone id q relative to the centre of the child in
 // octant o - hence its child cone, local coordinates and the ratio
-// K(x, y_B)/K(x, y_P) - depends on (q, o, node) only, not on the box.  A
-// work item is one cone id q and up to 8 NW parent boxes holding it.  For
-// each octant the block computes the P node geometries once and groups the
-// nodes by child cone; then each wave evaluates, for 8 boxes that have a
-// child in octant o (the octant's boxes are packed into the waves' rows),
-// the child interpolants at the nodes of a group as the product
+// K(x, y_B)/K(x, y_P) - depends on (q, o, node) only, not on the box; the
+// plan computes these node records once per (q, o), grouped by child cone
+// (k_ti_geo).  A work item is one cone id q and up to 8 NW parent boxes
+// holding it.  For each octant the block copies q's records into LDS; the
+// boxes that have a child in octant o are packed into row blocks of 8, and
+// the (row block, column tile) units are split evenly over the waves.  A
+// unit evaluates the child interpolants of 8 boxes at 16 nodes of a group
+// as the product
 //     OUT[row][e] = sum_k C[row][k] B[k][e],
 // rows = 8 boxes x (re, im) of the child cone's coefficients, columns = 16
 // nodes of the group, B[k][e] = T_a(ts_e) T_b(tt_e) T_c(tp_e), on
 // v_mfma_f32_16x16x4_f32 with the basis index ordered (b, c, a) so that a
-// fills the 4-wide K step.  The wave adds ratio * OUT to its boxes' node
+// fills the 4-wide K step.  The wave adds ratio * OUT to the boxes' node
 // values in LDS (each (box, node) has one writer per octant, octants in
 // order: deterministic).  After the 8 octants the node values are turned
 // into coefficients in place and written to the parent level.
 //
-// Latency hiding: the geometry of the next octant with children is computed
-// and grouped before the current octant's MFMA phase (two geometry buffers),
-// so that a wave's A-operand pipeline runs on from the last group of one
-// octant into the first group of the next; node records are stored in group
-// order, so a column tile reads its nodes with one LDS access each.
+// Latency hiding: the records of the next octant with children are in LDS
+// before the current octant's MFMA phase (two buffers), so that a wave's
+// A-operand pipeline runs on from its last segment in one octant into its
+// first in the next.
 // ---------------------------------------------------------------------------
 // A run of a wave's work units with the same row block and group: octant
 // k (0: current, 1: next; SEG_NONE / SEG_UNKNOWN: none, or not known yet),
