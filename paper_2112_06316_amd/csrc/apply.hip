@@ -2193,7 +2193,6 @@ template <int PS, int PA, int NW> struct Ti64Smem {
   signed char olist[8][NB];
   int ocnt[8];
   int pslot[NB];
-  int anychild;
   double ms[PS * PS], ma[PA * PA];
 };
 
@@ -2206,8 +2205,7 @@ __device__ __forceinline__ double swap_lane_pair(double v) {
 
 template <int PS, int PA, int NW>
 __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl, const int* __restrict__ ti_slot,
-                                               const int* __restrict__ rel_box_up,
-                                               const int* __restrict__ child_lo_up, const int* __restrict__ coords,
+                                               const int* __restrict__ ti_child,
                                                const int* __restrict__ slot_c, const cpx<double>* __restrict__ Fc_c,
                                                const LevelGeom& gp, const LevelGeom& gc, const ChebTab& ct,
                                                const double* __restrict__ Ms, const double* __restrict__ Ma,
@@ -2223,32 +2221,25 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
   // ---- set-up: boxes, their children by octant ----------------------------------
   if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = Ms[threadIdx.x];
   if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
-  if (threadIdx.x == 0) sm.anychild = 0;
-  for (int t = threadIdx.x; t < NB * 8; t += BS) sm.child[t >> 3][t & 7] = -1;
+  for (int t = threadIdx.x; t < NB * 8; t += BS)   // each box's children by octant, from the plan
+    sm.child[t >> 3][t & 7] = (t >> 3) < nb ? ti_child[(int64_t)(tl.y + (t >> 3)) * 8 + (t & 7)] : -1;
+  if (threadIdx.x < nb) sm.pslot[threadIdx.x] = ti_slot[tl.y + threadIdx.x];
   for (int t = threadIdx.x; t < NB * S::ACC_LD; t += BS) sm.acc[t / S::ACC_LD][t % S::ACC_LD] = {0.0, 0.0};
   __syncthreads();
-  if (threadIdx.x < nb) {
-    const int sl = ti_slot[tl.y + threadIdx.x];
-    const int Pb = rel_box_up[sl];
-    sm.pslot[threadIdx.x] = sl;
-    int mask = 0;
-    for (int B = child_lo_up[Pb]; B < child_lo_up[Pb + 1]; ++B) {
-      const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
-      sm.child[threadIdx.x][oct] = B;
-      mask |= 1 << oct;
+  // per octant, the boxes that have a child in it: every wave forms the
+  // octant mask, wave 0 writes the lists (read after the next barrier)
+  static_assert(NB <= 64, "one lane per box");
+  int anychild = 0;
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    const bool has = lane < nb && sm.child[lane < nb ? lane : 0][o] >= 0;
+    const uint64_t b = __ballot(has);
+    anychild |= b ? 1 << o : 0;
+    if (wv == 0) {
+      if (has) sm.olist[o][__popcll(b & ((1ull << lane) - 1))] = (signed char)lane;
+      if (lane == 0) sm.ocnt[o] = __popcll(b);
     }
-    atomicOr(&sm.anychild, mask);
   }
-  __syncthreads();
-  if (threadIdx.x < 8) {
-    const int o = threadIdx.x;
-    int c = 0;
-    for (int t = 0; t < nb; ++t)
-      if (sm.child[t][o] >= 0) sm.olist[o][c++] = (signed char)t;
-    sm.ocnt[o] = c;
-  }
-  __syncthreads();
-  const int anychild = sm.anychild;
   const int li = lane & 15;       // A row (box, re/im) and B / OUT column
   const int la = lane >> 4;       // index within the 4-wide K step: the radial index a
   const int reim = li & 1;
@@ -2491,13 +2482,13 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
 
 template <int PS, int PA, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_prop_ti64(
-    const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ rel_box_up,
-    const int* __restrict__ child_lo_up, const int* __restrict__ coords, const int* __restrict__ slot_c,
-    const cpx<double>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct, const double* __restrict__ Ms,
-    const double* __restrict__ Ma, double k, int kind, cpx<double>* __restrict__ Fc_up, int* __restrict__ err) {
+    const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ ti_child,
+    const int* __restrict__ slot_c, const cpx<double>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct,
+    const double* __restrict__ Ms, const double* __restrict__ Ma, double k, int kind, cpx<double>* __restrict__ Fc_up,
+    int* __restrict__ err) {
   __shared__ Ti64Smem<PS, PA, NW> sm;
-  prop_ti64_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, rel_box_up, child_lo_up, coords,
-                             slot_c, Fc_c, gp, gc, ct, Ms, Ma, k, kind, Fc_up, err);
+  prop_ti64_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, ti_child, slot_c, Fc_c, gp, gc, ct,
+                             Ms, Ma, k, kind, Fc_up, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -2946,9 +2937,9 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
           auto launch = [&](auto kern, int nw) {
             kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
-                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.rel_box.as<int>(), lp.child_lo.as<int>(),
-                lc.coords.as<int>(), lc.slot.as<int>(), lc.Fc.as<cpx<double>>(), lp.geom, lc.geom, p->cheb,
-                (const double*)Ms, (const double*)Ma, p->k, kind, lp.Fc.as<cpx<double>>(), p->err.as<int>());
+                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lc.slot.as<int>(),
+                lc.Fc.as<cpx<double>>(), lp.geom, lc.geom, p->cheb, (const double*)Ms, (const double*)Ma, p->k, kind,
+                lp.Fc.as<cpx<double>>(), p->err.as<int>());
           };
           if (lp.ti_nw == 2) launch(k_prop_ti64<PS, PA, 2>, 2);
           else launch(k_prop_ti64<PS, PA, 1>, 1);
