@@ -734,11 +734,7 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
       // sorted by child mask (stable: Morton order within a mask), then cut
       // into tiles, so that the boxes of a tile - and the 8 rows of a wave -
       // mostly have children in the same octants (MFMA rows of a box without
-      // a child in the current octant are wasted, and a wave whose boxes have
-      // none waits at the octant's barriers).  The tiles are then ordered by
-      // their first box, so that tiles of different cone ids over the same
-      // boxes - which read the same child cones - run back to back (and, with
-      // the XCD-aware block mapping, on one XCD).
+      // a child in the current octant are wasted).
       std::vector<int> slots(lv.nrel);
       std::vector<std::array<int, 5>> tl;   // (first box, cid, start, count, 0)
       for (int64_t i = 0; i < lv.nrel; ++i) slots[i] = (int)(keys[i] & 0xffffffffu);
@@ -756,9 +752,16 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
         }
         i = j;
       }
-      std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
-        return x[0] < y[0];
-      });
+      // Order the tiles by first box, so that tiles of different cone ids
+      // over the same boxes - which read the same child cones - run back to
+      // back (and, with the XCD-aware block mapping, on one XCD); except, in
+      // FP32, where a cone id has several tiles (4 or more on average): those
+      // stay together, so that its node records (8 x 5.2 KB at P = 144) stay
+      // in L2 from one tile to the next.
+      if (!f32 || (int64_t)tl.size() < 4 * ndistinct)
+        std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
+          return x[0] < y[0];
+        });
       // FP32: the node records of each (cone id, octant) are computed once
       // per level; a tile's fourth entry indexes its cone id's records
       std::vector<int> qlist;
