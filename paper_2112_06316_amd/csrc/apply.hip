@@ -820,10 +820,10 @@ template <typename T, int PS, int PA, int BS_ = PropShape<PS * PA * PA>::BS> str
   int wsum[BS / 64];
   T ms[PS * PS], ma[PA * PA];
   __align__(16) T cbuf[BS / 64][2 * P];
-  // FP32: per cone of the item, (sin, cos) of its PA polar and PA azimuthal
-  // node angles, and its PS node radii h / s
-  float ang[PropShape<P>::CH][2 * PA][2];
-  float rad[PropShape<P>::CH][PS];
+  // per cone of the item, (sin, cos) of its PA polar and PA azimuthal node
+  // angles, and its PS node radii h / s
+  T ang[PropShape<P>::CH][2 * PA][2];
+  T rad[PropShape<P>::CH][PS];
 };
 
 // One work item wk = (parent box, first slot, end slot) of the upward pass,
@@ -859,18 +859,25 @@ __device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_>& sm, int4 wk,
   const int nn = ncn * P;
   if (threadIdx.x < PS * PS) ms[threadIdx.x] = Ms[threadIdx.x];
   if (threadIdx.x < PA * PA) ma[threadIdx.x] = Ma[threadIdx.x];
-  if constexpr (Prec<T>::f32) {   // node angles and radii of the item's cones (the terms of node_rel32)
-    for (int t = threadIdx.x; t < ncn * (2 * PA + PS); t += BS) {
-      const int c = t / (2 * PA + PS), j = t % (2 * PA + PS);
-      int is, it, ip;
-      cone_split(rel_cone_up[s0 + c], gp.nc, &is, &it, &ip);
-      if (j < PA) {
+  // node angles and radii of the item's cones (the terms of node_rel32 / node_rel64)
+  for (int t = threadIdx.x; t < ncn * (2 * PA + PS); t += BS) {
+    const int c = t / (2 * PA + PS), j = t % (2 * PA + PS);
+    int is, it, ip;
+    cone_split(rel_cone_up[s0 + c], gp.nc, &is, &it, &ip);
+    if constexpr (Prec<T>::f32) {
+      if (j < PA)
         sincos_f(((float)it + ct.uaf[j]) * gp.daf, &sm.ang[c][j][0], &sm.ang[c][j][1]);
-      } else if (j < 2 * PA) {
+      else if (j < 2 * PA)
         sincos_f(((float)ip + ct.uaf[j - PA]) * gp.daf, &sm.ang[c][j][0], &sm.ang[c][j][1]);
-      } else {
+      else
         sm.rad[c][j - 2 * PA] = gp.hf * rcp_f(((float)is + ct.usf[j - 2 * PA]) * gp.dsf);
-      }
+    } else {
+      if (j < PA)
+        sincos(((double)it + ct.ua[j]) * gp.da, &sm.ang[c][j][0], &sm.ang[c][j][1]);
+      else if (j < 2 * PA)
+        sincos(((double)ip + ct.ua[j - PA]) * gp.da, &sm.ang[c][j][0], &sm.ang[c][j][1]);
+      else
+        sm.rad[c][j - 2 * PA] = gp.h / (((double)is + ct.us[j - 2 * PA]) * gp.ds);
     }
   }
   for (int q = threadIdx.x; q < nn; q += BS) acc[q] = {0, 0};
@@ -889,20 +896,19 @@ __device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_>& sm, int4 wk,
       const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
       T x[3], rp;
       typename PropGeomT<T>::P pr;
-      if constexpr (Prec<T>::f32) {   // node_rel32 from the tabulated terms
-        const float st = sm.ang[c][bi][0], ctt = sm.ang[c][bi][1];
-        const float sp = sm.ang[c][PA + ci][0], cp = sm.ang[c][PA + ci][1];
-        const float e0 = st * cp, e1 = st * sp;
+      {   // the node relative to the parent centre (node_rel32 / node_rel64) from the tabulated terms
+        const T st = sm.ang[c][bi][0], ctt = sm.ang[c][bi][1];
+        const T sp = sm.ang[c][PA + ci][0], cp = sm.ang[c][PA + ci][1];
+        const T e0 = st * cp, e1 = st * sp;
         rp = sm.rad[c][ai];
         x[0] = rp * e0;
         x[1] = rp * e1;
         x[2] = rp * ctt;
-        pr = child_loc32(x, rp, oct, gc);
-      } else {
-        const int pcid = rel_cone_up[s0 + c];
-        node_rel64(pcid, ai, bi, ci, gp, ct, x, &rp);
-        pr = child_loc64(x, rp, oct, gc);
       }
+      if constexpr (Prec<T>::f32)
+        pr = child_loc32(x, rp, oct, gc);
+      else
+        pr = child_loc64(x, rp, oct, gc);
       const int sl = slot_c[(int64_t)B * gc.ncone + pr.loc.cid];
       if (sl < 0) atomicOr(err, 2);
       st[q][0] = pr.loc.ts;
