@@ -2224,6 +2224,8 @@ template <int PS, int PA, int NW> struct Ti64Smem {
   int ocnt[8];
   int pslot[NB];
   double ms[PS * PS], ma[PA * PA];
+  double ang[2 * PA][2];   // (sin, cos) of the tile cone id's PA polar and PA azimuthal node angles
+  double rad[PS];          // and its node radii h / s
 };
 
 __device__ __forceinline__ double swap_lane_pair(double v) {
@@ -2253,6 +2255,17 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
   if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
   for (int t = threadIdx.x; t < NB * 8; t += BS)   // each box's children by octant, from the plan
     sm.child[t >> 3][t & 7] = (t >> 3) < nb ? ti_child[(int64_t)(tl.y + (t >> 3)) * 8 + (t & 7)] : -1;
+  if (threadIdx.x < 2 * PA + PS) {   // the terms of node_rel64 for cone id q
+    const int j = threadIdx.x;
+    int is, it, ip;
+    cone_split(q, gp.nc, &is, &it, &ip);
+    if (j < PA)
+      sincos(((double)it + ct.ua[j]) * gp.da, &sm.ang[j][0], &sm.ang[j][1]);
+    else if (j < 2 * PA)
+      sincos(((double)ip + ct.ua[j - PA]) * gp.da, &sm.ang[j][0], &sm.ang[j][1]);
+    else
+      sm.rad[j - 2 * PA] = gp.h / (((double)is + ct.us[j - 2 * PA]) * gp.ds);
+  }
   if (threadIdx.x < nb) sm.pslot[threadIdx.x] = ti_slot[tl.y + threadIdx.x];
   for (int t = threadIdx.x; t < NB * S::ACC_LD; t += BS) sm.acc[t / S::ACC_LD][t % S::ACC_LD] = {0.0, 0.0};
   __syncthreads();
@@ -2279,7 +2292,15 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
     // ---- node geometry in the child frame of octant o ------------------------
     for (int n = threadIdx.x; n < P; n += BS) {
       double x[3], rp;
-      node_rel64(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
+      {   // node_rel64 from the tabulated terms
+        const int bi = (n / PA) % PA, ci = n % PA;
+        const double st = sm.ang[bi][0], ctt = sm.ang[bi][1], sp = sm.ang[PA + ci][0], cp = sm.ang[PA + ci][1];
+        const double e0 = st * cp, e1 = st * sp;
+        rp = sm.rad[n / (PA * PA)];
+        x[0] = rp * e0;
+        x[1] = rp * e1;
+        x[2] = rp * ctt;
+      }
       const Prop64 pr = child_loc64(x, rp, o, gc);
       sm.cid[n] = pr.loc.cid;
       sm.crd[n][0] = pr.loc.ts;
