@@ -1499,6 +1499,8 @@ template <int PS, int PA> struct BcSmem {
   int gstart[P + 1], gcid[P];
   int ngroup;
   float ms[PS * PS], ma[PA * PA];
+  float ang[2 * PA][2];   // (sin, cos) of the parent cone's PA polar and PA azimuthal node angles
+  float rad[PS];          // and its node radii h / s
 };
 
 template <int PS, int PA>
@@ -1522,13 +1524,32 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
   for (int t = threadIdx.x; t < P * (MF_RG + 1); t += TPB) sm.acc[t / (MF_RG + 1)][t % (MF_RG + 1)] = {0.f, 0.f};
   if (threadIdx.x < PS * PS) sm.ms[threadIdx.x] = Ms[threadIdx.x];
   if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
+  if (threadIdx.x < 2 * PA + PS) {   // the terms of node_rel32 for cone id q
+    const int j = threadIdx.x;
+    int is, it, ip;
+    cone_split(q, gp.nc, &is, &it, &ip);
+    if (j < PA)
+      sincos_f(((float)it + ct.uaf[j]) * gp.daf, &sm.ang[j][0], &sm.ang[j][1]);
+    else if (j < 2 * PA)
+      sincos_f(((float)ip + ct.uaf[j - PA]) * gp.daf, &sm.ang[j][0], &sm.ang[j][1]);
+    else
+      sm.rad[j - 2 * PA] = gp.hf * rcp_f(((float)is + ct.usf[j - 2 * PA]) * gp.dsf);
+  }
   const int B0 = child_lo_up[Pb], B1 = child_lo_up[Pb + 1];
   for (int B = B0; B < B1; ++B) {
     const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
-    __syncthreads();   // previous child's groups and geometry no longer read
+    __syncthreads();   // previous child's groups and geometry no longer read; the node terms written
     for (int n = threadIdx.x; n < P; n += TPB) {
       float x[3], rp;
-      node_rel32(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
+      {   // node_rel32 from the tabulated terms
+        const int bi = (n / PA) % PA, ci = n % PA;
+        const float st = sm.ang[bi][0], ctt = sm.ang[bi][1], sp_ = sm.ang[PA + ci][0], cp = sm.ang[PA + ci][1];
+        const float e0 = st * cp, e1 = st * sp_;
+        rp = sm.rad[n / (PA * PA)];
+        x[0] = rp * e0;
+        x[1] = rp * e1;
+        x[2] = rp * ctt;
+      }
       const PropF pr = child_loc32(x, rp, oct, gc);
       sm.cid[n] = pr.loc.cid;
       cheb_T<float, PS>(pr.loc.ts, &sm.bas[n][0]);
