@@ -2239,6 +2239,8 @@ template <int PS, int PA, int NW> struct Ti64Smem {
   int cid[P];
   short order[P];
   int gstart[P + 1], gcid[P];
+  short tstart[P + 1];          // group g: column tiles tstart[g] .. tstart[g+1]-1
+  short tgrp[P + P / 16 + 1];   // group of each column tile
   int ngroup;
   int child[NB][8];
   signed char olist[8][NB];
@@ -2347,7 +2349,7 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
         pend[m] = n < P;
         cv[m] = pend[m] ? sm.cid[n] : 0;
       }
-      int pos = 0, g = 0;
+      int pos = 0, g = 0, tpos = 0;
       while (true) {
         int lead = -1, su = 0;
 #pragma unroll
@@ -2361,8 +2363,10 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
         if (lead < 0) break;
         if (lane == 0) {
           sm.gstart[g] = pos;
+          sm.tstart[g] = (short)tpos;
           sm.gcid[g] = su;
         }
+        const int pos0 = pos;
 #pragma unroll
         for (int m = 0; m < NPL; ++m) {
           const bool hit = pend[m] && cv[m] == su;
@@ -2371,22 +2375,42 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
           pos += __popcll(b);
           pend[m] = pend[m] && !hit;
         }
+        const int nt = (pos - pos0 + 15) >> 4;   // at most ceil(P / 16) <= 64 column tiles
+        if (lane < nt) sm.tgrp[tpos + lane] = (short)g;
+        tpos += nt;
         ++g;
       }
       if (lane == 0) {
         sm.gstart[g] = pos;
+        sm.tstart[g] = (short)tpos;
         sm.ngroup = g;
       }
     }
     __syncthreads();
-    // ---- child interpolants on MFMA, group by group -----------------------------------
+    // ---- child interpolants on MFMA ------------------------------------------------
+    // Work units (row block r: 8 boxes of the octant's list, column tile t of
+    // the groups), r-major, split evenly over the waves; a run of units with
+    // the same (r, group) is a segment with one A operand, loaded one segment
+    // ahead.  Units are disjoint in (box, node).
     const int ng = sm.ngroup;
     const int no = sm.ocnt[o];
-    const int le = wv * 8 + (li >> 1);
-    const int Bc = le < no ? sm.child[sm.olist[o][le]][o] : -1;
-    const bool wave_has = 8 * wv < no;
-    auto slot_of = [&](int g) -> int {
-      return (g < ng && Bc >= 0) ? slot_c[(int64_t)Bc * gc.ncone + sm.gcid[g]] : -1;
+    const int T = sm.tstart[ng];
+    const int U = ((no + 7) >> 3) * T;
+    const int u0 = wv * U / NW, u1 = (wv + 1) * U / NW;
+    struct Seg64 {
+      int r, g, ue;   // r < 0: none
+    };
+    auto seg_at = [&](int u) -> Seg64 {
+      if (u >= u1) return Seg64{-1, 0, u1};
+      const int r = u / T, g = sm.tgrp[u - r * T];
+      return Seg64{r, g, min(u1, r * T + sm.tstart[g + 1])};
+    };
+    auto child_of = [&](const Seg64& sg) -> int {   // the child box of this lane's A row
+      const int le = sg.r * 8 + (li >> 1);
+      return (sg.r >= 0 && le < no) ? sm.child[sm.olist[o][le]][o] : -1;
+    };
+    auto slot_of = [&](const Seg64& sg, int Bc) -> int {
+      return Bc >= 0 ? slot_c[(int64_t)Bc * gc.ncone + sm.gcid[sg.g]] : -1;
     };
     constexpr bool PAIR = (PA * PA) % 2 == 0;
     constexpr int NRAW = PAIR ? PA * PA / 2 : PA * PA;
@@ -2414,51 +2438,59 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
         }
       }
     };
+    // The f64 MFMA spreads a lane's four outputs over the rows: element v of
+    // lane 16 r + j is row 4 v + r, i.e. box 2 v + (r >> 1), part r & 1, of
+    // column j.  Lanes r and r ^ 1 (16 apart) exchange their values, and
+    // each lane then adds two boxes: r even elements 0, 1 (boxes r >> 1,
+    // 2 + (r >> 1)), r odd elements 2, 3 (boxes 4 + (r >> 1), 6 + (r >> 1)).
+    // A tile's accumulation is deferred to the next tile's iteration; unused
+    // entries go to row NB (the b entry to column P there).
+    const bool odd = la & 1;
+    doublex4 dq = {0.0, 0.0, 0.0, 0.0};
+    int qn = 0, qa = NB, qb = NB;
+    auto xchg = [](double v) {
+      const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+      const int lo = __shfl_xor((int)(unsigned)b, 16, 64), hi = __shfl_xor((int)(unsigned)(b >> 32), 16, 64);
+      return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
+    };
+    auto flush = [&]() {
+      const double o0 = xchg(dq[0]), o1 = xchg(dq[1]), o2 = xchg(dq[2]), o3 = xchg(dq[3]);
+      const double m0 = odd ? dq[2] : dq[0], m1 = odd ? dq[3] : dq[1];
+      const double t0 = odd ? o2 : o0, t1 = odd ? o3 : o1;
+      const double re0 = odd ? t0 : m0, im0 = odd ? m0 : t0, re1 = odd ? t1 : m1, im1 = odd ? m1 : t1;
+      const double er = sm.rat[qn][0], ei = sm.rat[qn][1];
+      cpx<double>& ua = sm.acc[qa][qn];
+      cpx<double>& ub = sm.acc[qb][qb == NB ? P : qn];
+      cpx<double> va = ua, vb = ub;
+      va.re += er * re0 - ei * im0;
+      va.im += er * im0 + ei * re0;
+      vb.re += er * re1 - ei * im1;
+      vb.im += er * im1 + ei * re1;
+      ua = va;
+      ub = vb;
+    };
     double av[PA * PA];
     double2 rn[NRAW];
-    int s_cur = -1, s_nxt = -1;
-    if (wave_has) {
-      s_cur = slot_of(0);
-      s_nxt = slot_of(1);
+    Seg64 cur = seg_at(u0);
+    Seg64 nxt = seg_at(cur.ue);
+    int b_cur = child_of(cur), b_nxt = child_of(nxt);
+    int s_cur = slot_of(cur, b_cur), s_nxt = slot_of(nxt, b_nxt);
+    if (u0 < u1) {
       load_raw(s_cur, rn);
       unpack(rn, av);
     }
-    for (int g = 0; g < (wave_has ? ng : 0); ++g) {
-      const int n0 = sm.gstart[g], n1 = sm.gstart[g + 1];
-      const int s_nn = slot_of(g + 2);
+    for (int u = u0; u < u1;) {   // wave-uniform
+      const Seg64 nn = seg_at(nxt.ue);
+      const int b_nn = child_of(nn);
+      const int s_nn = slot_of(nn, b_nn);
       load_raw(s_nxt, rn);
-      if (Bc >= 0 && s_cur < 0) atomicOr(err, 2);
-      // The f64 MFMA spreads a lane's four outputs over the rows: element v of
-      // lane 16 r + j is row 4 v + r, i.e. box 2 v + (r >> 1), part r & 1, of
-      // column j.  Lanes r and r ^ 1 (16 apart) exchange their values, and
-      // each lane then adds two boxes: r even elements 0, 1 (boxes r >> 1,
-      // 2 + (r >> 1)), r odd elements 2, 3 (boxes 4 + (r >> 1), 6 + (r >> 1)).
-      // A tile's accumulation is deferred to the next tile's iteration.
-      const bool odd = la & 1;
-      const int e2a = wv * 8 + (odd ? 4 : 0) + (la >> 1), e2b = e2a + 2;
+      if (b_cur >= 0 && s_cur < 0) atomicOr(err, 2);
+      const int g = cur.g, t0 = cur.r * T + sm.tstart[g];
+      const int n0 = sm.gstart[g], n1 = sm.gstart[g + 1];
+      const int e2a = cur.r * 8 + (odd ? 4 : 0) + (la >> 1), e2b = e2a + 2;
       const int bxa = e2a < no ? (int)sm.olist[o][e2a] : NB, bxb = e2b < no ? (int)sm.olist[o][e2b] : NB;
-      doublex4 dq = {0.0, 0.0, 0.0, 0.0};
-      int qn = 0, qa = NB, qb = NB;
-      auto xchg = [](double v) {
-        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-        const int lo = __shfl_xor((int)(unsigned)b, 16, 64), hi = __shfl_xor((int)(unsigned)(b >> 32), 16, 64);
-        return __builtin_bit_cast(double, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
-      };
-      auto flush = [&]() {
-        const double o0 = xchg(dq[0]), o1 = xchg(dq[1]), o2 = xchg(dq[2]), o3 = xchg(dq[3]);
-        const double m0 = odd ? dq[2] : dq[0], m1 = odd ? dq[3] : dq[1];
-        const double t0 = odd ? o2 : o0, t1 = odd ? o3 : o1;
-        const double re0 = odd ? t0 : m0, im0 = odd ? m0 : t0, re1 = odd ? t1 : m1, im1 = odd ? m1 : t1;
-        const double er = sm.rat[qn][0], ei = sm.rat[qn][1];
-        cpx<double>& ua = sm.acc[qa][qn];
-        cpx<double>& ub = sm.acc[qb][qn];
-        ua.re += er * re0 - ei * im0;
-        ua.im += er * im0 + ei * re0;
-        ub.re += er * re1 - ei * im1;
-        ub.im += er * im1 + ei * re1;
-      };
-      for (int c0 = n0; c0 < n1; c0 += 16) {
-        const int e = c0 + li;
+      for (; u < cur.ue; ++u) {
+        const int e = n0 + 16 * (u - t0) + li;
         const bool ok = e < n1;
         const int n = sm.order[ok ? e : n0];
         double Ts[PS], Tt[PA], Tp[PA];
@@ -2483,11 +2515,15 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
         qa = ok ? bxa : NB;
         qb = ok ? bxb : NB;
       }
-      if (n1 > n0) flush();
       unpack(rn, av);
+      cur = nxt;
+      nxt = nn;
       s_cur = s_nxt;
       s_nxt = s_nn;
+      b_cur = b_nxt;
+      b_nxt = b_nn;
     }
+    flush();
     __syncthreads();
   }
 
