@@ -2229,26 +2229,124 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(3))) vo
 // ---------------------------------------------------------------------------
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
+// FP64 node records of one (cone id, octant), in group order (as TiGeo).
+template <int PS, int PA> struct alignas(16) TiGeo64 {
+  static constexpr int P = PS * PA * PA;
+  double crd[P][3];            // (ts, tt, tp): local coordinates in the node's child cone
+  double rat[P][2];            // ratio K(x, y_B) / K(x, y_P)
+  short node[P];               // node index
+  short gstart[P + 1];         // group g: entries gstart[g] .. gstart[g+1]-1
+  short tstart[P + 1];         // group g: column tiles tstart[g] .. tstart[g+1]-1
+  short tgrp[P + P / 16 + 1];  // group of each column tile
+  int gcid[P];                 // child cone id of group g
+  int ngroup;
+};
+
+// One TiGeo64 record per work-group: (cone id qlist[b / 8], octant b % 8), node
+// n on thread n (the scheme of k_ti_geo in FP64).
+template <int PS, int PA>
+__global__ __launch_bounds__(256) void k_ti_geo64(const int* __restrict__ qlist, LevelGeom gp, LevelGeom gc,
+                                                  ChebTab ct, double k, int kind, TiGeo64<PS, PA>* __restrict__ out) {
+  using Geo = TiGeo64<PS, PA>;
+  constexpr int P = Geo::P;
+  static_assert(P <= 256, "one node per thread");
+  __shared__ Geo G;
+  __shared__ int cid[P];
+  __shared__ short rank[P];
+  const int q = qlist[blockIdx.x >> 3], o = blockIdx.x & 7;
+  const int n = threadIdx.x, lane = n & 63, wv = n >> 6;
+  double ts = 0, tt = 0, tp = 0, r0 = 0, r1 = 0;
+  if (n < P) {
+    double x[3], rp;   // node relative to the parent centre
+    node_rel64(q, n / (PA * PA), (n / PA) % PA, n % PA, gp, ct, x, &rp);
+    const Prop64 pr = child_loc64(x, rp, o, gc);
+    cid[n] = pr.loc.cid;
+    ts = pr.loc.ts;
+    tt = pr.loc.tt;
+    tp = pr.loc.tp;
+    double c_ = 1.0, s_ = 0.0, rr = 1.0;
+    if (kind != IFGF_KERNEL_CONSTANT) {
+      sincos(k * pr.dr, &s_, &c_);
+      rr = pr.rp_over_rc;
+    }
+    r0 = rr * c_;
+    r1 = rr * s_;
+  }
+  __syncthreads();
+  if (wv == 0) {   // groups in order of first appearance; ranks within them
+    constexpr int NPL = (P + 63) / 64;
+    int cv[NPL];
+    bool pend[NPL];
+#pragma unroll
+    for (int m = 0; m < NPL; ++m) {
+      const int nn = lane + 64 * m;
+      pend[m] = nn < P;
+      cv[m] = pend[m] ? cid[nn] : 0;
+    }
+    int pos = 0, g = 0, tpos = 0;
+    while (true) {
+      int lead = -1, su = 0;
+#pragma unroll
+      for (int m = 0; m < NPL && lead < 0; ++m) {
+        const uint64_t b = __ballot(pend[m]);
+        if (b) {
+          lead = first_lane(b);
+          su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
+        }
+      }
+      if (lead < 0) break;
+      if (lane == 0) {
+        G.gstart[g] = (short)pos;
+        G.tstart[g] = (short)tpos;
+        G.gcid[g] = su;
+      }
+      const int pos0 = pos;
+#pragma unroll
+      for (int m = 0; m < NPL; ++m) {
+        const bool hit = pend[m] && cv[m] == su;
+        const uint64_t b = __ballot(hit);
+        if (hit) rank[lane + 64 * m] = (short)(pos + __popcll(b & ((1ull << lane) - 1)));
+        pos += __popcll(b);
+        pend[m] = pend[m] && !hit;
+      }
+      const int nt = (pos - pos0 + 15) >> 4;
+      if (lane < nt) G.tgrp[tpos + lane] = (short)g;
+      tpos += nt;
+      ++g;
+    }
+    if (lane == 0) {
+      G.gstart[g] = (short)pos;
+      G.tstart[g] = (short)tpos;
+      G.ngroup = g;
+    }
+  }
+  __syncthreads();
+  if (n < P) {
+    const int r = rank[n];
+    G.crd[r][0] = ts;
+    G.crd[r][1] = tt;
+    G.crd[r][2] = tp;
+    G.rat[r][0] = r0;
+    G.rat[r][1] = r1;
+    G.node[r] = (short)n;
+  }
+  __syncthreads();
+  const uint4* src = reinterpret_cast<const uint4*>(&G);
+  uint4* dst = reinterpret_cast<uint4*>(out + blockIdx.x);
+  for (int i = threadIdx.x; i < (int)(sizeof(Geo) / 16); i += 256) dst[i] = src[i];
+}
+
 template <int PS, int PA, int NW> struct Ti64Smem {
   static constexpr int P = PS * PA * PA;
   static constexpr int NB = 8 * NW;
   static constexpr int ACC_LD = P + 1;
   cpx<double> acc[NB + 1][ACC_LD];  // node values of the tile's boxes; row NB takes unused updates
-  double crd[P][3];                 // per node, current octant: ts, tt, tp
-  double rat[P][2];                 // ratio K(x, y_B) / K(x, y_P)
-  int cid[P];
-  short order[P];
-  int gstart[P + 1], gcid[P];
-  short tstart[P + 1];          // group g: column tiles tstart[g] .. tstart[g+1]-1
-  short tgrp[P + P / 16 + 1];   // group of each column tile
-  int ngroup;
+  TiGeo64<PS, PA> geo;              // the current octant's node records
   int child[NB][8];
   signed char olist[8][NB];
   int ocnt[8];
   int pslot[NB];
   double ms[PS * PS], ma[PA * PA];
-  double ang[2 * PA][2];   // (sin, cos) of the tile cone id's PA polar and PA azimuthal node angles
-  double rad[PS];          // and its node radii h / s
 };
 
 __device__ __forceinline__ double swap_lane_pair(double v) {
@@ -2261,6 +2359,7 @@ __device__ __forceinline__ double swap_lane_pair(double v) {
 template <int PS, int PA, int NW>
 __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl, const int* __restrict__ ti_slot,
                                                const int* __restrict__ ti_child,
+                                               const TiGeo64<PS, PA>* __restrict__ ti_geo,
                                                const int* __restrict__ slot_c, const cpx<double>* __restrict__ Fc_c,
                                                const LevelGeom& gp, const LevelGeom& gc, const ChebTab& ct,
                                                const double* __restrict__ Ms, const double* __restrict__ Ma,
@@ -2270,7 +2369,7 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
   constexpr int P = S::P;
   constexpr int NB = S::NB;
   constexpr int BS = 64 * NW;
-  const int q = tl.x, nb = tl.z;
+  const int nb = tl.z;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
   // ---- set-up: boxes, their children by octant ----------------------------------
@@ -2278,17 +2377,6 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
   if (threadIdx.x < PA * PA) sm.ma[threadIdx.x] = Ma[threadIdx.x];
   for (int t = threadIdx.x; t < NB * 8; t += BS)   // each box's children by octant, from the plan
     sm.child[t >> 3][t & 7] = (t >> 3) < nb ? ti_child[(int64_t)(tl.y + (t >> 3)) * 8 + (t & 7)] : -1;
-  if (threadIdx.x < 2 * PA + PS) {   // the terms of node_rel64 for cone id q
-    const int j = threadIdx.x;
-    int is, it, ip;
-    cone_split(q, gp.nc, &is, &it, &ip);
-    if (j < PA)
-      sincos(((double)it + ct.ua[j]) * gp.da, &sm.ang[j][0], &sm.ang[j][1]);
-    else if (j < 2 * PA)
-      sincos(((double)ip + ct.ua[j - PA]) * gp.da, &sm.ang[j][0], &sm.ang[j][1]);
-    else
-      sm.rad[j - 2 * PA] = gp.h / (((double)is + ct.us[j - 2 * PA]) * gp.ds);
-  }
   if (threadIdx.x < nb) sm.pslot[threadIdx.x] = ti_slot[tl.y + threadIdx.x];
   for (int t = threadIdx.x; t < NB * S::ACC_LD; t += BS) sm.acc[t / S::ACC_LD][t % S::ACC_LD] = {0.0, 0.0};
   __syncthreads();
@@ -2312,89 +2400,22 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
 
   for (int o = 0; o < 8; ++o) {
     if (!((anychild >> o) & 1)) continue;   // block-uniform
-    // ---- node geometry in the child frame of octant o ------------------------
-    for (int n = threadIdx.x; n < P; n += BS) {
-      double x[3], rp;
-      {   // node_rel64 from the tabulated terms
-        const int bi = (n / PA) % PA, ci = n % PA;
-        const double st = sm.ang[bi][0], ctt = sm.ang[bi][1], sp = sm.ang[PA + ci][0], cp = sm.ang[PA + ci][1];
-        const double e0 = st * cp, e1 = st * sp;
-        rp = sm.rad[n / (PA * PA)];
-        x[0] = rp * e0;
-        x[1] = rp * e1;
-        x[2] = rp * ctt;
-      }
-      const Prop64 pr = child_loc64(x, rp, o, gc);
-      sm.cid[n] = pr.loc.cid;
-      sm.crd[n][0] = pr.loc.ts;
-      sm.crd[n][1] = pr.loc.tt;
-      sm.crd[n][2] = pr.loc.tp;
-      double c_ = 1.0, s_ = 0.0, rr = 1.0;
-      if (kind != IFGF_KERNEL_CONSTANT) {
-        sincos(k * pr.dr, &s_, &c_);
-        rr = pr.rp_over_rc;
-      }
-      sm.rat[n][0] = rr * c_;
-      sm.rat[n][1] = rr * s_;
+    // ---- the octant's node records, from the plan's table --------------------------
+    {
+      const uint4* src = reinterpret_cast<const uint4*>(ti_geo + (int64_t)tl.w * 8 + o);
+      uint4* d = reinterpret_cast<uint4*>(&sm.geo);
+      for (int i = threadIdx.x; i < (int)(sizeof(TiGeo64<PS, PA>) / 16); i += BS) d[i] = src[i];
     }
     __syncthreads();
-    // ---- group the nodes by child cone (wave 0) ----------------------------------
-    if (wv == 0) {
-      constexpr int NPL = (P + 63) / 64;
-      int cv[NPL];
-      bool pend[NPL];
-#pragma unroll
-      for (int m = 0; m < NPL; ++m) {
-        const int n = lane + 64 * m;
-        pend[m] = n < P;
-        cv[m] = pend[m] ? sm.cid[n] : 0;
-      }
-      int pos = 0, g = 0, tpos = 0;
-      while (true) {
-        int lead = -1, su = 0;
-#pragma unroll
-        for (int m = 0; m < NPL && lead < 0; ++m) {
-          const uint64_t b = __ballot(pend[m]);
-          if (b) {
-            lead = first_lane(b);
-            su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
-          }
-        }
-        if (lead < 0) break;
-        if (lane == 0) {
-          sm.gstart[g] = pos;
-          sm.tstart[g] = (short)tpos;
-          sm.gcid[g] = su;
-        }
-        const int pos0 = pos;
-#pragma unroll
-        for (int m = 0; m < NPL; ++m) {
-          const bool hit = pend[m] && cv[m] == su;
-          const uint64_t b = __ballot(hit);
-          if (hit) sm.order[pos + __popcll(b & ((1ull << lane) - 1))] = (short)(lane + 64 * m);
-          pos += __popcll(b);
-          pend[m] = pend[m] && !hit;
-        }
-        const int nt = (pos - pos0 + 15) >> 4;   // at most ceil(P / 16) <= 64 column tiles
-        if (lane < nt) sm.tgrp[tpos + lane] = (short)g;
-        tpos += nt;
-        ++g;
-      }
-      if (lane == 0) {
-        sm.gstart[g] = pos;
-        sm.tstart[g] = (short)tpos;
-        sm.ngroup = g;
-      }
-    }
-    __syncthreads();
+    const TiGeo64<PS, PA>& G = sm.geo;
     // ---- child interpolants on MFMA ------------------------------------------------
     // Work units (row block r: 8 boxes of the octant's list, column tile t of
     // the groups), r-major, split evenly over the waves; a run of units with
     // the same (r, group) is a segment with one A operand, loaded one segment
     // ahead.  Units are disjoint in (box, node).
-    const int ng = sm.ngroup;
+    const int ng = G.ngroup;
     const int no = sm.ocnt[o];
-    const int T = sm.tstart[ng];
+    const int T = G.tstart[ng];
     const int U = ((no + 7) >> 3) * T;
     const int u0 = wv * U / NW, u1 = (wv + 1) * U / NW;
     struct Seg64 {
@@ -2402,15 +2423,15 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
     };
     auto seg_at = [&](int u) -> Seg64 {
       if (u >= u1) return Seg64{-1, 0, u1};
-      const int r = u / T, g = sm.tgrp[u - r * T];
-      return Seg64{r, g, min(u1, r * T + sm.tstart[g + 1])};
+      const int r = u / T, g = G.tgrp[u - r * T];
+      return Seg64{r, g, min(u1, r * T + G.tstart[g + 1])};
     };
     auto child_of = [&](const Seg64& sg) -> int {   // the child box of this lane's A row
       const int le = sg.r * 8 + (li >> 1);
       return (sg.r >= 0 && le < no) ? sm.child[sm.olist[o][le]][o] : -1;
     };
     auto slot_of = [&](const Seg64& sg, int Bc) -> int {
-      return Bc >= 0 ? slot_c[(int64_t)Bc * gc.ncone + sm.gcid[sg.g]] : -1;
+      return Bc >= 0 ? slot_c[(int64_t)Bc * gc.ncone + G.gcid[sg.g]] : -1;
     };
     constexpr bool PAIR = (PA * PA) % 2 == 0;
     constexpr int NRAW = PAIR ? PA * PA / 2 : PA * PA;
@@ -2447,6 +2468,7 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
     // entries go to row NB (the b entry to column P there).
     const bool odd = la & 1;
     doublex4 dq = {0.0, 0.0, 0.0, 0.0};
+    double2 qr = make_double2(0.0, 0.0);
     int qn = 0, qa = NB, qb = NB;
     auto xchg = [](double v) {
       const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
@@ -2458,7 +2480,7 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
       const double m0 = odd ? dq[2] : dq[0], m1 = odd ? dq[3] : dq[1];
       const double t0 = odd ? o2 : o0, t1 = odd ? o3 : o1;
       const double re0 = odd ? t0 : m0, im0 = odd ? m0 : t0, re1 = odd ? t1 : m1, im1 = odd ? m1 : t1;
-      const double er = sm.rat[qn][0], ei = sm.rat[qn][1];
+      const double er = qr.x, ei = qr.y;
       cpx<double>& ua = sm.acc[qa][qn];
       cpx<double>& ub = sm.acc[qb][qb == NB ? P : qn];
       cpx<double> va = ua, vb = ub;
@@ -2485,18 +2507,20 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
       const int s_nn = slot_of(nn, b_nn);
       load_raw(s_nxt, rn);
       if (b_cur >= 0 && s_cur < 0) atomicOr(err, 2);
-      const int g = cur.g, t0 = cur.r * T + sm.tstart[g];
-      const int n0 = sm.gstart[g], n1 = sm.gstart[g + 1];
+      const int g = cur.g, t0 = cur.r * T + G.tstart[g];
+      const int n0 = G.gstart[g], n1 = G.gstart[g + 1];
       const int e2a = cur.r * 8 + (odd ? 4 : 0) + (la >> 1), e2b = e2a + 2;
       const int bxa = e2a < no ? (int)sm.olist[o][e2a] : NB, bxb = e2b < no ? (int)sm.olist[o][e2b] : NB;
       for (; u < cur.ue; ++u) {
         const int e = n0 + 16 * (u - t0) + li;
         const bool ok = e < n1;
-        const int n = sm.order[ok ? e : n0];
+        const int ee = ok ? e : n0;
+        const int n = G.node[ee];
+        const double2 rt = make_double2(G.rat[ee][0], G.rat[ee][1]);
         double Ts[PS], Tt[PA], Tp[PA];
-        cheb_T<double, PS>(sm.crd[n][0], Ts);
-        cheb_T<double, PA>(sm.crd[n][1], Tt);
-        cheb_T<double, PA>(sm.crd[n][2], Tp);
+        cheb_T<double, PS>(G.crd[ee][0], Ts);
+        cheb_T<double, PA>(G.crd[ee][1], Tt);
+        cheb_T<double, PA>(G.crd[ee][2], Tp);
         double ta = 0.0;
 #pragma unroll
         for (int a = 0; a < PS; ++a)
@@ -2511,6 +2535,7 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
           for (int c = 0; c < PA; ++c) d = __builtin_amdgcn_mfma_f64_16x16x4f64(av[b * PA + c], w * Tp[c], d, 0, 0, 0);
         }
         dq = d;
+        qr = rt;
         qn = n;
         qa = ok ? bxa : NB;
         qb = ok ? bxb : NB;
@@ -2591,12 +2616,12 @@ __device__ __forceinline__ void prop_ti64_tile(Ti64Smem<PS, PA, NW>& sm, int4 tl
 template <int PS, int PA, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2))) void k_prop_ti64(
     const int4* __restrict__ tiles, const int* __restrict__ ti_slot, const int* __restrict__ ti_child,
-    const int* __restrict__ slot_c, const cpx<double>* __restrict__ Fc_c, LevelGeom gp, LevelGeom gc, ChebTab ct,
-    const double* __restrict__ Ms, const double* __restrict__ Ma, double k, int kind, cpx<double>* __restrict__ Fc_up,
-    int* __restrict__ err) {
+    const TiGeo64<PS, PA>* __restrict__ ti_geo, const int* __restrict__ slot_c, const cpx<double>* __restrict__ Fc_c,
+    LevelGeom gp, LevelGeom gc, ChebTab ct, const double* __restrict__ Ms, const double* __restrict__ Ma, double k,
+    int kind, cpx<double>* __restrict__ Fc_up, int* __restrict__ err) {
   __shared__ Ti64Smem<PS, PA, NW> sm;
-  prop_ti64_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, ti_child, slot_c, Fc_c, gp, gc, ct,
-                             Ms, Ma, k, kind, Fc_up, err);
+  prop_ti64_tile<PS, PA, NW>(sm, tiles[xcd_block(blockIdx.x, gridDim.x)], ti_slot, ti_child, ti_geo, slot_c, Fc_c, gp,
+                             gc, ct, Ms, Ma, k, kind, Fc_up, err);
 }
 
 // ---------------------------------------------------------------------------
@@ -3045,9 +3070,9 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
           auto launch = [&](auto kern, int nw) {
             kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
-                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lc.slot.as<int>(),
-                lc.Fc.as<cpx<double>>(), lp.geom, lc.geom, p->cheb, (const double*)Ms, (const double*)Ma, p->k, kind,
-                lp.Fc.as<cpx<double>>(), p->err.as<int>());
+                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lp.ti_geo.as<TiGeo64<PS, PA>>(),
+                lc.slot.as<int>(), lc.Fc.as<cpx<double>>(), lp.geom, lc.geom, p->cheb, (const double*)Ms,
+                (const double*)Ma, p->k, kind, lp.Fc.as<cpx<double>>(), p->err.as<int>());
           };
           if (lp.ti_nw == 2) launch(k_prop_ti64<PS, PA, 2>, 2);
           else launch(k_prop_ti64<PS, PA, 1>, 1);
@@ -3671,18 +3696,25 @@ void ti_geo_impl(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream
   DevBuf qd;
   qd.alloc(sizeof(int) * qlist.size());
   HIPCHK(hipMemcpyAsync(qd.p, qlist.data(), sizeof(int) * qlist.size(), hipMemcpyHostToDevice, s));
-  lp.ti_geo.alloc(sizeof(TiGeo<PS, PA>) * 8 * qlist.size());
-  k_ti_geo<PS, PA><<<(unsigned)(8 * qlist.size()), 256, 0, s>>>(qd.as<int>(), lp.geom, lc.geom, p->cheb, p->k,
-                                                                 p->opt.kernel, lp.ti_geo.as<TiGeo<PS, PA>>());
+  const unsigned grid = (unsigned)(8 * qlist.size());
+  if (p->opt.precision == IFGF_PREC_FP32_INTERP) {
+    lp.ti_geo.alloc(sizeof(TiGeo<PS, PA>) * 8 * qlist.size());
+    k_ti_geo<PS, PA><<<grid, 256, 0, s>>>(qd.as<int>(), lp.geom, lc.geom, p->cheb, p->k, p->opt.kernel,
+                                          lp.ti_geo.as<TiGeo<PS, PA>>());
+  } else {
+    lp.ti_geo.alloc(sizeof(TiGeo64<PS, PA>) * 8 * qlist.size());
+    k_ti_geo64<PS, PA><<<grid, 256, 0, s>>>(qd.as<int>(), lp.geom, lc.geom, p->cheb, p->k, p->opt.kernel,
+                                            lp.ti_geo.as<TiGeo64<PS, PA>>());
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));   // qd is freed on return
 }
 
 }  // namespace
 
-size_t ti_geo_bytes(int ps, int pa) {
-  if (ps == 3 && pa == 5) return sizeof(TiGeo<3, 5>);
-  if (ps == 4 && pa == 6) return sizeof(TiGeo<4, 6>);
+size_t ti_geo_bytes(int ps, int pa, bool f32) {
+  if (ps == 3 && pa == 5) return f32 ? sizeof(TiGeo<3, 5>) : sizeof(TiGeo64<3, 5>);
+  if (ps == 4 && pa == 6) return f32 ? sizeof(TiGeo<4, 6>) : sizeof(TiGeo64<4, 6>);
   return 0;
 }
 

@@ -66,7 +66,7 @@ struct LevelPlan {
   // boxes sharing one cone id: int4 (cone id, first index into ti_slot, count, 0)
   DevBuf ti_slot, ti_tile;
   DevBuf ti_child;            // per ti_slot entry: its box's child in each octant (8 ints, -1 if none)
-  DevBuf ti_geo;              // FP32: node records per (cone id of the tiles, octant), see build_ti_geo
+  DevBuf ti_geo;              // node records per (cone id of the tiles, octant), see build_ti_geo
   int64_t ntile = 0;
   // near field at the finest level: int4 [n_near] (box, first target, target
   // count, 0), boxes split into chunks of at most kNearChunk targets
@@ -164,7 +164,7 @@ void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, 
 // The cone-major tiles' node records of level d (one per cone id in qlist and
 // octant), computed on the GPU into p->lev[d].ti_geo.
 void build_ti_geo(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s);
-size_t ti_geo_bytes(int ps, int pa);   // one (cone id, octant) record
+size_t ti_geo_bytes(int ps, int pa, bool f32);   // one (cone id, octant) record
 bool supported_order(int ps, int pa);
 int prop_chunk(int P);
 bool cone_prop_supported(const ifgf_plan_s* p);

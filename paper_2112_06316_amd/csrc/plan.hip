@@ -706,14 +706,13 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
       const double per = (double)lv.nrel / (double)ndistinct;
       int nw = per >= 12.0 ? 4 : (per >= 6.0 ? 2 : 0);
       if (!f32 && nw > 2) nw = 2;   // FP64 tiles: at most 16 boxes (LDS)
-      // FP32 tiles read their node records from a table of 8 records per
-      // cone id (about 42 KB at P = 144); where that would exceed 2.5 times
-      // the level's coefficients (few boxes per cone id), AUTO keeps the node
-      // formulation
+      // The tiles read their node records from a table of 8 records per
+      // cone id (about 42 KB at P = 144 in FP32, 60 KB in FP64); where that
+      // would exceed 2.5 times the level's coefficients (few boxes per cone
+      // id), AUTO keeps the node formulation
       const bool forced = p->opt.prop_kernel == IFGF_PROP_CONE;
-      if (f32 && !forced &&
-          (double)ndistinct * 8.0 * (double)ti_geo_bytes(p->opt.p_s, p->opt.p_ang) >
-              2.5 * (double)lv.nrel * P * sizeof(cpx<float>))
+      if (!forced && (double)ndistinct * 8.0 * (double)ti_geo_bytes(p->opt.p_s, p->opt.p_ang, f32) >
+                         2.5 * (double)lv.nrel * P * (f32 ? sizeof(cpx<float>) : sizeof(cpx<double>)))
         nw = 0;
       if (forced && nw == 0) nw = 1;
       if (nw == 0) continue;
@@ -762,8 +761,8 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
         std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
           return x[0] < y[0];
         });
-      // FP32: the node records of each (cone id, octant) are computed once
-      // per level; a tile's fourth entry indexes its cone id's records
+      // the node records of each (cone id, octant) are computed once per
+      // level; a tile's fourth entry indexes its cone id's records
       std::vector<int> qlist;
       for (const auto& t : tl) qlist.push_back(t[1]);
       std::sort(qlist.begin(), qlist.end());
@@ -774,9 +773,9 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
         tiles.push_back(t[1]);
         tiles.push_back(t[2]);
         tiles.push_back(t[3]);
-        tiles.push_back(f32 ? (int)(std::lower_bound(qlist.begin(), qlist.end(), t[1]) - qlist.begin()) : 0);
+        tiles.push_back((int)(std::lower_bound(qlist.begin(), qlist.end(), t[1]) - qlist.begin()));
       }
-      if (f32) build_ti_geo(p, d, qlist, s);
+      build_ti_geo(p, d, qlist, s);
       // each tile box's child per octant, in ti_slot order, so that a tile
       // reads its boxes' children with one coalesced load
       std::vector<int> tchild(8 * (size_t)lv.nrel, -1);
