@@ -98,12 +98,12 @@ typedef struct {
  * node's position in a child's frame depends only on (parent cone id, child
  * octant, node); the boxes holding the same parent cone id are taken
  * together and the interpolation becomes a product of their child
- * coefficients with one basis matrix, on MFMA.  In FP32 the plan stores the
- * node positions in each child frame once per (parent cone id, octant), about
- * 42 KB per cone id at P = (4,6,6).  AUTO picks CONE for the levels where the
- * boxes per parent cone id fill its tiles and, in FP32, that table stays
- * within 2.5 times the level's coefficient storage; CONE forces it on every
- * level.  Both give the same operator up to rounding. */
+ * coefficients with one basis matrix, on MFMA.  The plan stores the node
+ * positions in each child frame once per (parent cone id, octant), about
+ * 42 KB (FP32) or 60 KB (FP64) per cone id at P = (4,6,6).  AUTO picks CONE
+ * for the levels where the boxes per parent cone id fill its tiles and that
+ * table stays within 2.5 times the level's coefficient storage; CONE forces
+ * it on every level.  Both give the same operator up to rounding. */
 enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2 };
 
 /* Cousin-target formulation (Algorithm 1, target evaluation; nrhs = 1, FP32
