@@ -753,11 +753,11 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
       }
       // Order the tiles by first box, so that tiles of different cone ids
       // over the same boxes - which read the same child cones - run back to
-      // back (and, with the XCD-aware block mapping, on one XCD); except, in
-      // FP32, where a cone id has several tiles (4 or more on average): those
-      // stay together, so that its node records (8 x 5.2 KB at P = 144) stay
-      // in L2 from one tile to the next.
-      if (!f32 || (int64_t)tl.size() < 4 * ndistinct)
+      // back (and, with the XCD-aware block mapping, on one XCD); except
+      // where a cone id has several tiles (4 or more on average): those stay
+      // together, so that its node records (8 x 5.2 KB at P = 144 in FP32,
+      // 8 x 7.5 KB in FP64) stay in L2 from one tile to the next.
+      if ((int64_t)tl.size() < 4 * ndistinct)
         std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
           return x[0] < y[0];
         });
