@@ -283,7 +283,8 @@ void ifgf_plan_destroy(ifgf_plan p);
 /*
  * Ragged batch: the forward apply (as ifgf_apply, one right-hand side) of
  * several plans - different geometries, sizes, depths and wavenumbers - in
- * ONE persistent kernel launch.  Algorithm 1 of every geometry is cut into
+ * ONE kernel launch (one work-group per queue item, not a persistent
+ * kernel).  Algorithm 1 of every geometry is cut into
  * work items (gather chunks, near-field boxes, leaf boxes, coefficient
  * chunks, upward-pass items of each level, target chunks) held in one
  * queue in data-flow order; work-groups take items from the queue and wait
@@ -315,7 +316,7 @@ void ifgf_plan_destroy(ifgf_plan p);
  *   abandoned (default 4194304, each about 0.3 us apart; 0 = never wait).
  *   A test hook for the bounded wait.
  * ifgf_batch_get_info: [host] outputs, each may be NULL: queue items,
- *   queue segments, work-groups of the persistent launch, threads per
+ *   queue segments, work-groups of the launch, threads per
  *   work-group.
  * ifgf_batch_destroy: releases the batch (not the plans).  NULL is ignored.
  */

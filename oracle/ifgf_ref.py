@@ -218,12 +218,6 @@ def build_tree(points: np.ndarray, D: int) -> Tree:
     return Tree(D=D, L=L, corner=corner, perm=perm, keys=keys_s, points=pts_s, levels=levels)
 
 
-def auto_depth(L: float, k: float, leaf_h_lambda: float = 0.5) -> int:
-    """Smallest-error integer depth whose leaf side is closest to leaf_h_lambda wavelengths."""
-    lam = 2.0 * math.pi / k
-    return max(1, 1 + int(round(math.log2(L / (leaf_h_lambda * lam)))))
-
-
 # ----------------------------------------------------------------------------
 # Cone segments (Section 3.2) and their refinement across levels
 # ----------------------------------------------------------------------------

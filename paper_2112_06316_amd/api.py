@@ -31,6 +31,30 @@ def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
+def _check_out(out, like, name="out"):
+    """A caller's output buffer must match the input it receives: the library
+    sees raw pointers only, so a smaller or mistyped buffer would be written
+    past its end on the device."""
+    if not isinstance(out, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if out.dtype != like.dtype:
+        raise TypeError(f"{name} has dtype {out.dtype}, expected {like.dtype}")
+    if out.device != like.device:
+        raise ValueError(f"{name} is on {out.device}, expected {like.device}")
+    if out.dim() == 1 and like.dim() == 2 and like.shape[1] == 1:
+        out = out[:, None]
+    if tuple(out.shape) != tuple(like.shape):
+        raise ValueError(f"{name} has shape {tuple(out.shape)}, expected {tuple(like.shape)}")
+    if not out.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if out.numel() and like.numel():
+        o0, o1 = out.data_ptr(), out.data_ptr() + out.numel() * out.element_size()
+        l0, l1 = like.data_ptr(), like.data_ptr() + like.numel() * like.element_size()
+        if o0 < l1 and l0 < o1:
+            raise ValueError(f"{name} overlaps the input")
+    return out
+
+
 def _dev_f64(x, device, shape):
     t = torch.as_tensor(x, dtype=torch.float64)
     t = t.to(device).contiguous()
@@ -109,7 +133,7 @@ class Plan:
     def apply(self, sigma, out=None):
         """u = A sigma (forward IFGF apply)."""
         s, squeeze, dtype = self._prep(sigma)
-        u = torch.empty_like(s) if out is None else out
+        u = torch.empty_like(s) if out is None else _check_out(out, s)
         st = self._lib.ifgf_apply(self._h, s.data_ptr(), u.data_ptr(), s.shape[1], dtype, _stream_ptr(self.device))
         L.check(st, "ifgf_apply")
         return u[:, 0] if squeeze else u
@@ -257,7 +281,13 @@ class Batch:
                 raise TypeError("all densities must share one dtype")
             dtype = d
             xs.append(x.to(self.device).contiguous())
-        us = [torch.empty_like(x) for x in xs] if outs is None else list(outs)
+        if outs is None:
+            us = [torch.empty_like(x) for x in xs]
+        else:
+            outs = list(outs)
+            if len(outs) != len(xs):
+                raise ValueError("one output per plan")
+            us = [_check_out(o, x, f"outs[{g}]") for g, (o, x) in enumerate(zip(outs, xs))]
         sp = (ctypes.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
         up = (ctypes.c_void_p * len(us))(*[u.data_ptr() for u in us])
         L.check(self._lib.ifgf_batch_apply(self._h, sp, up, dtype, _stream_ptr(self.device)), "ifgf_batch_apply")

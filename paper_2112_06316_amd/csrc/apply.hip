@@ -3219,7 +3219,7 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
 }
 
 // ---------------------------------------------------------------------------
-// Ragged batch: several plans (geometries) in one persistent launch.
+// Ragged batch: several plans (geometries) in one launch (one work-group per queue item).
 //
 // The whole apply of every geometry is cut into work items - gather chunks,
 // near-field boxes, leaf boxes, coefficient chunks of the finest level,

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2112_06316_amd import _lib
@@ -47,3 +48,27 @@ def test_struct_layout_matches_header():
     assert _lib.Options.leaf_h_lambda.offset == 24
     assert _lib.Options.target_kernel.offset == 48
     assert _lib.Stats.boxes.offset == 64
+
+
+def test_output_buffer_validation():
+    # The library sees raw pointers only: a caller's output buffer must match
+    # the input exactly, or the binding refuses it before any device call.
+    import torch
+    from paper_2112_06316_amd.api import _check_out
+    s = torch.zeros(10, 2, dtype=torch.complex128)
+    assert _check_out(torch.empty(10, 2, dtype=torch.complex128), s).shape == (10, 2)
+    s1 = torch.zeros(10, 1, dtype=torch.complex64)
+    assert _check_out(torch.empty(10, dtype=torch.complex64), s1).shape == (10, 1)
+    with pytest.raises(TypeError):
+        _check_out(torch.empty(10, 2, dtype=torch.complex64), s)
+    with pytest.raises(ValueError):
+        _check_out(torch.empty(9, 2, dtype=torch.complex128), s)
+    with pytest.raises(ValueError):
+        _check_out(torch.empty(2, 10, dtype=torch.complex128).t(), s)
+    with pytest.raises(ValueError):
+        _check_out(s, s)
+    big = torch.zeros(20, 2, dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        _check_out(big[5:15], big[:10])
+    with pytest.raises(TypeError):
+        _check_out(np.zeros((10, 2), dtype=np.complex128), s)

@@ -245,3 +245,104 @@ def test_error_decreases_with_order():
         errs.append(np.linalg.norm(R.apply(plan, s) - ud) / np.linalg.norm(ud))
     assert errs[0] > errs[1] > errs[2] > errs[3]
     assert errs[3] < 5e-5
+
+
+# ----------------------------------------------------------------------------
+# Relevant cones (eq. RelevantCones): the returned set is exactly the set of
+# cone segments that contain a cousin point or a node of a relevant parent
+# cone.  Checked by interval membership of each candidate point, with the
+# polar angle from arccos (a formulation independent of the oracle's floor
+# indexing), so that a superset (cones marked from the wrong parent, the
+# wrong level or the wrong refinement) fails as well as a missing cone.
+# ----------------------------------------------------------------------------
+
+def _candidates(plan, d, b):
+    t = plan.tree
+    lev = t.levels[d]
+    pts = [t.points[lev.start[c]:lev.start[c + 1]] for c in lev.cousins[b]]
+    if d > 3:
+        up = t.levels[d - 1]
+        p = lev.parent[b]
+        pc = plan.cones[d - 1][p]
+        if pc.size:
+            pns, pnc = plan.counts[d - 1]
+            pts.append(R.node_points(up.centre[p], up.H, pc, pns, pnc, plan.ps, plan.pa).reshape(-1, 3))
+    return np.concatenate(pts) if pts else np.zeros((0, 3))
+
+
+def _inside(cid, x, y0, H, ns, nc, tol=1e-12):
+    """Boolean per point: x lies in the closed cone segment cid about y0."""
+    i_p = cid % (2 * nc)
+    i_t = (cid // (2 * nc)) % nc
+    i_s = cid // (2 * nc * nc)
+    dx = x - y0
+    r = np.linalg.norm(dx, axis=1)
+    s = math.sqrt(3.0) / 2.0 * H / r
+    th = np.arccos(np.clip(dx[:, 2] / r, -1.0, 1.0))
+    ph = np.mod(np.arctan2(dx[:, 1], dx[:, 0]), 2.0 * math.pi)
+    ds, da = math.sqrt(3.0) / 3.0 / ns, math.pi / nc
+    ok = (s >= i_s * ds - tol) & (s <= (i_s + 1) * ds + tol)
+    ok &= (th >= i_t * da - 1e-9) & (th <= (i_t + 1) * da + 1e-9)
+    hi_p = (i_p + 1) * da + 1e-9
+    ok &= ((ph >= i_p * da - 1e-9) & (ph <= hi_p)) | ((i_p == 0) & (ph >= 2.0 * math.pi - 1e-9))
+    return ok
+
+
+@pytest.mark.parametrize("ps,pa,ns0,nc0,D,shape", [(3, 5, 1, 2, 4, "sphere"), (4, 6, 2, 4, 4, "sphere"),
+                                                   (3, 5, 1, 2, 5, "ellipsoid")])
+def test_relevant_cones_are_exactly_the_hit_cones(ps, pa, ns0, nc0, D, shape):
+    if shape == "sphere":
+        p, nr, w = inputs.cubed_sphere(20)
+    else:
+        p, nr, w = inputs.ellipsoid(16, semi_axes=(0.5, 0.375, 0.25))
+    k = 8 * np.pi
+    plan = R.make_plan(p, nr, w, k, k, D, ps=ps, pa=pa, ns0=ns0, nc0=nc0)
+    t = plan.tree
+    for d in range(3, D + 1):
+        lev = t.levels[d]
+        ns, nc = plan.counts[d]
+        for b in range(lev.coords.shape[0]):
+            x = _candidates(plan, d, b)
+            cones = plan.cones[d][b]
+            covered = np.zeros(x.shape[0], dtype=bool)
+            for c in cones.tolist():
+                inside = _inside(c, x, lev.centre[b], lev.H, ns, nc)
+                assert inside.any(), f"level {d} box {b}: cone {c} holds no cousin point or parent node"
+                covered |= inside
+            assert covered.all(), f"level {d} box {b}: a candidate point lies in no relevant cone"
+
+
+def test_relevant_counts_match_independent_estimate_small():
+    # Counts for the 6,144-point cubed sphere at 4 wavelengths, D = 4,
+    # (P_s, P_ang) = (3, 5), (n_S0, n_C0) = (1, 2), computed before this
+    # implementation by an independent estimator written from eqs.
+    # RelevantBoxes, NeighborsCousins and RelevantCones.
+    p, nr, w = inputs.cubed_sphere(32)
+    k = 8 * np.pi
+    plan = R.make_plan(p, nr, w, k, k, 4, ps=3, pa=5, ns0=1, nc0=2)
+    t = plan.tree
+    assert [t.levels[d].coords.shape[0] for d in (3, 4)] == [56, 272]
+    assert [sum(c.size for c in plan.cones[d]) for d in (3, 4)] == [1296, 1904]
+    lev = t.levels[4]
+    cnt = np.diff(lev.start)
+    near = sum(int(cnt[b]) * int(cnt[lev.neighbours[b]].sum()) for b in range(cnt.size)) - p.shape[0]
+    assert abs(near - 1.97e6) < 0.01e6
+    cous = sum(int(np.diff(t.levels[d].start)[t.levels[d].cousins[b]].sum())
+               for d in (3, 4) for b in range(t.levels[d].coords.shape[0]))
+    assert abs(cous - 0.55e6) < 0.01e6
+
+
+@pytest.mark.slow
+def test_relevant_counts_match_independent_estimate_16_wavelengths():
+    # The 98,304-point cubed sphere at 16 wavelengths, D = 6, same setting:
+    # the independent estimate gives boxes 56 / 272 / 1,160 / 4,472 and
+    # relevant cones 16.8k / 40.8k / 44.8k / 34.7k at d = 3..6.
+    p, nr, w = inputs.cubed_sphere(128)
+    k = 32 * np.pi
+    tree = R.build_tree(p, 6)
+    counts = R.cone_counts(k, tree.L, 6, 1, 2)
+    cones = R.relevant_cones(tree, counts, 3, 5)
+    assert [tree.levels[d].coords.shape[0] for d in range(3, 7)] == [56, 272, 1160, 4472]
+    got = [sum(c.size for c in cones[d]) for d in range(3, 7)]
+    for g, e in zip(got, [16.8e3, 40.8e3, 44.8e3, 34.7e3]):
+        assert abs(g - e) <= 0.005 * e + 50
