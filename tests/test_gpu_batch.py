@@ -120,8 +120,12 @@ def test_batch_argument_errors():
     s = to_dev(inputs.random_density(len(p), seed=51))
     with pytest.raises(ValueError):
         bt.apply([s, s])
-    with pytest.raises(L.IFGFError):   # an output aliasing an input
+    with pytest.raises(ValueError):    # the binding rejects an output aliasing an input
         bt.apply([s], outs=[s])
+    # and so does the library itself, called through the C ABI
+    sp = (ctypes.c_void_p * 1)(s.data_ptr())
+    st = lib.ifgf_batch_apply(bt._h, sp, sp, L.C128, torch.cuda.current_stream().cuda_stream)
+    assert st == L.EINVAL
 
 
 def test_bounded_wait_returns_and_flags():
