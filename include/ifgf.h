@@ -324,6 +324,28 @@ void ifgf_plan_destroy(ifgf_plan p);
 ifgf_status ifgf_batch_create(ifgf_batch *out, int32_t nplans, const ifgf_plan *plans);
 ifgf_status ifgf_batch_apply(ifgf_batch b, const void *const *sigma, void *const *u, int32_t dtype,
                              void *stream);
+
+/*
+ * ifgf_batch_apply_noalloc: ifgf_batch_apply for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results, ownership and errors as
+ * ifgf_batch_apply; the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine, on the device or through torch).  The launch's
+ * completion counters (queue head and 16 per geometry) come from one fixed
+ * device array of IFGF_BATCH_NOALLOC_COUNTERS ints (4,100 bytes) per GPU,
+ * held by the library until the process ends, instead of the batch's own
+ * buffer; a fill kernel clears them at the start of every call.  The batch
+ * must have been created with the current device current (EINVAL otherwise).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (on different streams, or on
+ * different batches) race on the counters and must be serialized by the
+ * caller.  The first call on a device looks the array's address up once.
+ * Errors: EINVAL (also a batch needing more counters than the array holds),
+ * EBUSY, EHIP.
+ */
+#define IFGF_BATCH_NOALLOC_COUNTERS (1 + 16 * IFGF_BATCH_MAX)
+ifgf_status ifgf_batch_apply_noalloc(ifgf_batch b, const void *const *sigma, void *const *u, int32_t dtype,
+                                     void *stream);
 ifgf_status ifgf_batch_check(ifgf_batch b, int32_t *flags);
 ifgf_status ifgf_batch_set_spin_limit(ifgf_batch b, int32_t limit);
 ifgf_status ifgf_batch_get_info(ifgf_batch b, int64_t *items, int32_t *segments, int32_t *grid,

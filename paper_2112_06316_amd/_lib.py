@@ -78,6 +78,7 @@ SIGNATURES = {
     "ifgf_plan_destroy": (None, [VP]),
     "ifgf_batch_create": (I32, [ctypes.POINTER(VP), I32, ctypes.POINTER(VP)]),
     "ifgf_batch_apply": (I32, [VP, ctypes.POINTER(VP), ctypes.POINTER(VP), I32, VP]),
+    "ifgf_batch_apply_noalloc": (I32, [VP, ctypes.POINTER(VP), ctypes.POINTER(VP), I32, VP]),
     "ifgf_batch_check": (I32, [VP, ctypes.POINTER(I32)]),
     "ifgf_batch_set_spin_limit": (I32, [VP, I32]),
     "ifgf_batch_get_info": (I32, [VP, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32),

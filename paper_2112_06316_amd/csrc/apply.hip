@@ -24,6 +24,7 @@
 // served together: the wave repeatedly takes the slot of its first pending
 // lane, makes it wave-uniform with readfirstlane, and every lane holding that
 // slot evaluates with the uniform coefficient pointer.
+#include <mutex>
 #include <type_traits>
 
 #include "internal.h"
@@ -3656,19 +3657,22 @@ void batch_prepare_impl(ifgf_batch_s* b) {
 }
 
 template <typename T, int PS, int PA>
-void batch_apply_impl(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, hipStream_t s) {
+void batch_apply_impl(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, int* ctr,
+                      hipStream_t s) {
   BIo io{};
   const int ng = (int)b->plans.size();
   for (int g = 0; g < ng; ++g) {
     io.sigma[g] = sigma[g];
     io.u[g] = u[g];
   }
-  k_zero_i32<<<nblocks(b->nctr), TPB, 0, s>>>(b->ctr.as<int>(), b->nctr);
+  // the counters start at zero; a fill kernel rather than a memset, so that a
+  // captured graph replays it as an ordinary kernel node
+  k_zero_i32<<<nblocks(b->nctr), TPB, 0, s>>>(ctr, b->nctr);
   HIPCHK(hipGetLastError());
   if (b->total == 0) return;
   k_batch<T, PS, PA><<<b->grid, b->block, b->smem, s>>>(b->segs.as<BSeg>(), b->seg_of.as<int>(), b->total,
-                                                        b->geoms.as<BGeom<T>>(), io, dtype, b->ctr.as<int>(),
-                                                        b->spin_limit, b->err.as<int>());
+                                                        b->geoms.as<BGeom<T>>(), io, dtype, ctr, b->spin_limit,
+                                                        b->err.as<int>());
   HIPCHK(hipGetLastError());
 }
 
@@ -3763,15 +3767,49 @@ void run_batch_prepare(ifgf_batch_s* b) {
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
 }
 
-void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, hipStream_t s) {
+void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, int* ctr, hipStream_t s) {
   ifgf_plan_s* p = b->plans[0];
   const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
   const int ps = p->opt.p_s, pa = p->opt.p_ang;
+  if (!ctr) ctr = b->ctr.as<int>();
   if (ps == 3 && pa == 5)
-    return f32 ? batch_apply_impl<float, 3, 5>(b, sigma, u, dtype, s) : batch_apply_impl<double, 3, 5>(b, sigma, u, dtype, s);
+    return f32 ? batch_apply_impl<float, 3, 5>(b, sigma, u, dtype, ctr, s)
+               : batch_apply_impl<double, 3, 5>(b, sigma, u, dtype, ctr, s);
   if (ps == 4 && pa == 6)
-    return f32 ? batch_apply_impl<float, 4, 6>(b, sigma, u, dtype, s) : batch_apply_impl<double, 4, 6>(b, sigma, u, dtype, s);
+    return f32 ? batch_apply_impl<float, 4, 6>(b, sigma, u, dtype, ctr, s)
+               : batch_apply_impl<double, 4, 6>(b, sigma, u, dtype, ctr, s);
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
+}
+
+// ---------------------------------------------------------------------------
+// Completion counters of the allocation-free batch apply.  The launch's queue
+// head and its 16 counters per geometry live in this fixed device array (one
+// copy per GPU, held until the process ends) instead of the batch's own
+// buffer.  Host code never names the array in a launch or a copy: its device
+// address is looked up once per device, with that device current, and that
+// address is what the kernels receive.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) int scratch[BATCH_STATIC_COUNTERS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+int* batch_static_counters(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error{IFGF_EINVAL, "device ordinal out of range"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != device) throw Error{IFGF_EINVAL, "the counters' device is not the current device"};
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Error{IFGF_EHIP, "no device address for the static counters"};
+    g_scratch_addr[device] = (int*)ptr;
+  }
+  return g_scratch_addr[device];
 }
 
 }  // namespace ifgf

@@ -348,6 +348,7 @@ ifgf_status ifgf_batch_create(ifgf_batch* out, int32_t nplans, const ifgf_plan* 
         throw Error{IFGF_EINVAL, "batch plans must share precision, p_s and p_ang"};
       b->plans.push_back(p);
     }
+    HIPCHK(hipGetDevice(&b->device));
     HIPCHK(hipDeviceSynchronize());
     run_batch_prepare(b.get());
     HIPCHK(hipDeviceSynchronize());
@@ -356,25 +357,61 @@ ifgf_status ifgf_batch_create(ifgf_batch* out, int32_t nplans, const ifgf_plan* 
   return st;
 }
 
+// Argument checks shared by the two batch applies.
+static void check_batch_args(ifgf_batch b, const void* const* sigma, void* const* u, int32_t dtype) {
+  if (!b || !sigma || !u) throw Error{IFGF_EINVAL, "null pointer argument"};
+  if (dtype != IFGF_C64 && dtype != IFGF_C128) throw Error{IFGF_EINVAL, "bad dtype"};
+  const int ng = (int)b->plans.size();
+  for (int g = 0; g < ng; ++g) {
+    if (!sigma[g] || !u[g]) throw Error{IFGF_EINVAL, "null sigma or u pointer"};
+    for (int h = 0; h < ng; ++h)
+      if ((const void*)u[g] == sigma[h]) throw Error{IFGF_EINVAL, "an output aliases an input"};
+  }
+}
+
+// Busy flags of the batch and of each of its plans, taken together (fixed
+// storage: no allocation) and released on scope exit.
+struct BatchGuard {
+  std::atomic<int>* held[IFGF_BATCH_MAX + 1];
+  int n = 0;
+  bool take(std::atomic<int>* busy) {
+    int expect = 0;
+    if (!busy->compare_exchange_strong(expect, 1)) return false;
+    held[n++] = busy;
+    return true;
+  }
+  ~BatchGuard() {
+    for (int i = 0; i < n; ++i) held[i]->store(0);
+  }
+};
+
+static void batch_apply_common(ifgf_batch b, const void* const* sigma, void* const* u, int32_t dtype, int* ctr,
+                               void* stream) {
+  BatchGuard g;
+  if (!g.take(&b->busy)) throw Error{IFGF_EBUSY, "another apply of this batch is being enqueued"};
+  for (auto* p : b->plans)
+    if (!g.take(&p->busy)) throw Error{IFGF_EBUSY, "an apply on a plan of the batch is being enqueued"};
+  run_batch_apply(b, sigma, u, dtype, ctr, (hipStream_t)stream);
+  for (auto* p : b->plans) p->last_rhs = 1;
+}
+
 ifgf_status ifgf_batch_apply(ifgf_batch b, const void* const* sigma, void* const* u, int32_t dtype, void* stream) {
   return guarded([&] {
-    if (!b || !sigma || !u) throw Error{IFGF_EINVAL, "null pointer argument"};
-    if (dtype != IFGF_C64 && dtype != IFGF_C128) throw Error{IFGF_EINVAL, "bad dtype"};
-    const int ng = (int)b->plans.size();
-    for (int g = 0; g < ng; ++g) {
-      if (!sigma[g] || !u[g]) throw Error{IFGF_EINVAL, "null sigma or u pointer"};
-      for (int h = 0; h < ng; ++h)
-        if ((const void*)u[g] == sigma[h]) throw Error{IFGF_EINVAL, "an output aliases an input"};
-    }
-    BusyGuard gb(b);
-    if (!gb.ok) throw Error{IFGF_EBUSY, "another apply of this batch is being enqueued"};
-    std::vector<std::unique_ptr<BusyGuard>> guards;
-    for (auto* p : b->plans) {
-      guards.emplace_back(new BusyGuard(p));
-      if (!guards.back()->ok) throw Error{IFGF_EBUSY, "an apply on a plan of the batch is being enqueued"};
-    }
-    run_batch_apply(b, sigma, u, dtype, (hipStream_t)stream);
-    for (auto* p : b->plans) p->last_rhs = 1;
+    check_batch_args(b, sigma, u, dtype);
+    batch_apply_common(b, sigma, u, dtype, nullptr, stream);
+  });
+}
+
+ifgf_status ifgf_batch_apply_noalloc(ifgf_batch b, const void* const* sigma, void* const* u, int32_t dtype,
+                                     void* stream) {
+  return guarded([&] {
+    check_batch_args(b, sigma, u, dtype);
+    if (b->nctr > BATCH_STATIC_COUNTERS)
+      throw Error{IFGF_EINVAL, "the batch needs more completion counters than the static array holds"};
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev != b->device) throw Error{IFGF_EINVAL, "the batch's device is not the current device"};
+    batch_apply_common(b, sigma, u, dtype, batch_static_counters(dev), stream);
   });
 }
 

@@ -139,6 +139,7 @@ struct ifgf_batch_s {
   int grid = 0, block = 0;
   size_t smem = 0;
   int spin_limit = 1 << 22;
+  int device = 0;                    // current device when the batch was created
   std::atomic<int> busy{0};
 };
 
@@ -159,7 +160,12 @@ void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, 
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
 
 void run_batch_prepare(ifgf_batch_s* b);
-void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, hipStream_t s);
+// ctr: the launch's completion counters (b->nctr ints); nullptr = the batch's own buffer.
+void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, int* ctr, hipStream_t s);
+// Device address of the fixed counter array (BATCH_STATIC_COUNTERS ints) on `device`,
+// which must be the current device; looked up once per device.
+constexpr int BATCH_STATIC_COUNTERS = IFGF_BATCH_NOALLOC_COUNTERS;
+int* batch_static_counters(int device);
 
 // The cone-major tiles' node records of level d (one per cone id in qlist and
 // octant), computed on the GPU into p->lev[d].ti_geo.
