@@ -171,27 +171,38 @@ def main():
         for _ in range(warmup):
             plan.apply(sig_d, out=u[:, None])
         torch.cuda.synchronize()
-        if profile:
-            plan.set_profiling(64 * steps)
+        # timed region: the applies alone, one event pair per apply on the
+        # stream the library launches on (no per-kernel events)
         stream = torch.cuda.current_stream(dev)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(steps):
+        for e0, e1 in ev:
+            e0.record(stream)
             plan.apply(sig_d, out=u[:, None])
-        e1.record(stream)
+            e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ev_ms = e0.elapsed_time(e1)
-        prof = plan.read_profile() if profile else {}
+        per = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+        ev_ms = sum(per)
+        prof = {}
         if profile:
+            # the same applies again with every kernel launch bracketed by
+            # events (stage times and the dominant kernel's launch duration)
+            plan.set_profiling(64 * steps)
+            for _ in range(steps):
+                plan.apply(sig_d, out=u[:, None])
+            torch.cuda.synchronize()
+            prof = plan.read_profile()
             plan.set_profiling(0)
         flags = plan.check()
         st = plan.stats()
         uh = u.cpu().numpy()
-        log(f"{precision}: {steps} applies, wall {wall * 1e3 / steps:.3f} ms/apply, events {ev_ms / steps:.3f} ms/apply")
-        return dict(plan=plan, t_plan=t_plan, wall=wall, ev_ms=ev_ms, prof=prof, stats=st, u=uh, flags=flags)
+        med = per[len(per) // 2] if len(per) % 2 else 0.5 * (per[len(per) // 2 - 1] + per[len(per) // 2])
+        log(f"{precision}: {steps} applies, wall {wall * 1e3 / steps:.3f} ms/apply, events median {med:.3f} "
+            f"min {per[0]:.3f} ms")
+        return dict(plan=plan, t_plan=t_plan, wall=wall, ev_ms=ev_ms, ev_median=med, ev_min=per[0], prof=prof,
+                    stats=st, u=uh, flags=flags)
 
     r32 = run("fp32", args.steps, args.warmup, True)
     st = r32["stats"]
@@ -432,6 +443,8 @@ def main():
         },
         "applies_per_s": 1e3 / ms_per_step,
         "event_ms_per_step": r32["ev_ms"] / args.steps,
+        "event_ms_median": r32["ev_median"],
+        "event_ms_min": r32["ev_min"],
         "rel_err": err32,
         "rel_err_targets": len(tg),
         "plan_create_s": r32["t_plan"],

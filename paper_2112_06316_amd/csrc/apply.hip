@@ -433,16 +433,15 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
                                                 const T* __restrict__ Ms, const T* __restrict__ Ma,
                                                 cpx<T>* __restrict__ Fc) {
   constexpr int P = PS * PA * PA;
-  static_assert(P <= TPB, "one cone per block");
   __shared__ cpx<T> v0[P], v1[P];
   __shared__ T ms[PS * PS], ma[PA * PA];
-  const int sl = blockIdx.x, r = blockIdx.y, t = threadIdx.x;
-  if (t < PS * PS) ms[t] = TR ? Ms[(t % PS) * PS + t / PS] : Ms[t];
-  if (t < PA * PA) ma[t] = TR ? Ma[(t % PA) * PA + t / PA] : Ma[t];
-  if (t < P) v0[t] = Fn[((int64_t)sl * P + t) * R + r];
+  const int sl = blockIdx.x, r = blockIdx.y, t0 = threadIdx.x;
+  if (t0 < PS * PS) ms[t0] = TR ? Ms[(t0 % PS) * PS + t0 / PS] : Ms[t0];
+  if (t0 < PA * PA) ma[t0] = TR ? Ma[(t0 % PA) * PA + t0 / PA] : Ma[t0];
+  for (int t = t0; t < P; t += TPB) v0[t] = Fn[((int64_t)sl * P + t) * R + r];
   __syncthreads();
-  int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
-  if (t < P) {  // over a (s)
+  for (int t = t0; t < P; t += TPB) {  // over a (s)
+    const int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
     cpx<T> s = {0, 0};
     for (int q = 0; q < PS; ++q) {
       cpx<T> x = v0[(q * PA + j) * PA + l];
@@ -452,7 +451,8 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
     v1[t] = s;
   }
   __syncthreads();
-  if (t < P) {  // over b (theta)
+  for (int t = t0; t < P; t += TPB) {  // over b (theta)
+    const int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
     cpx<T> s = {0, 0};
     for (int q = 0; q < PA; ++q) {
       cpx<T> x = v1[(i * PA + q) * PA + l];
@@ -462,7 +462,8 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
     v0[t] = s;
   }
   __syncthreads();
-  if (t < P) {  // over c (phi)
+  for (int t = t0; t < P; t += TPB) {  // over c (phi)
+    const int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
     cpx<T> s = {0, 0};
     for (int q = 0; q < PA; ++q) {
       cpx<T> x = v0[(i * PA + j) * PA + q];
@@ -730,6 +731,7 @@ __device__ __forceinline__ cpx<T> eval_rows(const cpx<T>* __restrict__ Fc, int s
 template <int P> struct PropShape;
 template <> struct PropShape<75> { static constexpr int CH = 10, BS = 256; };    // 750 nodes, 3 x 256
 template <> struct PropShape<144> { static constexpr int CH = 4, BS = 192; };    // 576 nodes, 3 x 192
+template <> struct PropShape<512> { static constexpr int CH = 1, BS = 256; };    // 512 nodes, 2 x 256
 
 template <typename T> struct PropGeomT;
 template <> struct PropGeomT<float> { using P = PropF; };
@@ -957,7 +959,7 @@ __device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_>& sm, int4 wk,
         tp = st[n][2];
       }
       cpx<T> v;
-      if constexpr (ONE)
+      if constexpr (ONE && RowStage1<T, PS, PA>::ok)
         v = eval_rows<T, PS, PA>(Fc_c, sl, ts, tt, tp);
       else
         v = eval_uniform<T, PS, PA>(Fc_c, sl, R, r, ts, tt, tp, cbuf[threadIdx.x >> 6]);
@@ -2967,6 +2969,10 @@ __global__ __launch_bounds__(TPB) void k_adj_out(const cpx<T>* __restrict__ g, c
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// Orders with cone-major upward-pass tiles (P <= 144: the tile keeps a
+// child's P_ang^2 coefficients per radial index in registers).
+constexpr bool cone_major_order(int ps, int pa) { return ps <= 4 && ps * pa * pa <= 144; }
+
 template <typename T, int PS, int PA>
 void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, int stage_mask, int level_lo,
                 int level_hi, hipStream_t s) {
@@ -2984,7 +2990,10 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   const int kind = p->opt.kernel;
   LevelPlan& lD = p->lev[D];
   const bool near = stage_mask & 1;
-  const bool grouped = R % MF_RG == 0;   // right-hand sides in groups of 16 per launch column
+  // right-hand sides in groups of 16 per launch column (the group kernels hold
+  // P x 16 values per block in LDS: orders up to P = 144)
+  constexpr bool kGroups = P <= 144;
+  const bool grouped = kGroups && R % MF_RG == 0;
   if (near) {
     StageTimer tm(p, s, IFGF_STAGE_NEAR);
     if (grouped)
@@ -3003,12 +3012,13 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     const T* Ma = (const T*)(Prec<T>::f32 ? p->Maf.p : p->Ma.p);
     if (lD.n_leaf > 0) {
       StageTimer tm(p, s, IFGF_STAGE_LEAF);
-      if (grouped)
-        k_leaf<T, PS, PA, MF_RG, false><<<dim3(lD.n_leaf, R / MF_RG), TPB, 0, s>>>(
-            lD.leaf_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
-            lD.centre.as<double>(), lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta,
-            kind, lD.Fn.as<cpx<T>>(), Ms, Ma, lD.Fc.as<cpx<T>>());
-      else if (R == 1)
+      if (grouped) {
+        if constexpr (kGroups)
+          k_leaf<T, PS, PA, MF_RG, false><<<dim3(lD.n_leaf, R / MF_RG), TPB, 0, s>>>(
+              lD.leaf_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
+              lD.centre.as<double>(), lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta,
+              kind, lD.Fn.as<cpx<T>>(), Ms, Ma, lD.Fc.as<cpx<T>>());
+      } else if (R == 1)
         k_leaf<T, PS, PA, 1, true><<<dim3(lD.n_leaf, 1), TPB, 0, s>>>(
             lD.leaf_work.as<int4>(), p->pts.as<double>(), p->nrm.as<double>(), a, R, lD.start.as<int>(),
             lD.centre.as<double>(), lD.slot_off.as<int>(), lD.rel_cone.as<int>(), lD.geom, p->cheb, p->k, p->eta,
@@ -3022,10 +3032,11 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     HIPCHK(hipGetLastError());
     if (lD.nrel > 0 && (grouped || R > 1)) {   // one RHS: done inside k_leaf
       StageTimer tm(p, s, IFGF_STAGE_COEFFS);
-      if (grouped)
-        k_coeffs_rg<T, PS, PA, MF_RG><<<dim3(lD.nrel, R / MF_RG), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), R, Ms, Ma,
-                                                                              lD.Fc.as<cpx<T>>());
-      else
+      if (grouped) {
+        if constexpr (kGroups)
+          k_coeffs_rg<T, PS, PA, MF_RG><<<dim3(lD.nrel, R / MF_RG), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), R, Ms, Ma,
+                                                                                lD.Fc.as<cpx<T>>());
+      } else
         k_coeffs<T, PS, PA, false><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma,
                                                                    lD.Fc.as<cpx<T>>());
       HIPCHK(hipGetLastError());
@@ -3050,7 +3061,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           continue;
         }
       }
-      if constexpr (Prec<T>::f32 && PS <= 4) {
+      if constexpr (Prec<T>::f32 && cone_major_order(PS, PA)) {
         if (R == 1 && lp.ntile > 0) {
           StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
           auto launch = [&](auto kern, int nw) {
@@ -3066,7 +3077,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           continue;
         }
       }
-      if constexpr (!Prec<T>::f32 && PS <= 4) {
+      if constexpr (!Prec<T>::f32 && cone_major_order(PS, PA)) {
         if (R == 1 && lp.ntile > 0) {
           StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
           auto launch = [&](auto kern, int nw) {
@@ -3114,19 +3125,21 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
       return;
     }
   }
-  if (R == 1 && p->opt.target_kernel != IFGF_TARGET_WAVE) {
-    StageTimer tm(p, s, IFGF_STAGE_TARGETS);
-    const int nlev = dlo <= dhi ? dhi - dlo + 1 : 0;
-    if ((size_t)nlev * n * sizeof(cpx<T>) > p->tpart.bytes) throw Error{IFGF_EINTERNAL, "target level buffer"};
-    cpx<T>* part = p->tpart.as<cpx<T>>();
-    if (nlev > 0) {
-      k_targets_rows<T, PS, PA><<<dim3(nblocks(n), nlev), TPB, 0, s>>>(p->pts.as<double>(), n, L, dlo, p->k, kind,
-                                                                       part, p->err.as<int>());
+  if constexpr (RowStage1<T, PS, PA>::ok) {   // orders with a generated row stage
+    if (R == 1 && p->opt.target_kernel != IFGF_TARGET_WAVE) {
+      StageTimer tm(p, s, IFGF_STAGE_TARGETS);
+      const int nlev = dlo <= dhi ? dhi - dlo + 1 : 0;
+      if ((size_t)nlev * n * sizeof(cpx<T>) > p->tpart.bytes) throw Error{IFGF_EINTERNAL, "target level buffer"};
+      cpx<T>* part = p->tpart.as<cpx<T>>();
+      if (nlev > 0) {
+        k_targets_rows<T, PS, PA><<<dim3(nblocks(n), nlev), TPB, 0, s>>>(p->pts.as<double>(), n, L, dlo, p->k,
+                                                                         kind, part, p->err.as<int>());
+        HIPCHK(hipGetLastError());
+      }
+      k_targets_sum<T><<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), uacc, near ? 1 : 0, part, nlev, dtype, u);
       HIPCHK(hipGetLastError());
+      return;
     }
-    k_targets_sum<T><<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), uacc, near ? 1 : 0, part, nlev, dtype, u);
-    HIPCHK(hipGetLastError());
-    return;
   }
   {
     StageTimer tm(p, s, IFGF_STAGE_TARGETS);
@@ -3676,20 +3689,38 @@ void batch_apply_impl(ifgf_batch_s* b, const void* const* sigma, void* const* u,
   HIPCHK(hipGetLastError());
 }
 
+// Interpolation orders (P_s, P_ang) compiled in: the ORDERS_ALL list in both
+// precisions (every formulation: node and cone-major upward pass, row and
+// wave targets, batched right-hand sides, ragged batch); the ORDERS_FP64 list
+// in FP64 only, for accuracy beyond FP32's reach (node upward pass, wave
+// targets, transposed apply; no ragged batch).
+#define IFGF_ORDERS_ALL(X) X(3, 5) X(4, 6)
+#define IFGF_ORDERS_FP64(X) X(8, 8)
+
 template <typename T>
 void dispatch_adjoint(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, int conj, hipStream_t s) {
-  int ps = p->opt.p_s, pa = p->opt.p_ang;
-  if (ps == 3 && pa == 5) return adjoint_impl<T, 3, 5>(p, v, out, R, dtype, conj, s);
-  if (ps == 4 && pa == 6) return adjoint_impl<T, 4, 6>(p, v, out, R, dtype, conj, s);
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+#define X(a, b) \
+  if (ps == a && pa == b) return adjoint_impl<T, a, b>(p, v, out, R, dtype, conj, s);
+  IFGF_ORDERS_ALL(X)
+  if constexpr (!Prec<T>::f32) {
+    IFGF_ORDERS_FP64(X)
+  }
+#undef X
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
 }
 
 template <typename T>
 void dispatch_apply(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, int stage_mask, int lo, int hi,
                     hipStream_t s) {
-  int ps = p->opt.p_s, pa = p->opt.p_ang;
-  if (ps == 3 && pa == 5) return apply_impl<T, 3, 5>(p, sigma, u, R, dtype, stage_mask, lo, hi, s);
-  if (ps == 4 && pa == 6) return apply_impl<T, 4, 6>(p, sigma, u, R, dtype, stage_mask, lo, hi, s);
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+#define X(a, b) \
+  if (ps == a && pa == b) return apply_impl<T, a, b>(p, sigma, u, R, dtype, stage_mask, lo, hi, s);
+  IFGF_ORDERS_ALL(X)
+  if constexpr (!Prec<T>::f32) {
+    IFGF_ORDERS_FP64(X)
+  }
+#undef X
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
 }
 
@@ -3733,13 +3764,30 @@ void build_ti_geo(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStrea
 int prop_chunk(int P) {
   if (P == 75) return PropShape<75>::CH;
   if (P == 144) return PropShape<144>::CH;
+  if (P == 512) return PropShape<512>::CH;
   return 1;
 }
 
-bool supported_order(int ps, int pa) { return (ps == 3 && pa == 5) || (ps == 4 && pa == 6); }
+static bool order_in_all(int ps, int pa) {
+#define X(a, b) \
+  if (ps == a && pa == b) return true;
+  IFGF_ORDERS_ALL(X)
+#undef X
+  return false;
+}
+
+bool supported_order(int ps, int pa, int precision) {
+  if (order_in_all(ps, pa)) return true;
+  if (precision != IFGF_PREC_FP64) return false;
+#define X(a, b) \
+  if (ps == a && pa == b) return true;
+  IFGF_ORDERS_FP64(X)
+#undef X
+  return false;
+}
 
 bool cone_prop_supported(const ifgf_plan_s* p) {
-  return p->opt.p_s <= 4 && p->opt.prop_kernel != IFGF_PROP_NODE && supported_order(p->opt.p_s, p->opt.p_ang);
+  return p->opt.p_s <= 4 && p->opt.prop_kernel != IFGF_PROP_NODE && order_in_all(p->opt.p_s, p->opt.p_ang);
 }
 
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask, int level_lo,
@@ -3762,6 +3810,7 @@ void run_batch_prepare(ifgf_batch_s* b) {
   ifgf_plan_s* p = b->plans[0];
   const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
   const int ps = p->opt.p_s, pa = p->opt.p_ang;
+  if (!order_in_all(ps, pa)) throw Error{IFGF_EUNSUPPORTED, "the ragged batch is not compiled for this order"};
   if (ps == 3 && pa == 5) return f32 ? batch_prepare_impl<float, 3, 5>(b) : batch_prepare_impl<double, 3, 5>(b);
   if (ps == 4 && pa == 6) return f32 ? batch_prepare_impl<float, 4, 6>(b) : batch_prepare_impl<double, 4, 6>(b);
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};

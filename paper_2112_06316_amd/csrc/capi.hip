@@ -148,7 +148,8 @@ ifgf_status ifgf_plan_create(ifgf_plan* out, int64_t n, const double* points, co
     if (o.target_kernel < IFGF_TARGET_AUTO || o.target_kernel > IFGF_TARGET_ROWS)
       throw Error{IFGF_EINVAL, "bad target_kernel"};
     if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
-    if (!supported_order(o.p_s, o.p_ang)) throw Error{IFGF_EUNSUPPORTED, "p_s/p_ang pair not compiled in"};
+    if (!supported_order(o.p_s, o.p_ang, o.precision))
+      throw Error{IFGF_EUNSUPPORTED, "p_s/p_ang pair not compiled in for this precision"};
     p = new ifgf_plan_s();
     p->n = n;
     p->k = k;

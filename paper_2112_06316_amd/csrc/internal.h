@@ -171,7 +171,7 @@ int* batch_static_counters(int device);
 // octant), computed on the GPU into p->lev[d].ti_geo.
 void build_ti_geo(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s);
 size_t ti_geo_bytes(int ps, int pa, bool f32);   // one (cone id, octant) record
-bool supported_order(int ps, int pa);
+bool supported_order(int ps, int pa, int precision);   // compiled in for this precision
 int prop_chunk(int P);
 bool cone_prop_supported(const ifgf_plan_s* p);
 

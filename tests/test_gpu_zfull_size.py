@@ -96,3 +96,32 @@ def test_sphere_128_wavelengths_sampled():
     err = float(np.linalg.norm(u[tg] - ref) / np.linalg.norm(ref))
     log(f"  rel l2 err = {err:.3e}")
     assert err < 1e-4
+
+
+@pytest.mark.timeout(600)
+def test_sphere_32_wavelengths_fp64_high_order_sampled():
+    # The FP64 form at (P_s, P_ang) = (8, 8), (n_S0, n_C0) = (1, 4) on the
+    # benchmark workload (N = 393,216, k = 64 pi, D = 7) against the FP64
+    # direct sum at 4,096 seeded targets: relative error at most 1e-6.
+    import time
+    wl = inputs.workload("sphere32")
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    sigma = inputs.random_density(len(p), seed=inputs.config_seed(2))
+    tg = inputs.sample_targets(len(p), 4096, seed=inputs.config_seed(2) + 100)
+    log("case sphere32 fp64 P=(8,8) n0=(1,4) sampled")
+    t0 = time.perf_counter()
+    plan = Plan(p, nr, w, k, k, depth=7, precision="fp64", p_s=8, p_ang=8, ns0=1, nc0=4)
+    torch.cuda.synchronize()
+    log(f"  plan {time.perf_counter() - t0:.2f} s, cones {plan.stats()['cones']}")
+    s = to_dev(sigma)
+    t0 = time.perf_counter()
+    u = plan.apply(s)
+    torch.cuda.synchronize()
+    log(f"  apply {time.perf_counter() - t0:.2f} s")
+    u = u.cpu().numpy()
+    assert plan.check() == 0
+    ref = direct.apply_c(p, nr, w, k, k, sigma, targets=tg)
+    err = float(np.linalg.norm(u[tg] - ref) / np.linalg.norm(ref))
+    log(f"  rel l2 err = {err:.3e}")
+    assert err <= 1e-6
