@@ -116,13 +116,52 @@ def measure_peaks(log):
     return out
 
 
+PEAK_FP64_VECTOR_TFLOPS = 78.6     # MI355X published dense FP64 vector rate
+
+
+def fp64_hi_entry(r, err, steps, n, D):
+    """The FP64 apply at (P_s, P_ang) = (8, 8): time, error and the roofline of
+    its dominant kernel (FP64 vector ALUs, 78.6 TFLOP/s)."""
+    st, prof = r["stats"], r["prof"]
+    P = 8 * 8 * 8
+    fi = interp_flops(8, 8)
+    work = {
+        "prop": sum(st["prop_evals"].values()) * fi,
+        "targets": sum(st["cousin_pairs"].values()) * fi,
+        "near": st["near_pairs"] * NEAR_FLOPS,
+        "leaf": (st["cones"][D] * P * (n / st["boxes"][D]) * LEAF_FLOPS + st["cones"][D] * coeff_flops(8, 8))
+        if D >= 3 else 0,
+    }
+    stages = {}
+    for name, (ms, cnt) in prof.items():
+        e = {"ms_per_apply": ms / steps, "launches_per_apply": cnt / steps}
+        if name in work and ms > 0:
+            e["achieved_tflops"] = work[name] / (ms / steps * 1e-3) / 1e12
+        stages[name] = e
+    roof = None
+    cand = [s_ for s_ in prof if s_ in work and prof[s_][0] > 0]
+    if cand:
+        dom = max(cand, key=lambda s_: prof[s_][0])
+        ms_dom, cnt_dom = prof[dom]
+        per_launch = work[dom] / (cnt_dom / steps)
+        ach = per_launch / (ms_dom / cnt_dom * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP64_VECTOR_TFLOPS, "kernel": KERNEL_OF_STAGE.get(dom, dom), "stage": dom,
+                "avg_launch_ms": ms_dom / cnt_dom, "launches_per_apply": cnt_dom / steps,
+                "algorithmic_flops_per_launch": per_launch}
+    return {"ms_per_step": r["wall"] * 1e3 / steps, "event_ms_median": r["ev_median"], "event_ms_min": r["ev_min"],
+            "rel_err": err, "setting": "P=(8,8,8), cones (n_s0,n_C0)=(1,4), FP64 throughout",
+            "plan_create_s": r["t_plan"], "stages": stages, "roofline": roof,
+            "cones": st["cones"], "device_bytes": st["device_bytes"], "consistency_flags": r["flags"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sphere32")
-    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--fp64-steps", type=int, default=10)
     ap.add_argument("--targets", type=int, default=4096, help="sampled targets for the error and the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--p-s", type=int, default=4)
@@ -160,10 +199,10 @@ def main():
     opts = dict(p_s=args.p_s, p_ang=args.p_ang, ns0=args.ns0, nc0=args.nc0, depth=D)
     log(f"workload {args.workload}: N={n} k={k:.4f} D={D} opts={opts}")
 
-    def run(precision, steps, warmup, profile):
+    def run(precision, steps, warmup, profile, o=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan = Plan(p, nr, w, k, eta, precision=precision, **opts)
+        plan = Plan(p, nr, w, k, eta, precision=precision, **(o or opts))
         torch.cuda.synchronize()
         t_plan = time.perf_counter() - t0
         log(f"{precision}: plan built in {t_plan:.3f} s")
@@ -231,9 +270,16 @@ def main():
         del v, plan
     r32.pop("plan")
     r64 = run("fp64", args.fp64_steps, 2, False) if args.fp64_steps > 0 else None
+    if r64 is not None:
+        r64.pop("plan")
+    # the FP64 form at the order that reaches 1e-6: (P_s, P_ang) = (8, 8), cones (1, 4)
+    hi_opts = dict(p_s=8, p_ang=8, ns0=1, nc0=4, depth=D)
+    r64h = run("fp64", args.fp64_steps, 2, True, hi_opts) if args.fp64_steps > 0 else None
+    if r64h is not None:
+        r64h.pop("plan")
 
     # ---- oracle: error and CPU baseline on the sampled targets ----------------
-    err32 = err64 = None
+    err32 = err64 = err64h = None
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import direct
@@ -245,6 +291,8 @@ def main():
         err32 = float(np.linalg.norm(r32["u"][tg] - ref) / np.linalg.norm(ref))
         if r64 is not None:
             err64 = float(np.linalg.norm(r64["u"][tg] - ref) / np.linalg.norm(ref))
+        if r64h is not None:
+            err64h = float(np.linalg.norm(r64h["u"][tg] - ref) / np.linalg.norm(ref))
         cpu = {
             "value": t_cpu * n / len(tg), "unit": "s", "cores": direct.num_threads(), "kind": "oracle",
             "sample": (f"FP64 direct sum (C/OpenMP) at {len(tg)} seeded targets x {n} sources = "
@@ -360,7 +408,24 @@ def main():
                               "frac": (ach / 157.3) if ach else None, "kernel": "k_prop_mfma_cone",
                               "algorithmic_flops_per_apply": flops_prop},
         }
-        del planb, Ub, Sb_d
+        # the same workload one right-hand side at a time (the single-RHS
+        # kernels), for the gain of the batched contraction per RHS
+        plan1 = Plan(pb, nb_, wb_, wb["k"], wb["eta"], precision="fp32", **dict(opts, depth=wb["depth"]))
+        s1 = Sb_d[:, 0].contiguous()
+        u1 = torch.empty_like(s1)
+        for _ in range(3):
+            plan1.apply(s1, out=u1[:, None])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps1 = 20
+        for _ in range(reps1):
+            plan1.apply(s1, out=u1[:, None])
+        torch.cuda.synchronize()
+        ms1 = (time.perf_counter() - t0) * 1e3 / reps1
+        batched["single_rhs_ms_per_apply"] = ms1
+        batched["gain_per_rhs_vs_single"] = ms1 / batched["ms_per_rhs"]
+        log(f"batched: single-RHS apply {ms1:.3f} ms, per-RHS gain {ms1 / batched['ms_per_rhs']:.2f}x")
+        del planb, Ub, Sb_d, plan1
 
     # ---- ragged batch: 8 geometries in one launch vs 8 separate applies ----------
     ragged = None
@@ -461,8 +526,12 @@ def main():
     out["batched"] = batched
     out["ragged"] = ragged
     if r64 is not None:
-        out["fp64"] = {"ms_per_step": r64["wall"] * 1e3 / args.fp64_steps, "rel_err": err64,
-                       "plan_create_s": r64["t_plan"], "consistency_flags": r64["flags"]}
+        out["fp64"] = {"ms_per_step": r64["wall"] * 1e3 / args.fp64_steps, "event_ms_median": r64["ev_median"],
+                       "event_ms_min": r64["ev_min"], "rel_err": err64, "plan_create_s": r64["t_plan"],
+                       "setting": f"P=({ps},{pa},{pa}), cones ({args.ns0},{args.nc0}), as the FP32 apply",
+                       "consistency_flags": r64["flags"]}
+    if r64h is not None:
+        out["fp64_1e-6"] = fp64_hi_entry(r64h, err64h, args.fp64_steps, n, D)
     print(json.dumps(out), flush=True)
 
 
