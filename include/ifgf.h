@@ -281,6 +281,45 @@ ifgf_status ifgf_plan_read_profile(ifgf_plan p, double *ms, int64_t *launches);
 void ifgf_plan_destroy(ifgf_plan p);
 
 /*
+ * GMRES solution of the combined-field integral equation (Sec. 2.2, eq.
+ * CombLayIE, solved in Sec. 5 with complex GMRES):
+ *
+ *     (alpha I + A) sigma = f,
+ *
+ * where A is the plan's operator (the sum of ifgf_apply, without singular
+ * corrections), alpha = 1/2 and f = -u^i for eq. CombLayIE.  Restarted
+ * GMRES(restart) with classical Gram-Schmidt applied twice.  The Krylov
+ * vectors, inner products, norms and updates are complex FP64 whatever the
+ * plan's precision (the applies take and return complex128); inner products
+ * are reduced in a fixed order, so a solve is deterministic.
+ *
+ * ifgf_gmres_solve: f [device] n complex128 right-hand side, sigma [device]
+ *   n complex128 solution, caller's point order; with use_guess = 1 sigma
+ *   holds the initial iterate on entry, else it starts from zero.  f and
+ *   sigma must not alias.  iters [host]: operator applies of the Krylov
+ *   iterations; rel_res [host]: ||f - (alpha I + A) sigma|| / ||f|| of the
+ *   returned sigma (recomputed from sigma, not the recurrence); history
+ *   [host, may be NULL]: max_iter + 1 doubles, the relative residual before
+ *   the first iteration and the recurrence estimate after each.  Iterates
+ *   until the residual is at most tol or max_iter iterations have run.  The
+ *   library allocates (restart + 2) n complex128 values of workspace for
+ *   the call.  Enqueues on `stream` and synchronizes it many times (the
+ *   Hessenberg problem is solved on the host); returns when sigma is
+ *   written.  Errors: EINVAL, EBUSY, ENOMEM, EHIP.
+ */
+typedef struct {
+    int32_t restart;        /* Krylov dimension per cycle; default 30                    */
+    int32_t max_iter;       /* maximum iterations (operator applies); default 300         */
+    double tol;             /* relative residual target; default 1e-4 (Sec. 5.1)          */
+    double alpha_re;        /* identity coefficient alpha; default 1/2 (eq. CombLayIE)    */
+    double alpha_im;
+    int32_t use_guess;      /* 1: start from sigma's content; default 0 (zero)            */
+} ifgf_gmres_options;
+void ifgf_gmres_options_default(ifgf_gmres_options *o);
+ifgf_status ifgf_gmres_solve(ifgf_plan p, const void *f, void *sigma, const ifgf_gmres_options *opt,
+                             int32_t *iters, double *rel_res, double *history, void *stream);
+
+/*
  * Ragged batch: the forward apply (as ifgf_apply, one right-hand side) of
  * several plans - different geometries, sizes, depths and wavenumbers - in
  * ONE kernel launch (one work-group per queue item, not a persistent

@@ -56,6 +56,17 @@ class Stats(ctypes.Structure):
     ]
 
 
+class GmresOptions(ctypes.Structure):
+    _fields_ = [
+        ("restart", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("alpha_re", ctypes.c_double),
+        ("alpha_im", ctypes.c_double),
+        ("use_guess", ctypes.c_int32),
+    ]
+
+
 VP = ctypes.c_void_p
 I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 
@@ -76,6 +87,9 @@ SIGNATURES = {
     "ifgf_plan_set_profiling": (I32, [VP, I32]),
     "ifgf_plan_read_profile": (I32, [VP, VP, VP]),
     "ifgf_plan_destroy": (None, [VP]),
+    "ifgf_gmres_options_default": (None, [ctypes.POINTER(GmresOptions)]),
+    "ifgf_gmres_solve": (I32, [VP, VP, VP, ctypes.POINTER(GmresOptions), ctypes.POINTER(I32),
+                               ctypes.POINTER(F64), VP, VP]),
     "ifgf_batch_create": (I32, [ctypes.POINTER(VP), I32, ctypes.POINTER(VP)]),
     "ifgf_batch_apply": (I32, [VP, ctypes.POINTER(VP), ctypes.POINTER(VP), I32, VP]),
     "ifgf_batch_apply_noalloc": (I32, [VP, ctypes.POINTER(VP), ctypes.POINTER(VP), I32, VP]),

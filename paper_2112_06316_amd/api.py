@@ -155,6 +155,33 @@ class Plan:
         L.check(st, "ifgf_apply_adjoint")
         return out[:, 0] if squeeze else out
 
+    def solve(self, f, tol=1e-4, restart=30, max_iter=300, alpha=0.5, x0=None):
+        """GMRES solution of (alpha I + A) sigma = f (eq. CombLayIE with alpha = 1/2,
+        f = -u^i).  f: (n,) complex; x0: optional initial iterate.  Returns
+        (sigma complex128, info) with info = {iters, rel_res, history}."""
+        fx = torch.as_tensor(f)
+        if not torch.is_complex(fx) or fx.dim() != 1 or fx.shape[0] != self.n:
+            raise ValueError(f"expected a complex ({self.n},) right-hand side")
+        fx = fx.to(self.device, torch.complex128).contiguous()
+        if x0 is None:
+            x = torch.empty_like(fx)
+        else:
+            x = torch.as_tensor(x0).to(self.device, torch.complex128).clone().contiguous()
+            if x.shape != fx.shape:
+                raise ValueError("x0 must have the shape of f")
+        o = L.GmresOptions()
+        self._lib.ifgf_gmres_options_default(ctypes.byref(o))
+        o.restart, o.max_iter, o.tol = int(restart), int(max_iter), float(tol)
+        a = complex(alpha)
+        o.alpha_re, o.alpha_im = a.real, a.imag
+        o.use_guess = 0 if x0 is None else 1
+        iters, res = ctypes.c_int32(0), ctypes.c_double(0.0)
+        hist = (ctypes.c_double * (int(max_iter) + 1))()
+        st = self._lib.ifgf_gmres_solve(self._h, fx.data_ptr(), x.data_ptr(), ctypes.byref(o), ctypes.byref(iters),
+                                        ctypes.byref(res), hist, _stream_ptr(self.device))
+        L.check(st, "ifgf_gmres_solve")
+        return x, {"iters": iters.value, "rel_res": res.value, "history": list(hist[:iters.value + 1])}
+
     # -- introspection -------------------------------------------------------
     def stats(self) -> dict:
         s = L.Stats()

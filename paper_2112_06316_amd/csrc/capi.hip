@@ -196,6 +196,35 @@ ifgf_status ifgf_apply_adjoint(ifgf_plan p, const void* v, void* out, int32_t nr
   });
 }
 
+void ifgf_gmres_options_default(ifgf_gmres_options* o) {
+  if (!o) return;
+  o->restart = 30;
+  o->max_iter = 300;
+  o->tol = 1e-4;
+  o->alpha_re = 0.5;
+  o->alpha_im = 0.0;
+  o->use_guess = 0;
+}
+
+ifgf_status ifgf_gmres_solve(ifgf_plan p, const void* f, void* sigma, const ifgf_gmres_options* opt, int32_t* iters,
+                             double* rel_res, double* history, void* stream) {
+  return guarded([&] {
+    if (!p || !f || !sigma || !iters || !rel_res) throw Error{IFGF_EINVAL, "null pointer argument"};
+    if (f == sigma) throw Error{IFGF_EINVAL, "f and sigma alias"};
+    ifgf_gmres_options o;
+    ifgf_gmres_options_default(&o);
+    if (opt) o = *opt;
+    if (o.restart < 1 || o.restart > 1000) throw Error{IFGF_EINVAL, "restart out of range (1..1000)"};
+    if (o.max_iter < 1) throw Error{IFGF_EINVAL, "max_iter must be >= 1"};
+    if (!(o.tol >= 0.0) || !std::isfinite(o.tol)) throw Error{IFGF_EINVAL, "tol must be finite and >= 0"};
+    if (!std::isfinite(o.alpha_re) || !std::isfinite(o.alpha_im)) throw Error{IFGF_EINVAL, "alpha must be finite"};
+    BusyGuard g(p);
+    if (!g.ok) throw Error{IFGF_EBUSY, "another apply on this plan is being enqueued"};
+    run_gmres(p, f, sigma, o, iters, rel_res, history, (hipStream_t)stream);
+    p->last_rhs = 1;
+  });
+}
+
 ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
   return guarded([&] {
     if (!p || !st) throw Error{IFGF_EINVAL, "null pointer argument"};

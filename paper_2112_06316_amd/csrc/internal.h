@@ -159,6 +159,10 @@ void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, 
                int level_lo, int level_hi, hipStream_t s);
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
 
+// solve.hip: restarted GMRES on (alpha I + A) sigma = f (complex128 device vectors).
+void run_gmres(ifgf_plan_s* p, const void* f, void* sigma, const ifgf_gmres_options& o, int32_t* iters,
+               double* rel_res, double* history, hipStream_t s);
+
 void run_batch_prepare(ifgf_batch_s* b);
 // ctr: the launch's completion counters (b->nctr ints); nullptr = the batch's own buffer.
 void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, int dtype, int* ctr, hipStream_t s);
