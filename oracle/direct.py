@@ -142,3 +142,23 @@ def dense_np(points, normals, weights, k, eta, kind=0):
         K = kernel_np(pts[:, None, :], pts[None, :, :], nrm[None, :, :], k, eta, kind)
     K[np.arange(n), np.arange(n)] = 0.0
     return K * w[None, :]
+
+
+def far_field_np(points, normals, weights, k, eta, sigma, dirs, block=512):
+    """Far-field pattern of the combined-field potential with density sigma
+    (Sec. 5, eq. FarField, coupling gamma = eta):
+
+        u_inf(xh) = 1/(4 pi) sum_j w_j sigma_j exp(-i k xh.y_j) (-i k <xh, n_j> - i eta)
+
+    for unit directions dirs (m, 3); the derivative along n_j of
+    exp(-i k xh.y) is -i k <xh, n_j> exp(-i k xh.y)."""
+    pts = np.asarray(points, dtype=np.float64)
+    nrm = np.asarray(normals, dtype=np.float64)
+    a = np.asarray(weights, dtype=np.float64) * np.asarray(sigma, dtype=np.complex128)
+    xh = np.asarray(dirs, dtype=np.float64)
+    out = np.zeros(xh.shape[0], dtype=np.complex128)
+    for b0 in range(0, xh.shape[0], block):
+        d = xh[b0:b0 + block]
+        ph = np.exp(-1j * k * (d @ pts.T))
+        out[b0:b0 + block] = (ph * (-1j * k * (d @ nrm.T) - 1j * eta)) @ a / (4.0 * np.pi)
+    return out

@@ -362,9 +362,12 @@ class Plan:
     kind: int = 0
 
 
-def relevant_cones(tree: Tree, counts: dict, ps: int, pa: int) -> dict:
+def relevant_cones(tree: Tree, counts: dict, ps: int, pa: int, far_field: bool = False) -> dict:
     """Top-down from d = 3: cones hit by cousin points, and for d > 3 also by
-    the interpolation nodes of the parent's relevant cones."""
+    the interpolation nodes of the parent's relevant cones.  With far_field,
+    every level-3 cone whose radial interval starts at s = 0 (x at infinity,
+    any direction) is relevant too, and so, through the node rule, is what
+    those cones need below."""
     out = {}
     D = tree.D
     for d in range(3, D + 1):
@@ -373,6 +376,8 @@ def relevant_cones(tree: Tree, counts: dict, ps: int, pa: int) -> dict:
         per_box = []
         for b in range(lev.coords.shape[0]):
             hit = set()
+            if far_field and d == 3:
+                hit.update(range(nc * 2 * nc))      # i_s = 0, every (i_theta, i_phi)
             y0 = lev.centre[b]
             for c in lev.cousins[b]:
                 x = tree.points[lev.start[c]:lev.start[c + 1]]
@@ -394,10 +399,10 @@ def relevant_cones(tree: Tree, counts: dict, ps: int, pa: int) -> dict:
     return out
 
 
-def make_plan(points, normals, weights, k, eta, D, ps=3, pa=5, ns0=1, nc0=2, kind=0) -> Plan:
+def make_plan(points, normals, weights, k, eta, D, ps=3, pa=5, ns0=1, nc0=2, kind=0, far_field=False) -> Plan:
     tree = build_tree(points, D)
     counts = cone_counts(k, tree.L, D, ns0, nc0)
-    cones = relevant_cones(tree, counts, ps, pa) if D >= 3 else {}
+    cones = relevant_cones(tree, counts, ps, pa, far_field) if D >= 3 else {}
     return Plan(tree=tree, k=float(k), eta=float(eta), ps=ps, pa=pa, counts=counts, cones=cones,
                 normals=np.asarray(normals, dtype=np.float64)[tree.perm],
                 weights=np.asarray(weights, dtype=np.float64)[tree.perm], kind=kind)
@@ -511,6 +516,45 @@ def apply(plan: Plan, sigma: np.ndarray, stages: bool = False):
     if stages:
         return out, info
     return out
+
+
+def far_field(plan: Plan, sigma: np.ndarray, dirs: np.ndarray) -> np.ndarray:
+    """Far-field pattern (Sec. 5, eq. FarField) from the level-3 interpolants.
+
+    For x = R xh with R -> infinity, |x - y_B| = R - xh.y_B + O(1/R) and
+    s = h / |x - y_B| -> 0, so the field of box B's sources tends to
+    exp(i k R) / (4 pi R) exp(-i k xh.y_B) F_B(0, theta(xh), phi(xh)); summed
+    over the level-3 boxes (which hold every source):
+        u_inf(xh) = 1/(4 pi) sum_B exp(-i k xh.y_B) F_B(0, xh).
+    The plan must have been made with far_field=True (the s = 0 cones are then
+    relevant).  For D <= 2 there is no interpolant and the plain sum over the
+    points is returned."""
+    xh = np.asarray(dirs, dtype=np.float64)
+    t = plan.tree
+    perm = t.perm
+    a = plan.weights * np.asarray(sigma, dtype=np.complex128)[perm]
+    if t.D < 3:
+        ph = np.exp(-1j * plan.k * (xh @ t.points.T))
+        return (ph * (-1j * plan.k * (xh @ plan.normals.T) - 1j * plan.eta)) @ a / (4.0 * math.pi)
+    _, info = apply(plan, sigma, stages=True)
+    lev = t.levels[3]
+    ns, nc = plan.counts[3]
+    theta = np.arctan2(np.sqrt(xh[:, 0] ** 2 + xh[:, 1] ** 2), xh[:, 2])
+    phi = np.arctan2(xh[:, 1], xh[:, 0])
+    phi = np.where(phi < 0.0, phi + 2.0 * math.pi, phi)
+    cid, cts, ctt, ctp = cone_of(np.zeros(xh.shape[0]), theta, phi, ns, nc)   # s = 0: i_s = 0, t_s = -1
+    out = np.zeros(xh.shape[0], dtype=np.complex128)
+    for b in range(lev.coords.shape[0]):
+        cones = plan.cones[3][b]
+        if cones.size == 0:
+            continue
+        coef = cheb_coeffs_3d(info["F_nodes"][3][b])
+        pos = np.searchsorted(cones, cid)
+        if np.any(pos >= cones.size) or np.any(cones[np.minimum(pos, cones.size - 1)] != cid):
+            raise AssertionError("far-field direction outside the relevant cones (plan without far_field?)")
+        val = cheb_eval_3d(coef[pos], cts, ctt, ctp)
+        out += np.exp(-1j * plan.k * (xh @ lev.centre[b])) * val
+    return out / (4.0 * math.pi)
 
 
 def tree_pairs_count(tree: Tree):

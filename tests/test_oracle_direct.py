@@ -178,3 +178,42 @@ def test_surfaces():
     # normal orthogonal to the surface tangent: grad of x^2/a^2 + ... is parallel to n
     g = pe / np.array([1.0, 4.0, 9.0])
     assert np.allclose(np.cross(g, ne), 0.0, atol=1e-12)
+
+
+def test_far_field_pattern_is_the_limit_of_the_field():
+    # u(R xh) = e^{ikR} / R (u_inf(xh) + O(1/R)) for the potential of eq.
+    # CombinedLayer evaluated off the surface by the plain kernel sum: the
+    # far-field sum is pinned to the field itself, not to its own formula.
+    from paper_2112_06316_amd import inputs
+    p, nr, w = inputs.cubed_sphere(4)
+    k, eta = 7.0, 3.0
+    sig = inputs.random_density(len(p), seed=5)
+    xh = np.array([[0.0, 0.6, 0.8], [1.0, 0.0, 0.0], [-2.0, 1.0, 2.0]])
+    xh /= np.linalg.norm(xh, axis=1, keepdims=True)
+    uinf = direct.far_field_np(p, nr, w, k, eta, sig, xh)
+    errs = []
+    for R in (1e3, 1e4):
+        x = R * xh
+        u = np.array([np.sum(w * sig * direct.kernel_np(x[i], p, nr, k, eta)) for i in range(len(xh))])
+        errs.append(np.abs(R * np.exp(-1j * k * R) * u - uinf).max() / np.abs(uinf).max())
+    assert errs[1] < 1e-3 and errs[0] / errs[1] > 5        # O(1/R)
+
+
+def test_far_field_pattern_closed_forms():
+    # one source at the origin with normal n: u_inf = w s (-i k <xh, n> - i eta) / (4 pi);
+    # a translation y -> y + c multiplies u_inf(xh) by exp(-i k xh.c).
+    k, eta = 5.0, 2.0
+    n0 = np.array([[0.0, 0.0, 1.0]])
+    xh = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, -0.6, 0.8]])
+    u = direct.far_field_np(np.zeros((1, 3)), n0, np.array([2.0]), k, eta, np.array([1.5 - 0.5j]), xh)
+    want = 2.0 * (1.5 - 0.5j) * (-1j * k * xh[:, 2] - 1j * eta) / (4 * np.pi)
+    assert np.allclose(u, want, rtol=0, atol=1e-15)
+    rng = np.random.default_rng(9)
+    p = rng.standard_normal((20, 3))
+    nr = rng.standard_normal((20, 3))
+    w = rng.random(20)
+    s = rng.standard_normal(20) + 1j * rng.standard_normal(20)
+    c = np.array([0.3, -1.2, 0.7])
+    u0 = direct.far_field_np(p, nr, w, k, eta, s, xh)
+    u1 = direct.far_field_np(p + c, nr, w, k, eta, s, xh)
+    assert np.allclose(u1, u0 * np.exp(-1j * k * xh @ c), rtol=1e-13, atol=0)

@@ -346,3 +346,32 @@ def test_relevant_counts_match_independent_estimate_16_wavelengths():
     got = [sum(c.size for c in cones[d]) for d in range(3, 7)]
     for g, e in zip(got, [16.8e3, 40.8e3, 44.8e3, 34.7e3]):
         assert abs(g - e) <= 0.005 * e + 50
+
+
+def test_far_field_from_level3_interpolants():
+    # The IFGF far field (level-3 interpolants at s = 0) agrees with the
+    # plain far-field sum of eq. FarField to the interpolation accuracy, and
+    # exactly (to rounding) when D <= 2 leaves no interpolation; the far-field
+    # cones add to, and never remove, the relevant cones of the plain plan.
+    p, nr, w = inputs.cubed_sphere(12)
+    k = 4 * np.pi
+    sig = inputs.random_density(len(p), seed=12)
+    rng = np.random.default_rng(3)
+    dirs = rng.standard_normal((40, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    dirs[0] = [0.0, 0.0, 1.0]                     # the poles, where theta's interval is closed
+    dirs[1] = [0.0, 0.0, -1.0]
+    ref = direct.far_field_np(p, nr, w, k, k, sig, dirs)
+    plan = R.make_plan(p, nr, w, k, k, 4, ps=4, pa=6, ns0=2, nc0=4, far_field=True)
+    got = R.far_field(plan, sig, dirs)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err < 1e-4, err
+    plain = R.make_plan(p, nr, w, k, k, 4, ps=4, pa=6, ns0=2, nc0=4)
+    for d in (3, 4):
+        for b in range(len(plain.cones[d])):
+            assert set(plain.cones[d][b].tolist()) <= set(plan.cones[d][b].tolist())
+    assert sum(c.size for c in plan.cones[3]) > sum(c.size for c in plain.cones[3])
+    shallow = R.make_plan(p, nr, w, k, k, 2, far_field=True)
+    assert np.allclose(R.far_field(shallow, sig, dirs), ref, rtol=1e-12, atol=1e-14)
+    with pytest.raises(AssertionError):             # the plain plan lacks the s = 0 cones
+        R.far_field(plain, sig, dirs)
