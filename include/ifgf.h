@@ -72,6 +72,9 @@ enum { IFGF_C64 = 0, IFGF_C128 = 1 };
 enum { IFGF_KERNEL_COMBINED = 0, IFGF_KERNEL_CONSTANT = 1 };
 
 typedef struct {
+    /* Compiled orders (p_s, p_ang): (3, 5) and (4, 6) in both precisions; (8, 8)
+       with IFGF_PREC_FP64 only (relative error about 4e-7, the FP64 accuracy
+       setting, with ns0 = 1, nc0 = 4).  Others return IFGF_EUNSUPPORTED.           */
     int32_t p_s;            /* Chebyshev points per cone segment along s (paper P_s); default 4 */
     int32_t p_ang;          /* ... along theta and along phi (paper P_ang); default 6      */
     int32_t ns0;            /* radial cone intervals at the finest level (paper n_S,0); default 2  */
@@ -89,6 +92,12 @@ typedef struct {
     int32_t target_kernel;  /* cousin-target stage with one right-hand side:
                                IFGF_TARGET_AUTO (default), IFGF_TARGET_WAVE or
                                IFGF_TARGET_ROWS (below)                                    */
+    int32_t far_field;      /* 1: also make the far-field cones relevant - every level-3
+                               cone whose radial interval starts at s = 0 (x at infinity,
+                               any direction) and, by eq. RelevantCones' node rule, what
+                               they need at the finer levels - so that ifgf_far_field can
+                               evaluate the far-field pattern; adds up to about one cone
+                               per angular interval and box at every level.  Default 0.  */
 } ifgf_options;
 
 /* Upward-pass formulation (nrhs = 1, FP32 or FP64; other nrhs always use
@@ -246,8 +255,9 @@ ifgf_status ifgf_apply_stages(ifgf_plan p, const void *sigma, void *u, int32_t n
 /*
  * Device-side consistency flags accumulated since the plan was built:
  * bit 1 = an upward-pass node fell outside the relevant cones of a child,
- * bit 2 = a cousin point fell outside the relevant cones of a box.  Both
- * mean a plan/apply mismatch and are 0 in a correct build.  flags: [host].
+ * bit 2 = a cousin point fell outside the relevant cones of a box,
+ * bit 3 = a far-field direction fell outside the level-3 relevant cones.
+ * All mean a plan/apply mismatch and are 0 in a correct build.  flags: [host].
  * Synchronizes the device.
  */
 ifgf_status ifgf_plan_check(ifgf_plan p, int32_t *flags);
@@ -279,6 +289,31 @@ ifgf_status ifgf_plan_read_profile(ifgf_plan p, double *ms, int64_t *launches);
 /* Release the plan and its device memory (after its work has completed).
  * NULL is ignored. */
 void ifgf_plan_destroy(ifgf_plan p);
+
+/*
+ * Far-field pattern (Sec. 5, eq. FarField) of the combined-field potential
+ * (eq. CombinedLayer, coupling eta) with density sigma:
+ *
+ *   u_inf(xh) = 1/(4 pi) sum_j w_j sigma_j exp(-i k xh.x_j) (-i k <xh, nu_j> - i eta),
+ *
+ * through the plan's tree: the leaf factors and the upward pass run as in
+ * ifgf_apply, and since for x = R xh, R -> infinity, s = h / |x - y_B| -> 0
+ * and |x - y_B| = R - xh.y_B + O(1/R), the field of level-3 box B tends to
+ * exp(ikR)/(4 pi R) exp(-ik xh.y_B) F_B(0, xh):
+ *
+ *   u_inf(xh) = 1/(4 pi) sum_B exp(-ik xh.y_B) F_B(0, theta(xh), phi(xh)),
+ *
+ * with F_B's interpolant taken at s = 0 (FP64 phase and box sum).  The plan
+ * must have been created with far_field = 1 (EINVAL otherwise), except for
+ * D <= 2, where the sum over the points is evaluated directly (exact).
+ * sigma [device] n x 1 complex of `dtype`, caller's order; dirs [device]
+ * ndir x 3 float64 unit vectors (used as given); uinf [device] ndir complex
+ * of `dtype`.  Allocates a workspace of n complex128 values for the call and
+ * synchronizes `stream` before returning.  Errors: EINVAL, EBUSY, ENOMEM,
+ * EUNSUPPORTED, EHIP.
+ */
+ifgf_status ifgf_far_field(ifgf_plan p, const void *sigma, int64_t ndir, const double *dirs, void *uinf,
+                           int32_t dtype, void *stream);
 
 /*
  * GMRES solution of the combined-field integral equation (Sec. 2.2, eq.

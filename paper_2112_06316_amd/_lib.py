@@ -32,6 +32,7 @@ class Options(ctypes.Structure):
         ("kernel", ctypes.c_int32),
         ("prop_kernel", ctypes.c_int32),
         ("target_kernel", ctypes.c_int32),
+        ("far_field", ctypes.c_int32),
     ]
 
 
@@ -87,6 +88,7 @@ SIGNATURES = {
     "ifgf_plan_set_profiling": (I32, [VP, I32]),
     "ifgf_plan_read_profile": (I32, [VP, VP, VP]),
     "ifgf_plan_destroy": (None, [VP]),
+    "ifgf_far_field": (I32, [VP, VP, I64, VP, VP, I32, VP]),
     "ifgf_gmres_options_default": (None, [ctypes.POINTER(GmresOptions)]),
     "ifgf_gmres_solve": (I32, [VP, VP, VP, ctypes.POINTER(GmresOptions), ctypes.POINTER(I32),
                                ctypes.POINTER(F64), VP, VP]),

@@ -72,7 +72,7 @@ class Plan:
 
     def __init__(self, points, normals, weights, k, eta, *, p_s=4, p_ang=6, ns0=2, nc0=4, depth=0,
                  leaf_h_lambda=0.5, precision="fp32", max_rhs=1, kernel="combined", prop_kernel="auto",
-                 target_kernel="auto", device="cuda"):
+                 target_kernel="auto", far_field=False, device="cuda"):
         lib = L.load()
         self._lib = lib
         self.device = torch.device(device)
@@ -94,6 +94,7 @@ class Plan:
         o.kernel = _KERNEL[kernel]
         o.prop_kernel = _PROP[prop_kernel]
         o.target_kernel = _TARGET[target_kernel]
+        o.far_field = 1 if far_field else 0
         self.options = o
         h = ctypes.c_void_p()
         st = lib.ifgf_plan_create(ctypes.byref(h), n, pts.data_ptr(), nrm.data_ptr(), w.data_ptr(),
@@ -154,6 +155,19 @@ class Plan:
                                           1 if conjugate else 0, _stream_ptr(self.device))
         L.check(st, "ifgf_apply_adjoint")
         return out[:, 0] if squeeze else out
+
+    def far_field(self, sigma, dirs):
+        """Far-field pattern u_inf at unit directions dirs (m, 3) (eq. FarField),
+        through the tree (plan created with far_field=True unless depth <= 2)."""
+        s, squeeze, dtype = self._prep(sigma)
+        if s.shape[1] != 1:
+            raise ValueError("one density")
+        d = _dev_f64(dirs, self.device, (int(np.shape(dirs)[0]), 3))
+        out = torch.empty(d.shape[0], dtype=s.dtype, device=self.device)
+        st = self._lib.ifgf_far_field(self._h, s.data_ptr(), d.shape[0], d.data_ptr(), out.data_ptr(), dtype,
+                                      _stream_ptr(self.device))
+        L.check(st, "ifgf_far_field")
+        return out
 
     def solve(self, f, tol=1e-4, restart=30, max_iter=300, alpha=0.5, x0=None):
         """GMRES solution of (alpha I + A) sigma = f (eq. CombLayIE with alpha = 1/2,

@@ -2967,6 +2967,116 @@ __global__ __launch_bounds__(TPB) void k_adj_out(const cpx<T>* __restrict__ g, c
 }
 
 // ---------------------------------------------------------------------------
+// Far-field pattern (Sec. 5, eq. FarField).  For x = R xh with R -> inf,
+// |x - y_B| = R - xh.y_B + O(1/R) and s = h / |x - y_B| -> 0: the field of
+// level-3 box B tends to exp(ikR)/(4 pi R) exp(-ik xh.y_B) F_B(0, xh), so
+//     u_inf(xh) = 1/(4 pi) sum_B exp(-ik xh.y_B) F_B(0, theta(xh), phi(xh)),
+// F_B's interpolant taken at the left end (t_s = -1) of the first radial
+// interval of the cone holding xh's angles.  One wave per direction, one
+// lane per level-3 box (at most 4^3 = 64); the phase and the sum over boxes
+// in FP64.
+// ---------------------------------------------------------------------------
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_far_field(const double* __restrict__ dirs, int64_t ndir, int nb,
+                                                   const double* __restrict__ centre, const int* __restrict__ slot,
+                                                   const cpx<T>* __restrict__ Fc, LevelGeom g, double k, int dtype,
+                                                   void* __restrict__ out, int* __restrict__ err) {
+  constexpr int P = PS * PA * PA;
+  const int64_t dr = ((int64_t)blockIdx.x * TPB + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (dr >= ndir) return;   // wave-uniform
+  const double xh0 = dirs[3 * dr], xh1 = dirs[3 * dr + 1], xh2 = dirs[3 * dr + 2];
+  const Loc loc = locate64(xh0, xh1, xh2, 0.0, g);
+  double re = 0.0, im = 0.0;
+  if (lane < nb) {
+    const int sl = slot[(int64_t)lane * g.ncone + loc.cid];
+    if (sl < 0) {
+      atomicOr(err, 8);
+    } else {
+      T Ts[PS], Tt[PA], Tp[PA];
+      cheb_T<T, PS>((T)loc.ts, Ts);
+      cheb_T<T, PA>((T)loc.tt, Tt);
+      cheb_T<T, PA>((T)loc.tp, Tp);
+      const cpx<T>* C = Fc + (int64_t)sl * P;
+      double vr = 0.0, vi = 0.0;
+      for (int a = 0; a < PS; ++a) {
+        T hr = 0, hi = 0;
+        for (int b = 0; b < PA; ++b) {
+          T gr = 0, gi = 0;
+          for (int c = 0; c < PA; ++c) {
+            const cpx<T> x = C[(a * PA + b) * PA + c];
+            gr += x.re * Tp[c];
+            gi += x.im * Tp[c];
+          }
+          hr += gr * Tt[b];
+          hi += gi * Tt[b];
+        }
+        vr += (double)(hr * Ts[a]);
+        vi += (double)(hi * Ts[a]);
+      }
+      const double* y = centre + 3 * lane;
+      double sp, cp;
+      sincos(-k * (xh0 * y[0] + xh1 * y[1] + xh2 * y[2]), &sp, &cp);
+      re = cp * vr - sp * vi;
+      im = cp * vi + sp * vr;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (lane == 0) {
+    const double q = 1.0 / (4.0 * IFGF_PI);
+    if (dtype == IFGF_C128) {
+      ((double*)out)[2 * dr] = q * re;
+      ((double*)out)[2 * dr + 1] = q * im;
+    } else {
+      ((float*)out)[2 * dr] = (float)(q * re);
+      ((float*)out)[2 * dr + 1] = (float)(q * im);
+    }
+  }
+}
+
+// The far-field sum of eq. FarField taken directly over the (sorted) points,
+// for trees without interpolation levels (D <= 2): one wave per direction.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_far_direct(const double* __restrict__ dirs, int64_t ndir,
+                                                    const double* __restrict__ pts, const double* __restrict__ nrm,
+                                                    const cpx<T>* __restrict__ a, int64_t n, double k, double eta,
+                                                    int dtype, void* __restrict__ out) {
+  const int64_t dr = ((int64_t)blockIdx.x * TPB + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (dr >= ndir) return;   // wave-uniform
+  const double xh0 = dirs[3 * dr], xh1 = dirs[3 * dr + 1], xh2 = dirs[3 * dr + 2];
+  double re = 0.0, im = 0.0;
+  for (int64_t j = lane; j < n; j += 64) {
+    double sp, cp;
+    sincos(-k * (xh0 * pts[3 * j] + xh1 * pts[3 * j + 1] + xh2 * pts[3 * j + 2]), &sp, &cp);
+    const double xn = xh0 * nrm[3 * j] + xh1 * nrm[3 * j + 1] + xh2 * nrm[3 * j + 2];
+    // e^{-ik xh.y} (-i k xh.n - i eta) a_j
+    const double fr = cp, fi = sp, g = -(k * xn + eta);   // factor = (fr + i fi) * (i g)
+    const double tr = -fi * g, ti = fr * g;
+    const double ar = (double)a[j].re, ai = (double)a[j].im;
+    re += tr * ar - ti * ai;
+    im += tr * ai + ti * ar;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    re += __shfl_xor(re, off, 64);
+    im += __shfl_xor(im, off, 64);
+  }
+  if (lane == 0) {
+    const double q = 1.0 / (4.0 * IFGF_PI);
+    if (dtype == IFGF_C128) {
+      ((double*)out)[2 * dr] = q * re;
+      ((double*)out)[2 * dr + 1] = q * im;
+    } else {
+      ((float*)out)[2 * dr] = (float)(q * re);
+      ((float*)out)[2 * dr + 1] = (float)(q * im);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 // Orders with cone-major upward-pass tiles (P <= 144: the tile keeps a
@@ -3724,6 +3834,42 @@ void dispatch_apply(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
 }
 
+template <typename T, int PS, int PA>
+void far_field_impl(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double* dirs, void* uinf, int dtype,
+                    hipStream_t s) {
+  // the leaf factors and the upward pass to level 3, as in the apply
+  // (stage mask 0: no near field, no cousin targets; u, of sigma's dtype,
+  // is discarded)
+  DevBuf tmp;
+  tmp.alloc(sizeof(cpx<double>) * (size_t)p->n);
+  apply_impl<T, PS, PA>(p, sigma, tmp.p, 1, dtype, 0, 0, 0, s);
+  const unsigned grid = (unsigned)((ndir * 64 + TPB - 1) / TPB);
+  if (p->D >= 3) {
+    const LevelPlan& l3 = p->lev[3];
+    k_far_field<T, PS, PA><<<grid, TPB, 0, s>>>(dirs, ndir, l3.nb, l3.centre.as<double>(), l3.slot.as<int>(),
+                                                l3.Fc.as<cpx<T>>(), l3.geom, p->k, dtype, uinf, p->err.as<int>());
+  } else {
+    k_far_direct<T><<<grid, TPB, 0, s>>>(dirs, ndir, p->pts.as<double>(), p->nrm.as<double>(), p->a.as<cpx<T>>(),
+                                         p->n, p->k, p->eta, dtype, uinf);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));   // tmp is freed on return
+}
+
+template <typename T>
+void dispatch_far_field(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double* dirs, void* uinf, int dtype,
+                        hipStream_t s) {
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+#define X(a, b) \
+  if (ps == a && pa == b) return far_field_impl<T, a, b>(p, sigma, ndir, dirs, uinf, dtype, s);
+  IFGF_ORDERS_ALL(X)
+  if constexpr (!Prec<T>::f32) {
+    IFGF_ORDERS_FP64(X)
+  }
+#undef X
+  throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
+}
+
 template <int PS, int PA>
 void ti_geo_impl(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s) {
   LevelPlan& lp = p->lev[d];
@@ -3797,6 +3943,15 @@ void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, 
   else
     dispatch_apply<double>(p, sigma, u, nrhs, dtype, stage_mask, level_lo, level_hi, s);
   p->last_rhs = nrhs;
+}
+
+void run_far_field(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double* dirs, void* uinf, int dtype,
+                   hipStream_t s) {
+  if (p->opt.precision == IFGF_PREC_FP32_INTERP)
+    dispatch_far_field<float>(p, sigma, ndir, dirs, uinf, dtype, s);
+  else
+    dispatch_far_field<double>(p, sigma, ndir, dirs, uinf, dtype, s);
+  p->last_rhs = 1;
 }
 
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s) {

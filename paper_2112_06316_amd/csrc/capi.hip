@@ -109,6 +109,7 @@ void ifgf_options_default(ifgf_options* o) {
   o->kernel = IFGF_KERNEL_COMBINED;
   o->prop_kernel = IFGF_PROP_AUTO;
   o->target_kernel = IFGF_TARGET_AUTO;
+  o->far_field = 0;
 }
 
 const char* ifgf_status_string(ifgf_status st) {
@@ -148,6 +149,7 @@ ifgf_status ifgf_plan_create(ifgf_plan* out, int64_t n, const double* points, co
     if (o.target_kernel < IFGF_TARGET_AUTO || o.target_kernel > IFGF_TARGET_ROWS)
       throw Error{IFGF_EINVAL, "bad target_kernel"};
     if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
+    if (o.far_field != 0 && o.far_field != 1) throw Error{IFGF_EINVAL, "far_field must be 0 or 1"};
     if (!supported_order(o.p_s, o.p_ang, o.precision))
       throw Error{IFGF_EUNSUPPORTED, "p_s/p_ang pair not compiled in for this precision"};
     p = new ifgf_plan_s();
@@ -193,6 +195,20 @@ ifgf_status ifgf_apply_adjoint(ifgf_plan p, const void* v, void* out, int32_t nr
     BusyGuard g(p);
     if (!g.ok) throw Error{IFGF_EBUSY, "another apply on this plan is being enqueued"};
     run_adjoint(p, v, out, nrhs, dtype, conjugate ? 1 : 0, (hipStream_t)stream);
+  });
+}
+
+ifgf_status ifgf_far_field(ifgf_plan p, const void* sigma, int64_t ndir, const double* dirs, void* uinf,
+                           int32_t dtype, void* stream) {
+  return guarded([&] {
+    if (!p || !sigma || !dirs || !uinf) throw Error{IFGF_EINVAL, "null pointer argument"};
+    if (ndir < 1 || ndir > ((int64_t)1 << 31) / 64) throw Error{IFGF_EINVAL, "ndir out of range"};
+    if (dtype != IFGF_C64 && dtype != IFGF_C128) throw Error{IFGF_EINVAL, "bad dtype"};
+    if (p->opt.kernel != IFGF_KERNEL_COMBINED) throw Error{IFGF_EINVAL, "the far field needs the combined kernel"};
+    if (p->D >= 3 && !p->opt.far_field) throw Error{IFGF_EINVAL, "plan created without far_field = 1"};
+    BusyGuard g(p);
+    if (!g.ok) throw Error{IFGF_EBUSY, "another apply on this plan is being enqueued"};
+    run_far_field(p, sigma, ndir, dirs, uinf, dtype, (hipStream_t)stream);
   });
 }
 

@@ -158,6 +158,8 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask,
                int level_lo, int level_hi, hipStream_t s);
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
+void run_far_field(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double* dirs, void* uinf, int dtype,
+                   hipStream_t s);
 
 // solve.hip: restarted GMRES on (alpha I + A) sigma = f (complex128 device vectors).
 void run_gmres(ifgf_plan_s* p, const void* f, void* sigma, const ifgf_gmres_options& o, int32_t* iters,

@@ -295,6 +295,13 @@ __global__ __launch_bounds__(TPB) void k_mark_parent_nodes(int nrel_up, int P, c
   }
 }
 
+// The far-field cones of a level: cone ids 0 .. nfar - 1 (radial index 0) of every box.
+__global__ __launch_bounds__(TPB) void k_mark_far(int64_t nt, int nfar, int ncone, uint8_t* __restrict__ mark) {
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= nt) return;
+  mark[(t / nfar) * ncone + t % nfar] = 1;
+}
+
 __global__ __launch_bounds__(TPB) void k_slot_finalize(const uint8_t* __restrict__ mark, int64_t total, int ncone,
                                                        int* __restrict__ slot, int* __restrict__ slot_off,
                                                        int* __restrict__ rel_box, int* __restrict__ rel_cone) {
@@ -592,6 +599,14 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
       k_mark_targets<false><<<nblocks(n), TPB, 0, s>>>(p->pts.as<double>(), n, lv.pbox.as<int>(), lv.cou_off.as<int>(),
                                                       lv.cou.as<int>(), lv.centre.as<double>(), g, mark.as<uint8_t>());
     HIPCHK(hipGetLastError());
+    if (d == 3 && p->opt.far_field) {   // far-field cones: i_s = 0, every angular interval
+      const int nfar = g.nc * 2 * g.nc;
+      const int64_t nt = (int64_t)lv.nb * nfar;
+      if (nt > 0) {
+        k_mark_far<<<nblocks(nt), TPB, 0, s>>>(nt, nfar, g.ncone, mark.as<uint8_t>());
+        HIPCHK(hipGetLastError());
+      }
+    }
     if (d > 3) {
       LevelPlan& up = p->lev[d - 1];
       int64_t nt = (int64_t)up.nrel * P;
