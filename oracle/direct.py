@@ -162,3 +162,18 @@ def far_field_np(points, normals, weights, k, eta, sigma, dirs, block=512):
         ph = np.exp(-1j * k * (d @ pts.T))
         out[b0:b0 + block] = (ph * (-1j * k * (d @ nrm.T) - 1j * eta)) @ a / (4.0 * np.pi)
     return out
+
+
+def field_np(points, normals, weights, k, eta, sigma, targets, block=256):
+    """The combined-field potential (eq. CombinedLayer, discretized as in
+    eq. field1) at arbitrary points x distinct from the surface points:
+    u(x) = sum_j w_j sigma_j K(x, x_j), every j included."""
+    pts = np.asarray(points, dtype=np.float64)
+    nrm = np.asarray(normals, dtype=np.float64)
+    a = np.asarray(weights, dtype=np.float64) * np.asarray(sigma, dtype=np.complex128)
+    x = np.asarray(targets, dtype=np.float64)
+    out = np.zeros(x.shape[0], dtype=np.complex128)
+    for b0 in range(0, x.shape[0], block):
+        K = kernel_np(x[b0:b0 + block][:, None, :], pts[None, :, :], nrm[None, :, :], k, eta)
+        out[b0:b0 + block] = K @ a
+    return out

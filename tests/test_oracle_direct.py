@@ -217,3 +217,24 @@ def test_far_field_pattern_closed_forms():
     u0 = direct.far_field_np(p, nr, w, k, eta, s, xh)
     u1 = direct.far_field_np(p + c, nr, w, k, eta, s, xh)
     assert np.allclose(u1, u0 * np.exp(-1j * k * xh @ c), rtol=1e-13, atol=0)
+
+
+def test_field_at_off_surface_points_brute_force():
+    # u(x) = sum_j w_j s_j K(x, y_j) written out with scalar loops
+    rng = np.random.default_rng(21)
+    y = rng.standard_normal((12, 3))
+    ny = rng.standard_normal((12, 3))
+    w = rng.random(12)
+    s = rng.standard_normal(12) + 1j * rng.standard_normal(12)
+    x = 3.0 + rng.standard_normal((5, 3))
+    k, eta = 2.5, 1.5
+    got = direct.field_np(y, ny, w, k, eta, s, x)
+    for t in range(5):
+        acc = 0j
+        for j in range(12):
+            d = [x[t][c] - y[j][c] for c in range(3)]
+            r = math.sqrt(sum(v * v for v in d))
+            dn = sum(d[c] * ny[j][c] for c in range(3))
+            g = cmath.exp(1j * k * r) / (4 * math.pi * r)
+            acc += w[j] * s[j] * g * ((1 - 1j * k * r) * dn / r ** 2 - 1j * eta)
+        assert abs(got[t] - acc) <= 1e-13 * abs(acc)
