@@ -182,6 +182,28 @@ ifgf_status ifgf_plan_create(ifgf_plan *out, int64_t n, const double *points,
                              void *stream);
 
 /*
+ * A plan whose outputs are separate target points (Sec. 5: the scattered
+ * field off the surface, eq. CombinedLayer discretized as eq. field1):
+ *
+ *     u(t_l) = sum_j w_j sigma_j K(t_l, x_j),   l = 0 .. nt - 1,
+ *
+ * every source j included.  The octree, lists and relevant cones are built
+ * over sources and targets together (the root box holds both; target boxes
+ * get neighbours and cousins like any other), the targets carrying zero
+ * density, so the targets receive the same near-field sums and cousin
+ * interpolations as surface points.  Arguments as ifgf_plan_create, plus
+ * nt >= 1 and targets [device] nt x 3 doubles, distinct from each other and
+ * from the sources (EDUPLICATE otherwise).  For such a plan ifgf_apply takes
+ * sigma with n rows and writes u with nt rows; the work of one apply is that
+ * of an apply over the n + nt points.  ifgf_apply_adjoint (EUNSUPPORTED),
+ * ifgf_gmres_solve and ifgf_batch_create (EINVAL) do not take such plans;
+ * ifgf_far_field does.
+ */
+ifgf_status ifgf_plan_create_targets(ifgf_plan *out, int64_t n, const double *points, const double *normals,
+                                     const double *weights, int64_t nt, const double *targets, double k,
+                                     double eta, const ifgf_options *opt, void *stream);
+
+/*
  * Forward apply: u = A sigma with A_ij = w_j K(x_i, x_j) for i != j, A_ii = 0
  * (eq. field1), approximated by Algorithm 1.
  *

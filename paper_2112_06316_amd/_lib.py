@@ -75,6 +75,8 @@ I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 SIGNATURES = {
     "ifgf_options_default": (None, [ctypes.POINTER(Options)]),
     "ifgf_plan_create": (I32, [ctypes.POINTER(VP), I64, VP, VP, VP, F64, F64, ctypes.POINTER(Options), VP]),
+    "ifgf_plan_create_targets": (I32, [ctypes.POINTER(VP), I64, VP, VP, VP, I64, VP, F64, F64,
+                                       ctypes.POINTER(Options), VP]),
     "ifgf_apply": (I32, [VP, VP, VP, I32, I32, VP]),
     "ifgf_apply_adjoint": (I32, [VP, VP, VP, I32, I32, I32, VP]),
     "ifgf_apply_stages": (I32, [VP, VP, VP, I32, I32, I32, I32, I32, VP]),

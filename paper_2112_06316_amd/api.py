@@ -31,10 +31,11 @@ def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def _check_out(out, like, name="out"):
-    """A caller's output buffer must match the input it receives: the library
-    sees raw pointers only, so a smaller or mistyped buffer would be written
-    past its end on the device."""
+def _check_out(out, like, name="out", inp=None):
+    """A caller's output buffer must match the shape, dtype and device the
+    library writes (those of `like`) and must not overlap the input (`inp`,
+    default `like`): the library sees raw pointers only, so a smaller or
+    mistyped buffer would be written past its end on the device."""
     if not isinstance(out, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
     if out.dtype != like.dtype:
@@ -47,9 +48,10 @@ def _check_out(out, like, name="out"):
         raise ValueError(f"{name} has shape {tuple(out.shape)}, expected {tuple(like.shape)}")
     if not out.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
-    if out.numel() and like.numel():
+    src = like if inp is None else inp
+    if out.numel() and src.numel():
         o0, o1 = out.data_ptr(), out.data_ptr() + out.numel() * out.element_size()
-        l0, l1 = like.data_ptr(), like.data_ptr() + like.numel() * like.element_size()
+        l0, l1 = src.data_ptr(), src.data_ptr() + src.numel() * src.element_size()
         if o0 < l1 and l0 < o1:
             raise ValueError(f"{name} overlaps the input")
     return out
@@ -72,7 +74,7 @@ class Plan:
 
     def __init__(self, points, normals, weights, k, eta, *, p_s=4, p_ang=6, ns0=2, nc0=4, depth=0,
                  leaf_h_lambda=0.5, precision="fp32", max_rhs=1, kernel="combined", prop_kernel="auto",
-                 target_kernel="auto", far_field=False, device="cuda"):
+                 target_kernel="auto", far_field=False, targets=None, device="cuda"):
         lib = L.load()
         self._lib = lib
         self.device = torch.device(device)
@@ -97,9 +99,19 @@ class Plan:
         o.far_field = 1 if far_field else 0
         self.options = o
         h = ctypes.c_void_p()
-        st = lib.ifgf_plan_create(ctypes.byref(h), n, pts.data_ptr(), nrm.data_ptr(), w.data_ptr(),
-                                  self.k, self.eta, ctypes.byref(o), _stream_ptr(self.device))
-        L.check(st, "ifgf_plan_create")
+        self.n_out = n
+        if targets is None:
+            st = lib.ifgf_plan_create(ctypes.byref(h), n, pts.data_ptr(), nrm.data_ptr(), w.data_ptr(),
+                                      self.k, self.eta, ctypes.byref(o), _stream_ptr(self.device))
+            L.check(st, "ifgf_plan_create")
+        else:
+            nt = int(np.shape(targets)[0])
+            tg = _dev_f64(targets, self.device, (nt, 3))
+            st = lib.ifgf_plan_create_targets(ctypes.byref(h), n, pts.data_ptr(), nrm.data_ptr(), w.data_ptr(), nt,
+                                              tg.data_ptr(), self.k, self.eta, ctypes.byref(o),
+                                              _stream_ptr(self.device))
+            L.check(st, "ifgf_plan_create_targets")
+            self.n_out = nt
         self._h = h
         self.max_rhs = int(max_rhs)
 
@@ -132,9 +144,10 @@ class Plan:
         return x, squeeze, dtype
 
     def apply(self, sigma, out=None):
-        """u = A sigma (forward IFGF apply)."""
+        """u = A sigma (forward IFGF apply); for a plan with targets, u at the targets."""
         s, squeeze, dtype = self._prep(sigma)
-        u = torch.empty_like(s) if out is None else _check_out(out, s)
+        like = s if self.n_out == self.n else s.new_empty((self.n_out, s.shape[1]))
+        u = torch.empty_like(like) if out is None else _check_out(out, like, inp=s)
         st = self._lib.ifgf_apply(self._h, s.data_ptr(), u.data_ptr(), s.shape[1], dtype, _stream_ptr(self.device))
         L.check(st, "ifgf_apply")
         return u[:, 0] if squeeze else u

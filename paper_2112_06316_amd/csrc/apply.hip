@@ -58,17 +58,22 @@ template <> __device__ __forceinline__ float rcp_t<float>(float x) { return rcp_
 template <> __device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
 
 // ---------------------------------------------------------------------------
-// gather: a[i, r] = w_i sigma[perm_i, r]
+// gather: a[i, r] = w_i sigma[perm_i, r]; points with caller index >= n_src
+// (targets only) get 0 and sigma is not read there.
 // ---------------------------------------------------------------------------
 // Element q = (point i, right-hand side r), right-hand sides fastest.
 template <typename T>
 __device__ __forceinline__ void gather_one(int64_t q, const void* __restrict__ sigma, int dtype, int conj_in,
                                            const int* __restrict__ perm, const double* __restrict__ w, int64_t n,
-                                           int R, cpx<T>* __restrict__ a) {
+                                           int R, cpx<T>* __restrict__ a, int64_t n_src) {
   if (q >= n * R) return;
   const int64_t i = q / R;
   const int r = (int)(q % R);
   const int64_t j = perm[i];
+  if (j >= n_src) {
+    a[i * R + r] = {(T)0, (T)0};
+    return;
+  }
   const double wi = w ? w[i] : 1.0;
   double re, im;
   if (dtype == IFGF_C128) {
@@ -87,8 +92,19 @@ __device__ __forceinline__ void gather_one(int64_t q, const void* __restrict__ s
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_gather(const void* __restrict__ sigma, int dtype, int conj_in,
                                                 const int* __restrict__ perm, const double* __restrict__ w,
-                                                int64_t n, int R, cpx<T>* __restrict__ a) {
-  gather_one<T>((int64_t)blockIdx.x * TPB + threadIdx.x, sigma, dtype, conj_in, perm, w, n, R, a);
+                                                int64_t n, int R, cpx<T>* __restrict__ a, int64_t n_src) {
+  gather_one<T>((int64_t)blockIdx.x * TPB + threadIdx.x, sigma, dtype, conj_in, perm, w, n, R, a, n_src);
+}
+
+// Plans with separate targets: u[t, r] = uext[n_src + t, r] (caller order).
+__global__ __launch_bounds__(TPB) void k_copy_targets(const void* __restrict__ uext, int64_t n_src, int64_t nt,
+                                                      int R, int dtype, void* __restrict__ u) {
+  const int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q >= nt * R) return;
+  if (dtype == IFGF_C128)
+    reinterpret_cast<double2*>(u)[q] = reinterpret_cast<const double2*>(uext)[n_src * R + q];
+  else
+    reinterpret_cast<float2*>(u)[q] = reinterpret_cast<const float2*>(uext)[n_src * R + q];
 }
 
 // ---------------------------------------------------------------------------
@@ -3094,7 +3110,8 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   dim3 gpts(nblocks(n), R);
   {
     StageTimer tm(p, s, IFGF_STAGE_GATHER);
-    k_gather<T><<<nblocks(n * R), TPB, 0, s>>>(sigma, dtype, 0, p->perm.as<int>(), p->w.as<double>(), n, R, a);
+    k_gather<T><<<nblocks(n * R), TPB, 0, s>>>(sigma, dtype, 0, p->perm.as<int>(), p->w.as<double>(), n, R, a,
+                                               p->n_src);
   }
   HIPCHK(hipGetLastError());
   const int kind = p->opt.kernel;
@@ -3270,7 +3287,7 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
   dim3 gpts(nblocks(n), R);
   {
     StageTimer tm(p, s, IFGF_STAGE_GATHER);
-    k_gather<T><<<nblocks(n * R), TPB, 0, s>>>(v, dtype, conj, p->perm.as<int>(), nullptr, n, R, vs);
+    k_gather<T><<<nblocks(n * R), TPB, 0, s>>>(v, dtype, conj, p->perm.as<int>(), nullptr, n, R, vs, n);
   }
   HIPCHK(hipGetLastError());
   LevelPlan& lD = p->lev[D];
@@ -3500,7 +3517,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
     case BT_GATHER:
       for (int u = 0; u < BG_GATHER; ++u)
         gather_one<T>(((int64_t)local * BG_GATHER + u) * BS + threadIdx.x, io.sigma[S.geom], dtype, 0, gen(G.perm),
-                      gen(G.w), G.n, 1, gen(G.a));
+                      gen(G.w), G.n, 1, gen(G.a), G.n);
       break;
     case BT_NEAR: {   // near-field work items (box, first target, targets)
       const BLevel<T>& L = G.lv[D];
@@ -3938,10 +3955,18 @@ bool cone_prop_supported(const ifgf_plan_s* p) {
 
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask, int level_lo,
                int level_hi, hipStream_t s) {
+  // with separate targets the apply runs over sources and targets together
+  // (targets carrying zero density) and the targets' values are copied out
+  void* dst = p->n_src < p->n ? p->uext.p : u;
   if (p->opt.precision == IFGF_PREC_FP32_INTERP)
-    dispatch_apply<float>(p, sigma, u, nrhs, dtype, stage_mask, level_lo, level_hi, s);
+    dispatch_apply<float>(p, sigma, dst, nrhs, dtype, stage_mask, level_lo, level_hi, s);
   else
-    dispatch_apply<double>(p, sigma, u, nrhs, dtype, stage_mask, level_lo, level_hi, s);
+    dispatch_apply<double>(p, sigma, dst, nrhs, dtype, stage_mask, level_lo, level_hi, s);
+  if (p->n_src < p->n) {
+    const int64_t nt = p->n - p->n_src;
+    k_copy_targets<<<nblocks(nt * nrhs), TPB, 0, s>>>(dst, p->n_src, nt, nrhs, dtype, u);
+    HIPCHK(hipGetLastError());
+  }
   p->last_rhs = nrhs;
 }
 

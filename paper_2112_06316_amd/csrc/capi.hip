@@ -128,37 +128,77 @@ const char* ifgf_status_string(ifgf_status st) {
 
 const char* ifgf_last_error(void) { return g_last_error.c_str(); }
 
+// Plan creation shared by ifgf_plan_create and ifgf_plan_create_targets: the
+// first n_src of the n points carry densities, the others are targets only.
+static void create_plan(ifgf_plan_s*& p, int64_t n, int64_t n_src, const double* points, const double* normals,
+                        const double* weights, double k, double eta, const ifgf_options* opt, hipStream_t stream) {
+  if (n < 1 || n > (int64_t)0x7fffffff) throw Error{IFGF_EINVAL, "n out of range"};
+  if (!(k > 0.0) || !std::isfinite(k) || !std::isfinite(eta)) throw Error{IFGF_EINVAL, "k must be finite and > 0"};
+  ifgf_options o;
+  ifgf_options_default(&o);
+  if (opt) o = *opt;
+  if (o.p_s < 1 || o.p_ang < 1 || o.p_s > IFGF_MAXP || o.p_ang > IFGF_MAXP) throw Error{IFGF_EINVAL, "bad p_s/p_ang"};
+  if (o.ns0 < 1 || o.nc0 < 1) throw Error{IFGF_EINVAL, "bad ns0/nc0"};
+  if (o.depth < 0 || o.depth > 11) throw Error{IFGF_EINVAL, "depth must be in 0..11"};
+  if (o.depth == 0 && !(o.leaf_h_lambda > 0.0)) throw Error{IFGF_EINVAL, "leaf_h_lambda must be > 0"};
+  if (o.precision != IFGF_PREC_FP64 && o.precision != IFGF_PREC_FP32_INTERP) throw Error{IFGF_EINVAL, "bad precision"};
+  if (o.max_rhs < 1) throw Error{IFGF_EINVAL, "max_rhs must be >= 1"};
+  if (o.prop_kernel < IFGF_PROP_AUTO || o.prop_kernel > IFGF_PROP_CONE) throw Error{IFGF_EINVAL, "bad prop_kernel"};
+  if (o.target_kernel < IFGF_TARGET_AUTO || o.target_kernel > IFGF_TARGET_ROWS)
+    throw Error{IFGF_EINVAL, "bad target_kernel"};
+  if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
+  if (o.far_field != 0 && o.far_field != 1) throw Error{IFGF_EINVAL, "far_field must be 0 or 1"};
+  if (!supported_order(o.p_s, o.p_ang, o.precision))
+    throw Error{IFGF_EUNSUPPORTED, "p_s/p_ang pair not compiled in for this precision"};
+  p = new ifgf_plan_s();
+  p->n = n;
+  p->n_src = n_src;
+  p->k = k;
+  p->eta = eta;
+  p->opt = o;
+  p->P = o.p_s * o.p_ang * o.p_ang;
+  build_plan(p, points, normals, weights, stream);
+  if (n_src < n) p->uext.alloc(sizeof(double) * 2 * (size_t)n * o.max_rhs);
+}
+
 ifgf_status ifgf_plan_create(ifgf_plan* out, int64_t n, const double* points, const double* normals,
                              const double* weights, double k, double eta, const ifgf_options* opt, void* stream) {
   if (out) *out = nullptr;
   ifgf_plan_s* p = nullptr;
   ifgf_status st = guarded([&] {
     if (!out || !points || !normals || !weights) throw Error{IFGF_EINVAL, "null pointer argument"};
-    if (n < 1 || n > (int64_t)0x7fffffff) throw Error{IFGF_EINVAL, "n out of range"};
-    if (!(k > 0.0) || !std::isfinite(k) || !std::isfinite(eta)) throw Error{IFGF_EINVAL, "k must be finite and > 0"};
-    ifgf_options o;
-    ifgf_options_default(&o);
-    if (opt) o = *opt;
-    if (o.p_s < 1 || o.p_ang < 1 || o.p_s > IFGF_MAXP || o.p_ang > IFGF_MAXP) throw Error{IFGF_EINVAL, "bad p_s/p_ang"};
-    if (o.ns0 < 1 || o.nc0 < 1) throw Error{IFGF_EINVAL, "bad ns0/nc0"};
-    if (o.depth < 0 || o.depth > 11) throw Error{IFGF_EINVAL, "depth must be in 0..11"};
-    if (o.depth == 0 && !(o.leaf_h_lambda > 0.0)) throw Error{IFGF_EINVAL, "leaf_h_lambda must be > 0"};
-    if (o.precision != IFGF_PREC_FP64 && o.precision != IFGF_PREC_FP32_INTERP) throw Error{IFGF_EINVAL, "bad precision"};
-    if (o.max_rhs < 1) throw Error{IFGF_EINVAL, "max_rhs must be >= 1"};
-    if (o.prop_kernel < IFGF_PROP_AUTO || o.prop_kernel > IFGF_PROP_CONE) throw Error{IFGF_EINVAL, "bad prop_kernel"};
-    if (o.target_kernel < IFGF_TARGET_AUTO || o.target_kernel > IFGF_TARGET_ROWS)
-      throw Error{IFGF_EINVAL, "bad target_kernel"};
-    if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
-    if (o.far_field != 0 && o.far_field != 1) throw Error{IFGF_EINVAL, "far_field must be 0 or 1"};
-    if (!supported_order(o.p_s, o.p_ang, o.precision))
-      throw Error{IFGF_EUNSUPPORTED, "p_s/p_ang pair not compiled in for this precision"};
-    p = new ifgf_plan_s();
-    p->n = n;
-    p->k = k;
-    p->eta = eta;
-    p->opt = o;
-    p->P = o.p_s * o.p_ang * o.p_ang;
-    build_plan(p, points, normals, weights, (hipStream_t)stream);
+    create_plan(p, n, n, points, normals, weights, k, eta, opt, (hipStream_t)stream);
+    *out = p;
+  });
+  if (st != IFGF_OK) {
+    delete p;
+  }
+  return st;
+}
+
+ifgf_status ifgf_plan_create_targets(ifgf_plan* out, int64_t n, const double* points, const double* normals,
+                                     const double* weights, int64_t nt, const double* targets, double k, double eta,
+                                     const ifgf_options* opt, void* stream) {
+  if (out) *out = nullptr;
+  ifgf_plan_s* p = nullptr;
+  ifgf_status st = guarded([&] {
+    if (!out || !points || !normals || !weights || !targets) throw Error{IFGF_EINVAL, "null pointer argument"};
+    if (n < 1 || nt < 1 || n + nt > (int64_t)0x7fffffff) throw Error{IFGF_EINVAL, "n or nt out of range"};
+    const hipStream_t s = (hipStream_t)stream;
+    // one point set: the sources, then the targets with zero weight and normal
+    const int64_t m = n + nt;
+    DevBuf up, un, uw;
+    up.alloc(sizeof(double) * 3 * m);
+    un.alloc(sizeof(double) * 3 * m);
+    uw.alloc(sizeof(double) * m);
+    HIPCHK(hipMemcpyAsync(up.p, points, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(up.as<double>() + 3 * n, targets, sizeof(double) * 3 * nt, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(un.p, normals, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(un.as<double>() + 3 * n, 0, sizeof(double) * 3 * nt, s));
+    HIPCHK(hipMemcpyAsync(uw.p, weights, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(uw.as<double>() + n, 0, sizeof(double) * nt, s));
+    create_plan(p, m, n, up.as<double>(), un.as<double>(), uw.as<double>(), k, eta, opt, s);
+    HIPCHK(hipStreamSynchronize(s));   // the union arrays are freed on return
     *out = p;
   });
   if (st != IFGF_OK) {
@@ -192,6 +232,7 @@ ifgf_status ifgf_apply_adjoint(ifgf_plan p, const void* v, void* out, int32_t nr
                                void* stream) {
   return guarded([&] {
     check_apply_args(p, v, out, nrhs, dtype);
+    if (p->n_src < p->n) throw Error{IFGF_EUNSUPPORTED, "no transposed apply for a plan with separate targets"};
     BusyGuard g(p);
     if (!g.ok) throw Error{IFGF_EBUSY, "another apply on this plan is being enqueued"};
     run_adjoint(p, v, out, nrhs, dtype, conjugate ? 1 : 0, (hipStream_t)stream);
@@ -227,6 +268,7 @@ ifgf_status ifgf_gmres_solve(ifgf_plan p, const void* f, void* sigma, const ifgf
   return guarded([&] {
     if (!p || !f || !sigma || !iters || !rel_res) throw Error{IFGF_EINVAL, "null pointer argument"};
     if (f == sigma) throw Error{IFGF_EINVAL, "f and sigma alias"};
+    if (p->n_src < p->n) throw Error{IFGF_EINVAL, "a plan with separate targets is not a square operator"};
     ifgf_gmres_options o;
     ifgf_gmres_options_default(&o);
     if (opt) o = *opt;
@@ -387,6 +429,7 @@ ifgf_status ifgf_batch_create(ifgf_batch* out, int32_t nplans, const ifgf_plan* 
     for (int g = 0; g < nplans; ++g) {
       ifgf_plan_s* p = plans[g];
       if (!p) throw Error{IFGF_EINVAL, "null plan in batch"};
+      if (p->n_src < p->n) throw Error{IFGF_EINVAL, "a plan with separate targets cannot join a batch"};
       for (auto* q : b->plans)
         if (q == p) throw Error{IFGF_EINVAL, "a plan appears twice in the batch"};
       const ifgf_plan_s* p0 = plans[0];

@@ -88,6 +88,8 @@ struct LevelPlan {
 struct ifgf_plan_s {
   int64_t n = 0;
   int D = 0;
+  int64_t n_src = 0;          // points carrying densities (caller indices < n_src); the rest are targets only
+  ifgf::DevBuf uext;          // plans with targets: the apply's result at every point, caller's order
   double k = 0, eta = 0;
   ifgf_options opt{};
   int P = 0;                  // p_s * p_ang^2
