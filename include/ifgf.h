@@ -313,6 +313,34 @@ ifgf_status ifgf_plan_read_profile(ifgf_plan p, double *ms, int64_t *launches);
 void ifgf_plan_destroy(ifgf_plan p);
 
 /*
+ * Autotuner of the plan's one-right-hand-side formulations, by measurement
+ * on the plan's own data and this device.  For every level of the upward
+ * pass (prop_kernel AUTO only) it times the node formulation and the
+ * cone-major MFMA tiles of 8, 16 and 32 boxes per tile (those the order,
+ * the precision - FP64 tiles hold at most 16 boxes - and the node-record
+ * memory rule allow), `reps` passes each with HIP events, and keeps the
+ * fastest; then (target_kernel AUTO, orders with row-broadcast targets) it
+ * times `reps` whole applies with row-broadcast and with per-wave cousin
+ * targets and keeps the faster.  The choices persist in the plan and every
+ * later apply uses them; results change only by rounding.  A plan with a
+ * ragged batch built over it cannot be tuned (EBUSY: the batch's queue
+ * points into the buffers the tuner rebuilds); tune before creating
+ * batches.  report [host, may be NULL] receives the measurements.  Runs
+ * 1 + about (4 x levels + 2) x (reps + 1) passes or applies, synchronizes
+ * `stream`.  Errors: EINVAL (reps < 1), EBUSY, ENOMEM, EHIP.
+ */
+typedef struct {
+    int32_t nlevels;                        /* upward-pass levels tuned (entries below)       */
+    int32_t parent_level[IFGF_MAX_LEVELS];  /* level d - 1 of the pass d -> d - 1             */
+    int32_t choice[IFGF_MAX_LEVELS];        /* 0: node formulation; 8, 16, 32: boxes per tile */
+    double ms[IFGF_MAX_LEVELS][4];          /* ms per pass: node, 8-, 16-, 32-box tiles; -1 if
+                                               not a candidate                                */
+    int32_t target_choice;                  /* IFGF_TARGET_ROWS or _WAVE; 0 if not tuned      */
+    double target_ms[2];                    /* ms per apply with row, with wave targets; -1   */
+} ifgf_tune_report;
+ifgf_status ifgf_plan_autotune(ifgf_plan p, int32_t reps, ifgf_tune_report *report, void *stream);
+
+/*
  * Far-field pattern (Sec. 5, eq. FarField) of the combined-field potential
  * (eq. CombinedLayer, coupling eta) with density sigma:
  *

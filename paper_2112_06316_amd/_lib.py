@@ -68,6 +68,17 @@ class GmresOptions(ctypes.Structure):
     ]
 
 
+class TuneReport(ctypes.Structure):
+    _fields_ = [
+        ("nlevels", ctypes.c_int32),
+        ("parent_level", ctypes.c_int32 * MAX_LEVELS),
+        ("choice", ctypes.c_int32 * MAX_LEVELS),
+        ("ms", (ctypes.c_double * 4) * MAX_LEVELS),
+        ("target_choice", ctypes.c_int32),
+        ("target_ms", ctypes.c_double * 2),
+    ]
+
+
 VP = ctypes.c_void_p
 I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
 
@@ -91,6 +102,7 @@ SIGNATURES = {
     "ifgf_plan_read_profile": (I32, [VP, VP, VP]),
     "ifgf_plan_destroy": (None, [VP]),
     "ifgf_far_field": (I32, [VP, VP, I64, VP, VP, I32, VP]),
+    "ifgf_plan_autotune": (I32, [VP, I32, ctypes.POINTER(TuneReport), VP]),
     "ifgf_gmres_options_default": (None, [ctypes.POINTER(GmresOptions)]),
     "ifgf_gmres_solve": (I32, [VP, VP, VP, ctypes.POINTER(GmresOptions), ctypes.POINTER(I32),
                                ctypes.POINTER(F64), VP, VP]),

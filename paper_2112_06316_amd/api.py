@@ -169,6 +169,24 @@ class Plan:
         L.check(st, "ifgf_apply_adjoint")
         return out[:, 0] if squeeze else out
 
+    def autotune(self, reps=5) -> dict:
+        """Measure and keep the fastest one-RHS formulation of every upward-pass
+        level (node, or cone-major tiles of 8/16/32 boxes) and of the cousin
+        targets (rows or wave).  Returns the measurements."""
+        r = L.TuneReport()
+        L.check(self._lib.ifgf_plan_autotune(self._h, int(reps), ctypes.byref(r), _stream_ptr(self.device)),
+                "ifgf_plan_autotune")
+        names = ["node", "tile8", "tile16", "tile32"]
+        levels = {}
+        for i in range(r.nlevels):
+            levels[r.parent_level[i]] = {
+                "choice": "node" if r.choice[i] == 0 else f"tile{r.choice[i]}",
+                "ms": {names[c]: r.ms[i][c] for c in range(4) if r.ms[i][c] >= 0},
+            }
+        tgt = {L.TARGET_ROWS: "rows", L.TARGET_WAVE: "wave"}.get(r.target_choice)
+        return {"prop": levels, "targets": tgt,
+                "targets_ms": {"rows": r.target_ms[0], "wave": r.target_ms[1]} if tgt else None}
+
     def far_field(self, sigma, dirs):
         """Far-field pattern u_inf at unit directions dirs (m, 3) (eq. FarField),
         through the tree (plan created with far_field=True unless depth <= 2)."""

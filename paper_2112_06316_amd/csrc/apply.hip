@@ -3099,6 +3099,75 @@ __global__ __launch_bounds__(TPB) void k_far_direct(const double* __restrict__ d
 // child's P_ang^2 coefficients per radial index in registers).
 constexpr bool cone_major_order(int ps, int pa) { return ps <= 4 && ps * pa * pa <= 144; }
 
+// The upward pass from child level d into level d - 1 (Algorithm 1, parent
+// interpolation nodes), with the formulation the plan holds for that level:
+// MFMA over RHS groups (FP32, nrhs a multiple of 16), cone-major tiles (one
+// RHS, levels with tiles) or the node formulation.
+template <typename T, int PS, int PA>
+void prop_level(ifgf_plan_s* p, int d, int R, hipStream_t s) {
+  constexpr int P = PS * PA * PA;
+  const int kind = p->opt.kernel;
+  const T* Ms = (const T*)(Prec<T>::f32 ? p->Msf.p : p->Ms.p);
+  const T* Ma = (const T*)(Prec<T>::f32 ? p->Maf.p : p->Ma.p);
+  const bool mfma = Prec<T>::f32 && R % MF_RG == 0 && PS <= 4;
+
+  LevelPlan& lc = p->lev[d];
+  LevelPlan& lp = p->lev[d - 1];
+  if (lp.nrel == 0 || lp.nwork == 0) return;
+  if constexpr (Prec<T>::f32 && PS <= 4) {
+    if (mfma) {
+      const int64_t items = (int64_t)lp.nrel * P;
+      {
+        StageTimer tm(p, s, IFGF_STAGE_PROP);
+        (void)items;
+        k_prop_mfma_cone<PS, PA><<<dim3((unsigned)lp.nrel, R / MF_RG), TPB, 0, s>>>(
+            lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
+            lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms,
+            (const float*)Ma, p->k, kind, R, lp.Fc.as<cpx<T>>(), p->err.as<int>());
+      }
+      HIPCHK(hipGetLastError());
+      return;
+    }
+  }
+  if constexpr (Prec<T>::f32 && cone_major_order(PS, PA)) {
+    if (R == 1 && lp.ntile > 0) {
+      StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
+      auto launch = [&](auto kern, int nw) {
+        kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
+            lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lp.ti_geo.as<TiGeo<PS, PA>>(),
+            lc.slot.as<int>(), lc.Fc.as<cpx<float>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms,
+            (const float*)Ma, p->k, kind, lp.Fc.as<cpx<float>>(), p->err.as<int>());
+      };
+      if (lp.ti_nw == 4) launch(k_prop_ti<PS, PA, 4>, 4);
+      else if (lp.ti_nw == 2) launch(k_prop_ti<PS, PA, 2>, 2);
+      else launch(k_prop_ti<PS, PA, 1>, 1);
+      HIPCHK(hipGetLastError());
+      return;
+    }
+  }
+  if constexpr (!Prec<T>::f32 && cone_major_order(PS, PA)) {
+    if (R == 1 && lp.ntile > 0) {
+      StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
+      auto launch = [&](auto kern, int nw) {
+        kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
+            lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lp.ti_geo.as<TiGeo64<PS, PA>>(),
+            lc.slot.as<int>(), lc.Fc.as<cpx<double>>(), lp.geom, lc.geom, p->cheb, (const double*)Ms,
+            (const double*)Ma, p->k, kind, lp.Fc.as<cpx<double>>(), p->err.as<int>());
+      };
+      if (lp.ti_nw == 2) launch(k_prop_ti64<PS, PA, 2>, 2);
+      else launch(k_prop_ti64<PS, PA, 1>, 1);
+      HIPCHK(hipGetLastError());
+      return;
+    }
+  }
+  StageTimer tm(p, s, IFGF_STAGE_PROP);
+  auto kp = R == 1 ? k_prop<T, PS, PA, true> : k_prop<T, PS, PA, false>;
+  kp<<<dim3((unsigned)lp.nwork, R), PropShape<P>::BS, 0, s>>>(
+      lp.work.as<int4>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(), lc.slot.as<int>(),
+      lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, Ms, Ma, p->k, kind, R, lp.Fc.as<cpx<T>>(), p->err.as<int>());
+  HIPCHK(hipGetLastError());
+}
+
 template <typename T, int PS, int PA>
 void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, int stage_mask, int level_lo,
                 int level_hi, hipStream_t s) {
@@ -3168,64 +3237,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
                                                                    lD.Fc.as<cpx<T>>());
       HIPCHK(hipGetLastError());
     }
-    const bool mfma = Prec<T>::f32 && R % MF_RG == 0 && PS <= 4;
-    for (int d = D; d >= 4; --d) {
-      LevelPlan& lc = p->lev[d];
-      LevelPlan& lp = p->lev[d - 1];
-      if (lp.nrel == 0 || lp.nwork == 0) continue;
-      if constexpr (Prec<T>::f32 && PS <= 4) {
-        if (mfma) {
-          const int64_t items = (int64_t)lp.nrel * P;
-          {
-            StageTimer tm(p, s, IFGF_STAGE_PROP);
-            (void)items;
-            k_prop_mfma_cone<PS, PA><<<dim3((unsigned)lp.nrel, R / MF_RG), TPB, 0, s>>>(
-                lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
-                lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms,
-                (const float*)Ma, p->k, kind, R, lp.Fc.as<cpx<T>>(), p->err.as<int>());
-          }
-          HIPCHK(hipGetLastError());
-          continue;
-        }
-      }
-      if constexpr (Prec<T>::f32 && cone_major_order(PS, PA)) {
-        if (R == 1 && lp.ntile > 0) {
-          StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
-          auto launch = [&](auto kern, int nw) {
-            kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
-                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lp.ti_geo.as<TiGeo<PS, PA>>(),
-                lc.slot.as<int>(), lc.Fc.as<cpx<float>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms,
-                (const float*)Ma, p->k, kind, lp.Fc.as<cpx<float>>(), p->err.as<int>());
-          };
-          if (lp.ti_nw == 4) launch(k_prop_ti<PS, PA, 4>, 4);
-          else if (lp.ti_nw == 2) launch(k_prop_ti<PS, PA, 2>, 2);
-          else launch(k_prop_ti<PS, PA, 1>, 1);
-          HIPCHK(hipGetLastError());
-          continue;
-        }
-      }
-      if constexpr (!Prec<T>::f32 && cone_major_order(PS, PA)) {
-        if (R == 1 && lp.ntile > 0) {
-          StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
-          auto launch = [&](auto kern, int nw) {
-            kern<<<(unsigned)lp.ntile, 64 * nw, 0, s>>>(
-                lp.ti_tile.as<int4>(), lp.ti_slot.as<int>(), lp.ti_child.as<int>(), lp.ti_geo.as<TiGeo64<PS, PA>>(),
-                lc.slot.as<int>(), lc.Fc.as<cpx<double>>(), lp.geom, lc.geom, p->cheb, (const double*)Ms,
-                (const double*)Ma, p->k, kind, lp.Fc.as<cpx<double>>(), p->err.as<int>());
-          };
-          if (lp.ti_nw == 2) launch(k_prop_ti64<PS, PA, 2>, 2);
-          else launch(k_prop_ti64<PS, PA, 1>, 1);
-          HIPCHK(hipGetLastError());
-          continue;
-        }
-      }
-      StageTimer tm(p, s, IFGF_STAGE_PROP);
-      auto kp = R == 1 ? k_prop<T, PS, PA, true> : k_prop<T, PS, PA, false>;
-      kp<<<dim3((unsigned)lp.nwork, R), PropShape<P>::BS, 0, s>>>(
-          lp.work.as<int4>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(), lc.slot.as<int>(),
-          lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, Ms, Ma, p->k, kind, R, lp.Fc.as<cpx<T>>(), p->err.as<int>());
-      HIPCHK(hipGetLastError());
-    }
+    for (int d = D; d >= 4; --d) prop_level<T, PS, PA>(p, d, R, s);
   }
   TLevels<T> L{};
   for (int d = 3; d <= D; ++d) {
@@ -3887,6 +3899,95 @@ void dispatch_far_field(ifgf_plan_s* p, const void* sigma, int64_t ndir, const d
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
 }
 
+__global__ __launch_bounds__(TPB) void k_fill_one(double* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) {
+    x[2 * i] = 1.0;
+    x[2 * i + 1] = 0.0;
+  }
+}
+
+// Measured choice of the one-RHS formulations of a plan: for every level of
+// the upward pass, the node formulation against cone-major tiles of 8, 16 and
+// 32 boxes (those the level and precision allow), each timed with events over
+// `reps` passes on the plan's own data; then row-broadcast against per-wave
+// cousin targets, over `reps` whole applies.  The fastest is kept in the plan.
+template <typename T, int PS, int PA>
+void autotune_impl(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t s) {
+  const int D = p->D;
+  *rep = ifgf_tune_report{};
+  DevBuf sig, out;
+  sig.alloc(sizeof(double) * 2 * (size_t)p->n);
+  out.alloc(sizeof(double) * 2 * (size_t)p->n);
+  k_fill_one<<<nblocks(p->n), TPB, 0, s>>>(sig.as<double>(), p->n);
+  HIPCHK(hipGetLastError());
+  auto full_apply = [&]() { apply_impl<T, PS, PA>(p, sig.p, out.p, 1, IFGF_C128, 3, 0, 1 << 20, s); };
+  full_apply();   // every level's coefficients in place for the per-level timings
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto timed = [&](auto&& fn) -> double {
+    fn();
+    HIPCHK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) fn();
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms / reps;
+  };
+  const bool f32 = Prec<T>::f32;
+  if (p->opt.prop_kernel == IFGF_PROP_AUTO) {
+    int nl = 0;
+    for (int d = D; d >= 4; --d) {   // child level d into parent level d - 1
+      LevelPlan& lp = p->lev[d - 1];
+      if (lp.nrel == 0 || lp.nwork == 0) continue;
+      const bool cone = cone_major_order(PS, PA) && cone_prop_supported(p) && lp.ti_allowed;
+      static const int kNw[4] = {0, 1, 2, 4};
+      int best = -1;
+      for (int c = 0; c < 4; ++c) {
+        rep->ms[nl][c] = -1.0;
+        if (c > 0 && (!cone || (!f32 && kNw[c] > 2))) continue;
+        build_cone_tiles(p, d - 1, kNw[c], s);
+        rep->ms[nl][c] = timed([&]() { prop_level<T, PS, PA>(p, d, 1, s); });
+        if (best < 0 || rep->ms[nl][c] < rep->ms[nl][best]) best = c;
+      }
+      build_cone_tiles(p, d - 1, kNw[best], s);
+      rep->parent_level[nl] = d - 1;
+      rep->choice[nl] = 8 * kNw[best];
+      ++nl;
+    }
+    rep->nlevels = nl;
+  }
+  rep->target_ms[0] = rep->target_ms[1] = -1.0;
+  if constexpr (RowStage1<T, PS, PA>::ok) {
+    if (p->opt.target_kernel == IFGF_TARGET_AUTO && p->tpart.bytes > 0) {
+      p->opt.target_kernel = IFGF_TARGET_ROWS;
+      rep->target_ms[0] = timed(full_apply);
+      p->opt.target_kernel = IFGF_TARGET_WAVE;
+      rep->target_ms[1] = timed(full_apply);
+      p->opt.target_kernel = rep->target_ms[0] <= rep->target_ms[1] ? IFGF_TARGET_ROWS : IFGF_TARGET_WAVE;
+      rep->target_choice = p->opt.target_kernel;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIPCHK(hipStreamSynchronize(s));   // sig and out are freed on return
+}
+
+template <typename T>
+void dispatch_autotune(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t s) {
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+#define X(a, b) \
+  if (ps == a && pa == b) return autotune_impl<T, a, b>(p, reps, rep, s);
+  IFGF_ORDERS_ALL(X)
+  if constexpr (!Prec<T>::f32) {
+    IFGF_ORDERS_FP64(X)
+  }
+#undef X
+  throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
+}
+
 template <int PS, int PA>
 void ti_geo_impl(ifgf_plan_s* p, int d, const std::vector<int>& qlist, hipStream_t s) {
   LevelPlan& lp = p->lev[d];
@@ -3976,6 +4077,14 @@ void run_far_field(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double
     dispatch_far_field<float>(p, sigma, ndir, dirs, uinf, dtype, s);
   else
     dispatch_far_field<double>(p, sigma, ndir, dirs, uinf, dtype, s);
+  p->last_rhs = 1;
+}
+
+void run_autotune(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t s) {
+  if (p->opt.precision == IFGF_PREC_FP32_INTERP)
+    dispatch_autotune<float>(p, reps, rep, s);
+  else
+    dispatch_autotune<double>(p, reps, rep, s);
   p->last_rhs = 1;
 }
 

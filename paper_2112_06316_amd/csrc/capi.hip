@@ -239,6 +239,19 @@ ifgf_status ifgf_apply_adjoint(ifgf_plan p, const void* v, void* out, int32_t nr
   });
 }
 
+ifgf_status ifgf_plan_autotune(ifgf_plan p, int32_t reps, ifgf_tune_report* report, void* stream) {
+  return guarded([&] {
+    if (!p) throw Error{IFGF_EINVAL, "null plan"};
+    if (reps < 1) throw Error{IFGF_EINVAL, "reps must be >= 1"};
+    if (p->batch_refs.load() > 0) throw Error{IFGF_EBUSY, "a batch is built over this plan"};
+    BusyGuard g(p);
+    if (!g.ok) throw Error{IFGF_EBUSY, "another apply on this plan is being enqueued"};
+    ifgf_tune_report r;
+    run_autotune(p, reps, &r, (hipStream_t)stream);
+    if (report) *report = r;
+  });
+}
+
 ifgf_status ifgf_far_field(ifgf_plan p, const void* sigma, int64_t ndir, const double* dirs, void* uinf,
                            int32_t dtype, void* stream) {
   return guarded([&] {
@@ -442,7 +455,10 @@ ifgf_status ifgf_batch_create(ifgf_batch* out, int32_t nplans, const ifgf_plan* 
     run_batch_prepare(b.get());
     HIPCHK(hipDeviceSynchronize());
   });
-  if (st == IFGF_OK) *out = b.release();
+  if (st == IFGF_OK) {
+    for (auto* p : b->plans) p->batch_refs.fetch_add(1);
+    *out = b.release();
+  }
   return st;
 }
 
@@ -538,6 +554,7 @@ ifgf_status ifgf_batch_get_info(ifgf_batch b, int64_t* items, int32_t* segments,
 void ifgf_batch_destroy(ifgf_batch b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
+  for (auto* p : b->plans) p->batch_refs.fetch_sub(1);
   delete b;
 }
 

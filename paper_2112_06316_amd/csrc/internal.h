@@ -78,6 +78,8 @@ struct LevelPlan {
   DevBuf leaf_work;
   int n_leaf = 0;
   int ti_nw = 0;              // 0: this level uses the node formulation
+  bool ti_allowed = false;    // the node-record table fits the memory rule (or CONE is forced)
+  bool ti_geo_built = false;  // ti_geo holds this level's node records
   // statistics
   int64_t cousin_pairs = 0;
   int64_t prop_evals = 0;     // child interpolations into level d-1 nodes
@@ -89,6 +91,7 @@ struct ifgf_plan_s {
   int64_t n = 0;
   int D = 0;
   int64_t n_src = 0;          // points carrying densities (caller indices < n_src); the rest are targets only
+  std::atomic<int> batch_refs{0};   // batches built over this plan (their queues point into its buffers)
   ifgf::DevBuf uext;          // plans with targets: the apply's result at every point, caller's order
   double k = 0, eta = 0;
   ifgf_options opt{};
@@ -155,6 +158,9 @@ void sort_u64(uint64_t* data, int64_t n, hipStream_t s);                        
 
 // plan.hip
 void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const double* w, hipStream_t s);
+// (Re)build the cone-major tiles of the upward pass into level d with tiles of
+// 8 * nw_req boxes (nw_req < 0: heuristic; 0: node formulation); returns nw.
+int build_cone_tiles(ifgf_plan_s* p, int d, int nw_req, hipStream_t s);
 
 // apply.hip
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask,
@@ -162,6 +168,7 @@ void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, 
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
 void run_far_field(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double* dirs, void* uinf, int dtype,
                    hipStream_t s);
+void run_autotune(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t s);
 
 // solve.hip: restarted GMRES on (alpha I + A) sigma = f (complex128 device vectors).
 void run_gmres(ifgf_plan_s* p, const void* f, void* sigma, const ifgf_gmres_options& o, int32_t* iters,

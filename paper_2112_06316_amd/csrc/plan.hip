@@ -365,6 +365,128 @@ __global__ __launch_bounds__(TPB) void k_cone_keys(const int* __restrict__ rel_c
   if (i < nrel) keys[i] = ((uint64_t)(uint32_t)rel_cone[i] << 32) | (uint32_t)i;
 }
 
+// Cone-major tiles of the upward pass into level d (one right-hand side):
+// the relevant cones of level d sorted by (cone id, child octant mask, Morton
+// order) and cut into tiles of 8 * nw boxes of one cone id.  nw_req < 0
+// picks nw by the heuristic below; 0 leaves the level to the node
+// formulation.  Returns the nw in use.  Callable again on a built plan (the
+// autotuner re-cuts a level's tiles; the node records are built once).
+int build_cone_tiles(ifgf_plan_s* p, int d, int nw_req, hipStream_t s) {
+  const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
+  const int P = p->P;
+  LevelPlan& lv = p->lev[d];
+  lv.ntile = 0;
+  lv.ti_nw = 0;
+  if (lv.nrel == 0) return 0;
+  DevBuf kb;
+  kb.alloc(sizeof(uint64_t) * sort_padded_length(lv.nrel));
+  k_cone_keys<<<nblocks(lv.nrel), TPB, 0, s>>>(lv.rel_cone.as<int>(), lv.nrel, kb.as<uint64_t>());
+  HIPCHK(hipGetLastError());
+  sort_u64(kb.as<uint64_t>(), lv.nrel, s);
+  std::vector<uint64_t> keys(lv.nrel);
+  HIPCHK(hipMemcpyAsync(keys.data(), kb.p, sizeof(uint64_t) * lv.nrel, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int64_t ndistinct = 0;
+  for (int64_t i = 0; i < lv.nrel; ++i)
+    if (i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32)) ++ndistinct;
+  const double per = (double)lv.nrel / (double)ndistinct;
+  // The tiles read their node records from a table of 8 records per
+  // cone id (about 42 KB at P = 144 in FP32, 60 KB in FP64); where that
+  // would exceed 2.5 times the level's coefficients (few boxes per cone
+  // id), only a forced CONE uses them
+  const bool forced = p->opt.prop_kernel == IFGF_PROP_CONE;
+  lv.ti_allowed = forced || (double)ndistinct * 8.0 * (double)ti_geo_bytes(p->opt.p_s, p->opt.p_ang, f32) <=
+                                2.5 * (double)lv.nrel * P * (f32 ? sizeof(cpx<float>) : sizeof(cpx<double>));
+  int nw = nw_req;
+  if (nw < 0) {   // the heuristic
+    nw = per >= 12.0 ? 4 : (per >= 6.0 ? 2 : 0);
+    if (!lv.ti_allowed) nw = 0;
+    if (forced && nw == 0) nw = 1;
+  }
+  if (!f32 && nw > 2) nw = 2;   // FP64 tiles: at most 16 boxes (LDS)
+  if (nw == 0) return 0;
+  const int cap = 8 * nw;
+  // child-octant mask of every box of this level, to order the boxes of
+  // one cone id so that the 8 boxes of a wave tend to share their octants
+  std::vector<int> clo(lv.nb + 1), ccoords(3 * (size_t)std::max(1, p->lev[d + 1].nb)), rbox(lv.nrel);
+  HIPCHK(hipMemcpy(clo.data(), lv.child_lo.p, sizeof(int) * (lv.nb + 1), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ccoords.data(), p->lev[d + 1].coords.p, sizeof(int) * 3 * p->lev[d + 1].nb,
+                   hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(rbox.data(), lv.rel_box.p, sizeof(int) * lv.nrel, hipMemcpyDeviceToHost));
+  std::vector<uint8_t> cmask(lv.nb, 0);
+  for (int b = 0; b < lv.nb; ++b)
+    for (int c = clo[b]; c < clo[b + 1]; ++c)
+      cmask[b] |= (uint8_t)(1u << ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) |
+                                   ((ccoords[3 * c + 2] & 1) << 2)));
+  // Within a cone id the boxes come in Morton order (slot order); they are
+  // sorted by child mask (stable: Morton order within a mask), then cut
+  // into tiles, so that the boxes of a tile - and the 8 rows of a wave -
+  // mostly have children in the same octants (MFMA rows of a box without
+  // a child in the current octant are wasted).
+  std::vector<int> slots(lv.nrel);
+  std::vector<std::array<int, 5>> tl;   // (first box, cid, start, count, 0)
+  for (int64_t i = 0; i < lv.nrel; ++i) slots[i] = (int)(keys[i] & 0xffffffffu);
+  for (int64_t i = 0; i < lv.nrel;) {
+    const int cid = (int)(keys[i] >> 32);
+    int64_t j = i;
+    while (j < lv.nrel && (int)(keys[j] >> 32) == cid) ++j;
+    std::stable_sort(slots.begin() + i, slots.begin() + j,
+                     [&](int x, int y) { return cmask[rbox[x]] < cmask[rbox[y]]; });
+    for (int64_t t = i; t < j; t += cap) {
+      const int cnt = (int)std::min<int64_t>(cap, j - t);
+      int b0 = rbox[slots[t]];
+      for (int u = 1; u < cnt; ++u) b0 = std::min(b0, rbox[slots[t + u]]);
+      tl.push_back({b0, cid, (int)t, cnt, 0});
+    }
+    i = j;
+  }
+  // Order the tiles by first box, so that tiles of different cone ids
+  // over the same boxes - which read the same child cones - run back to
+  // back (and, with the XCD-aware block mapping, on one XCD); except
+  // where a cone id has several tiles (4 or more on average): those stay
+  // together, so that its node records (8 x 5.2 KB at P = 144 in FP32,
+  // 8 x 7.5 KB in FP64) stay in L2 from one tile to the next.
+  if ((int64_t)tl.size() < 4 * ndistinct)
+    std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
+      return x[0] < y[0];
+    });
+  // the node records of each (cone id, octant) are computed once per
+  // level; a tile's fourth entry indexes its cone id's records
+  std::vector<int> qlist;
+  for (const auto& t : tl) qlist.push_back(t[1]);
+  std::sort(qlist.begin(), qlist.end());
+  qlist.erase(std::unique(qlist.begin(), qlist.end()), qlist.end());
+  std::vector<int> tiles;
+  tiles.reserve(tl.size() * 4);
+  for (const auto& t : tl) {
+    tiles.push_back(t[1]);
+    tiles.push_back(t[2]);
+    tiles.push_back(t[3]);
+    tiles.push_back((int)(std::lower_bound(qlist.begin(), qlist.end(), t[1]) - qlist.begin()));
+  }
+  if (!lv.ti_geo_built) {   // the records depend on the cone ids only, not on the tile height
+    build_ti_geo(p, d, qlist, s);
+    lv.ti_geo_built = true;
+  }
+  // each tile box's child per octant, in ti_slot order, so that a tile
+  // reads its boxes' children with one coalesced load
+  std::vector<int> tchild(8 * (size_t)lv.nrel, -1);
+  for (int64_t i = 0; i < lv.nrel; ++i) {
+    const int b = rbox[slots[i]];
+    for (int c = clo[b]; c < clo[b + 1]; ++c)
+      tchild[8 * i + ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) | ((ccoords[3 * c + 2] & 1) << 2))] = c;
+  }
+  lv.ti_nw = nw;
+  lv.ntile = (int64_t)tiles.size() / 4;
+  lv.ti_slot.alloc(sizeof(int) * lv.nrel);
+  lv.ti_tile.alloc(sizeof(int) * tiles.size());
+  lv.ti_child.alloc(sizeof(int) * tchild.size());
+  HIPCHK(hipMemcpy(lv.ti_slot.p, slots.data(), sizeof(int) * lv.nrel, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(lv.ti_tile.p, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(lv.ti_child.p, tchild.data(), sizeof(int) * tchild.size(), hipMemcpyHostToDevice));
+  return nw;
+}
+
 void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const double* w, hipStream_t s) {
   const int64_t n = p->n;
   const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
@@ -698,117 +820,14 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
     if (!wk.empty()) HIPCHK(hipMemcpy(lv.work.p, wk.data(), sizeof(int) * wk.size(), hipMemcpyHostToDevice));
   }
 
-  // ---- cone-major tiles of the upward pass (FP32, one RHS) ------------------------
+  // ---- cone-major tiles of the upward pass (one RHS) ------------------------------
   // Boxes per distinct cone id decide the tile height: 32 boxes (4 waves of
   // 8) from 12 boxes per cone id on - partly filled 4-wave tiles beat fuller
   // 2-wave ones, which leave the CU at 2 waves per SIMD - 16 boxes from 6;
   // AUTO leaves sparser levels to the node formulation (forced CONE: 8).
-  if (cone_prop_supported(p)) {
-    for (int d = 3; d < D; ++d) {
-      LevelPlan& lv = p->lev[d];
-      if (lv.nrel == 0) continue;
-      DevBuf kb;
-      kb.alloc(sizeof(uint64_t) * sort_padded_length(lv.nrel));
-      k_cone_keys<<<nblocks(lv.nrel), TPB, 0, s>>>(lv.rel_cone.as<int>(), lv.nrel, kb.as<uint64_t>());
-      HIPCHK(hipGetLastError());
-      sort_u64(kb.as<uint64_t>(), lv.nrel, s);
-      std::vector<uint64_t> keys(lv.nrel);
-      HIPCHK(hipMemcpyAsync(keys.data(), kb.p, sizeof(uint64_t) * lv.nrel, hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      int64_t ndistinct = 0;
-      for (int64_t i = 0; i < lv.nrel; ++i)
-        if (i == 0 || (keys[i] >> 32) != (keys[i - 1] >> 32)) ++ndistinct;
-      const double per = (double)lv.nrel / (double)ndistinct;
-      int nw = per >= 12.0 ? 4 : (per >= 6.0 ? 2 : 0);
-      if (!f32 && nw > 2) nw = 2;   // FP64 tiles: at most 16 boxes (LDS)
-      // The tiles read their node records from a table of 8 records per
-      // cone id (about 42 KB at P = 144 in FP32, 60 KB in FP64); where that
-      // would exceed 2.5 times the level's coefficients (few boxes per cone
-      // id), AUTO keeps the node formulation
-      const bool forced = p->opt.prop_kernel == IFGF_PROP_CONE;
-      if (!forced && (double)ndistinct * 8.0 * (double)ti_geo_bytes(p->opt.p_s, p->opt.p_ang, f32) >
-                         2.5 * (double)lv.nrel * P * (f32 ? sizeof(cpx<float>) : sizeof(cpx<double>)))
-        nw = 0;
-      if (forced && nw == 0) nw = 1;
-      if (nw == 0) continue;
-      const int cap = 8 * nw;
-      // child-octant mask of every box of this level, to order the boxes of
-      // one cone id so that the 8 boxes of a wave tend to share their octants
-      std::vector<int> clo(lv.nb + 1), ccoords(3 * (size_t)std::max(1, p->lev[d + 1].nb)), rbox(lv.nrel);
-      HIPCHK(hipMemcpy(clo.data(), lv.child_lo.p, sizeof(int) * (lv.nb + 1), hipMemcpyDeviceToHost));
-      HIPCHK(hipMemcpy(ccoords.data(), p->lev[d + 1].coords.p, sizeof(int) * 3 * p->lev[d + 1].nb,
-                       hipMemcpyDeviceToHost));
-      HIPCHK(hipMemcpy(rbox.data(), lv.rel_box.p, sizeof(int) * lv.nrel, hipMemcpyDeviceToHost));
-      std::vector<uint8_t> cmask(lv.nb, 0);
-      for (int b = 0; b < lv.nb; ++b)
-        for (int c = clo[b]; c < clo[b + 1]; ++c)
-          cmask[b] |= (uint8_t)(1u << ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) |
-                                       ((ccoords[3 * c + 2] & 1) << 2)));
-      // Within a cone id the boxes come in Morton order (slot order); they are
-      // sorted by child mask (stable: Morton order within a mask), then cut
-      // into tiles, so that the boxes of a tile - and the 8 rows of a wave -
-      // mostly have children in the same octants (MFMA rows of a box without
-      // a child in the current octant are wasted).
-      std::vector<int> slots(lv.nrel);
-      std::vector<std::array<int, 5>> tl;   // (first box, cid, start, count, 0)
-      for (int64_t i = 0; i < lv.nrel; ++i) slots[i] = (int)(keys[i] & 0xffffffffu);
-      for (int64_t i = 0; i < lv.nrel;) {
-        const int cid = (int)(keys[i] >> 32);
-        int64_t j = i;
-        while (j < lv.nrel && (int)(keys[j] >> 32) == cid) ++j;
-        std::stable_sort(slots.begin() + i, slots.begin() + j,
-                         [&](int x, int y) { return cmask[rbox[x]] < cmask[rbox[y]]; });
-        for (int64_t t = i; t < j; t += cap) {
-          const int cnt = (int)std::min<int64_t>(cap, j - t);
-          int b0 = rbox[slots[t]];
-          for (int u = 1; u < cnt; ++u) b0 = std::min(b0, rbox[slots[t + u]]);
-          tl.push_back({b0, cid, (int)t, cnt, 0});
-        }
-        i = j;
-      }
-      // Order the tiles by first box, so that tiles of different cone ids
-      // over the same boxes - which read the same child cones - run back to
-      // back (and, with the XCD-aware block mapping, on one XCD); except
-      // where a cone id has several tiles (4 or more on average): those stay
-      // together, so that its node records (8 x 5.2 KB at P = 144 in FP32,
-      // 8 x 7.5 KB in FP64) stay in L2 from one tile to the next.
-      if ((int64_t)tl.size() < 4 * ndistinct)
-        std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
-          return x[0] < y[0];
-        });
-      // the node records of each (cone id, octant) are computed once per
-      // level; a tile's fourth entry indexes its cone id's records
-      std::vector<int> qlist;
-      for (const auto& t : tl) qlist.push_back(t[1]);
-      std::sort(qlist.begin(), qlist.end());
-      qlist.erase(std::unique(qlist.begin(), qlist.end()), qlist.end());
-      std::vector<int> tiles;
-      tiles.reserve(tl.size() * 4);
-      for (const auto& t : tl) {
-        tiles.push_back(t[1]);
-        tiles.push_back(t[2]);
-        tiles.push_back(t[3]);
-        tiles.push_back((int)(std::lower_bound(qlist.begin(), qlist.end(), t[1]) - qlist.begin()));
-      }
-      build_ti_geo(p, d, qlist, s);
-      // each tile box's child per octant, in ti_slot order, so that a tile
-      // reads its boxes' children with one coalesced load
-      std::vector<int> tchild(8 * (size_t)lv.nrel, -1);
-      for (int64_t i = 0; i < lv.nrel; ++i) {
-        const int b = rbox[slots[i]];
-        for (int c = clo[b]; c < clo[b + 1]; ++c)
-          tchild[8 * i + ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) | ((ccoords[3 * c + 2] & 1) << 2))] = c;
-      }
-      lv.ti_nw = nw;
-      lv.ntile = (int64_t)tiles.size() / 4;
-      lv.ti_slot.alloc(sizeof(int) * lv.nrel);
-      lv.ti_tile.alloc(sizeof(int) * tiles.size());
-      lv.ti_child.alloc(sizeof(int) * tchild.size());
-      HIPCHK(hipMemcpy(lv.ti_slot.p, slots.data(), sizeof(int) * lv.nrel, hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(lv.ti_tile.p, tiles.data(), sizeof(int) * tiles.size(), hipMemcpyHostToDevice));
-      HIPCHK(hipMemcpy(lv.ti_child.p, tchild.data(), sizeof(int) * tchild.size(), hipMemcpyHostToDevice));
-    }
-  }
+  // ifgf_plan_autotune replaces this choice by measurement.
+  if (cone_prop_supported(p))
+    for (int d = 3; d < D; ++d) build_cone_tiles(p, d, -1, s);
 
   // ---- workspaces -------------------------------------------------------------
   size_t csz = f32 ? sizeof(cpx<float>) : sizeof(cpx<double>);
