@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=5)
     ap.add_argument("--ragged-steps", type=int, default=5, help="applies of the ragged 8-geometry batch (0 = skip)")
     ap.add_argument("--no-peak-probe", action="store_true", help="skip the measured-peak probes")
+    ap.add_argument("--autotune-reps", type=int, default=3,
+                    help="passes per candidate of the plan's formulation autotuner (0 = the built-in heuristic)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the FP32 leg, copy a buffer of this many MiB three times with a plain device copy "
                          "(the reference point that scales HBM byte counters)")
@@ -206,6 +208,13 @@ def main():
         torch.cuda.synchronize()
         t_plan = time.perf_counter() - t0
         log(f"{precision}: plan built in {t_plan:.3f} s")
+        tune, t_tune = None, 0.0
+        if args.autotune_reps > 0:   # measured formulation choice, kept in the plan (plan-time work)
+            t0 = time.perf_counter()
+            tune = plan.autotune(reps=args.autotune_reps)
+            t_tune = time.perf_counter() - t0
+            log(f"{precision}: autotuned in {t_tune:.3f} s: "
+                f"{ {d: e['choice'] for d, e in tune['prop'].items()} } targets {tune['targets']}")
         u = torch.empty_like(sig_d)
         for _ in range(warmup):
             plan.apply(sig_d, out=u[:, None])
@@ -241,7 +250,7 @@ def main():
         log(f"{precision}: {steps} applies, wall {wall * 1e3 / steps:.3f} ms/apply, events median {med:.3f} "
             f"min {per[0]:.3f} ms")
         return dict(plan=plan, t_plan=t_plan, wall=wall, ev_ms=ev_ms, ev_median=med, ev_min=per[0], prof=prof,
-                    stats=st, u=uh, flags=flags)
+                    stats=st, u=uh, flags=flags, tune=tune, t_tune=t_tune)
 
     r32 = run("fp32", args.steps, args.warmup, True)
     st = r32["stats"]
@@ -513,6 +522,8 @@ def main():
         "rel_err": err32,
         "rel_err_targets": len(tg),
         "plan_create_s": r32["t_plan"],
+        "plan_autotune_s": r32["t_tune"],
+        "autotune": r32["tune"],
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,

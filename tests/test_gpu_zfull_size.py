@@ -125,3 +125,29 @@ def test_sphere_32_wavelengths_fp64_high_order_sampled():
     err = float(np.linalg.norm(u[tg] - ref) / np.linalg.norm(ref))
     log(f"  rel l2 err = {err:.3e}")
     assert err <= 1e-6
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("D", [7, 8])
+def test_spheroid_40_wavelengths_small_leaves(D):
+    # The 1.5M-point spheroid with 0.625- and 0.3125-wavelength leaves: the
+    # combined factor keeps the IFGF error within 1e-4 below half a
+    # wavelength, and halving the leaves cuts the near-field pairs about 4x.
+    wl = inputs.workload("spheroid40")
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    n = len(p)
+    sigma = inputs.random_density(n, seed=inputs.config_seed(4))
+    tg = inputs.sample_targets(n, 2048, seed=inputs.config_seed(4) + 100)
+    plan = Plan(p, nr, w, k, k, depth=D, precision="fp32")
+    st = plan.stats()
+    log(f"case spheroid40 D={D}: near pairs {st['near_pairs']:.4g}, cones {st['cones']}")
+    u = plan.apply(to_dev(sigma).to(torch.complex64)).cpu().numpy()
+    assert plan.check() == 0
+    plan.close()
+    ref = direct.apply_c(p, nr, w, k, k, sigma, targets=tg)
+    err = float(np.linalg.norm(u[tg] - ref) / np.linalg.norm(ref))
+    log(f"  rel l2 err = {err:.3e}")
+    assert err < 1e-4
+    if D == 8:
+        assert 2.5e9 < st["near_pairs"] < 3.6e9
