@@ -275,7 +275,14 @@ def main():
             plan.apply_adjoint(sig_d)
         torch.cuda.synchronize()
         adj = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.adjoint_steps, "conjugate": True}
-        log(f"adjoint: {adj['ms_per_step']:.3f} ms/apply")
+        plan.set_profiling(64)   # one more transposed apply with its stages timed
+        plan.apply_adjoint(sig_d)
+        torch.cuda.synchronize()
+        adj["stages"] = {k2: {"ms_per_apply": v2[0], "launches_per_apply": v2[1]}
+                         for k2, v2 in plan.read_profile().items()}
+        plan.set_profiling(0)
+        log(f"adjoint: {adj['ms_per_step']:.3f} ms/apply, stages "
+            f"{ {k2: round(v2['ms_per_apply'], 2) for k2, v2 in adj['stages'].items()} }")
         del v, plan
     r32.pop("plan")
     r64 = run("fp64", args.fp64_steps, 2, False) if args.fp64_steps > 0 else None

@@ -2859,6 +2859,242 @@ __global__ __launch_bounds__(TPB) void k_adj_prop(int nrel_up, const int* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// P^T by gathering, on the levels with node records (the cone-major
+// geometry, inverted).  All boxes of a level have one size, so parent node n
+// of parent cone id q lands, seen from the child in octant o, in a child cone
+// id, at local coordinates and with a ratio that depend on (q, o, n) only:
+// the node records of (q, o), grouped by child cone id.  For a child box B
+// (octant o) and its relevant cone c, the transposed pass is
+//     G[B, c]_j = sum over the record groups (q, o, g) with child cone id c,
+//                 over their nodes n, of ratio * Fhat[P(B), q]_n * T_j(coords),
+// where Fhat[P(B), q] is zero unless q is relevant at the parent P(B).  A
+// wave takes up to 64 child boxes of one (o, c) bucket, one box per lane:
+// the group and node data are uniform across the wave, the parent values
+// are gathered per lane.  Each G[B, c] has one writer (added onto the
+// cousin-target part already there): no atomics, and the same sums in the
+// same order on every run.
+// ---------------------------------------------------------------------------
+template <typename T, int PS, int PA> struct RecOf;
+template <int PS, int PA> struct RecOf<float, PS, PA> { using type = TiGeo<PS, PA>; };
+template <int PS, int PA> struct RecOf<double, PS, PA> { using type = TiGeo64<PS, PA>; };
+
+template <int PS, int PA>
+__device__ __forceinline__ void rec_entry(const TiGeo<PS, PA>& G, int e, float (&c)[3], float (&r)[2]) {
+  const float4 l = G.loc[e];
+  const float2 q = G.rat[e];
+  c[0] = l.x;
+  c[1] = l.y;
+  c[2] = l.z;
+  r[0] = q.x;
+  r[1] = q.y;
+}
+template <int PS, int PA>
+__device__ __forceinline__ void rec_entry(const TiGeo64<PS, PA>& G, int e, double (&c)[3], double (&r)[2]) {
+  c[0] = G.crd[e][0];
+  c[1] = G.crd[e][1];
+  c[2] = G.crd[e][2];
+  r[0] = G.rat[e][0];
+  r[1] = G.rat[e][1];
+}
+
+// Coefficients C0 .. C0 + CN - 1 of the lane's child cone, summed over the bucket's groups.
+template <typename T, int PS, int PA, int C0, int CN>
+__device__ __forceinline__ void adj_gather_chunk(const typename RecOf<T, PS, PA>::type* __restrict__ recs,
+                                                 const int2* __restrict__ gref, int g0, int g1,
+                                                 const int* __restrict__ qlist, const int* __restrict__ slot_p,
+                                                 int ncone_p, int pb, bool valid, const cpx<T>* __restrict__ Fhat_p,
+                                                 cpx<T>* __restrict__ out) {
+  constexpr int P = PS * PA * PA;
+  cpx<T> acc[CN];
+#pragma unroll
+  for (int jj = 0; jj < CN; ++jj) acc[jj] = {0, 0};
+  for (int gi = g0; gi < g1; ++gi) {   // wave-uniform
+    const int2 ref = gref[gi];
+    const auto& G = recs[ref.x];
+    const int q = qlist[ref.x >> 3];
+    const int psl = valid ? slot_p[(int64_t)pb * ncone_p + q] : -1;
+    if (!__ballot(psl >= 0)) continue;   // no box of the tile has this parent cone
+    const cpx<T>* F = Fhat_p + (int64_t)(psl >= 0 ? psl : 0) * P;
+    const int e0 = G.gstart[ref.y], e1 = G.gstart[ref.y + 1];
+    for (int e = e0; e < e1; ++e) {
+      T c[3], r[2];
+      rec_entry<PS, PA>(G, e, c, r);
+      cpx<T> f = {0, 0};
+      if (psl >= 0) f = F[G.node[e]];
+      const T ar = r[0] * f.re - r[1] * f.im, ai = r[0] * f.im + r[1] * f.re;
+      T Ts[PS], Tt[PA], Tp[PA];
+      cheb_T<T, PS>(c[0], Ts);
+      cheb_T<T, PA>(c[1], Tt);
+      cheb_T<T, PA>(c[2], Tp);
+#pragma unroll
+      for (int jj = 0; jj < CN; ++jj) {
+        const int j = C0 + jj;
+        const T b = Ts[j / (PA * PA)] * Tt[(j / PA) % PA] * Tp[j % PA];
+        acc[jj].re += ar * b;
+        acc[jj].im += ai * b;
+      }
+    }
+  }
+  if (valid) {
+#pragma unroll
+    for (int jj = 0; jj < CN; ++jj) {
+      cpx<T> v = out[C0 + jj];
+      v.re += acc[jj].re;
+      v.im += acc[jj].im;
+      out[C0 + jj] = v;
+    }
+  }
+}
+
+template <typename T, int PS, int PA, int C0>
+__device__ __forceinline__ void adj_gather_chunks(const typename RecOf<T, PS, PA>::type* __restrict__ recs,
+                                                  const int2* __restrict__ gref, int g0, int g1,
+                                                  const int* __restrict__ qlist, const int* __restrict__ slot_p,
+                                                  int ncone_p, int pb, bool valid, const cpx<T>* __restrict__ Fhat_p,
+                                                  cpx<T>* __restrict__ out) {
+  constexpr int P = PS * PA * PA;
+  constexpr int CH = Prec<T>::f32 ? 48 : 24;   // accumulators per lane per pass
+  constexpr int CN = P - C0 < CH ? P - C0 : CH;
+  adj_gather_chunk<T, PS, PA, C0, CN>(recs, gref, g0, g1, qlist, slot_p, ncone_p, pb, valid, Fhat_p, out);
+  if constexpr (C0 + CN < P)
+    adj_gather_chunks<T, PS, PA, C0 + CN>(recs, gref, g0, g1, qlist, slot_p, ncone_p, pb, valid, Fhat_p, out);
+}
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(64) void k_adj_ti(const int4* __restrict__ tiles, const int* __restrict__ slots,
+                                               const int2* __restrict__ gref, const int* __restrict__ gref_off,
+                                               const typename RecOf<T, PS, PA>::type* __restrict__ recs,
+                                               const int* __restrict__ qlist, const int* __restrict__ rel_box_c,
+                                               const int* __restrict__ parent_c, const int* __restrict__ slot_p,
+                                               int ncone_p, const cpx<T>* __restrict__ Fhat_p,
+                                               cpx<T>* __restrict__ G_c) {
+  constexpr int P = PS * PA * PA;
+  const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const int lane = threadIdx.x;
+  const bool valid = lane < tl.z;
+  const int cs = valid ? slots[tl.y + lane] : 0;
+  const int pb = valid ? parent_c[rel_box_c[cs]] : 0;
+  adj_gather_chunks<T, PS, PA, 0>(recs, gref, gref_off[tl.x], gref_off[tl.x + 1], qlist, slot_p, ncone_p, pb, valid,
+                                  Fhat_p, G_c + (int64_t)cs * P);
+}
+
+// FP32 with P_s = 4: the same gather on MFMA (v_mfma_f32_16x16x4_f32).  A
+// wave takes 8 child boxes of one bucket: rows = 8 boxes x (re, im), K = the
+// bucket's nodes, 4 per step (a group's last step padded with zeros), columns
+// = the P coefficients in tiles of 16, column 4a + u of tile t being
+// coefficient (a, pair 4t + u) with pair = (b, c), so that a lane's radial
+// index a is fixed and its pair comes from a compile-time set of four.
+// Lane layouts as in the forward kernels: A[i][k] from lane 16k + i, B[k][j]
+// from lane 16k + j, D[4q + v][j] in lane 16q + j, element v.
+template <int PA>
+__global__ __launch_bounds__(64) void k_adj_ti_mfma(const int4* __restrict__ tiles, const int* __restrict__ slots,
+                                                    const int2* __restrict__ gref, const int* __restrict__ gref_off,
+                                                    const TiGeo<4, PA>* __restrict__ recs,
+                                                    const int* __restrict__ qlist, const int* __restrict__ rel_box_c,
+                                                    const int* __restrict__ parent_c, const int* __restrict__ slot_p,
+                                                    int ncone_p, const cpx<float>* __restrict__ Fhat_p,
+                                                    cpx<float>* __restrict__ G_c) {
+  constexpr int PS = 4, NP = PA * PA, P = PS * NP, NT = NP / 4;
+  static_assert(NP % 4 == 0, "pairs in groups of four");
+  const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
+  const int l = threadIdx.x;
+  const int i = l & 15, k = l >> 4;
+  const int bA = i >> 1, partA = i & 1;   // A row: box, re / im
+  const bool validA = bA < tl.z;
+  const int csA = validA ? slots[tl.y + bA] : 0;
+  const int pbA = validA ? parent_c[rel_box_c[csA]] : 0;
+  const int aB = i >> 2, uB = i & 3;      // B column: radial index, pair within the tile's four
+  floatx4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int g0 = gref_off[tl.x], g1 = gref_off[tl.x + 1];
+  for (int gi = g0; gi < g1; ++gi) {   // wave-uniform
+    const int2 ref = gref[gi];
+    const TiGeo<4, PA>& G = recs[ref.x];
+    const int q = qlist[ref.x >> 3];
+    const int psl = validA ? slot_p[(int64_t)pbA * ncone_p + q] : -1;
+    if (!__ballot(psl >= 0)) continue;   // no box of the wave has this parent cone
+    const cpx<float>* F = Fhat_p + (int64_t)(psl >= 0 ? psl : 0) * P;
+    const int e0 = G.gstart[ref.y], e1 = G.gstart[ref.y + 1];
+    for (int e = e0; e < e1; e += 4) {   // wave-uniform
+      const int ek = e + k;
+      const bool ok = ek < e1;
+      const int ee = ok ? ek : e0;
+      const float4 loc = G.loc[ee];
+      const float2 rt = G.rat[ee];
+      cpx<float> f = {0.0f, 0.0f};
+      if (ok && psl >= 0) f = F[G.node[ee]];
+      const float av = partA ? rt.x * f.im + rt.y * f.re : rt.x * f.re - rt.y * f.im;
+      float Ts[PS], Tt[PA], Tp[PA];
+      cheb_T<float, PS>(loc.x, Ts);
+      cheb_T<float, PA>(loc.y, Tt);
+      cheb_T<float, PA>(loc.z, Tp);
+      const float ta = aB == 0 ? Ts[0] : (aB == 1 ? Ts[1] : (aB == 2 ? Ts[2] : Ts[3]));
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int p0 = 4 * t;
+        const float w0 = Tt[(p0 + 0) / PA] * Tp[(p0 + 0) % PA], w1 = Tt[(p0 + 1) / PA] * Tp[(p0 + 1) % PA];
+        const float w2 = Tt[(p0 + 2) / PA] * Tp[(p0 + 2) % PA], w3 = Tt[(p0 + 3) / PA] * Tp[(p0 + 3) % PA];
+        const float bv = ta * (uB == 0 ? w0 : (uB == 1 ? w1 : (uB == 2 ? w2 : w3)));
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  // lane 16 qd + jd holds rows 4 qd .. 4 qd + 3 = boxes 2 qd (re, im), 2 qd + 1 (re, im) of column jd
+  const int qd = l >> 4, jd = l & 15;
+  const int aD = jd >> 2, uD = jd & 3;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int bx = 2 * qd + h;
+    if (bx >= tl.z) continue;
+    cpx<float>* out = G_c + (int64_t)slots[tl.y + bx] * P + aD * NP + uD;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      cpx<float> v = out[4 * t];
+      v.re += acc[t][2 * h];
+      v.im += acc[t][2 * h + 1];
+      out[4 * t] = v;
+    }
+  }
+}
+
+// Groups per node record.
+template <typename Rec>
+__global__ __launch_bounds__(TPB) void k_rec_ngroup(const Rec* __restrict__ recs, int64_t nrec, int* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (r < nrec) out[r] = recs[r].ngroup;
+}
+
+// One key per (record r = 8 qi + o, group g): bucket (o, child cone id) high,
+// (qi, g) low, so that a bucket's groups sort by parent cone, then group.
+template <typename Rec>
+__global__ __launch_bounds__(TPB) void k_rec_keys(const Rec* __restrict__ recs, int64_t nrec,
+                                                  const int64_t* __restrict__ off, int ncone_c,
+                                                  uint64_t* __restrict__ keys) {
+  const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (r >= nrec) return;
+  const int o = (int)(r & 7);
+  const uint32_t qi = (uint32_t)(r >> 3);
+  const int ng = recs[r].ngroup;
+  for (int g = 0; g < ng; ++g) {
+    const uint64_t bucket = (uint64_t)o * (uint64_t)ncone_c + (uint64_t)recs[r].gcid[g];
+    keys[off[r] + g] = (bucket << 32) | (uint64_t)((qi << 8) | (uint32_t)g);
+  }
+}
+
+// One key per relevant cone of the child level: bucket (octant of its box, cone id) high, slot low.
+__global__ __launch_bounds__(TPB) void k_adj_child_keys(const int* __restrict__ rel_box, const int* __restrict__ rel_cone,
+                                                        const int* __restrict__ coords, int64_t nrel, int ncone,
+                                                        uint64_t* __restrict__ keys) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= nrel) return;
+  const int b = rel_box[i];
+  const int o = (coords[3 * b] & 1) | ((coords[3 * b + 1] & 1) << 1) | ((coords[3 * b + 2] & 1) << 2);
+  const uint64_t bucket = (uint64_t)o * (uint64_t)ncone + (uint64_t)rel_cone[i];
+  keys[i] = (bucket << 32) | (uint64_t)(uint32_t)i;
+}
+
 // L^T: each source y of a finest-level box gets sum over the box's relevant
 // cones and their nodes of W_c(node, y) Fhat(node), added to acc.  The
 // sources are taken SC at a time; each thread sums its share of the nodes in
@@ -3288,6 +3524,87 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
   HIPCHK(hipGetLastError());
 }
 
+// The gather index of the transposed upward pass from level d (node records)
+// into level d + 1: built once, at the first transposed apply.
+// The MFMA form of the gather: FP32 with P_s = 4 (8 boxes per wave).
+template <typename T, int PS, int PA>
+constexpr bool adj_mfma() { return Prec<T>::f32 && PS == 4 && (PA * PA) % 4 == 0; }
+
+template <typename T, int PS, int PA>
+void build_adj_gather(ifgf_plan_s* p, int d, hipStream_t s) {
+  using Rec = typename RecOf<T, PS, PA>::type;
+  LevelPlan& lv = p->lev[d];
+  LevelPlan& lc = p->lev[d + 1];
+  const int nc = lc.geom.ncone;
+  const int64_t nrec = 8 * lv.ti_nq;
+  const Rec* recs = lv.ti_geo.as<Rec>();
+  // (record, group) pairs by (octant, child cone id), then parent cone, then group
+  DevBuf ngd;
+  ngd.alloc(sizeof(int) * nrec);
+  k_rec_ngroup<Rec><<<nblocks(nrec), TPB, 0, s>>>(recs, nrec, ngd.as<int>());
+  HIPCHK(hipGetLastError());
+  std::vector<int> ng(nrec);
+  HIPCHK(hipMemcpyAsync(ng.data(), ngd.p, sizeof(int) * nrec, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int64_t> off(nrec + 1, 0);
+  for (int64_t r = 0; r < nrec; ++r) off[r + 1] = off[r] + ng[r];
+  const int64_t total = off[nrec];
+  DevBuf offd, keys;
+  offd.alloc(sizeof(int64_t) * (nrec + 1));
+  keys.alloc(sizeof(uint64_t) * sort_padded_length(std::max<int64_t>(1, total)));
+  HIPCHK(hipMemcpyAsync(offd.p, off.data(), sizeof(int64_t) * (nrec + 1), hipMemcpyHostToDevice, s));
+  k_rec_keys<Rec><<<nblocks(nrec), TPB, 0, s>>>(recs, nrec, offd.as<int64_t>(), nc, keys.as<uint64_t>());
+  HIPCHK(hipGetLastError());
+  sort_u64(keys.as<uint64_t>(), total, s);
+  std::vector<uint64_t> hk(total);
+  HIPCHK(hipMemcpyAsync(hk.data(), keys.p, sizeof(uint64_t) * total, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t nbucket = 8 * (int64_t)nc;
+  std::vector<int> goff(nbucket + 1, 0);
+  std::vector<int2> gref(std::max<int64_t>(1, total));
+  for (int64_t i = 0; i < total; ++i) {
+    const int64_t bucket = (int64_t)(hk[i] >> 32);
+    const uint32_t lo = (uint32_t)hk[i];
+    const int o = (int)(bucket / nc);
+    gref[i] = make_int2((int)((lo >> 8) * 8 + o), (int)(lo & 255));
+    ++goff[bucket + 1];
+  }
+  for (int64_t b = 0; b < nbucket; ++b) goff[b + 1] += goff[b];
+  // the child level's relevant cones by (octant, cone id, slot), in tiles of <= 64
+  DevBuf ck;
+  ck.alloc(sizeof(uint64_t) * sort_padded_length(std::max<int64_t>(1, lc.nrel)));
+  k_adj_child_keys<<<nblocks(lc.nrel), TPB, 0, s>>>(lc.rel_box.as<int>(), lc.rel_cone.as<int>(), lc.coords.as<int>(),
+                                                   lc.nrel, nc, ck.as<uint64_t>());
+  HIPCHK(hipGetLastError());
+  sort_u64(ck.as<uint64_t>(), lc.nrel, s);
+  std::vector<uint64_t> hc(lc.nrel);
+  HIPCHK(hipMemcpyAsync(hc.data(), ck.p, sizeof(uint64_t) * lc.nrel, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  std::vector<int> slots(std::max<int64_t>(1, lc.nrel));
+  std::vector<int4> tiles;
+  for (int64_t i = 0; i < lc.nrel;) {
+    const uint64_t bucket = hc[i] >> 32;
+    int64_t j = i;
+    while (j < lc.nrel && (hc[j] >> 32) == bucket) ++j;
+    const int cap = adj_mfma<T, PS, PA>() ? 8 : 64;   // boxes per wave
+    for (int64_t t = i; t < j; t += cap)
+      tiles.push_back(make_int4((int)bucket, (int)t, (int)std::min<int64_t>(cap, j - t), 0));
+    i = j;
+  }
+  for (int64_t i = 0; i < lc.nrel; ++i) slots[i] = (int)(uint32_t)hc[i];
+  lv.adj_gref.alloc(sizeof(int2) * gref.size());
+  lv.adj_gref_off.alloc(sizeof(int) * goff.size());
+  lv.adj_slots.alloc(sizeof(int) * slots.size());
+  lv.adj_tiles.alloc(sizeof(int4) * std::max<size_t>(1, tiles.size()));
+  HIPCHK(hipMemcpy(lv.adj_gref.p, gref.data(), sizeof(int2) * gref.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(lv.adj_gref_off.p, goff.data(), sizeof(int) * goff.size(), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(lv.adj_slots.p, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice));
+  if (!tiles.empty())
+    HIPCHK(hipMemcpy(lv.adj_tiles.p, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice));
+  lv.adj_ntile = (int64_t)tiles.size();
+  lv.adj_built = true;
+}
+
 template <typename T, int PS, int PA>
 void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, int conj, hipStream_t s) {
   constexpr int P = PS * PA * PA;
@@ -3345,6 +3662,27 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
       if (d == D || lv.nrel == 0) continue;
       LevelPlan& lc = p->lev[d + 1];
       int64_t items = (int64_t)lv.nrel * P;
+      if constexpr (cone_major_order(PS, PA)) {
+        if (R == 1 && lv.ti_geo_built) {   // gather form: one writer per child coefficient
+          if (!lv.adj_built) build_adj_gather<T, PS, PA>(p, d, s);
+          StageTimer tm(p, s, IFGF_STAGE_ADJ_PROP);
+          if constexpr (adj_mfma<T, PS, PA>()) {
+            if (lv.adj_ntile > 0)
+              k_adj_ti_mfma<PA><<<(unsigned)lv.adj_ntile, 64, 0, s>>>(
+                  lv.adj_tiles.as<int4>(), lv.adj_slots.as<int>(), lv.adj_gref.as<int2>(),
+                  lv.adj_gref_off.as<int>(), lv.ti_geo.as<TiGeo<4, PA>>(), lv.ti_qlist.as<int>(),
+                  lc.rel_box.as<int>(), lc.parent.as<int>(), lv.slot.as<int>(), lv.geom.ncone,
+                  (const cpx<float>*)p->adj_g[d].p, (cpx<float>*)p->adj_g[d + 1].p);
+          } else if (lv.adj_ntile > 0)
+            k_adj_ti<T, PS, PA><<<(unsigned)lv.adj_ntile, 64, 0, s>>>(
+                lv.adj_tiles.as<int4>(), lv.adj_slots.as<int>(), lv.adj_gref.as<int2>(), lv.adj_gref_off.as<int>(),
+                lv.ti_geo.as<typename RecOf<T, PS, PA>::type>(), lv.ti_qlist.as<int>(), lc.rel_box.as<int>(),
+                lc.parent.as<int>(), lv.slot.as<int>(), lv.geom.ncone, p->adj_g[d].as<cpx<T>>(),
+                p->adj_g[d + 1].as<cpx<T>>());
+          HIPCHK(hipGetLastError());
+          continue;
+        }
+      }
       {
         StageTimer tm(p, s, IFGF_STAGE_ADJ_PROP);
         k_adj_prop<T, PS, PA><<<dim3(nblocks(items), R), TPB, 0, s>>>(

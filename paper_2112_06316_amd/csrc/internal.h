@@ -80,6 +80,19 @@ struct LevelPlan {
   int ti_nw = 0;              // 0: this level uses the node formulation
   bool ti_allowed = false;    // the node-record table fits the memory rule (or CONE is forced)
   bool ti_geo_built = false;  // ti_geo holds this level's node records
+  DevBuf ti_qlist;            // int [ti_nq]: the cone id of records 8 q .. 8 q + 7
+  int64_t ti_nq = 0;
+  // Transposed upward pass into level d + 1 by gathering (built at the first
+  // transposed apply, where this level has node records): the relevant cones
+  // of level d + 1 in (child octant, cone id, slot) order, cut into tiles of
+  // up to 64 with one (octant, cone id) bucket; per bucket, the (record,
+  // group) pairs of this level's records whose nodes fall in that cone.
+  DevBuf adj_tiles;           // int4 (bucket = octant * ncone(d+1) + cone id, first index into adj_slots, count, 0)
+  DevBuf adj_slots;           // int [nrel(d+1)]
+  DevBuf adj_gref;            // int2 (record index, group)
+  DevBuf adj_gref_off;        // int [8 * ncone(d+1) + 1]
+  int64_t adj_ntile = 0;
+  bool adj_built = false;
   // statistics
   int64_t cousin_pairs = 0;
   int64_t prop_evals = 0;     // child interpolations into level d-1 nodes

@@ -466,6 +466,9 @@ int build_cone_tiles(ifgf_plan_s* p, int d, int nw_req, hipStream_t s) {
   }
   if (!lv.ti_geo_built) {   // the records depend on the cone ids only, not on the tile height
     build_ti_geo(p, d, qlist, s);
+    lv.ti_qlist.alloc(sizeof(int) * qlist.size());
+    HIPCHK(hipMemcpy(lv.ti_qlist.p, qlist.data(), sizeof(int) * qlist.size(), hipMemcpyHostToDevice));
+    lv.ti_nq = (int64_t)qlist.size();
     lv.ti_geo_built = true;
   }
   // each tile box's child per octant, in ti_slot order, so that a tile

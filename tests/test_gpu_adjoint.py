@@ -28,6 +28,8 @@ def to_dev(x):
 
 CASES = [
     ("sphere4", lambda: inputs.cubed_sphere(32), 8 * np.pi, 4, dict()),
+    ("sphere4_cone", lambda: inputs.cubed_sphere(32), 8 * np.pi, 4, dict(prop_kernel="cone")),
+    ("sphere8_cone", lambda: inputs.cubed_sphere(48), 16 * np.pi, 5, dict(prop_kernel="cone")),
     ("sphere4_paper", lambda: inputs.cubed_sphere(32), 8 * np.pi, 4, dict(p_s=3, p_ang=5, ns0=1, nc0=2)),
     ("ellipsoid", lambda: inputs.ellipsoid(20, (0.5, 0.375, 0.25)), 12 * np.pi, 5, dict()),
 ]
@@ -139,3 +141,24 @@ def test_autograd_gradient_matches_finite_differences_and_dense():
     err = np.linalg.norm(g - gd) / np.linalg.norm(gd)
     log(f"  grad vs dense rel err {err:.3e}")
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_gathered_transposed_pass_equals_scattered(precision, tol):
+    # Levels with node records run the transposed upward pass by gathering
+    # (one writer per child coefficient); without records it scatters with
+    # atomics.  Both are the transpose of the same forward operator.
+    wl = inputs.workload("sphere16")                          # N = 98,304, D = 6
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    v = to_dev(inputs.random_density(len(p), seed=24))
+    if precision == "fp32":
+        v = v.to(torch.complex64)
+    out = {}
+    for prop in ("cone", "node"):
+        plan = Plan(p, nr, w, k, k, depth=wl["depth"], precision=precision, prop_kernel=prop)
+        out[prop] = plan.apply_adjoint(v, conjugate=True).to(torch.complex128).cpu().numpy()
+        assert plan.check() == 0
+    e = np.linalg.norm(out["cone"] - out["node"]) / np.linalg.norm(out["node"])
+    log(f"case gathered vs scattered transposed pass {precision}: rel diff {e:.2e}")
+    assert e <= tol
