@@ -90,8 +90,8 @@ typedef struct {
     int32_t prop_kernel;    /* upward pass with one right-hand side: IFGF_PROP_AUTO
                                (default), IFGF_PROP_NODE or IFGF_PROP_CONE (below)          */
     int32_t target_kernel;  /* cousin-target stage with one right-hand side:
-                               IFGF_TARGET_AUTO (default), IFGF_TARGET_WAVE or
-                               IFGF_TARGET_ROWS (below)                                    */
+                               IFGF_TARGET_AUTO (default), IFGF_TARGET_WAVE,
+                               IFGF_TARGET_ROWS or IFGF_TARGET_PAIRS (below)               */
     int32_t far_field;      /* 1: also make the far-field cones relevant - every level-3
                                cone whose radial interval starts at s = 0 (x at infinity,
                                any direction) and, by eq. RelevantCones' node rule, what
@@ -123,9 +123,15 @@ enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2 };
  * together, load the row's current cone across the row and contract with the
  * coefficients broadcast between lanes (no LDS); levels run as separate
  * work-groups and are added afterwards, which needs n x (D - 2) complex values
- * (plan precision) of plan memory.  AUTO = ROWS.  Both give the same operator
- * up to rounding. */
-enum { IFGF_TARGET_AUTO = 0, IFGF_TARGET_WAVE = 1, IFGF_TARGET_ROWS = 2 };
+ * (plan precision) of plan memory.  PAIRS: the plan lists every (target,
+ * cousin box) pair of every level with its cone slot, local coordinates and
+ * centred factor, sorted by cone; a row of 16 lanes then mostly holds pairs
+ * of one cone, evaluates them with the row stage of ROWS, and a second pass
+ * sums each target's pairs in the order ROWS uses; about 40 bytes (FP32) or
+ * 72 bytes (FP64) per pair of plan memory, built for at most 2^28 pairs.
+ * AUTO = PAIRS where the lists were built, else ROWS.  All give the same
+ * operator up to rounding. */
+enum { IFGF_TARGET_AUTO = 0, IFGF_TARGET_WAVE = 1, IFGF_TARGET_ROWS = 2, IFGF_TARGET_PAIRS = 3 };
 
 /* Plan statistics (host struct). */
 #define IFGF_MAX_LEVELS 12
@@ -320,8 +326,9 @@ void ifgf_plan_destroy(ifgf_plan p);
  * the precision - FP64 tiles hold at most 16 boxes - and the node-record
  * memory rule allow), `reps` passes each with HIP events, and keeps the
  * fastest; then (target_kernel AUTO, orders with row-broadcast targets) it
- * times `reps` whole applies with row-broadcast and with per-wave cousin
- * targets and keeps the faster.  The choices persist in the plan and every
+ * times `reps` whole applies with row-broadcast, per-wave and (where the plan
+ * holds them) pair-list cousin targets and keeps the fastest; the pair lists
+ * are released when they lose.  The choices persist in the plan and every
  * later apply uses them; results change only by rounding.  A plan with a
  * ragged batch built over it cannot be tuned (EBUSY: the batch's queue
  * points into the buffers the tuner rebuilds); tune before creating
@@ -335,8 +342,9 @@ typedef struct {
     int32_t choice[IFGF_MAX_LEVELS];        /* 0: node formulation; 8, 16, 32: boxes per tile */
     double ms[IFGF_MAX_LEVELS][4];          /* ms per pass: node, 8-, 16-, 32-box tiles; -1 if
                                                not a candidate                                */
-    int32_t target_choice;                  /* IFGF_TARGET_ROWS or _WAVE; 0 if not tuned      */
-    double target_ms[2];                    /* ms per apply with row, with wave targets; -1   */
+    int32_t target_choice;                  /* IFGF_TARGET_ROWS, _WAVE or _PAIRS; 0 if not tuned */
+    double target_ms[3];                    /* ms per apply with row, wave, pair-list targets;
+                                               -1 if not a candidate                          */
 } ifgf_tune_report;
 ifgf_status ifgf_plan_autotune(ifgf_plan p, int32_t reps, ifgf_tune_report *report, void *stream);
 

@@ -24,7 +24,7 @@ def library_path() -> str:
 _PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32_INTERP}
 _KERNEL = {"combined": L.KERNEL_COMBINED, "constant": L.KERNEL_CONSTANT}
 _PROP = {"auto": L.PROP_AUTO, "node": L.PROP_NODE, "cone": L.PROP_CONE}
-_TARGET = {"auto": L.TARGET_AUTO, "wave": L.TARGET_WAVE, "rows": L.TARGET_ROWS}
+_TARGET = {"auto": L.TARGET_AUTO, "wave": L.TARGET_WAVE, "rows": L.TARGET_ROWS, "pairs": L.TARGET_PAIRS}
 
 
 def _stream_ptr(device) -> int:
@@ -183,9 +183,9 @@ class Plan:
                 "choice": "node" if r.choice[i] == 0 else f"tile{r.choice[i]}",
                 "ms": {names[c]: r.ms[i][c] for c in range(4) if r.ms[i][c] >= 0},
             }
-        tgt = {L.TARGET_ROWS: "rows", L.TARGET_WAVE: "wave"}.get(r.target_choice)
-        return {"prop": levels, "targets": tgt,
-                "targets_ms": {"rows": r.target_ms[0], "wave": r.target_ms[1]} if tgt else None}
+        tgt = {L.TARGET_ROWS: "rows", L.TARGET_WAVE: "wave", L.TARGET_PAIRS: "pairs"}.get(r.target_choice)
+        ms = {name: r.target_ms[i] for i, name in enumerate(("rows", "wave", "pairs")) if r.target_ms[i] >= 0}
+        return {"prop": levels, "targets": tgt, "targets_ms": ms if tgt else None}
 
     def far_field(self, sigma, dirs):
         """Far-field pattern u_inf at unit directions dirs (m, 3) (eq. FarField),

@@ -1305,6 +1305,216 @@ __global__ __launch_bounds__(TPB) void k_targets_sum(int64_t n, const int* __res
 }
 
 // ---------------------------------------------------------------------------
+// Cousin targets from plan-time pair lists (one RHS, orders with a row stage).
+// The plan lists, per level, every (target, cousin box) pair with its cone
+// slot, local coordinates and centred factor e^{ikr}/(4 pi r) (the same
+// expressions as the row-broadcast formulation), sorted by slot, i.e. by
+// (box, cone).  Pass one: each row of 16 lanes takes 16 consecutive pairs,
+// which mostly share one cone, loads that cone across the row once and
+// contracts by DPP broadcast (the row stage), and writes each pair's value.
+// Pass two: each target sums its pairs' values in cousin order within a
+// level and the levels from the finest down, as the row-broadcast
+// formulation does, so the two formulations give the same sums.
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+
+template <typename T> struct PLevel {
+  int64_t np;
+  const int* slot;
+  const typename Vec4<T>::type* loc;
+  const T* fim;
+  cpx<T>* val;
+  const int* off;
+  const int* pos;
+  const cpx<T>* Fc;
+};
+template <typename T> struct PLevels {
+  PLevel<T> lv[IFGF_MAX_LEVELS];
+};
+
+// One thread per target: its cousin pairs at level lv, in cousin order.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_pair_gen(const double* __restrict__ pts, int64_t n, TLevel<T> lv,
+                                                  const int* __restrict__ off, double k, int kind,
+                                                  uint64_t* __restrict__ keys, typename Vec4<T>::type* __restrict__ tloc,
+                                                  T* __restrict__ tfim, int* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  const int A = lv.pbox[i];
+  const int c0 = lv.cou_off[A], cnt = lv.cou_off[A + 1] - c0;
+  const int64_t o = off[i];
+  const double x[3] = {pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]};
+  for (int t = 0; t < cnt; ++t) {
+    const int B = lv.cou[c0 + t];
+    double rr;
+    int cid;
+    T ts, tt, tp, e_re, e_im;
+    if constexpr (Prec<T>::f32) {
+      const LocF loc = target_loc32(x, gen(lv.centre) + 3 * B, lv.g, &rr);
+      cid = loc.cid;
+      ts = loc.ts;
+      tt = loc.tt;
+      tp = loc.tp;
+      if (kind == IFGF_KERNEL_CONSTANT) {
+        e_re = 1;
+        e_im = 0;
+      } else {
+        float c, sn;
+        expi_reduced32(k * rr, &c, &sn);
+        const float g = (float)(1.0 / (4.0 * IFGF_PI)) / (float)rr;
+        e_re = g * c;
+        e_im = g * sn;
+      }
+    } else {
+      const Loc loc = target_loc64(x, gen(lv.centre) + 3 * B, lv.g, &rr);
+      cid = loc.cid;
+      ts = loc.ts;
+      tt = loc.tt;
+      tp = loc.tp;
+      if (kind == IFGF_KERNEL_CONSTANT) {
+        e_re = 1;
+        e_im = 0;
+      } else {
+        double c, sn;
+        sincos(k * rr, &sn, &c);
+        const double g = (1.0 / (4.0 * IFGF_PI)) / rr;
+        e_re = g * c;
+        e_im = g * sn;
+      }
+    }
+    int sl = lv.slot[(int64_t)B * lv.g.ncone + cid];
+    if (sl < 0) {
+      atomicOr(err, 4);
+      sl = 0;
+      e_re = e_im = 0;
+    }
+    keys[o + t] = ((uint64_t)(uint32_t)sl << 32) | (uint64_t)(uint32_t)(o + t);
+    tloc[o + t] = {ts, tt, tp, e_re};
+    tfim[o + t] = e_im;
+  }
+}
+
+// Sorted position q holds original pair orig = low word of its key.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_pair_place(const uint64_t* __restrict__ keys, int64_t np,
+                                                    const typename Vec4<T>::type* __restrict__ tloc,
+                                                    const T* __restrict__ tfim, int* __restrict__ slot,
+                                                    typename Vec4<T>::type* __restrict__ loc, T* __restrict__ fim,
+                                                    int* __restrict__ pos) {
+  const int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q >= np) return;
+  const uint64_t key = keys[q];
+  const int64_t orig = (int64_t)(uint32_t)key;
+  slot[q] = (int)(key >> 32);
+  loc[q] = tloc[orig];
+  fim[q] = tfim[orig];
+  pos[orig] = (int)q;
+}
+
+// Pass one: the value of every pair of level dlo + blockIdx.y.
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
+  constexpr int P = PS * PA * PA;
+  using S1 = RowStage1<T, PS, PA>;
+  constexpr int NREG = S1::NREG;
+  constexpr int NONE = 0x7fffffff;
+  const PLevel<T>& lv = L.lv[dlo + blockIdx.y];
+  const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB;
+  if (q0 >= lv.np) return;   // block-uniform
+  const int64_t q = q0 + threadIdx.x;
+  const bool valid = q < lv.np;
+  const int sl = valid ? lv.slot[q] : NONE;
+  typename Vec4<T>::type lc = {0, 0, 0, 0};
+  T fim = 0;
+  if (valid) {
+    lc = lv.loc[q];
+    fim = lv.fim[q];
+  }
+  T Ts[PS], Tt[PA], Tp[PA];
+  cheb_T<T, PS>(lc.x, Ts);
+  cheb_T<T, PA>(lc.y, Tt);
+  cheb_T<T, PA>(lc.z, Tp);
+  const int nl = threadIdx.x & 15;
+  const T* F = reinterpret_cast<const T*>(lv.Fc);
+  T o_re = 0, o_im = 0;
+  bool pend = valid;
+  while (__ballot(pend)) {
+    const int su = row_min16(pend ? sl : NONE);
+    T c[NREG];
+    row_load_cone<P, NREG>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, c);
+    T D[2 * PS * PA];
+    S1::run(c, Tp, D);
+    T h_re[PS], h_im[PS];
+#pragma unroll
+    for (int a = 0; a < PS; ++a) {
+      h_re[a] = D[2 * a * PA];
+      h_im[a] = D[2 * a * PA + 1];
+#pragma unroll
+      for (int b = 1; b < PA; ++b) {
+        h_re[a] += D[2 * (a * PA + b)] * Tt[b];
+        h_im[a] += D[2 * (a * PA + b) + 1] * Tt[b];
+      }
+    }
+    T v_re = h_re[0], v_im = h_im[0];
+#pragma unroll
+    for (int a = 1; a < PS; ++a) {
+      v_re += h_re[a] * Ts[a];
+      v_im += h_im[a] * Ts[a];
+    }
+    if (pend && sl == su) {
+      o_re = lc.w * v_re - fim * v_im;
+      o_im = lc.w * v_im + fim * v_re;
+      pend = false;
+    }
+  }
+  if (valid) lv.val[q] = {o_re, o_im};
+}
+
+// Pass two: u = near field + per level (finest first) the sum of the
+// target's pair values in cousin order; scattered to the caller's order.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_targets_pairsum(int64_t n, const int* __restrict__ perm,
+                                                         const cpx<T>* __restrict__ uacc, int use_near,
+                                                         PLevels<T> L, int dlo, int dhi, int dtype,
+                                                         void* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  double re = 0, im = 0;
+  if (use_near) {
+    re = uacc[i].re;
+    im = uacc[i].im;
+  }
+  for (int d = dhi; d >= dlo; --d) {
+    const PLevel<T>& lv = L.lv[d];
+    T lre = 0, lim = 0;
+    for (int t = lv.off[i]; t < lv.off[i + 1]; ++t) {
+      const cpx<T> v = lv.val[lv.pos[t]];
+      lre += v.re;
+      lim += v.im;
+    }
+    re += lre;
+    im += lim;
+  }
+  const int64_t o = perm[i];
+  if (dtype == IFGF_C128) {
+    ((double*)u)[2 * o] = re;
+    ((double*)u)[2 * o + 1] = im;
+  } else {
+    ((float*)u)[2 * o] = (float)re;
+    ((float*)u)[2 * o + 1] = (float)im;
+  }
+}
+
+// per target, the number of its cousin pairs at a level
+__global__ __launch_bounds__(TPB) void k_pair_count(const int* __restrict__ pbox, const int* __restrict__ cou_off,
+                                                    int64_t n, int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i < n) cnt[i] = cou_off[pbox[i] + 1] - cou_off[pbox[i]];
+}
+
+// ---------------------------------------------------------------------------
 // Batched right-hand sides on MFMA (FP32 mode, nrhs a multiple of 16).
 //
 // For the 64 evaluations held by a wave (one per lane: a target and a cousin
@@ -3501,6 +3711,26 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     }
   }
   if constexpr (RowStage1<T, PS, PA>::ok) {   // orders with a generated row stage
+    if (R == 1 && p->pairs && (p->opt.target_kernel == IFGF_TARGET_AUTO || p->opt.target_kernel == IFGF_TARGET_PAIRS)) {
+      StageTimer tm(p, s, IFGF_STAGE_TARGETS);
+      PLevels<T> PL{};
+      int64_t maxp = 0;
+      for (int d = 3; d <= D; ++d) {
+        LevelPlan& lv = p->lev[d];
+        PL.lv[d] = {lv.npair, lv.pr_slot.as<int>(), lv.pr_loc.as<typename Vec4<T>::type>(), lv.pr_fim.as<T>(),
+                    lv.pr_val.as<cpx<T>>(), lv.pr_off.as<int>(), lv.pr_pos.as<int>(), lv.Fc.as<cpx<T>>()};
+        if (d >= dlo && d <= dhi) maxp = std::max(maxp, lv.npair);
+      }
+      const int nlev = dlo <= dhi ? dhi - dlo + 1 : 0;
+      if (nlev > 0 && maxp > 0) {
+        k_targets_pairs<T, PS, PA><<<dim3(nblocks(maxp), nlev), TPB, 0, s>>>(PL, dlo);
+        HIPCHK(hipGetLastError());
+      }
+      k_targets_pairsum<T><<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), uacc, near ? 1 : 0, PL, dlo, dhi, dtype,
+                                                     u);
+      HIPCHK(hipGetLastError());
+      return;
+    }
     if (R == 1 && p->opt.target_kernel != IFGF_TARGET_WAVE) {
       StageTimer tm(p, s, IFGF_STAGE_TARGETS);
       const int nlev = dlo <= dhi ? dhi - dlo + 1 : 0;
@@ -4297,15 +4527,20 @@ void autotune_impl(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t 
     }
     rep->nlevels = nl;
   }
-  rep->target_ms[0] = rep->target_ms[1] = -1.0;
+  rep->target_ms[0] = rep->target_ms[1] = rep->target_ms[2] = -1.0;
   if constexpr (RowStage1<T, PS, PA>::ok) {
     if (p->opt.target_kernel == IFGF_TARGET_AUTO && p->tpart.bytes > 0) {
-      p->opt.target_kernel = IFGF_TARGET_ROWS;
-      rep->target_ms[0] = timed(full_apply);
-      p->opt.target_kernel = IFGF_TARGET_WAVE;
-      rep->target_ms[1] = timed(full_apply);
-      p->opt.target_kernel = rep->target_ms[0] <= rep->target_ms[1] ? IFGF_TARGET_ROWS : IFGF_TARGET_WAVE;
-      rep->target_choice = p->opt.target_kernel;
+      static const int kT[3] = {IFGF_TARGET_ROWS, IFGF_TARGET_WAVE, IFGF_TARGET_PAIRS};
+      int best = -1;
+      for (int c = 0; c < 3; ++c) {
+        if (kT[c] == IFGF_TARGET_PAIRS && !p->pairs) continue;
+        p->opt.target_kernel = kT[c];
+        rep->target_ms[c] = timed(full_apply);
+        if (best < 0 || rep->target_ms[c] < rep->target_ms[best]) best = c;
+      }
+      p->opt.target_kernel = kT[best];
+      rep->target_choice = kT[best];
+      if (kT[best] != IFGF_TARGET_PAIRS && p->pairs) release_target_pairs(p);
     }
   }
   (void)hipEventDestroy(e0);
@@ -4390,6 +4625,90 @@ bool supported_order(int ps, int pa, int precision) {
 
 bool cone_prop_supported(const ifgf_plan_s* p) {
   return p->opt.p_s <= 4 && p->opt.prop_kernel != IFGF_PROP_NODE && order_in_all(p->opt.p_s, p->opt.p_ang);
+}
+
+template <typename T>
+void build_target_pairs_impl(ifgf_plan_s* p, hipStream_t s) {
+  using V4 = typename Vec4<T>::type;
+  const int64_t n = p->n;
+  DevBuf cnt;
+  cnt.alloc(sizeof(int) * (n + 1));
+  for (int d = 3; d <= p->D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    lv.pr_off.alloc(sizeof(int) * (n + 1));
+    k_pair_count<<<nblocks(n), TPB, 0, s>>>(lv.pbox.as<int>(), lv.cou_off.as<int>(), n, cnt.as<int>());
+    HIPCHK(hipGetLastError());
+    scan_exclusive_i32(cnt.as<int>(), lv.pr_off.as<int>(), n, s);
+    int np32 = 0;   // the list's length: the scan's total
+    HIPCHK(hipMemcpyAsync(&np32, lv.pr_off.as<int>() + n, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const int64_t np = np32;
+    lv.npair = np;
+    const size_t npa = (size_t)std::max<int64_t>(1, np);
+    lv.pr_slot.alloc(sizeof(int) * npa);
+    lv.pr_loc.alloc(sizeof(V4) * npa);
+    lv.pr_fim.alloc(sizeof(T) * npa);
+    lv.pr_val.alloc(sizeof(cpx<T>) * npa);
+    lv.pr_pos.alloc(sizeof(int) * npa);
+    if (np == 0) continue;
+    DevBuf keys, tloc, tfim;
+    keys.alloc(sizeof(uint64_t) * sort_padded_length(np));
+    tloc.alloc(sizeof(V4) * npa);
+    tfim.alloc(sizeof(T) * npa);
+    TLevel<T> tl{gas(lv.pbox.as<const int>()), gas(lv.cou_off.as<const int>()), gas(lv.cou.as<const int>()),
+                 gas(lv.centre.as<const double>()), gas(lv.slot.as<const int>()), gas(lv.Fc.as<const cpx<T>>()),
+                 lv.geom};
+    k_pair_gen<T><<<nblocks(n), TPB, 0, s>>>(p->pts.as<double>(), n, tl, lv.pr_off.as<int>(), p->k, p->opt.kernel,
+                                            keys.as<uint64_t>(), tloc.as<V4>(), tfim.as<T>(), p->err.as<int>());
+    HIPCHK(hipGetLastError());
+    sort_u64(keys.as<uint64_t>(), np, s);
+    k_pair_place<T><<<nblocks(np), TPB, 0, s>>>(keys.as<uint64_t>(), np, tloc.as<V4>(), tfim.as<T>(),
+                                               lv.pr_slot.as<int>(), lv.pr_loc.as<V4>(), lv.pr_fim.as<T>(),
+                                               lv.pr_pos.as<int>());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));   // the temporaries are freed on return
+  }
+  p->pairs = true;
+}
+
+template <typename T>
+bool pairs_compiled(int ps, int pa) {
+#define X(a, b) \
+  if (ps == a && pa == b) return RowStage1<T, a, b>::ok;
+  IFGF_ORDERS_ALL(X)
+#undef X
+  return false;
+}
+
+void release_target_pairs(ifgf_plan_s* p) {
+  for (int d = 0; d < IFGF_MAX_LEVELS; ++d) {
+    LevelPlan& lv = p->lev[d];
+    lv.npair = 0;
+    lv.pr_slot.release();
+    lv.pr_loc.release();
+    lv.pr_fim.release();
+    lv.pr_val.release();
+    lv.pr_off.release();
+    lv.pr_pos.release();
+  }
+  p->pairs = false;
+}
+
+// Pair lists are built where the order has a row stage, one RHS is possible
+// and the lists stay within 2^28 pairs (about 10 GB in FP32).
+void build_target_pairs(ifgf_plan_s* p, hipStream_t s) {
+  const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
+  if (p->D < 3) return;
+  if (p->opt.target_kernel != IFGF_TARGET_AUTO && p->opt.target_kernel != IFGF_TARGET_PAIRS) return;
+  if (!(f32 ? pairs_compiled<float>(p->opt.p_s, p->opt.p_ang) : pairs_compiled<double>(p->opt.p_s, p->opt.p_ang)))
+    return;
+  int64_t tot = 0;
+  for (int d = 3; d <= p->D; ++d) tot += p->lev[d].cousin_pairs;
+  if (tot > ((int64_t)1 << 28)) return;
+  if (f32)
+    build_target_pairs_impl<float>(p, s);
+  else
+    build_target_pairs_impl<double>(p, s);
 }
 
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask, int level_lo,

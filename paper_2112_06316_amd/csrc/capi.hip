@@ -144,7 +144,7 @@ static void create_plan(ifgf_plan_s*& p, int64_t n, int64_t n_src, const double*
   if (o.precision != IFGF_PREC_FP64 && o.precision != IFGF_PREC_FP32_INTERP) throw Error{IFGF_EINVAL, "bad precision"};
   if (o.max_rhs < 1) throw Error{IFGF_EINVAL, "max_rhs must be >= 1"};
   if (o.prop_kernel < IFGF_PROP_AUTO || o.prop_kernel > IFGF_PROP_CONE) throw Error{IFGF_EINVAL, "bad prop_kernel"};
-  if (o.target_kernel < IFGF_TARGET_AUTO || o.target_kernel > IFGF_TARGET_ROWS)
+  if (o.target_kernel < IFGF_TARGET_AUTO || o.target_kernel > IFGF_TARGET_PAIRS)
     throw Error{IFGF_EINVAL, "bad target_kernel"};
   if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
   if (o.far_field != 0 && o.far_field != 1) throw Error{IFGF_EINVAL, "far_field must be 0 or 1"};
@@ -323,6 +323,8 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
       add(l.start); add(l.coords); add(l.centre); add(l.parent); add(l.child_lo); add(l.nbr_off); add(l.nbr);
       add(l.cou_off); add(l.cou); add(l.pbox); add(l.slot); add(l.slot_off); add(l.rel_box); add(l.rel_cone);
       add(l.Fn); add(l.Fc); add(l.work); add(l.ti_slot); add(l.ti_tile); add(l.ti_child); add(l.ti_geo); add(l.near_work); add(l.leaf_work);
+      add(l.ti_qlist); add(l.adj_tiles); add(l.adj_slots); add(l.adj_gref); add(l.adj_gref_off);
+      add(l.pr_slot); add(l.pr_loc); add(l.pr_fim); add(l.pr_val); add(l.pr_off); add(l.pr_pos);
       add(p->adj_g[d]);
       if (d >= 4 && p->lev[d - 1].nrel > 0)
         st->prop_kernel[d] = p->lev[d - 1].ntile > 0 ? IFGF_PROP_CONE : IFGF_PROP_NODE;

@@ -93,6 +93,17 @@ struct LevelPlan {
   DevBuf adj_gref_off;        // int [8 * ncone(d+1) + 1]
   int64_t adj_ntile = 0;
   bool adj_built = false;
+  // Cousin-target pair list (one RHS): every (target, cousin box) pair of this
+  // level sorted by cone slot; per pair its slot, local coordinates and centred
+  // factor (plan precision), its value after the apply's first pass; per
+  // target, the positions of its pairs in cousin order.
+  int64_t npair = 0;
+  DevBuf pr_slot;             // int [npair]
+  DevBuf pr_loc;              // T4 [npair]: (ts, tt, tp, factor re)
+  DevBuf pr_fim;              // T [npair]: factor im
+  DevBuf pr_val;              // complex T [npair]
+  DevBuf pr_off;              // int [n + 1]: target i's pairs are pr_pos[pr_off[i] .. pr_off[i + 1])
+  DevBuf pr_pos;              // int [npair]
   // statistics
   int64_t cousin_pairs = 0;
   int64_t prop_evals = 0;     // child interpolations into level d-1 nodes
@@ -104,6 +115,7 @@ struct ifgf_plan_s {
   int64_t n = 0;
   int D = 0;
   int64_t n_src = 0;          // points carrying densities (caller indices < n_src); the rest are targets only
+  bool pairs = false;         // every level 3..D holds its cousin-target pair list
   std::atomic<int> batch_refs{0};   // batches built over this plan (their queues point into its buffers)
   ifgf::DevBuf uext;          // plans with targets: the apply's result at every point, caller's order
   double k = 0, eta = 0;
@@ -182,6 +194,10 @@ void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, 
 void run_far_field(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double* dirs, void* uinf, int dtype,
                    hipStream_t s);
 void run_autotune(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t s);
+// Builds the cousin-target pair lists (plan time) where the order, precision
+// and size allow; sets p->pairs.
+void build_target_pairs(ifgf_plan_s* p, hipStream_t s);
+void release_target_pairs(ifgf_plan_s* p);
 
 // solve.hip: restarted GMRES on (alpha I + A) sigma = f (complex128 device vectors).
 void run_gmres(ifgf_plan_s* p, const void* f, void* sigma, const ifgf_gmres_options& o, int32_t* iters,

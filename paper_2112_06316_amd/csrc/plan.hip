@@ -846,6 +846,7 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
   p->err.alloc(sizeof(int) * 4);
   HIPCHK(hipMemsetAsync(p->err.p, 0, sizeof(int) * 4, s));
   HIPCHK(hipStreamSynchronize(s));
+  build_target_pairs(p, s);   // after the error flags exist: the pair generator reports missing cones there
 }
 
 }  // namespace ifgf

@@ -113,7 +113,7 @@ def _stage_reference(ps, pa, ns0, nc0):
 # the plan-time node records and the row-broadcast targets at that order.
 @pytest.mark.parametrize("setting", [(3, 5, 1, 2), (4, 6, 2, 4), (4, 6, 1, 2)])
 @pytest.mark.parametrize("prop", ["cone", "node"])
-@pytest.mark.parametrize("target", ["rows", "wave"])
+@pytest.mark.parametrize("target", ["rows", "wave", "pairs"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_stage_parity_with_reference(setting, prop, target, precision):
     ps, pa, ns0, nc0 = setting
@@ -393,3 +393,23 @@ def test_auto_depth_matches_paper_levels(lam, D):
     k = 2 * np.pi * lam
     plan = Plan(p, nr, w, k, k, depth=0, p_s=3, p_ang=5, ns0=1, nc0=2, kernel="constant")
     assert plan.stats()["depth"] == D
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("fp64", 1e-14)])
+def test_pair_targets_equal_row_targets(precision, tol):
+    # The pair lists evaluate each (target, cousin) pair with the row stage and
+    # sum them in the row formulation's order: the same operator.
+    wl = inputs.workload("sphere16")
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    s = torch.from_numpy(inputs.random_density(len(p), seed=63)).to(DEV)
+    if precision == "fp32":
+        s = s.to(torch.complex64)
+    u = {}
+    for tk in ("rows", "pairs"):
+        plan = Plan(p, nr, w, k, k, depth=wl["depth"], precision=precision, target_kernel=tk)
+        u[tk] = plan.apply(s).cpu().numpy()
+        assert plan.check() == 0
+    e = float(np.linalg.norm(u["pairs"] - u["rows"]) / np.linalg.norm(u["rows"]))
+    log(f"case pairs vs rows {precision}: rel diff {e:.2e}, bitwise equal {bool(np.array_equal(u['pairs'], u['rows']))}")
+    assert e <= tol
