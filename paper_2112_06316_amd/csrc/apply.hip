@@ -677,6 +677,79 @@ __device__ __forceinline__ void row_load_cone(const float* __restrict__ src, int
 }
 
 
+// Radial indices per row-stage pass: the whole cone where a stage for the
+// order is generated, else pairs of radial indices with the (2, P_ang) stage
+// (the cone's coefficients of two consecutive radial indices are contiguous);
+// 0 if neither exists.
+template <typename T, int PS, int PA> constexpr int row_chunk() {
+  if constexpr (RowStage1<T, PS, PA>::ok) return PS;
+  else if constexpr (PS % 2 == 0 && RowStage1<T, 2, PA>::ok) return 2;
+  else return 0;
+}
+template <typename T, int PS, int PA> constexpr bool rows_ok() { return row_chunk<T, PS, PA>() > 0; }
+
+// The interpolant of one cone (2P values at `cone`, held across the row's 16
+// lanes pass by pass) at this lane's Chebyshev values: sum_a Ts[a] sum_b Tt[b]
+// sum_c C[a][b][c] Tp[c], the c sum by DPP broadcast (RowStage1).  All lanes
+// of the row call it with the same cone.
+// One row-stage pass: for the CS radial indices whose coefficients start at
+// `chunk`, h[a] = sum_b Tt[b] sum_c C[a][b][c] Tp[c].
+template <typename T, int CS, int PA>
+__device__ __forceinline__ void row_pass(const T* __restrict__ chunk, int nl, const T (&Tt)[PA], const T (&Tp)[PA],
+                                         T (&h_re)[CS], T (&h_im)[CS]) {
+  using S1 = RowStage1<T, CS, PA>;
+  constexpr int NREG = S1::NREG;
+  T c[NREG];
+  row_load_cone<CS * PA * PA, NREG>(chunk, nl, c);
+  T D[2 * CS * PA];
+  S1::run(c, Tp, D);
+#pragma unroll
+  for (int a = 0; a < CS; ++a) {
+    h_re[a] = D[2 * a * PA];
+    h_im[a] = D[2 * a * PA + 1];
+#pragma unroll
+    for (int b = 1; b < PA; ++b) {
+      h_re[a] += D[2 * (a * PA + b)] * Tt[b];
+      h_im[a] += D[2 * (a * PA + b) + 1] * Tt[b];
+    }
+  }
+}
+
+// The interpolant of one cone (2P values at `cone`, held across the row's 16
+// lanes pass by pass) at this lane's Chebyshev values: sum_a Ts[a] sum_b Tt[b]
+// sum_c C[a][b][c] Tp[c], the c sum by DPP broadcast (RowStage1).  All lanes
+// of the row call it with the same cone.
+template <typename T, int PS, int PA>
+__device__ __forceinline__ void row_contract(const T* __restrict__ cone, int nl, const T (&Ts)[PS], const T (&Tt)[PA],
+                                             const T (&Tp)[PA], T& v_re, T& v_im) {
+  constexpr int CS = row_chunk<T, PS, PA>();
+  T h_re[CS], h_im[CS];
+  row_pass<T, CS, PA>(cone, nl, Tt, Tp, h_re, h_im);
+  v_re = h_re[0];
+  v_im = h_im[0];
+#pragma unroll
+  for (int a = 1; a < CS; ++a) {
+    v_re += h_re[a] * Ts[a];
+    v_im += h_im[a] * Ts[a];
+  }
+  if constexpr (CS < PS) {   // the further radial chunks, one pass each
+    constexpr int PC = CS * PA * PA;
+#pragma unroll 1
+    for (int h = 1; h < PS / CS; ++h) {
+      row_pass<T, CS, PA>(cone + (int64_t)h * 2 * PC, nl, Tt, Tp, h_re, h_im);
+#pragma unroll
+      for (int a = 0; a < CS; ++a) {
+        T ta = Ts[0];
+#pragma unroll
+        for (int m = 1; m < PS; ++m)
+          if (m == h * CS + a) ta = Ts[m];
+        v_re += h_re[a] * ta;
+        v_im += h_im[a] * ta;
+      }
+    }
+  }
+}
+
 // For every lane with slot >= 0, the interpolant of cone `slot` of F (one
 // right-hand side, layout [slot][P]) at (ts, tt, tp), by rows: each row of
 // 16 lanes loads one cone across its lanes and contracts with the
@@ -686,8 +759,6 @@ __device__ __forceinline__ void row_load_cone(const float* __restrict__ src, int
 template <typename T, int PS, int PA>
 __device__ __forceinline__ cpx<T> eval_rows(const cpx<T>* __restrict__ Fc, int slot, T ts, T tt, T tp) {
   constexpr int P = PS * PA * PA;
-  using S1 = RowStage1<T, PS, PA>;
-  constexpr int NREG = S1::NREG;
   constexpr int NONE = 0x7fffffff;
   const T* F = reinterpret_cast<const T*>(Fc);
   const int nl = threadIdx.x & 15;
@@ -699,28 +770,10 @@ __device__ __forceinline__ cpx<T> eval_rows(const cpx<T>* __restrict__ Fc, int s
   bool pend = slot >= 0;
   while (__ballot(pend)) {
     const int su = row_min16(pend ? slot : NONE);
-    T c[NREG];
-    row_load_cone<P, NREG>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, c);
-    T D[2 * PS * PA];
-    S1::run(c, Tp, D);
+    T v_re, v_im;
+    row_contract<T, PS, PA>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, Ts, Tt, Tp, v_re, v_im);
     if (pend && slot == su) {
-      T h_re[PS], h_im[PS];
-#pragma unroll
-      for (int a = 0; a < PS; ++a) {
-        h_re[a] = D[2 * a * PA];
-        h_im[a] = D[2 * a * PA + 1];
-#pragma unroll
-        for (int b = 1; b < PA; ++b) {
-          h_re[a] += D[2 * (a * PA + b)] * Tt[b];
-          h_im[a] += D[2 * (a * PA + b) + 1] * Tt[b];
-        }
-      }
-      out = {h_re[0], h_im[0]};
-#pragma unroll
-      for (int a = 1; a < PS; ++a) {
-        out.re += h_re[a] * Ts[a];
-        out.im += h_im[a] * Ts[a];
-      }
+      out = {v_re, v_im};
       pend = false;
     }
   }
@@ -824,7 +877,9 @@ __device__ __forceinline__ void lds_coeffs_store(cpx<T>* v, cpx<T>* t, int nc, c
   }
 }
 
-template <typename T, int PS, int PA, int BS_ = PropShape<PS * PA * PA>::BS> struct PropSmem {
+// CB: the per-wave coefficient buffer of the LDS-staged evaluation (not
+// needed by a single right-hand side with a row stage).
+template <typename T, int PS, int PA, int BS_ = PropShape<PS * PA * PA>::BS, bool CB = true> struct PropSmem {
   static constexpr int P = PS * PA * PA;
   static constexpr int BS = BS_;
   static constexpr int NN = PropShape<P>::CH * P;
@@ -838,7 +893,7 @@ template <typename T, int PS, int PA, int BS_ = PropShape<PS * PA * PA>::BS> str
   int hkey[HT], hoff[HT];
   int wsum[BS / 64];
   T ms[PS * PS], ma[PA * PA];
-  __align__(16) T cbuf[BS / 64][2 * P];
+  __align__(16) T cbuf[CB ? BS / 64 : 1][CB ? 2 * P : 4];
   // per cone of the item, (sin, cos) of its PA polar and PA azimuthal node
   // angles, and its PS node radii h / s
   T ang[PropShape<P>::CH][2 * PA][2];
@@ -849,14 +904,14 @@ template <typename T, int PS, int PA, int BS_ = PropShape<PS * PA * PA>::BS> str
 // right-hand side r, by a block of BS threads (PropShape::BS in the
 // standalone kernel).  ONE: a single right-hand side (R = 1 at compile time,
 // contiguous cones).
-template <typename T, int PS, int PA, bool ONE, int BS_ = PropShape<PS * PA * PA>::BS>
-__device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_>& sm, int4 wk, int r, const int* __restrict__ rel_cone_up,
+template <typename T, int PS, int PA, bool ONE, int BS_ = PropShape<PS * PA * PA>::BS, bool CB = true>
+__device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_, CB>& sm, int4 wk, int r, const int* __restrict__ rel_cone_up,
                                           const int* __restrict__ child_lo_up, const int* __restrict__ coords,
                                           const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c,
                                           const LevelGeom& gp, const LevelGeom& gc, const ChebTab& ct,
                                           const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind,
                                           int R_, cpx<T>* __restrict__ Fc_up, int* __restrict__ err) {
-  using S = PropSmem<T, PS, PA, BS_>;
+  using S = PropSmem<T, PS, PA, BS_, CB>;
   constexpr int P = S::P;
   constexpr int BS = S::BS;
   constexpr int NN = S::NN;
@@ -975,9 +1030,9 @@ __device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_>& sm, int4 wk,
         tp = st[n][2];
       }
       cpx<T> v;
-      if constexpr (ONE && RowStage1<T, PS, PA>::ok)
+      if constexpr (ONE && rows_ok<T, PS, PA>())
         v = eval_rows<T, PS, PA>(Fc_c, sl, ts, tt, tp);
-      else
+      else if constexpr (CB)
         v = eval_uniform<T, PS, PA>(Fc_c, sl, R, r, ts, tt, tp, cbuf[threadIdx.x >> 6]);
       if (n >= 0 && sl >= 0) {
         T rr = tmp[n].re, dr = tmp[n].im;
@@ -1005,8 +1060,9 @@ __global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
     const int* __restrict__ coords, const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c, LevelGeom gp,
     LevelGeom gc, ChebTab ct, const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind, int R,
     cpx<T>* __restrict__ Fc_up, int* __restrict__ err) {
-  __shared__ PropSmem<T, PS, PA> sm;
-  prop_item<T, PS, PA, ONE>(sm, work[xcd_block(blockIdx.x, gridDim.x)], ONE ? 0 : blockIdx.y, rel_cone_up,
+  constexpr bool CB = !(ONE && rows_ok<T, PS, PA>());
+  __shared__ PropSmem<T, PS, PA, PropShape<PS * PA * PA>::BS, CB> sm;
+  prop_item<T, PS, PA, ONE, PropShape<PS * PA * PA>::BS, CB>(sm, work[xcd_block(blockIdx.x, gridDim.x)], ONE ? 0 : blockIdx.y, rel_cone_up,
                             child_lo_up, coords, slot_c, Fc_c, gp, gc, ct, Ms, Ma, k, kind, R, Fc_up, err);
 }
 
@@ -1158,8 +1214,6 @@ template <typename T, int PS, int PA>
 __device__ __forceinline__ void rows_level(const TLevel<T>& lv, const double (&x)[3], bool valid, int64_t i,
                                            double k, int kind, int* __restrict__ err, T& acc_re, T& acc_im) {
   constexpr int P = PS * PA * PA;
-  using S1 = RowStage1<T, PS, PA>;
-  constexpr int NREG = S1::NREG;
   constexpr int NONE = 0x7fffffff;
   int ptr = 0, end = 0;
   if (valid) {
@@ -1228,27 +1282,8 @@ __device__ __forceinline__ void rows_level(const TLevel<T>& lv, const double (&x
     bool pend = sl != NONE;
     while (__ballot(pend)) {
       const int su = row_min16(pend ? sl : NONE);
-      T c[NREG];
-      row_load_cone<P, NREG>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, c);
-      T D[2 * PS * PA];
-      S1::run(c, Tp, D);
-      T h_re[PS], h_im[PS];
-#pragma unroll
-      for (int a = 0; a < PS; ++a) {
-        h_re[a] = D[2 * a * PA];
-        h_im[a] = D[2 * a * PA + 1];
-#pragma unroll
-        for (int b = 1; b < PA; ++b) {
-          h_re[a] += D[2 * (a * PA + b)] * Tt[b];
-          h_im[a] += D[2 * (a * PA + b) + 1] * Tt[b];
-        }
-      }
-      T v_re = h_re[0], v_im = h_im[0];
-#pragma unroll
-      for (int a = 1; a < PS; ++a) {
-        v_re += h_re[a] * Ts[a];
-        v_im += h_im[a] * Ts[a];
-      }
+      T v_re, v_im;
+      row_contract<T, PS, PA>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, Ts, Tt, Tp, v_re, v_im);
       if (pend && sl == su) {
         acc_re += e_re * v_re - e_im * v_im;
         acc_im += e_re * v_im + e_im * v_re;
@@ -1417,8 +1452,6 @@ __global__ __launch_bounds__(TPB) void k_pair_place(const uint64_t* __restrict__
 template <typename T, int PS, int PA>
 __global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
   constexpr int P = PS * PA * PA;
-  using S1 = RowStage1<T, PS, PA>;
-  constexpr int NREG = S1::NREG;
   constexpr int NONE = 0x7fffffff;
   const PLevel<T>& lv = L.lv[dlo + blockIdx.y];
   const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB;
@@ -1442,27 +1475,8 @@ __global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
   bool pend = valid;
   while (__ballot(pend)) {
     const int su = row_min16(pend ? sl : NONE);
-    T c[NREG];
-    row_load_cone<P, NREG>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, c);
-    T D[2 * PS * PA];
-    S1::run(c, Tp, D);
-    T h_re[PS], h_im[PS];
-#pragma unroll
-    for (int a = 0; a < PS; ++a) {
-      h_re[a] = D[2 * a * PA];
-      h_im[a] = D[2 * a * PA + 1];
-#pragma unroll
-      for (int b = 1; b < PA; ++b) {
-        h_re[a] += D[2 * (a * PA + b)] * Tt[b];
-        h_im[a] += D[2 * (a * PA + b) + 1] * Tt[b];
-      }
-    }
-    T v_re = h_re[0], v_im = h_im[0];
-#pragma unroll
-    for (int a = 1; a < PS; ++a) {
-      v_re += h_re[a] * Ts[a];
-      v_im += h_im[a] * Ts[a];
-    }
+    T v_re, v_im;
+    row_contract<T, PS, PA>(F + (int64_t)(su == NONE ? 0 : su) * (2 * P), nl, Ts, Tt, Tp, v_re, v_im);
     if (pend && sl == su) {
       o_re = lc.w * v_re - fim * v_im;
       o_im = lc.w * v_im + fim * v_re;
@@ -3710,7 +3724,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
       return;
     }
   }
-  if constexpr (RowStage1<T, PS, PA>::ok) {   // orders with a generated row stage
+  if constexpr (rows_ok<T, PS, PA>()) {   // orders with a generated row stage
     if (R == 1 && p->pairs && (p->opt.target_kernel == IFGF_TARGET_AUTO || p->opt.target_kernel == IFGF_TARGET_PAIRS)) {
       StageTimer tm(p, s, IFGF_STAGE_TARGETS);
       PLevels<T> PL{};
@@ -4528,7 +4542,7 @@ void autotune_impl(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t 
     rep->nlevels = nl;
   }
   rep->target_ms[0] = rep->target_ms[1] = rep->target_ms[2] = -1.0;
-  if constexpr (RowStage1<T, PS, PA>::ok) {
+  if constexpr (rows_ok<T, PS, PA>()) {
     if (p->opt.target_kernel == IFGF_TARGET_AUTO && p->tpart.bytes > 0) {
       static const int kT[3] = {IFGF_TARGET_ROWS, IFGF_TARGET_WAVE, IFGF_TARGET_PAIRS};
       int best = -1;
@@ -4674,8 +4688,11 @@ void build_target_pairs_impl(ifgf_plan_s* p, hipStream_t s) {
 template <typename T>
 bool pairs_compiled(int ps, int pa) {
 #define X(a, b) \
-  if (ps == a && pa == b) return RowStage1<T, a, b>::ok;
+  if (ps == a && pa == b) return rows_ok<T, a, b>();
   IFGF_ORDERS_ALL(X)
+  if constexpr (!Prec<T>::f32) {
+    IFGF_ORDERS_FP64(X)
+  }
 #undef X
   return false;
 }
