@@ -1721,6 +1721,94 @@ __global__ __launch_bounds__(TPB) void k_targets_mfma(const double* __restrict__
   }
 }
 
+// Pair-list cousin targets for RHS group g (FP32, nrhs a multiple of
+// 16): a wave takes 64 consecutive pairs of level dlo + blockIdx.y, which
+// mostly share one cone, and evaluates them for the group's 16 right-hand
+// sides on MFMA (wave_eval_mfma: one pass per distinct cone); the values,
+// times each pair's centred factor, go to val[pair][16].
+template <int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets_pairs_rg(PLevels<float> L, int dlo, int R, int g) {
+  constexpr int NR = MfRec<PS, PA>::NR;
+  __shared__ float rec[TPB / 64][64 * NR];
+  const PLevel<float>& lv = L.lv[dlo + blockIdx.y];
+  const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB;
+  if (q0 >= lv.np) return;   // block-uniform
+  const int l = threadIdx.x & 63;
+  const int64_t qw = q0 + (threadIdx.x & ~63);
+  const int64_t q = qw + l;
+  const bool valid = q < lv.np;
+  int sl = -1;
+  float4 lc = {0.f, 0.f, 0.f, 0.f};
+  float fim = 0.f;
+  if (valid) {
+    sl = lv.slot[q];
+    lc = lv.loc[q];
+    fim = lv.fim[q];
+  }
+  cpx<float> tot[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) tot[b][c] = {0.f, 0.f};
+  wave_eval_mfma<PS, PA>(lv.Fc, R, g, sl, lc.x, lc.y, lc.z, lc.w, fim, rec[threadIdx.x >> 6], tot);
+  // lane l holds RHS 8 rt + 2 (l >> 4) + p of pair 16 b + (l & 15) of its wave
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t e = qw + 16 * b + (l & 15);
+    if (e >= lv.np) continue;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int p2 = 0; p2 < 2; ++p2) lv.val[e * MF_RG + 8 * rt + 2 * (l >> 4) + p2] = tot[b][2 * rt + p2];
+  }
+}
+
+// u[:, group g] = near field + per level (finest first) the sum of the
+// target's pair values in cousin order; 16 right-hand sides per thread.
+__global__ __launch_bounds__(TPB) void k_targets_pairsum_rg(int64_t n, const int* __restrict__ perm,
+                                                            const cpx<float>* __restrict__ uacc, int use_near,
+                                                            PLevels<float> L, int dlo, int dhi, int R, int g,
+                                                            int dtype, void* __restrict__ u) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  double re[MF_RG], im[MF_RG];
+#pragma unroll
+  for (int r = 0; r < MF_RG; ++r) {
+    re[r] = use_near ? uacc[i * R + g * MF_RG + r].re : 0.0;
+    im[r] = use_near ? uacc[i * R + g * MF_RG + r].im : 0.0;
+  }
+  for (int d = dhi; d >= dlo; --d) {
+    const PLevel<float>& lv = L.lv[d];
+    float lre[MF_RG], lim[MF_RG];
+#pragma unroll
+    for (int r = 0; r < MF_RG; ++r) lre[r] = lim[r] = 0.f;
+    for (int t = lv.off[i]; t < lv.off[i + 1]; ++t) {
+      const cpx<float>* v = lv.val + (int64_t)lv.pos[t] * MF_RG;
+#pragma unroll
+      for (int r = 0; r < MF_RG; ++r) {
+        lre[r] += v[r].re;
+        lim[r] += v[r].im;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < MF_RG; ++r) {
+      re[r] += lre[r];
+      im[r] += lim[r];
+    }
+  }
+  const int64_t o = (int64_t)perm[i] * R + g * MF_RG;
+#pragma unroll
+  for (int r = 0; r < MF_RG; ++r) {
+    if (dtype == IFGF_C128) {
+      ((double*)u)[2 * (o + r)] = re[r];
+      ((double*)u)[2 * (o + r) + 1] = im[r];
+    } else {
+      ((float*)u)[2 * (o + r)] = (float)re[r];
+      ((float*)u)[2 * (o + r) + 1] = (float)im[r];
+    }
+  }
+}
+
 // Upward pass for RHS group blockIdx.y with the nodes grouped by child cone:
 // one work-group per parent slot.  For each child, the P node geometries are
 // computed once and grouped by child cone; the waves then evaluate, per
@@ -3715,6 +3803,29 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
     dhi = std::min(dhi, level_hi);
   }
   if constexpr (Prec<T>::f32 && PS <= 4) {
+    if (R % MF_RG == 0 && p->pairs && p->pairs_rg &&
+        (p->opt.target_kernel == IFGF_TARGET_AUTO || p->opt.target_kernel == IFGF_TARGET_PAIRS)) {
+      StageTimer tm(p, s, IFGF_STAGE_TARGETS);
+      PLevels<float> PL{};
+      int64_t maxp = 0;
+      for (int d = 3; d <= D; ++d) {
+        LevelPlan& lv = p->lev[d];
+        PL.lv[d] = {lv.npair, lv.pr_slot.as<int>(), lv.pr_loc.as<float4>(), lv.pr_fim.as<float>(),
+                    lv.pr_val.as<cpx<float>>(), lv.pr_off.as<int>(), lv.pr_pos.as<int>(), lv.Fc.as<cpx<float>>()};
+        if (d >= dlo && d <= dhi) maxp = std::max(maxp, lv.npair);
+      }
+      const int nlev = dlo <= dhi ? dhi - dlo + 1 : 0;
+      for (int g = 0; g < R / MF_RG; ++g) {   // the value buffer holds one group at a time
+        if (nlev > 0 && maxp > 0) {
+          k_targets_pairs_rg<PS, PA><<<dim3(nblocks(maxp), nlev), TPB, 0, s>>>(PL, dlo, R, g);
+          HIPCHK(hipGetLastError());
+        }
+        k_targets_pairsum_rg<<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), (const cpx<float>*)uacc, near ? 1 : 0,
+                                                       PL, dlo, dhi, R, g, dtype, u);
+        HIPCHK(hipGetLastError());
+      }
+      return;
+    }
     if (R % MF_RG == 0) {
       StageTimer tm(p, s, IFGF_STAGE_TARGETS);
       k_targets_mfma<PS, PA><<<dim3(nblocks(n), R / MF_RG), TPB, 0, s>>>(p->pts.as<double>(), n, p->perm.as<int>(),
@@ -4645,6 +4756,8 @@ template <typename T>
 void build_target_pairs_impl(ifgf_plan_s* p, hipStream_t s) {
   using V4 = typename Vec4<T>::type;
   const int64_t n = p->n;
+  // RHS groups of 16 (FP32, P_s <= 4): the value list holds 16 values per pair
+  p->pairs_rg = Prec<T>::f32 && p->opt.max_rhs >= MF_RG && p->opt.p_s <= 4;
   DevBuf cnt;
   cnt.alloc(sizeof(int) * (n + 1));
   for (int d = 3; d <= p->D; ++d) {
@@ -4662,7 +4775,7 @@ void build_target_pairs_impl(ifgf_plan_s* p, hipStream_t s) {
     lv.pr_slot.alloc(sizeof(int) * npa);
     lv.pr_loc.alloc(sizeof(V4) * npa);
     lv.pr_fim.alloc(sizeof(T) * npa);
-    lv.pr_val.alloc(sizeof(cpx<T>) * npa);
+    lv.pr_val.alloc(sizeof(cpx<T>) * npa * (p->pairs_rg ? MF_RG : 1));
     lv.pr_pos.alloc(sizeof(int) * npa);
     if (np == 0) continue;
     DevBuf keys, tloc, tfim;
@@ -4709,6 +4822,7 @@ void release_target_pairs(ifgf_plan_s* p) {
     lv.pr_pos.release();
   }
   p->pairs = false;
+  p->pairs_rg = false;
 }
 
 // Pair lists are built where the order has a row stage, one RHS is possible

@@ -116,6 +116,7 @@ struct ifgf_plan_s {
   int D = 0;
   int64_t n_src = 0;          // points carrying densities (caller indices < n_src); the rest are targets only
   bool pairs = false;         // every level 3..D holds its cousin-target pair list
+  bool pairs_rg = false;      // ... with room for 16 values per pair (RHS groups of 16)
   std::atomic<int> batch_refs{0};   // batches built over this plan (their queues point into its buffers)
   ifgf::DevBuf uext;          // plans with targets: the apply's result at every point, caller's order
   double k = 0, eta = 0;
