@@ -40,7 +40,8 @@ def test_autotuned_plan_computes_the_same_operator(precision, tol):
         assert e["choice"] in e["ms"] and all(v > 0 for v in e["ms"].values())
         assert "node" in e["ms"]
         assert plan.stats()["prop_kernel"][d + 1] == ("node" if e["choice"] == "node" else "cone")
-    assert rep["targets"] in ("rows", "wave")
+    assert rep["targets"] in ("rows", "wave", "pairs")
+    assert rep["targets"] in rep["targets_ms"] and set(rep["targets_ms"]) == {"rows", "wave", "pairs"}
     u1 = plan.apply(s).cpu().numpy()
     assert np.linalg.norm(u1 - u0) / np.linalg.norm(u0) <= tol
     tg = inputs.sample_targets(len(p), 256, seed=62)
