@@ -1503,7 +1503,23 @@ __global__ __launch_bounds__(TPB) void k_targets_pairsum(int64_t n, const int* _
   for (int d = dhi; d >= dlo; --d) {
     const PLevel<T>& lv = L.lv[d];
     T lre = 0, lim = 0;
-    for (int t = lv.off[i]; t < lv.off[i + 1]; ++t) {
+    const int t1 = lv.off[i + 1];
+    int t = lv.off[i];
+    // batches of 8 independent gathers in flight, summed in cousin order
+    for (; t + 8 <= t1; t += 8) {
+      int ps[8];
+      cpx<T> v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ps[j] = lv.pos[t + j];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = lv.val[ps[j]];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        lre += v[j].re;
+        lim += v[j].im;
+      }
+    }
+    for (; t < t1; ++t) {
       const cpx<T> v = lv.val[lv.pos[t]];
       lre += v.re;
       lim += v.im;
@@ -1782,7 +1798,27 @@ __global__ __launch_bounds__(TPB) void k_targets_pairsum_rg(int64_t n, const int
     float lre[MF_RG], lim[MF_RG];
 #pragma unroll
     for (int r = 0; r < MF_RG; ++r) lre[r] = lim[r] = 0.f;
-    for (int t = lv.off[i]; t < lv.off[i + 1]; ++t) {
+    const int t1 = lv.off[i + 1];
+    int t = lv.off[i];
+    // pairs two at a time: 32 independent loads in flight, summed in cousin order
+    for (; t + 2 <= t1; t += 2) {
+      const cpx<float>* v0 = lv.val + (int64_t)lv.pos[t] * MF_RG;
+      const cpx<float>* v1 = lv.val + (int64_t)lv.pos[t + 1] * MF_RG;
+      cpx<float> a[MF_RG], b[MF_RG];
+#pragma unroll
+      for (int r = 0; r < MF_RG; ++r) {
+        a[r] = v0[r];
+        b[r] = v1[r];
+      }
+#pragma unroll
+      for (int r = 0; r < MF_RG; ++r) {
+        lre[r] += a[r].re;
+        lim[r] += a[r].im;
+        lre[r] += b[r].re;
+        lim[r] += b[r].im;
+      }
+    }
+    for (; t < t1; ++t) {
       const cpx<float>* v = lv.val + (int64_t)lv.pos[t] * MF_RG;
 #pragma unroll
       for (int r = 0; r < MF_RG; ++r) {

@@ -366,8 +366,8 @@ __global__ __launch_bounds__(TPB) void k_cone_keys(const int* __restrict__ rel_c
 }
 
 // Cone-major tiles of the upward pass into level d (one right-hand side):
-// the relevant cones of level d sorted by (cone id, child octant mask, Morton
-// order) and cut into tiles of 8 * nw boxes of one cone id.  nw_req < 0
+// the relevant cones of level d cut into tiles of up to 8 * nw boxes of one
+// cone id, ordered by families of cone ids (below).  nw_req < 0
 // picks nw by the heuristic below; 0 leaves the level to the node
 // formulation.  Returns the nw in use.  Callable again on a built plan (the
 // autotuner re-cuts a level's tiles; the node records are built once).
@@ -418,51 +418,94 @@ int build_cone_tiles(ifgf_plan_s* p, int d, int nw_req, hipStream_t s) {
     for (int c = clo[b]; c < clo[b + 1]; ++c)
       cmask[b] |= (uint8_t)(1u << ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) |
                                    ((ccoords[3 * c + 2] & 1) << 2)));
-  // Within a cone id the boxes come in Morton order (slot order); they are
-  // sorted by child mask (stable: Morton order within a mask), then cut
-  // into tiles, so that the boxes of a tile - and the 8 rows of a wave -
-  // mostly have children in the same octants (MFMA rows of a box without
-  // a child in the current octant are wasted).
-  std::vector<int> slots(lv.nrel);
-  std::vector<std::array<int, 5>> tl;   // (first box, cid, start, count, 0)
-  for (int64_t i = 0; i < lv.nrel; ++i) slots[i] = (int)(keys[i] & 0xffffffffu);
+  // Tile order.  A child cone is read by the parent cones whose nodes fall
+  // in it: as seen from the child, the parent's radial index s maps to about
+  // s / 4 and its angular indices to about half theirs, so the 16 parent
+  // cone ids (s >> 2, theta >> 1, phi >> 1) - a family - read mostly the
+  // same child cones.  The families come in Morton order of those indices.
+  // Within a family, the union of its cone ids' boxes is ordered by child
+  // octant mask, then Morton order (the 8 rows of a wave then mostly have
+  // children in the same octants: rows of a box without a child in the
+  // current octant are wasted); each cone id's boxes are cut, in that
+  // order, into tiles of up to cap boxes, and the family's tiles run by the
+  // middle of their range in it, so that tiles of sibling cone ids over the
+  // same boxes run back to back (with the XCD-aware block mapping, on one
+  // XCD, where the child cones they share stay in L2).
+  const LevelGeom& g = lv.geom;
+  auto family_key = [&](int cid) -> uint64_t {
+    const int ip = cid % (2 * g.nc), it = (cid / (2 * g.nc)) % g.nc, is = cid / (2 * g.nc * g.nc);
+    return ((uint64_t)morton_encode((uint32_t)(is >> 1), (uint32_t)it, (uint32_t)ip) << 1) | (uint64_t)(is & 1);
+  };
+  struct ConeRange {
+    uint64_t key;
+    int cid;
+    int64_t b, e;   // the cone id's entries of keys[]
+  };
+  std::vector<ConeRange> cr;
   for (int64_t i = 0; i < lv.nrel;) {
     const int cid = (int)(keys[i] >> 32);
     int64_t j = i;
     while (j < lv.nrel && (int)(keys[j] >> 32) == cid) ++j;
-    std::stable_sort(slots.begin() + i, slots.begin() + j,
-                     [&](int x, int y) { return cmask[rbox[x]] < cmask[rbox[y]]; });
-    for (int64_t t = i; t < j; t += cap) {
-      const int cnt = (int)std::min<int64_t>(cap, j - t);
-      int b0 = rbox[slots[t]];
-      for (int u = 1; u < cnt; ++u) b0 = std::min(b0, rbox[slots[t + u]]);
-      tl.push_back({b0, cid, (int)t, cnt, 0});
-    }
+    cr.push_back({family_key(cid), cid, i, j});
     i = j;
   }
-  // Order the tiles by first box, so that tiles of different cone ids
-  // over the same boxes - which read the same child cones - run back to
-  // back (and, with the XCD-aware block mapping, on one XCD); except
-  // where a cone id has several tiles (4 or more on average): those stay
-  // together, so that its node records (8 x 5.2 KB at P = 144 in FP32,
-  // 8 x 7.5 KB in FP64) stay in L2 from one tile to the next.
-  if ((int64_t)tl.size() < 4 * ndistinct)
-    std::stable_sort(tl.begin(), tl.end(), [](const std::array<int, 5>& x, const std::array<int, 5>& y) {
-      return x[0] < y[0];
-    });
+  std::sort(cr.begin(), cr.end(), [](const ConeRange& x, const ConeRange& y) { return x.key < y.key; });
+  std::vector<int> slots;   // ti_slot: the tiles' boxes (as parent slots), tile after tile
+  slots.reserve(lv.nrel);
+  std::vector<std::array<int, 4>> tl;   // (cid, start, count, 0)
+  std::vector<int> pos(lv.nb, -1), ub;
+  struct FamTile {
+    int mid;
+    int cid;
+    std::vector<int> sl;
+  };
+  std::vector<FamTile> ft;
+  std::vector<std::pair<int, int>> v;
+  for (size_t f0 = 0; f0 < cr.size();) {
+    size_t f1 = f0;
+    while (f1 < cr.size() && (cr[f1].key >> 4) == (cr[f0].key >> 4)) ++f1;
+    ub.clear();
+    for (size_t f = f0; f < f1; ++f)
+      for (int64_t t = cr[f].b; t < cr[f].e; ++t) ub.push_back(rbox[(int)(keys[t] & 0xffffffffu)]);
+    std::sort(ub.begin(), ub.end(), [&](int x, int y) { return cmask[x] != cmask[y] ? cmask[x] < cmask[y] : x < y; });
+    ub.erase(std::unique(ub.begin(), ub.end()), ub.end());
+    for (size_t u = 0; u < ub.size(); ++u) pos[ub[u]] = (int)u;
+    ft.clear();
+    for (size_t f = f0; f < f1; ++f) {
+      v.clear();
+      for (int64_t t = cr[f].b; t < cr[f].e; ++t) {
+        const int sl = (int)(keys[t] & 0xffffffffu);
+        v.push_back({pos[rbox[sl]], sl});
+      }
+      std::sort(v.begin(), v.end());
+      for (size_t t = 0; t < v.size(); t += cap) {
+        const size_t e = std::min(v.size(), t + (size_t)cap);
+        FamTile x{(v[t].first + v[e - 1].first) / 2, cr[f].cid, {}};
+        for (size_t u = t; u < e; ++u) x.sl.push_back(v[u].second);
+        ft.push_back(std::move(x));
+      }
+    }
+    std::stable_sort(ft.begin(), ft.end(), [](const FamTile& x, const FamTile& y) { return x.mid < y.mid; });
+    for (const FamTile& x : ft) {
+      tl.push_back({x.cid, (int)slots.size(), (int)x.sl.size(), 0});
+      slots.insert(slots.end(), x.sl.begin(), x.sl.end());
+    }
+    for (int u : ub) pos[u] = -1;
+    f0 = f1;
+  }
   // the node records of each (cone id, octant) are computed once per
   // level; a tile's fourth entry indexes its cone id's records
   std::vector<int> qlist;
-  for (const auto& t : tl) qlist.push_back(t[1]);
+  for (const auto& t : tl) qlist.push_back(t[0]);
   std::sort(qlist.begin(), qlist.end());
   qlist.erase(std::unique(qlist.begin(), qlist.end()), qlist.end());
   std::vector<int> tiles;
   tiles.reserve(tl.size() * 4);
   for (const auto& t : tl) {
+    tiles.push_back(t[0]);
     tiles.push_back(t[1]);
     tiles.push_back(t[2]);
-    tiles.push_back(t[3]);
-    tiles.push_back((int)(std::lower_bound(qlist.begin(), qlist.end(), t[1]) - qlist.begin()));
+    tiles.push_back((int)(std::lower_bound(qlist.begin(), qlist.end(), t[0]) - qlist.begin()));
   }
   if (!lv.ti_geo_built) {   // the records depend on the cone ids only, not on the tile height
     build_ti_geo(p, d, qlist, s);
