@@ -115,6 +115,16 @@ __device__ __forceinline__ float atan2_f(float y, float x) {
   return y < 0.0f ? -r : r;
 }
 
+// sin and cos in FP32 from the hardware sine and cosine, whose argument is
+// in revolutions.  The rounding of x / (2 pi) in FP32 dominates: the
+// absolute error measured on gfx950 is about 1.5e-7 + 8.7e-8 |x| (3.9e-7 for
+// |x| <= 4, 1.4e-6 for |x| <= 16).  For phases of a few radians only.
+__device__ __forceinline__ void sincos_hw(float x, float* sn, float* cs) {
+  const float rv = x * 0.159154943f;
+  *sn = __builtin_amdgcn_sinf(rv);
+  *cs = __builtin_amdgcn_cosf(rv);
+}
+
 // sin and cos in FP32: quadrant k = rint(2x/pi), remainder x - k pi/2 by a
 // three-term Cody-Waite reduction with FMAs (pi/2 split into FP32 parts),
 // then polynomials on |r| <= pi/4 whose coefficients are a least-squares fit
