@@ -4000,6 +4000,122 @@ void build_adj_gather(ifgf_plan_s* p, int d, hipStream_t s) {
   lv.adj_built = true;
 }
 
+// ---------------------------------------------------------------------------
+// Transposed cousin targets from the pair lists (gather form).  The pairs of
+// a level are sorted by cone slot, so the pairs of one slot form a run; one
+// wave takes a run and sums, in the run's order, every pair's target value
+// times its centred factor times the basis at its local coordinates into
+// the slot's P coefficient adjoints: one writer per coefficient, the same
+// sums on every call.  Lane (b, c) (lanes < p_ang^2) holds the coefficients
+// (a, b, c) for every a; the run is read in chunks of 64 pairs whose
+// Chebyshev vectors and weights each lane first puts in LDS.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_run_flag(const int* __restrict__ slot, int64_t np, int* __restrict__ flag) {
+  const int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q < np) flag[q] = (q == 0 || slot[q] != slot[q - 1]) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(TPB) void k_run_place(const int* __restrict__ flag, const int* __restrict__ idx,
+                                                   int64_t np, int* __restrict__ run) {
+  const int64_t q = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (q < np && flag[q]) run[idx[q]] = (int)q;
+  if (q == 0) run[idx[np]] = (int)np;
+}
+
+// target of every sorted pair: pairs off[i] .. off[i+1]-1 of target i sit at pos[]
+__global__ __launch_bounds__(TPB) void k_pair_tgt(int64_t n, const int* __restrict__ off, const int* __restrict__ pos,
+                                                  int* __restrict__ tgt) {
+  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (i >= n) return;
+  for (int t = off[i]; t < off[i + 1]; ++t) tgt[pos[t]] = (int)i;
+}
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_adj_pairs(const int* __restrict__ run, int64_t nrun,
+                                                   const typename Vec4<T>::type* __restrict__ loc,
+                                                   const T* __restrict__ fim, const int* __restrict__ tgt,
+                                                   const int* __restrict__ slot, const cpx<T>* __restrict__ vs, int R,
+                                                   cpx<T>* __restrict__ G) {
+  constexpr int P = PS * PA * PA;
+  constexpr int NBC = PA * PA;
+  static_assert(NBC <= 64, "one lane per (b, c)");
+  constexpr int NF = PS + 2 * PA + 2;   // Ts, Tt, Tp, weight (re, im)
+  __shared__ T buf[TPB / 64][64][NF + 1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = blockIdx.y;
+  const int64_t ri = (int64_t)blockIdx.x * (TPB / 64) + wv;
+  if (ri >= nrun) return;   // wave-uniform; the kernel has no block barrier
+  const int q0 = run[ri], q1 = run[ri + 1];
+  const int su = slot[q0];
+  const int bl = lane / PA, cl = lane % PA;
+  cpx<T> acc[PS];
+#pragma unroll
+  for (int a = 0; a < PS; ++a) acc[a] = {0, 0};
+  T* f = buf[wv][lane];
+  for (int qb = q0; qb < q1; qb += 64) {
+    const int q = qb + lane;
+    if (q < q1) {
+      const typename Vec4<T>::type lc = loc[q];
+      const T fi = fim[q];
+      const cpx<T> v = vs[(int64_t)tgt[q] * R + r];
+      cheb_T<T, PS>(lc.x, f);
+      cheb_T<T, PA>(lc.y, f + PS);
+      cheb_T<T, PA>(lc.z, f + PS + PA);
+      f[NF - 2] = lc.w * v.re - fi * v.im;
+      f[NF - 1] = lc.w * v.im + fi * v.re;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = min(64, q1 - qb);
+    if (lane < NBC) {
+      for (int k = 0; k < cnt; ++k) {
+        const T* fk = buf[wv][k];
+        const T tbc = fk[PS + bl] * fk[PS + PA + cl];
+        const T wre = fk[NF - 2], wim = fk[NF - 1];
+#pragma unroll
+        for (int a = 0; a < PS; ++a) {
+          const T fa = fk[a] * tbc;
+          acc[a].re += fa * wre;
+          acc[a].im += fa * wim;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();   // the chunk is read before the next one is written
+  }
+  if (lane < NBC) {
+#pragma unroll
+    for (int a = 0; a < PS; ++a) G[((int64_t)su * P + a * NBC + lane) * R + r] = acc[a];
+  }
+}
+
+// The transposed-apply index of the pair lists: per sorted pair its target,
+// per level the runs of equal slots.
+void build_adj_pairs(ifgf_plan_s* p, hipStream_t s) {
+  const int64_t n = p->n;
+  for (int d = 3; d <= p->D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    const int64_t np = lv.npair;
+    lv.nrun = 0;
+    if (np == 0) continue;
+    lv.pr_tgt.alloc(sizeof(int) * np);
+    k_pair_tgt<<<nblocks(n), TPB, 0, s>>>(n, lv.pr_off.as<int>(), lv.pr_pos.as<int>(), lv.pr_tgt.as<int>());
+    HIPCHK(hipGetLastError());
+    DevBuf flag, idx;
+    flag.alloc(sizeof(int) * (np + 1));
+    idx.alloc(sizeof(int) * (np + 1));
+    k_run_flag<<<nblocks(np), TPB, 0, s>>>(lv.pr_slot.as<int>(), np, flag.as<int>());
+    HIPCHK(hipGetLastError());
+    scan_exclusive_i32(flag.as<int>(), idx.as<int>(), np, s);
+    int nr32 = 0;
+    HIPCHK(hipMemcpyAsync(&nr32, idx.as<int>() + np, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    lv.nrun = nr32;
+    lv.pr_run.alloc(sizeof(int) * (lv.nrun + 1));
+    k_run_place<<<nblocks(np), TPB, 0, s>>>(flag.as<int>(), idx.as<int>(), np, lv.pr_run.as<int>());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));   // the temporaries are freed on return
+  }
+  p->adj_pairs = true;
+}
+
 template <typename T, int PS, int PA>
 void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, int conj, hipStream_t s) {
   constexpr int P = PS * PA * PA;
@@ -4038,7 +4154,23 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
       L.lv[d] = {lv.pbox.as<int>(), lv.cou_off.as<int>(), lv.cou.as<int>(), lv.centre.as<double>(),
                  lv.slot.as<int>(), p->adj_g[d].as<cpx<T>>(), lv.geom};
     }
-    {
+    bool gathered = false;
+    if constexpr (rows_ok<T, PS, PA>()) {
+      if (p->pairs && !p->adj_pairs) build_adj_pairs(p, s);
+      if (p->pairs && p->adj_pairs) {   // gather form from the pair lists
+        StageTimer tm(p, s, IFGF_STAGE_ADJ_TARGETS);
+        for (int d = 3; d <= D; ++d) {
+          LevelPlan& lv = p->lev[d];
+          if (lv.nrun == 0) continue;
+          k_adj_pairs<T, PS, PA><<<dim3((unsigned)((lv.nrun + TPB / 64 - 1) / (TPB / 64)), R), TPB, 0, s>>>(
+              lv.pr_run.as<int>(), lv.nrun, lv.pr_loc.as<typename Vec4<T>::type>(), lv.pr_fim.as<T>(),
+              lv.pr_tgt.as<int>(), lv.pr_slot.as<int>(), vs, R, p->adj_g[d].as<cpx<T>>());
+          HIPCHK(hipGetLastError());
+        }
+        gathered = true;
+      }
+    }
+    if (!gathered) {
       StageTimer tm(p, s, IFGF_STAGE_ADJ_TARGETS);
       k_adj_targets<T, PS, PA><<<gpts, TPB, 0, s>>>(p->pts.as<double>(), n, vs, L, 3, D, p->k, kind, R,
                                                     p->err.as<int>());
@@ -4860,8 +4992,12 @@ void release_target_pairs(ifgf_plan_s* p) {
     lv.pr_val.release();
     lv.pr_off.release();
     lv.pr_pos.release();
+    lv.pr_tgt.release();
+    lv.pr_run.release();
+    lv.nrun = 0;
   }
   p->pairs = false;
+  p->adj_pairs = false;
   p->pairs_rg = false;
 }
 

@@ -104,6 +104,11 @@ struct LevelPlan {
   DevBuf pr_val;              // complex T [npair]
   DevBuf pr_off;              // int [n + 1]: target i's pairs are pr_pos[pr_off[i] .. pr_off[i + 1])
   DevBuf pr_pos;              // int [npair]
+  // for the transposed apply (built on its first call): the target of each
+  // sorted pair, and the runs of pairs of one slot (starts, then npair)
+  DevBuf pr_tgt;              // int [npair]
+  DevBuf pr_run;              // int [nrun + 1]
+  int64_t nrun = 0;
   // statistics
   int64_t cousin_pairs = 0;
   int64_t prop_evals = 0;     // child interpolations into level d-1 nodes
@@ -116,6 +121,7 @@ struct ifgf_plan_s {
   int D = 0;
   int64_t n_src = 0;          // points carrying densities (caller indices < n_src); the rest are targets only
   bool pairs = false;         // every level 3..D holds its cousin-target pair list
+  bool adj_pairs = false;     // ... and its transposed-apply index (pr_tgt, pr_run)
   bool pairs_rg = false;      // ... with room for 16 values per pair (RHS groups of 16)
   std::atomic<int> batch_refs{0};   // batches built over this plan (their queues point into its buffers)
   ifgf::DevBuf uext;          // plans with targets: the apply's result at every point, caller's order

@@ -162,3 +162,40 @@ def test_gathered_transposed_pass_equals_scattered(precision, tol):
     e = np.linalg.norm(out["cone"] - out["node"]) / np.linalg.norm(out["node"])
     log(f"case gathered vs scattered transposed pass {precision}: rel diff {e:.2e}")
     assert e <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_pair_list_transposed_targets_equal_scattered(precision, tol):
+    # With pair lists the transposed cousin-target stage gathers per cone slot
+    # (one writer per coefficient); without them (row targets) it scatters
+    # with atomics.  Both are the transpose of the same forward operator.
+    p, nr, w = inputs.cubed_sphere(48)
+    k = 16 * np.pi
+    v = to_dev(inputs.random_density(len(p), seed=25))
+    if precision == "fp32":
+        v = v.to(torch.complex64)
+    out = {}
+    for tk in ("pairs", "rows"):
+        plan = Plan(p, nr, w, k, k, depth=5, precision=precision, target_kernel=tk)
+        out[tk] = plan.apply_adjoint(v, conjugate=True).to(torch.complex128).cpu().numpy()
+        assert plan.check() == 0
+    e = np.linalg.norm(out["pairs"] - out["rows"]) / np.linalg.norm(out["rows"])
+    log(f"case pair-list vs scattered transposed targets {precision}: rel diff {e:.2e}")
+    assert e <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gathered_adjoint_is_bitwise_deterministic(precision):
+    # Pair-list targets and cone-major tiles on every level: every transposed
+    # stage has one writer per value, so two calls give identical bits.
+    p, nr, w = inputs.cubed_sphere(48)
+    k = 16 * np.pi
+    plan = Plan(p, nr, w, k, k, depth=5, precision=precision, prop_kernel="cone", target_kernel="pairs")
+    v = to_dev(inputs.random_density(len(p), seed=26))
+    if precision == "fp32":
+        v = v.to(torch.complex64)
+    a = plan.apply_adjoint(v, conjugate=True).cpu().numpy()
+    b = plan.apply_adjoint(v, conjugate=True).cpu().numpy()
+    log(f"case deterministic adjoint {precision}: max |a - b| {np.abs(a - b).max():.2e}")
+    assert np.array_equal(a, b)
+    assert plan.check() == 0
