@@ -1351,9 +1351,8 @@ __global__ __launch_bounds__(TPB) void k_targets_sum(int64_t n, const int* __res
 // (box, cone).  Pass one: each row of 16 lanes takes 16 consecutive pairs,
 // which mostly share one cone, loads that cone across the row once and
 // contracts by DPP broadcast (the row stage), and writes each pair's value.
-// Pass two: each target sums its pairs' values in cousin order within a
-// level and the levels from the finest down, as the row-broadcast
-// formulation does, so the two formulations give the same sums.
+// Pass two: each target sums its pairs' values, the levels from the finest
+// down, in a fixed order.
 // ---------------------------------------------------------------------------
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };
@@ -1491,45 +1490,42 @@ __global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
 }
 
 // Pass two: u = near field + per level (finest first) the sum of the
-// target's pair values in cousin order; scattered to the caller's order.
+// target's pair values, scattered to the caller's order.  16 lanes per
+// target: lane j adds pairs j, j + 16, ... of the target's list at a level
+// (coalesced reads of the position list), then a fixed butterfly adds the 16
+// partial sums.  The order is fixed (every call gives the same sums), not
+// the row formulation's sequential one (the two agree to rounding).
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_targets_pairsum(int64_t n, const int* __restrict__ perm,
                                                          const cpx<T>* __restrict__ uacc, int use_near,
                                                          PLevels<T> L, int dlo, int dhi, int dtype,
                                                          void* __restrict__ u) {
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (i >= n) return;
+  const int64_t i0 = ((int64_t)blockIdx.x * TPB + threadIdx.x) >> 4;
+  const int j = threadIdx.x & 15;
+  const bool valid = i0 < n;
+  const int64_t i = valid ? i0 : n - 1;   // every lane takes part in the butterfly
   double re = 0, im = 0;
-  if (use_near) {
-    re = uacc[i].re;
-    im = uacc[i].im;
-  }
   for (int d = dhi; d >= dlo; --d) {
     const PLevel<T>& lv = L.lv[d];
     T lre = 0, lim = 0;
     const int t1 = lv.off[i + 1];
-    int t = lv.off[i];
-    // batches of 8 independent gathers in flight, summed in cousin order
-    for (; t + 8 <= t1; t += 8) {
-      int ps[8];
-      cpx<T> v[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) ps[j] = lv.pos[t + j];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = lv.val[ps[j]];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        lre += v[j].re;
-        lim += v[j].im;
-      }
-    }
-    for (; t < t1; ++t) {
+    for (int t = lv.off[i] + j; t < t1; t += 16) {
       const cpx<T> v = lv.val[lv.pos[t]];
       lre += v.re;
       lim += v.im;
     }
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1) {
+      lre += __shfl_xor(lre, m, 16);
+      lim += __shfl_xor(lim, m, 16);
+    }
     re += lre;
     im += lim;
+  }
+  if (!valid || j != 0) return;
+  if (use_near) {
+    re += uacc[i].re;
+    im += uacc[i].im;
   }
   const int64_t o = perm[i];
   if (dtype == IFGF_C128) {
@@ -3891,7 +3887,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
         k_targets_pairs<T, PS, PA><<<dim3(nblocks(maxp), nlev), TPB, 0, s>>>(PL, dlo);
         HIPCHK(hipGetLastError());
       }
-      k_targets_pairsum<T><<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), uacc, near ? 1 : 0, PL, dlo, dhi, dtype,
+      k_targets_pairsum<T><<<nblocks(16 * n), TPB, 0, s>>>(n, p->perm.as<int>(), uacc, near ? 1 : 0, PL, dlo, dhi, dtype,
                                                      u);
       HIPCHK(hipGetLastError());
       return;

@@ -398,7 +398,8 @@ def test_auto_depth_matches_paper_levels(lam, D):
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-6), ("fp64", 1e-14)])
 def test_pair_targets_equal_row_targets(precision, tol):
     # The pair lists evaluate each (target, cousin) pair with the row stage and
-    # sum them in the row formulation's order: the same operator.
+    # sum each target's pairs in a fixed order of their own: the same
+    # operator, equal to rounding.
     wl = inputs.workload("sphere16")
     p, nr, w = inputs.build_surface(wl)
     k = wl["k"]
