@@ -1854,6 +1854,8 @@ __global__ __launch_bounds__(TPB) void k_targets_pairsum_rg(int64_t n, const int
 // cone.  ratio * OUT is added to the node values in LDS (one writer per
 // (node, RHS) per child: deterministic); they are turned into coefficients
 // in place and written to level d-1.
+template <int PS, int PA> struct TiGeo;
+
 template <int PS, int PA> struct BcSmem {
   static constexpr int P = PS * PA * PA;
   static constexpr int NBAS = PS + 2 * PA;
@@ -1864,6 +1866,8 @@ template <int PS, int PA> struct BcSmem {
   int cid[P];
   short order[P];
   int gstart[P + 1], gcid[P];
+  short tstart[P + 1];          // group g: column tiles tstart[g] .. tstart[g+1]-1
+  short tgrp[P + P / 16 + 1];   // group of each column tile
   int ngroup;
   float ms[PS * PS], ma[PA * PA];
   float ang[2 * PA][2];   // (sin, cos) of the parent cone's PA polar and PA azimuthal node angles
@@ -1878,7 +1882,9 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
                                                         const cpx<float>* __restrict__ Fc_c, LevelGeom gp,
                                                         LevelGeom gc, ChebTab ct, const float* __restrict__ Ms,
                                                         const float* __restrict__ Ma, double k, int kind, int R,
-                                                        cpx<float>* __restrict__ Fc_up, int* __restrict__ err) {
+                                                        const TiGeo<PS, PA>* __restrict__ recs,
+                                                        const int* __restrict__ rec_of, cpx<float>* __restrict__ Fc_up,
+                                                        int* __restrict__ err) {
   using S = BcSmem<PS, PA>;
   constexpr int P = S::P;
   constexpr int NWV = TPB / 64;
@@ -1903,99 +1909,141 @@ __global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ 
       sm.rad[j - 2 * PA] = gp.hf * rcp_f(((float)is + ct.usf[j - 2 * PA]) * gp.dsf);
   }
   const int B0 = child_lo_up[Pb], B1 = child_lo_up[Pb + 1];
+  // the plan's node records of the cone id, where the level has them
+  const int rec = rec_of ? rec_of[sp] : -1;   // block-uniform
   for (int B = B0; B < B1; ++B) {
     const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
     __syncthreads();   // previous child's groups and geometry no longer read; the node terms written
-    for (int n = threadIdx.x; n < P; n += TPB) {
-      float x[3], rp;
-      {   // node_rel32 from the tabulated terms
-        const int bi = (n / PA) % PA, ci = n % PA;
-        const float st = sm.ang[bi][0], ctt = sm.ang[bi][1], sp_ = sm.ang[PA + ci][0], cp = sm.ang[PA + ci][1];
-        const float e0 = st * cp, e1 = st * sp_;
-        rp = sm.rad[n / (PA * PA)];
-        x[0] = rp * e0;
-        x[1] = rp * e1;
-        x[2] = rp * ctt;
+    if (rec >= 0) {   // geometry and groups from the record of (cone id, octant)
+      const TiGeo<PS, PA>& G = recs[(int64_t)rec * 8 + oct];
+      const int ngr = G.ngroup;
+      for (int e = threadIdx.x; e < P; e += TPB) {
+        const int n = G.node[e];
+        const float4 lc = G.loc[e];
+        const float2 rt = G.rat[e];
+        sm.order[e] = (short)n;
+        cheb_T<float, PS>(lc.x, &sm.bas[n][0]);
+        cheb_T<float, PA>(lc.y, &sm.bas[n][PS]);
+        cheb_T<float, PA>(lc.z, &sm.bas[n][PS + PA]);
+        sm.rat[n][0] = rt.x;
+        sm.rat[n][1] = rt.y;
       }
-      const PropF pr = child_loc32(x, rp, oct, gc);
-      sm.cid[n] = pr.loc.cid;
-      cheb_T<float, PS>(pr.loc.ts, &sm.bas[n][0]);
-      cheb_T<float, PA>(pr.loc.tt, &sm.bas[n][PS]);
-      cheb_T<float, PA>(pr.loc.tp, &sm.bas[n][PS + PA]);
-      float c_ = 1.f, s_ = 0.f, rr = 1.f;
-      if (kind != IFGF_KERNEL_CONSTANT) {
-        sincos_f((float)k * pr.dr, &s_, &c_);
-        rr = pr.rp_over_rc;
+      for (int t = threadIdx.x; t <= ngr; t += TPB) {
+        sm.gstart[t] = G.gstart[t];
+        sm.tstart[t] = G.tstart[t];
+        if (t < ngr) sm.gcid[t] = G.gcid[t];
       }
-      sm.rat[n][0] = rr * c_;
-      sm.rat[n][1] = rr * s_;
-    }
-    __syncthreads();
-    if (wv == 0) {   // group the nodes by child cone
-      constexpr int NPL = (P + 63) / 64;
-      int cv[NPL];
-      bool pend[NPL];
-#pragma unroll
-      for (int m = 0; m < NPL; ++m) {
-        const int n = lane + 64 * m;
-        pend[m] = n < P;
-        cv[m] = pend[m] ? sm.cid[n] : 0;
-      }
-      int pos = 0, ng = 0;
-      while (true) {
-        int lead = -1, su = 0;
-#pragma unroll
-        for (int m = 0; m < NPL && lead < 0; ++m) {
-          const uint64_t b = __ballot(pend[m]);
-          if (b) {
-            lead = first_lane(b);
-            su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
-          }
+      const int nt = G.tstart[ngr];
+      for (int t = threadIdx.x; t < nt; t += TPB) sm.tgrp[t] = G.tgrp[t];
+      if (threadIdx.x == 0) sm.ngroup = ngr;
+    } else {
+      for (int n = threadIdx.x; n < P; n += TPB) {
+        float x[3], rp;
+        {   // node_rel32 from the tabulated terms
+          const int bi = (n / PA) % PA, ci = n % PA;
+          const float st = sm.ang[bi][0], ctt = sm.ang[bi][1], sp_ = sm.ang[PA + ci][0], cp = sm.ang[PA + ci][1];
+          const float e0 = st * cp, e1 = st * sp_;
+          rp = sm.rad[n / (PA * PA)];
+          x[0] = rp * e0;
+          x[1] = rp * e1;
+          x[2] = rp * ctt;
         }
-        if (lead < 0) break;
-        if (lane == 0) {
-          sm.gstart[ng] = pos;
-          sm.gcid[ng] = su;
+        const PropF pr = child_loc32(x, rp, oct, gc);
+        sm.cid[n] = pr.loc.cid;
+        cheb_T<float, PS>(pr.loc.ts, &sm.bas[n][0]);
+        cheb_T<float, PA>(pr.loc.tt, &sm.bas[n][PS]);
+        cheb_T<float, PA>(pr.loc.tp, &sm.bas[n][PS + PA]);
+        float c_ = 1.f, s_ = 0.f, rr = 1.f;
+        if (kind != IFGF_KERNEL_CONSTANT) {
+          sincos_f((float)k * pr.dr, &s_, &c_);
+          rr = pr.rp_over_rc;
         }
+        sm.rat[n][0] = rr * c_;
+        sm.rat[n][1] = rr * s_;
+      }
+      __syncthreads();
+      if (wv == 0) {   // group the nodes by child cone
+        constexpr int NPL = (P + 63) / 64;
+        int cv[NPL];
+        bool pend[NPL];
 #pragma unroll
         for (int m = 0; m < NPL; ++m) {
-          const bool hit = pend[m] && cv[m] == su;
-          const uint64_t b = __ballot(hit);
-          if (hit) sm.order[pos + __popcll(b & ((1ull << lane) - 1))] = (short)(lane + 64 * m);
-          pos += __popcll(b);
-          pend[m] = pend[m] && !hit;
+          const int n = lane + 64 * m;
+          pend[m] = n < P;
+          cv[m] = pend[m] ? sm.cid[n] : 0;
         }
-        ++ng;
+        int pos = 0, ng = 0;
+        while (true) {
+          int lead = -1, su = 0;
+#pragma unroll
+          for (int m = 0; m < NPL && lead < 0; ++m) {
+            const uint64_t b = __ballot(pend[m]);
+            if (b) {
+              lead = first_lane(b);
+              su = __builtin_amdgcn_readfirstlane(__shfl(cv[m], lead, 64));
+            }
+          }
+          if (lead < 0) break;
+          if (lane == 0) {
+            sm.gstart[ng] = pos;
+            sm.gcid[ng] = su;
+          }
+#pragma unroll
+          for (int m = 0; m < NPL; ++m) {
+            const bool hit = pend[m] && cv[m] == su;
+            const uint64_t b = __ballot(hit);
+            if (hit) sm.order[pos + __popcll(b & ((1ull << lane) - 1))] = (short)(lane + 64 * m);
+            pos += __popcll(b);
+            pend[m] = pend[m] && !hit;
+          }
+          ++ng;
+        }
+        if (lane == 0) {
+          sm.gstart[ng] = pos;
+          sm.ngroup = ng;
+        }
       }
-      if (lane == 0) {
-        sm.gstart[ng] = pos;
-        sm.ngroup = ng;
+      __syncthreads();
+      if (threadIdx.x == 0) {   // column tiles of the groups
+        int tp = 0;
+        for (int gi = 0; gi < sm.ngroup; ++gi) {
+          sm.tstart[gi] = (short)tp;
+          const int nt = (sm.gstart[gi + 1] - sm.gstart[gi] + 15) >> 4;
+          for (int t = 0; t < nt; ++t) sm.tgrp[tp + t] = (short)gi;
+          tp += nt;
+        }
+        sm.tstart[sm.ngroup] = (short)tp;
       }
     }
     __syncthreads();
-    // whole groups dealt to the waves in turn; a wave loads the group's A
-    // operand (the child cone's coefficients for the 16 RHS, re and im) once
-    // and runs all of the group's column tiles with it
-    const int ng = sm.ngroup;
-    for (int gi = wv; gi < ng; gi += NWV) {
+    // the groups' column tiles, in order, split evenly over the waves; a
+    // wave loads a group's A operand (the child cone's coefficients for the
+    // 16 RHS, re and im) when its run of tiles enters the group
+    const int ngt = sm.tstart[sm.ngroup];
+    const int u0 = wv * ngt / NWV, u1 = (wv + 1) * ngt / NWV;
+    int gcur = -1, sl = -1;
+    float are[PA * PA], aim[PA * PA];
+    for (int u = u0; u < u1; ++u) {
+      const int gi = sm.tgrp[u];
       const int n0 = sm.gstart[gi], n1 = sm.gstart[gi + 1];
-      const int sl = slot_c[(int64_t)B * gc.ncone + sm.gcid[gi]];
-      if (sl < 0) {
-        if (lane == 0) atomicOr(err, 2);
-        continue;
-      }
-      // A rows: RHS g*16 + li of coefficient (la, b, c) of the child cone
-      float are[PA * PA], aim[PA * PA];
-      {
-        const cpx<float>* Cs = Fc_c + ((int64_t)sl * P + (la < PS ? la : 0) * PA * PA) * R + g * MF_RG + li;
+      if (gi != gcur) {   // wave-uniform
+        gcur = gi;
+        sl = slot_c[(int64_t)B * gc.ncone + sm.gcid[gi]];
+        if (sl < 0) {
+          if (lane == 0) atomicOr(err, 2);
+        } else {   // A rows: RHS g*16 + li of coefficient (la, b, c) of the child cone
+          const cpx<float>* Cs = Fc_c + ((int64_t)sl * P + (la < PS ? la : 0) * PA * PA) * R + g * MF_RG + li;
 #pragma unroll
-        for (int t = 0; t < PA * PA; ++t) {
-          const cpx<float> av = la < PS ? Cs[(int64_t)t * R] : cpx<float>{0.f, 0.f};
-          are[t] = av.re;
-          aim[t] = av.im;
+          for (int t = 0; t < PA * PA; ++t) {
+            const cpx<float> av = la < PS ? Cs[(int64_t)t * R] : cpx<float>{0.f, 0.f};
+            are[t] = av.re;
+            aim[t] = av.im;
+          }
         }
       }
-      for (int c0 = n0; c0 < n1; c0 += 16) {
+      if (sl < 0) continue;
+      {
+        const int c0 = n0 + 16 * (u - sm.tstart[gi]);
         const int e = c0 + li;
         const int n = e < n1 ? sm.order[e] : -1;
         float ta = 0.f, tt[PA], tp[PA];
@@ -3707,7 +3755,9 @@ void prop_level(ifgf_plan_s* p, int d, int R, hipStream_t s) {
         k_prop_mfma_cone<PS, PA><<<dim3((unsigned)lp.nrel, R / MF_RG), TPB, 0, s>>>(
             lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
             lc.slot.as<int>(), lc.Fc.as<cpx<T>>(), lp.geom, lc.geom, p->cheb, (const float*)Ms,
-            (const float*)Ma, p->k, kind, R, lp.Fc.as<cpx<T>>(), p->err.as<int>());
+            (const float*)Ma, p->k, kind, R,
+            lp.ti_geo_built && lp.ti_rec.p ? lp.ti_geo.as<TiGeo<PS, PA>>() : nullptr,
+            lp.ti_geo_built && lp.ti_rec.p ? lp.ti_rec.as<int>() : nullptr, lp.Fc.as<cpx<T>>(), p->err.as<int>());
       }
       HIPCHK(hipGetLastError());
       return;

@@ -323,7 +323,7 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
       add(l.start); add(l.coords); add(l.centre); add(l.parent); add(l.child_lo); add(l.nbr_off); add(l.nbr);
       add(l.cou_off); add(l.cou); add(l.pbox); add(l.slot); add(l.slot_off); add(l.rel_box); add(l.rel_cone);
       add(l.Fn); add(l.Fc); add(l.work); add(l.ti_slot); add(l.ti_tile); add(l.ti_child); add(l.ti_geo); add(l.near_work); add(l.leaf_work);
-      add(l.ti_qlist); add(l.adj_tiles); add(l.adj_slots); add(l.adj_gref); add(l.adj_gref_off);
+      add(l.ti_qlist); add(l.ti_rec); add(l.adj_tiles); add(l.adj_slots); add(l.adj_gref); add(l.adj_gref_off);
       add(l.pr_slot); add(l.pr_loc); add(l.pr_fim); add(l.pr_val); add(l.pr_off); add(l.pr_pos);
       add(l.pr_tgt); add(l.pr_run);
       add(p->adj_g[d]);

@@ -81,6 +81,7 @@ struct LevelPlan {
   bool ti_allowed = false;    // the node-record table fits the memory rule (or CONE is forced)
   bool ti_geo_built = false;  // ti_geo holds this level's node records
   DevBuf ti_qlist;            // int [ti_nq]: the cone id of records 8 q .. 8 q + 7
+  DevBuf ti_rec;              // int [nrel]: per relevant cone, the index q of its cone id's records
   int64_t ti_nq = 0;
   // Transposed upward pass into level d + 1 by gathering (built at the first
   // transposed apply, where this level has node records): the relevant cones

@@ -522,6 +522,13 @@ int build_cone_tiles(ifgf_plan_s* p, int d, int nw_req, hipStream_t s) {
     for (int c = clo[b]; c < clo[b + 1]; ++c)
       tchild[8 * i + ((ccoords[3 * c] & 1) | ((ccoords[3 * c + 1] & 1) << 1) | ((ccoords[3 * c + 2] & 1) << 2))] = c;
   }
+  // per relevant cone, the index of its cone id's records (the batched pass reads them)
+  std::vector<int> trec(lv.nrel, -1);
+  for (const auto& t : tl)
+    for (int i = t[1]; i < t[1] + t[2]; ++i)
+      trec[slots[i]] = (int)(std::lower_bound(qlist.begin(), qlist.end(), t[0]) - qlist.begin());
+  lv.ti_rec.alloc(sizeof(int) * lv.nrel);
+  HIPCHK(hipMemcpy(lv.ti_rec.p, trec.data(), sizeof(int) * lv.nrel, hipMemcpyHostToDevice));
   lv.ti_nw = nw;
   lv.ntile = (int64_t)tiles.size() / 4;
   lv.ti_slot.alloc(sizeof(int) * lv.nrel);
