@@ -3255,6 +3255,155 @@ __global__ __launch_bounds__(TPB) void k_adj_prop(int nrel_up, const int* __rest
   }
 }
 
+// P_{d+1}^T as k_adj_prop, with fewer atomic additions: a wave takes NR
+// rounds of 64 consecutive (parent cone, node) items (NR * 64 / P parent
+// cones, mostly of one parent box) and, per child, collects the anterpolated
+// contributions of all its rounds in a table of up to NT child slots held in
+// registers (lane l holds coefficients l + 64 m of every entry).  Each entry
+// is added to the child's coefficient adjoint once per wave and child
+// instead of once per round; a full table is emptied early.
+constexpr int kAdjRounds = 4;   // rounds of 64 items per wave in k_adj_prop_tab (8 measured no faster)
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_adj_prop_tab(int nrel_up, const int* __restrict__ rel_box_up,
+                                                      const int* __restrict__ rel_cone_up,
+                                                      const int* __restrict__ child_lo_up,
+                                                      const int* __restrict__ coords, const int* __restrict__ slot_c,
+                                                      const cpx<T>* __restrict__ Fhat_up, cpx<T>* __restrict__ G_c,
+                                                      LevelGeom gp, LevelGeom gc, ChebTab ct, double k, int kind, int R,
+                                                      int* __restrict__ err) {
+  using S = AntShape<T, PS, PA>;
+  constexpr int P = S::P, NF = S::NF, NCP = S::NCP;
+  constexpr int NR = kAdjRounds;
+  constexpr int NT = Prec<T>::f32 ? 6 : 4;
+  __shared__ T fbuf[TPB / 64][64 * NF];
+  T* fb = fbuf[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63, r = blockIdx.y;
+  const int64_t nit = (int64_t)nrel_up * P;
+  const int64_t wbase = ((int64_t)xcd_block(blockIdx.x, gridDim.x) * (TPB / 64) + (threadIdx.x >> 6)) * (64 * NR);
+  if (wbase >= nit) return;   // wave-uniform; no block barrier below
+  T xr[NR][3], rpr[NR];
+  cpx<T> fhr[NR];
+  int b0r[NR], nchr[NR];
+  bool vr[NR];
+  int cmax = 0;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int64_t t0 = wbase + 64 * q + lane;
+    vr[q] = t0 < nit;
+    const int64_t t = vr[q] ? t0 : nit - 1;
+    const int sp = (int)(t / P), node = (int)(t % P);
+    const int Pb = rel_box_up[sp], pcid = rel_cone_up[sp];
+    fhr[q] = Fhat_up[((int64_t)sp * P + node) * R + r];
+    if constexpr (Prec<T>::f32) node_rel32(pcid, node / (PA * PA), (node / PA) % PA, node % PA, gp, ct, xr[q], &rpr[q]);
+    else node_rel64(pcid, node / (PA * PA), (node / PA) % PA, node % PA, gp, ct, xr[q], &rpr[q]);
+    b0r[q] = child_lo_up[Pb];
+    nchr[q] = child_lo_up[Pb + 1] - b0r[q];
+    if (vr[q]) cmax = max(cmax, nchr[q]);
+  }
+  for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off, 64));
+  int ia[NCP], ib[NCP], ic[NCP];   // this lane's coefficients in a basis row of fbuf
+#pragma unroll
+  for (int m = 0; m < NCP; ++m) {
+    const int j = min(lane + 64 * m, P - 1);
+    ia[m] = 2 + j / (PA * PA);
+    ib[m] = 2 + PS + (j / PA) % PA;
+    ic[m] = 2 + PS + PA + j % PA;
+  }
+  T* f = fb + lane * NF;
+  for (int c = 0; c < cmax; ++c) {
+    int tslot[NT];       // the table's child slots (wave-uniform)
+    cpx<T> tacc[NT][NCP];
+    int tn = 0;
+    auto flush = [&]() {
+#pragma unroll
+      for (int x = 0; x < NT; ++x) {
+        if (x < tn) {
+          cpx<T>* dst = G_c + (int64_t)tslot[x] * P * R + r;
+#pragma unroll
+          for (int m = 0; m < NCP; ++m) {
+            const int j = lane + 64 * m;
+            if (j < P) {
+              atomic_add_t<T>(&dst[(int64_t)j * R].re, tacc[x][m].re);
+              atomic_add_t<T>(&dst[(int64_t)j * R].im, tacc[x][m].im);
+            }
+          }
+        }
+      }
+      tn = 0;
+    };
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const bool has = vr[q] && c < nchr[q];
+      const int B = b0r[q] + min(c, nchr[q] - 1);
+      const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+      typename PropGeomT<T>::P pr;
+      if constexpr (Prec<T>::f32) pr = child_loc32(xr[q], rpr[q], oct, gc);
+      else pr = child_loc64(xr[q], rpr[q], oct, gc);
+      int sl = slot_c[(int64_t)B * gc.ncone + pr.loc.cid];
+      if (sl < 0 && has) atomicOr(err, 2);
+      if (!has) sl = -1;
+      T rr = pr.rp_over_rc, c_, s_;
+      if (kind == IFGF_KERNEL_CONSTANT) {
+        c_ = 1;
+        s_ = 0;
+        rr = 1;
+      } else {
+        sincos_t<T>((T)k * pr.dr, &s_, &c_);
+      }
+      const T rre = rr * c_, rim = rr * s_;
+      const cpx<T> fh = fhr[q];
+      f[0] = rre * fh.re - rim * fh.im;
+      f[1] = rre * fh.im + rim * fh.re;
+      cheb_T<T, PS>(pr.loc.ts, f + 2);
+      cheb_T<T, PA>(pr.loc.tt, f + 2 + PS);
+      cheb_T<T, PA>(pr.loc.tp, f + 2 + PS + PA);
+      __builtin_amdgcn_wave_barrier();
+      uint64_t pending = __ballot(sl >= 0);
+      while (pending) {
+        const int lead = first_lane(pending);
+        const int su = __builtin_amdgcn_readfirstlane(__shfl(sl, lead, 64));
+        const uint64_t grp = __ballot(sl == su);
+        pending &= ~grp;
+        int e = -1;
+#pragma unroll
+        for (int x = 0; x < NT; ++x)
+          if (x < tn && tslot[x] == su) e = x;
+        if (e < 0) {   // a new entry (the table emptied first if full)
+          if (tn == NT) flush();
+          e = tn++;
+#pragma unroll
+          for (int x = 0; x < NT; ++x)
+            if (x == e) {
+              tslot[x] = su;
+#pragma unroll
+              for (int m = 0; m < NCP; ++m) tacc[x][m] = {0, 0};
+            }
+        }
+#pragma unroll
+        for (int x = 0; x < NT; ++x) {
+          if (x != e) continue;
+          uint64_t gg = grp;
+          while (gg) {
+            const int qq = first_lane(gg);
+            gg &= gg - 1;
+            const T* fq = fb + qq * NF;
+            const T wre = fq[0], wim = fq[1];
+#pragma unroll
+            for (int m = 0; m < NCP; ++m) {
+              const T b = fq[ia[m]] * fq[ib[m]] * fq[ic[m]];
+              tacc[x][m].re += wre * b;
+              tacc[x][m].im += wim * b;
+            }
+          }
+        }
+      }
+      __builtin_amdgcn_wave_barrier();   // the round's rows are read before the next round writes them
+    }
+    flush();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // P^T by gathering, on the levels with node records (the cone-major
 // geometry, inverted).  All boxes of a level have one size, so parent node n
@@ -4258,10 +4407,18 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
       }
       {
         StageTimer tm(p, s, IFGF_STAGE_ADJ_PROP);
-        k_adj_prop<T, PS, PA><<<dim3(nblocks(items), R), TPB, 0, s>>>(
-            lv.nrel, lv.rel_box.as<int>(), lv.rel_cone.as<int>(), lv.child_lo.as<int>(), lc.coords.as<int>(),
-            lc.slot.as<int>(), p->adj_g[d].as<cpx<T>>(), p->adj_g[d + 1].as<cpx<T>>(), lv.geom, lc.geom, p->cheb,
-            p->k, kind, R, p->err.as<int>());
+        if constexpr (Prec<T>::f32) {   // the register table (FP64 would need twice the registers)
+          const int64_t nwave = (items + 64 * kAdjRounds - 1) / (64 * kAdjRounds);
+          k_adj_prop_tab<T, PS, PA><<<dim3((unsigned)((nwave + TPB / 64 - 1) / (TPB / 64)), R), TPB, 0, s>>>(
+              lv.nrel, lv.rel_box.as<int>(), lv.rel_cone.as<int>(), lv.child_lo.as<int>(), lc.coords.as<int>(),
+              lc.slot.as<int>(), p->adj_g[d].as<cpx<T>>(), p->adj_g[d + 1].as<cpx<T>>(), lv.geom, lc.geom, p->cheb,
+              p->k, kind, R, p->err.as<int>());
+        } else {
+          k_adj_prop<T, PS, PA><<<dim3(nblocks(items), R), TPB, 0, s>>>(
+              lv.nrel, lv.rel_box.as<int>(), lv.rel_cone.as<int>(), lv.child_lo.as<int>(), lc.coords.as<int>(),
+              lc.slot.as<int>(), p->adj_g[d].as<cpx<T>>(), p->adj_g[d + 1].as<cpx<T>>(), lv.geom, lc.geom, p->cheb,
+              p->k, kind, R, p->err.as<int>());
+        }
       }
       HIPCHK(hipGetLastError());
     }
