@@ -3562,14 +3562,43 @@ __global__ __launch_bounds__(64) void k_adj_ti_mfma(const int4* __restrict__ til
     if (!__ballot(psl >= 0)) continue;   // no box of the wave has this parent cone
     const cpx<float>* F = Fhat_p + (int64_t)(psl >= 0 ? psl : 0) * P;
     const int e0 = G.gstart[ref.y], e1 = G.gstart[ref.y + 1];
-    for (int e = e0; e < e1; e += 4) {   // wave-uniform
+    // a step's records (coordinates, ratio, node) and parent node value; the
+    // next step's node value and the records of the step after it are in
+    // flight while a step runs
+    auto rec_load = [&](int e, float4& lc, float2& rt, int& nd, bool& ok) {
       const int ek = e + k;
-      const bool ok = ek < e1;
+      ok = ek < e1;
       const int ee = ok ? ek : e0;
-      const float4 loc = G.loc[ee];
-      const float2 rt = G.rat[ee];
-      cpx<float> f = {0.0f, 0.0f};
-      if (ok && psl >= 0) f = F[G.node[ee]];
+      lc = G.loc[ee];
+      rt = G.rat[ee];
+      nd = G.node[ee];
+    };
+    float4 lc0, lc1;
+    float2 rt0, rt1;
+    int nd0, nd1;
+    bool ok0, ok1;
+    rec_load(e0, lc0, rt0, nd0, ok0);
+    cpx<float> f0 = {0.0f, 0.0f};
+    if (ok0 && psl >= 0) f0 = F[nd0];
+    rec_load(e0 + 4, lc1, rt1, nd1, ok1);
+    for (int e = e0; e < e1; e += 4) {   // wave-uniform
+      cpx<float> f1 = {0.0f, 0.0f};
+      if (ok1 && psl >= 0) f1 = F[nd1];
+      float4 lc2;
+      float2 rt2;
+      int nd2;
+      bool ok2;
+      rec_load(e + 8, lc2, rt2, nd2, ok2);
+      const float4 loc = lc0;
+      const float2 rt = rt0;
+      const cpx<float> f = f0;
+      lc0 = lc1;
+      rt0 = rt1;
+      f0 = f1;
+      lc1 = lc2;
+      rt1 = rt2;
+      nd1 = nd2;
+      ok1 = ok2;
       const float av = partA ? rt.x * f.im + rt.y * f.re : rt.x * f.re - rt.y * f.im;
       float Ts[PS], Tt[PA], Tp[PA];
       cheb_T<float, PS>(loc.x, Ts);
