@@ -445,52 +445,62 @@ __global__ __launch_bounds__(TPB) void k_leaf(const int4* __restrict__ work, con
 
 // ---------------------------------------------------------------------------
 // node values -> coefficients: c_ijl = sum_abc Ms[i][a] Ma[j][b] Ma[l][c] v_abc,
-// one block per cone, three separable passes through LDS.  With TR the
+// coeff_cones(P) cones per block (one cone of 144 coefficients is too small
+// to fill a block), three separable passes through LDS.  With TR the
 // transposed map (Ms^T, Ma^T) is applied.  Fn may equal Fc (in place).
 // ---------------------------------------------------------------------------
+constexpr int coeff_cones(int P) { return P <= 160 ? 8 : 1; }
+
 template <typename T, int PS, int PA, bool TR>
 __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, int nrel, int R,
                                                 const T* __restrict__ Ms, const T* __restrict__ Ma,
                                                 cpx<T>* __restrict__ Fc) {
   constexpr int P = PS * PA * PA;
-  __shared__ cpx<T> v0[P], v1[P];
+  constexpr int NC = coeff_cones(P);
+  __shared__ cpx<T> v0[NC * P], v1[NC * P];
   __shared__ T ms[PS * PS], ma[PA * PA];
-  const int sl = blockIdx.x, r = blockIdx.y, t0 = threadIdx.x;
+  const int c0 = blockIdx.x * NC, r = blockIdx.y, t0 = threadIdx.x;
+  const int nc = min(NC, nrel - c0);
+  const int nt = nc * P;
   if (t0 < PS * PS) ms[t0] = TR ? Ms[(t0 % PS) * PS + t0 / PS] : Ms[t0];
   if (t0 < PA * PA) ma[t0] = TR ? Ma[(t0 % PA) * PA + t0 / PA] : Ma[t0];
-  for (int t = t0; t < P; t += TPB) v0[t] = Fn[((int64_t)sl * P + t) * R + r];
+  for (int t = t0; t < nt; t += TPB) v0[t] = Fn[((int64_t)c0 * P + t) * R + r];
   __syncthreads();
-  for (int t = t0; t < P; t += TPB) {  // over a (s)
-    const int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
+  for (int t = t0; t < nt; t += TPB) {  // over a (s)
+    const int cb = t / P * P, u = t % P;
+    const int i = u / (PA * PA), j = (u / PA) % PA, l = u % PA;
     cpx<T> s = {0, 0};
     for (int q = 0; q < PS; ++q) {
-      cpx<T> x = v0[(q * PA + j) * PA + l];
+      cpx<T> x = v0[cb + (q * PA + j) * PA + l];
       s.re += ms[i * PS + q] * x.re;
       s.im += ms[i * PS + q] * x.im;
     }
     v1[t] = s;
   }
   __syncthreads();
-  for (int t = t0; t < P; t += TPB) {  // over b (theta)
-    const int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
+  for (int t = t0; t < nt; t += TPB) {  // over b (theta)
+    const int cb = t / P * P, u = t % P;
+    const int i = u / (PA * PA), j = (u / PA) % PA, l = u % PA;
     cpx<T> s = {0, 0};
     for (int q = 0; q < PA; ++q) {
-      cpx<T> x = v1[(i * PA + q) * PA + l];
+      cpx<T> x = v1[cb + (i * PA + q) * PA + l];
       s.re += ma[j * PA + q] * x.re;
       s.im += ma[j * PA + q] * x.im;
     }
     v0[t] = s;
   }
   __syncthreads();
-  for (int t = t0; t < P; t += TPB) {  // over c (phi)
-    const int i = t / (PA * PA), j = (t / PA) % PA, l = t % PA;
+  for (int t = t0; t < nt; t += TPB) {  // over c (phi)
+    const int cb = t / P * P, u = t % P;
+    const int i = u / (PA * PA), j = (u / PA) % PA;
+    const int l = u % PA;
     cpx<T> s = {0, 0};
     for (int q = 0; q < PA; ++q) {
-      cpx<T> x = v0[(i * PA + j) * PA + q];
+      cpx<T> x = v0[cb + (i * PA + j) * PA + q];
       s.re += ma[l * PA + q] * x.re;
       s.im += ma[l * PA + q] * x.im;
     }
-    Fc[((int64_t)sl * P + t) * R + r] = s;
+    Fc[((int64_t)c0 * P + t) * R + r] = s;
   }
 }
 
@@ -4045,7 +4055,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           k_coeffs_rg<T, PS, PA, MF_RG><<<dim3(lD.nrel, R / MF_RG), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), R, Ms, Ma,
                                                                                 lD.Fc.as<cpx<T>>());
       } else
-        k_coeffs<T, PS, PA, false><<<dim3(lD.nrel, R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma,
+        k_coeffs<T, PS, PA, false><<<dim3((lD.nrel + coeff_cones(P) - 1) / coeff_cones(P), R), TPB, 0, s>>>(lD.Fn.as<cpx<T>>(), lD.nrel, R, Ms, Ma,
                                                                    lD.Fc.as<cpx<T>>());
       HIPCHK(hipGetLastError());
     }
@@ -4406,7 +4416,7 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
       LevelPlan& lv = p->lev[d];
       if (lv.nrel > 0) {
         StageTimer tm(p, s, IFGF_STAGE_ADJ_COEFFS);
-        k_coeffs<T, PS, PA, true><<<dim3(lv.nrel, R), TPB, 0, s>>>(p->adj_g[d].as<cpx<T>>(), lv.nrel, R, Ms, Ma,
+        k_coeffs<T, PS, PA, true><<<dim3((lv.nrel + coeff_cones(P) - 1) / coeff_cones(P), R), TPB, 0, s>>>(p->adj_g[d].as<cpx<T>>(), lv.nrel, R, Ms, Ma,
                                                                   p->adj_g[d].as<cpx<T>>());
       }
       HIPCHK(hipGetLastError());
