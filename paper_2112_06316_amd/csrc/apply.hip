@@ -3746,7 +3746,9 @@ __global__ __launch_bounds__(TPB) void k_adj_leaf(const double* __restrict__ pts
           T inv = (T)1 / nv;
           T ph = kh * qq / (nv + (T)1);
           T sp, cp;
-          sincos_t<T>(ph, &sp, &cp);
+          // |ph| <= k h, as in the forward leaf factors
+          if constexpr (Prec<T>::f32) sincos_hw(ph, &sp, &cp);
+          else sincos_t<T>(ph, &sp, &cp);
           T vn = en - s * sun[q];
           T A = vn * s * inv * inv * inv * ih;
           T Bv = kk * vn * inv * inv + ee * inv;
