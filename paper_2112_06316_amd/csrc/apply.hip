@@ -53,6 +53,18 @@ template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return sqr
 template <> __device__ __forceinline__ double sqrt_t<double>(double x) { return sqrt(x); }
 // 1/x: the hardware reciprocal in FP32 (about 1 ulp, as elsewhere in the FP32
 // path), IEEE division in FP64.
+// sqrt(x) and 1 / sqrt(x) of x > 0: in FP32 from the hardware reciprocal
+// square root (one transcendental instead of a square root and a reciprocal)
+template <typename T> __device__ __forceinline__ void sqrt_rsqrt(T x, T* sq, T* rs);
+template <> __device__ __forceinline__ void sqrt_rsqrt<float>(float x, float* sq, float* rs) {
+  const float r = __builtin_amdgcn_rsqf(x);
+  *rs = r;
+  *sq = x * r;
+}
+template <> __device__ __forceinline__ void sqrt_rsqrt<double>(double x, double* sq, double* rs) {
+  *sq = sqrt(x);
+  *rs = 1.0 / *sq;
+}
 template <typename T> __device__ __forceinline__ T rcp_t(T x);
 template <> __device__ __forceinline__ float rcp_t<float>(float x) { return rcp_f(x); }
 template <> __device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
@@ -226,8 +238,8 @@ __device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int tof
           } else {
             T d0 = x0 - sx[e][0], d1 = x1 - sx[e][1], d2 = x2 - sx[e][2];
             T r2 = d0 * d0 + d1 * d1 + d2 * d2;
-            T rr = sqrt_t<T>(r2);
-            T ir = rcp_t<T>(rr);
+            T rr, ir;
+            sqrt_rsqrt<T>(r2, &rr, &ir);
             // forward: <x_t - x_s, n_s>; transposed: <x_s - x_t, n_t>
             T dn = TR ? -(d0 * m0 + d1 * m1 + d2 * m2) * ir * ir
                       : (d0 * sn[e][0] + d1 * sn[e][1] + d2 * sn[e][2]) * ir * ir;
@@ -376,8 +388,8 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int i0, int
             T eu = e[0] * su[q][0] + e[1] * su[q][1] + e[2] * su[q][2];
             T en = e[0] * sn[q][0] + e[1] * sn[q][1] + e[2] * sn[q][2];
             T qq = s * suu[q] - (T)2 * eu;
-            T nv = sqrt_t<T>((T)1 + s * qq);
-            T inv = rcp_t<T>(nv);
+            T nv, inv;
+            sqrt_rsqrt<T>((T)1 + s * qq, &nv, &inv);
             T ph = kh * qq * rcp_t<T>(nv + (T)1);
             T sp, cp;
             // |ph| <= k h (h: the box's half diagonal, k h = 2.7 for leaves
@@ -3742,9 +3754,9 @@ __global__ __launch_bounds__(TPB) void k_adj_leaf(const double* __restrict__ pts
           T eu = e[0] * su[q][0] + e[1] * su[q][1] + e[2] * su[q][2];
           T en = e[0] * sn[q][0] + e[1] * sn[q][1] + e[2] * sn[q][2];
           T qq = s * suu[q] - (T)2 * eu;
-          T nv = sqrt_t<T>((T)1 + s * qq);
-          T inv = (T)1 / nv;
-          T ph = kh * qq / (nv + (T)1);
+          T nv, inv;
+          sqrt_rsqrt<T>((T)1 + s * qq, &nv, &inv);
+          T ph = kh * qq * rcp_t<T>(nv + (T)1);
           T sp, cp;
           // |ph| <= k h, as in the forward leaf factors
           if constexpr (Prec<T>::f32) sincos_hw(ph, &sp, &cp);
