@@ -61,6 +61,18 @@ KERNEL_OF_STAGE = {"prop": "k_prop (node formulation)", "prop_cone": "k_prop_ti 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_06316_amd", "csrc", f) for f in ("apply.hip", "common.h", "plan.hip")]
 
 
+def pair_row_use(st):
+    """Per level, the pair-list row stage's passes per row of 16 pairs and its
+    lane use (pairs / (16 x passes)); empty without pair lists."""
+    out = {}
+    for d, rows in st.get("pair_rows", {}).items():
+        passes = st["pair_row_cones"][d]
+        if rows and passes:
+            pairs = st["cousin_pairs"][d]
+            out[d] = {"rows": rows, "passes_per_row": passes / rows, "lane_use": pairs / (16.0 * passes)}
+    return out
+
+
 def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
@@ -537,7 +549,8 @@ def main():
         "peaks_measured": peaks,
         "plan": {"cones": st["cones"], "boxes": st["boxes"], "near_pairs": st["near_pairs"],
                  "upward_pass_formulation": st["prop_kernel"],
-                 "cousin_pairs": cousin, "prop_evals": prop_evals, "device_bytes": st["device_bytes"]},
+                 "cousin_pairs": cousin, "prop_evals": prop_evals, "device_bytes": st["device_bytes"],
+                 "pair_row_stage": pair_row_use(st)},
         "consistency_flags": r32["flags"],
     }
     out["adjoint"] = adj

@@ -155,6 +155,11 @@ typedef struct {
     int32_t prop_kernel[IFGF_MAX_LEVELS];   /* upward pass from child level d (index d):
                                                IFGF_PROP_NODE or IFGF_PROP_CONE with one
                                                FP32 right-hand side, 0 if no pass       */
+    int64_t pair_rows[IFGF_MAX_LEVELS];     /* rows of 16 consecutive pairs of level d's
+                                               cousin-target pair list (0: no lists)    */
+    int64_t pair_row_cones[IFGF_MAX_LEVELS];/* cone slots met by those rows, summed: the
+                                               row stage's passes (lane use = pairs /
+                                               (16 x passes))                           */
 } ifgf_plan_stats;
 
 /* Fill *o with the defaults listed above.  o: [host], non-null. */

@@ -54,6 +54,8 @@ class Stats(ctypes.Structure):
         ("prop_evals", ctypes.c_int64 * MAX_LEVELS),
         ("device_bytes", ctypes.c_int64),
         ("prop_kernel", ctypes.c_int32 * MAX_LEVELS),
+        ("pair_rows", ctypes.c_int64 * MAX_LEVELS),
+        ("pair_row_cones", ctypes.c_int64 * MAX_LEVELS),
     ]
 
 

@@ -243,6 +243,8 @@ class Plan:
             "prop_evals": {d: s.prop_evals[d] for d in range(4, D + 1)},
             "near_pairs": s.near_pairs, "device_bytes": s.device_bytes,
             "prop_kernel": {d: {1: "node", 2: "cone"}.get(s.prop_kernel[d], "none") for d in range(4, D + 1)},
+            "pair_rows": {d: s.pair_rows[d] for d in range(3, D + 1)},
+            "pair_row_cones": {d: s.pair_row_cones[d] for d in range(3, D + 1)},
         }
 
     def set_profiling(self, max_launches: int):

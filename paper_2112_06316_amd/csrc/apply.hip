@@ -1559,6 +1559,21 @@ __global__ __launch_bounds__(TPB) void k_targets_pairsum(int64_t n, const int* _
   }
 }
 
+// Per row of 16 consecutive sorted pairs, the cone slots it meets (1 + the
+// slot changes inside the row): the passes of the row stage.
+__global__ __launch_bounds__(TPB) void k_pair_rows(const int* __restrict__ slot, int64_t np,
+                                                   unsigned long long* __restrict__ acc) {
+  const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  unsigned long long v = 0;
+  if (r * 16 < np) {
+    const int64_t q0 = r * 16, q1 = min(np, q0 + 16);
+    v = 1;
+    for (int64_t q = q0 + 1; q < q1; ++q) v += slot[q] != slot[q - 1] ? 1 : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(acc, v);
+}
+
 // per target, the number of its cousin pairs at a level
 __global__ __launch_bounds__(TPB) void k_pair_count(const int* __restrict__ pbox, const int* __restrict__ cou_off,
                                                     int64_t n, int* __restrict__ cnt) {
@@ -5221,6 +5236,19 @@ void build_target_pairs_impl(ifgf_plan_s* p, hipStream_t s) {
                                                lv.pr_slot.as<int>(), lv.pr_loc.as<V4>(), lv.pr_fim.as<T>(),
                                                lv.pr_pos.as<int>());
     HIPCHK(hipGetLastError());
+    {   // row-stage passes, for the statistics
+      DevBuf acc;
+      acc.alloc(sizeof(unsigned long long));
+      HIPCHK(hipMemsetAsync(acc.p, 0, sizeof(unsigned long long), s));   // plan time
+      const int64_t nrow = (np + 15) / 16;
+      k_pair_rows<<<nblocks(nrow), TPB, 0, s>>>(lv.pr_slot.as<int>(), np, acc.as<unsigned long long>());
+      HIPCHK(hipGetLastError());
+      unsigned long long h = 0;
+      HIPCHK(hipMemcpyAsync(&h, acc.p, sizeof(h), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      lv.pair_rows = nrow;
+      lv.pair_row_cones = (int64_t)h;
+    }
     HIPCHK(hipStreamSynchronize(s));   // the temporaries are freed on return
   }
   p->pairs = true;
@@ -5251,6 +5279,7 @@ void release_target_pairs(ifgf_plan_s* p) {
     lv.pr_tgt.release();
     lv.pr_run.release();
     lv.nrun = 0;
+    lv.pair_rows = lv.pair_row_cones = 0;
   }
   p->pairs = false;
   p->adj_pairs = false;

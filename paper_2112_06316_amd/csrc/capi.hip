@@ -320,6 +320,8 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
       st->cones[d] = l.nrel;
       st->cousin_pairs[d] = l.cousin_pairs;
       st->prop_evals[d] = l.prop_evals;
+      st->pair_rows[d] = l.pair_rows;
+      st->pair_row_cones[d] = l.pair_row_cones;
       add(l.start); add(l.coords); add(l.centre); add(l.parent); add(l.child_lo); add(l.nbr_off); add(l.nbr);
       add(l.cou_off); add(l.cou); add(l.pbox); add(l.slot); add(l.slot_off); add(l.rel_box); add(l.rel_cone);
       add(l.Fn); add(l.Fc); add(l.work); add(l.ti_slot); add(l.ti_tile); add(l.ti_child); add(l.ti_geo); add(l.near_work); add(l.leaf_work);

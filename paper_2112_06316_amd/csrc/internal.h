@@ -110,6 +110,7 @@ struct LevelPlan {
   DevBuf pr_tgt;              // int [npair]
   DevBuf pr_run;              // int [nrun + 1]
   int64_t nrun = 0;
+  int64_t pair_rows = 0, pair_row_cones = 0;   // rows of 16 pairs, and the cone slots they meet
   // statistics
   int64_t cousin_pairs = 0;
   int64_t prop_evals = 0;     // child interpolations into level d-1 nodes

@@ -414,3 +414,20 @@ def test_pair_targets_equal_row_targets(precision, tol):
     e = float(np.linalg.norm(u["pairs"] - u["rows"]) / np.linalg.norm(u["rows"]))
     log(f"case pairs vs rows {precision}: rel diff {e:.2e}, bitwise equal {bool(np.array_equal(u['pairs'], u['rows']))}")
     assert e <= tol
+
+
+def test_pair_row_statistics():
+    # Rows of 16 consecutive sorted pairs: ceil(pairs / 16) per level, each
+    # meeting at least one cone slot and at most 16; no lists, no rows.
+    p, nr, w = inputs.cubed_sphere(32)
+    k = 8 * np.pi
+    plan = Plan(p, nr, w, k, k, depth=4, target_kernel="pairs")
+    st = plan.stats()
+    for d in range(3, 5):
+        npair = st["cousin_pairs"][d]
+        rows = st["pair_rows"][d]
+        log(f"case pair rows level {d}: pairs {npair}, rows {rows}, cones met {st['pair_row_cones'][d]}")
+        assert rows == (npair + 15) // 16
+        assert rows <= st["pair_row_cones"][d] <= 16 * rows
+    plain = Plan(p, nr, w, k, k, depth=4, target_kernel="rows")
+    assert all(v == 0 for v in plain.stats()["pair_rows"].values())
