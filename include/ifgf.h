@@ -262,8 +262,10 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats *st);
  * ifgf_plan_export_cones: level d relevant cones: box (cones int32) and
  *   cone id (cones int32), cone id = (i_s * n_C + i_theta) * 2 n_C + i_phi.
  * ifgf_plan_export_field: after an apply, the level-d field of the last
- *   call, as node values (what = 0, finest level d = D only; the other
- *   levels keep coefficients only) or Chebyshev coefficients (what = 1):
+ *   call, as node values (what = 0, finest level d = D only, recovered
+ *   from its coefficients by the inverse Chebyshev transform: equal to
+ *   rounding to the values the coefficients were made from) or Chebyshev
+ *   coefficients (what = 1):
  *   cones x P x nrhs complex of the plan precision (double or float pairs),
  *   P = p_s * p_ang^2, node (a, b, c) or coefficient (i, j, l) at index
  *   (a * p_ang + b) * p_ang + c.

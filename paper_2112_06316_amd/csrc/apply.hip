@@ -412,9 +412,12 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int i0, int
       }
     }
     if (valid) {
+      if (fv) {   // one RHS: the node values go to LDS only (the caller turns them into coefficients)
+        fv[it - i0] = acc[0];
+      } else {
 #pragma unroll
-      for (int q2 = 0; q2 < RG; ++q2) Fn[((int64_t)s0 * P + it) * R + r0 + q2] = acc[q2];
-      if (fv) fv[it - i0] = acc[0];   // the node values also kept in LDS (one RHS)
+        for (int q2 = 0; q2 < RG; ++q2) Fn[((int64_t)s0 * P + it) * R + r0 + q2] = acc[q2];
+      }
     }
   }
 }
@@ -4999,6 +5002,33 @@ void dispatch_apply(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype
   throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
 }
 
+// The finest level's node values of the last apply, from its coefficients:
+// v_abc = sum_ijl T_i(x_a) T_j(x_b) T_l(x_c) c_ijl (the inverse of the
+// coefficient transform, the same three separable passes with the matrices
+// of Chebyshev values at the nodes).  The single-RHS apply keeps the node
+// values in LDS only, so they are recovered here when asked for.
+template <typename T, int PS, int PA>
+void export_nodes_impl(ifgf_plan_s* p, void* dst, hipStream_t s) {
+  constexpr int P = PS * PA * PA;
+  LevelPlan& l = p->lev[p->D];
+  const int R = std::max(1, p->last_rhs);
+  if (l.nrel == 0) return;
+  std::vector<T> mi(PS * PS), ai(PA * PA);
+  for (int a = 0; a < PS; ++a)
+    for (int i = 0; i < PS; ++i) mi[a * PS + i] = (T)std::cos(i * (2.0 * a + 1.0) * IFGF_PI / (2.0 * PS));
+  for (int b = 0; b < PA; ++b)
+    for (int j = 0; j < PA; ++j) ai[b * PA + j] = (T)std::cos(j * (2.0 * b + 1.0) * IFGF_PI / (2.0 * PA));
+  DevBuf md, ad;
+  md.alloc(sizeof(T) * mi.size());
+  ad.alloc(sizeof(T) * ai.size());
+  HIPCHK(hipMemcpyAsync(md.p, mi.data(), sizeof(T) * mi.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ad.p, ai.data(), sizeof(T) * ai.size(), hipMemcpyHostToDevice, s));
+  k_coeffs<T, PS, PA, false><<<dim3((l.nrel + coeff_cones(P) - 1) / coeff_cones(P), R), TPB, 0, s>>>(
+      l.Fc.as<cpx<T>>(), l.nrel, R, md.as<T>(), ad.as<T>(), (cpx<T>*)dst);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));   // the matrices are freed on return
+}
+
 template <typename T, int PS, int PA>
 void far_field_impl(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double* dirs, void* uinf, int dtype,
                     hipStream_t s) {
@@ -5301,6 +5331,26 @@ void build_target_pairs(ifgf_plan_s* p, hipStream_t s) {
     build_target_pairs_impl<float>(p, s);
   else
     build_target_pairs_impl<double>(p, s);
+}
+
+template <typename T>
+void dispatch_export_nodes(ifgf_plan_s* p, void* dst, hipStream_t s) {
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+#define X(a, b) \
+  if (ps == a && pa == b) return export_nodes_impl<T, a, b>(p, dst, s);
+  IFGF_ORDERS_ALL(X)
+  if constexpr (!Prec<T>::f32) {
+    IFGF_ORDERS_FP64(X)
+  }
+#undef X
+  throw Error{IFGF_EUNSUPPORTED, "interpolation order not compiled"};
+}
+
+void run_export_nodes(ifgf_plan_s* p, void* dst, hipStream_t s) {
+  if (p->opt.precision == IFGF_PREC_FP32_INTERP)
+    dispatch_export_nodes<float>(p, dst, s);
+  else
+    dispatch_export_nodes<double>(p, dst, s);
 }
 
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask, int level_lo,

@@ -389,7 +389,11 @@ ifgf_status ifgf_plan_export_field(ifgf_plan p, int32_t d, int32_t what, void* d
     if (what == 0 && d != p->D) throw Error{IFGF_EINVAL, "node values are kept for the finest level only"};
     size_t csz = p->opt.precision == IFGF_PREC_FP32_INTERP ? 8 : 16;
     size_t bytes = csz * (size_t)l.nrel * p->P * std::max(1, p->last_rhs);
-    if (bytes) sync_copy(dst, (what == 0 ? l.Fn : l.Fc).p, bytes);
+    if (!bytes) return;
+    if (what == 0)
+      run_export_nodes(p, dst, nullptr);   // the default stream, as the copies here
+    else
+      sync_copy(dst, l.Fc.p, bytes);
   });
 }
 

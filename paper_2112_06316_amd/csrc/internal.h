@@ -200,6 +200,7 @@ int build_cone_tiles(ifgf_plan_s* p, int d, int nw_req, hipStream_t s);
 void run_apply(ifgf_plan_s* p, const void* sigma, void* u, int nrhs, int dtype, int stage_mask,
                int level_lo, int level_hi, hipStream_t s);
 void run_adjoint(ifgf_plan_s* p, const void* v, void* out, int nrhs, int dtype, int conj, hipStream_t s);
+void run_export_nodes(ifgf_plan_s* p, void* dst, hipStream_t s);   // finest level's node values, device dst
 void run_far_field(ifgf_plan_s* p, const void* sigma, int64_t ndir, const double* dirs, void* uinf, int dtype,
                    hipStream_t s);
 void run_autotune(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t s);
