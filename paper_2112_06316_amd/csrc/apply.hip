@@ -1476,14 +1476,11 @@ __global__ __launch_bounds__(TPB) void k_pair_place(const uint64_t* __restrict__
   pos[orig] = (int)q;
 }
 
-// Pass one: the value of every pair of level dlo + blockIdx.y.
+// Pass one for the TPB pairs q0 .. q0 + TPB - 1 of a level (one per thread).
 template <typename T, int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
+__device__ __forceinline__ void pairs_block(const PLevel<T>& lv, int64_t q0) {
   constexpr int P = PS * PA * PA;
   constexpr int NONE = 0x7fffffff;
-  const PLevel<T>& lv = L.lv[dlo + blockIdx.y];
-  const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB;
-  if (q0 >= lv.np) return;   // block-uniform
   const int64_t q = q0 + threadIdx.x;
   const bool valid = q < lv.np;
   const int sl = valid ? lv.slot[q] : NONE;
@@ -1514,6 +1511,15 @@ __global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
   if (valid) lv.val[q] = {o_re, o_im};
 }
 
+// Pass one: the value of every pair of level dlo + blockIdx.y.
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
+  const PLevel<T>& lv = L.lv[dlo + blockIdx.y];
+  const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB;
+  if (q0 >= lv.np) return;   // block-uniform
+  pairs_block<T, PS, PA>(lv, q0);
+}
+
 // Pass two: u = near field + per level (finest first) the sum of the
 // target's pair values, scattered to the caller's order.  16 lanes per
 // target: lane j adds pairs j, j + 16, ... of the target's list at a level
@@ -1521,11 +1527,10 @@ __global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
 // partial sums.  The order is fixed (every call gives the same sums), not
 // the row formulation's sequential one (the two agree to rounding).
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_targets_pairsum(int64_t n, const int* __restrict__ perm,
-                                                         const cpx<T>* __restrict__ uacc, int use_near,
-                                                         PLevels<T> L, int dlo, int dhi, int dtype,
-                                                         void* __restrict__ u) {
-  const int64_t i0 = ((int64_t)blockIdx.x * TPB + threadIdx.x) >> 4;
+__device__ __forceinline__ void pairsum16(int64_t tid, int64_t n, const int* __restrict__ perm,
+                                          const cpx<T>* __restrict__ uacc, int use_near, const PLevels<T>& L,
+                                          int dlo, int dhi, int dtype, void* __restrict__ u) {
+  const int64_t i0 = tid >> 4;
   const int j = threadIdx.x & 15;
   const bool valid = i0 < n;
   const int64_t i = valid ? i0 : n - 1;   // every lane takes part in the butterfly
@@ -1560,6 +1565,14 @@ __global__ __launch_bounds__(TPB) void k_targets_pairsum(int64_t n, const int* _
     ((float*)u)[2 * o] = (float)re;
     ((float*)u)[2 * o + 1] = (float)im;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_targets_pairsum(int64_t n, const int* __restrict__ perm,
+                                                         const cpx<T>* __restrict__ uacc, int use_near,
+                                                         PLevels<T> L, int dlo, int dhi, int dtype,
+                                                         void* __restrict__ u) {
+  pairsum16<T>((int64_t)blockIdx.x * TPB + threadIdx.x, n, perm, uacc, use_near, L, dlo, dhi, dtype, u);
 }
 
 // Per row of 16 consecutive sorted pairs, the cone slots it meets (1 + the
@@ -4534,7 +4547,7 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
 // counter increment; after a wait every wave issues an agent-scope acquire
 // fence (stale cache lines dropped) before it reads.
 // ---------------------------------------------------------------------------
-enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_PROP = 4, BT_TARGET = 5, BT_PROPTI = 6 };
+enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_PROP = 4, BT_TARGET = 5, BT_PROPTI = 6, BT_PAIRS = 7, BT_PAIRSUM = 8 };
 // Threads per work-group of the batch launch: every stage body runs at this
 // size (the cone-major tiles need 4 waves of 8 boxes).
 constexpr int BBS = 256;
@@ -4544,6 +4557,8 @@ constexpr int BBS = 256;
 // cones' node values into coefficients); target items hold BBS points; a
 // cone-major item is one tile.
 constexpr int BG_GATHER = 4, BG_PROP = 8, BG_NEAR = 16, BG_LEAF = 8;
+// pair items: BG_PAIRS chunks of BS sorted pairs; pair-sum items: BG_PAIRSUM x BS / 16 targets
+constexpr int BG_PAIRS = 16, BG_PAIRSUM = 8;
 
 template <typename T> struct BLevel {
   int nb, nrel, nwork, n_near, n_leaf;
@@ -4573,6 +4588,8 @@ template <typename T> struct BGeom {
   int64_t n;
   int D, kind;
   int trows;   // cousin targets in the row-broadcast formulation
+  int pairs;   // cousin targets from the plan's pair lists (two item kinds)
+  int64_t pchunk[IFGF_MAX_LEVELS + 1];   // pair items: level d's first item (d = 3 .. D), then the total
   double k, eta;
   const double IFGF_GAS* pts;
   const double IFGF_GAS* nrm;
@@ -4585,6 +4602,7 @@ template <typename T> struct BGeom {
   int IFGF_GAS* err;
   ChebTab ct;
   TLevels<T> tl;
+  PLevels<T> pl;
   BLevel<T> lv[IFGF_MAX_LEVELS];
 };
 
@@ -4728,6 +4746,18 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
       }
       break;
     }
+    case BT_PAIRS: {   // BG_PAIRS chunks of BS sorted pairs of level S.level: their values
+      const int d = S.level;
+      const int64_t n = G.pchunk[d + 1] - G.pchunk[d];
+      const int64_t c0 = (int64_t)local * BG_PAIRS, c1 = min(c0 + BG_PAIRS, n);
+      for (int64_t c = c0; c < c1; ++c) pairs_block<T, PS, PA>(G.pl.lv[d], c * BS);
+      break;
+    }
+    case BT_PAIRSUM:   // BG_PAIRSUM x BS / 16 targets: near field + their pair values, to the caller's order
+      for (int u = 0; u < BG_PAIRSUM; ++u)
+        pairsum16<T>(((int64_t)local * BG_PAIRSUM + u) * BS + threadIdx.x, G.n, gen(G.perm), gen(G.uacc), 1, G.pl,
+                     3, D, dtype, io.u[S.geom]);
+      break;
     case BT_TARGET: {
       const int dlo = D >= 3 ? 3 : 1, dhi = D >= 3 ? D : 0;
       if (G.trows) {
@@ -4769,7 +4799,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
   }
   // every wave waits until its stores have reached L2; then one agent-scope
   // release (L2 write-back) covers the stores of the whole work-group
-  if (S.type == BT_TARGET) return;   // nothing in the launch consumes the targets' output
+  if (S.type == BT_TARGET || S.type == BT_PAIRSUM) return;   // nothing in the launch consumes the targets' output
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -4809,6 +4839,17 @@ void batch_prepare_impl(ifgf_batch_s* b) {
     G.uacc = gas(p->uacc.as<cpx<T>>());
     G.err = gas(p->err.as<int>());
     G.ct = p->cheb;
+    G.pairs = p->pairs && rows_ok<T, PS, PA>() ? 1 : 0;
+    int64_t pc = 0;
+    for (int d = 0; d <= IFGF_MAX_LEVELS; ++d) G.pchunk[d] = 0;
+    for (int d = 3; d <= p->D && G.pairs; ++d) {
+      const LevelPlan& l = p->lev[d];
+      G.pl.lv[d] = {l.npair, l.pr_slot.as<int>(), l.pr_loc.as<typename Vec4<T>::type>(), l.pr_fim.as<T>(),
+                    l.pr_val.as<cpx<T>>(), l.pr_off.as<int>(), l.pr_pos.as<int>(), l.Fc.as<cpx<T>>()};
+      G.pchunk[d] = pc;
+      pc += (l.npair + BBS - 1) / BBS;
+    }
+    if (G.pairs) G.pchunk[p->D + 1] = pc;
     for (int d = 1; d <= p->D; ++d) {
       const LevelPlan& l = p->lev[d];
       BLevel<T>& L = G.lv[d];
@@ -4846,7 +4887,7 @@ void batch_prepare_impl(ifgf_batch_s* b) {
 
   // ---- the queue ----------------------------------------------------------------
   auto C = [](int g, int k) { return 1 + 16 * g + k; };   // counters: 0 = queue head, then 16 per geometry
-  enum { K_GATHER = 0, K_LEAF = 1, K_NEAR = 2, K_PROP0 = 4, K_TARGET = 15 };   // K_PROP0 + d: into level d
+  enum { K_GATHER = 0, K_LEAF = 1, K_NEAR = 2, K_PAIRS = 3, K_PROP0 = 4, K_TARGET = 15 };   // K_PROP0 + d: into level d
   std::vector<BSeg> segs;
   int64_t first = 0;
   auto emit = [&](int type, int g, int level, int64_t count, int dep0, int need0, int dep1, int need1, int done) {
@@ -4888,9 +4929,35 @@ void batch_prepare_impl(ifgf_batch_s* b) {
   // targets of shallow trees overlap the upward pass of deeper ones.
   int maxD = 0;
   for (auto* p : b->plans) maxD = std::max(maxD, p->D);
+  // Pair values of level d need only level d's coefficients: they are queued
+  // right behind the next upward step, whose waits they fill.
+  std::vector<std::vector<std::pair<int, int>>> made(ng);   // made[g][d]: producer of level d's coefficients
+  std::vector<int> pend(ng);                                // next level whose pairs are not queued
+  std::vector<int64_t> npair(ng, 0);
+  for (int g = 0; g < ng; ++g) {
+    made[g].assign(IFGF_MAX_LEVELS + 1, {-1, 0});
+    made[g][b->plans[g]->D] = last[g];
+    pend[g] = b->plans[g]->D;
+  }
+  auto emit_pairs = [&](int g, int dmin) {   // the pair items of levels pend[g] down to dmin
+    const BGeom<T>& G = geo[g];
+    for (; G.pairs && pend[g] >= std::max(3, dmin); --pend[g]) {
+      const int d = pend[g];
+      const int64_t np = (G.pchunk[d + 1] - G.pchunk[d] + BG_PAIRS - 1) / BG_PAIRS;
+      emit(BT_PAIRS, g, d, np, made[g][d].first, made[g][d].second, -1, 0, C(g, K_PAIRS));
+      npair[g] += std::max<int64_t>(0, np);
+    }
+  };
   auto emit_targets = [&](int g) {
-    emit(BT_TARGET, g, 0, (b->plans[g]->n + BS - 1) / BS, C(g, K_NEAR), (int)nnear[g], last[g].first,
-         last[g].second, C(g, K_TARGET));
+    const BGeom<T>& G = geo[g];
+    if (G.pairs) {   // the remaining pair values, then the per-target sums
+      emit_pairs(g, 3);
+      emit(BT_PAIRSUM, g, 0, (16 * b->plans[g]->n + (int64_t)BS * BG_PAIRSUM - 1) / ((int64_t)BS * BG_PAIRSUM),
+           C(g, K_PAIRS), (int)npair[g], C(g, K_NEAR), (int)nnear[g], C(g, K_TARGET));
+    } else {
+      emit(BT_TARGET, g, 0, (b->plans[g]->n + BS - 1) / BS, C(g, K_NEAR), (int)nnear[g], last[g].first,
+           last[g].second, C(g, K_TARGET));
+    }
   };
   for (int g = 0; g < ng; ++g)
     if (b->plans[g]->D < 4) emit_targets(g);
@@ -4906,6 +4973,12 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       const int64_t cnt = ti ? lp.ntile : (lp.nwork + BG_PROP - 1) / BG_PROP;
       emit(ti ? BT_PROPTI : BT_PROP, g, d, cnt, last[g].first, last[g].second, -1, 0, C(g, K_PROP0 + d - 1));
       last[g] = {C(g, K_PROP0 + d - 1), (int)cnt};
+    }
+    for (int g = 0; g < ng; ++g) {
+      const int d = b->plans[g]->D - j;
+      if (d < 4) continue;
+      made[g][d - 1] = last[g];
+      emit_pairs(g, d);   // level d's pairs behind the step out of it
     }
     for (int g = 0; g < ng; ++g)
       if (b->plans[g]->D - j == 4) emit_targets(g);   // its last step was this one
