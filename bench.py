@@ -335,7 +335,7 @@ def main():
     prop_evals = sum(st["prop_evals"].values())
     cousin = sum(st["cousin_pairs"].values())
     cone_lv = [d for d, m in st["prop_kernel"].items() if m == "cone"]
-    node_lv = [d for d, m in st["prop_kernel"].items() if m == "node"]
+    node_lv = [d for d, m in st["prop_kernel"].items() if m in ("node", "pairs")]   # both time as "prop"
     leaf_cones = st["cones"][D] if D >= 3 else 0
     pts_per_leaf = n / st["boxes"][D]
     # leaf factors: every relevant leaf cone node against every source of its box

@@ -88,7 +88,8 @@ typedef struct {
     int32_t max_rhs;        /* largest nrhs accepted by the apply calls; default 1         */
     int32_t kernel;         /* IFGF_KERNEL_*; default IFGF_KERNEL_COMBINED                  */
     int32_t prop_kernel;    /* upward pass with one right-hand side: IFGF_PROP_AUTO
-                               (default), IFGF_PROP_NODE or IFGF_PROP_CONE (below)          */
+                               (default), IFGF_PROP_NODE, IFGF_PROP_CONE or
+                               IFGF_PROP_PAIRS (below)                                     */
     int32_t target_kernel;  /* cousin-target stage with one right-hand side:
                                IFGF_TARGET_AUTO (default), IFGF_TARGET_WAVE,
                                IFGF_TARGET_ROWS or IFGF_TARGET_PAIRS (below)               */
@@ -112,8 +113,14 @@ typedef struct {
  * 42 KB (FP32) or 60 KB (FP64) per cone id at P = (4,6,6).  AUTO picks CONE
  * for the levels where the boxes per parent cone id fill its tiles and that
  * table stays within 2.5 times the level's coefficient storage; CONE forces
- * it on every level.  Both give the same operator up to rounding. */
-enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2 };
+ * it on every level.  PAIRS: the plan locates every (parent node, child box)
+ * pair of the pass once - child cone slot, local coordinates, kernel ratio -
+ * and sorts the pairs by child slot; an apply evaluates them in that order
+ * and adds each node's pairs in child order (36 bytes per pair, up to 2^28
+ * pairs per level; levels with more use NODE).  AUTO takes PAIRS on the
+ * levels without tiles.  All give the same operator up to rounding; the
+ * transposed apply gathers over a level's pair list where it has one. */
+enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2, IFGF_PROP_PAIRS = 3 };
 
 /* Cousin-target formulation (Algorithm 1, target evaluation; nrhs = 1, FP32
  * or FP64 — other nrhs always use their own kernels).  WAVE: a
@@ -153,8 +160,8 @@ typedef struct {
                                                indexed by the child level d            */
     int64_t device_bytes;                   /* device memory held by the plan           */
     int32_t prop_kernel[IFGF_MAX_LEVELS];   /* upward pass from child level d (index d):
-                                               IFGF_PROP_NODE or IFGF_PROP_CONE with one
-                                               FP32 right-hand side, 0 if no pass       */
+                                               IFGF_PROP_NODE, _CONE or _PAIRS with one
+                                               right-hand side, 0 if no pass            */
     int64_t pair_rows[IFGF_MAX_LEVELS];     /* rows of 16 consecutive pairs of level d's
                                                cousin-target pair list (0: no lists)    */
     int64_t pair_row_cones[IFGF_MAX_LEVELS];/* cone slots met by those rows, summed: the
@@ -328,11 +335,13 @@ void ifgf_plan_destroy(ifgf_plan p);
 /*
  * Autotuner of the plan's one-right-hand-side formulations, by measurement
  * on the plan's own data and this device.  For every level of the upward
- * pass (prop_kernel AUTO only) it times the node formulation and the
+ * pass (prop_kernel AUTO only) it times the node formulation, the
  * cone-major MFMA tiles of 8, 16 and 32 boxes per tile (those the order,
  * the precision - FP64 tiles hold at most 16 boxes - and the node-record
- * memory rule allow), `reps` passes each with HIP events, and keeps the
- * fastest; then (target_kernel AUTO, orders with row-broadcast targets) it
+ * memory rule allow) and the pair list (where the level's pairs stay within
+ * 2^28; built if the plan has none), `reps` passes each with HIP events, and
+ * keeps the fastest (a pair list stays where the node formulation wins, for
+ * the transposed apply); then (target_kernel AUTO, orders with row-broadcast targets) it
  * times `reps` whole applies with row-broadcast, per-wave and (where the plan
  * holds them) pair-list cousin targets and keeps the fastest; the pair lists
  * are released when they lose.  The choices persist in the plan and every
@@ -340,15 +349,16 @@ void ifgf_plan_destroy(ifgf_plan p);
  * ragged batch built over it cannot be tuned (EBUSY: the batch's queue
  * points into the buffers the tuner rebuilds); tune before creating
  * batches.  report [host, may be NULL] receives the measurements.  Runs
- * 1 + about (4 x levels + 2) x (reps + 1) passes or applies, synchronizes
+ * 1 + about (5 x levels + 2) x (reps + 1) passes or applies, synchronizes
  * `stream`.  Errors: EINVAL (reps < 1), EBUSY, ENOMEM, EHIP.
  */
 typedef struct {
     int32_t nlevels;                        /* upward-pass levels tuned (entries below)       */
     int32_t parent_level[IFGF_MAX_LEVELS];  /* level d - 1 of the pass d -> d - 1             */
-    int32_t choice[IFGF_MAX_LEVELS];        /* 0: node formulation; 8, 16, 32: boxes per tile */
-    double ms[IFGF_MAX_LEVELS][4];          /* ms per pass: node, 8-, 16-, 32-box tiles; -1 if
-                                               not a candidate                                */
+    int32_t choice[IFGF_MAX_LEVELS];        /* 0: node formulation; 8, 16, 32: boxes per tile;
+                                               1: pair list                                   */
+    double ms[IFGF_MAX_LEVELS][5];          /* ms per pass: node, 8-, 16-, 32-box tiles, pair
+                                               list; -1 if not a candidate                    */
     int32_t target_choice;                  /* IFGF_TARGET_ROWS, _WAVE or _PAIRS; 0 if not tuned */
     double target_ms[3];                    /* ms per apply with row, wave, pair-list targets;
                                                -1 if not a candidate                          */

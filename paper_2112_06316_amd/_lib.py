@@ -13,7 +13,7 @@ OK, EINVAL, EDUPLICATE, ENOMEM, EHIP, EUNSUPPORTED, EBUSY, EINTERNAL = range(8)
 PREC_FP64, PREC_FP32_INTERP = 0, 1
 C64, C128 = 0, 1
 KERNEL_COMBINED, KERNEL_CONSTANT = 0, 1
-PROP_AUTO, PROP_NODE, PROP_CONE = 0, 1, 2
+PROP_AUTO, PROP_NODE, PROP_CONE, PROP_PAIRS = 0, 1, 2, 3
 TARGET_AUTO, TARGET_WAVE, TARGET_ROWS, TARGET_PAIRS = 0, 1, 2, 3
 STAGES = ["gather", "near", "leaf", "coeffs", "prop", "targets", "adj_targets", "adj_prop", "adj_coeffs",
           "adj_leaf", "adj_near", "adj_out", "prop_cone"]
@@ -75,7 +75,7 @@ class TuneReport(ctypes.Structure):
         ("nlevels", ctypes.c_int32),
         ("parent_level", ctypes.c_int32 * MAX_LEVELS),
         ("choice", ctypes.c_int32 * MAX_LEVELS),
-        ("ms", (ctypes.c_double * 4) * MAX_LEVELS),
+        ("ms", (ctypes.c_double * 5) * MAX_LEVELS),
         ("target_choice", ctypes.c_int32),
         ("target_ms", ctypes.c_double * 3),
     ]

@@ -23,7 +23,7 @@ def library_path() -> str:
 
 _PREC = {"fp64": L.PREC_FP64, "fp32": L.PREC_FP32_INTERP}
 _KERNEL = {"combined": L.KERNEL_COMBINED, "constant": L.KERNEL_CONSTANT}
-_PROP = {"auto": L.PROP_AUTO, "node": L.PROP_NODE, "cone": L.PROP_CONE}
+_PROP = {"auto": L.PROP_AUTO, "node": L.PROP_NODE, "cone": L.PROP_CONE, "pairs": L.PROP_PAIRS}
 _TARGET = {"auto": L.TARGET_AUTO, "wave": L.TARGET_WAVE, "rows": L.TARGET_ROWS, "pairs": L.TARGET_PAIRS}
 
 
@@ -171,17 +171,18 @@ class Plan:
 
     def autotune(self, reps=5) -> dict:
         """Measure and keep the fastest one-RHS formulation of every upward-pass
-        level (node, or cone-major tiles of 8/16/32 boxes) and of the cousin
-        targets (rows or wave).  Returns the measurements."""
+        level (node, cone-major tiles of 8/16/32 boxes, or the pair list) and of
+        the cousin targets (rows, wave or pairs).  Returns the measurements."""
         r = L.TuneReport()
         L.check(self._lib.ifgf_plan_autotune(self._h, int(reps), ctypes.byref(r), _stream_ptr(self.device)),
                 "ifgf_plan_autotune")
-        names = ["node", "tile8", "tile16", "tile32"]
+        names = ["node", "tile8", "tile16", "tile32", "pairs"]
         levels = {}
         for i in range(r.nlevels):
+            ch = r.choice[i]
             levels[r.parent_level[i]] = {
-                "choice": "node" if r.choice[i] == 0 else f"tile{r.choice[i]}",
-                "ms": {names[c]: r.ms[i][c] for c in range(4) if r.ms[i][c] >= 0},
+                "choice": "node" if ch == 0 else ("pairs" if ch == 1 else f"tile{ch}"),
+                "ms": {names[c]: r.ms[i][c] for c in range(5) if r.ms[i][c] >= 0},
             }
         tgt = {L.TARGET_ROWS: "rows", L.TARGET_WAVE: "wave", L.TARGET_PAIRS: "pairs"}.get(r.target_choice)
         ms = {name: r.target_ms[i] for i, name in enumerate(("rows", "wave", "pairs")) if r.target_ms[i] >= 0}
@@ -242,7 +243,7 @@ class Plan:
             "cousin_pairs": {d: s.cousin_pairs[d] for d in range(3, D + 1)},
             "prop_evals": {d: s.prop_evals[d] for d in range(4, D + 1)},
             "near_pairs": s.near_pairs, "device_bytes": s.device_bytes,
-            "prop_kernel": {d: {1: "node", 2: "cone"}.get(s.prop_kernel[d], "none") for d in range(4, D + 1)},
+            "prop_kernel": {d: {1: "node", 2: "cone", 3: "pairs"}.get(s.prop_kernel[d], "none") for d in range(4, D + 1)},
             "pair_rows": {d: s.pair_rows[d] for d in range(3, D + 1)},
             "pair_row_cones": {d: s.pair_row_cones[d] for d in range(3, D + 1)},
         }

@@ -466,21 +466,13 @@ __global__ __launch_bounds__(TPB) void k_leaf(const int4* __restrict__ work, con
 // ---------------------------------------------------------------------------
 constexpr int coeff_cones(int P) { return P <= 160 ? 8 : 1; }
 
-template <typename T, int PS, int PA, bool TR>
-__global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, int nrel, int R,
-                                                const T* __restrict__ Ms, const T* __restrict__ Ma,
-                                                cpx<T>* __restrict__ Fc) {
+// The three passes over nt = (cones) x P node values in v0 (LDS), the
+// matrices in ms, ma; the result to Fc (cones from c0, RHS r of R).
+template <typename T, int PS, int PA>
+__device__ __forceinline__ void coeffs_passes(cpx<T>* v0, cpx<T>* v1, const T* ms, const T* ma, int nt, int c0,
+                                              int R, int r, cpx<T>* __restrict__ Fc) {
   constexpr int P = PS * PA * PA;
-  constexpr int NC = coeff_cones(P);
-  __shared__ cpx<T> v0[NC * P], v1[NC * P];
-  __shared__ T ms[PS * PS], ma[PA * PA];
-  const int c0 = blockIdx.x * NC, r = blockIdx.y, t0 = threadIdx.x;
-  const int nc = min(NC, nrel - c0);
-  const int nt = nc * P;
-  if (t0 < PS * PS) ms[t0] = TR ? Ms[(t0 % PS) * PS + t0 / PS] : Ms[t0];
-  if (t0 < PA * PA) ma[t0] = TR ? Ma[(t0 % PA) * PA + t0 / PA] : Ma[t0];
-  for (int t = t0; t < nt; t += TPB) v0[t] = Fn[((int64_t)c0 * P + t) * R + r];
-  __syncthreads();
+  const int t0 = threadIdx.x;
   for (int t = t0; t < nt; t += TPB) {  // over a (s)
     const int cb = t / P * P, u = t % P;
     const int i = u / (PA * PA), j = (u / PA) % PA, l = u % PA;
@@ -517,6 +509,58 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
     }
     Fc[((int64_t)c0 * P + t) * R + r] = s;
   }
+}
+
+template <typename T, int PS, int PA, bool TR>
+__global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, int nrel, int R,
+                                                const T* __restrict__ Ms, const T* __restrict__ Ma,
+                                                cpx<T>* __restrict__ Fc) {
+  constexpr int P = PS * PA * PA;
+  constexpr int NC = coeff_cones(P);
+  __shared__ cpx<T> v0[NC * P], v1[NC * P];
+  __shared__ T ms[PS * PS], ma[PA * PA];
+  const int c0 = blockIdx.x * NC, r = blockIdx.y, t0 = threadIdx.x;
+  const int nc = min(NC, nrel - c0);
+  const int nt = nc * P;
+  if (t0 < PS * PS) ms[t0] = TR ? Ms[(t0 % PS) * PS + t0 / PS] : Ms[t0];
+  if (t0 < PA * PA) ma[t0] = TR ? Ma[(t0 % PA) * PA + t0 / PA] : Ma[t0];
+  for (int t = t0; t < nt; t += TPB) v0[t] = Fn[((int64_t)c0 * P + t) * R + r];
+  __syncthreads();
+  coeffs_passes<T, PS, PA>(v0, v1, ms, ma, nt, c0, R, r, Fc);
+}
+
+// Upward pass from a pair list, second kernel: node (s, j) of level d is the
+// sum of its pair values (pairs base[s] + j * nch + t, t over the children in
+// order; val in sorted order, pos[] the sorted position), then the level's
+// coefficients as k_coeffs (one RHS).
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_upsum_coeffs(const int* __restrict__ base, const int* __restrict__ pos,
+                                                      const cpx<T>* __restrict__ val, int nrel,
+                                                      const T* __restrict__ Ms, const T* __restrict__ Ma,
+                                                      cpx<T>* __restrict__ Fc) {
+  constexpr int P = PS * PA * PA;
+  constexpr int NC = coeff_cones(P);
+  __shared__ cpx<T> v0[NC * P], v1[NC * P];
+  __shared__ T ms[PS * PS], ma[PA * PA];
+  const int c0 = xcd_block(blockIdx.x, gridDim.x) * NC, t0 = threadIdx.x;
+  const int nc = min(NC, nrel - c0);
+  const int nt = nc * P;
+  if (t0 < PS * PS) ms[t0] = Ms[t0];
+  if (t0 < PA * PA) ma[t0] = Ma[t0];
+  for (int t = t0; t < nt; t += TPB) {
+    const int sc = c0 + t / P, j = t % P;
+    const int b0 = base[sc], nch = (base[sc + 1] - b0) / P;
+    const int* pp = pos + b0 + j * nch;
+    cpx<T> a = {0, 0};
+    for (int c = 0; c < nch; ++c) {
+      const cpx<T> v = val[pp[c]];
+      a.re += v.re;
+      a.im += v.im;
+    }
+    v0[t] = a;
+  }
+  __syncthreads();
+  coeffs_passes<T, PS, PA>(v0, v1, ms, ma, nt, c0, 1, 0, Fc);
 }
 
 // Node values -> coefficients for RG right-hand sides at once (layout
@@ -1474,6 +1518,85 @@ __global__ __launch_bounds__(TPB) void k_pair_place(const uint64_t* __restrict__
   loc[q] = tloc[orig];
   fim[q] = tfim[orig];
   pos[orig] = (int)q;
+}
+
+// ---------------------------------------------------------------------------
+// Upward pass d+1 -> d from a pair list (sparse levels, one RHS; Algorithm 1,
+// parent interpolation nodes).  Where few boxes share a cone id the
+// cone-major tiles run nearly empty, and the node formulation re-locates and
+// re-buckets every node at every apply.  The plan instead locates once every
+// (parent node, child box) pair - child cone slot, local coordinates, factor
+// K(x, y_child) / K(x, y_parent) - and sorts the pairs by slot; an apply then
+// evaluates them with pairs_block (the rows of 16 lanes mostly share one
+// cone) and k_upsum_coeffs adds each node's pairs in child order and turns
+// the node values into coefficients.
+// ---------------------------------------------------------------------------
+// pairs of relevant cone s: P per child of its box
+__global__ __launch_bounds__(TPB) void k_upair_count(int nrel, const int* __restrict__ rel_box,
+                                                     const int* __restrict__ child_lo, int P, int* __restrict__ cnt) {
+  const int64_t sc = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (sc >= nrel) return;
+  const int b = rel_box[sc];
+  cnt[sc] = P * (child_lo[b + 1] - child_lo[b]);
+}
+
+// One thread per parent node (s, j): its pairs with the children of s's box,
+// in child order, at base[s] + j * nch + t (key: slot, then that index).
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_upair_gen(int nrel, const int* __restrict__ rel_box,
+                                                   const int* __restrict__ rel_cone, const int* __restrict__ child_lo,
+                                                   const int* __restrict__ coords, const int* __restrict__ slot_c,
+                                                   const int* __restrict__ base, LevelGeom gp, LevelGeom gc,
+                                                   ChebTab ct, double k, int kind, uint64_t* __restrict__ keys,
+                                                   typename Vec4<T>::type* __restrict__ tloc, T* __restrict__ tfim,
+                                                   int* __restrict__ err) {
+  constexpr int P = PS * PA * PA;
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= (int64_t)nrel * P) return;
+  const int sc = (int)(t / P), node = (int)(t % P);
+  const int ai = node / (PA * PA), bi = (node / PA) % PA, ci = node % PA;
+  const int Pb = rel_box[sc];
+  T x[3], rp;
+  if constexpr (Prec<T>::f32) node_rel32(rel_cone[sc], ai, bi, ci, gp, ct, x, &rp);
+  else node_rel64(rel_cone[sc], ai, bi, ci, gp, ct, x, &rp);
+  const int B0 = child_lo[Pb], nch = child_lo[Pb + 1] - B0;
+  const int64_t o0 = base[sc] + (int64_t)node * nch;
+  for (int c = 0; c < nch; ++c) {
+    const int B = B0 + c;
+    const int oct = (coords[3 * B] & 1) | ((coords[3 * B + 1] & 1) << 1) | ((coords[3 * B + 2] & 1) << 2);
+    typename PropGeomT<T>::P pr;
+    if constexpr (Prec<T>::f32) pr = child_loc32(x, rp, oct, gc);
+    else pr = child_loc64(x, rp, oct, gc);
+    int sl = slot_c[(int64_t)B * gc.ncone + pr.loc.cid];
+    T rr = pr.rp_over_rc, c_, s_;
+    if (kind == IFGF_KERNEL_CONSTANT) {
+      c_ = 1;
+      s_ = 0;
+      rr = 1;
+    } else {
+      sincos_t<T>((T)k * pr.dr, &s_, &c_);
+    }
+    T rre = rr * c_, rim = rr * s_;
+    if (sl < 0) {   // a missing child cone: flagged, the pair adds nothing
+      atomicOr(err, 2);
+      sl = 0;
+      rre = rim = 0;
+    }
+    const int64_t o = o0 + c;
+    keys[o] = ((uint64_t)(uint32_t)sl << 32) | (uint64_t)(uint32_t)o;
+    tloc[o] = {pr.loc.ts, pr.loc.tt, pr.loc.tp, rre};
+    tfim[o] = rim;
+  }
+}
+
+// parent node s * P + j of every sorted pair (for the transposed pass)
+__global__ __launch_bounds__(TPB) void k_upair_node(int nrel, int P, const int* __restrict__ base,
+                                                    const int* __restrict__ pos, int* __restrict__ node) {
+  const int64_t t = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (t >= (int64_t)nrel * P) return;
+  const int sc = (int)(t / P), j = (int)(t % P);
+  const int b0 = base[sc], nch = (base[sc + 1] - b0) / P;
+  for (int c = 0; c < nch; ++c) node[pos[b0 + j * nch + c]] = (int)t;
 }
 
 // Pass one for the TPB pairs q0 .. q0 + TPB - 1 of a level (one per thread).
@@ -3996,6 +4119,20 @@ void prop_level(ifgf_plan_s* p, int d, int R, hipStream_t s) {
       return;
     }
   }
+  if constexpr (rows_ok<T, PS, PA>()) {
+    if (R == 1 && lp.up_use && lp.nup > 0) {   // from the level's pair list
+      StageTimer tm(p, s, IFGF_STAGE_PROP);
+      PLevels<T> L{};
+      L.lv[0] = {lp.nup, lp.up_slot.as<int>(), lp.up_loc.as<typename Vec4<T>::type>(), lp.up_fim.as<T>(),
+                 lp.up_val.as<cpx<T>>(), nullptr, lp.up_pos.as<int>(), lc.Fc.as<cpx<T>>()};
+      k_targets_pairs<T, PS, PA><<<dim3((unsigned)((lp.nup + TPB - 1) / TPB), 1), TPB, 0, s>>>(L, 0);
+      HIPCHK(hipGetLastError());
+      k_upsum_coeffs<T, PS, PA><<<(unsigned)((lp.nrel + coeff_cones(P) - 1) / coeff_cones(P)), TPB, 0, s>>>(
+          lp.up_base.as<int>(), lp.up_pos.as<int>(), lp.up_val.as<cpx<T>>(), lp.nrel, Ms, Ma, lp.Fc.as<cpx<T>>());
+      HIPCHK(hipGetLastError());
+      return;
+    }
+  }
   if constexpr (Prec<T>::f32 && cone_major_order(PS, PA)) {
     if (R == 1 && lp.ntile > 0) {
       StageTimer tm(p, s, IFGF_STAGE_PROP_CONE);
@@ -4309,7 +4446,7 @@ __global__ __launch_bounds__(TPB) void k_pair_tgt(int64_t n, const int* __restri
   for (int t = off[i]; t < off[i + 1]; ++t) tgt[pos[t]] = (int)i;
 }
 
-template <typename T, int PS, int PA>
+template <typename T, int PS, int PA, bool ACC>
 __global__ __launch_bounds__(TPB) void k_adj_pairs(const int* __restrict__ run, int64_t nrun,
                                                    const typename Vec4<T>::type* __restrict__ loc,
                                                    const T* __restrict__ fim, const int* __restrict__ tgt,
@@ -4361,8 +4498,44 @@ __global__ __launch_bounds__(TPB) void k_adj_pairs(const int* __restrict__ run, 
   }
   if (lane < NBC) {
 #pragma unroll
-    for (int a = 0; a < PS; ++a) G[((int64_t)su * P + a * NBC + lane) * R + r] = acc[a];
+    for (int a = 0; a < PS; ++a) {
+      cpx<T>& g = G[((int64_t)su * P + a * NBC + lane) * R + r];
+      if constexpr (ACC) g = {g.re + acc[a].re, g.im + acc[a].im};
+      else g = acc[a];
+    }
   }
+}
+
+// Runs of equal slots of a sorted list of np pairs: run[] gets the starts,
+// then np; returns the number of runs.
+int64_t build_slot_runs(const int* slot, int64_t np, DevBuf& run, hipStream_t s) {
+  DevBuf flag, idx;
+  flag.alloc(sizeof(int) * (np + 1));
+  idx.alloc(sizeof(int) * (np + 1));
+  k_run_flag<<<nblocks(np), TPB, 0, s>>>(slot, np, flag.as<int>());
+  HIPCHK(hipGetLastError());
+  scan_exclusive_i32(flag.as<int>(), idx.as<int>(), np, s);
+  int nr32 = 0;
+  HIPCHK(hipMemcpyAsync(&nr32, idx.as<int>() + np, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  run.alloc(sizeof(int) * ((int64_t)nr32 + 1));
+  k_run_place<<<nblocks(np), TPB, 0, s>>>(flag.as<int>(), idx.as<int>(), np, run.as<int>());
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));   // the temporaries are freed on return
+  return nr32;
+}
+
+// The transposed-pass index of level d's upward pair list (on the first
+// transposed apply): the parent node of every sorted pair, the slot runs.
+void build_up_adj(ifgf_plan_s* p, int d, hipStream_t s) {
+  LevelPlan& lv = p->lev[d];
+  const int P = p->P;
+  lv.up_node.alloc(sizeof(int) * lv.nup);
+  const int64_t nn = (int64_t)lv.nrel * P;
+  k_upair_node<<<nblocks(nn), TPB, 0, s>>>(lv.nrel, P, lv.up_base.as<int>(), lv.up_pos.as<int>(),
+                                           lv.up_node.as<int>());
+  HIPCHK(hipGetLastError());
+  lv.up_nrun = build_slot_runs(lv.up_slot.as<int>(), lv.nup, lv.up_run, s);
 }
 
 // The transposed-apply index of the pair lists: per sorted pair its target,
@@ -4377,20 +4550,7 @@ void build_adj_pairs(ifgf_plan_s* p, hipStream_t s) {
     lv.pr_tgt.alloc(sizeof(int) * np);
     k_pair_tgt<<<nblocks(n), TPB, 0, s>>>(n, lv.pr_off.as<int>(), lv.pr_pos.as<int>(), lv.pr_tgt.as<int>());
     HIPCHK(hipGetLastError());
-    DevBuf flag, idx;
-    flag.alloc(sizeof(int) * (np + 1));
-    idx.alloc(sizeof(int) * (np + 1));
-    k_run_flag<<<nblocks(np), TPB, 0, s>>>(lv.pr_slot.as<int>(), np, flag.as<int>());
-    HIPCHK(hipGetLastError());
-    scan_exclusive_i32(flag.as<int>(), idx.as<int>(), np, s);
-    int nr32 = 0;
-    HIPCHK(hipMemcpyAsync(&nr32, idx.as<int>() + np, sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    lv.nrun = nr32;
-    lv.pr_run.alloc(sizeof(int) * (lv.nrun + 1));
-    k_run_place<<<nblocks(np), TPB, 0, s>>>(flag.as<int>(), idx.as<int>(), np, lv.pr_run.as<int>());
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));   // the temporaries are freed on return
+    lv.nrun = build_slot_runs(lv.pr_slot.as<int>(), np, lv.pr_run, s);
   }
   p->adj_pairs = true;
 }
@@ -4441,7 +4601,7 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
         for (int d = 3; d <= D; ++d) {
           LevelPlan& lv = p->lev[d];
           if (lv.nrun == 0) continue;
-          k_adj_pairs<T, PS, PA><<<dim3((unsigned)((lv.nrun + TPB / 64 - 1) / (TPB / 64)), R), TPB, 0, s>>>(
+          k_adj_pairs<T, PS, PA, false><<<dim3((unsigned)((lv.nrun + TPB / 64 - 1) / (TPB / 64)), R), TPB, 0, s>>>(
               lv.pr_run.as<int>(), lv.nrun, lv.pr_loc.as<typename Vec4<T>::type>(), lv.pr_fim.as<T>(),
               lv.pr_tgt.as<int>(), lv.pr_slot.as<int>(), vs, R, p->adj_g[d].as<cpx<T>>());
           HIPCHK(hipGetLastError());
@@ -4468,6 +4628,17 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
       if (d == D || lv.nrel == 0) continue;
       LevelPlan& lc = p->lev[d + 1];
       int64_t items = (int64_t)lv.nrel * P;
+      if constexpr (rows_ok<T, PS, PA>()) {
+        if (lv.nup > 0) {   // gather form from the upward pair list: one writer per child coefficient
+          if (lv.up_nrun == 0) build_up_adj(p, d, s);
+          StageTimer tm(p, s, IFGF_STAGE_ADJ_PROP);
+          k_adj_pairs<T, PS, PA, true><<<dim3((unsigned)((lv.up_nrun + TPB / 64 - 1) / (TPB / 64)), R), TPB, 0, s>>>(
+              lv.up_run.as<int>(), lv.up_nrun, lv.up_loc.as<typename Vec4<T>::type>(), lv.up_fim.as<T>(),
+              lv.up_node.as<int>(), lv.up_slot.as<int>(), p->adj_g[d].as<cpx<T>>(), R, p->adj_g[d + 1].as<cpx<T>>());
+          HIPCHK(hipGetLastError());
+          continue;
+        }
+      }
       if constexpr (cone_major_order(PS, PA)) {
         if (R == 1 && lv.ti_geo_built) {   // gather form: one writer per child coefficient
           if (!lv.adj_built) build_adj_gather<T, PS, PA>(p, d, s);
@@ -5182,8 +5353,10 @@ void autotune_impl(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t 
       LevelPlan& lp = p->lev[d - 1];
       if (lp.nrel == 0 || lp.nwork == 0) continue;
       const bool cone = cone_major_order(PS, PA) && cone_prop_supported(p) && lp.ti_allowed;
+      const bool pairs = up_pairs_possible(p, d - 1);
       static const int kNw[4] = {0, 1, 2, 4};
       int best = -1;
+      lp.up_use = false;
       for (int c = 0; c < 4; ++c) {
         rep->ms[nl][c] = -1.0;
         if (c > 0 && (!cone || (!f32 && kNw[c] > 2))) continue;
@@ -5191,9 +5364,23 @@ void autotune_impl(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t 
         rep->ms[nl][c] = timed([&]() { prop_level<T, PS, PA>(p, d, 1, s); });
         if (best < 0 || rep->ms[nl][c] < rep->ms[nl][best]) best = c;
       }
-      build_cone_tiles(p, d - 1, kNw[best], s);
+      rep->ms[nl][4] = -1.0;
+      if (pairs) {   // the pair list (built here if the plan has none)
+        build_cone_tiles(p, d - 1, 0, s);
+        if (lp.nup == 0) build_up_pairs(p, d - 1, s);
+        lp.up_use = lp.nup > 0;
+        if (lp.up_use) {
+          rep->ms[nl][4] = timed([&]() { prop_level<T, PS, PA>(p, d, 1, s); });
+          if (rep->ms[nl][4] < rep->ms[nl][best]) best = 4;
+        }
+      }
+      lp.up_use = best == 4;
+      // tiles won: their gathered transposed pass serves the adjoint too; the
+      // node formulation won: the list stays for the adjoint's gather
+      if (best >= 1 && best <= 3 && lp.nup > 0) release_up_pairs(lp);
+      build_cone_tiles(p, d - 1, best == 4 ? 0 : kNw[best], s);
       rep->parent_level[nl] = d - 1;
-      rep->choice[nl] = 8 * kNw[best];
+      rep->choice[nl] = best == 4 ? 1 : 8 * kNw[best];
       ++nl;
     }
     rep->nlevels = nl;
@@ -5404,6 +5591,111 @@ void build_target_pairs(ifgf_plan_s* p, hipStream_t s) {
     build_target_pairs_impl<float>(p, s);
   else
     build_target_pairs_impl<double>(p, s);
+}
+
+void release_up_pairs(LevelPlan& lv) {
+  lv.nup = 0;
+  lv.up_use = false;
+  lv.up_nrun = 0;
+  lv.up_slot.release();
+  lv.up_loc.release();
+  lv.up_fim.release();
+  lv.up_val.release();
+  lv.up_base.release();
+  lv.up_pos.release();
+  lv.up_node.release();
+  lv.up_run.release();
+}
+
+// Upward pairs of the pass d+1 -> d: located, keyed by child slot, sorted.
+template <typename T, int PS, int PA>
+void build_up_pairs_impl(ifgf_plan_s* p, int d, hipStream_t s) {
+  using V4 = typename Vec4<T>::type;
+  constexpr int P = PS * PA * PA;
+  LevelPlan& lp = p->lev[d];
+  const LevelPlan& lc = p->lev[d + 1];
+  release_up_pairs(lp);
+  const int64_t np = lc.prop_evals;   // sum over the relevant cones of P x children
+  if (lp.nrel == 0 || np == 0) return;
+  lp.up_base.alloc(sizeof(int) * ((int64_t)lp.nrel + 1));
+  {
+    DevBuf cnt;
+    cnt.alloc(sizeof(int) * ((int64_t)lp.nrel + 1));
+    k_upair_count<<<nblocks(lp.nrel), TPB, 0, s>>>(lp.nrel, lp.rel_box.as<int>(), lp.child_lo.as<int>(), P,
+                                                   cnt.as<int>());
+    HIPCHK(hipGetLastError());
+    scan_exclusive_i32(cnt.as<int>(), lp.up_base.as<int>(), lp.nrel, s);
+    int tot = 0;
+    HIPCHK(hipMemcpyAsync(&tot, lp.up_base.as<int>() + lp.nrel, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (tot != np) throw Error{IFGF_EUNSUPPORTED, "internal error: upward pair count"};
+  }
+  lp.up_slot.alloc(sizeof(int) * np);
+  lp.up_loc.alloc(sizeof(V4) * np);
+  lp.up_fim.alloc(sizeof(T) * np);
+  lp.up_val.alloc(sizeof(cpx<T>) * np);
+  lp.up_pos.alloc(sizeof(int) * np);
+  DevBuf keys, tloc, tfim;
+  keys.alloc(sizeof(uint64_t) * sort_padded_length(np));
+  tloc.alloc(sizeof(V4) * np);
+  tfim.alloc(sizeof(T) * np);
+  const int64_t nn = (int64_t)lp.nrel * P;
+  k_upair_gen<T, PS, PA><<<nblocks(nn), TPB, 0, s>>>(
+      lp.nrel, lp.rel_box.as<int>(), lp.rel_cone.as<int>(), lp.child_lo.as<int>(), lc.coords.as<int>(),
+      lc.slot.as<int>(), lp.up_base.as<int>(), lp.geom, lc.geom, p->cheb, p->k, p->opt.kernel, keys.as<uint64_t>(),
+      tloc.as<V4>(), tfim.as<T>(), p->err.as<int>());
+  HIPCHK(hipGetLastError());
+  sort_u64(keys.as<uint64_t>(), np, s);
+  k_pair_place<T><<<nblocks(np), TPB, 0, s>>>(keys.as<uint64_t>(), np, tloc.as<V4>(), tfim.as<T>(),
+                                             lp.up_slot.as<int>(), lp.up_loc.as<V4>(), lp.up_fim.as<T>(),
+                                             lp.up_pos.as<int>());
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));   // the temporaries are freed on return
+  lp.nup = np;
+}
+
+template <typename T>
+void dispatch_up_pairs(ifgf_plan_s* p, int d, hipStream_t s) {
+  const int ps = p->opt.p_s, pa = p->opt.p_ang;
+#define X(a, b) \
+  if (ps == a && pa == b) { if constexpr (rows_ok<T, a, b>()) build_up_pairs_impl<T, a, b>(p, d, s); return; }
+  IFGF_ORDERS_ALL(X)
+  if constexpr (!Prec<T>::f32) {
+    IFGF_ORDERS_FP64(X)
+  }
+#undef X
+}
+
+// Whether level d's pass d+1 -> d can run from a pair list: an order with a
+// row stage and at most 2^28 pairs (about 9 GB in FP32).
+bool up_pairs_possible(const ifgf_plan_s* p, int d) {
+  if (d < 3 || d >= p->D || p->lev[d].nrel == 0) return false;
+  const bool f32 = p->opt.precision == IFGF_PREC_FP32_INTERP;
+  if (!(f32 ? pairs_compiled<float>(p->opt.p_s, p->opt.p_ang) : pairs_compiled<double>(p->opt.p_s, p->opt.p_ang)))
+    return false;
+  const int64_t np = p->lev[d + 1].prop_evals;
+  return np > 0 && np <= ((int64_t)1 << 28);
+}
+
+void build_up_pairs(ifgf_plan_s* p, int d, hipStream_t s) {
+  if (p->opt.precision == IFGF_PREC_FP32_INTERP)
+    dispatch_up_pairs<float>(p, d, s);
+  else
+    dispatch_up_pairs<double>(p, d, s);
+}
+
+// At plan creation: PAIRS takes the lists wherever possible; AUTO where the
+// level has no cone-major tiles (the sparse levels); NODE and CONE never.
+void build_plan_up_pairs(ifgf_plan_s* p, hipStream_t s) {
+  const int pk = p->opt.prop_kernel;
+  if (pk != IFGF_PROP_AUTO && pk != IFGF_PROP_PAIRS) return;
+  for (int d = 3; d < p->D; ++d) {
+    LevelPlan& lv = p->lev[d];
+    if (!up_pairs_possible(p, d)) continue;
+    if (pk == IFGF_PROP_AUTO && lv.ntile > 0) continue;
+    build_up_pairs(p, d, s);
+    lv.up_use = lv.nup > 0;
+  }
 }
 
 template <typename T>

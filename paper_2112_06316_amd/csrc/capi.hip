@@ -143,7 +143,7 @@ static void create_plan(ifgf_plan_s*& p, int64_t n, int64_t n_src, const double*
   if (o.depth == 0 && !(o.leaf_h_lambda > 0.0)) throw Error{IFGF_EINVAL, "leaf_h_lambda must be > 0"};
   if (o.precision != IFGF_PREC_FP64 && o.precision != IFGF_PREC_FP32_INTERP) throw Error{IFGF_EINVAL, "bad precision"};
   if (o.max_rhs < 1) throw Error{IFGF_EINVAL, "max_rhs must be >= 1"};
-  if (o.prop_kernel < IFGF_PROP_AUTO || o.prop_kernel > IFGF_PROP_CONE) throw Error{IFGF_EINVAL, "bad prop_kernel"};
+  if (o.prop_kernel < IFGF_PROP_AUTO || o.prop_kernel > IFGF_PROP_PAIRS) throw Error{IFGF_EINVAL, "bad prop_kernel"};
   if (o.target_kernel < IFGF_TARGET_AUTO || o.target_kernel > IFGF_TARGET_PAIRS)
     throw Error{IFGF_EINVAL, "bad target_kernel"};
   if (o.kernel != IFGF_KERNEL_COMBINED && o.kernel != IFGF_KERNEL_CONSTANT) throw Error{IFGF_EINVAL, "bad kernel"};
@@ -328,9 +328,12 @@ ifgf_status ifgf_plan_get_stats(ifgf_plan p, ifgf_plan_stats* st) {
       add(l.ti_qlist); add(l.ti_rec); add(l.adj_tiles); add(l.adj_slots); add(l.adj_gref); add(l.adj_gref_off);
       add(l.pr_slot); add(l.pr_loc); add(l.pr_fim); add(l.pr_val); add(l.pr_off); add(l.pr_pos);
       add(l.pr_tgt); add(l.pr_run);
+      add(l.up_slot); add(l.up_loc); add(l.up_fim); add(l.up_val); add(l.up_base); add(l.up_pos);
+      add(l.up_node); add(l.up_run);
       add(p->adj_g[d]);
       if (d >= 4 && p->lev[d - 1].nrel > 0)
-        st->prop_kernel[d] = p->lev[d - 1].ntile > 0 ? IFGF_PROP_CONE : IFGF_PROP_NODE;
+        st->prop_kernel[d] = p->lev[d - 1].up_use ? IFGF_PROP_PAIRS
+                             : p->lev[d - 1].ntile > 0 ? IFGF_PROP_CONE : IFGF_PROP_NODE;
     }
     st->near_pairs = p->near_pairs;
     st->device_bytes = bytes;

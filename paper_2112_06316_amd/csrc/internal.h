@@ -111,6 +111,26 @@ struct LevelPlan {
   DevBuf pr_run;              // int [nrun + 1]
   int64_t nrun = 0;
   int64_t pair_rows = 0, pair_row_cones = 0;   // rows of 16 pairs, and the cone slots they meet
+  // Upward-pair list of the pass d+1 -> d (sparse levels, one RHS): every
+  // (node of a relevant cone of this level, child box) pair sorted by the
+  // child's cone slot; per pair its slot, local coordinates in the child cone
+  // and factor K(x, y_child) / K(x, y_parent) (plan precision), its value
+  // after the pass's first kernel.  The pairs of node j of relevant cone s
+  // are pairs up_base[s] + j * nch + t (t over the nch children of s's box,
+  // in child order) before sorting; up_pos maps them to sorted positions.
+  int64_t nup = 0;
+  bool up_use = false;        // the pass d+1 -> d runs from this list
+  DevBuf up_slot;             // int [nup]
+  DevBuf up_loc;              // T4 [nup]: (ts, tt, tp, factor re)
+  DevBuf up_fim;              // T [nup]: factor im
+  DevBuf up_val;              // complex T [nup]
+  DevBuf up_base;             // int [nrel + 1]
+  DevBuf up_pos;              // int [nup]
+  // for the transposed apply (built on its first call): the parent node
+  // (s * P + j) of each sorted pair, and the runs of pairs of one slot
+  DevBuf up_node;             // int [nup]
+  DevBuf up_run;              // int [up_nrun + 1]
+  int64_t up_nrun = 0;
   // statistics
   int64_t cousin_pairs = 0;
   int64_t prop_evals = 0;     // child interpolations into level d-1 nodes
@@ -208,6 +228,11 @@ void run_autotune(ifgf_plan_s* p, int reps, ifgf_tune_report* rep, hipStream_t s
 // and size allow; sets p->pairs.
 void build_target_pairs(ifgf_plan_s* p, hipStream_t s);
 void release_target_pairs(ifgf_plan_s* p);
+// upward pair lists of the pass d+1 -> d (sparse levels)
+bool up_pairs_possible(const ifgf_plan_s* p, int d);
+void build_up_pairs(ifgf_plan_s* p, int d, hipStream_t s);
+void release_up_pairs(LevelPlan& lv);
+void build_plan_up_pairs(ifgf_plan_s* p, hipStream_t s);
 
 // solve.hip: restarted GMRES on (alpha I + A) sigma = f (complex128 device vectors).
 void run_gmres(ifgf_plan_s* p, const void* f, void* sigma, const ifgf_gmres_options& o, int32_t* iters,

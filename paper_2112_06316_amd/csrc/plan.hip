@@ -896,7 +896,8 @@ void build_plan(ifgf_plan_s* p, const double* pts, const double* nrm, const doub
   p->err.alloc(sizeof(int) * 4);
   HIPCHK(hipMemsetAsync(p->err.p, 0, sizeof(int) * 4, s));
   HIPCHK(hipStreamSynchronize(s));
-  build_target_pairs(p, s);   // after the error flags exist: the pair generator reports missing cones there
+  build_target_pairs(p, s);   // after the error flags exist: the pair generators report missing cones there
+  build_plan_up_pairs(p, s);
 }
 
 }  // namespace ifgf

@@ -30,6 +30,7 @@ CASES = [
     ("sphere4", lambda: inputs.cubed_sphere(32), 8 * np.pi, 4, dict()),
     ("sphere4_cone", lambda: inputs.cubed_sphere(32), 8 * np.pi, 4, dict(prop_kernel="cone")),
     ("sphere8_cone", lambda: inputs.cubed_sphere(48), 16 * np.pi, 5, dict(prop_kernel="cone")),
+    ("sphere8_pairs", lambda: inputs.cubed_sphere(48), 16 * np.pi, 5, dict(prop_kernel="pairs")),
     ("sphere4_paper", lambda: inputs.cubed_sphere(32), 8 * np.pi, 4, dict(p_s=3, p_ang=5, ns0=1, nc0=2)),
     ("ellipsoid", lambda: inputs.ellipsoid(20, (0.5, 0.375, 0.25)), 12 * np.pi, 5, dict()),
 ]
@@ -155,13 +156,14 @@ def test_gathered_transposed_pass_equals_scattered(precision, tol):
     if precision == "fp32":
         v = v.to(torch.complex64)
     out = {}
-    for prop in ("cone", "node"):
+    for prop in ("cone", "node", "pairs"):
         plan = Plan(p, nr, w, k, k, depth=wl["depth"], precision=precision, prop_kernel=prop)
         out[prop] = plan.apply_adjoint(v, conjugate=True).to(torch.complex128).cpu().numpy()
         assert plan.check() == 0
-    e = np.linalg.norm(out["cone"] - out["node"]) / np.linalg.norm(out["node"])
-    log(f"case gathered vs scattered transposed pass {precision}: rel diff {e:.2e}")
-    assert e <= tol
+    for g in ("cone", "pairs"):
+        e = np.linalg.norm(out[g] - out["node"]) / np.linalg.norm(out["node"])
+        log(f"case gathered ({g}) vs scattered transposed pass {precision}: rel diff {e:.2e}")
+        assert e <= tol
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])

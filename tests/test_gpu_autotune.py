@@ -39,7 +39,7 @@ def test_autotuned_plan_computes_the_same_operator(precision, tol):
     for d, e in rep["prop"].items():
         assert e["choice"] in e["ms"] and all(v > 0 for v in e["ms"].values())
         assert "node" in e["ms"]
-        assert plan.stats()["prop_kernel"][d + 1] == ("node" if e["choice"] == "node" else "cone")
+        assert plan.stats()["prop_kernel"][d + 1] == {"node": "node", "pairs": "pairs"}.get(e["choice"], "cone")
     assert rep["targets"] in ("rows", "wave", "pairs")
     assert rep["targets"] in rep["targets_ms"] and set(rep["targets_ms"]) == {"rows", "wave", "pairs"}
     u1 = plan.apply(s).cpu().numpy()

@@ -56,7 +56,7 @@ def test_stage_parity_high_order():
     log("case stages P=(8,8) fp64")
     plan = Plan(p, nr, w, k, k, depth=4, precision="fp64", **HI)
     st = plan.stats()
-    assert st["prop_kernel"][4] == "node"
+    assert st["prop_kernel"][4] in ("node", "pairs")
     for d in (3, 4):
         assert (st["ns"][d], st["nc"][d]) == ref.counts[d]
         box, cone = plan.export_cones(d)

@@ -112,7 +112,7 @@ def _stage_reference(ps, pa, ns0, nc0):
 # tiles.  P = 144 covers the quad-load A operand of the cone-major kernel,
 # the plan-time node records and the row-broadcast targets at that order.
 @pytest.mark.parametrize("setting", [(3, 5, 1, 2), (4, 6, 2, 4), (4, 6, 1, 2)])
-@pytest.mark.parametrize("prop", ["cone", "node"])
+@pytest.mark.parametrize("prop", ["cone", "node", "pairs"])
 @pytest.mark.parametrize("target", ["rows", "wave", "pairs"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_stage_parity_with_reference(setting, prop, target, precision):
@@ -299,6 +299,50 @@ def test_cone_major_upward_pass_equals_node_formulation(ps, pa, ns0, nc0, D, pre
         assert e < tol, d
     assert np.linalg.norm(uc - un) / np.linalg.norm(un) < tol / 2
     assert cone.check() == 0 and node.check() == 0
+
+
+@pytest.mark.parametrize("precision,tol", [("fp32", 2e-6), ("fp64", 1e-13)])
+@pytest.mark.parametrize("ps,pa,ns0,nc0,D", [(4, 6, 2, 4, 5), (3, 5, 1, 2, 5), (4, 6, 2, 4, 6)])
+def test_pair_list_upward_pass_equals_node_formulation(ps, pa, ns0, nc0, D, precision, tol):
+    # The pair-list upward pass evaluates the same (parent node, child) pairs
+    # as the node formulation, located once at plan time, and adds each node's
+    # pairs in the same child order: the coefficients agree to rounding at
+    # every level.
+    log(f"case upward pairs {precision} P=({ps},{pa}) D={D}")
+    p, nr, w = inputs.cubed_sphere(48)
+    k = 16 * np.pi
+    s = torch.from_numpy(inputs.random_density(len(p), seed=63)).to(DEV)
+    if precision == "fp32":
+        s = s.to(torch.complex64)
+    opts = dict(depth=D, p_s=ps, p_ang=pa, ns0=ns0, nc0=nc0, precision=precision)
+    node = Plan(p, nr, w, k, k, prop_kernel="node", **opts)
+    pairs = Plan(p, nr, w, k, k, prop_kernel="pairs", **opts)
+    kinds = pairs.stats()["prop_kernel"]
+    assert set(kinds.values()) == {"pairs"}, kinds
+    un = node.apply(s).cpu().numpy()
+    up = pairs.apply(s).cpu().numpy()
+    for d in range(3, D):
+        Cn = node.export_field(d, 1)[:, 0, :]
+        Cp = pairs.export_field(d, 1)[:, 0, :]
+        e = np.abs(Cp - Cn).max() / np.abs(Cn).max()
+        log(f"  level {d}: {Cn.shape[0]} cones, max rel diff {e:.2e}")
+        assert e < tol, d
+    assert np.linalg.norm(up - un) / np.linalg.norm(un) < tol
+    assert pairs.check() == 0 and node.check() == 0
+
+
+def test_auto_takes_pair_lists_on_levels_without_tiles():
+    # AUTO: cone-major tiles where the boxes per cone id fill them, the pair
+    # list on the other levels; NODE keeps every level on the node kernel.
+    wl = inputs.workload("sphere16")
+    p, nr, w = inputs.build_surface(wl)
+    auto = Plan(p, nr, w, wl["k"], wl["k"], depth=wl["depth"])
+    kinds = auto.stats()["prop_kernel"]
+    log(f"case auto formulations: {kinds}")
+    assert set(kinds.values()) <= {"cone", "pairs"} and "pairs" in kinds.values()
+    node = Plan(p, nr, w, wl["k"], wl["k"], depth=wl["depth"], prop_kernel="node")
+    assert set(node.stats()["prop_kernel"].values()) == {"node"}
+    assert node.stats()["device_bytes"] < auto.stats()["device_bytes"]
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp64", 1e-11)])
