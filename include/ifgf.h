@@ -480,8 +480,8 @@ ifgf_status ifgf_batch_apply(ifgf_batch b, const void *const *sigma, void *const
  * that forbid hipMalloc).  Same arguments, results, ownership and errors as
  * ifgf_batch_apply; the call allocates nothing (no hipMalloc, hipFree or
  * allocating library routine, on the device or through torch).  The launch's
- * completion counters (queue head and 16 per geometry) come from one fixed
- * device array of IFGF_BATCH_NOALLOC_COUNTERS ints (4,100 bytes) per GPU,
+ * completion counters (queue head and 32 per geometry) come from one fixed
+ * device array of IFGF_BATCH_NOALLOC_COUNTERS ints (8,196 bytes) per GPU,
  * held by the library until the process ends, instead of the batch's own
  * buffer; a fill kernel clears them at the start of every call.  The batch
  * must have been created with the current device current (EINVAL otherwise).
@@ -492,7 +492,7 @@ ifgf_status ifgf_batch_apply(ifgf_batch b, const void *const *sigma, void *const
  * Errors: EINVAL (also a batch needing more counters than the array holds),
  * EBUSY, EHIP.
  */
-#define IFGF_BATCH_NOALLOC_COUNTERS (1 + 16 * IFGF_BATCH_MAX)
+#define IFGF_BATCH_NOALLOC_COUNTERS (1 + 32 * IFGF_BATCH_MAX)
 ifgf_status ifgf_batch_apply_noalloc(ifgf_batch b, const void *const *sigma, void *const *u, int32_t dtype,
                                      void *stream);
 ifgf_status ifgf_batch_check(ifgf_batch b, int32_t *flags);

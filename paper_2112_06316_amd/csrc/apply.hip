@@ -533,20 +533,26 @@ __global__ __launch_bounds__(TPB) void k_coeffs(const cpx<T>* __restrict__ Fn, i
 // sum of its pair values (pairs base[s] + j * nch + t, t over the children in
 // order; val in sorted order, pos[] the sorted position), then the level's
 // coefficients as k_coeffs (one RHS).
+template <typename T, int PS, int PA> struct UpsumSmem {
+  static constexpr int P = PS * PA * PA, NC = coeff_cones(P);
+  cpx<T> v0[NC * P], v1[NC * P];
+  T ms[PS * PS], ma[PA * PA];
+};
+
+// The cones c0 .. c0 + NC - 1 (NC = coeff_cones(P)) of one block of TPB threads.
 template <typename T, int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_upsum_coeffs(const int* __restrict__ base, const int* __restrict__ pos,
-                                                      const cpx<T>* __restrict__ val, int nrel,
-                                                      const T* __restrict__ Ms, const T* __restrict__ Ma,
-                                                      cpx<T>* __restrict__ Fc) {
+__device__ __forceinline__ void upsum_chunk(UpsumSmem<T, PS, PA>& sm, int c0, const int* __restrict__ base,
+                                            const int* __restrict__ pos, const cpx<T>* __restrict__ val, int nrel,
+                                            const T* __restrict__ Ms, const T* __restrict__ Ma,
+                                            cpx<T>* __restrict__ Fc) {
   constexpr int P = PS * PA * PA;
   constexpr int NC = coeff_cones(P);
-  __shared__ cpx<T> v0[NC * P], v1[NC * P];
-  __shared__ T ms[PS * PS], ma[PA * PA];
-  const int c0 = xcd_block(blockIdx.x, gridDim.x) * NC, t0 = threadIdx.x;
+  cpx<T>* v0 = sm.v0;
+  const int t0 = threadIdx.x;
   const int nc = min(NC, nrel - c0);
   const int nt = nc * P;
-  if (t0 < PS * PS) ms[t0] = Ms[t0];
-  if (t0 < PA * PA) ma[t0] = Ma[t0];
+  if (t0 < PS * PS) sm.ms[t0] = Ms[t0];
+  if (t0 < PA * PA) sm.ma[t0] = Ma[t0];
   for (int t = t0; t < nt; t += TPB) {
     const int sc = c0 + t / P, j = t % P;
     const int b0 = base[sc], nch = (base[sc + 1] - b0) / P;
@@ -560,7 +566,17 @@ __global__ __launch_bounds__(TPB) void k_upsum_coeffs(const int* __restrict__ ba
     v0[t] = a;
   }
   __syncthreads();
-  coeffs_passes<T, PS, PA>(v0, v1, ms, ma, nt, c0, 1, 0, Fc);
+  coeffs_passes<T, PS, PA>(v0, sm.v1, sm.ms, sm.ma, nt, c0, 1, 0, Fc);
+}
+
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_upsum_coeffs(const int* __restrict__ base, const int* __restrict__ pos,
+                                                      const cpx<T>* __restrict__ val, int nrel,
+                                                      const T* __restrict__ Ms, const T* __restrict__ Ma,
+                                                      cpx<T>* __restrict__ Fc) {
+  __shared__ UpsumSmem<T, PS, PA> sm;
+  upsum_chunk<T, PS, PA>(sm, xcd_block(blockIdx.x, gridDim.x) * coeff_cones(PS * PA * PA), base, pos, val, nrel, Ms,
+                         Ma, Fc);
 }
 
 // Node values -> coefficients for RG right-hand sides at once (layout
@@ -4538,6 +4554,100 @@ void build_up_adj(ifgf_plan_s* p, int d, hipStream_t s) {
   lv.up_nrun = build_slot_runs(lv.up_slot.as<int>(), lv.nup, lv.up_run, s);
 }
 
+// k_adj_pairs on MFMA (FP32, P_s P_ang <= 32, 2 P_ang <= 16).  For one slot
+// run the coefficient adjoints are a matrix product over the run's pairs p:
+// G[(a, b), (c, re/im)] = sum_p Ts_a(p) Tt_b(p) * Tp_c(p) w_(re/im)(p), with
+// w the pair's factor times its target value.  A wave takes a run, stages 64
+// pairs at a time in LDS (lane = pair: its Chebyshev values and w, as
+// k_adj_pairs, so that as many waves stay resident) and accumulates 4 pairs
+// per v_mfma_f32_16x16x4_f32 into MT row tiles, each lane forming its A
+// entry Ts_a Tt_b and B entry Tp_c w from the staged values; one writer per
+// coefficient and a fixed order, as k_adj_pairs.
+template <int PS, int PA> constexpr bool adj_pairs_mfma_ok() { return PS * PA <= 32 && 2 * PA <= 16; }
+
+template <int PS, int PA, bool ACC>
+__global__ __launch_bounds__(TPB) void k_adj_pairs_mfma(const int* __restrict__ run, int64_t nrun,
+                                                        const float4* __restrict__ loc, const float* __restrict__ fim,
+                                                        const int* __restrict__ tgt, const int* __restrict__ slot,
+                                                        const cpx<float>* __restrict__ vs, int R,
+                                                        cpx<float>* __restrict__ G) {
+  static_assert(adj_pairs_mfma_ok<PS, PA>(), "rows (a, b) in two tiles, columns (c, re/im) in one");
+  constexpr int P = PS * PA * PA;
+  constexpr int MR = PS * PA;               // A rows used
+  constexpr int MT = (MR + 15) / 16;        // row tiles
+  constexpr int NC = 2 * PA;                // B columns used
+  constexpr int NW = TPB / 64;
+  constexpr int NF = PS + 2 * PA + 2;       // Ts, Tt, Tp, w (re, im)
+  __shared__ float buf[NW][64][NF + 1];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, r = blockIdx.y;
+  const int64_t ri = (int64_t)blockIdx.x * NW + wv;
+  if (ri >= nrun) return;   // wave-uniform; the kernel has no block barrier
+  const int q0 = run[ri], q1 = run[ri + 1];
+  const int su = slot[q0];
+  const int li = lane & 15, lk = lane >> 4;
+  // this lane's A entries (row 16 m + li: Ts_a Tt_b) and B entry (column li: Tp_c w_re/im)
+  int fa[MT], fb[MT];
+  bool va[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int i = 16 * m + li;
+    va[m] = i < MR;
+    fa[m] = va[m] ? i / PA : 0;
+    fb[m] = va[m] ? PS + i % PA : 0;
+  }
+  const bool vb = li < NC;
+  const int fc = vb ? PS + PA + (li >> 1) : 0, fw = vb ? PS + 2 * PA + (li & 1) : 0;
+  floatx4 d[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) d[m] = {0.f, 0.f, 0.f, 0.f};
+  for (int qb = q0; qb < q1; qb += 64) {
+    {   // stage pair qb + lane; past the run's end: zero weight
+      const int q = qb + lane;
+      float* f = buf[wv][lane];
+      float4 lc = make_float4(0.f, 0.f, 0.f, 0.f);
+      float wre = 0.f, wim = 0.f;
+      if (q < q1) {
+        lc = loc[q];
+        const float fi = fim[q];
+        const cpx<float> v = vs[(int64_t)tgt[q] * R + r];
+        wre = lc.w * v.re - fi * v.im;
+        wim = lc.w * v.im + fi * v.re;
+      }
+      cheb_T<float, PS>(lc.x, f);
+      cheb_T<float, PA>(lc.y, f + PS);
+      cheb_T<float, PA>(lc.z, f + PS + PA);
+      f[NF - 2] = wre;
+      f[NF - 1] = wim;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int cnt = min(64, q1 - qb);
+    for (int k = 0; k < cnt; k += 4) {   // pairs past the run's end carry zero weight
+      const float* fk = buf[wv][k + lk];
+      const float bv = vb ? fk[fc] * fk[fw] : 0.f;
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+        d[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(va[m] ? fk[fa[m]] * fk[fb[m]] : 0.f, bv, d[m], 0, 0, 0);
+    }
+    __builtin_amdgcn_wave_barrier();   // the chunk is read before the next one is written
+  }
+  // lane 16 lk + j holds rows 4 lk .. 4 lk + 3 of column j of every row tile
+  if (vb) {
+    const int c = li >> 1, ri2 = li & 1;
+    float* Gf = reinterpret_cast<float*>(G);
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * m + 4 * lk + e;
+        if (i >= MR) continue;
+        const int a = i / PA, b = i % PA;
+        float& g = Gf[2 * (((int64_t)su * P + (a * PA + b) * PA + c) * R + r) + ri2];
+        g = ACC ? g + d[m][e] : d[m][e];
+      }
+    }
+  }
+}
+
 // The transposed-apply index of the pair lists: per sorted pair its target,
 // per level the runs of equal slots.
 void build_adj_pairs(ifgf_plan_s* p, hipStream_t s) {
@@ -4601,9 +4711,15 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
         for (int d = 3; d <= D; ++d) {
           LevelPlan& lv = p->lev[d];
           if (lv.nrun == 0) continue;
-          k_adj_pairs<T, PS, PA, false><<<dim3((unsigned)((lv.nrun + TPB / 64 - 1) / (TPB / 64)), R), TPB, 0, s>>>(
-              lv.pr_run.as<int>(), lv.nrun, lv.pr_loc.as<typename Vec4<T>::type>(), lv.pr_fim.as<T>(),
-              lv.pr_tgt.as<int>(), lv.pr_slot.as<int>(), vs, R, p->adj_g[d].as<cpx<T>>());
+          const dim3 grid((unsigned)((lv.nrun + TPB / 64 - 1) / (TPB / 64)), R);
+          if constexpr (Prec<T>::f32 && adj_pairs_mfma_ok<PS, PA>())
+            k_adj_pairs_mfma<PS, PA, false><<<grid, TPB, 0, s>>>(
+                lv.pr_run.as<int>(), lv.nrun, lv.pr_loc.as<float4>(), lv.pr_fim.as<float>(), lv.pr_tgt.as<int>(),
+                lv.pr_slot.as<int>(), (const cpx<float>*)vs, R, p->adj_g[d].as<cpx<float>>());
+          else
+            k_adj_pairs<T, PS, PA, false><<<grid, TPB, 0, s>>>(
+                lv.pr_run.as<int>(), lv.nrun, lv.pr_loc.as<typename Vec4<T>::type>(), lv.pr_fim.as<T>(),
+                lv.pr_tgt.as<int>(), lv.pr_slot.as<int>(), vs, R, p->adj_g[d].as<cpx<T>>());
           HIPCHK(hipGetLastError());
         }
         gathered = true;
@@ -4632,9 +4748,16 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
         if (lv.nup > 0) {   // gather form from the upward pair list: one writer per child coefficient
           if (lv.up_nrun == 0) build_up_adj(p, d, s);
           StageTimer tm(p, s, IFGF_STAGE_ADJ_PROP);
-          k_adj_pairs<T, PS, PA, true><<<dim3((unsigned)((lv.up_nrun + TPB / 64 - 1) / (TPB / 64)), R), TPB, 0, s>>>(
-              lv.up_run.as<int>(), lv.up_nrun, lv.up_loc.as<typename Vec4<T>::type>(), lv.up_fim.as<T>(),
-              lv.up_node.as<int>(), lv.up_slot.as<int>(), p->adj_g[d].as<cpx<T>>(), R, p->adj_g[d + 1].as<cpx<T>>());
+          const dim3 grid((unsigned)((lv.up_nrun + TPB / 64 - 1) / (TPB / 64)), R);
+          if constexpr (Prec<T>::f32 && adj_pairs_mfma_ok<PS, PA>())
+            k_adj_pairs_mfma<PS, PA, true><<<grid, TPB, 0, s>>>(
+                lv.up_run.as<int>(), lv.up_nrun, lv.up_loc.as<float4>(), lv.up_fim.as<float>(), lv.up_node.as<int>(),
+                lv.up_slot.as<int>(), p->adj_g[d].as<cpx<float>>(), R, p->adj_g[d + 1].as<cpx<float>>());
+          else
+            k_adj_pairs<T, PS, PA, true><<<grid, TPB, 0, s>>>(
+                lv.up_run.as<int>(), lv.up_nrun, lv.up_loc.as<typename Vec4<T>::type>(), lv.up_fim.as<T>(),
+                lv.up_node.as<int>(), lv.up_slot.as<int>(), p->adj_g[d].as<cpx<T>>(), R,
+                p->adj_g[d + 1].as<cpx<T>>());
           HIPCHK(hipGetLastError());
           continue;
         }
@@ -4718,7 +4841,8 @@ void adjoint_impl(ifgf_plan_s* p, const void* v, void* out, int R, int dtype, in
 // counter increment; after a wait every wave issues an agent-scope acquire
 // fence (stale cache lines dropped) before it reads.
 // ---------------------------------------------------------------------------
-enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_PROP = 4, BT_TARGET = 5, BT_PROPTI = 6, BT_PAIRS = 7, BT_PAIRSUM = 8 };
+enum { BT_GATHER = 0, BT_LEAF = 1, BT_NEAR = 2, BT_PROP = 4, BT_TARGET = 5, BT_PROPTI = 6, BT_PAIRS = 7, BT_PAIRSUM = 8,
+       BT_UPAIRS = 9, BT_UPSUM = 10 };
 // Threads per work-group of the batch launch: every stage body runs at this
 // size (the cone-major tiles need 4 waves of 8 boxes).
 constexpr int BBS = 256;
@@ -4728,8 +4852,9 @@ constexpr int BBS = 256;
 // cones' node values into coefficients); target items hold BBS points; a
 // cone-major item is one tile.
 constexpr int BG_GATHER = 4, BG_PROP = 8, BG_NEAR = 16, BG_LEAF = 8;
-// pair items: BG_PAIRS chunks of BS sorted pairs; pair-sum items: BG_PAIRSUM x BS / 16 targets
-constexpr int BG_PAIRS = 16, BG_PAIRSUM = 8;
+// pair items: BG_PAIRS chunks of BS sorted pairs; pair-sum items: BG_PAIRSUM x BS / 16 targets;
+// upward pair items: BG_UPAIRS chunks of BS pairs; upward sum items: BG_UPSUM chunks of coeff_cones(P) cones
+constexpr int BG_PAIRS = 32, BG_PAIRSUM = 8, BG_UPAIRS = 64, BG_UPSUM = 16;
 
 template <typename T> struct BLevel {
   int nb, nrel, nwork, n_near, n_leaf;
@@ -4774,6 +4899,8 @@ template <typename T> struct BGeom {
   ChebTab ct;
   TLevels<T> tl;
   PLevels<T> pl;
+  PLevels<T> up;                                  // upward pair lists of the passes into level l (index l)
+  const int IFGF_GAS* up_base[IFGF_MAX_LEVELS];
   BLevel<T> lv[IFGF_MAX_LEVELS];
 };
 
@@ -4807,8 +4934,9 @@ template <typename T, int PS, int PA> struct BLeafSmem {
 template <typename T, int PS, int PA> struct BatchSmem {
   static constexpr size_t a = sizeof(PropSmem<T, PS, PA, BBS>), b = sizeof(NearSmem<T, 1, BBS>),
                           c = sizeof(BLeafSmem<T, PS, PA>), t = Prec<T>::f32 ? sizeof(TiSmem<PS, PA, 4>) : 0;
-  static constexpr size_t ab = a > b ? a : b, ct = c > t ? c : t;
-  static constexpr size_t bytes = ab > ct ? ab : ct;
+  static constexpr size_t u = sizeof(UpsumSmem<T, PS, PA>);
+  static constexpr size_t ab = a > b ? a : b, ct = c > t ? c : t, abu = ab > u ? ab : u;
+  static constexpr size_t bytes = abu > ct ? abu : ct;
 };
 
 // One launch of `total` work-groups; each takes the next ticket of the queue
@@ -4917,6 +5045,26 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : 1))) void k_batch(const 
       }
       break;
     }
+    case BT_UPAIRS: {   // BG_UPAIRS chunks of BS sorted upward pairs of the pass S.level -> S.level - 1
+      const PLevel<T>& ul = G.up.lv[S.level - 1];
+      const int64_t n = (ul.np + BS - 1) / BS;
+      const int64_t c0 = (int64_t)local * BG_UPAIRS, c1 = min(c0 + BG_UPAIRS, n);
+      for (int64_t c = c0; c < c1; ++c) pairs_block<T, PS, PA>(ul, c * BS);
+      break;
+    }
+    case BT_UPSUM: {   // BG_UPSUM chunks of coeff_cones(P) cones of level S.level - 1: node sums, coefficients
+      constexpr int NC = coeff_cones(PS * PA * PA);
+      const int l = S.level - 1;
+      const BLevel<T>& lp = G.lv[l];
+      for (int u = 0; u < BG_UPSUM; ++u) {
+        const int c0 = (local * BG_UPSUM + u) * NC;
+        if (c0 >= lp.nrel) break;   // block-uniform
+        if (u > 0) __syncthreads();   // LDS reuse
+        upsum_chunk<T, PS, PA>(*reinterpret_cast<UpsumSmem<T, PS, PA>*>(smem), c0, gen(G.up_base[l]),
+                               G.up.lv[l].pos, G.up.lv[l].val, lp.nrel, gen(G.Ms), gen(G.Ma), gen(lp.Fc));
+      }
+      break;
+    }
     case BT_PAIRS: {   // BG_PAIRS chunks of BS sorted pairs of level S.level: their values
       const int d = S.level;
       const int64_t n = G.pchunk[d + 1] - G.pchunk[d];
@@ -5021,6 +5169,15 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       pc += (l.npair + BBS - 1) / BBS;
     }
     if (G.pairs) G.pchunk[p->D + 1] = pc;
+    if constexpr (rows_ok<T, PS, PA>()) {
+      for (int l = 3; l < p->D; ++l) {   // upward pair lists the plan's applies use
+        const LevelPlan& lp = p->lev[l];
+        if (!lp.up_use || lp.nup == 0) continue;
+        G.up.lv[l] = {lp.nup, lp.up_slot.as<int>(), lp.up_loc.as<typename Vec4<T>::type>(), lp.up_fim.as<T>(),
+                      lp.up_val.as<cpx<T>>(), nullptr, lp.up_pos.as<int>(), p->lev[l + 1].Fc.as<cpx<T>>()};
+        G.up_base[l] = gas(lp.up_base.as<const int>());
+      }
+    }
     for (int d = 1; d <= p->D; ++d) {
       const LevelPlan& l = p->lev[d];
       BLevel<T>& L = G.lv[d];
@@ -5057,8 +5214,11 @@ void batch_prepare_impl(ifgf_batch_s* b) {
   }
 
   // ---- the queue ----------------------------------------------------------------
-  auto C = [](int g, int k) { return 1 + 16 * g + k; };   // counters: 0 = queue head, then 16 per geometry
-  enum { K_GATHER = 0, K_LEAF = 1, K_NEAR = 2, K_PAIRS = 3, K_PROP0 = 4, K_TARGET = 15 };   // K_PROP0 + d: into level d
+  auto C = [](int g, int k) { return 1 + kBatchCtrPerGeom * g + k; };   // counters: 0 = queue head, then per geometry
+  // K_PROP0 + l: the coefficients of level l; K_UPV0 + l: the upward pair values of the pass into level l
+  enum { K_GATHER = 0, K_LEAF = 1, K_NEAR = 2, K_PAIRS = 3, K_PROP0 = 4, K_UPV0 = 16, K_TARGET = 31 };
+  static_assert(K_PROP0 + IFGF_MAX_LEVELS - 1 < K_UPV0 && K_UPV0 + IFGF_MAX_LEVELS - 1 < K_TARGET &&
+                    K_TARGET < kBatchCtrPerGeom, "batch counter layout");
   std::vector<BSeg> segs;
   int64_t first = 0;
   auto emit = [&](int type, int g, int level, int64_t count, int dep0, int need0, int dep1, int need1, int done) {
@@ -5139,6 +5299,15 @@ void batch_prepare_impl(ifgf_batch_s* b) {
       if (d < 4) continue;
       const LevelPlan& lp = p->lev[d - 1];
       if (lp.nrel == 0 || lp.nwork == 0) continue;
+      if (geo[g].up.lv[d - 1].np > 0) {   // the plan's upward pair list: pair values, then node sums
+        const int64_t nv = ((geo[g].up.lv[d - 1].np + BS - 1) / BS + BG_UPAIRS - 1) / BG_UPAIRS;
+        const int NC = coeff_cones(P);
+        const int64_t ns = ((lp.nrel + NC - 1) / NC + BG_UPSUM - 1) / BG_UPSUM;
+        emit(BT_UPAIRS, g, d, nv, last[g].first, last[g].second, -1, 0, C(g, K_UPV0 + d - 1));
+        emit(BT_UPSUM, g, d, ns, C(g, K_UPV0 + d - 1), (int)nv, -1, 0, C(g, K_PROP0 + d - 1));
+        last[g] = {C(g, K_PROP0 + d - 1), (int)ns};
+        continue;
+      }
       // the cone-major tiles where the plan has them (FP32), else node work items
       const bool ti = Prec<T>::f32 && lp.ntile > 0;
       const int64_t cnt = ti ? lp.ntile : (lp.nwork + BG_PROP - 1) / BG_PROP;
@@ -5175,7 +5344,7 @@ void batch_prepare_impl(ifgf_batch_s* b) {
     for (int q = 0; q < segs[i].count; ++q) seg_of[(size_t)segs[i].first + q] = (int)i;
   b->seg_of.alloc(sizeof(int) * seg_of.size());
   HIPCHK(hipMemcpy(b->seg_of.p, seg_of.data(), sizeof(int) * seg_of.size(), hipMemcpyHostToDevice));
-  b->nctr = 1 + 16 * ng;
+  b->nctr = 1 + kBatchCtrPerGeom * ng;
   b->segs.alloc(sizeof(BSeg) * std::max<size_t>(1, segs.size()));
   if (!segs.empty()) HIPCHK(hipMemcpy(b->segs.p, segs.data(), sizeof(BSeg) * segs.size(), hipMemcpyHostToDevice));
   b->geoms.alloc(sizeof(BGeom<T>) * ng);

@@ -244,6 +244,8 @@ void run_batch_apply(ifgf_batch_s* b, const void* const* sigma, void* const* u, 
 // Device address of the fixed counter array (BATCH_STATIC_COUNTERS ints) on `device`,
 // which must be the current device; looked up once per device.
 constexpr int BATCH_STATIC_COUNTERS = IFGF_BATCH_NOALLOC_COUNTERS;
+constexpr int kBatchCtrPerGeom = 32;   // completion counters per geometry of a ragged batch
+static_assert(BATCH_STATIC_COUNTERS == 1 + kBatchCtrPerGeom * IFGF_BATCH_MAX, "noalloc counter array");
 int* batch_static_counters(int device);
 
 // The cone-major tiles' node records of level d (one per cone id in qlist and
