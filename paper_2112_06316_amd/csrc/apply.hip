@@ -3719,11 +3719,22 @@ __global__ __launch_bounds__(64) void k_adj_ti(const int4* __restrict__ tiles, c
 // FP32 with P_s = 4: the same gather on MFMA (v_mfma_f32_16x16x4_f32).  A
 // wave takes 8 child boxes of one bucket: rows = 8 boxes x (re, im), K = the
 // bucket's nodes, 4 per step (a group's last step padded with zeros), columns
-// = the P coefficients in tiles of 16, column 4a + u of tile t being
-// coefficient (a, pair 4t + u) with pair = (b, c), so that a lane's radial
-// index a is fixed and its pair comes from a compile-time set of four.
+// = the P coefficients in (P_ang / 2)^2 tiles of 16: column 4a + 2 beta +
+// gamma of tile t = tb (P_ang / 2) + tc is coefficient (a, b = 2 tb + beta,
+// c = 2 tc + gamma).  A lane's (a, beta, gamma) is fixed, so it picks its
+// Chebyshev values once per step and each tile's basis value is one product;
+// its output addresses are a per-lane base plus a per-tile constant.
 // Lane layouts as in the forward kernels: A[i][k] from lane 16k + i, B[k][j]
 // from lane 16k + j, D[4q + v][j] in lane 16q + j, element v.
+// Per-lane choice between two values (bit set in `mask`: b), as one
+// v_cndmask: written out so that the compiler cannot turn a choice between
+// neighbouring array elements into an indexed access of a private array.
+__device__ __forceinline__ float lane_sel(uint64_t mask, float a, float b) {
+  float r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
+  return r;
+}
+
 template <int PA>
 __global__ __launch_bounds__(64) void k_adj_ti_mfma(const int4* __restrict__ tiles, const int* __restrict__ slots,
                                                     const int2* __restrict__ gref, const int* __restrict__ gref_off,
@@ -3732,8 +3743,8 @@ __global__ __launch_bounds__(64) void k_adj_ti_mfma(const int4* __restrict__ til
                                                     const int* __restrict__ parent_c, const int* __restrict__ slot_p,
                                                     int ncone_p, const cpx<float>* __restrict__ Fhat_p,
                                                     cpx<float>* __restrict__ G_c) {
-  constexpr int PS = 4, NP = PA * PA, P = PS * NP, NT = NP / 4;
-  static_assert(NP % 4 == 0, "pairs in groups of four");
+  constexpr int PS = 4, NP = PA * PA, P = PS * NP, HM = PA / 2, NT = HM * HM;
+  static_assert(PA % 2 == 0, "(b, c) in 2 x 2 blocks");
   const int4 tl = tiles[xcd_block(blockIdx.x, gridDim.x)];
   const int l = threadIdx.x;
   const int i = l & 15, k = l >> 4;
@@ -3741,7 +3752,8 @@ __global__ __launch_bounds__(64) void k_adj_ti_mfma(const int4* __restrict__ til
   const bool validA = bA < tl.z;
   const int csA = validA ? slots[tl.y + bA] : 0;
   const int pbA = validA ? parent_c[rel_box_c[csA]] : 0;
-  const int aB = i >> 2, uB = i & 3;      // B column: radial index, pair within the tile's four
+  const int aB = i >> 2, bB = (i >> 1) & 1, cB = i & 1;   // B column: a, beta, gamma
+  const uint64_t ma0 = __ballot(aB & 1), ma1 = __ballot(aB & 2), mb = __ballot(bB), mc = __ballot(cB);
   floatx4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -3796,31 +3808,41 @@ __global__ __launch_bounds__(64) void k_adj_ti_mfma(const int4* __restrict__ til
       cheb_T<float, PS>(loc.x, Ts);
       cheb_T<float, PA>(loc.y, Tt);
       cheb_T<float, PA>(loc.z, Tp);
-      const float ta = aB == 0 ? Ts[0] : (aB == 1 ? Ts[1] : (aB == 2 ? Ts[2] : Ts[3]));
+      const float ta = lane_sel(ma1, lane_sel(ma0, Ts[0], Ts[1]), lane_sel(ma0, Ts[2], Ts[3]));
+      float tb[HM], tc[HM];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int p0 = 4 * t;
-        const float w0 = Tt[(p0 + 0) / PA] * Tp[(p0 + 0) % PA], w1 = Tt[(p0 + 1) / PA] * Tp[(p0 + 1) % PA];
-        const float w2 = Tt[(p0 + 2) / PA] * Tp[(p0 + 2) % PA], w3 = Tt[(p0 + 3) / PA] * Tp[(p0 + 3) % PA];
-        const float bv = ta * (uB == 0 ? w0 : (uB == 1 ? w1 : (uB == 2 ? w2 : w3)));
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[t], 0, 0, 0);
+      for (int h = 0; h < HM; ++h) {
+        tb[h] = ta * lane_sel(mb, Tt[2 * h], Tt[2 * h + 1]);
+        tc[h] = lane_sel(mc, Tp[2 * h], Tp[2 * h + 1]);
+      }
+#pragma unroll
+      for (int hb = 0; hb < HM; ++hb) {
+#pragma unroll
+        for (int hc = 0; hc < HM; ++hc) {
+          const int t = hb * HM + hc;
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, tb[hb] * tc[hc], acc[t], 0, 0, 0);
+        }
       }
     }
   }
   // lane 16 qd + jd holds rows 4 qd .. 4 qd + 3 = boxes 2 qd (re, im), 2 qd + 1 (re, im) of column jd
   const int qd = l >> 4, jd = l & 15;
-  const int aD = jd >> 2, uD = jd & 3;
+  const int aD = jd >> 2, bD = (jd >> 1) & 1, cD = jd & 1;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int bx = 2 * qd + h;
     if (bx >= tl.z) continue;
-    cpx<float>* out = G_c + (int64_t)slots[tl.y + bx] * P + aD * NP + uD;
+    cpx<float>* out = G_c + (int64_t)slots[tl.y + bx] * P + aD * NP + bD * PA + cD;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      cpx<float> v = out[4 * t];
-      v.re += acc[t][2 * h];
-      v.im += acc[t][2 * h + 1];
-      out[4 * t] = v;
+    for (int hb = 0; hb < HM; ++hb) {
+#pragma unroll
+      for (int hc = 0; hc < HM; ++hc) {
+        const int t = hb * HM + hc;
+        cpx<float> v = out[2 * hb * PA + 2 * hc];
+        v.re += acc[t][2 * h];
+        v.im += acc[t][2 * h + 1];
+        out[2 * hb * PA + 2 * hc] = v;
+      }
     }
   }
 }
