@@ -53,10 +53,11 @@ def log(msg):
 # sources it was taken with; when the sources have changed since, the figure
 # no longer describes this kernel and is not reported.
 TRAFFIC_SUMMARY = {
-    "prop": os.path.join(ROOT, "profiles", "k_prop_sphere32_hbm_traffic.md"),
+    "prop": os.path.join(ROOT, "profiles", "k_upairs_sphere32_hbm_traffic.md"),
     "prop_cone": os.path.join(ROOT, "profiles", "k_prop_ti_sphere32_hbm_traffic.md"),
 }
-KERNEL_OF_STAGE = {"prop": "k_prop (node formulation)", "prop_cone": "k_prop_ti (cone-major, MFMA)",
+KERNEL_OF_STAGE = {"prop": "k_upairs + k_upsum_coeffs (pair list) or k_prop (node formulation)",
+                   "prop_cone": "k_prop_ti (cone-major, MFMA)",
                    "targets": "k_targets", "leaf": "k_leaf", "near": "k_near", "coeffs": "k_coeffs"}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2112_06316_amd", "csrc", f) for f in ("apply.hip", "common.h", "plan.hip")]
 

@@ -1650,6 +1650,14 @@ __device__ __forceinline__ void pairs_block(const PLevel<T>& lv, int64_t q0) {
   if (valid) lv.val[q] = {o_re, o_im};
 }
 
+// Upward pass from a pair list, first kernel: the value of every pair.
+template <typename T, int PS, int PA>
+__global__ __launch_bounds__(TPB) void k_upairs(PLevel<T> lv) {
+  const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB;
+  if (q0 >= lv.np) return;   // block-uniform
+  pairs_block<T, PS, PA>(lv, q0);
+}
+
 // Pass one: the value of every pair of level dlo + blockIdx.y.
 template <typename T, int PS, int PA>
 __global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
@@ -4160,10 +4168,9 @@ void prop_level(ifgf_plan_s* p, int d, int R, hipStream_t s) {
   if constexpr (rows_ok<T, PS, PA>()) {
     if (R == 1 && lp.up_use && lp.nup > 0) {   // from the level's pair list
       StageTimer tm(p, s, IFGF_STAGE_PROP);
-      PLevels<T> L{};
-      L.lv[0] = {lp.nup, lp.up_slot.as<int>(), lp.up_loc.as<typename Vec4<T>::type>(), lp.up_fim.as<T>(),
-                 lp.up_val.as<cpx<T>>(), nullptr, lp.up_pos.as<int>(), lc.Fc.as<cpx<T>>()};
-      k_targets_pairs<T, PS, PA><<<dim3((unsigned)((lp.nup + TPB - 1) / TPB), 1), TPB, 0, s>>>(L, 0);
+      const PLevel<T> ul{lp.nup, lp.up_slot.as<int>(), lp.up_loc.as<typename Vec4<T>::type>(), lp.up_fim.as<T>(),
+                         lp.up_val.as<cpx<T>>(), nullptr, lp.up_pos.as<int>(), lc.Fc.as<cpx<T>>()};
+      k_upairs<T, PS, PA><<<(unsigned)((lp.nup + TPB - 1) / TPB), TPB, 0, s>>>(ul);
       HIPCHK(hipGetLastError());
       k_upsum_coeffs<T, PS, PA><<<(unsigned)((lp.nrel + coeff_cones(P) - 1) / coeff_cones(P)), TPB, 0, s>>>(
           lp.up_base.as<int>(), lp.up_pos.as<int>(), lp.up_val.as<cpx<T>>(), lp.nrel, Ms, Ma, lp.Fc.as<cpx<T>>());
