@@ -2075,7 +2075,7 @@ template <int PS, int PA> struct BcSmem {
 };
 
 template <int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_prop_mfma_cone(const int* __restrict__ rel_box_up,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(4))) void k_prop_mfma_cone(const int* __restrict__ rel_box_up,
                                                         const int* __restrict__ rel_cone_up,
                                                         const int* __restrict__ child_lo_up,
                                                         const int* __restrict__ coords, const int* __restrict__ slot_c,
