@@ -1144,7 +1144,7 @@ __device__ __forceinline__ void prop_item(PropSmem<T, PS, PA, BS_, CB>& sm, int4
 }
 
 template <typename T, int PS, int PA, bool ONE>
-__global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) void k_prop(
+__global__ __launch_bounds__(PropShape<PS * PA * PA>::BS) __attribute__((amdgpu_waves_per_eu(3))) void k_prop(
     const int4* __restrict__ work, const int* __restrict__ rel_cone_up, const int* __restrict__ child_lo_up,
     const int* __restrict__ coords, const int* __restrict__ slot_c, const cpx<T>* __restrict__ Fc_c, LevelGeom gp,
     LevelGeom gc, ChebTab ct, const T* __restrict__ Ms, const T* __restrict__ Ma, double k, int kind, int R,
@@ -1652,7 +1652,7 @@ __device__ __forceinline__ void pairs_block(const PLevel<T>& lv, int64_t q0) {
 
 // Upward pass from a pair list, first kernel: the value of every pair.
 template <typename T, int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_upairs(PLevel<T> lv) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k_upairs(PLevel<T> lv) {
   const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB;
   if (q0 >= lv.np) return;   // block-uniform
   pairs_block<T, PS, PA>(lv, q0);
@@ -1660,7 +1660,7 @@ __global__ __launch_bounds__(TPB) void k_upairs(PLevel<T> lv) {
 
 // Pass one: the value of every pair of level dlo + blockIdx.y.
 template <typename T, int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_targets_pairs(PLevels<T> L, int dlo) {
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(3))) void k_targets_pairs(PLevels<T> L, int dlo) {
   const PLevel<T>& lv = L.lv[dlo + blockIdx.y];
   const int64_t q0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * TPB;
   if (q0 >= lv.np) return;   // block-uniform
