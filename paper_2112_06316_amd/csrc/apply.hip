@@ -3898,7 +3898,7 @@ __global__ __launch_bounds__(TPB) void k_adj_child_keys(const int* __restrict__ 
 constexpr int ADJ_LEAF_SC = 8;
 
 template <typename T, int PS, int PA>
-__global__ __launch_bounds__(TPB) void k_adj_leaf(const double* __restrict__ pts, const double* __restrict__ nrm,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 1))) void k_adj_leaf(const double* __restrict__ pts, const double* __restrict__ nrm,
                                                   const int* __restrict__ start, const double* __restrict__ centre,
                                                   const int* __restrict__ slot_off, const int* __restrict__ rel_cone,
                                                   const cpx<T>* __restrict__ Fhat, LevelGeom g, ChebTab ct, double k,
