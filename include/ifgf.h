@@ -117,7 +117,8 @@ typedef struct {
  * pair of the pass once - child cone slot, local coordinates, kernel ratio -
  * and sorts the pairs by child slot; an apply evaluates them in that order
  * and adds each node's pairs in child order (36 bytes per pair, up to 2^28
- * pairs per level; levels with more use NODE).  AUTO takes PAIRS on the
+ * pairs per level; levels with more, or whose list the device memory does
+ * not hold at plan creation, use NODE).  AUTO takes PAIRS on the
  * levels without tiles.  All give the same operator up to rounding; the
  * transposed apply gathers over a level's pair list where it has one. */
 enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2, IFGF_PROP_PAIRS = 3 };
@@ -135,7 +136,8 @@ enum { IFGF_PROP_AUTO = 0, IFGF_PROP_NODE = 1, IFGF_PROP_CONE = 2, IFGF_PROP_PAI
  * centred factor, sorted by cone; a row of 16 lanes then mostly holds pairs
  * of one cone, evaluates them with the row stage of ROWS, and a second pass
  * sums each target's pairs in the order ROWS uses; about 40 bytes (FP32) or
- * 72 bytes (FP64) per pair of plan memory, built for at most 2^28 pairs.
+ * 72 bytes (FP64) per pair of plan memory, built for at most 2^28 pairs
+ * and where the device memory holds them (else the plan keeps ROWS).
  * AUTO = PAIRS where the lists were built, else ROWS.  All give the same
  * operator up to rounding. */
 enum { IFGF_TARGET_AUTO = 0, IFGF_TARGET_WAVE = 1, IFGF_TARGET_ROWS = 2, IFGF_TARGET_PAIRS = 3 };

@@ -5785,10 +5785,16 @@ void build_target_pairs(ifgf_plan_s* p, hipStream_t s) {
   int64_t tot = 0;
   for (int d = 3; d <= p->D; ++d) tot += p->lev[d].cousin_pairs;
   if (tot > ((int64_t)1 << 28)) return;
-  if (f32)
-    build_target_pairs_impl<float>(p, s);
-  else
-    build_target_pairs_impl<double>(p, s);
+  try {   // where the device memory runs out the plan keeps the row targets
+    if (f32)
+      build_target_pairs_impl<float>(p, s);
+    else
+      build_target_pairs_impl<double>(p, s);
+  } catch (const Error& e) {
+    if (e.st != IFGF_ENOMEM) throw;
+    HIPCHK(hipStreamSynchronize(s));   // the lists' generators are done before they are freed
+    release_target_pairs(p);
+  }
 }
 
 void release_up_pairs(LevelPlan& lv) {
@@ -5875,11 +5881,18 @@ bool up_pairs_possible(const ifgf_plan_s* p, int d) {
   return np > 0 && np <= ((int64_t)1 << 28);
 }
 
+// Where the device memory runs out the level keeps the node formulation.
 void build_up_pairs(ifgf_plan_s* p, int d, hipStream_t s) {
-  if (p->opt.precision == IFGF_PREC_FP32_INTERP)
-    dispatch_up_pairs<float>(p, d, s);
-  else
-    dispatch_up_pairs<double>(p, d, s);
+  try {
+    if (p->opt.precision == IFGF_PREC_FP32_INTERP)
+      dispatch_up_pairs<float>(p, d, s);
+    else
+      dispatch_up_pairs<double>(p, d, s);
+  } catch (const Error& e) {
+    if (e.st != IFGF_ENOMEM) throw;
+    HIPCHK(hipStreamSynchronize(s));   // nothing in flight reads the list before it is freed
+    release_up_pairs(p->lev[d]);
+  }
 }
 
 // At plan creation: PAIRS takes the lists wherever possible; AUTO where the
