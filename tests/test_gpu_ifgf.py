@@ -345,6 +345,42 @@ def test_auto_takes_pair_lists_on_levels_without_tiles():
     assert node.stats()["device_bytes"] < auto.stats()["device_bytes"]
 
 
+def test_pair_lists_fall_back_when_device_memory_is_short():
+    # Plan creation builds the pair lists last; where the device memory does
+    # not hold them the plan keeps the node formulation and the row targets
+    # and still gives the same operator.  The shortage is made from the host:
+    # a placeholder allocation leaves room for the plan without lists and
+    # 256 MB, far less than its lists need.
+    wl = inputs.workload("sphere16")
+    p, nr, w = inputs.build_surface(wl)
+    k = wl["k"]
+    s = torch.from_numpy(inputs.random_density(len(p), seed=64)).to(DEV).to(torch.complex64)
+    ref = Plan(p, nr, w, k, k, depth=wl["depth"])
+    assert "pairs" in ref.stats()["prop_kernel"].values()
+    u_ref = ref.apply(s).cpu().numpy()
+    bare = Plan(p, nr, w, k, k, depth=wl["depth"], prop_kernel="node", target_kernel="rows")
+    b_bare, b_ref = bare.stats()["device_bytes"], ref.stats()["device_bytes"]
+    log(f"case memory fallback: plan {b_ref / 1e9:.2f} GB, without lists {b_bare / 1e9:.2f} GB")
+    assert b_ref - b_bare > (1 << 30)
+    del ref, bare
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    blocker = torch.empty(max(0, free - b_bare - (256 << 20)), dtype=torch.uint8, device=DEV)
+    try:
+        plan = Plan(p, nr, w, k, k, depth=wl["depth"])
+        st = plan.stats()
+    finally:
+        del blocker
+        torch.cuda.empty_cache()
+    log(f"  without room: {st['prop_kernel']}, {st['device_bytes'] / 1e9:.2f} GB")
+    assert "pairs" not in st["prop_kernel"].values()
+    assert st["device_bytes"] < b_ref
+    u = plan.apply(s).cpu().numpy()
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) < 1e-5
+    assert plan.check() == 0
+
+
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("fp64", 1e-11)])
 @pytest.mark.parametrize("ps,pa", [(4, 6), (3, 5)])
 def test_cone_major_constant_kernel_exact(ps, pa, precision, tol):
