@@ -1980,68 +1980,43 @@ __global__ __launch_bounds__(TPB) void k_targets_pairs_rg(PLevels<float> L, int 
 }
 
 // u[:, group g] = near field + per level (finest first) the sum of the
-// target's pair values in cousin order; 16 right-hand sides per thread.
+// target's pair values in cousin order.
 __global__ __launch_bounds__(TPB) void k_targets_pairsum_rg(int64_t n, const int* __restrict__ perm,
                                                             const cpx<float>* __restrict__ uacc, int use_near,
                                                             PLevels<float> L, int dlo, int dhi, int R, int g,
                                                             int dtype, void* __restrict__ u) {
-  const int64_t i = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  // 16 lanes per target, lane r = RHS g * 16 + r: a pair's 16 values are one
+  // 128-byte row read by the 16 lanes together; each lane adds its RHS over
+  // the target's pairs in cousin order
+  const int64_t tid = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  const int64_t i = tid / MF_RG;
+  const int r = (int)(tid % MF_RG);
   if (i >= n) return;
-  double re[MF_RG], im[MF_RG];
-#pragma unroll
-  for (int r = 0; r < MF_RG; ++r) {
-    re[r] = use_near ? uacc[i * R + g * MF_RG + r].re : 0.0;
-    im[r] = use_near ? uacc[i * R + g * MF_RG + r].im : 0.0;
+  double re = 0.0, im = 0.0;
+  if (use_near) {
+    const cpx<float> v = uacc[i * R + g * MF_RG + r];
+    re = v.re;
+    im = v.im;
   }
   for (int d = dhi; d >= dlo; --d) {
     const PLevel<float>& lv = L.lv[d];
-    float lre[MF_RG], lim[MF_RG];
-#pragma unroll
-    for (int r = 0; r < MF_RG; ++r) lre[r] = lim[r] = 0.f;
+    float lre = 0.f, lim = 0.f;
     const int t1 = lv.off[i + 1];
-    int t = lv.off[i];
-    // pairs two at a time: 32 independent loads in flight, summed in cousin order
-    for (; t + 2 <= t1; t += 2) {
-      const cpx<float>* v0 = lv.val + (int64_t)lv.pos[t] * MF_RG;
-      const cpx<float>* v1 = lv.val + (int64_t)lv.pos[t + 1] * MF_RG;
-      cpx<float> a[MF_RG], b[MF_RG];
-#pragma unroll
-      for (int r = 0; r < MF_RG; ++r) {
-        a[r] = v0[r];
-        b[r] = v1[r];
-      }
-#pragma unroll
-      for (int r = 0; r < MF_RG; ++r) {
-        lre[r] += a[r].re;
-        lim[r] += a[r].im;
-        lre[r] += b[r].re;
-        lim[r] += b[r].im;
-      }
+    for (int t = lv.off[i]; t < t1; ++t) {
+      const cpx<float> v = lv.val[(int64_t)lv.pos[t] * MF_RG + r];
+      lre += v.re;
+      lim += v.im;
     }
-    for (; t < t1; ++t) {
-      const cpx<float>* v = lv.val + (int64_t)lv.pos[t] * MF_RG;
-#pragma unroll
-      for (int r = 0; r < MF_RG; ++r) {
-        lre[r] += v[r].re;
-        lim[r] += v[r].im;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < MF_RG; ++r) {
-      re[r] += lre[r];
-      im[r] += lim[r];
-    }
+    re += lre;
+    im += lim;
   }
-  const int64_t o = (int64_t)perm[i] * R + g * MF_RG;
-#pragma unroll
-  for (int r = 0; r < MF_RG; ++r) {
-    if (dtype == IFGF_C128) {
-      ((double*)u)[2 * (o + r)] = re[r];
-      ((double*)u)[2 * (o + r) + 1] = im[r];
-    } else {
-      ((float*)u)[2 * (o + r)] = (float)re[r];
-      ((float*)u)[2 * (o + r) + 1] = (float)im[r];
-    }
+  const int64_t o = (int64_t)perm[i] * R + g * MF_RG + r;
+  if (dtype == IFGF_C128) {
+    ((double*)u)[2 * o] = re;
+    ((double*)u)[2 * o + 1] = im;
+  } else {
+    ((float*)u)[2 * o] = (float)re;
+    ((float*)u)[2 * o + 1] = (float)im;
   }
 }
 
@@ -4321,7 +4296,7 @@ void apply_impl(ifgf_plan_s* p, const void* sigma, void* u, int R, int dtype, in
           k_targets_pairs_rg<PS, PA><<<dim3(nblocks(maxp), nlev), TPB, 0, s>>>(PL, dlo, R, g);
           HIPCHK(hipGetLastError());
         }
-        k_targets_pairsum_rg<<<nblocks(n), TPB, 0, s>>>(n, p->perm.as<int>(), (const cpx<float>*)uacc, near ? 1 : 0,
+        k_targets_pairsum_rg<<<nblocks(n * MF_RG), TPB, 0, s>>>(n, p->perm.as<int>(), (const cpx<float>*)uacc, near ? 1 : 0,
                                                        PL, dlo, dhi, R, g, dtype, u);
         HIPCHK(hipGetLastError());
       }
