@@ -47,6 +47,12 @@ template <> struct Prec<double> {
 template <typename T> __device__ __forceinline__ void sincos_t(T x, T* s, T* c);
 template <> __device__ __forceinline__ void sincos_t<float>(float x, float* s, float* c) { sincos_f(x, s, c); }
 template <> __device__ __forceinline__ void sincos_t<double>(double x, double* s, double* c) { sincos(x, s, c); }
+// The leaf and near-field phases (a few radians to a few hundred): in FP64
+// the reduction and series of sincos_cw64 instead of the library call
+template <typename T> __device__ __forceinline__ void sincos_phase(T x, T* s, T* c) {
+  if constexpr (sizeof(T) == 8) sincos_cw64(x, s, c);
+  else sincos_t<T>(x, s, c);
+}
 
 template <typename T> __device__ __forceinline__ T sqrt_t(T x);
 template <> __device__ __forceinline__ float sqrt_t<float>(float x) { return sqrt_f(x); }   // hardware, ~1 ulp
@@ -62,12 +68,11 @@ template <> __device__ __forceinline__ void sqrt_rsqrt<float>(float x, float* sq
   *sq = x * r;
 }
 template <> __device__ __forceinline__ void sqrt_rsqrt<double>(double x, double* sq, double* rs) {
-  *sq = sqrt(x);
-  *rs = 1.0 / *sq;
+  sqrt_rsqrt_nr64(x, sq, rs);
 }
 template <typename T> __device__ __forceinline__ T rcp_t(T x);
 template <> __device__ __forceinline__ float rcp_t<float>(float x) { return rcp_f(x); }
-template <> __device__ __forceinline__ double rcp_t<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ double rcp_t<double>(double x) { return rcp_nr64(x); }
 
 // ---------------------------------------------------------------------------
 // gather: a[i, r] = w_i sigma[perm_i, r]; points with caller index >= n_src
@@ -244,7 +249,7 @@ __device__ __forceinline__ void near_box(NearSmem<T, RG, BS>& sm, int b, int tof
             T dn = TR ? -(d0 * m0 + d1 * m1 + d2 * m2) * ir * ir
                       : (d0 * sn[e][0] + d1 * sn[e][1] + d2 * sn[e][2]) * ir * ir;
             T sn_, cs_;
-            sincos_t<T>(kk * rr, &sn_, &cs_);
+            sincos_phase<T>(kk * rr, &sn_, &cs_);
             // G = e^{ikr}/(4 pi r);  K = G [ (1 - ikr) dn - i eta ]
             T g = inv4pi * ir;
             T pr = dn, pi = -(kk * rr * dn + ee);
@@ -396,7 +401,7 @@ __device__ __forceinline__ void leaf_box(LeafSmem<T, RG>& sm, int b, int i0, int
             // of half a wavelength): in FP32 the hardware sine and cosine,
             // absolute error about 1.5e-7 + 8.7e-8 k h
             if constexpr (Prec<T>::f32) sincos_hw(ph, &sp, &cp);
-            else sincos_t<T>(ph, &sp, &cp);
+            else sincos_phase<T>(ph, &sp, &cp);
             T vn = en - s * sun[q];
             T A = vn * s * inv * inv * inv * ih;
             T B = kk * vn * inv * inv + ee * inv;
@@ -3935,7 +3940,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
           T sp, cp;
           // |ph| <= k h, as in the forward leaf factors
           if constexpr (Prec<T>::f32) sincos_hw(ph, &sp, &cp);
-          else sincos_t<T>(ph, &sp, &cp);
+          else sincos_phase<T>(ph, &sp, &cp);
           T vn = en - s * sun[q];
           T A = vn * s * inv * inv * inv * ih;
           T Bv = kk * vn * inv * inv + ee * inv;

@@ -125,6 +125,72 @@ __device__ __forceinline__ void sincos_hw(float x, float* sn, float* cs) {
   *cs = __builtin_amdgcn_cosf(rv);
 }
 
+// sin and cos in FP64 for |x| <= 2^20: quadrant q = rint(2x/pi), remainder
+// r = x - q pi/2 by a two-term Cody-Waite reduction with FMAs (pi/2 = HI +
+// LO, HI the double nearest pi/2), then the Taylor series of sin and cos on
+// |r| <= pi/4 through r^15 and r^16 (truncation below 5e-17), and the
+// quadrant's signs and swap.  Within about 2 ulp of sin and cos; larger |x|
+// go to the library sincos.
+__device__ __forceinline__ void sincos_cw64(double x, double* sn, double* cs) {
+  if (!(fabs(x) <= 1048576.0)) {
+    sincos(x, sn, cs);
+    return;
+  }
+  constexpr double PIO2_HI = 1.5707963267948966;       // nearest double to pi/2
+  constexpr double PIO2_LO = 6.123233995736766e-17;    // pi/2 - PIO2_HI
+  constexpr double TWO_OVER_PI = 0.6366197723675814;
+  const double q = rint(x * TWO_OVER_PI);
+  double r = fma(-q, PIO2_HI, x);
+  r = fma(-q, PIO2_LO, r);
+  const double r2 = r * r;
+  // 1/n! for the Taylor terms
+  constexpr double F2 = 1.0 / 2, F3 = F2 / 3, F4 = F3 / 4, F5 = F4 / 5, F6 = F5 / 6, F7 = F6 / 7, F8 = F7 / 8,
+                   F9 = F8 / 9, F10 = F9 / 10, F11 = F10 / 11, F12 = F11 / 12, F13 = F12 / 13, F14 = F13 / 14,
+                   F15 = F14 / 15, F16 = F15 / 16;
+  double ps = fma(r2, -F15, F13);
+  ps = fma(r2, ps, -F11);
+  ps = fma(r2, ps, F9);
+  ps = fma(r2, ps, -F7);
+  ps = fma(r2, ps, F5);
+  ps = fma(r2, ps, -F3);
+  const double s_r = fma(r * r2, ps, r);
+  double pc = fma(r2, F16, -F14);
+  pc = fma(r2, pc, F12);
+  pc = fma(r2, pc, -F10);
+  pc = fma(r2, pc, F8);
+  pc = fma(r2, pc, -F6);
+  pc = fma(r2, pc, F4);
+  const double c_r = fma(r2 * r2, pc, fma(r2, -F2, 1.0));
+  const int n = (int)q & 3;
+  const double a = (n & 1) ? c_r : s_r, b = (n & 1) ? s_r : c_r;
+  *sn = (n & 2) ? -a : a;
+  *cs = ((n + 1) & 2) ? -b : b;
+}
+
+// FP64 1/sqrt(x) and sqrt(x) for positive normal x: the hardware estimate
+// refined by two Newton-Raphson steps y <- y + y (1 - x y^2) / 2, then
+// sqrt(x) = x y corrected once by its residual x - (x y)^2.
+__device__ __forceinline__ void sqrt_rsqrt_nr64(double x, double* sq, double* rs) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-(x * y), y, 1.0);
+  y = fma(0.5 * y, e, y);
+  e = fma(-(x * y), y, 1.0);
+  y = fma(0.5 * y, e, y);
+  double s = x * y;
+  s = fma(0.5 * y, fma(-s, s, x), s);
+  *rs = y;
+  *sq = s;
+}
+
+// FP64 1/x for normal x: the hardware estimate refined by two Newton-Raphson
+// steps y <- y + y (1 - x y).
+__device__ __forceinline__ double rcp_nr64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
 // sin and cos in FP32: quadrant k = rint(2x/pi), remainder x - k pi/2 by a
 // three-term Cody-Waite reduction with FMAs (pi/2 split into FP32 parts),
 // then polynomials on |r| <= pi/4 whose coefficients are a least-squares fit

@@ -10,9 +10,16 @@
 //                                           vector loads/stores, GB/s (read + written)
 //
 // Returns 0 on success, a HIP error code otherwise (v untouched).
+//
+//   ifgf_probe_math64(x, out, n, stream)  for device FP64 x[n]: out[5 i ..] =
+//       sin x_i, cos x_i (sincos_cw64), sqrt |x_i|, 1/sqrt |x_i|
+//       (sqrt_rsqrt_nr64) and 1/x_i (rcp_nr64), as the IFGF kernels compute
+//       them; for the accuracy tests (x_i != 0).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+
+#include "common.h"
 
 namespace {
 
@@ -110,9 +117,30 @@ hipError_t timed(F launch, float* ms) {
   return st;
 }
 
+__global__ __launch_bounds__(PTPB) void k_probe_math64(const double* __restrict__ x, double* __restrict__ out,
+                                                       int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * PTPB + threadIdx.x;
+  if (i >= n) return;
+  double s, c, sq, rs;
+  sincos_cw64(x[i], &s, &c);
+  sqrt_rsqrt_nr64(fabs(x[i]), &sq, &rs);
+  out[5 * i] = s;
+  out[5 * i + 1] = c;
+  out[5 * i + 2] = sq;
+  out[5 * i + 3] = rs;
+  out[5 * i + 4] = rcp_nr64(x[i]);
+}
+
 }  // namespace
 
 extern "C" {
+
+int ifgf_probe_math64(const double* x, double* out, int64_t n, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !out))) return (int)hipErrorInvalidValue;
+  if (n == 0) return 0;
+  k_probe_math64<<<(unsigned)((n + PTPB - 1) / PTPB), PTPB, 0, (hipStream_t)stream>>>(x, out, n);
+  return (int)hipGetLastError();
+}
 
 enum { IFGF_PROBE_MFMA_F32 = 0, IFGF_PROBE_FMA_F32 = 1, IFGF_PROBE_FMA_F64 = 2, IFGF_PROBE_COPY = 3 };
 
